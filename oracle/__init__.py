@@ -1,0 +1,246 @@
+"""CPU oracle for the edge clustering of dynamic graphs -- TEST INFRASTRUCTURE.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package. The GPU library neither imports nor links
+it; the two share no code. The arithmetic lives in ``ce_oracle.c`` (plain C,
+host only); this module is argument marshalling.
+
+Tier A (``tier=0``) is the definition: the full undirected line graph
+(Sec. 1.2.2) and Kruskal in canonical-key order. Tier B (``tier=1``) follows
+the method's own steps: per-vertex time-sorted incidence lists, the path
+skeleton (Alg. 3 with the undirected node-local MST of Sec. 5.3), Kruskal.
+Both continue with the union-find dendrogram and the HDBSCAN condensing and
+excess-of-mass extraction of Alg. 1.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from typing import NamedTuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+LG_EDGE = np.dtype([("w", "<i8"), ("tail", "<u4"), ("head", "<u4")])
+
+OK, EINVAL, ESELFLOOP, ERANGE, ENOMEM = 0, -1, -2, -3, -4
+
+
+def build_oracle(force: bool = False) -> str:
+    src = os.path.join(_HERE, "ce_oracle.c")
+    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(src):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-shared", "-fPIC", "-o", tmp, src])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        path = os.environ.get("CE_ORACLE_LIB")  # tests load planted-mistake builds this way
+        if not path:
+            if not os.path.exists(_LIB_PATH):
+                build_oracle()
+            path = _LIB_PATH
+        lib = ctypes.CDLL(path)
+        i64, p = ctypes.c_int64, ctypes.c_void_p
+        lib.oracle_validate.argtypes = [i64, p, p, p, i64]
+        lib.oracle_validate.restype = ctypes.c_int
+        lib.oracle_full_line_graph.argtypes = [i64, p, p, p, i64, p]
+        lib.oracle_full_line_graph.restype = i64
+        lib.oracle_skeleton.argtypes = [i64, p, p, p, i64, p]
+        lib.oracle_skeleton.restype = i64
+        lib.oracle_kruskal.argtypes = [i64, i64, p, p, p, p, p]
+        lib.oracle_kruskal.restype = i64
+        lib.oracle_dendrogram.argtypes = [i64, i64, p, p, p, p, p, p, p]
+        lib.oracle_dendrogram.restype = ctypes.c_int
+        lib.oracle_condense.argtypes = [i64, i64, p, p, p, p, i64] + [p] * 11 + [p]
+        lib.oracle_condense.restype = ctypes.c_int
+        lib.oracle_cluster.argtypes = [i64, p, p, p, i64, i64, ctypes.c_int] + [p] * 18
+        lib.oracle_cluster.restype = ctypes.c_int
+        _lib = lib
+    return _lib
+
+
+def _prep(src, dst, t):
+    src = np.ascontiguousarray(src, dtype=np.int32)
+    dst = np.ascontiguousarray(dst, dtype=np.int32)
+    t = np.ascontiguousarray(t, dtype=np.int64)
+    assert src.shape == dst.shape == t.shape and src.ndim == 1
+    return src, dst, t
+
+
+def _V(src, dst, V):
+    if V is None or V == 0:
+        return int(max(src.max(initial=-1), dst.max(initial=-1)) + 1)
+    return int(V)
+
+
+def validate(src, dst, t, V=None) -> int:
+    src, dst, t = _prep(src, dst, t)
+    return int(_load().oracle_validate(src.size, src.ctypes.data, dst.ctypes.data, t.ctypes.data, _V(src, dst, V)))
+
+
+def full_line_graph_size(src, dst, t, V=None) -> int:
+    src, dst, t = _prep(src, dst, t)
+    return int(_load().oracle_full_line_graph(src.size, src.ctypes.data, dst.ctypes.data, t.ctypes.data,
+                                              _V(src, dst, V), None))
+
+
+def full_line_graph(src, dst, t, V=None, limit=200_000_000) -> np.ndarray:
+    """All undirected line-graph edges (tail, head, w), pairs sharing both endpoints once."""
+    src, dst, t = _prep(src, dst, t)
+    V = _V(src, dst, V)
+    lib = _load()
+    cnt = int(lib.oracle_full_line_graph(src.size, src.ctypes.data, dst.ctypes.data, t.ctypes.data, V, None))
+    if cnt > limit:
+        raise MemoryError("full line graph has %d edges (limit %d)" % (cnt, limit))
+    out = np.empty(max(cnt, 1), dtype=LG_EDGE)
+    lib.oracle_full_line_graph(src.size, src.ctypes.data, dst.ctypes.data, t.ctypes.data, V, out.ctypes.data)
+    return out[:cnt]
+
+
+def skeleton(src, dst, t, V=None) -> np.ndarray:
+    """Path skeleton rows (tail, head, w), 2n - V' rows, in vertex then list order."""
+    src, dst, t = _prep(src, dst, t)
+    V = _V(src, dst, V)
+    lib = _load()
+    cnt = int(lib.oracle_skeleton(src.size, src.ctypes.data, dst.ctypes.data, t.ctypes.data, V, None))
+    out = np.empty(max(cnt, 1), dtype=LG_EDGE)
+    lib.oracle_skeleton(src.size, src.ctypes.data, dst.ctypes.data, t.ctypes.data, V, out.ctypes.data)
+    return out[:cnt]
+
+
+def kruskal(n, edges, t):
+    """MSF rows (tail, head, w) in ascending canonical key; edges are not modified."""
+    e = np.array(edges, dtype=LG_EDGE, copy=True)
+    t = np.ascontiguousarray(t, dtype=np.int64)
+    cap = max(int(n) - 1, 1)
+    mt = np.empty(cap, np.uint32)
+    mh = np.empty(cap, np.uint32)
+    mw = np.empty(cap, np.int64)
+    m = int(_load().oracle_kruskal(int(n), e.size, e.ctypes.data, t.ctypes.data, mt.ctypes.data, mh.ctypes.data,
+                                   mw.ctypes.data))
+    if m < 0:
+        raise RuntimeError("oracle_kruskal: %d" % m)
+    return mt[:m], mh[:m], mw[:m]
+
+
+def dendrogram(n, msf_tail, msf_head, msf_w):
+    mt = np.ascontiguousarray(msf_tail, np.uint32)
+    mh = np.ascontiguousarray(msf_head, np.uint32)
+    mw = np.ascontiguousarray(msf_w, np.int64)
+    m = mt.size
+    left = np.empty(max(m, 1), np.uint32)
+    right = np.empty(max(m, 1), np.uint32)
+    lw = np.empty(max(m, 1), np.int64)
+    size = np.empty(max(m, 1), np.uint32)
+    rc = _load().oracle_dendrogram(int(n), m, mt.ctypes.data, mh.ctypes.data, mw.ctypes.data, left.ctypes.data,
+                                   right.ctypes.data, lw.ctypes.data, size.ctypes.data)
+    if rc:
+        raise RuntimeError("oracle_dendrogram: %d" % rc)
+    return left[:m], right[:m], lw[:m], size[:m]
+
+
+def max_clusters(n, M):
+    return 2 * (int(n) // int(M)) + 1
+
+
+class Condensed(NamedTuple):
+    pt_cluster: np.ndarray
+    pt_lambda: np.ndarray
+    cl_id: np.ndarray
+    cl_parent: np.ndarray
+    cl_size: np.ndarray
+    cl_lambda_birth: np.ndarray
+    cl_stab_hi: np.ndarray
+    cl_stab_lo: np.ndarray
+    cl_selected: np.ndarray
+    labels: np.ndarray
+    n_labels: int
+
+
+class _Counts(ctypes.Structure):
+    _fields_ = [("n_clusters", ctypes.c_int64), ("n_labels", ctypes.c_int64)]
+
+
+def condense(n, left, right, lw, size, M) -> Condensed:
+    left = np.ascontiguousarray(left, np.uint32)
+    right = np.ascontiguousarray(right, np.uint32)
+    lw = np.ascontiguousarray(lw, np.int64)
+    size = np.ascontiguousarray(size, np.uint32)
+    m = left.size
+    C = max_clusters(n, M)
+    ptc = np.empty(max(n, 1), np.uint32)
+    ptl = np.empty(max(n, 1), np.uint64)
+    arrs = [np.empty(C, np.uint32), np.empty(C, np.uint32), np.empty(C, np.uint32), np.empty(C, np.uint64),
+            np.empty(C, np.uint64), np.empty(C, np.uint64), np.empty(C, np.uint8)]
+    labels = np.empty(max(n, 1), np.int32)
+    cnt = _Counts()
+    rc = _load().oracle_condense(int(n), m, left.ctypes.data, right.ctypes.data, lw.ctypes.data, size.ctypes.data,
+                                 int(M), ptc.ctypes.data, ptl.ctypes.data, *[a.ctypes.data for a in arrs],
+                                 labels.ctypes.data, ctypes.byref(cnt))
+    if rc:
+        raise RuntimeError("oracle_condense: %d" % rc)
+    k = int(cnt.n_clusters)
+    return Condensed(ptc[:n], ptl[:n], *[a[:k] for a in arrs], labels[:n], int(cnt.n_labels))
+
+
+class Result(NamedTuple):
+    status: int
+    m: int
+    msf_tail: np.ndarray
+    msf_head: np.ndarray
+    msf_w: np.ndarray
+    sl_left: np.ndarray
+    sl_right: np.ndarray
+    sl_w: np.ndarray
+    sl_size: np.ndarray
+    pt_cluster: np.ndarray
+    pt_lambda: np.ndarray
+    cl_id: np.ndarray
+    cl_parent: np.ndarray
+    cl_size: np.ndarray
+    cl_lambda_birth: np.ndarray
+    cl_stab_hi: np.ndarray
+    cl_stab_lo: np.ndarray
+    cl_selected: np.ndarray
+    labels: np.ndarray
+    n_clusters: int
+    n_labels: int
+
+
+def cluster(src, dst, t, min_cluster_size, num_vertices=None, tier=1) -> Result:
+    """Whole pipeline. tier=0: full line graph (definition); tier=1: path skeleton."""
+    src, dst, t = _prep(src, dst, t)
+    n = src.size
+    V = _V(src, dst, num_vertices)
+    M = int(min_cluster_size)
+    R = max(n - 1, 1)
+    C = max_clusters(n, max(M, 2))
+    bufs = [np.empty(R, np.uint32), np.empty(R, np.uint32), np.empty(R, np.int64),
+            np.empty(R, np.uint32), np.empty(R, np.uint32), np.empty(R, np.int64), np.empty(R, np.uint32),
+            np.empty(max(n, 1), np.uint32), np.empty(max(n, 1), np.uint64),
+            np.empty(C, np.uint32), np.empty(C, np.uint32), np.empty(C, np.uint32), np.empty(C, np.uint64),
+            np.empty(C, np.uint64), np.empty(C, np.uint64), np.empty(C, np.uint8),
+            np.empty(max(n, 1), np.int32)]
+    hdr = np.zeros(4, np.int64)
+    _load().oracle_cluster(n, src.ctypes.data, dst.ctypes.data, t.ctypes.data, V, M, int(tier),
+                           *[b.ctypes.data for b in bufs], hdr.ctypes.data)
+    st, m, nc, nl = (int(x) for x in hdr)
+    if st != 0:
+        e = [np.empty(0, b.dtype) for b in bufs]
+        return Result(st, 0, *e, 0, 0)
+    b = bufs
+    return Result(st, m, b[0][:m], b[1][:m], b[2][:m], b[3][:m], b[4][:m], b[5][:m], b[6][:m],
+                  b[7][:n], b[8][:n], *[x[:nc] for x in b[9:16]], b[16][:n], nc, nl)
+
+
+def stability(res_or_cond, i):
+    """Exact u128 stability of cluster row i as a Python int."""
+    return (int(res_or_cond.cl_stab_hi[i]) << 64) | int(res_or_cond.cl_stab_lo[i])

@@ -1,0 +1,494 @@
+/*
+ * CPU ORACLE -- test infrastructure only.
+ *
+ * Plain, slow, obviously-correct host implementation of what the edge
+ * clustering of a dynamic multigraph computes. Only the tests, the smoke
+ * check and the benchmark's CPU-baseline leg may load this library; the
+ * GPU product path never calls it and shares no code with it.
+ *
+ * Paper: "Scalable Edge Clustering of Dynamic Graphs via Weighted Line
+ * Graphs" (arXiv 2311.10337). Passages followed:
+ *   - dynamic multigraph model, incidence sets E_i, degree d_i  (Sec. 1.2.1)
+ *   - undirected line graph: line-graph nodes are the temporal edges,
+ *     adjacent when they share a vertex                          (Sec. 1.2.2)
+ *   - node-local formation L = union_i L(i)                      (Sec. 2, Def. 2)
+ *   - skeleton L* = union of node-local MSTs, and for |t_a-t_b|
+ *     weights the node-local MST is the path through the
+ *     time-sorted incidence list                                 (Alg. 3; Sec. 5.3)
+ *   - hierarchical clustering: MST, sort, union-find dendrogram,
+ *     condense with M, extract by stability ("volume")           (Alg. 1, Alg. 4)
+ *   - weight-filtered connectivity and tie-breaking by a
+ *     perturbation that fixes a deterministic order            (App. A, Thm 1-3)
+ *
+ * Readings where the paper is silent or garbled (listed again in the design
+ * notes):
+ *   R1 record order e < f  <=>  (t_e, e) < (t_f, f), ids = input indices.
+ *   R2 line-graph edge {a,b}: tail = <-min, head = <-max, w = t_head - t_tail;
+ *      a pair sharing both endpoints is ONE edge.
+ *   R3 canonical key K = (w, head, 2^32-1-tail), lexicographic; keys are
+ *      distinct, so the minimum spanning forest is unique.
+ *   R4 forest: MSF + a virtual ROOT (id n+m) at w = infinity, lambda = 0.
+ *   R5 lambda(w) = floor(2^63 / max(2w,1)) (u64); stability is exact u128.
+ *   R6 condensing follows HDBSCAN (Campello et al. 2013, to which the paper
+ *      defers): a split with both children >= M starts two clusters; one
+ *      small child sheds its points; two small children end the cluster.
+ *      At ROOT: components < M shed at lambda 0; if >= 2 components are
+ *      >= M each starts a cluster at lambda 0; if exactly 1, ROOT continues
+ *      into it.
+ *   R7 excess-of-mass selection, ties keep the parent, ROOT never selected;
+ *      label = the selected cluster above a point's exit cluster, else -1;
+ *      labels numbered by ascending minimum member id.
+ *
+ * Output conventions (identical to the GPU library's documented ones):
+ *   MSF rows (tail, head, w) in ascending K; m = n - (#components).
+ *   Dendrogram row k creates node n+k: (left=min child, right=max child, w, size).
+ *   Cluster id = dendrogram node id where the cluster is born, ROOT = n+m;
+ *   cluster rows in ascending id (ROOT last).
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef unsigned __int128 u128;
+
+enum { OR_OK = 0, OR_EINVAL = -1, OR_ESELFLOOP = -2, OR_ERANGE = -3, OR_ENOMEM = -4 };
+
+#define NONE32 0xffffffffu
+
+/* ------------------------------------------------------------------ */
+/* O0: validation                                                      */
+/* ------------------------------------------------------------------ */
+int oracle_validate(int64_t n, const int32_t *src, const int32_t *dst, const int64_t *t, int64_t V) {
+  if (n < 0 || n > 2147483647LL || V < 0) return OR_EINVAL;
+  if (n == 0) return OR_OK;
+  int64_t tmin = t[0], tmax = t[0];
+  for (int64_t i = 0; i < n; i++) {
+    if (src[i] < 0 || dst[i] < 0 || (int64_t)src[i] >= V || (int64_t)dst[i] >= V) return OR_ERANGE;
+    if (src[i] == dst[i]) return OR_ESELFLOOP;
+    if (t[i] < tmin) tmin = t[i];
+    if (t[i] > tmax) tmax = t[i];
+  }
+  if ((u128)((__int128)tmax - (__int128)tmin) >= ((u128)1 << 62)) return OR_ERANGE;
+  return OR_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* Line-graph edges and the canonical key                              */
+/* ------------------------------------------------------------------ */
+typedef struct {
+  int64_t w;
+  uint32_t tail, head;
+} lg_edge;
+
+static const int64_t *g_t; /* timestamps for the record order in qsort callbacks */
+
+/* R1: strict total order on records */
+static int rec_before(uint32_t a, uint32_t b) {
+  if (g_t[a] != g_t[b]) return g_t[a] < g_t[b];
+  return a < b;
+}
+
+static lg_edge make_edge(uint32_t a, uint32_t b) {
+  lg_edge e;
+  if (rec_before(a, b)) { e.tail = a; e.head = b; }
+  else { e.tail = b; e.head = a; }
+  e.w = g_t[e.head] - g_t[e.tail];
+  return e;
+}
+
+/* R3: K = (w, head, 2^32-1-tail) */
+static int cmp_key(const void *pa, const void *pb) {
+  const lg_edge *a = (const lg_edge *)pa, *b = (const lg_edge *)pb;
+  if (a->w != b->w) return a->w < b->w ? -1 : 1;
+  if (a->head != b->head) return a->head < b->head ? -1 : 1;
+  if (a->tail != b->tail) return a->tail > b->tail ? -1 : 1; /* larger tail = smaller key */
+  return 0;
+}
+
+/* incidence lists E_i (Sec. 1.2.1): CSR of record ids per vertex, ascending id */
+static int build_incidence(int64_t n, const int32_t *src, const int32_t *dst, int64_t V,
+                           int64_t **off_out, uint32_t **lst_out) {
+  int64_t *off = (int64_t *)calloc((size_t)V + 1, sizeof(int64_t));
+  uint32_t *lst = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(2 * n + 1));
+  int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(V + 1));
+  if (!off || !lst || !fill) { free(off); free(lst); free(fill); return OR_ENOMEM; }
+  for (int64_t i = 0; i < n; i++) { off[src[i] + 1]++; off[dst[i] + 1]++; }
+  for (int64_t v = 0; v < V; v++) off[v + 1] += off[v];
+  memcpy(fill, off, sizeof(int64_t) * (size_t)V);
+  for (int64_t i = 0; i < n; i++) {
+    lst[fill[src[i]]++] = (uint32_t)i;
+    lst[fill[dst[i]]++] = (uint32_t)i;
+  }
+  free(fill);
+  *off_out = off;
+  *lst_out = lst;
+  return OR_OK;
+}
+
+/*
+ * Tier A, the definition (Sec. 1.2.2 undirected line graph; Sec. 2 formula for
+ * |F| = sum_i C(d_i,2) before de-duplication): every unordered pair of distinct
+ * records sharing a vertex is one line-graph edge (R2). A pair is emitted at
+ * the smallest vertex the two records share, so pairs sharing both endpoints
+ * appear once. If out == NULL only the count is returned.
+ */
+int64_t oracle_full_line_graph(int64_t n, const int32_t *src, const int32_t *dst, const int64_t *t,
+                               int64_t V, lg_edge *out) {
+  int64_t *off;
+  uint32_t *lst;
+  if (build_incidence(n, src, dst, V, &off, &lst)) return OR_ENOMEM;
+  g_t = t;
+  int64_t cnt = 0;
+  for (int64_t x = 0; x < V; x++) {
+    for (int64_t i = off[x]; i < off[x + 1]; i++)
+      for (int64_t j = i + 1; j < off[x + 1]; j++) {
+        uint32_t a = lst[i], b = lst[j];
+        /* smallest shared vertex of the two records */
+        int64_t best = -1;
+        int32_t ea[2] = {src[a], dst[a]}, eb[2] = {src[b], dst[b]};
+        for (int p = 0; p < 2; p++)
+          for (int q = 0; q < 2; q++)
+            if (ea[p] == eb[q] && (best < 0 || ea[p] < best)) best = ea[p];
+        if (best != x) continue;
+        if (out) out[cnt] = make_edge(a, b);
+        cnt++;
+      }
+  }
+  free(off);
+  free(lst);
+  return cnt;
+}
+
+/*
+ * Tier B, the method's own steps (Alg. 3 with the undirected node-local MST of
+ * Sec. 5.3): per vertex, sort E_i by the record order R1, emit each
+ * consecutive pair. Emits exactly sum_i (d_i - 1) over vertices with d_i >= 1
+ * rows, i.e. 2n - V'. Rows are in vertex order, then list order.
+ */
+static int cmp_rec(const void *pa, const void *pb) {
+  uint32_t a = *(const uint32_t *)pa, b = *(const uint32_t *)pb;
+  if (a == b) return 0;
+  return rec_before(a, b) ? -1 : 1;
+}
+
+int64_t oracle_skeleton(int64_t n, const int32_t *src, const int32_t *dst, const int64_t *t, int64_t V,
+                        lg_edge *out) {
+  int64_t *off;
+  uint32_t *lst;
+  if (build_incidence(n, src, dst, V, &off, &lst)) return OR_ENOMEM;
+  g_t = t;
+  int64_t cnt = 0;
+  for (int64_t x = 0; x < V; x++) {
+    int64_t d = off[x + 1] - off[x];
+    if (d < 2) continue;
+    qsort(lst + off[x], (size_t)d, sizeof(uint32_t), cmp_rec); /* "Sort E_i by time" */
+    for (int64_t k = off[x] + 1; k < off[x + 1]; k++) {
+      if (out) out[cnt] = make_edge(lst[k - 1], lst[k]);
+      cnt++;
+    }
+  }
+  free(off);
+  free(lst);
+  return cnt;
+}
+
+/* plain union-find with path halving */
+static uint32_t uf_find(uint32_t *par, uint32_t x) {
+  while (par[x] != x) {
+    par[x] = par[par[x]];
+    x = par[x];
+  }
+  return x;
+}
+
+/*
+ * Alg. 1 steps 1-2: Kruskal in ascending K (R3) over the given line-graph
+ * edges (sorted in place). Writes the MSF rows in ascending K; returns m.
+ */
+int64_t oracle_kruskal(int64_t n, int64_t E, lg_edge *edges, const int64_t *t, uint32_t *msf_tail,
+                       uint32_t *msf_head, int64_t *msf_w) {
+  g_t = t;
+  qsort(edges, (size_t)E, sizeof(lg_edge), cmp_key);
+  uint32_t *par = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n ? n : 1));
+  if (!par) return OR_ENOMEM;
+  for (int64_t i = 0; i < n; i++) par[i] = (uint32_t)i;
+  int64_t m = 0;
+  for (int64_t k = 0; k < E; k++) {
+    uint32_t a = uf_find(par, edges[k].tail), b = uf_find(par, edges[k].head);
+    if (a == b) continue;
+    par[a] = b;
+    msf_tail[m] = edges[k].tail;
+    msf_head[m] = edges[k].head;
+    msf_w[m] = edges[k].w;
+    m++;
+  }
+  free(par);
+  return m;
+}
+
+/*
+ * Alg. 1 step 3: dendrogram by union-find over the MSF rows in order. Row k
+ * merges the sets holding tail and head; the new node is n+k with
+ * left = min(child ids), right = max(child ids), w, size = sum.
+ */
+int oracle_dendrogram(int64_t n, int64_t m, const uint32_t *msf_tail, const uint32_t *msf_head,
+                      const int64_t *msf_w, uint32_t *left, uint32_t *right, int64_t *lw,
+                      uint32_t *size) {
+  uint32_t *par = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n ? n : 1));
+  uint32_t *node = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n ? n : 1));
+  uint32_t *sz = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n ? n : 1));
+  if (!par || !node || !sz) { free(par); free(node); free(sz); return OR_ENOMEM; }
+  for (int64_t i = 0; i < n; i++) { par[i] = (uint32_t)i; node[i] = (uint32_t)i; sz[i] = 1; }
+  for (int64_t k = 0; k < m; k++) {
+    uint32_t a = uf_find(par, msf_tail[k]), b = uf_find(par, msf_head[k]);
+    if (a == b) { free(par); free(node); free(sz); return OR_EINVAL; } /* not a forest */
+    uint32_t na = node[a], nb = node[b];
+    left[k] = na < nb ? na : nb;
+    right[k] = na < nb ? nb : na;
+    lw[k] = msf_w[k];
+    size[k] = sz[a] + sz[b];
+    par[a] = b;
+    sz[b] = size[k];
+    node[b] = (uint32_t)(n + k);
+  }
+  free(par); free(node); free(sz);
+  return OR_OK;
+}
+
+/* R5 */
+static uint64_t lam(int64_t w) {
+  if (w <= 0) return (uint64_t)1 << 63;
+  return ((uint64_t)1 << 63) / (2 * (uint64_t)w);
+}
+
+typedef struct {
+  int64_t n_clusters; /* rows written, ROOT included (last) */
+  int64_t n_labels;
+} condense_counts;
+
+/*
+ * Alg. 1 steps 4-5 (condense with M, extract by stability), HDBSCAN
+ * semantics per R4-R7. Inputs: dendrogram rows. Outputs: per point the
+ * cluster it leaves and the lambda at which it leaves; cluster rows in
+ * ascending id; labels. Arrays cl_* must hold 2*floor(n/M)+1 rows.
+ */
+int oracle_condense(int64_t n, int64_t m, const uint32_t *left, const uint32_t *right,
+                    const int64_t *lw, const uint32_t *size, int64_t M, uint32_t *pt_cluster,
+                    uint64_t *pt_lambda, uint32_t *cl_id, uint32_t *cl_parent, uint32_t *cl_size,
+                    uint64_t *cl_lambda_birth, uint64_t *cl_stab_hi, uint64_t *cl_stab_lo,
+                    uint8_t *cl_selected, int32_t *labels, condense_counts *counts) {
+  if (M < 2) return OR_EINVAL;
+  int64_t N = n + m;            /* dendrogram nodes */
+  uint32_t ROOT = (uint32_t)N;  /* virtual root */
+  uint32_t *parent = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(N + 1));
+  uint32_t *nsize = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(N + 1));
+  uint32_t *clus = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(N + 1)); /* cluster of a big node */
+  uint32_t *stack = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(N + 1));
+  uint8_t *is_cluster = (uint8_t *)calloc((size_t)(N + 1), 1);
+  uint32_t *cpar = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(N + 1)); /* parent cluster, by id */
+  uint64_t *cbirth = (uint64_t *)calloc((size_t)(N + 1), sizeof(uint64_t));
+  u128 *stab = (u128 *)calloc((size_t)(N + 1), sizeof(u128));
+  if (!parent || !nsize || !clus || !stack || !is_cluster || !cpar || !cbirth || !stab) {
+    free(parent); free(nsize); free(clus); free(stack); free(is_cluster); free(cpar); free(cbirth); free(stab);
+    return OR_ENOMEM;
+  }
+  for (int64_t x = 0; x <= N; x++) { parent[x] = NONE32; clus[x] = NONE32; cpar[x] = NONE32; }
+  for (int64_t x = 0; x < n; x++) nsize[x] = 1;
+  for (int64_t k = 0; k < m; k++) {
+    nsize[n + k] = size[k];
+    parent[left[k]] = (uint32_t)(n + k);
+    parent[right[k]] = (uint32_t)(n + k);
+  }
+  nsize[ROOT] = (uint32_t)n;
+  is_cluster[ROOT] = 1;
+  cbirth[ROOT] = 0;
+
+  /* exits: every leaf under node y leaves cluster C at lambda L */
+#define SHED(y, C, L)                                                      \
+  do {                                                                     \
+    int64_t sp_ = 0;                                                       \
+    stack[sp_++] = (y);                                                    \
+    while (sp_) {                                                          \
+      uint32_t z_ = stack[--sp_];                                          \
+      if (z_ < (uint32_t)n) { pt_cluster[z_] = (C); pt_lambda[z_] = (L); } \
+      else { stack[sp_++] = left[z_ - n]; stack[sp_++] = right[z_ - n]; }  \
+    }                                                                      \
+  } while (0)
+
+  /* R6 at ROOT: count components of size >= M */
+  int64_t nbig = 0;
+  for (int64_t x = 0; x < N; x++)
+    if (parent[x] == NONE32 && nsize[x] >= (uint64_t)M) nbig++;
+  /* work list of (big node, its cluster) processed top-down */
+  uint32_t *wl_node = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(N + 1));
+  int64_t wl = 0;
+  if (!wl_node) { free(parent); free(nsize); free(clus); free(stack); free(is_cluster); free(cpar); free(cbirth); free(stab); return OR_ENOMEM; }
+  for (int64_t x = 0; x < N; x++) {
+    if (parent[x] != NONE32) continue;
+    if (nsize[x] < (uint64_t)M) { SHED((uint32_t)x, ROOT, 0); continue; }
+    if (nbig >= 2) {
+      is_cluster[x] = 1; cpar[x] = ROOT; cbirth[x] = 0; clus[x] = (uint32_t)x;
+    } else {
+      clus[x] = ROOT;
+    }
+    wl_node[wl++] = (uint32_t)x;
+  }
+  while (wl) {
+    uint32_t x = wl_node[--wl];
+    uint32_t C = clus[x];
+    int64_t k = (int64_t)x - n;
+    uint32_t c1 = left[k], c2 = right[k];
+    uint64_t L = lam(lw[k]);
+    int b1 = nsize[c1] >= (uint64_t)M, b2 = nsize[c2] >= (uint64_t)M;
+    if (b1 && b2) {
+      is_cluster[c1] = 1; cpar[c1] = C; cbirth[c1] = L; clus[c1] = c1;
+      is_cluster[c2] = 1; cpar[c2] = C; cbirth[c2] = L; clus[c2] = c2;
+      wl_node[wl++] = c1;
+      wl_node[wl++] = c2;
+    } else if (b1) {
+      SHED(c2, C, L);
+      clus[c1] = C;
+      wl_node[wl++] = c1;
+    } else if (b2) {
+      SHED(c1, C, L);
+      clus[c2] = C;
+      wl_node[wl++] = c2;
+    } else {
+      SHED(x, C, L);
+    }
+  }
+#undef SHED
+  free(wl_node);
+
+  /* O8 stability: points that leave C, and child clusters born inside C */
+  for (int64_t p = 0; p < n; p++) {
+    uint32_t C = pt_cluster[p];
+    stab[C] += (u128)(pt_lambda[p] - cbirth[C]);
+  }
+  for (int64_t x = 0; x < N; x++) {
+    if (!is_cluster[x]) continue;
+    uint32_t P = cpar[x];
+    stab[P] += (u128)nsize[x] * (u128)(cbirth[x] - cbirth[P]);
+  }
+
+  /* cluster rows in ascending id, ROOT last */
+  int64_t nc = 0;
+  uint32_t *row = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(N + 1));
+  for (int64_t x = 0; x <= N; x++) {
+    if (!is_cluster[x]) continue;
+    row[x] = (uint32_t)nc;
+    cl_id[nc] = (uint32_t)x;
+    cl_parent[nc] = (x == N) ? NONE32 : cpar[x];
+    cl_size[nc] = nsize[x];
+    cl_lambda_birth[nc] = cbirth[x];
+    cl_stab_hi[nc] = (uint64_t)(stab[x] >> 64);
+    cl_stab_lo[nc] = (uint64_t)stab[x];
+    nc++;
+  }
+
+  /* O9 excess of mass: explicit post-order over the cluster tree */
+  int64_t *child_cnt = (int64_t *)calloc((size_t)nc, sizeof(int64_t));
+  u128 *best = (u128 *)calloc((size_t)nc, sizeof(u128));
+  u128 *childsum = (u128 *)calloc((size_t)nc, sizeof(u128));
+  uint8_t *sel = (uint8_t *)calloc((size_t)nc, 1);
+  int64_t *pending = (int64_t *)calloc((size_t)nc, sizeof(int64_t));
+  int64_t *queue = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nc ? nc : 1));
+  for (int64_t r = 0; r < nc - 1; r++) child_cnt[row[cl_parent[r]]]++;
+  int64_t qh = 0, qt = 0;
+  for (int64_t r = 0; r < nc; r++) {
+    pending[r] = child_cnt[r];
+    if (pending[r] == 0) queue[qt++] = r;
+  }
+  while (qh < qt) {
+    int64_t r = queue[qh++];
+    u128 S = ((u128)cl_stab_hi[r] << 64) | cl_stab_lo[r];
+    if (child_cnt[r] == 0) { sel[r] = 1; best[r] = S; }
+    else if (childsum[r] > S) { sel[r] = 0; best[r] = childsum[r]; }
+    else { sel[r] = 1; best[r] = S; }
+    if (r == nc - 1) continue; /* ROOT has no parent */
+    int64_t pr = row[cl_parent[r]];
+    childsum[pr] += best[r];
+    if (--pending[pr] == 0) queue[qt++] = pr;
+  }
+  sel[nc - 1] = 0; /* ROOT is never selected */
+  /* final choice: selected with no selected proper ancestor (ROOT excluded) */
+  for (int64_t r = 0; r < nc; r++) {
+    int chosen = sel[r];
+    if (chosen) {
+      uint32_t a = cl_parent[r];
+      while (a != NONE32 && a != ROOT) {
+        if (sel[row[a]]) { chosen = 0; break; }
+        a = cl_parent[row[a]];
+      }
+    }
+    cl_selected[r] = (uint8_t)chosen;
+  }
+  /* O10 labels: the chosen cluster on the path from the exit cluster to ROOT */
+  int32_t *lab_of_row = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nc ? nc : 1));
+  int64_t *minmem = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nc ? nc : 1));
+  for (int64_t r = 0; r < nc; r++) { lab_of_row[r] = -1; minmem[r] = INT64_MAX; }
+  for (int64_t p = 0; p < n; p++) {
+    uint32_t a = pt_cluster[p];
+    int64_t got = -1;
+    while (a != NONE32 && a != ROOT) {
+      if (cl_selected[row[a]]) { got = row[a]; break; }
+      a = cl_parent[row[a]];
+    }
+    labels[p] = (int32_t)got; /* temporarily the row */
+    if (got >= 0 && p < minmem[got]) minmem[got] = p;
+  }
+  /* number chosen clusters by ascending minimum member id */
+  int64_t L = 0;
+  for (int64_t p = 0; p < n; p++) {
+    int32_t r = labels[p];
+    if (r >= 0 && minmem[r] == p) lab_of_row[r] = (int32_t)L++;
+  }
+  for (int64_t p = 0; p < n; p++)
+    if (labels[p] >= 0) labels[p] = lab_of_row[labels[p]];
+  counts->n_clusters = nc;
+  counts->n_labels = L;
+
+  free(lab_of_row); free(minmem);
+  free(child_cnt); free(best); free(childsum); free(sel); free(pending); free(queue); free(row);
+  free(parent); free(nsize); free(clus); free(stack); free(is_cluster); free(cpar); free(cbirth); free(stab);
+  return OR_OK;
+}
+
+/*
+ * Whole pipeline (Alg. 4): tier 0 = definition (full line graph), tier 1 =
+ * skeleton (Alg. 3). Output arrays are caller-allocated: msf_* and sl_* hold
+ * n-1 rows (n >= 1), cl_* hold 2*floor(n/M)+1 rows. hdr = {status, m,
+ * n_clusters, n_labels}.
+ */
+int oracle_cluster(int64_t n, const int32_t *src, const int32_t *dst, const int64_t *t, int64_t V,
+                   int64_t M, int tier, uint32_t *msf_tail, uint32_t *msf_head, int64_t *msf_w,
+                   uint32_t *sl_left, uint32_t *sl_right, int64_t *sl_w, uint32_t *sl_size,
+                   uint32_t *pt_cluster, uint64_t *pt_lambda, uint32_t *cl_id, uint32_t *cl_parent,
+                   uint32_t *cl_size, uint64_t *cl_lambda_birth, uint64_t *cl_stab_hi,
+                   uint64_t *cl_stab_lo, uint8_t *cl_selected, int32_t *labels, int64_t *hdr) {
+  hdr[0] = hdr[1] = hdr[2] = hdr[3] = 0;
+  if (M < 2) { hdr[0] = OR_EINVAL; return OR_EINVAL; }
+  int rc = oracle_validate(n, src, dst, t, V);
+  if (rc) { hdr[0] = rc; return rc; }
+  int64_t E = tier == 0 ? oracle_full_line_graph(n, src, dst, t, V, NULL)
+                        : oracle_skeleton(n, src, dst, t, V, NULL);
+  if (E < 0) { hdr[0] = (int)E; return (int)E; }
+  lg_edge *edges = (lg_edge *)malloc(sizeof(lg_edge) * (size_t)(E ? E : 1));
+  if (!edges) { hdr[0] = OR_ENOMEM; return OR_ENOMEM; }
+  if (tier == 0) oracle_full_line_graph(n, src, dst, t, V, edges);
+  else oracle_skeleton(n, src, dst, t, V, edges);
+  int64_t m = oracle_kruskal(n, E, edges, t, msf_tail, msf_head, msf_w);
+  free(edges);
+  if (m < 0) { hdr[0] = (int)m; return (int)m; }
+  rc = oracle_dendrogram(n, m, msf_tail, msf_head, msf_w, sl_left, sl_right, sl_w, sl_size);
+  if (rc) { hdr[0] = rc; return rc; }
+  condense_counts cc = {0, 0};
+  rc = oracle_condense(n, m, sl_left, sl_right, sl_w, sl_size, M, pt_cluster, pt_lambda, cl_id,
+                       cl_parent, cl_size, cl_lambda_birth, cl_stab_hi, cl_stab_lo, cl_selected,
+                       labels, &cc);
+  if (rc) { hdr[0] = rc; return rc; }
+  hdr[1] = m;
+  hdr[2] = cc.n_clusters;
+  hdr[3] = cc.n_labels;
+  return OR_OK;
+}

@@ -1,0 +1,44 @@
+"""Planted mistakes in the oracle (on the CPU): each mutated copy of the oracle's
+C source must fail at least one pin in test_oracle_pins.py. This shows the pins
+would catch a dropped term, a wrong sign or index, or a transposed operand."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+SRC = os.path.join(ROOT, "oracle", "ce_oracle.c")
+
+MUTANTS = [
+    ("key tie on tail reversed", "a->tail > b->tail ? -1 : 1", "a->tail < b->tail ? -1 : 1"),
+    ("record order ties by descending id", "  return a < b;\n}", "  return a > b;\n}"),
+    ("weight sign flipped", "e.w = g_t[e.head] - g_t[e.tail];", "e.w = g_t[e.tail] - g_t[e.head];"),
+    ("skeleton drops first pair", "for (int64_t k = off[x] + 1; k < off[x + 1]; k++)",
+     "for (int64_t k = off[x] + 2; k < off[x + 1]; k++)"),
+    ("dendrogram children transposed", "left[k] = na < nb ? na : nb;", "left[k] = na < nb ? nb : na;"),
+    ("dendrogram size off by one", "size[k] = sz[a] + sz[b];", "size[k] = sz[a] + sz[b] - 1;"),
+    ("lambda drops the factor 2", "/ (2 * (uint64_t)w);", "/ ((uint64_t)w);"),
+    ("stability drops child-cluster term", "stab[P] += (u128)nsize[x] *", "stab[P] += (u128)0 *"),
+    ("EOM ties go to children", "else if (childsum[r] > S)", "else if (childsum[r] >= S)"),
+    ("big child test strict", "int b1 = nsize[c1] >= (uint64_t)M", "int b1 = nsize[c1] > (uint64_t)M"),
+    ("root rule: one big component becomes a cluster", "if (nbig >= 2) {", "if (nbig >= 1) {"),
+    ("labels numbered by maximum member", "if (got >= 0 && p < minmem[got]) minmem[got] = p;",
+     "if (got >= 0 && (minmem[got] == INT64_MAX || p > minmem[got])) minmem[got] = p;"),
+]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pins_catch_planted_mistake(name, old, new, tmp_path):
+    text = open(SRC).read()
+    assert text.count(old) == 1, "mutation anchor not unique: %s" % name
+    mut = tmp_path / "ce_oracle_mut.c"
+    mut.write_text(text.replace(old, new))
+    lib = tmp_path / "liboracle_mut.so"
+    subprocess.check_call(["gcc", "-O1", "-shared", "-fPIC", "-o", str(lib), str(mut)])
+    env = dict(os.environ, CE_ORACLE_LIB=str(lib))
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py"), "-k", "not four_records_full"],
+                       cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
+    assert r.returncode != 0, "planted mistake '%s' passed every pin:\n%s" % (name, r.stdout[-2000:])
