@@ -1,0 +1,124 @@
+/*
+ * ce.h -- C ABI of the MI355X (gfx950) edge-clustering library libce.so.
+ *
+ * Computes the hierarchical edge clustering of a dynamic multigraph
+ * (arXiv 2311.10337, "Scalable Edge Clustering of Dynamic Graphs via
+ * Weighted Line Graphs"), undirected variant: line-graph nodes are the
+ * temporal edges (Sec. 1.2.2), two are adjacent when they share a vertex,
+ * with weight |t_a - t_b|. The library
+ *   1. groups each vertex's incident temporal edges and sorts them by time
+ *      ("Generate adjacency list", "Sort E_i by time": Alg. 3, Alg. 2),
+ *   2. emits the line-graph skeleton L* = union of node-local MSTs, which for
+ *      |t_a - t_b| weights is the path through each time-sorted list
+ *      (Alg. 3; Sec. 5.3), never forming the line graph,
+ *   3. runs Alg. 1 on L* (Alg. 4): minimum spanning forest, sorted MSF,
+ *      union-find dendrogram, condensing with the minimum cluster size M,
+ *      extraction by stability (HDBSCAN excess of mass).
+ * The skeleton has the same weighted connectivity as the full line graph
+ * (App. A, Thm 3), so every output equals that of the full line graph.
+ *
+ * Conventions (all ids 0-based; a temporal edge's id is its input index):
+ *   record order  e < f  iff  (t_e, e) < (t_f, f)
+ *   line-graph edge {a,b}: tail = <-min, head = <-max, w = t_head - t_tail
+ *   canonical key K = (w, head, 2^32-1-tail), lexicographic -> unique MSF
+ *   MSF rows (tail, head, w) in ascending K;  m = n - #components
+ *   dendrogram row k creates node n+k: left = min(child ids),
+ *     right = max(child ids), w, size (leaf nodes are the records 0..n-1)
+ *   lambda(w) = floor(2^63 / max(2w,1)); virtual ROOT = node n+m, lambda 0
+ *   clusters: id = dendrogram node at which the cluster is born; rows in
+ *     ascending id, ROOT last; stability exact unsigned 128-bit (hi, lo)
+ *   labels: -1 = noise, else 0..L-1 numbered by ascending minimum member id
+ *
+ * Memory: every pointer argument except `params`, `out` (the struct itself),
+ * `counts` and `workspace_bytes` is a DEVICE pointer on the current HIP
+ * device. Inputs are read-only and owned by the caller. Outputs are owned by
+ * the caller and must hold the documented row counts. The library keeps
+ * nothing between calls.
+ */
+#ifndef CE_H
+#define CE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  CE_OK = 0,
+  CE_EINVAL = -1,     /* bad argument: null pointer, n < 0, M < 2, unknown mode/flags */
+  CE_ESELFLOOP = -2,  /* an input record has src == dst (the model excludes self loops, Sec. 1.2.1) */
+  CE_ERANGE = -3,     /* vertex id outside [0, V), or time span too wide for the packed key */
+  CE_ENOMEM = -4,     /* workspace too small or device allocation failed */
+  CE_EDEVICE = -5,    /* a HIP runtime call failed */
+  CE_EBUSY = -6       /* serving queue full */
+} ce_status;
+
+typedef enum { CE_MODE_UNDIRECTED = 0 } ce_mode;
+
+typedef struct {
+  uint32_t struct_size;      /* = sizeof(ce_params) */
+  uint32_t mode;             /* CE_MODE_UNDIRECTED */
+  int64_t min_cluster_size;  /* M >= 2 (Alg. 1 input) */
+  int64_t num_vertices;      /* V > 0; vertex ids must lie in [0, V) */
+  uint32_t flags;            /* must be 0 */
+  uint32_t reserved;         /* must be 0 */
+} ce_params;
+
+/* Caller-allocated DEVICE output buffers. Any pointer may be NULL to skip
+ * that output. Row capacities: rows of msf_* and sl_* >= max(n-1, 1);
+ * pt_* and labels >= n; cl_* >= ce_max_clusters(n, M). */
+typedef struct {
+  uint32_t *msf_tail, *msf_head;
+  int64_t *msf_w;
+  uint32_t *sl_left, *sl_right;
+  int64_t *sl_w;
+  uint32_t *sl_size;
+  uint32_t *pt_cluster;   /* cluster each record leaves (its exit), by record id */
+  uint64_t *pt_lambda;    /* lambda at which it leaves */
+  uint32_t *cl_id, *cl_parent, *cl_size; /* parent of ROOT = 0xFFFFFFFF */
+  uint64_t *cl_lambda_birth;
+  uint64_t *cl_stab_hi, *cl_stab_lo;
+  uint8_t *cl_selected;   /* 1 = the cluster is one of the output labels */
+  int32_t *labels;
+} ce_result;
+
+/* Host-side counts filled when the call returns. */
+typedef struct {
+  int64_t m;           /* MSF / dendrogram rows */
+  int64_t n_clusters;  /* cluster rows, ROOT included */
+  int64_t n_labels;    /* L */
+} ce_counts;
+
+/* Upper bound on cluster rows, ROOT included: 2*floor(n/M) + 1. Pure. */
+int64_t ce_max_clusters(int64_t n, int64_t min_cluster_size);
+
+/* Bytes of device workspace ce_cluster_edges needs for n records over V
+ * vertices. Pure host function; returns 0 on invalid arguments. */
+size_t ce_workspace_bytes(int64_t n, int64_t num_vertices, const ce_params *params);
+
+/*
+ * Cluster the n temporal edges (src[i], dst[i], t[i]) (Alg. 4).
+ *   src, dst : int32[n], vertex ids in [0, V), src[i] != dst[i]
+ *   t        : int64[n], seconds; max(t) - min(t) must satisfy
+ *              bits(max-min) + bits(n-1) + 1 <= 64 (else CE_ERANGE)
+ *   workspace: device buffer of >= ce_workspace_bytes(...) bytes, or NULL to
+ *              let the library allocate (stream-ordered) and free it
+ *   stream   : a hipStream_t (NULL = default stream)
+ * Runs on `stream` and returns when every output is written (it waits on the
+ * stream). Returns CE_OK or an error; on a data error (CE_ESELFLOOP,
+ * CE_ERANGE) no output is written. Reentrant: concurrent calls need
+ * distinct workspaces. ce_last_error() gives a message.
+ */
+ce_status ce_cluster_edges(const int32_t *src, const int32_t *dst, const int64_t *t, int64_t n,
+                           const ce_params *params, const ce_result *out, ce_counts *counts,
+                           void *workspace, size_t workspace_bytes, void *stream);
+
+/* Thread-local text of the last error on this thread (never NULL). */
+const char *ce_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CE_H */

@@ -1,0 +1,185 @@
+"""MI355X-native hierarchical edge clustering of dynamic graphs (arXiv 2311.10337).
+
+Thin Python binding over the C ABI of ``libce.so`` (see ``include/ce.h``): it
+allocates output tensors with PyTorch on the GPU, passes raw device pointers
+and the current HIP stream, and returns the trimmed tensors. Every step of the
+computation runs in the library's HIP kernels; there is no CPU fallback, and a
+missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import NamedTuple, Optional
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libce.so")
+
+CE_OK, CE_EINVAL, CE_ESELFLOOP, CE_ERANGE, CE_ENOMEM, CE_EDEVICE, CE_EBUSY = 0, -1, -2, -3, -4, -5, -6
+CE_MODE_UNDIRECTED = 0
+NONE32 = 0xFFFFFFFF
+
+
+class CeParams(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("mode", ctypes.c_uint32), ("min_cluster_size", ctypes.c_int64),
+                ("num_vertices", ctypes.c_int64), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+_RESULT_FIELDS = ["msf_tail", "msf_head", "msf_w", "sl_left", "sl_right", "sl_w", "sl_size", "pt_cluster",
+                  "pt_lambda", "cl_id", "cl_parent", "cl_size", "cl_lambda_birth", "cl_stab_hi", "cl_stab_lo",
+                  "cl_selected", "labels"]
+
+
+class CeResult(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_void_p) for f in _RESULT_FIELDS]
+
+
+class CeCounts(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n_clusters", ctypes.c_int64), ("n_labels", ctypes.c_int64)]
+
+
+_EXPORTS = ["ce_cluster_edges", "ce_workspace_bytes", "ce_max_clusters", "ce_last_error"]
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libce.so; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise RuntimeError("libce.so is not built (%s); run __graft_entry__.build()" % path)
+        lib = ctypes.CDLL(path)
+        lib.ce_cluster_edges.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int64, ctypes.POINTER(CeParams),
+                                                                 ctypes.POINTER(CeResult), ctypes.POINTER(CeCounts),
+                                                                 ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+        lib.ce_cluster_edges.restype = ctypes.c_int
+        lib.ce_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(CeParams)]
+        lib.ce_workspace_bytes.restype = ctypes.c_size_t
+        lib.ce_max_clusters.argtypes = [ctypes.c_int64, ctypes.c_int64]
+        lib.ce_max_clusters.restype = ctypes.c_int64
+        lib.ce_last_error.argtypes = []
+        lib.ce_last_error.restype = ctypes.c_char_p
+        _lib = lib
+    return _lib
+
+
+def exported_symbols():
+    lib = load_library()
+    return {name: hasattr(lib, name) for name in _EXPORTS}
+
+
+def make_params(min_cluster_size: int, num_vertices: int) -> CeParams:
+    return CeParams(ctypes.sizeof(CeParams), CE_MODE_UNDIRECTED, int(min_cluster_size), int(num_vertices), 0, 0)
+
+
+def workspace_bytes(n: int, num_vertices: int, min_cluster_size: int) -> int:
+    p = make_params(min_cluster_size, num_vertices)
+    return int(load_library().ce_workspace_bytes(int(n), int(num_vertices), ctypes.byref(p)))
+
+
+def max_clusters(n: int, min_cluster_size: int) -> int:
+    return int(load_library().ce_max_clusters(int(n), int(min_cluster_size)))
+
+
+def last_error() -> str:
+    return load_library().ce_last_error().decode()
+
+
+class ClusterError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("ce_cluster_edges failed (%d): %s" % (status, msg))
+        self.status = status
+
+
+class Result(NamedTuple):
+    """Device tensors. u32/u64 fields are stored in int32/int64 tensors bit for bit."""
+    m: int
+    n_clusters: int
+    n_labels: int
+    msf_tail: object
+    msf_head: object
+    msf_w: object
+    sl_left: object
+    sl_right: object
+    sl_w: object
+    sl_size: object
+    pt_cluster: object
+    pt_lambda: object
+    cl_id: object
+    cl_parent: object
+    cl_size: object
+    cl_lambda_birth: object
+    cl_stab_hi: object
+    cl_stab_lo: object
+    cl_selected: object
+    labels: object
+
+
+class Outputs:
+    """Preallocated device output buffers for n records (reusable across calls)."""
+
+    def __init__(self, n: int, min_cluster_size: int, device):
+        import torch
+        R = max(n - 1, 1)
+        C = max_clusters(n, min_cluster_size)
+        i32, i64, u8 = torch.int32, torch.int64, torch.uint8
+        e = lambda k, dt: torch.empty(max(k, 1), dtype=dt, device=device)
+        self.n, self.C = n, C
+        self.t = {"msf_tail": e(R, i32), "msf_head": e(R, i32), "msf_w": e(R, i64), "sl_left": e(R, i32),
+                  "sl_right": e(R, i32), "sl_w": e(R, i64), "sl_size": e(R, i32), "pt_cluster": e(n, i32),
+                  "pt_lambda": e(n, i64), "cl_id": e(C, i32), "cl_parent": e(C, i32), "cl_size": e(C, i32),
+                  "cl_lambda_birth": e(C, i64), "cl_stab_hi": e(C, i64), "cl_stab_lo": e(C, i64),
+                  "cl_selected": e(C, u8), "labels": e(n, i32)}
+        self.struct = CeResult(**{f: ctypes.c_void_p(self.t[f].data_ptr()) for f in _RESULT_FIELDS})
+
+
+def cluster_edges(src, dst, t, min_cluster_size: int, num_vertices: int, outputs: Optional[Outputs] = None,
+                  workspace=None, stream=None) -> Result:
+    """Cluster temporal edges (src[i], dst[i], t[i]) held in GPU tensors (int32, int32, int64).
+
+    Runs ``ce_cluster_edges`` on the current (or given) HIP stream and returns
+    when the results are written. ``workspace`` may be a uint8 device tensor of
+    at least ``workspace_bytes(...)`` bytes; otherwise the library allocates.
+    """
+    import torch
+    lib = load_library()
+    for name, x, dt in (("src", src, torch.int32), ("dst", dst, torch.int32), ("t", t, torch.int64)):
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == dt and x.is_contiguous() and x.dim() == 1):
+            raise TypeError("%s must be a contiguous 1-D %s GPU tensor" % (name, dt))
+    n = int(src.numel())
+    if dst.numel() != n or t.numel() != n:
+        raise ValueError("src, dst, t must have the same length")
+    if outputs is None or outputs.n < n or outputs.C < max_clusters(n, min_cluster_size):
+        outputs = Outputs(n, min_cluster_size, src.device)
+    params = make_params(min_cluster_size, num_vertices)
+    counts = CeCounts()
+    s = stream if stream is not None else torch.cuda.current_stream(src.device)
+    ws_ptr, ws_len = None, 0
+    if workspace is not None:
+        ws_ptr, ws_len = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+    st = lib.ce_cluster_edges(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                              ctypes.c_void_p(t.data_ptr()), n, ctypes.byref(params), ctypes.byref(outputs.struct),
+                              ctypes.byref(counts), ctypes.c_void_p(ws_ptr), ws_len, ctypes.c_void_p(s.cuda_stream))
+    if st != CE_OK:
+        raise ClusterError(st, last_error())
+    m, nc, nl = int(counts.m), int(counts.n_clusters), int(counts.n_labels)
+    o = outputs.t
+    rows = {f: o[f][:m] for f in ("msf_tail", "msf_head", "msf_w", "sl_left", "sl_right", "sl_w", "sl_size")}
+    pts = {f: o[f][:n] for f in ("pt_cluster", "pt_lambda", "labels")}
+    cls = {f: o[f][:nc] for f in ("cl_id", "cl_parent", "cl_size", "cl_lambda_birth", "cl_stab_hi", "cl_stab_lo",
+                                  "cl_selected")}
+    return Result(m=m, n_clusters=nc, n_labels=nl, **rows, **pts, **cls)
+
+
+_UNSIGNED = {"msf_tail": "u4", "msf_head": "u4", "sl_left": "u4", "sl_right": "u4", "sl_size": "u4",
+             "pt_cluster": "u4", "pt_lambda": "u8", "cl_id": "u4", "cl_parent": "u4", "cl_size": "u4",
+             "cl_lambda_birth": "u8", "cl_stab_hi": "u8", "cl_stab_lo": "u8"}
+
+
+def to_numpy(res: Result) -> dict:
+    """Copy a Result to host numpy arrays with the documented (unsigned) dtypes."""
+    out = {"m": res.m, "n_clusters": res.n_clusters, "n_labels": res.n_labels}
+    for f in Result._fields[3:]:
+        a = getattr(res, f).cpu().numpy()
+        out[f] = a.view(_UNSIGNED[f]) if f in _UNSIGNED else a
+    return out

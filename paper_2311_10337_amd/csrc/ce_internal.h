@@ -1,0 +1,175 @@
+// Internal declarations shared by the HIP translation units of libce.
+// gfx950 (CDNA4) only: 64-wide wavefronts, 160 KB LDS per CU.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/ce.h"
+
+namespace ce {
+
+constexpr uint32_t NONE32 = 0xffffffffu;
+constexpr uint64_t NONE64 = 0xffffffffffffffffull;
+
+// ---------------------------------------------------------------- errors
+void set_error(const std::string &msg);
+
+#define CE_HIP(call)                                                                   \
+  do {                                                                                 \
+    hipError_t e_ = (call);                                                            \
+    if (e_ != hipSuccess) {                                                            \
+      ::ce::set_error(std::string(#call " failed: ") + hipGetErrorString(e_));         \
+      return CE_EDEVICE;                                                               \
+    }                                                                                  \
+  } while (0)
+
+#define CE_WS_CHECK(ws)                                                   \
+  do {                                                                    \
+    if ((ws).overflow) {                                                  \
+      ::ce::set_error("internal: workspace carve exceeds its capacity");  \
+      return CE_ENOMEM;                                                   \
+    }                                                                     \
+  } while (0)
+
+#define CE_TRY(expr)                   \
+  do {                                 \
+    ce_status s_ = (expr);             \
+    if (s_ != CE_OK) return s_;        \
+  } while (0)
+
+// ---------------------------------------------------------- workspace plan
+// Bump allocator over one device buffer. With base == nullptr it only
+// measures (used by ce_workspace_bytes), so the same layout code sizes and
+// carves the workspace. Regions are 256-byte aligned.
+struct Ws {
+  char *base = nullptr;
+  size_t off = 0;
+  size_t peak = 0;
+  size_t cap = ~size_t(0);
+  bool overflow = false;  // set when a carve would pass cap; callers check before launching
+  template <class T>
+  T *alloc(size_t count) {
+    size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
+    if (bytes == 0) bytes = 256;
+    if (off + bytes > cap) overflow = true;
+    T *p = (base && !overflow) ? reinterpret_cast<T *>(base + off) : nullptr;
+    off += bytes;
+    if (off > peak) peak = off;
+    return p;
+  }
+  size_t mark() const { return off; }
+  void release(size_t m) { off = m; }
+};
+
+inline int bits_for(uint64_t v) {  // bits needed to represent v (0 -> 0)
+  int b = 0;
+  while (v) { b++; v >>= 1; }
+  return b;
+}
+
+inline unsigned grid_for(int64_t work, int block, int64_t cap = 1 << 20) {
+  int64_t g = (work + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (unsigned)g;
+}
+
+// ----------------------------------------------------------- u128 helpers
+struct u128 {
+  uint64_t lo, hi;
+};
+__host__ __device__ inline u128 u128_make(uint64_t hi, uint64_t lo) { return u128{lo, hi}; }
+__host__ __device__ inline u128 u128_add(u128 a, u128 b) {
+  u128 r;
+  r.lo = a.lo + b.lo;
+  r.hi = a.hi + b.hi + (r.lo < a.lo ? 1 : 0);
+  return r;
+}
+__host__ __device__ inline u128 u128_sub(u128 a, u128 b) {
+  u128 r;
+  r.lo = a.lo - b.lo;
+  r.hi = a.hi - b.hi - (a.lo < b.lo ? 1 : 0);
+  return r;
+}
+__host__ __device__ inline bool u128_gt(u128 a, u128 b) { return a.hi != b.hi ? a.hi > b.hi : a.lo > b.lo; }
+__host__ __device__ inline u128 u128_max(u128 a, u128 b) { return u128_gt(b, a) ? b : a; }
+__host__ __device__ inline u128 u128_mul64(uint64_t a, uint64_t b) {
+  uint64_t a0 = a & 0xffffffffull, a1 = a >> 32, b0 = b & 0xffffffffull, b1 = b >> 32;
+  uint64_t p00 = a0 * b0, p01 = a0 * b1, p10 = a1 * b0, p11 = a1 * b1;
+  uint64_t mid = (p00 >> 32) + (p01 & 0xffffffffull) + (p10 & 0xffffffffull);
+  u128 r;
+  r.lo = (p00 & 0xffffffffull) | (mid << 32);
+  r.hi = p11 + (p01 >> 32) + (p10 >> 32) + (mid >> 32);
+  return r;
+}
+
+// lambda(w) = floor(2^63 / max(2w, 1)) for w >= 0
+__host__ __device__ inline uint64_t lambda_of(int64_t w) {
+  return w <= 0 ? (uint64_t(1) << 63) : ((uint64_t(1) << 63) / (2 * (uint64_t)w));
+}
+
+// ------------------------------------------------------------ primitives
+// Exclusive scan of n elements; out must hold n+1 (out[n] = total). In-place allowed.
+ce_status scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, Ws &ws, hipStream_t s);
+size_t scan_ws_bytes(int64_t n);
+
+// Stable LSD radix sort of (key, value) pairs on bits [begin_bit, end_bit).
+// Sorts the data in (k0, v0) using (k1, v1) as ping-pong buffers; on return
+// *result_in_alt tells which pair holds the sorted output. With iota_values the
+// values start as the identity 0..n-1 (v0's contents are not read).
+template <class K, class V>
+ce_status radix_sort_pairs(K *k0, V *v0, K *k1, V *v1, int64_t n, int begin_bit, int end_bit, bool iota_values,
+                           bool *result_in_alt, Ws &ws, hipStream_t s);
+size_t radix_ws_bytes(int64_t n);
+
+}  // namespace ce
+
+namespace ce {
+
+// ---------------------------------------------------------------- pipeline
+// Device buffers of one clustering call, carved from the workspace.
+// Internal record ids are RANKS in the record order (t, id): rank r is the
+// r-th record by time; perm[r] is its input id.
+struct Bufs {
+  int64_t n = 0, V = 0, M = 0;
+  int tbits = 0, idbits = 0, vbits = 0, keybits = 0;
+  int64_t tmin = 0;
+  // persistent
+  uint64_t *hdr = nullptr;      // [16] device header / counters
+  uint64_t *ts = nullptr;       // [n] t - tmin by rank
+  uint32_t *perm = nullptr;     // [n] rank -> input id
+  uint64_t *skel_key = nullptr; // [2n] slot 2h+s: key of the skeleton edge whose head is rank h
+  uint32_t *skel_tail = nullptr;// [2n] tail rank of that edge or NONE
+  uint8_t *msf_flag = nullptr;  // [2n]
+  uint64_t *msf_key = nullptr;  // [n] sorted MSF keys
+  uint64_t *msf_val = nullptr;  // [n] (head rank << 32) | tail rank
+  uint32_t *kc_u = nullptr, *kc_v = nullptr, *ksize = nullptr; // [n] dendrogram children (internal labels) and size
+  // scratch arena (aliased across stages)
+  char *scratch = nullptr;
+  size_t scratch_bytes = 0;
+};
+
+// host pinned staging for small readbacks (per thread)
+uint64_t *pinned_scratch();
+ce_status read_u64(const uint64_t *dev, uint64_t *host_out, int count, hipStream_t s);
+
+ce_status stage_validate(const int32_t *src, const int32_t *dst, const int64_t *t, Bufs &b, hipStream_t s,
+                         uint64_t *flags, int64_t *tmin, int64_t *tmax);
+ce_status stage_sort_skeleton(const int32_t *src, const int32_t *dst, const int64_t *t, Bufs &b, Ws &ws,
+                              hipStream_t s);
+ce_status stage_boruvka(Bufs &b, Ws &ws, hipStream_t s);
+ce_status stage_msf_sort(Bufs &b, Ws &ws, hipStream_t s, int64_t *m_out);
+ce_status stage_dendrogram(Bufs &b, int64_t m, Ws &ws, hipStream_t s);
+ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipStream_t s, ce_counts *counts);
+ce_status stage_write_rows(Bufs &b, int64_t m, const ce_result *out, hipStream_t s);
+
+size_t stage_sort_skeleton_scratch(int64_t n);
+size_t stage_boruvka_scratch(int64_t n);
+size_t stage_msf_sort_scratch(int64_t n);
+size_t stage_dendrogram_scratch(int64_t n);
+size_t stage_condense_scratch(int64_t n, int64_t M);
+
+}  // namespace ce

@@ -1,0 +1,563 @@
+// Stages A8-A9: condense the dendrogram with the minimum cluster size M,
+// stability, excess-of-mass selection and labels (Alg. 1 steps 4-5, with the
+// HDBSCAN semantics of Campello et al. 2013 to which the paper defers).
+//
+// Node space: records are ranks [0,n), row j of the sorted MSF is node n+j,
+// the virtual root is n+m. A node is "big" if its size >= M.
+//  - birth nodes: both children of a row whose two children are big; and the
+//    big component roots when there are at least two of them. A cluster is
+//    identified by its birth node.
+//  - the cluster of a big node is its nearest birth ancestor-or-self, found by
+//    pointer jumping over big nodes (chains can be as deep as the data).
+//  - a record leaves the cluster of its lowest big ancestor y, at lambda(w_y);
+//    with no big ancestor it leaves ROOT at lambda 0.
+//  - stability sums exact 96-bit quantities as 32-bit limbs in u64 atomics.
+//  - excess of mass is a tree DP; chains are contracted by composing
+//    f(x) = max(a, x + b) (pointer jumping), leaves are raked each round.
+//  - the highest selected cluster above each cluster is again pointer jumping.
+#include "ce_internal.h"
+
+namespace ce {
+
+namespace {
+
+constexpr int B = 256;
+
+__device__ inline uint32_t node_size(uint32_t x, int64_t n, const uint32_t *ksize) {
+  return x < (uint64_t)n ? 1u : ksize[x - n];
+}
+__device__ inline int64_t row_w(int64_t j, const uint64_t *msf_key, int idbits) {
+  return (int64_t)(msf_key[j] >> (idbits + 1));
+}
+
+__global__ __launch_bounds__(B) void k_fill32(uint32_t *p, int64_t n, uint32_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < n; i += (int64_t)gridDim.x * B) p[i] = v;
+}
+__global__ __launch_bounds__(B) void k_fill64(uint64_t *p, int64_t n, uint64_t v) {
+  for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < n; i += (int64_t)gridDim.x * B) p[i] = v;
+}
+__global__ void k_set64(uint64_t *p, uint64_t v) { *p = v; }
+
+__global__ __launch_bounds__(B) void k_cd_parents(const uint32_t *kc_u, const uint32_t *kc_v, int64_t m, int64_t n,
+                                                  uint32_t *kpar) {
+  for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
+    kpar[kc_u[j]] = (uint32_t)(n + j);
+    kpar[kc_v[j]] = (uint32_t)(n + j);
+  }
+}
+
+__global__ __launch_bounds__(B) void k_cd_bigroots(const uint32_t *kpar, const uint32_t *ksize, int64_t m, int64_t n,
+                                                   int64_t M, unsigned long long *cnt) {
+  for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B)
+    if (kpar[n + j] == NONE32 && ksize[j] >= (uint64_t)M) atomicAdd(cnt, 1ull);
+}
+
+__global__ __launch_bounds__(B) void k_cd_birth(const uint32_t *kc_u, const uint32_t *kc_v, const uint32_t *ksize,
+                                                const uint32_t *kpar, const uint64_t *msf_key, int idbits, int64_t m,
+                                                int64_t n, int64_t M, uint64_t nbig, uint8_t *isbirth,
+                                                uint64_t *birthL) {
+  for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
+    uint32_t a = kc_u[j], b = kc_v[j];
+    if (node_size(a, n, ksize) >= (uint64_t)M && node_size(b, n, ksize) >= (uint64_t)M) {
+      uint64_t L = lambda_of(row_w(j, msf_key, idbits));
+      isbirth[a - n] = 1;
+      birthL[a - n] = L;
+      isbirth[b - n] = 1;
+      birthL[b - n] = L;
+    }
+    if (kpar[n + j] == NONE32 && ksize[j] >= (uint64_t)M && nbig >= 2) {
+      isbirth[j] = 1;
+      birthL[j] = 0;
+    }
+  }
+}
+
+// J[j] for big rows: self if birth, ROOT if a root, else the parent node
+__global__ __launch_bounds__(B) void k_cd_jinit(const uint8_t *isbirth, const uint32_t *kpar, const uint32_t *ksize,
+                                                int64_t m, int64_t n, int64_t M, uint32_t *J) {
+  const uint32_t ROOT = (uint32_t)(n + m);
+  for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
+    uint32_t v = NONE32;
+    if (ksize[j] >= (uint64_t)M) {
+      if (isbirth[j]) v = (uint32_t)(n + j);
+      else if (kpar[n + j] == NONE32) v = ROOT;
+      else v = kpar[n + j];
+    }
+    J[j] = v;
+  }
+}
+
+__global__ __launch_bounds__(B) void k_cd_jjump(const uint32_t *Jin, uint32_t *Jout, int64_t m, int64_t n,
+                                                uint32_t *changed) {
+  const uint32_t ROOT = (uint32_t)(n + m);
+  bool ch = false;
+  for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
+    uint32_t x = Jin[j];
+    uint32_t y = x;
+    if (x != NONE32 && x != ROOT && x != (uint32_t)(n + j)) {
+      y = Jin[x - n];
+      if (y != x) ch = true;
+    }
+    Jout[j] = y;
+  }
+  if (__ballot(ch) != 0 && (threadIdx.x & 63) == 0) atomicOr(changed, 1u);
+}
+
+// exit of each record: lowest big ancestor y -> (cluster of y, lambda(w_y))
+__global__ __launch_bounds__(B) void k_cd_exit(const uint32_t *kpar, const uint32_t *ksize, const uint32_t *J,
+                                               const uint64_t *msf_key, int idbits, int64_t m, int64_t n, int64_t M,
+                                               uint32_t *exc, uint64_t *exl) {
+  const uint32_t ROOT = (uint32_t)(n + m);
+  for (int64_t p = (int64_t)blockIdx.x * B + threadIdx.x; p < n; p += (int64_t)gridDim.x * B) {
+    uint32_t y = kpar[p];
+    while (y != NONE32 && ksize[y - n] < (uint64_t)M) y = kpar[y];
+    if (y == NONE32) {
+      exc[p] = ROOT;
+      exl[p] = 0;
+    } else {
+      exc[p] = J[y - n];
+      exl[p] = lambda_of(row_w((int64_t)y - n, msf_key, idbits));
+    }
+  }
+}
+
+__global__ __launch_bounds__(B) void k_u8_to_u32(const uint8_t *a, int64_t n, uint32_t *o) {
+  for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < n; i += (int64_t)gridDim.x * B) o[i] = a[i];
+}
+
+__device__ inline uint32_t row_of(uint32_t c, int64_t n, int64_t m, const uint32_t *rowof, uint32_t nbirth) {
+  return c == (uint32_t)(n + m) ? nbirth : rowof[c - n];
+}
+
+// cluster rows: node, size, birth lambda, parent row
+__global__ __launch_bounds__(B) void k_cd_rows(const uint8_t *isbirth, const uint32_t *rowof, const uint32_t *ksize,
+                                               const uint64_t *birthL, const uint32_t *kpar, const uint32_t *J,
+                                               int64_t m, int64_t n, uint32_t nbirth, uint32_t *cnode,
+                                               uint32_t *csize, uint64_t *cbirth, uint32_t *cprow) {
+  const uint32_t ROOT = (uint32_t)(n + m);
+  for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
+    if (!isbirth[j]) continue;
+    uint32_t r = rowof[j];
+    cnode[r] = (uint32_t)(n + j);
+    csize[r] = ksize[j];
+    cbirth[r] = birthL[j];
+    uint32_t par = kpar[n + j];
+    uint32_t pc = par == NONE32 ? ROOT : J[par - n];
+    cprow[r] = row_of(pc, n, m, rowof, nbirth);
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    cnode[nbirth] = ROOT;
+    csize[nbirth] = (uint32_t)n;
+    cbirth[nbirth] = 0;
+    cprow[nbirth] = NONE32;
+  }
+}
+
+__device__ inline uint64_t wave_sum64(uint64_t v) {
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+
+// exact sums of 32-bit limbs; lanes with equal rows are combined first
+__device__ inline void wave_add_limbs(bool active, uint32_t row, uint64_t l0, uint64_t l1, uint64_t l2,
+                                      unsigned long long *acc) {
+  const int lane = threadIdx.x & 63;
+  uint64_t pending = __ballot(active);
+  while (pending) {
+    int leader = __ffsll((unsigned long long)pending) - 1;
+    uint32_t key = __shfl(row, leader, 64);
+    bool mine = active && row == key && ((pending >> lane) & 1ull);
+    uint64_t match = __ballot(mine);
+    uint64_t s0 = wave_sum64(mine ? l0 : 0), s1 = wave_sum64(mine ? l1 : 0), s2 = wave_sum64(mine ? l2 : 0);
+    if (lane == leader) {
+      if (s0) atomicAdd(&acc[3 * (uint64_t)key], (unsigned long long)s0);
+      if (s1) atomicAdd(&acc[3 * (uint64_t)key + 1], (unsigned long long)s1);
+      if (s2) atomicAdd(&acc[3 * (uint64_t)key + 2], (unsigned long long)s2);
+    }
+    pending &= ~match;
+  }
+}
+
+__global__ __launch_bounds__(B) void k_cd_acc_points(const uint32_t *exc, const uint64_t *exl, const uint32_t *rowof,
+                                                     int64_t m, int64_t n, uint32_t nbirth,
+                                                     unsigned long long *acc) {
+  int64_t p = (int64_t)blockIdx.x * B + threadIdx.x;
+  bool act = p < n;
+  uint32_t r = 0;
+  uint64_t L = 0;
+  if (act) {
+    r = row_of(exc[p], n, m, rowof, nbirth);
+    L = exl[p];
+  }
+  wave_add_limbs(act, r, L & 0xffffffffull, L >> 32, 0, acc);
+}
+
+__global__ __launch_bounds__(B) void k_cd_acc_children(const uint32_t *csize, const uint64_t *cbirth,
+                                                       const uint32_t *cprow, uint32_t nrows,
+                                                       unsigned long long *acc) {
+  int64_t r = (int64_t)blockIdx.x * B + threadIdx.x;
+  bool act = r < (int64_t)nrows && cprow[r] != NONE32;
+  uint32_t pr = 0;
+  u128 prod{0, 0};
+  if (act) {
+    pr = cprow[r];
+    prod = u128_mul64(csize[r], cbirth[r]);
+  }
+  wave_add_limbs(act, pr, prod.lo & 0xffffffffull, prod.lo >> 32, prod.hi, acc);
+}
+
+// S = sum - size * birth  (exact u128)
+__global__ __launch_bounds__(B) void k_cd_stab(const unsigned long long *acc, const uint32_t *csize,
+                                               const uint64_t *cbirth, uint32_t nrows, uint64_t *shi, uint64_t *slo) {
+  for (int64_t r = (int64_t)blockIdx.x * B + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * B) {
+    u128 t0{acc[3 * r], 0};
+    u128 t1 = u128_mul64(acc[3 * r + 1], uint64_t(1) << 32);
+    u128 t2{0, acc[3 * r + 2]};
+    u128 T = u128_add(u128_add(t0, t1), t2);
+    u128 S = u128_sub(T, u128_mul64(csize[r], cbirth[r]));
+    shi[r] = S.hi;
+    slo[r] = S.lo;
+  }
+}
+
+__global__ __launch_bounds__(B) void k_cd_children(const uint32_t *cprow, uint32_t nrows, uint32_t rootrow,
+                                                   uint32_t *nch, uint32_t *ch) {
+  for (int64_t r = (int64_t)blockIdx.x * B + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * B) {
+    uint32_t p = cprow[r];
+    if (p == NONE32 || p == rootrow) continue;
+    uint32_t k = atomicAdd(&nch[p], 1u);
+    if (k < 2) ch[2 * (uint64_t)p + k] = (uint32_t)r;
+  }
+}
+
+// EOM state per row: st = 0 pending-binary, 1 pending-unary, 2 done
+struct Eom {
+  uint8_t *st;
+  uint64_t *vhi, *vlo;  // value when done
+  uint64_t *ahi, *alo, *bhi, *blo;  // unary f(x) = max(a, x + b)
+  uint32_t *dep;
+};
+
+__global__ __launch_bounds__(B) void k_eom_init(const uint32_t *nch, const uint64_t *shi, const uint64_t *slo,
+                                                uint32_t nrows, uint32_t rootrow, Eom e) {
+  for (int64_t r = (int64_t)blockIdx.x * B + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * B) {
+    bool leaf = nch[r] == 0 || r == rootrow;
+    e.st[r] = leaf ? 2 : 0;
+    e.vhi[r] = shi[r];
+    e.vlo[r] = slo[r];
+    e.dep[r] = NONE32;
+  }
+}
+
+__global__ __launch_bounds__(B) void k_eom_round(Eom in, Eom out, const uint32_t *ch, const uint64_t *shi,
+                                                 const uint64_t *slo, uint32_t nrows, unsigned long long *pending) {
+  bool pend = false;
+  for (int64_t r = (int64_t)blockIdx.x * B + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * B) {
+    uint8_t st = in.st[r];
+    u128 v{in.vlo[r], in.vhi[r]}, a{in.alo[r], in.ahi[r]}, bb{in.blo[r], in.bhi[r]};
+    uint32_t dep = in.dep[r];
+    if (st == 0) {
+      uint32_t c1 = ch[2 * r], c2 = ch[2 * r + 1];
+      bool d1 = in.st[c1] == 2, d2 = in.st[c2] == 2;
+      u128 S{slo[r], shi[r]};
+      if (d1 && d2) {
+        u128 sum = u128_add(u128{in.vlo[c1], in.vhi[c1]}, u128{in.vlo[c2], in.vhi[c2]});
+        v = u128_max(S, sum);
+        st = 2;
+      } else if (d1 || d2) {
+        uint32_t dn = d1 ? c1 : c2, pn = d1 ? c2 : c1;
+        a = S;
+        bb = u128{in.vlo[dn], in.vhi[dn]};
+        dep = pn;
+        st = 1;
+      }
+    } else if (st == 1) {
+      uint8_t ds = in.st[dep];
+      if (ds == 2) {
+        v = u128_max(a, u128_add(u128{in.vlo[dep], in.vhi[dep]}, bb));
+        st = 2;
+      } else if (ds == 1) {
+        u128 ad{in.alo[dep], in.ahi[dep]}, bd{in.blo[dep], in.bhi[dep]};
+        a = u128_max(a, u128_add(ad, bb));
+        bb = u128_add(bd, bb);
+        dep = in.dep[dep];
+      }
+    }
+    out.st[r] = st;
+    out.vhi[r] = v.hi; out.vlo[r] = v.lo;
+    out.ahi[r] = a.hi; out.alo[r] = a.lo;
+    out.bhi[r] = bb.hi; out.blo[r] = bb.lo;
+    out.dep[r] = dep;
+    if (st != 2) pend = true;
+  }
+  if (__ballot(pend) != 0 && (threadIdx.x & 63) == 0) atomicAdd(pending, 1ull);
+}
+
+// selection with ties kept by the parent; ROOT never selected
+__global__ __launch_bounds__(B) void k_eom_select(const uint32_t *nch, const uint32_t *ch, Eom e, const uint64_t *shi,
+                                                  const uint64_t *slo, uint32_t nrows, uint32_t rootrow,
+                                                  uint32_t *top, uint32_t *nxt, const uint32_t *cprow) {
+  for (int64_t r = (int64_t)blockIdx.x * B + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * B) {
+    bool sel;
+    if (r == rootrow) sel = false;
+    else if (nch[r] == 0) sel = true;
+    else {
+      uint32_t c1 = ch[2 * r], c2 = ch[2 * r + 1];
+      u128 sum = u128_add(u128{e.vlo[c1], e.vhi[c1]}, u128{e.vlo[c2], e.vhi[c2]});
+      sel = !u128_gt(sum, u128{slo[r], shi[r]});
+    }
+    top[r] = sel ? (uint32_t)r : NONE32;
+    uint32_t p = cprow[r];
+    nxt[r] = (p == NONE32 || p == rootrow) ? NONE32 : p;
+  }
+}
+
+// top[r] = highest selected row among r and its ancestors below ROOT
+__global__ __launch_bounds__(B) void k_top_jump(const uint32_t *tin, const uint32_t *nin, uint32_t *tout,
+                                                uint32_t *nout, uint32_t nrows, unsigned long long *active) {
+  bool act = false;
+  for (int64_t r = (int64_t)blockIdx.x * B + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * B) {
+    uint32_t nx = nin[r], t = tin[r];
+    if (nx != NONE32) {
+      uint32_t tv = tin[nx];
+      if (tv != NONE32) t = tv;
+      nx = nin[nx];
+    }
+    tout[r] = t;
+    nout[r] = nx;
+    if (nx != NONE32) act = true;
+  }
+  if (__ballot(act) != 0 && (threadIdx.x & 63) == 0) atomicAdd(active, 1ull);
+}
+
+__global__ __launch_bounds__(B) void k_lab_rows(const uint32_t *exc, const uint32_t *rowof, const uint32_t *top,
+                                                const uint32_t *perm, int64_t m, int64_t n, uint32_t nbirth,
+                                                uint32_t *labrow, uint32_t *minmem) {
+  for (int64_t p = (int64_t)blockIdx.x * B + threadIdx.x; p < n; p += (int64_t)gridDim.x * B) {
+    uint32_t r = row_of(exc[p], n, m, rowof, nbirth);
+    uint32_t lr = r == nbirth ? NONE32 : top[r];
+    labrow[p] = lr;
+    if (lr != NONE32) atomicMin(&minmem[lr], perm[p]);
+  }
+}
+
+__global__ __launch_bounds__(B) void k_lab_flags(const uint32_t *top, const uint32_t *minmem, uint32_t nrows,
+                                                 uint32_t *flag) {
+  for (int64_t r = (int64_t)blockIdx.x * B + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * B)
+    if (top[r] == (uint32_t)r && minmem[r] != NONE32) flag[minmem[r]] = 1;
+}
+
+__global__ __launch_bounds__(B) void k_out_points(const uint32_t *perm, const uint32_t *exc, const uint64_t *exl,
+                                                  const uint32_t *labrow, const uint32_t *minmem,
+                                                  const uint32_t *fscan, int64_t n, uint32_t *pt_cluster,
+                                                  uint64_t *pt_lambda, int32_t *labels) {
+  for (int64_t p = (int64_t)blockIdx.x * B + threadIdx.x; p < n; p += (int64_t)gridDim.x * B) {
+    uint32_t id = perm[p];
+    if (pt_cluster) pt_cluster[id] = exc[p];
+    if (pt_lambda) pt_lambda[id] = exl[p];
+    if (labels) {
+      uint32_t lr = labrow[p];
+      labels[id] = lr == NONE32 ? -1 : (int32_t)fscan[minmem[lr]];
+    }
+  }
+}
+
+__global__ __launch_bounds__(B) void k_out_clusters(const uint32_t *cnode, const uint32_t *cprow,
+                                                    const uint32_t *csize, const uint64_t *cbirth,
+                                                    const uint64_t *shi, const uint64_t *slo, const uint32_t *top,
+                                                    uint32_t nrows, uint32_t rootrow, ce_result out) {
+  for (int64_t r = (int64_t)blockIdx.x * B + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * B) {
+    if (out.cl_id) out.cl_id[r] = cnode[r];
+    if (out.cl_parent) out.cl_parent[r] = cprow[r] == NONE32 ? NONE32 : cnode[cprow[r]];
+    if (out.cl_size) out.cl_size[r] = csize[r];
+    if (out.cl_lambda_birth) out.cl_lambda_birth[r] = cbirth[r];
+    if (out.cl_stab_hi) out.cl_stab_hi[r] = shi[r];
+    if (out.cl_stab_lo) out.cl_stab_lo[r] = slo[r];
+    if (out.cl_selected) out.cl_selected[r] = (r != rootrow && top[r] == (uint32_t)r) ? 1 : 0;
+  }
+}
+
+}  // namespace
+
+size_t stage_condense_scratch(int64_t n, int64_t M) {
+  // n rows bound m; rows bound 2n/M + 1
+  int64_t m = n, R = 2 * (n / (M < 2 ? 2 : M)) + 2;
+  Ws w;
+  w.alloc<uint32_t>(n + m + 1);  // kpar
+  w.alloc<uint32_t>(m + 1); w.alloc<uint32_t>(m + 1);  // J, J2
+  w.alloc<uint8_t>(m + 4);       // isbirth
+  w.alloc<uint64_t>(m + 1);      // birthL
+  w.alloc<uint32_t>(m + 2); w.alloc<uint32_t>(m + 2);  // flags32, rowof
+  w.alloc<uint32_t>(n); w.alloc<uint64_t>(n);  // exc exl
+  w.alloc<uint32_t>(R); w.alloc<uint32_t>(R); w.alloc<uint64_t>(R); w.alloc<uint32_t>(R);  // cnode csize cbirth cprow
+  w.alloc<uint64_t>(3 * R);  // acc
+  w.alloc<uint64_t>(R); w.alloc<uint64_t>(R);  // shi slo
+  w.alloc<uint32_t>(R); w.alloc<uint32_t>(2 * R);  // nch ch
+  for (int k = 0; k < 2; k++) {
+    w.alloc<uint8_t>(R);
+    for (int q = 0; q < 6; q++) w.alloc<uint64_t>(R);
+    w.alloc<uint32_t>(R);
+  }
+  for (int k = 0; k < 4; k++) w.alloc<uint32_t>(R);  // top nxt x2
+  w.alloc<uint32_t>(R);  // minmem
+  w.alloc<uint32_t>(n);  // labrow
+  w.alloc<uint32_t>(n + 1);  // flag / scan
+  return w.off + scan_ws_bytes(n + 1) + scan_ws_bytes(m + 1) + 8192;
+}
+
+ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipStream_t s, ce_counts *counts) {
+  const int64_t n = b.n, M = b.M;
+  size_t m0 = ws.mark();
+  const int64_t R = 2 * (n / M) + 2;
+  uint32_t *kpar = ws.alloc<uint32_t>(n + m + 1);
+  uint32_t *J = ws.alloc<uint32_t>(m + 1), *J2 = ws.alloc<uint32_t>(m + 1);
+  uint8_t *isbirth = ws.alloc<uint8_t>(m + 4);
+  uint64_t *birthL = ws.alloc<uint64_t>(m + 1);
+  uint32_t *flags32 = ws.alloc<uint32_t>(m + 2), *rowof = ws.alloc<uint32_t>(m + 2);
+  uint32_t *exc = ws.alloc<uint32_t>(n);
+  uint64_t *exl = ws.alloc<uint64_t>(n);
+  uint32_t *cnode = ws.alloc<uint32_t>(R), *csize = ws.alloc<uint32_t>(R);
+  uint64_t *cbirth = ws.alloc<uint64_t>(R);
+  uint32_t *cprow = ws.alloc<uint32_t>(R);
+  unsigned long long *acc = ws.alloc<unsigned long long>(3 * R);
+  uint64_t *shi = ws.alloc<uint64_t>(R), *slo = ws.alloc<uint64_t>(R);
+  uint32_t *nch = ws.alloc<uint32_t>(R), *ch = ws.alloc<uint32_t>(2 * R);
+  Eom e[2];
+  for (int k = 0; k < 2; k++) {
+    e[k].st = ws.alloc<uint8_t>(R);
+    e[k].vhi = ws.alloc<uint64_t>(R); e[k].vlo = ws.alloc<uint64_t>(R);
+    e[k].ahi = ws.alloc<uint64_t>(R); e[k].alo = ws.alloc<uint64_t>(R);
+    e[k].bhi = ws.alloc<uint64_t>(R); e[k].blo = ws.alloc<uint64_t>(R);
+    e[k].dep = ws.alloc<uint32_t>(R);
+  }
+  uint32_t *top = ws.alloc<uint32_t>(R), *nxt = ws.alloc<uint32_t>(R);
+  uint32_t *top2 = ws.alloc<uint32_t>(R), *nxt2 = ws.alloc<uint32_t>(R);
+  uint32_t *minmem = ws.alloc<uint32_t>(R);
+  uint32_t *labrow = ws.alloc<uint32_t>(n);
+  uint32_t *fl = ws.alloc<uint32_t>(n + 1);
+  CE_WS_CHECK(ws);
+  unsigned long long *ctr = (unsigned long long *)&b.hdr[8];
+  uint32_t *chg = (uint32_t *)&b.hdr[9];
+
+  const unsigned gN = grid_for(n + m + 1, B), gm = grid_for(m + 1, B);
+  hipLaunchKernelGGL(k_fill32, dim3(gN), dim3(B), 0, s, kpar, n + m + 1, NONE32);
+  if (m > 0)
+    hipLaunchKernelGGL(k_cd_parents, dim3(grid_for(m, B)), dim3(B), 0, s, b.kc_u, b.kc_v, m, n, kpar);
+  hipLaunchKernelGGL(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[8], (uint64_t)0);
+  if (m > 0)
+    hipLaunchKernelGGL(k_cd_bigroots, dim3(grid_for(m, B)), dim3(B), 0, s, kpar, b.ksize, m, n, M, ctr);
+  CE_HIP(hipGetLastError());
+  uint64_t nbig = 0;
+  CE_TRY(read_u64(&b.hdr[8], &nbig, 1, s));
+  {
+    hipLaunchKernelGGL(k_fill32, dim3(grid_for((m + 4) / 4, B)), dim3(B), 0, s, (uint32_t *)isbirth, (m + 4) / 4, 0u);
+  }
+  if (m > 0) {
+    hipLaunchKernelGGL(k_cd_birth, dim3(grid_for(m, B)), dim3(B), 0, s, b.kc_u, b.kc_v, b.ksize, kpar, b.msf_key,
+                       b.idbits, m, n, M, nbig, isbirth, birthL);
+    hipLaunchKernelGGL(k_cd_jinit, dim3(grid_for(m, B)), dim3(B), 0, s, isbirth, kpar, b.ksize, m, n, M, J);
+    CE_HIP(hipGetLastError());
+    for (int it = 0;; it++) {
+      if (it > 40) {
+        set_error("cluster pointer jumping did not converge");
+        return CE_EDEVICE;
+      }
+      hipLaunchKernelGGL(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[9], (uint64_t)0);
+      hipLaunchKernelGGL(k_cd_jjump, dim3(grid_for(m, B)), dim3(B), 0, s, J, J2, m, n, chg);
+      CE_HIP(hipGetLastError());
+      uint32_t *tmp = J; J = J2; J2 = tmp;
+      uint64_t c = 0;
+      CE_TRY(read_u64(&b.hdr[9], &c, 1, s));
+      if ((c & 0xffffffffull) == 0) break;
+    }
+  }
+  hipLaunchKernelGGL(k_cd_exit, dim3(grid_for(n, B)), dim3(B), 0, s, kpar, b.ksize, J, b.msf_key, b.idbits, m, n, M,
+                     exc, exl);
+  hipLaunchKernelGGL(k_u8_to_u32, dim3(gm), dim3(B), 0, s, isbirth, m, flags32);
+  CE_HIP(hipGetLastError());
+  CE_TRY(scan_exclusive_u32(flags32, rowof, m, ws, s));
+  uint64_t nb64 = 0;
+  {
+    // rowof[m] holds the number of birth nodes
+    uint32_t *h = (uint32_t *)pinned_scratch();
+    CE_HIP(hipMemcpyAsync(h, rowof + m, 4, hipMemcpyDeviceToHost, s));
+    CE_HIP(hipStreamSynchronize(s));
+    nb64 = h[0];
+  }
+  const uint32_t nbirth = (uint32_t)nb64, nrows = nbirth + 1, rootrow = nbirth;
+  if ((int64_t)nrows > R) {
+    set_error("cluster rows exceed 2*floor(n/M)+1");
+    return CE_EDEVICE;
+  }
+  const unsigned gR = grid_for(nrows, B);
+  hipLaunchKernelGGL(k_cd_rows, dim3(gm), dim3(B), 0, s, isbirth, rowof, b.ksize, birthL, kpar, J, m, n, nbirth, cnode,
+                     csize, cbirth, cprow);
+  hipLaunchKernelGGL(k_fill64, dim3(grid_for(3 * (int64_t)nrows, B)), dim3(B), 0, s, (uint64_t *)acc,
+                     3 * (int64_t)nrows, (uint64_t)0);
+  hipLaunchKernelGGL(k_cd_acc_points, dim3((unsigned)((n + B - 1) / B)), dim3(B), 0, s, exc, exl, rowof, m, n,
+                     nbirth, acc);
+  hipLaunchKernelGGL(k_cd_acc_children, dim3((unsigned)((nrows + B - 1) / B)), dim3(B), 0, s, csize, cbirth, cprow,
+                     nrows, acc);
+  hipLaunchKernelGGL(k_cd_stab, dim3(gR), dim3(B), 0, s, acc, csize, cbirth, nrows, shi, slo);
+  hipLaunchKernelGGL(k_fill32, dim3(gR), dim3(B), 0, s, nch, (int64_t)nrows, 0u);
+  hipLaunchKernelGGL(k_fill32, dim3(grid_for(2 * (int64_t)nrows, B)), dim3(B), 0, s, ch, 2 * (int64_t)nrows, 0u);
+  hipLaunchKernelGGL(k_cd_children, dim3(gR), dim3(B), 0, s, cprow, nrows, rootrow, nch, ch);
+  hipLaunchKernelGGL(k_eom_init, dim3(gR), dim3(B), 0, s, nch, shi, slo, nrows, rootrow, e[0]);
+  CE_HIP(hipGetLastError());
+  int cur = 0;
+  for (int it = 0;; it++) {
+    if (it > 4096) {
+      set_error("excess-of-mass rounds did not converge");
+      return CE_EDEVICE;
+    }
+    hipLaunchKernelGGL(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[8], (uint64_t)0);
+    hipLaunchKernelGGL(k_eom_round, dim3(gR), dim3(B), 0, s, e[cur], e[1 - cur], ch, shi, slo, nrows, ctr);
+    CE_HIP(hipGetLastError());
+    cur = 1 - cur;
+    uint64_t p = 0;
+    CE_TRY(read_u64(&b.hdr[8], &p, 1, s));
+    if (p == 0) break;
+  }
+  hipLaunchKernelGGL(k_eom_select, dim3(gR), dim3(B), 0, s, nch, ch, e[cur], shi, slo, nrows, rootrow, top, nxt,
+                     cprow);
+  CE_HIP(hipGetLastError());
+  for (int it = 0;; it++) {
+    if (it > 40) {
+      set_error("label pointer jumping did not converge");
+      return CE_EDEVICE;
+    }
+    hipLaunchKernelGGL(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[8], (uint64_t)0);
+    hipLaunchKernelGGL(k_top_jump, dim3(gR), dim3(B), 0, s, top, nxt, top2, nxt2, nrows, ctr);
+    CE_HIP(hipGetLastError());
+    uint32_t *t1 = top; top = top2; top2 = t1;
+    uint32_t *t2 = nxt; nxt = nxt2; nxt2 = t2;
+    uint64_t a = 0;
+    CE_TRY(read_u64(&b.hdr[8], &a, 1, s));
+    if (a == 0) break;
+  }
+  hipLaunchKernelGGL(k_fill32, dim3(gR), dim3(B), 0, s, minmem, (int64_t)nrows, NONE32);
+  hipLaunchKernelGGL(k_lab_rows, dim3(grid_for(n, B)), dim3(B), 0, s, exc, rowof, top, b.perm, m, n, nbirth, labrow,
+                     minmem);
+  hipLaunchKernelGGL(k_fill32, dim3(grid_for(n + 1, B)), dim3(B), 0, s, fl, n + 1, 0u);
+  hipLaunchKernelGGL(k_lab_flags, dim3(gR), dim3(B), 0, s, top, minmem, nrows, fl);
+  CE_HIP(hipGetLastError());
+  CE_TRY(scan_exclusive_u32(fl, fl, n, ws, s));
+  hipLaunchKernelGGL(k_out_points, dim3(grid_for(n, B)), dim3(B), 0, s, b.perm, exc, exl, labrow, minmem, fl, n,
+                     out->pt_cluster, out->pt_lambda, out->labels);
+  hipLaunchKernelGGL(k_out_clusters, dim3(gR), dim3(B), 0, s, cnode, cprow, csize, cbirth, shi, slo, top, nrows,
+                     rootrow, *out);
+  CE_HIP(hipGetLastError());
+  uint32_t nl = 0;
+  {
+    uint32_t *h = (uint32_t *)pinned_scratch();
+    CE_HIP(hipMemcpyAsync(h, fl + n, 4, hipMemcpyDeviceToHost, s));
+    CE_HIP(hipStreamSynchronize(s));
+    nl = h[0];
+  }
+  counts->n_clusters = nrows;
+  counts->n_labels = nl;
+  ws.release(m0);
+  return CE_OK;
+}
+
+}  // namespace ce

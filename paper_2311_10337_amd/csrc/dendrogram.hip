@@ -1,0 +1,331 @@
+// Stage A7: exact single-linkage dendrogram from the sorted MSF (Alg. 1 step 3).
+//
+// The paper builds the dendrogram with a union-find pass over the sorted MST
+// edges and calls that pass an expensive serial operation (Sec. 3). Here it is
+// computed exactly in O(log m) parallel levels:
+//
+// For MSF row j (rows in key order), its two children are the dendrogram roots
+// of the components of its endpoints in the forest of rows < j; the root of a
+// component is its largest row (or the record itself when alone). Split the
+// row range into aligned intervals. For an interval I=[a,b) the edges of I only
+// see components of rows < a through their "labels" (roots at time a). The
+// labels used inside one interval are disjoint from those of every other
+// interval of the same length, because a root stays a root only until the
+// first later row touching it. So one global union-find indexed by label can
+// serve all intervals of a level at once. A level splits each interval into K
+// sub-intervals processed in order: relabel the rows of sub-interval q to the
+// roots after sub-intervals < q (largest row of the merged component), then
+// union them. Sizes travel with labels. When intervals are small enough
+// (512 rows) one workgroup finishes all remaining levels in LDS with binary
+// splits, and the labels at the end are exactly the children.
+#include "ce_internal.h"
+
+namespace ce {
+
+namespace {
+
+constexpr int B = 256;
+
+__device__ inline uint32_t ld(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st(uint32_t *p, uint32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// lock-free find with path halving; parent pointers only move to ancestors
+__device__ inline uint32_t g_find(uint32_t *uf, uint32_t x) {
+  while (true) {
+    uint32_t p = ld(&uf[x]);
+    if (p == x) return x;
+    uint32_t gp = ld(&uf[p]);
+    if (gp == p) return p;
+    st(&uf[x], gp);
+    x = gp;
+  }
+}
+
+// returns the root that was hooked (the larger of the two roots)
+__device__ inline uint32_t g_union(uint32_t *uf, uint32_t a, uint32_t b) {
+  while (true) {
+    a = g_find(uf, a);
+    b = g_find(uf, b);
+    if (a == b) return NONE32;
+    uint32_t hi = a > b ? a : b, lo = a > b ? b : a;
+    if (atomicCAS(&uf[hi], hi, lo) == hi) return hi;
+  }
+}
+
+__global__ __launch_bounds__(B) void k_krt_init(const uint64_t *msf_val, int64_t m, uint32_t *lu, uint32_t *lv,
+                                                uint32_t *su, uint32_t *sv) {
+  for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
+    uint64_t v = msf_val[j];
+    lu[j] = (uint32_t)(v & 0xffffffffu);  // tail rank
+    lv[j] = (uint32_t)(v >> 32);          // head rank
+    su[j] = 1;
+    sv[j] = 1;
+  }
+}
+
+__global__ __launch_bounds__(B) void k_krt_reset(const uint32_t *lu, const uint32_t *lv, const uint32_t *su,
+                                                 const uint32_t *sv, int64_t m, uint32_t *uf, uint32_t *mx,
+                                                 uint32_t *cs) {
+  for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
+    uint32_t a = lu[j], b = lv[j];
+    uf[a] = a;
+    uf[b] = b;
+    mx[a] = 0;
+    mx[b] = 0;
+    cs[a] = su[j];
+    cs[b] = sv[j];
+  }
+}
+
+__device__ inline int64_t step_row(int64_t tix, int lo, int hi, uint32_t q) {
+  int64_t interval = tix >> lo;
+  int64_t off = tix & ((int64_t(1) << lo) - 1);
+  return (interval << (hi + 1)) | ((int64_t)q << lo) | off;
+}
+
+// relabel the rows of sub-interval q (q >= 1) to the roots after sub-intervals < q
+__global__ __launch_bounds__(B) void k_krt_relabel(int64_t m, int64_t n, int lo, int hi, uint32_t q, int64_t nthreads,
+                                                   uint32_t *lu, uint32_t *lv, uint32_t *su, uint32_t *sv,
+                                                   uint32_t *ru, uint32_t *rv, uint32_t *uf, const uint32_t *mx,
+                                                   const uint32_t *cs) {
+  for (int64_t tix = (int64_t)blockIdx.x * B + threadIdx.x; tix < nthreads; tix += (int64_t)gridDim.x * B) {
+    int64_t j = step_row(tix, lo, hi, q);
+    if (j >= m) continue;
+    uint32_t a = g_find(uf, lu[j]);
+    ru[j] = a;
+    uint32_t ma = mx[a];
+    if (ma) {
+      lu[j] = (uint32_t)(n + ma - 1);
+      su[j] = cs[a];
+    }
+    uint32_t b = g_find(uf, lv[j]);
+    rv[j] = b;
+    uint32_t mb = mx[b];
+    if (mb) {
+      lv[j] = (uint32_t)(n + mb - 1);
+      sv[j] = cs[b];
+    }
+  }
+}
+
+__global__ __launch_bounds__(B) void k_krt_union(int64_t m, int lo, int hi, uint32_t q, int64_t nthreads,
+                                                 const uint32_t *lu, const uint32_t *lv, const uint32_t *ru,
+                                                 const uint32_t *rv, uint32_t *uf, uint32_t *hooked) {
+  for (int64_t tix = (int64_t)blockIdx.x * B + threadIdx.x; tix < nthreads; tix += (int64_t)gridDim.x * B) {
+    int64_t j = step_row(tix, lo, hi, q);
+    if (j >= m) continue;
+    uint32_t a = q ? ru[j] : lu[j];
+    uint32_t b = q ? rv[j] : lv[j];
+    hooked[j] = g_union(uf, a, b);
+  }
+}
+
+__global__ __launch_bounds__(B) void k_krt_accum(int64_t m, int lo, int hi, uint32_t q, int64_t nthreads,
+                                                 const uint32_t *hooked, uint32_t *uf, uint32_t *mx, uint32_t *cs) {
+  for (int64_t tix = (int64_t)blockIdx.x * B + threadIdx.x; tix < nthreads; tix += (int64_t)gridDim.x * B) {
+    int64_t j = step_row(tix, lo, hi, q);
+    if (j >= m) continue;
+    uint32_t h = hooked[j];
+    if (h == NONE32) continue;
+    uint32_t f = g_find(uf, h);
+    atomicAdd(&cs[f], cs[h]);
+    atomicMax(&mx[f], (uint32_t)(j + 1));
+  }
+}
+
+// ---------------------------------------------------------------- LDS level
+constexpr int LS_BITS = 9;
+constexpr int LS = 1 << LS_BITS;  // rows per workgroup
+constexpr int HS = 4 * LS;        // hash slots (load factor <= 1/2)
+constexpr uint32_t EMPTY = 0xffffffffu;
+
+__device__ inline uint32_t l_find(volatile uint32_t *uf, uint32_t x) {
+  while (true) {
+    uint32_t p = uf[x];
+    if (p == x) return x;
+    uint32_t gp = uf[p];
+    if (gp == p) return p;
+    uf[x] = gp;
+    x = gp;
+  }
+}
+
+__device__ inline uint32_t l_union(volatile uint32_t *uf, uint32_t a, uint32_t b) {
+  while (true) {
+    a = l_find(uf, a);
+    b = l_find(uf, b);
+    if (a == b) return EMPTY;
+    uint32_t hi = a > b ? a : b, lo = a > b ? b : a;
+    if (atomicCAS((uint32_t *)&uf[hi], hi, lo) == hi) return hi;
+  }
+}
+
+__device__ inline uint32_t hslot(uint32_t g) { return (g * 2654435761u) >> (32 - (LS_BITS + 2)); }
+
+__global__ __launch_bounds__(B) void k_krt_lds(const uint32_t *lu, const uint32_t *lv, const uint32_t *su,
+                                               const uint32_t *sv, int64_t m, int64_t n, uint32_t *kc_u,
+                                               uint32_t *kc_v, uint32_t *ksize) {
+  __shared__ uint32_t hkey[HS];
+  __shared__ uint16_t hid[HS];
+  __shared__ uint32_t glab[2 * LS];
+  __shared__ uint32_t luf[3 * LS];
+  __shared__ uint32_t lmx[3 * LS];
+  __shared__ uint32_t lcs[3 * LS];
+  __shared__ uint32_t lsz[3 * LS];
+  __shared__ uint16_t elu[LS], elv[LS], ehk[LS];
+  __shared__ uint32_t nloc;
+  const int tid = threadIdx.x;
+  const int64_t base = (int64_t)blockIdx.x * LS;
+  const int cnt = (int)((m - base) < LS ? (m - base) : LS);
+  for (int i = tid; i < HS; i += B) hkey[i] = EMPTY;
+  if (tid == 0) nloc = 0;
+  __syncthreads();
+  // 1. distinct labels of this interval into an LDS hash set
+  for (int i = tid; i < 2 * cnt; i += B) {
+    uint32_t g = (i & 1) ? lv[base + (i >> 1)] : lu[base + (i >> 1)];
+    uint32_t s = hslot(g);
+    while (true) {
+      uint32_t old = atomicCAS(&hkey[s], EMPTY, g);
+      if (old == EMPTY || old == g) break;
+      s = (s + 1) & (HS - 1);
+    }
+  }
+  __syncthreads();
+  // 2. local ids for the distinct labels
+  for (int s = tid; s < HS; s += B) {
+    uint32_t g = hkey[s];
+    if (g != EMPTY) {
+      uint32_t id = atomicAdd(&nloc, 1u);
+      hid[s] = (uint16_t)id;
+      glab[id] = g;
+    }
+  }
+  __syncthreads();
+  // 3. rows' labels as local ids, with sizes
+  for (int i = tid; i < 2 * cnt; i += B) {
+    const bool isv = i & 1;
+    const int r = i >> 1;
+    uint32_t g = isv ? lv[base + r] : lu[base + r];
+    uint32_t s = hslot(g);
+    while (hkey[s] != g) s = (s + 1) & (HS - 1);
+    uint16_t id = hid[s];
+    if (isv) elv[r] = id; else elu[r] = id;
+    lsz[id] = isv ? sv[base + r] : su[base + r];
+  }
+  __syncthreads();
+  volatile uint32_t *vuf = luf;
+  // 4. binary levels inside the interval
+  for (int bit = LS_BITS - 1; bit >= 0; bit--) {
+    for (int i = tid; i < cnt; i += B) {
+      uint32_t a = elu[i], b = elv[i];
+      luf[a] = a; luf[b] = b;
+      lmx[a] = 0; lmx[b] = 0;
+      lcs[a] = lsz[a]; lcs[b] = lsz[b];
+    }
+    __syncthreads();
+    for (int i = tid; i < cnt; i += B)
+      if (!((i >> bit) & 1)) ehk[i] = (uint16_t)l_union(vuf, elu[i], elv[i]);
+    __syncthreads();
+    for (int i = tid; i < cnt; i += B) {
+      if ((i >> bit) & 1) continue;
+      uint32_t h = ehk[i];
+      if (h == 0xffffu) continue;
+      uint32_t f = l_find(vuf, h);
+      atomicAdd(&lcs[f], lcs[h]);
+      atomicMax(&lmx[f], (uint32_t)(i + 1));
+    }
+    __syncthreads();
+    for (int i = tid; i < cnt; i += B) {
+      if (!((i >> bit) & 1)) continue;
+      uint32_t f = l_find(vuf, elu[i]);
+      if (lmx[f]) {
+        uint32_t nx = 2 * LS + lmx[f] - 1;
+        lsz[nx] = lcs[f];
+        elu[i] = (uint16_t)nx;
+      }
+      f = l_find(vuf, elv[i]);
+      if (lmx[f]) {
+        uint32_t nx = 2 * LS + lmx[f] - 1;
+        lsz[nx] = lcs[f];
+        elv[i] = (uint16_t)nx;
+      }
+    }
+    __syncthreads();
+  }
+  // 5. children as internal labels (record rank < n, or n + row)
+  for (int i = tid; i < cnt; i += B) {
+    uint32_t a = elu[i], b = elv[i];
+    uint32_t ga = a < 2 * LS ? glab[a] : (uint32_t)(n + base + (a - 2 * LS));
+    uint32_t gb = b < 2 * LS ? glab[b] : (uint32_t)(n + base + (b - 2 * LS));
+    kc_u[base + i] = ga;
+    kc_v[base + i] = gb;
+    ksize[base + i] = lsz[a] + lsz[b];
+  }
+}
+
+}  // namespace
+
+int krt_level_bits() {
+  static int bits = 0;
+  if (!bits) {
+    const char *e = getenv("CE_KRT_LEVEL_BITS");
+    bits = e ? atoi(e) : 5;
+    if (bits < 1) bits = 1;
+    if (bits > 10) bits = 10;
+  }
+  return bits;
+}
+
+size_t stage_dendrogram_scratch(int64_t n) {
+  Ws w;
+  for (int k = 0; k < 7; k++) w.alloc<uint32_t>(n);  // lu lv su sv ru rv hooked
+  for (int k = 0; k < 3; k++) w.alloc<uint32_t>(2 * n);  // uf mx cs over labels < n + m
+  return w.off + 4096;
+}
+
+ce_status stage_dendrogram(Bufs &b, int64_t m, Ws &ws, hipStream_t s) {
+  if (m <= 0) return CE_OK;
+  const int64_t n = b.n;
+  size_t m0 = ws.mark();
+  uint32_t *lu = ws.alloc<uint32_t>(m), *lv = ws.alloc<uint32_t>(m);
+  uint32_t *su = ws.alloc<uint32_t>(m), *sv = ws.alloc<uint32_t>(m);
+  uint32_t *ru = ws.alloc<uint32_t>(m), *rv = ws.alloc<uint32_t>(m);
+  uint32_t *hooked = ws.alloc<uint32_t>(m);
+  uint32_t *uf = ws.alloc<uint32_t>(n + m), *mx = ws.alloc<uint32_t>(n + m), *cs = ws.alloc<uint32_t>(n + m);
+  CE_WS_CHECK(ws);
+  hipLaunchKernelGGL(k_krt_init, dim3(grid_for(m, B)), dim3(B), 0, s, b.msf_val, m, lu, lv, su, sv);
+  CE_HIP(hipGetLastError());
+  const int L = bits_for((uint64_t)(m - 1));  // rows are j < 2^L
+  const int kb = krt_level_bits();
+  int hi = L - 1;
+  while (hi >= LS_BITS) {
+    int lo = hi - kb + 1;
+    if (lo < LS_BITS) lo = LS_BITS;
+    const uint32_t K = 1u << (hi - lo + 1);
+    const int64_t nint = (m + (int64_t(1) << (hi + 1)) - 1) >> (hi + 1);
+    const int64_t nthreads = nint << lo;
+    const unsigned g = grid_for(nthreads, B, 1 << 16);
+    hipLaunchKernelGGL(k_krt_reset, dim3(grid_for(m, B)), dim3(B), 0, s, lu, lv, su, sv, m, uf, mx, cs);
+    for (uint32_t q = 0; q < K; q++) {
+      // sub-interval q exists in at least one interval?
+      if (((int64_t)q << lo) >= m) break;
+      if (q) hipLaunchKernelGGL(k_krt_relabel, dim3(g), dim3(B), 0, s, m, n, lo, hi, q, nthreads, lu, lv, su, sv, ru,
+                                rv, uf, mx, cs);
+      hipLaunchKernelGGL(k_krt_union, dim3(g), dim3(B), 0, s, m, lo, hi, q, nthreads, lu, lv, ru, rv, uf, hooked);
+      hipLaunchKernelGGL(k_krt_accum, dim3(g), dim3(B), 0, s, m, lo, hi, q, nthreads, hooked, uf, mx, cs);
+    }
+    CE_HIP(hipGetLastError());
+    hi = lo - 1;
+  }
+  const int64_t nblk = (m + LS - 1) / LS;
+  hipLaunchKernelGGL(k_krt_lds, dim3((unsigned)nblk), dim3(B), 0, s, lu, lv, su, sv, m, n, b.kc_u, b.kc_v, b.ksize);
+  CE_HIP(hipGetLastError());
+  ws.release(m0);
+  return CE_OK;
+}
+
+}  // namespace ce
