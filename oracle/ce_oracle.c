@@ -411,29 +411,27 @@ int oracle_condense(int64_t n, int64_t m, const uint32_t *left, const uint32_t *
     if (--pending[pr] == 0) queue[qt++] = pr;
   }
   sel[nc - 1] = 0; /* ROOT is never selected */
-  /* final choice: selected with no selected proper ancestor (ROOT excluded) */
-  for (int64_t r = 0; r < nc; r++) {
-    int chosen = sel[r];
-    if (chosen) {
-      uint32_t a = cl_parent[r];
-      while (a != NONE32 && a != ROOT) {
-        if (sel[row[a]]) { chosen = 0; break; }
-        a = cl_parent[row[a]];
-      }
-    }
+  /* Final choice and labels, top-down (parents before children: the reverse
+   * of the post-order above). A cluster is chosen when it is selected and no
+   * proper ancestor below ROOT is selected; a point's label is the chosen
+   * cluster on the path from its exit cluster up to ROOT, if any. */
+  uint8_t *anc_sel = (uint8_t *)calloc((size_t)nc, 1);
+  int32_t *lab_row = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nc ? nc : 1));
+  for (int64_t i = qt - 1; i >= 0; i--) {
+    int64_t r = queue[i];
+    if (r == nc - 1) { anc_sel[r] = 0; lab_row[r] = -1; cl_selected[r] = 0; continue; }
+    int64_t pr = row[cl_parent[r]];
+    anc_sel[r] = (uint8_t)(sel[pr] || anc_sel[pr]);
+    int chosen = sel[r] && !anc_sel[r];
     cl_selected[r] = (uint8_t)chosen;
+    lab_row[r] = chosen ? (int32_t)r : (anc_sel[r] ? lab_row[pr] : -1);
   }
-  /* O10 labels: the chosen cluster on the path from the exit cluster to ROOT */
+  /* O10 labels */
   int32_t *lab_of_row = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nc ? nc : 1));
   int64_t *minmem = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nc ? nc : 1));
   for (int64_t r = 0; r < nc; r++) { lab_of_row[r] = -1; minmem[r] = INT64_MAX; }
   for (int64_t p = 0; p < n; p++) {
-    uint32_t a = pt_cluster[p];
-    int64_t got = -1;
-    while (a != NONE32 && a != ROOT) {
-      if (cl_selected[row[a]]) { got = row[a]; break; }
-      a = cl_parent[row[a]];
-    }
+    int64_t got = lab_row[row[pt_cluster[p]]];
     labels[p] = (int32_t)got; /* temporarily the row */
     if (got >= 0 && p < minmem[got]) minmem[got] = p;
   }
@@ -448,7 +446,7 @@ int oracle_condense(int64_t n, int64_t m, const uint32_t *left, const uint32_t *
   counts->n_clusters = nc;
   counts->n_labels = L;
 
-  free(lab_of_row); free(minmem);
+  free(lab_of_row); free(minmem); free(anc_sel); free(lab_row);
   free(child_cnt); free(best); free(childsum); free(sel); free(pending); free(queue); free(row);
   free(parent); free(nsize); free(clus); free(stack); free(is_cluster); free(cpar); free(cbirth); free(stab);
   return OR_OK;
