@@ -1,0 +1,119 @@
+#!/usr/bin/env python3
+"""Benchmark: temporal edges clustered per second on one MI355X.
+
+One step = one full clustering of the workload through the C ABI
+(group+sort by vertex and time, path skeleton, Boruvka MSF, sorted MSF,
+exact dendrogram, condensed tree, stability, excess of mass, labels), with
+the input records already resident in HBM and the workspace and outputs
+preallocated. Prints one JSON line.
+
+Default workload (N=1): R-MAT scale 20 (1M vertices), 50M records,
+per-pair Hawkes timestamps over 90 days, min_cluster_size 10, seed 1.
+"""
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "temporal edges clustered/sec (bit-exact) + % HBM roofline; batched vs single"
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def make_workload(name):
+    import synth
+    if name == "tiny":
+        return synth.plain_tiny(), {"workload": "chung-lu-bursts-tiny", "n_edges": 200_000, "n_vertices": 10_000,
+                                    "min_cluster_size": 5, "seed": 0, "timestamps": "poisson bursts, 30 days"}
+    if name == "mid":
+        return synth.plain_mid(), {"workload": "rmat-hawkes-mid", "n_edges": 50_000_000, "n_vertices": 1 << 20,
+                                   "min_cluster_size": 10, "seed": 1, "timestamps": "per-pair hawkes, 90 days"}
+    if name == "scale":
+        return synth.plain_scale(), {"workload": "rmat-hawkes-scale", "n_edges": 1 << 30, "n_vertices": 1 << 26,
+                                     "min_cluster_size": 25, "seed": 2,
+                                     "timestamps": "per-pair hawkes, 365 days, planted 1e7 hub"}
+    raise ValueError(name)
+
+
+def cpu_baseline(w, sample):
+    """Time the CPU oracle (single-threaded plain C) on the first `sample` records."""
+    import oracle
+    ns = min(sample, w.n)
+    t0 = time.perf_counter()
+    r = oracle.cluster(w.src[:ns], w.dst[:ns], w.t[:ns], w.min_cluster_size, w.num_vertices, tier=1)
+    dt = time.perf_counter() - t0
+    assert r.status == 0
+    return {"value": ns / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+            "sample": "first %d of %d records of the same workload (path-skeleton oracle, one host thread, %.1f s)"
+                      % (ns, w.n, dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="mid", choices=["tiny", "mid", "scale"])
+    ap.add_argument("--cpu-sample", type=int, default=10_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py: this build measures one GPU; --gpus %d is not supported (run with --gpus 1)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2311_10337_amd as ce
+    if not os.path.exists(ce.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+
+    log("generating workload %s" % args.workload)
+    t0 = time.perf_counter()
+    w, cfg = make_workload(args.workload)
+    log("generated n=%d in %.1f s" % (w.n, time.perf_counter() - t0))
+    dev = torch.device("cuda:0")
+    src = torch.from_numpy(w.src).to(dev)
+    dst = torch.from_numpy(w.dst).to(dev)
+    tt = torch.from_numpy(w.t).to(dev)
+    M, V = w.min_cluster_size, w.num_vertices
+    outs = ce.Outputs(w.n, M, dev)
+    ws = torch.empty(ce.workspace_bytes(w.n, V, M), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+
+    def step():
+        return ce.cluster_edges(src, dst, tt, M, V, outputs=outs, workspace=ws)
+
+    for i in range(args.warmup):
+        r = step()
+        log("warmup %d done: m=%d clusters=%d labels=%d" % (i, r.m, r.n_clusters, r.n_labels))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        r = step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    log("timed %d steps in %.3f s" % (args.steps, el))
+    value = w.n * args.steps / el
+    line = {"metric": METRIC, "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
+            "warmup": args.warmup, "ms_per_step": 1000.0 * el / args.steps, "higher_is_better": True,
+            "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
+            "config": dict(cfg, m_msf=r.m, n_clusters=r.n_clusters, n_labels=r.n_labels)}
+    if not args.no_cpu_baseline:
+        log("cpu baseline on a sample")
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
+    line["host"] = {"cpu": platform.processor() or platform.machine(), "nproc": os.cpu_count()}
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
