@@ -63,6 +63,7 @@ def main():
     ap.add_argument("--workload", default="mid", choices=["tiny", "mid", "scale"])
     ap.add_argument("--cpu-sample", type=int, default=10_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--time-kernel", default=None, help="kernel whose launches are timed with HIP events")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -97,12 +98,18 @@ def main():
         r = step()
         log("warmup %d done: m=%d clusters=%d labels=%d" % (i, r.m, r.n_clusters, r.n_labels))
     torch.cuda.synchronize()
+    if args.time_kernel:
+        ce.timing_enable(args.time_kernel)
     t0 = time.perf_counter()
     for i in range(args.steps):
         r = step()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     log("timed %d steps in %.3f s" % (args.steps, el))
+    if args.time_kernel:
+        kms, kcnt = ce.timing_read()
+        ce.timing_enable(None)
+        log("kernel %s: %d launches, %.3f ms total, %.1f us avg" % (args.time_kernel, kcnt, kms, 1e3 * kms / max(kcnt, 1)))
     value = w.n * args.steps / el
     line = {"metric": METRIC, "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": 1000.0 * el / args.steps, "higher_is_better": True,

@@ -118,6 +118,17 @@ ce_status ce_cluster_edges(const int32_t *src, const int32_t *dst, const int64_t
 /* Thread-local text of the last error on this thread (never NULL). */
 const char *ce_last_error(void);
 
+/*
+ * Diagnostics: kernel timing with HIP events. ce_timing_enable(name) makes
+ * every later launch of a library kernel whose name contains `name` record a
+ * pair of events on the stream it is launched on (NULL or "" turns this off)
+ * and resets the totals. ce_cluster_edges collects the elapsed times before
+ * it returns; ce_timing_read gives the accumulated milliseconds and launch
+ * count since the last enable. Process-wide; returns 0.
+ */
+int ce_timing_enable(const char *kernel_name);
+int ce_timing_read(double *total_ms, int64_t *launches);
+
 #ifdef __cplusplus
 }
 #endif

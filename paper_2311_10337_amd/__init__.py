@@ -38,7 +38,8 @@ class CeCounts(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int64), ("n_clusters", ctypes.c_int64), ("n_labels", ctypes.c_int64)]
 
 
-_EXPORTS = ["ce_cluster_edges", "ce_workspace_bytes", "ce_max_clusters", "ce_last_error"]
+_EXPORTS = ["ce_cluster_edges", "ce_workspace_bytes", "ce_max_clusters", "ce_last_error", "ce_timing_enable",
+            "ce_timing_read"]
 _lib = None
 
 
@@ -59,6 +60,10 @@ def load_library(path: str = LIB_PATH):
         lib.ce_max_clusters.restype = ctypes.c_int64
         lib.ce_last_error.argtypes = []
         lib.ce_last_error.restype = ctypes.c_char_p
+        lib.ce_timing_enable.argtypes = [ctypes.c_char_p]
+        lib.ce_timing_enable.restype = ctypes.c_int
+        lib.ce_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
+        lib.ce_timing_read.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -83,6 +88,18 @@ def max_clusters(n: int, min_cluster_size: int) -> int:
 
 def last_error() -> str:
     return load_library().ce_last_error().decode()
+
+
+def timing_enable(kernel_name):
+    """Time every launch of library kernels whose name contains kernel_name (None: off)."""
+    load_library().ce_timing_enable(kernel_name.encode() if kernel_name else None)
+
+
+def timing_read():
+    """(total milliseconds, launches) accumulated since timing_enable."""
+    ms, cnt = ctypes.c_double(), ctypes.c_int64()
+    load_library().ce_timing_read(ctypes.byref(ms), ctypes.byref(cnt))
+    return float(ms.value), int(cnt.value)
 
 
 class ClusterError(RuntimeError):

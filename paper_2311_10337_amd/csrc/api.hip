@@ -1,7 +1,10 @@
 // C ABI of libce: argument checks, workspace layout, stage orchestration.
 #include <string.h>
 
+#include <mutex>
 #include <string>
+#include <utility>
+#include <vector>
 
 #include "ce_internal.h"
 
@@ -10,6 +13,34 @@ namespace ce {
 static thread_local std::string g_err = "no error";
 
 void set_error(const std::string &msg) { g_err = msg; }
+
+static std::mutex g_tmu;
+static std::string g_tname;
+static std::vector<std::pair<hipEvent_t, hipEvent_t>> g_tev;
+static double g_tms = 0.0;
+static int64_t g_tcount = 0;
+
+bool timing_wants(const char *kernel) {
+  std::lock_guard<std::mutex> l(g_tmu);
+  return !g_tname.empty() && strstr(kernel, g_tname.c_str()) != nullptr;
+}
+void timing_push(hipEvent_t a, hipEvent_t b) {
+  std::lock_guard<std::mutex> l(g_tmu);
+  g_tev.emplace_back(a, b);
+}
+void timing_collect() {
+  std::lock_guard<std::mutex> l(g_tmu);
+  for (auto &pr : g_tev) {
+    float ms = 0.f;
+    if (hipEventSynchronize(pr.second) == hipSuccess && hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+      g_tms += ms;
+      g_tcount++;
+    }
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
+  g_tev.clear();
+}
 
 namespace {
 
@@ -55,7 +86,7 @@ __global__ void k_trivial(int64_t n, ce_result out) {
 
 ce_status stage_write_rows(Bufs &b, int64_t m, const ce_result *out, hipStream_t s) {
   if (m <= 0) return CE_OK;
-  hipLaunchKernelGGL(k_rows, dim3(grid_for(m, B)), dim3(B), 0, s, b.msf_key, b.msf_val, b.kc_u, b.kc_v, b.ksize, b.perm,
+  CE_LAUNCH(k_rows, dim3(grid_for(m, B)), dim3(B), 0, s, b.msf_key, b.msf_val, b.kc_u, b.kc_v, b.ksize, b.perm,
                      m, b.n, b.idbits, *out);
   CE_HIP(hipGetLastError());
   return CE_OK;
@@ -67,6 +98,7 @@ static void layout(Bufs &b, Ws &ws, int64_t n, int64_t M) {
   b.perm = ws.alloc<uint32_t>(n);
   b.skel_key = ws.alloc<uint64_t>(2 * n);
   b.skel_tail = ws.alloc<uint32_t>(2 * n);
+  b.best = ws.alloc<uint64_t>(n);
   b.msf_flag = ws.alloc<uint8_t>(2 * n);
   b.msf_key = ws.alloc<uint64_t>(n);
   b.msf_val = ws.alloc<uint64_t>(n);
@@ -122,6 +154,21 @@ size_t ce_workspace_bytes(int64_t n, int64_t num_vertices, const ce_params *para
 
 const char *ce_last_error(void) { return g_err.c_str(); }
 
+int ce_timing_enable(const char *kernel_name) {
+  std::lock_guard<std::mutex> l(g_tmu);
+  g_tname = kernel_name ? kernel_name : "";
+  g_tms = 0.0;
+  g_tcount = 0;
+  return 0;
+}
+
+int ce_timing_read(double *total_ms, int64_t *launches) {
+  std::lock_guard<std::mutex> l(g_tmu);
+  if (total_ms) *total_ms = g_tms;
+  if (launches) *launches = g_tcount;
+  return 0;
+}
+
 ce_status ce_cluster_edges(const int32_t *src, const int32_t *dst, const int64_t *t, int64_t n, const ce_params *params,
                            const ce_result *out, ce_counts *counts, void *workspace, size_t workspace_bytes,
                            void *stream) {
@@ -173,7 +220,7 @@ ce_status ce_cluster_edges(const int32_t *src, const int32_t *dst, const int64_t
   if (flags & 1) { set_error("self loop in input (src == dst)"); return CE_ESELFLOOP; }
   if (flags & 2) { set_error("vertex id outside [0, num_vertices)"); return CE_ERANGE; }
   if (n <= 1) {
-    hipLaunchKernelGGL(k_trivial, dim3(1), dim3(64), 0, s, n, *out);
+    CE_LAUNCH(k_trivial, dim3(1), dim3(64), 0, s, n, *out);
     CE_HIP(hipGetLastError());
     CE_HIP(hipStreamSynchronize(s));
     return CE_OK;
@@ -200,6 +247,7 @@ ce_status ce_cluster_edges(const int32_t *src, const int32_t *dst, const int64_t
   CE_TRY(stage_condense(b, m, out, sw, s, counts));
   counts->m = m;
   CE_HIP(hipStreamSynchronize(s));
+  timing_collect();
   return CE_OK;
 }
 

@@ -40,6 +40,38 @@ void set_error(const std::string &msg);
     if (s_ != CE_OK) return s_;        \
   } while (0)
 
+// ------------------------------------------------------- kernel timing
+// When enabled for a kernel name (ce_timing_enable), every launch whose
+// name contains it is bracketed by HIP events on the launch stream; the
+// elapsed times are collected when ce_cluster_edges returns.
+bool timing_wants(const char *kernel);
+void timing_push(hipEvent_t a, hipEvent_t b);
+void timing_collect();
+struct KTime {
+  hipEvent_t a = nullptr, b = nullptr;
+  hipStream_t s;
+  bool on;
+  KTime(const char *name, hipStream_t st) : s(st), on(timing_wants(name)) {
+    if (on) {
+      (void)hipEventCreate(&a);
+      (void)hipEventCreate(&b);
+      (void)hipEventRecord(a, s);
+    }
+  }
+  void stop() {
+    if (on) {
+      (void)hipEventRecord(b, s);
+      timing_push(a, b);
+    }
+  }
+};
+#define CE_LAUNCH(kernel, grid, block, shmem, stream, ...)              \
+  do {                                                                \
+    ::ce::KTime kt_(#kernel, stream);                                 \
+    hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__); \
+    kt_.stop();                                                       \
+  } while (0)
+
 // ---------------------------------------------------------- workspace plan
 // Bump allocator over one device buffer. With base == nullptr it only
 // measures (used by ce_workspace_bytes), so the same layout code sizes and
@@ -111,6 +143,49 @@ __host__ __device__ inline uint64_t lambda_of(int64_t w) {
   return w <= 0 ? (uint64_t(1) << 63) : ((uint64_t(1) << 63) / (2 * (uint64_t)w));
 }
 
+// ------------------------------------------------------ wave/block helpers
+__device__ inline uint32_t wave_lane() { return threadIdx.x & 63u; }
+__device__ inline uint64_t lanes_below(uint32_t lane) { return lane == 0 ? 0ull : (~0ull >> (64 - lane)); }
+
+// Tile compaction: a 256-thread block keeps the elements of its tile
+// [tile_base, tile_base + 256*CT) for which keep[k] is set and appends
+// vals[k] to out[] with ONE atomic on the global counter per tile. Thread t
+// owns elements tile_base + k*256 + t (coalesced loads). The output keeps
+// element order inside the tile: per (k, wave) a ballot count, one 64-wide
+// exclusive scan over the (k, wave) counts, then popcount ranks within the
+// wave. Call from all threads of the block.
+constexpr int CT = 16;
+__device__ inline void tile_append(const bool (&keep)[CT], const uint32_t (&vals)[CT], uint32_t *out,
+                                   unsigned long long *counter) {
+  __shared__ uint32_t s_cnt[CT * 4];
+  __shared__ uint32_t s_base;
+  const uint32_t lane = wave_lane(), w = threadIdx.x >> 6;
+  uint64_t mask[CT];
+#pragma unroll
+  for (int k = 0; k < CT; k++) {
+    mask[k] = __ballot(keep[k]);
+    if (lane == 0) s_cnt[k * 4 + w] = (uint32_t)__popcll(mask[k]);
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {  // CT * 4 == 64 counts in (k, wave) order
+    uint32_t x = s_cnt[threadIdx.x], inc = x;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      uint32_t y = __shfl_up(inc, d, 64);
+      if (threadIdx.x >= (uint32_t)d) inc += y;
+    }
+    uint32_t tot = __shfl(inc, 63, 64);
+    s_cnt[threadIdx.x] = inc - x;
+    if (threadIdx.x == 0) s_base = tot ? (uint32_t)atomicAdd(counter, (unsigned long long)tot) : 0u;
+  }
+  __syncthreads();
+  const uint64_t below = lanes_below(lane);
+#pragma unroll
+  for (int k = 0; k < CT; k++)
+    if (keep[k]) out[s_base + s_cnt[k * 4 + w] + (uint32_t)__popcll(mask[k] & below)] = vals[k];
+  __syncthreads();  // s_cnt / s_base may be reused by a second call
+}
+
 // ------------------------------------------------------------ primitives
 // Exclusive scan of n elements; out must hold n+1 (out[n] = total). In-place allowed.
 ce_status scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, Ws &ws, hipStream_t s);
@@ -143,6 +218,7 @@ struct Bufs {
   uint32_t *perm = nullptr;     // [n] rank -> input id
   uint64_t *skel_key = nullptr; // [2n] slot 2h+s: key of the skeleton edge whose head is rank h
   uint32_t *skel_tail = nullptr;// [2n] tail rank of that edge or NONE
+  uint64_t *best = nullptr;     // [n] Boruvka: minimum key leaving each component
   uint8_t *msf_flag = nullptr;  // [2n]
   uint64_t *msf_key = nullptr;  // [n] sorted MSF keys
   uint64_t *msf_val = nullptr;  // [n] (head rank << 32) | tail rank

@@ -72,35 +72,61 @@ __global__ __launch_bounds__(B) void k_cd_birth(const uint32_t *kc_u, const uint
   }
 }
 
-// J[j] for big rows: self if birth, ROOT if a root, else the parent node
+__device__ inline bool j_terminal(uint32_t x, int64_t n, int64_t m, const uint8_t *isbirth) {
+  return x == (uint32_t)(n + m) || isbirth[x - n];
+}
+
+// J[j] for big rows: self if birth, ROOT if a root, else the parent node.
+// Rows whose J is not yet a birth node or ROOT go to the active list.
 __global__ __launch_bounds__(B) void k_cd_jinit(const uint8_t *isbirth, const uint32_t *kpar, const uint32_t *ksize,
-                                                int64_t m, int64_t n, int64_t M, uint32_t *J) {
+                                                int64_t m, int64_t n, int64_t M, uint32_t *J, uint32_t *act,
+                                                unsigned long long *nact) {
   const uint32_t ROOT = (uint32_t)(n + m);
-  for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
+  bool keep[CT];
+  uint32_t vals[CT];
+  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < CT; k++) {
+    const int64_t j = base + (int64_t)k * B;
+    keep[k] = false;
+    vals[k] = (uint32_t)j;
+    if (j >= m) continue;
     uint32_t v = NONE32;
     if (ksize[j] >= (uint64_t)M) {
       if (isbirth[j]) v = (uint32_t)(n + j);
       else if (kpar[n + j] == NONE32) v = ROOT;
-      else v = kpar[n + j];
+      else {
+        v = kpar[n + j];
+        keep[k] = !j_terminal(v, n, m, isbirth);
+      }
     }
     J[j] = v;
   }
+  tile_append(keep, vals, act, nact);
 }
 
-__global__ __launch_bounds__(B) void k_cd_jjump(const uint32_t *Jin, uint32_t *Jout, int64_t m, int64_t n,
-                                                uint32_t *changed) {
-  const uint32_t ROOT = (uint32_t)(n + m);
-  bool ch = false;
-  for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
-    uint32_t x = Jin[j];
-    uint32_t y = x;
-    if (x != NONE32 && x != ROOT && x != (uint32_t)(n + j)) {
-      y = Jin[x - n];
-      if (y != x) ch = true;
+// pointer jumping toward the nearest birth ancestor; finished rows leave the list
+__global__ __launch_bounds__(B) void k_cd_jstep(const uint32_t *act, int64_t nact, uint32_t *J, const uint8_t *isbirth,
+                                                int64_t m, int64_t n, uint32_t *out, unsigned long long *nout) {
+  bool keep[CT];
+  uint32_t vals[CT];
+  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < CT; k++) {
+    const int64_t i = base + (int64_t)k * B;
+    keep[k] = false;
+    vals[k] = 0;
+    if (i >= nact) continue;
+    uint32_t j = act[i];
+    uint32_t x = J[j];
+    uint32_t y = J[x - n];
+    J[j] = y;
+    if (!j_terminal(y, n, m, isbirth)) {
+      keep[k] = true;
+      vals[k] = j;
     }
-    Jout[j] = y;
   }
-  if (__ballot(ch) != 0 && (threadIdx.x & 63) == 0) atomicOr(changed, 1u);
+  tile_append(keep, vals, out, nout);
 }
 
 // exit of each record: lowest big ancestor y -> (cluster of y, lambda(w_y))
@@ -178,18 +204,47 @@ __device__ inline void wave_add_limbs(bool active, uint32_t row, uint64_t l0, ui
   }
 }
 
+// Per-tile aggregation in an LDS hash of rows (one global atomic per row per
+// 4096 records); a record whose row finds no free slot adds directly.
+constexpr int AHS = 512;
 __global__ __launch_bounds__(B) void k_cd_acc_points(const uint32_t *exc, const uint64_t *exl, const uint32_t *rowof,
                                                      int64_t m, int64_t n, uint32_t nbirth,
                                                      unsigned long long *acc) {
-  int64_t p = (int64_t)blockIdx.x * B + threadIdx.x;
-  bool act = p < n;
-  uint32_t r = 0;
-  uint64_t L = 0;
-  if (act) {
-    r = row_of(exc[p], n, m, rowof, nbirth);
-    L = exl[p];
+  __shared__ uint32_t hk[AHS];
+  __shared__ unsigned long long h0[AHS], h1[AHS];
+  for (int i = threadIdx.x; i < AHS; i += B) { hk[i] = NONE32; h0[i] = 0; h1[i] = 0; }
+  __syncthreads();
+  const int64_t tbase = (int64_t)blockIdx.x * (B * CT);
+  for (int k = 0; k < CT; k++) {
+    const int64_t p = tbase + (int64_t)k * B + threadIdx.x;
+    if (p >= n) continue;
+    const uint64_t L = exl[p];
+    if (L == 0) continue;  // records leaving at lambda 0 add nothing
+    const uint32_t r = row_of(exc[p], n, m, rowof, nbirth);
+    uint32_t sl = (r * 2654435761u) >> 23;  // 9 bits
+    bool placed = false;
+    for (int probe = 0; probe < 16 && !placed; probe++) {
+      uint32_t old = atomicCAS(&hk[sl], NONE32, r);
+      if (old == NONE32 || old == r) {
+        atomicAdd(&h0[sl], (unsigned long long)(L & 0xffffffffull));
+        atomicAdd(&h1[sl], (unsigned long long)(L >> 32));
+        placed = true;
+      } else {
+        sl = (sl + 1) & (AHS - 1);
+      }
+    }
+    if (!placed) {
+      atomicAdd(&acc[3 * (uint64_t)r], (unsigned long long)(L & 0xffffffffull));
+      atomicAdd(&acc[3 * (uint64_t)r + 1], (unsigned long long)(L >> 32));
+    }
   }
-  wave_add_limbs(act, r, L & 0xffffffffull, L >> 32, 0, acc);
+  __syncthreads();
+  for (int i = threadIdx.x; i < AHS; i += B) {
+    uint32_t r = hk[i];
+    if (r == NONE32) continue;
+    if (h0[i]) atomicAdd(&acc[3 * (uint64_t)r], h0[i]);
+    if (h1[i]) atomicAdd(&acc[3 * (uint64_t)r + 1], h1[i]);
+  }
 }
 
 __global__ __launch_bounds__(B) void k_cd_acc_children(const uint32_t *csize, const uint64_t *cbirth,
@@ -238,31 +293,66 @@ struct Eom {
   uint32_t *dep;
 };
 
-__global__ __launch_bounds__(B) void k_eom_init(const uint32_t *nch, const uint64_t *shi, const uint64_t *slo,
-                                                uint32_t nrows, uint32_t rootrow, Eom e) {
-  for (int64_t r = (int64_t)blockIdx.x * B + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * B) {
-    bool leaf = nch[r] == 0 || r == rootrow;
-    e.st[r] = leaf ? 2 : 0;
-    e.vhi[r] = shi[r];
-    e.vlo[r] = slo[r];
-    e.dep[r] = NONE32;
-  }
+constexpr uint32_t COPY = 0x80000000u;  // list item flag: finished last round, copy state across buffers
+
+__device__ inline void eom_store(const Eom &o, uint32_t r, uint8_t st, u128 v, u128 a, u128 bb, uint32_t dep) {
+  o.st[r] = st;
+  o.vhi[r] = v.hi; o.vlo[r] = v.lo;
+  o.ahi[r] = a.hi; o.alo[r] = a.lo;
+  o.bhi[r] = bb.hi; o.blo[r] = bb.lo;
+  o.dep[r] = dep;
 }
 
-__global__ __launch_bounds__(B) void k_eom_round(Eom in, Eom out, const uint32_t *ch, const uint64_t *shi,
-                                                 const uint64_t *slo, uint32_t nrows, unsigned long long *pending) {
-  bool pend = false;
-  for (int64_t r = (int64_t)blockIdx.x * B + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * B) {
+__global__ __launch_bounds__(B) void k_eom_init(const uint32_t *nch, const uint64_t *shi, const uint64_t *slo,
+                                                uint32_t nrows, uint32_t rootrow, Eom e0, Eom e1, uint32_t *act,
+                                                unsigned long long *nact) {
+  bool keep[CT];
+  uint32_t vals[CT];
+  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < CT; k++) {
+    const int64_t r = base + (int64_t)k * B;
+    keep[k] = false;
+    vals[k] = (uint32_t)r;
+    if (r >= nrows) continue;
+    bool leaf = nch[r] == 0 || r == rootrow;
+    u128 S{slo[r], shi[r]}, z{0, 0};
+    eom_store(e0, (uint32_t)r, leaf ? 2 : 0, S, z, z, NONE32);
+    eom_store(e1, (uint32_t)r, leaf ? 2 : 0, S, z, z, NONE32);
+    keep[k] = !leaf;
+  }
+  tile_append(keep, vals, act, nact);
+}
+
+// One round over the pending rows: rake (both children done), turn into a
+// unary f(x) = max(a, x + b) when one child is done, or compose along a chain
+// of unary rows (pointer jumping). Reads `in`, writes `out`.
+__global__ __launch_bounds__(B) void k_eom_round(const uint32_t *act, int64_t nact, Eom in, Eom out,
+                                                 const uint32_t *ch, const uint64_t *shi, const uint64_t *slo,
+                                                 uint32_t *next, unsigned long long *nnext) {
+  bool keep[CT];
+  uint32_t vals[CT];
+  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < CT; k++) {
+    const int64_t i = base + (int64_t)k * B;
+    keep[k] = false;
+    vals[k] = 0;
+    if (i >= nact) continue;
+    const uint32_t item = act[i], r = item & ~COPY;
     uint8_t st = in.st[r];
     u128 v{in.vlo[r], in.vhi[r]}, a{in.alo[r], in.ahi[r]}, bb{in.blo[r], in.bhi[r]};
     uint32_t dep = in.dep[r];
+    if (item & COPY) {
+      eom_store(out, r, st, v, a, bb, dep);
+      continue;
+    }
     if (st == 0) {
-      uint32_t c1 = ch[2 * r], c2 = ch[2 * r + 1];
+      uint32_t c1 = ch[2 * (uint64_t)r], c2 = ch[2 * (uint64_t)r + 1];
       bool d1 = in.st[c1] == 2, d2 = in.st[c2] == 2;
       u128 S{slo[r], shi[r]};
       if (d1 && d2) {
-        u128 sum = u128_add(u128{in.vlo[c1], in.vhi[c1]}, u128{in.vlo[c2], in.vhi[c2]});
-        v = u128_max(S, sum);
+        v = u128_max(S, u128_add(u128{in.vlo[c1], in.vhi[c1]}, u128{in.vlo[c2], in.vhi[c2]}));
         st = 2;
       } else if (d1 || d2) {
         uint32_t dn = d1 ? c1 : c2, pn = d1 ? c2 : c1;
@@ -283,21 +373,27 @@ __global__ __launch_bounds__(B) void k_eom_round(Eom in, Eom out, const uint32_t
         dep = in.dep[dep];
       }
     }
-    out.st[r] = st;
-    out.vhi[r] = v.hi; out.vlo[r] = v.lo;
-    out.ahi[r] = a.hi; out.alo[r] = a.lo;
-    out.bhi[r] = bb.hi; out.blo[r] = bb.lo;
-    out.dep[r] = dep;
-    if (st != 2) pend = true;
+    eom_store(out, r, st, v, a, bb, dep);
+    keep[k] = true;
+    vals[k] = st == 2 ? (r | COPY) : r;
   }
-  if (__ballot(pend) != 0 && (threadIdx.x & 63) == 0) atomicAdd(pending, 1ull);
+  tile_append(keep, vals, next, nnext);
 }
 
 // selection with ties kept by the parent; ROOT never selected
 __global__ __launch_bounds__(B) void k_eom_select(const uint32_t *nch, const uint32_t *ch, Eom e, const uint64_t *shi,
                                                   const uint64_t *slo, uint32_t nrows, uint32_t rootrow,
-                                                  uint32_t *top, uint32_t *nxt, const uint32_t *cprow) {
-  for (int64_t r = (int64_t)blockIdx.x * B + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * B) {
+                                                  uint32_t *top, uint32_t *nxt, uint32_t *top2, uint32_t *nxt2,
+                                                  const uint32_t *cprow, uint32_t *act, unsigned long long *nact) {
+  bool keep[CT];
+  uint32_t vals[CT];
+  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < CT; k++) {
+    const int64_t r = base + (int64_t)k * B;
+    keep[k] = false;
+    vals[k] = (uint32_t)r;
+    if (r >= nrows) continue;
     bool sel;
     if (r == rootrow) sel = false;
     else if (nch[r] == 0) sel = true;
@@ -306,28 +402,45 @@ __global__ __launch_bounds__(B) void k_eom_select(const uint32_t *nch, const uin
       u128 sum = u128_add(u128{e.vlo[c1], e.vhi[c1]}, u128{e.vlo[c2], e.vhi[c2]});
       sel = !u128_gt(sum, u128{slo[r], shi[r]});
     }
-    top[r] = sel ? (uint32_t)r : NONE32;
+    uint32_t t = sel ? (uint32_t)r : NONE32;
     uint32_t p = cprow[r];
-    nxt[r] = (p == NONE32 || p == rootrow) ? NONE32 : p;
+    uint32_t nx = (p == NONE32 || p == rootrow) ? NONE32 : p;
+    top[r] = t; top2[r] = t;
+    nxt[r] = nx; nxt2[r] = nx;
+    keep[k] = nx != NONE32;
   }
+  tile_append(keep, vals, act, nact);
 }
 
 // top[r] = highest selected row among r and its ancestors below ROOT
-__global__ __launch_bounds__(B) void k_top_jump(const uint32_t *tin, const uint32_t *nin, uint32_t *tout,
-                                                uint32_t *nout, uint32_t nrows, unsigned long long *active) {
-  bool act = false;
-  for (int64_t r = (int64_t)blockIdx.x * B + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * B) {
+__global__ __launch_bounds__(B) void k_top_jump(const uint32_t *act, int64_t nact, const uint32_t *tin,
+                                                const uint32_t *nin, uint32_t *tout, uint32_t *nout, uint32_t *next,
+                                                unsigned long long *nnext) {
+  bool keep[CT];
+  uint32_t vals[CT];
+  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < CT; k++) {
+    const int64_t i = base + (int64_t)k * B;
+    keep[k] = false;
+    vals[k] = 0;
+    if (i >= nact) continue;
+    const uint32_t item = act[i], r = item & ~COPY;
     uint32_t nx = nin[r], t = tin[r];
-    if (nx != NONE32) {
-      uint32_t tv = tin[nx];
-      if (tv != NONE32) t = tv;
-      nx = nin[nx];
+    if (item & COPY) {
+      tout[r] = t;
+      nout[r] = nx;
+      continue;
     }
+    uint32_t tv = tin[nx];
+    if (tv != NONE32) t = tv;
+    nx = nin[nx];
     tout[r] = t;
     nout[r] = nx;
-    if (nx != NONE32) act = true;
+    keep[k] = true;
+    vals[k] = nx == NONE32 ? (r | COPY) : r;
   }
-  if (__ballot(act) != 0 && (threadIdx.x & 63) == 0) atomicAdd(active, 1ull);
+  tile_append(keep, vals, next, nnext);
 }
 
 __global__ __launch_bounds__(B) void k_lab_rows(const uint32_t *exc, const uint32_t *rowof, const uint32_t *top,
@@ -384,7 +497,7 @@ size_t stage_condense_scratch(int64_t n, int64_t M) {
   int64_t m = n, R = 2 * (n / (M < 2 ? 2 : M)) + 2;
   Ws w;
   w.alloc<uint32_t>(n + m + 1);  // kpar
-  w.alloc<uint32_t>(m + 1); w.alloc<uint32_t>(m + 1);  // J, J2
+  w.alloc<uint32_t>(m + 1); w.alloc<uint32_t>(m + 1); w.alloc<uint32_t>(m + 1);  // J, active lists
   w.alloc<uint8_t>(m + 4);       // isbirth
   w.alloc<uint64_t>(m + 1);      // birthL
   w.alloc<uint32_t>(m + 2); w.alloc<uint32_t>(m + 2);  // flags32, rowof
@@ -400,6 +513,7 @@ size_t stage_condense_scratch(int64_t n, int64_t M) {
   }
   for (int k = 0; k < 4; k++) w.alloc<uint32_t>(R);  // top nxt x2
   w.alloc<uint32_t>(R);  // minmem
+  w.alloc<uint32_t>(R); w.alloc<uint32_t>(R);  // row active lists
   w.alloc<uint32_t>(n);  // labrow
   w.alloc<uint32_t>(n + 1);  // flag / scan
   return w.off + scan_ws_bytes(n + 1) + scan_ws_bytes(m + 1) + 8192;
@@ -410,7 +524,8 @@ ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipSt
   size_t m0 = ws.mark();
   const int64_t R = 2 * (n / M) + 2;
   uint32_t *kpar = ws.alloc<uint32_t>(n + m + 1);
-  uint32_t *J = ws.alloc<uint32_t>(m + 1), *J2 = ws.alloc<uint32_t>(m + 1);
+  uint32_t *J = ws.alloc<uint32_t>(m + 1);
+  uint32_t *jact = ws.alloc<uint32_t>(m + 1), *jact2 = ws.alloc<uint32_t>(m + 1);
   uint8_t *isbirth = ws.alloc<uint8_t>(m + 4);
   uint64_t *birthL = ws.alloc<uint64_t>(m + 1);
   uint32_t *flags32 = ws.alloc<uint32_t>(m + 2), *rowof = ws.alloc<uint32_t>(m + 2);
@@ -433,47 +548,51 @@ ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipSt
   uint32_t *top = ws.alloc<uint32_t>(R), *nxt = ws.alloc<uint32_t>(R);
   uint32_t *top2 = ws.alloc<uint32_t>(R), *nxt2 = ws.alloc<uint32_t>(R);
   uint32_t *minmem = ws.alloc<uint32_t>(R);
+  uint32_t *ract = ws.alloc<uint32_t>(R), *ract2 = ws.alloc<uint32_t>(R);
   uint32_t *labrow = ws.alloc<uint32_t>(n);
   uint32_t *fl = ws.alloc<uint32_t>(n + 1);
   CE_WS_CHECK(ws);
   unsigned long long *ctr = (unsigned long long *)&b.hdr[8];
-  uint32_t *chg = (uint32_t *)&b.hdr[9];
+  auto tiles = [](int64_t k) { return (unsigned)((k + (int64_t)B * CT - 1) / ((int64_t)B * CT)); };
 
   const unsigned gN = grid_for(n + m + 1, B), gm = grid_for(m + 1, B);
-  hipLaunchKernelGGL(k_fill32, dim3(gN), dim3(B), 0, s, kpar, n + m + 1, NONE32);
+  CE_LAUNCH(k_fill32, dim3(gN), dim3(B), 0, s, kpar, n + m + 1, NONE32);
   if (m > 0)
-    hipLaunchKernelGGL(k_cd_parents, dim3(grid_for(m, B)), dim3(B), 0, s, b.kc_u, b.kc_v, m, n, kpar);
-  hipLaunchKernelGGL(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[8], (uint64_t)0);
+    CE_LAUNCH(k_cd_parents, dim3(grid_for(m, B)), dim3(B), 0, s, b.kc_u, b.kc_v, m, n, kpar);
+  CE_LAUNCH(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[8], (uint64_t)0);
   if (m > 0)
-    hipLaunchKernelGGL(k_cd_bigroots, dim3(grid_for(m, B)), dim3(B), 0, s, kpar, b.ksize, m, n, M, ctr);
+    CE_LAUNCH(k_cd_bigroots, dim3(grid_for(m, B)), dim3(B), 0, s, kpar, b.ksize, m, n, M, ctr);
   CE_HIP(hipGetLastError());
   uint64_t nbig = 0;
   CE_TRY(read_u64(&b.hdr[8], &nbig, 1, s));
   {
-    hipLaunchKernelGGL(k_fill32, dim3(grid_for((m + 4) / 4, B)), dim3(B), 0, s, (uint32_t *)isbirth, (m + 4) / 4, 0u);
+    CE_LAUNCH(k_fill32, dim3(grid_for((m + 4) / 4, B)), dim3(B), 0, s, (uint32_t *)isbirth, (m + 4) / 4, 0u);
   }
   if (m > 0) {
-    hipLaunchKernelGGL(k_cd_birth, dim3(grid_for(m, B)), dim3(B), 0, s, b.kc_u, b.kc_v, b.ksize, kpar, b.msf_key,
+    CE_LAUNCH(k_cd_birth, dim3(grid_for(m, B)), dim3(B), 0, s, b.kc_u, b.kc_v, b.ksize, kpar, b.msf_key,
                        b.idbits, m, n, M, nbig, isbirth, birthL);
-    hipLaunchKernelGGL(k_cd_jinit, dim3(grid_for(m, B)), dim3(B), 0, s, isbirth, kpar, b.ksize, m, n, M, J);
+    CE_LAUNCH(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[9], (uint64_t)0);
+    CE_LAUNCH(k_cd_jinit, dim3(tiles(m)), dim3(B), 0, s, isbirth, kpar, b.ksize, m, n, M, J, jact,
+                       (unsigned long long *)&b.hdr[9]);
     CE_HIP(hipGetLastError());
-    for (int it = 0;; it++) {
+    uint64_t nact = 0;
+    CE_TRY(read_u64(&b.hdr[9], &nact, 1, s));
+    for (int it = 0; nact > 0; it++) {
       if (it > 40) {
         set_error("cluster pointer jumping did not converge");
         return CE_EDEVICE;
       }
-      hipLaunchKernelGGL(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[9], (uint64_t)0);
-      hipLaunchKernelGGL(k_cd_jjump, dim3(grid_for(m, B)), dim3(B), 0, s, J, J2, m, n, chg);
+      CE_LAUNCH(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[9], (uint64_t)0);
+      CE_LAUNCH(k_cd_jstep, dim3(tiles((int64_t)nact)), dim3(B), 0, s, jact, (int64_t)nact, J, isbirth, m, n,
+                         jact2, (unsigned long long *)&b.hdr[9]);
       CE_HIP(hipGetLastError());
-      uint32_t *tmp = J; J = J2; J2 = tmp;
-      uint64_t c = 0;
-      CE_TRY(read_u64(&b.hdr[9], &c, 1, s));
-      if ((c & 0xffffffffull) == 0) break;
+      uint32_t *tmp = jact; jact = jact2; jact2 = tmp;
+      CE_TRY(read_u64(&b.hdr[9], &nact, 1, s));
     }
   }
-  hipLaunchKernelGGL(k_cd_exit, dim3(grid_for(n, B)), dim3(B), 0, s, kpar, b.ksize, J, b.msf_key, b.idbits, m, n, M,
+  CE_LAUNCH(k_cd_exit, dim3(grid_for(n, B)), dim3(B), 0, s, kpar, b.ksize, J, b.msf_key, b.idbits, m, n, M,
                      exc, exl);
-  hipLaunchKernelGGL(k_u8_to_u32, dim3(gm), dim3(B), 0, s, isbirth, m, flags32);
+  CE_LAUNCH(k_u8_to_u32, dim3(gm), dim3(B), 0, s, isbirth, m, flags32);
   CE_HIP(hipGetLastError());
   CE_TRY(scan_exclusive_u32(flags32, rowof, m, ws, s));
   uint64_t nb64 = 0;
@@ -490,61 +609,66 @@ ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipSt
     return CE_EDEVICE;
   }
   const unsigned gR = grid_for(nrows, B);
-  hipLaunchKernelGGL(k_cd_rows, dim3(gm), dim3(B), 0, s, isbirth, rowof, b.ksize, birthL, kpar, J, m, n, nbirth, cnode,
+  CE_LAUNCH(k_cd_rows, dim3(gm), dim3(B), 0, s, isbirth, rowof, b.ksize, birthL, kpar, J, m, n, nbirth, cnode,
                      csize, cbirth, cprow);
-  hipLaunchKernelGGL(k_fill64, dim3(grid_for(3 * (int64_t)nrows, B)), dim3(B), 0, s, (uint64_t *)acc,
+  CE_LAUNCH(k_fill64, dim3(grid_for(3 * (int64_t)nrows, B)), dim3(B), 0, s, (uint64_t *)acc,
                      3 * (int64_t)nrows, (uint64_t)0);
-  hipLaunchKernelGGL(k_cd_acc_points, dim3((unsigned)((n + B - 1) / B)), dim3(B), 0, s, exc, exl, rowof, m, n,
-                     nbirth, acc);
-  hipLaunchKernelGGL(k_cd_acc_children, dim3((unsigned)((nrows + B - 1) / B)), dim3(B), 0, s, csize, cbirth, cprow,
+  CE_LAUNCH(k_cd_acc_points, dim3(tiles(n)), dim3(B), 0, s, exc, exl, rowof, m, n, nbirth, acc);
+  CE_LAUNCH(k_cd_acc_children, dim3((unsigned)((nrows + B - 1) / B)), dim3(B), 0, s, csize, cbirth, cprow,
                      nrows, acc);
-  hipLaunchKernelGGL(k_cd_stab, dim3(gR), dim3(B), 0, s, acc, csize, cbirth, nrows, shi, slo);
-  hipLaunchKernelGGL(k_fill32, dim3(gR), dim3(B), 0, s, nch, (int64_t)nrows, 0u);
-  hipLaunchKernelGGL(k_fill32, dim3(grid_for(2 * (int64_t)nrows, B)), dim3(B), 0, s, ch, 2 * (int64_t)nrows, 0u);
-  hipLaunchKernelGGL(k_cd_children, dim3(gR), dim3(B), 0, s, cprow, nrows, rootrow, nch, ch);
-  hipLaunchKernelGGL(k_eom_init, dim3(gR), dim3(B), 0, s, nch, shi, slo, nrows, rootrow, e[0]);
+  CE_LAUNCH(k_cd_stab, dim3(gR), dim3(B), 0, s, acc, csize, cbirth, nrows, shi, slo);
+  CE_LAUNCH(k_fill32, dim3(gR), dim3(B), 0, s, nch, (int64_t)nrows, 0u);
+  CE_LAUNCH(k_fill32, dim3(grid_for(2 * (int64_t)nrows, B)), dim3(B), 0, s, ch, 2 * (int64_t)nrows, 0u);
+  CE_LAUNCH(k_cd_children, dim3(gR), dim3(B), 0, s, cprow, nrows, rootrow, nch, ch);
+  CE_LAUNCH(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[8], (uint64_t)0);
+  CE_LAUNCH(k_eom_init, dim3(tiles(nrows)), dim3(B), 0, s, nch, shi, slo, nrows, rootrow, e[0], e[1], ract,
+                     ctr);
   CE_HIP(hipGetLastError());
+  uint64_t nact = 0;
+  CE_TRY(read_u64(&b.hdr[8], &nact, 1, s));
   int cur = 0;
-  for (int it = 0;; it++) {
+  for (int it = 0; nact > 0; it++) {
     if (it > 4096) {
       set_error("excess-of-mass rounds did not converge");
       return CE_EDEVICE;
     }
-    hipLaunchKernelGGL(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[8], (uint64_t)0);
-    hipLaunchKernelGGL(k_eom_round, dim3(gR), dim3(B), 0, s, e[cur], e[1 - cur], ch, shi, slo, nrows, ctr);
+    CE_LAUNCH(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[8], (uint64_t)0);
+    CE_LAUNCH(k_eom_round, dim3(tiles((int64_t)nact)), dim3(B), 0, s, ract, (int64_t)nact, e[cur], e[1 - cur],
+                       ch, shi, slo, ract2, ctr);
     CE_HIP(hipGetLastError());
     cur = 1 - cur;
-    uint64_t p = 0;
-    CE_TRY(read_u64(&b.hdr[8], &p, 1, s));
-    if (p == 0) break;
+    uint32_t *tmp = ract; ract = ract2; ract2 = tmp;
+    CE_TRY(read_u64(&b.hdr[8], &nact, 1, s));
   }
-  hipLaunchKernelGGL(k_eom_select, dim3(gR), dim3(B), 0, s, nch, ch, e[cur], shi, slo, nrows, rootrow, top, nxt,
-                     cprow);
+  CE_LAUNCH(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[8], (uint64_t)0);
+  CE_LAUNCH(k_eom_select, dim3(tiles(nrows)), dim3(B), 0, s, nch, ch, e[cur], shi, slo, nrows, rootrow, top,
+                     nxt, top2, nxt2, cprow, ract, ctr);
   CE_HIP(hipGetLastError());
-  for (int it = 0;; it++) {
+  CE_TRY(read_u64(&b.hdr[8], &nact, 1, s));
+  for (int it = 0; nact > 0; it++) {
     if (it > 40) {
       set_error("label pointer jumping did not converge");
       return CE_EDEVICE;
     }
-    hipLaunchKernelGGL(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[8], (uint64_t)0);
-    hipLaunchKernelGGL(k_top_jump, dim3(gR), dim3(B), 0, s, top, nxt, top2, nxt2, nrows, ctr);
+    CE_LAUNCH(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[8], (uint64_t)0);
+    CE_LAUNCH(k_top_jump, dim3(tiles((int64_t)nact)), dim3(B), 0, s, ract, (int64_t)nact, top, nxt, top2,
+                       nxt2, ract2, ctr);
     CE_HIP(hipGetLastError());
     uint32_t *t1 = top; top = top2; top2 = t1;
     uint32_t *t2 = nxt; nxt = nxt2; nxt2 = t2;
-    uint64_t a = 0;
-    CE_TRY(read_u64(&b.hdr[8], &a, 1, s));
-    if (a == 0) break;
+    uint32_t *t3 = ract; ract = ract2; ract2 = t3;
+    CE_TRY(read_u64(&b.hdr[8], &nact, 1, s));
   }
-  hipLaunchKernelGGL(k_fill32, dim3(gR), dim3(B), 0, s, minmem, (int64_t)nrows, NONE32);
-  hipLaunchKernelGGL(k_lab_rows, dim3(grid_for(n, B)), dim3(B), 0, s, exc, rowof, top, b.perm, m, n, nbirth, labrow,
+  CE_LAUNCH(k_fill32, dim3(gR), dim3(B), 0, s, minmem, (int64_t)nrows, NONE32);
+  CE_LAUNCH(k_lab_rows, dim3(grid_for(n, B)), dim3(B), 0, s, exc, rowof, top, b.perm, m, n, nbirth, labrow,
                      minmem);
-  hipLaunchKernelGGL(k_fill32, dim3(grid_for(n + 1, B)), dim3(B), 0, s, fl, n + 1, 0u);
-  hipLaunchKernelGGL(k_lab_flags, dim3(gR), dim3(B), 0, s, top, minmem, nrows, fl);
+  CE_LAUNCH(k_fill32, dim3(grid_for(n + 1, B)), dim3(B), 0, s, fl, n + 1, 0u);
+  CE_LAUNCH(k_lab_flags, dim3(gR), dim3(B), 0, s, top, minmem, nrows, fl);
   CE_HIP(hipGetLastError());
   CE_TRY(scan_exclusive_u32(fl, fl, n, ws, s));
-  hipLaunchKernelGGL(k_out_points, dim3(grid_for(n, B)), dim3(B), 0, s, b.perm, exc, exl, labrow, minmem, fl, n,
+  CE_LAUNCH(k_out_points, dim3(grid_for(n, B)), dim3(B), 0, s, b.perm, exc, exl, labrow, minmem, fl, n,
                      out->pt_cluster, out->pt_lambda, out->labels);
-  hipLaunchKernelGGL(k_out_clusters, dim3(gR), dim3(B), 0, s, cnode, cprow, csize, cbirth, shi, slo, top, nrows,
+  CE_LAUNCH(k_out_clusters, dim3(gR), dim3(B), 0, s, cnode, cprow, csize, cbirth, shi, slo, top, nrows,
                      rootrow, *out);
   CE_HIP(hipGetLastError());
   uint32_t nl = 0;

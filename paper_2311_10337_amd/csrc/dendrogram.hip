@@ -33,26 +33,29 @@ __device__ inline void st(uint32_t *p, uint32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// One 16-byte entry per label keeps everything a level needs in a single
+// cache line: x = parent, y = largest row + 1 of the component (0 = none),
+// z = component size. (The hot-root atomics are pre-aggregated in LDS.)
 // lock-free find with path halving; parent pointers only move to ancestors
-__device__ inline uint32_t g_find(uint32_t *uf, uint32_t x) {
+__device__ inline uint32_t g_find(uint4 *uf, uint32_t x) {
   while (true) {
-    uint32_t p = ld(&uf[x]);
+    uint32_t p = ld(&uf[x].x);
     if (p == x) return x;
-    uint32_t gp = ld(&uf[p]);
+    uint32_t gp = ld(&uf[p].x);
     if (gp == p) return p;
-    st(&uf[x], gp);
+    st(&uf[x].x, gp);
     x = gp;
   }
 }
 
 // returns the root that was hooked (the larger of the two roots)
-__device__ inline uint32_t g_union(uint32_t *uf, uint32_t a, uint32_t b) {
+__device__ inline uint32_t g_union(uint4 *uf, uint32_t a, uint32_t b) {
   while (true) {
     a = g_find(uf, a);
     b = g_find(uf, b);
     if (a == b) return NONE32;
     uint32_t hi = a > b ? a : b, lo = a > b ? b : a;
-    if (atomicCAS(&uf[hi], hi, lo) == hi) return hi;
+    if (atomicCAS(&uf[hi].x, hi, lo) == hi) return hi;
   }
 }
 
@@ -68,16 +71,11 @@ __global__ __launch_bounds__(B) void k_krt_init(const uint64_t *msf_val, int64_t
 }
 
 __global__ __launch_bounds__(B) void k_krt_reset(const uint32_t *lu, const uint32_t *lv, const uint32_t *su,
-                                                 const uint32_t *sv, int64_t m, uint32_t *uf, uint32_t *mx,
-                                                 uint32_t *cs) {
+                                                 const uint32_t *sv, int64_t m, uint4 *uf) {
   for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
     uint32_t a = lu[j], b = lv[j];
-    uf[a] = a;
-    uf[b] = b;
-    mx[a] = 0;
-    mx[b] = 0;
-    cs[a] = su[j];
-    cs[b] = sv[j];
+    uf[a] = make_uint4(a, 0u, su[j], 0u);
+    uf[b] = make_uint4(b, 0u, sv[j], 0u);
   }
 }
 
@@ -90,31 +88,30 @@ __device__ inline int64_t step_row(int64_t tix, int lo, int hi, uint32_t q) {
 // relabel the rows of sub-interval q (q >= 1) to the roots after sub-intervals < q
 __global__ __launch_bounds__(B) void k_krt_relabel(int64_t m, int64_t n, int lo, int hi, uint32_t q, int64_t nthreads,
                                                    uint32_t *lu, uint32_t *lv, uint32_t *su, uint32_t *sv,
-                                                   uint32_t *ru, uint32_t *rv, uint32_t *uf, const uint32_t *mx,
-                                                   const uint32_t *cs) {
+                                                   uint32_t *ru, uint32_t *rv, uint4 *uf) {
   for (int64_t tix = (int64_t)blockIdx.x * B + threadIdx.x; tix < nthreads; tix += (int64_t)gridDim.x * B) {
     int64_t j = step_row(tix, lo, hi, q);
     if (j >= m) continue;
     uint32_t a = g_find(uf, lu[j]);
     ru[j] = a;
-    uint32_t ma = mx[a];
-    if (ma) {
-      lu[j] = (uint32_t)(n + ma - 1);
-      su[j] = cs[a];
+    uint4 na = uf[a];
+    if (na.y) {
+      lu[j] = (uint32_t)(n + na.y - 1);
+      su[j] = na.z;
     }
     uint32_t b = g_find(uf, lv[j]);
     rv[j] = b;
-    uint32_t mb = mx[b];
-    if (mb) {
-      lv[j] = (uint32_t)(n + mb - 1);
-      sv[j] = cs[b];
+    uint4 nb = uf[b];
+    if (nb.y) {
+      lv[j] = (uint32_t)(n + nb.y - 1);
+      sv[j] = nb.z;
     }
   }
 }
 
 __global__ __launch_bounds__(B) void k_krt_union(int64_t m, int lo, int hi, uint32_t q, int64_t nthreads,
                                                  const uint32_t *lu, const uint32_t *lv, const uint32_t *ru,
-                                                 const uint32_t *rv, uint32_t *uf, uint32_t *hooked) {
+                                                 const uint32_t *rv, uint4 *uf, uint32_t *hooked) {
   for (int64_t tix = (int64_t)blockIdx.x * B + threadIdx.x; tix < nthreads; tix += (int64_t)gridDim.x * B) {
     int64_t j = step_row(tix, lo, hi, q);
     if (j >= m) continue;
@@ -124,16 +121,50 @@ __global__ __launch_bounds__(B) void k_krt_union(int64_t m, int lo, int hi, uint
   }
 }
 
+// Rows of a sub-interval are consecutive, so a 4096-row tile mostly feeds few
+// components (late steps: the giant one). Sizes and largest rows are summed
+// per component root in an LDS hash first, then one atomic per root per
+// tile; rows whose root finds no free slot go straight to global atomics.
+constexpr int KHS = 256;
+constexpr int KCT = 16;
 __global__ __launch_bounds__(B) void k_krt_accum(int64_t m, int lo, int hi, uint32_t q, int64_t nthreads,
-                                                 const uint32_t *hooked, uint32_t *uf, uint32_t *mx, uint32_t *cs) {
-  for (int64_t tix = (int64_t)blockIdx.x * B + threadIdx.x; tix < nthreads; tix += (int64_t)gridDim.x * B) {
-    int64_t j = step_row(tix, lo, hi, q);
+                                                 const uint32_t *hooked, uint4 *uf) {
+  __shared__ uint32_t hk[KHS], hs[KHS], hm[KHS];
+  for (int i = threadIdx.x; i < KHS; i += B) { hk[i] = NONE32; hs[i] = 0; hm[i] = 0; }
+  __syncthreads();
+  const int64_t tbase = (int64_t)blockIdx.x * (B * KCT);
+  for (int k = 0; k < KCT; k++) {
+    const int64_t tix = tbase + (int64_t)k * B + threadIdx.x;
+    if (tix >= nthreads) continue;
+    const int64_t j = step_row(tix, lo, hi, q);
     if (j >= m) continue;
-    uint32_t h = hooked[j];
+    const uint32_t h = hooked[j];
     if (h == NONE32) continue;
-    uint32_t f = g_find(uf, h);
-    atomicAdd(&cs[f], cs[h]);
-    atomicMax(&mx[f], (uint32_t)(j + 1));
+    const uint32_t f = g_find(uf, h);
+    const uint32_t add = uf[h].z, mj = (uint32_t)(j + 1);
+    uint32_t sl = (f * 2654435761u) >> 24;  // 8 bits
+    bool placed = false;
+    for (int probe = 0; probe < 16 && !placed; probe++) {
+      uint32_t old = atomicCAS(&hk[sl], NONE32, f);
+      if (old == NONE32 || old == f) {
+        atomicAdd(&hs[sl], add);
+        atomicMax(&hm[sl], mj);
+        placed = true;
+      } else {
+        sl = (sl + 1) & (KHS - 1);
+      }
+    }
+    if (!placed) {
+      atomicAdd(&uf[f].z, add);
+      atomicMax(&uf[f].y, mj);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < KHS; i += B) {
+    const uint32_t f = hk[i];
+    if (f == NONE32) continue;
+    atomicAdd(&uf[f].z, hs[i]);
+    atomicMax(&uf[f].y, hm[i]);
   }
 }
 
@@ -273,7 +304,7 @@ int krt_level_bits() {
   static int bits = 0;
   if (!bits) {
     const char *e = getenv("CE_KRT_LEVEL_BITS");
-    bits = e ? atoi(e) : 5;
+    bits = e ? atoi(e) : 6;
     if (bits < 1) bits = 1;
     if (bits > 10) bits = 10;
   }
@@ -283,7 +314,7 @@ int krt_level_bits() {
 size_t stage_dendrogram_scratch(int64_t n) {
   Ws w;
   for (int k = 0; k < 7; k++) w.alloc<uint32_t>(n);  // lu lv su sv ru rv hooked
-  for (int k = 0; k < 3; k++) w.alloc<uint32_t>(2 * n);  // uf mx cs over labels < n + m
+  w.alloc<uint4>(2 * n);  // packed union-find over labels < n + m
   return w.off + 4096;
 }
 
@@ -295,9 +326,9 @@ ce_status stage_dendrogram(Bufs &b, int64_t m, Ws &ws, hipStream_t s) {
   uint32_t *su = ws.alloc<uint32_t>(m), *sv = ws.alloc<uint32_t>(m);
   uint32_t *ru = ws.alloc<uint32_t>(m), *rv = ws.alloc<uint32_t>(m);
   uint32_t *hooked = ws.alloc<uint32_t>(m);
-  uint32_t *uf = ws.alloc<uint32_t>(n + m), *mx = ws.alloc<uint32_t>(n + m), *cs = ws.alloc<uint32_t>(n + m);
+  uint4 *uf = ws.alloc<uint4>(n + m);
   CE_WS_CHECK(ws);
-  hipLaunchKernelGGL(k_krt_init, dim3(grid_for(m, B)), dim3(B), 0, s, b.msf_val, m, lu, lv, su, sv);
+  CE_LAUNCH(k_krt_init, dim3(grid_for(m, B)), dim3(B), 0, s, b.msf_val, m, lu, lv, su, sv);
   CE_HIP(hipGetLastError());
   const int L = bits_for((uint64_t)(m - 1));  // rows are j < 2^L
   const int kb = krt_level_bits();
@@ -309,20 +340,21 @@ ce_status stage_dendrogram(Bufs &b, int64_t m, Ws &ws, hipStream_t s) {
     const int64_t nint = (m + (int64_t(1) << (hi + 1)) - 1) >> (hi + 1);
     const int64_t nthreads = nint << lo;
     const unsigned g = grid_for(nthreads, B, 1 << 16);
-    hipLaunchKernelGGL(k_krt_reset, dim3(grid_for(m, B)), dim3(B), 0, s, lu, lv, su, sv, m, uf, mx, cs);
+    CE_LAUNCH(k_krt_reset, dim3(grid_for(m, B)), dim3(B), 0, s, lu, lv, su, sv, m, uf);
     for (uint32_t q = 0; q < K; q++) {
       // sub-interval q exists in at least one interval?
       if (((int64_t)q << lo) >= m) break;
-      if (q) hipLaunchKernelGGL(k_krt_relabel, dim3(g), dim3(B), 0, s, m, n, lo, hi, q, nthreads, lu, lv, su, sv, ru,
-                                rv, uf, mx, cs);
-      hipLaunchKernelGGL(k_krt_union, dim3(g), dim3(B), 0, s, m, lo, hi, q, nthreads, lu, lv, ru, rv, uf, hooked);
-      hipLaunchKernelGGL(k_krt_accum, dim3(g), dim3(B), 0, s, m, lo, hi, q, nthreads, hooked, uf, mx, cs);
+      if (q) CE_LAUNCH(k_krt_relabel, dim3(g), dim3(B), 0, s, m, n, lo, hi, q, nthreads, lu, lv, su, sv, ru,
+                                rv, uf);
+      CE_LAUNCH(k_krt_union, dim3(g), dim3(B), 0, s, m, lo, hi, q, nthreads, lu, lv, ru, rv, uf, hooked);
+      CE_LAUNCH(k_krt_accum, dim3((unsigned)((nthreads + B * KCT - 1) / (B * KCT))), dim3(B), 0, s, m, lo, hi,
+                         q, nthreads, hooked, uf);
     }
     CE_HIP(hipGetLastError());
     hi = lo - 1;
   }
   const int64_t nblk = (m + LS - 1) / LS;
-  hipLaunchKernelGGL(k_krt_lds, dim3((unsigned)nblk), dim3(B), 0, s, lu, lv, su, sv, m, n, b.kc_u, b.kc_v, b.ksize);
+  CE_LAUNCH(k_krt_lds, dim3((unsigned)nblk), dim3(B), 0, s, lu, lv, su, sv, m, n, b.kc_u, b.kc_v, b.ksize);
   CE_HIP(hipGetLastError());
   ws.release(m0);
   return CE_OK;

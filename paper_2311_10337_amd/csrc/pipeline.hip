@@ -91,14 +91,14 @@ __global__ __launch_bounds__(B) void k_skel_tails(const uint32_t *ikey, const ui
                                                   uint32_t *skel_tail) {
   for (int64_t k = (int64_t)blockIdx.x * B + threadIdx.x; k < n2; k += (int64_t)gridDim.x * B) {
     uint32_t slot = ival[k];
-    uint32_t tail = NONE32;
-    if (k > 0 && ikey[k - 1] == ikey[k]) tail = ival[k - 1] >> 1;
-    skel_tail[slot] = tail;
+    skel_tail[slot] = (k > 0 && ikey[k - 1] == ikey[k]) ? (ival[k - 1] >> 1) : NONE32;
   }
 }
 
+// Also seeds the first Boruvka round: every record starts as its own
+// component, so each edge offers its key to both of its records.
 __global__ __launch_bounds__(B) void k_skel_keys(uint32_t *skel_tail, const uint64_t *ts, const uint32_t *perm,
-                                                 int64_t n, int idbits, uint64_t *skel_key) {
+                                                 int64_t n, int idbits, uint64_t *skel_key, uint64_t *best) {
   for (int64_t h = (int64_t)blockIdx.x * B + threadIdx.x; h < n; h += (int64_t)gridDim.x * B) {
     uint32_t t0 = skel_tail[2 * h], t1 = skel_tail[2 * h + 1];
     if (t0 != NONE32 && t0 == t1) {  // the same pair twice: one line-graph edge
@@ -119,30 +119,11 @@ __global__ __launch_bounds__(B) void k_skel_keys(uint32_t *skel_tail, const uint
     }
     skel_key[2 * h] = k0;
     skel_key[2 * h + 1] = k1;
+    uint64_t mine = k0 < k1 ? k0 : k1;
+    if (mine != NONE64) atomicMin((unsigned long long *)&best[h], (unsigned long long)mine);
+    if (t0 != NONE32) atomicMin((unsigned long long *)&best[t0], (unsigned long long)k0);
+    if (t1 != NONE32) atomicMin((unsigned long long *)&best[t1], (unsigned long long)k1);
   }
-}
-
-// wave-aggregated append into a list through a device counter
-__device__ inline void wave_append(bool keep, uint32_t value, uint32_t *list, unsigned long long *counter) {
-  const int lane = threadIdx.x & 63;
-  uint64_t mask = __ballot(keep);
-  if (mask == 0) return;
-  uint32_t base = 0;
-  int leader = __ffsll((unsigned long long)mask) - 1;
-  if (lane == leader) base = (uint32_t)atomicAdd(counter, (unsigned long long)__popcll(mask));
-  base = __shfl(base, leader, 64);
-  if (keep) {
-    uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    list[base + __popcll(mask & below)] = value;
-  }
-}
-
-__global__ __launch_bounds__(B) void k_live_init(const uint64_t *skel_key, int64_t n2, uint32_t *live,
-                                                 unsigned long long *cnt) {
-  // grid covers n2 exactly (no grid-stride) so every wave reaches the ballot together
-  int64_t e = (int64_t)blockIdx.x * B + threadIdx.x;
-  bool keep = e < n2 && skel_key[e] != NONE64;
-  wave_append(keep, (uint32_t)e, live, cnt);
 }
 
 __global__ __launch_bounds__(B) void k_fill_u64(uint64_t *p, int64_t n, uint64_t v) {
@@ -154,103 +135,180 @@ __global__ __launch_bounds__(B) void k_iota_u32(uint32_t *p, int64_t n) {
 __global__ __launch_bounds__(B) void k_fill_u8(uint8_t *p, int64_t n, uint8_t v) {
   for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < n; i += (int64_t)gridDim.x * B) p[i] = v;
 }
+__global__ __launch_bounds__(B) void k_rankof(const uint32_t *perm, int64_t n, uint32_t *rankof) {
+  for (int64_t r = (int64_t)blockIdx.x * B + threadIdx.x; r < n; r += (int64_t)gridDim.x * B) rankof[perm[r]] = (uint32_t)r;
+}
 
-// Boruvka: per component, the minimum key over live edges leaving it
+// Boruvka: per component, the minimum key over live edges leaving it. A tile
+// of 4096 live edges first takes per-component minima in an LDS hash (big
+// components are hit by most edges of late rounds), then one atomicMin per
+// component per tile; edges whose component finds no free slot go straight
+// to global memory.
+constexpr int MHS = 512;
 __global__ __launch_bounds__(B) void k_bv_min(const uint32_t *live, int64_t nlive, const uint64_t *skel_key,
                                               const uint32_t *skel_tail, const uint32_t *comp, uint64_t *best) {
-  for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < nlive; i += (int64_t)gridDim.x * B) {
-    uint32_t e = live[i];
-    uint32_t cu = comp[skel_tail[e]], cv = comp[e >> 1];
+  __shared__ uint32_t hk[MHS];
+  __shared__ unsigned long long hv[MHS];
+  for (int i = threadIdx.x; i < MHS; i += B) { hk[i] = NONE32; hv[i] = NONE64; }
+  __syncthreads();
+  const int64_t tbase = (int64_t)blockIdx.x * (B * CT);
+  for (int k = 0; k < CT; k++) {
+    const int64_t i = tbase + (int64_t)k * B + threadIdx.x;
+    if (i >= nlive) continue;
+    const uint32_t e = live[i];
+    const unsigned long long key = skel_key[e];
+    const uint32_t cu = comp[skel_tail[e]], cv = comp[e >> 1];
     if (cu == cv) continue;
-    unsigned long long k = skel_key[e];
-    if (k < best[cu]) atomicMin((unsigned long long *)&best[cu], k);
-    if (k < best[cv]) atomicMin((unsigned long long *)&best[cv], k);
+#pragma unroll
+    for (int side = 0; side < 2; side++) {
+      const uint32_t c = side ? cv : cu;
+      uint32_t sl = (c * 2654435761u) >> 23;  // 9 bits
+      bool placed = false;
+      for (int probe = 0; probe < 16 && !placed; probe++) {
+        uint32_t old = atomicCAS(&hk[sl], NONE32, c);
+        if (old == NONE32 || old == c) {
+          if (key < hv[sl]) atomicMin(&hv[sl], key);
+          placed = true;
+        } else {
+          sl = (sl + 1) & (MHS - 1);
+        }
+      }
+      if (!placed && key < best[c]) atomicMin((unsigned long long *)&best[c], key);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < MHS; i += B) {
+    const uint32_t c = hk[i];
+    if (c == NONE32) continue;
+    const unsigned long long v = hv[i];
+    if (v < best[c]) atomicMin((unsigned long long *)&best[c], v);
   }
 }
 
-__global__ __launch_bounds__(B) void k_bv_pick(const uint32_t *live, int64_t nlive, const uint64_t *skel_key,
-                                               const uint32_t *skel_tail, const uint32_t *comp,
-                                               const uint64_t *best, uint32_t *bestslot) {
-  for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < nlive; i += (int64_t)gridDim.x * B) {
-    uint32_t e = live[i];
-    uint32_t cu = comp[skel_tail[e]], cv = comp[e >> 1];
-    if (cu == cv) continue;
-    uint64_t k = skel_key[e];
-    if (best[cu] == k) bestslot[cu] = e;
-    if (best[cv] == k) bestslot[cv] = e;
-  }
+// slot of the (unique) edge with key k: its head is rank rankof[head id]; of
+// the two slots of that head, the one holding k
+__device__ inline uint32_t slot_of_key(uint64_t k, int idbits, const uint32_t *rankof, const uint64_t *skel_key) {
+  uint32_t hid = (uint32_t)((k >> 1) & ((uint64_t(1) << idbits) - 1));
+  uint32_t h = rankof[hid];
+  return skel_key[2 * (uint64_t)h] == k ? 2 * h : 2 * h + 1;
 }
 
 // hook each component root onto the component across its minimum edge; of a
-// mutual pair the smaller root stays; the hooking edge joins the forest
-__global__ __launch_bounds__(B) void k_bv_hook(int64_t n, const uint32_t *comp, const uint64_t *best,
-                                               const uint32_t *bestslot, const uint32_t *skel_tail, uint32_t *hook,
-                                               uint8_t *msf_flag) {
-  for (int64_t c = (int64_t)blockIdx.x * B + threadIdx.x; c < n; c += (int64_t)gridDim.x * B) {
-    if (comp[c] != (uint32_t)c) continue;
-    uint32_t to = (uint32_t)c;
+// mutual pair the smaller root stays; the hooking edge joins the forest.
+// Roots that hook go to the active list for pointer jumping, the others to
+// the list of roots of the next round (roots == nullptr: all records).
+__global__ __launch_bounds__(B) void k_bv_hook(const uint32_t *roots, int64_t nroots, const uint32_t *comp,
+                                               const uint64_t *best, const uint64_t *skel_key,
+                                               const uint32_t *skel_tail, const uint32_t *rankof, int idbits,
+                                               uint32_t *hook, uint8_t *msf_flag, uint32_t *active,
+                                               unsigned long long *nactive, uint32_t *keep_roots,
+                                               unsigned long long *nkeep) {
+  bool hk[CT], st[CT];
+  uint32_t vals[CT];
+  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < CT; k++) {
+    const int64_t i = base + (int64_t)k * B;
+    hk[k] = false;
+    st[k] = false;
+    vals[k] = 0;
+    if (i >= nroots) continue;
+    const uint32_t c = roots ? roots[i] : (uint32_t)i;
+    vals[k] = c;
+    uint32_t to = c;
     uint64_t bk = best[c];
     if (bk != NONE64) {
-      uint32_t e = bestslot[c];
+      uint32_t e = slot_of_key(bk, idbits, rankof, skel_key);
       uint32_t cu = comp[skel_tail[e]], cv = comp[e >> 1];
-      uint32_t o = (cu == (uint32_t)c) ? cv : cu;
+      uint32_t o = (cu == c) ? cv : cu;
       bool mutual = best[o] == bk;
-      if (!(mutual && (uint32_t)c < o)) {
+      if (!(mutual && c < o)) {
         to = o;
         msf_flag[e] = 1;
+        hk[k] = true;
       }
     }
+    st[k] = !hk[k] && bk != NONE64;  // isolated components are final
     hook[c] = to;
   }
+  tile_append(hk, vals, active, nactive);
+  tile_append(st, vals, keep_roots, nkeep);
 }
 
-__global__ __launch_bounds__(B) void k_bv_jump(int64_t n, const uint32_t *comp, uint32_t *hook, uint32_t *changed) {
-  bool ch = false;
-  for (int64_t c = (int64_t)blockIdx.x * B + threadIdx.x; c < n; c += (int64_t)gridDim.x * B) {
-    if (comp[c] != (uint32_t)c) continue;
+__global__ __launch_bounds__(B) void k_fill_best(const uint32_t *roots, int64_t nroots, uint64_t *best) {
+  for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < nroots; i += (int64_t)gridDim.x * B)
+    best[roots[i]] = NONE64;
+}
+
+// pointer jumping over the hooked roots; converged ones leave the list
+__global__ __launch_bounds__(B) void k_bv_jump(const uint32_t *act, int64_t nact, uint32_t *hook, uint32_t *out,
+                                               unsigned long long *nout) {
+  bool keep[CT];
+  uint32_t vals[CT];
+  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < CT; k++) {
+    const int64_t i = base + (int64_t)k * B;
+    keep[k] = false;
+    vals[k] = 0;
+    if (i >= nact) continue;
+    uint32_t c = act[i];
     uint32_t h = hook[c];
     uint32_t hh = hook[h];
     if (hh != h) {
       hook[c] = hh;
-      ch = true;
+      keep[k] = true;
+      vals[k] = c;
     }
   }
-  if (__ballot(ch) != 0 && (threadIdx.x & 63) == 0) atomicOr(changed, 1u);
+  tile_append(keep, vals, out, nout);
 }
 
 __global__ __launch_bounds__(B) void k_bv_relabel(int64_t n, uint32_t *comp, const uint32_t *hook) {
   for (int64_t p = (int64_t)blockIdx.x * B + threadIdx.x; p < n; p += (int64_t)gridDim.x * B) comp[p] = hook[comp[p]];
 }
 
-__global__ __launch_bounds__(B) void k_bv_filter(const uint32_t *live, int64_t nlive, const uint32_t *skel_tail,
-                                                 const uint32_t *comp, uint32_t *out, unsigned long long *cnt) {
-  int64_t i = (int64_t)blockIdx.x * B + threadIdx.x;
-  bool keep = false;
-  uint32_t e = 0;
-  if (i < nlive) {
-    e = live[i];
-    keep = comp[skel_tail[e]] != comp[e >> 1];
+// keep edges whose endpoints lie in different components (live == nullptr: all slots)
+__global__ __launch_bounds__(B) void k_bv_filter(const uint32_t *live, int64_t nlive, const uint64_t *skel_key,
+                                                 const uint32_t *skel_tail, const uint32_t *comp, uint32_t *out,
+                                                 unsigned long long *cnt) {
+  bool keep[CT];
+  uint32_t vals[CT];
+  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < CT; k++) {
+    const int64_t i = base + (int64_t)k * B;
+    keep[k] = false;
+    vals[k] = 0;
+    if (i >= nlive) continue;
+    uint32_t e = live ? live[i] : (uint32_t)i;
+    if (!live && skel_key[e] == NONE64) continue;
+    vals[k] = e;
+    keep[k] = comp[skel_tail[e]] != comp[e >> 1];
   }
-  wave_append(keep, e, out, cnt);
+  tile_append(keep, vals, out, cnt);
 }
 
-__global__ __launch_bounds__(B) void k_msf_collect(const uint8_t *flag, int64_t n2, const uint64_t *skel_key,
-                                                   const uint32_t *skel_tail, uint64_t *okey, uint64_t *oval,
-                                                   unsigned long long *cnt) {
-  const int lane = threadIdx.x & 63;
-  int64_t e = (int64_t)blockIdx.x * B + threadIdx.x;
-  bool keep = e < n2 && flag[e];
-  uint64_t mask = __ballot(keep);
-  if (mask == 0) return;
-  int leader = __ffsll((unsigned long long)mask) - 1;
-  uint32_t base = 0;
-  if (lane == leader) base = (uint32_t)atomicAdd(cnt, (unsigned long long)__popcll(mask));
-  base = __shfl(base, leader, 64);
-  if (keep) {
-    uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
-    uint32_t p = base + __popcll(mask & below);
-    okey[p] = skel_key[e];
-    oval[p] = ((uint64_t)(e >> 1) << 32) | skel_tail[e];
+__global__ __launch_bounds__(B) void k_msf_list(const uint8_t *flag, int64_t n2, uint32_t *out,
+                                                unsigned long long *cnt) {
+  bool keep[CT];
+  uint32_t vals[CT];
+  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < CT; k++) {
+    const int64_t e = base + (int64_t)k * B;
+    keep[k] = e < n2 && flag[e];
+    vals[k] = (uint32_t)e;
+  }
+  tile_append(keep, vals, out, cnt);
+}
+
+__global__ __launch_bounds__(B) void k_msf_gather(const uint32_t *list, int64_t m, const uint64_t *skel_key,
+                                                  const uint32_t *skel_tail, uint64_t *okey, uint64_t *oval) {
+  for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < m; i += (int64_t)gridDim.x * B) {
+    uint32_t e = list[i];
+    okey[i] = skel_key[e];
+    oval[i] = ((uint64_t)(e >> 1) << 32) | skel_tail[e];
   }
 }
 
@@ -278,10 +336,10 @@ ce_status read_u64(const uint64_t *dev, uint64_t *host_out, int count, hipStream
 
 ce_status stage_validate(const int32_t *src, const int32_t *dst, const int64_t *t, Bufs &b, hipStream_t s,
                          uint64_t *flags, int64_t *tmin, int64_t *tmax) {
-  hipLaunchKernelGGL(k_init_hdr, dim3(1), dim3(64), 0, s, b.hdr);
+  CE_LAUNCH(k_init_hdr, dim3(1), dim3(64), 0, s, b.hdr);
   CE_HIP(hipGetLastError());
   if (b.n > 0) {
-    hipLaunchKernelGGL(k_validate, dim3(grid_for(b.n, B, 4096)), dim3(B), 0, s, src, dst, t, b.n, b.V, b.hdr);
+    CE_LAUNCH(k_validate, dim3(grid_for(b.n, B, 4096)), dim3(B), 0, s, src, dst, t, b.n, b.V, b.hdr);
     CE_HIP(hipGetLastError());
   }
   uint64_t h[3];
@@ -317,7 +375,7 @@ ce_status stage_sort_skeleton(const int32_t *src, const int32_t *dst, const int6
     uint64_t *tkey_alt = ws.alloc<uint64_t>(n);
     uint32_t *perm_alt = ws.alloc<uint32_t>(n);
     CE_WS_CHECK(ws);
-    hipLaunchKernelGGL(k_tkeys, dim3(grid_for(n, B)), dim3(B), 0, s, t, n, b.tmin, b.ts);
+    CE_LAUNCH(k_tkeys, dim3(grid_for(n, B)), dim3(B), 0, s, t, n, b.tmin, b.ts);
     CE_HIP(hipGetLastError());
     bool alt = false;
     CE_TRY((radix_sort_pairs<uint64_t, uint32_t>(b.ts, b.perm, tkey_alt, perm_alt, n, 0, b.tbits, true, &alt, ws, s)));
@@ -333,17 +391,18 @@ ce_status stage_sort_skeleton(const int32_t *src, const int32_t *dst, const int6
   uint32_t *ikey_alt = ws.alloc<uint32_t>(n2);
   uint32_t *ival_alt = ws.alloc<uint32_t>(n2);
   CE_WS_CHECK(ws);
-  hipLaunchKernelGGL(k_incidence, dim3(grid_for(n, B)), dim3(B), 0, s, b.perm, src, dst, n, ikey, ival);
+  CE_LAUNCH(k_incidence, dim3(grid_for(n, B)), dim3(B), 0, s, b.perm, src, dst, n, ikey, ival);
   CE_HIP(hipGetLastError());
   bool alt = false;
   CE_TRY((radix_sort_pairs<uint32_t, uint32_t>(ikey, ival, ikey_alt, ival_alt, n2, 0, b.vbits, true, &alt, ws, s)));
   const uint32_t *sk = alt ? ikey_alt : ikey;
   const uint32_t *sv = alt ? ival_alt : ival;
   // 3. skeleton: predecessor in the same vertex list, then packed keys
-  hipLaunchKernelGGL(k_skel_tails, dim3(grid_for(n2, B)), dim3(B), 0, s, sk, sv, n2, b.skel_tail);
+  CE_LAUNCH(k_skel_tails, dim3(grid_for(n2, B)), dim3(B), 0, s, sk, sv, n2, b.skel_tail);
+  CE_LAUNCH(k_fill_u64, dim3(grid_for(n, B)), dim3(B), 0, s, b.best, n, NONE64);
   CE_HIP(hipGetLastError());
-  hipLaunchKernelGGL(k_skel_keys, dim3(grid_for(n, B)), dim3(B), 0, s, b.skel_tail, b.ts, b.perm, n, b.idbits,
-                     b.skel_key);
+  CE_LAUNCH(k_skel_keys, dim3(grid_for(n, B)), dim3(B), 0, s, b.skel_tail, b.ts, b.perm, n, b.idbits,
+                     b.skel_key, b.best);
   CE_HIP(hipGetLastError());
   ws.release(m0);
   return CE_OK;
@@ -352,68 +411,86 @@ ce_status stage_sort_skeleton(const int32_t *src, const int32_t *dst, const int6
 size_t stage_boruvka_scratch(int64_t n) {
   Ws w;
   w.alloc<uint32_t>(n);      // comp
-  w.alloc<uint64_t>(n);      // best
-  w.alloc<uint32_t>(n);      // bestslot
+  w.alloc<uint32_t>(n);      // rankof
   w.alloc<uint32_t>(n);      // hook
+  w.alloc<uint32_t>(n);      // active
+  w.alloc<uint32_t>(n);      // active alt
+  w.alloc<uint32_t>(n);      // roots
+  w.alloc<uint32_t>(n);      // roots alt
   w.alloc<uint32_t>(2 * n);  // live
   w.alloc<uint32_t>(2 * n);  // live alt
   return w.off + 4096;
 }
 
+static unsigned tiles_for(int64_t n) { return (unsigned)((n + (int64_t)B * CT - 1) / ((int64_t)B * CT)); }
+
 ce_status stage_boruvka(Bufs &b, Ws &ws, hipStream_t s) {
   const int64_t n = b.n, n2 = 2 * n;
   size_t m0 = ws.mark();
   uint32_t *comp = ws.alloc<uint32_t>(n);
-  uint64_t *best = ws.alloc<uint64_t>(n);
-  uint32_t *bestslot = ws.alloc<uint32_t>(n);
+  uint32_t *rankof = ws.alloc<uint32_t>(n);
   uint32_t *hook = ws.alloc<uint32_t>(n);
+  uint32_t *act = ws.alloc<uint32_t>(n);
+  uint32_t *act2 = ws.alloc<uint32_t>(n);
+  uint32_t *roots = ws.alloc<uint32_t>(n);
+  uint32_t *roots2 = ws.alloc<uint32_t>(n);
   uint32_t *live = ws.alloc<uint32_t>(n2);
   uint32_t *live2 = ws.alloc<uint32_t>(n2);
   CE_WS_CHECK(ws);
+  uint64_t *best = b.best;  // seeded for the first round by k_skel_keys
   unsigned long long *cnt = (unsigned long long *)&b.hdr[4];
-  uint32_t *changed = (uint32_t *)&b.hdr[5];
-  hipLaunchKernelGGL(k_fill_u8, dim3(grid_for(n2, B)), dim3(B), 0, s, b.msf_flag, n2, (uint8_t)0);
-  hipLaunchKernelGGL(k_iota_u32, dim3(grid_for(n, B)), dim3(B), 0, s, comp, n);
-  hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[4], (uint64_t)0);
-  hipLaunchKernelGGL(k_live_init, dim3((unsigned)((n2 + B - 1) / B)), dim3(B), 0, s, b.skel_key, n2, live, cnt);
+  unsigned long long *cnt2 = (unsigned long long *)&b.hdr[5];
+  unsigned long long *cnt3 = (unsigned long long *)&b.hdr[7];
+  CE_LAUNCH(k_fill_u8, dim3(grid_for(n2, B)), dim3(B), 0, s, b.msf_flag, n2, (uint8_t)0);
+  CE_LAUNCH(k_iota_u32, dim3(grid_for(n, B)), dim3(B), 0, s, comp, n);
+  CE_LAUNCH(k_rankof, dim3(grid_for(n, B)), dim3(B), 0, s, b.perm, n, rankof);
   CE_HIP(hipGetLastError());
-  uint64_t nlive = 0;
-  CE_TRY(read_u64(&b.hdr[4], &nlive, 1, s));
+  const uint32_t *cur = nullptr;  // first round: all slots
+  const uint32_t *rcur = nullptr; // first round: all records are roots
+  int64_t nlive = n2, nroots = n;
   int rounds = 0;
   while (nlive > 0) {
     if (++rounds > 64) {
       set_error("Boruvka did not converge");
       return CE_EDEVICE;
     }
-    hipLaunchKernelGGL(k_fill_u64, dim3(grid_for(n, B)), dim3(B), 0, s, best, n, NONE64);
-    hipLaunchKernelGGL(k_bv_min, dim3(grid_for((int64_t)nlive, B)), dim3(B), 0, s, live, (int64_t)nlive, b.skel_key,
-                       b.skel_tail, comp, best);
-    hipLaunchKernelGGL(k_bv_pick, dim3(grid_for((int64_t)nlive, B)), dim3(B), 0, s, live, (int64_t)nlive,
-                       b.skel_key, b.skel_tail, comp, best, bestslot);
-    hipLaunchKernelGGL(k_bv_hook, dim3(grid_for(n, B)), dim3(B), 0, s, n, comp, best, bestslot, b.skel_tail, hook,
-                       b.msf_flag);
+    if (rounds > 1) {
+      CE_LAUNCH(k_fill_best, dim3(grid_for(nroots, B)), dim3(B), 0, s, rcur, nroots, best);
+      CE_LAUNCH(k_bv_min, dim3(tiles_for(nlive)), dim3(B), 0, s, cur, nlive, b.skel_key, b.skel_tail, comp, best);
+    }
+    CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[4], (uint64_t)0);
+    CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[7], (uint64_t)0);
+    CE_LAUNCH(k_bv_hook, dim3(tiles_for(nroots)), dim3(B), 0, s, rcur, nroots, comp, best, b.skel_key,
+                       b.skel_tail, rankof, b.idbits, hook, b.msf_flag, act, cnt, roots, cnt3);
     CE_HIP(hipGetLastError());
-    for (int it = 0;; it++) {
+    uint64_t hv[4];
+    CE_TRY(read_u64(&b.hdr[4], hv, 4, s));
+    uint64_t nact = hv[0];
+    nroots = (int64_t)hv[3];
+    rcur = roots;
+    uint32_t *tr = roots; roots = roots2; roots2 = tr;
+    for (int it = 0; nact > 0; it++) {
       if (it > 64) {
         set_error("Boruvka pointer jumping did not converge");
         return CE_EDEVICE;
       }
-      hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[5], (uint64_t)0);
-      hipLaunchKernelGGL(k_bv_jump, dim3(grid_for(n, B)), dim3(B), 0, s, n, comp, hook, changed);
+      CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[5], (uint64_t)0);
+      CE_LAUNCH(k_bv_jump, dim3(tiles_for((int64_t)nact)), dim3(B), 0, s, act, (int64_t)nact, hook, act2,
+                         cnt2);
       CE_HIP(hipGetLastError());
-      uint64_t ch = 0;
-      CE_TRY(read_u64(&b.hdr[5], &ch, 1, s));
-      if ((ch & 0xffffffffull) == 0) break;
+      CE_TRY(read_u64(&b.hdr[5], &nact, 1, s));
+      uint32_t *t = act; act = act2; act2 = t;
     }
-    hipLaunchKernelGGL(k_bv_relabel, dim3(grid_for(n, B)), dim3(B), 0, s, n, comp, hook);
-    hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[4], (uint64_t)0);
-    hipLaunchKernelGGL(k_bv_filter, dim3((unsigned)((nlive + B - 1) / B)), dim3(B), 0, s, live, (int64_t)nlive,
-                       b.skel_tail, comp, live2, cnt);
+    CE_LAUNCH(k_bv_relabel, dim3(grid_for(n, B)), dim3(B), 0, s, n, comp, hook);
+    CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[4], (uint64_t)0);
+    CE_LAUNCH(k_bv_filter, dim3(tiles_for(nlive)), dim3(B), 0, s, cur, nlive, b.skel_key, b.skel_tail, comp,
+                       live, cnt);
     CE_HIP(hipGetLastError());
-    CE_TRY(read_u64(&b.hdr[4], &nlive, 1, s));
-    uint32_t *tmp = live;
-    live = live2;
-    live2 = tmp;
+    uint64_t nl = 0;
+    CE_TRY(read_u64(&b.hdr[4], &nl, 1, s));
+    nlive = (int64_t)nl;
+    cur = live;
+    uint32_t *t = live; live = live2; live2 = t;
   }
   ws.release(m0);
   return CE_OK;
@@ -423,6 +500,7 @@ size_t stage_msf_sort_scratch(int64_t n) {
   Ws w;
   w.alloc<uint64_t>(n);
   w.alloc<uint64_t>(n);
+  w.alloc<uint32_t>(n);
   return w.off + radix_ws_bytes(n) + 4096;
 }
 
@@ -431,10 +509,11 @@ ce_status stage_msf_sort(Bufs &b, Ws &ws, hipStream_t s, int64_t *m_out) {
   size_t m0 = ws.mark();
   uint64_t *key_alt = ws.alloc<uint64_t>(n);
   uint64_t *val_alt = ws.alloc<uint64_t>(n);
+  uint32_t *list = ws.alloc<uint32_t>(n);
   CE_WS_CHECK(ws);
-  hipLaunchKernelGGL(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[6], (uint64_t)0);
-  hipLaunchKernelGGL(k_msf_collect, dim3((unsigned)((n2 + B - 1) / B)), dim3(B), 0, s, b.msf_flag, n2, b.skel_key,
-                     b.skel_tail, b.msf_key, b.msf_val, (unsigned long long *)&b.hdr[6]);
+  CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[6], (uint64_t)0);
+  CE_LAUNCH(k_msf_list, dim3(tiles_for(n2)), dim3(B), 0, s, b.msf_flag, n2, list,
+                     (unsigned long long *)&b.hdr[6]);
   CE_HIP(hipGetLastError());
   uint64_t m = 0;
   CE_TRY(read_u64(&b.hdr[6], &m, 1, s));
@@ -442,6 +521,9 @@ ce_status stage_msf_sort(Bufs &b, Ws &ws, hipStream_t s, int64_t *m_out) {
     set_error("spanning forest larger than n-1");
     return CE_EDEVICE;
   }
+  if (m > 0)
+    CE_LAUNCH(k_msf_gather, dim3(grid_for((int64_t)m, B)), dim3(B), 0, s, list, (int64_t)m, b.skel_key,
+                       b.skel_tail, b.msf_key, b.msf_val);
   bool alt = false;
   CE_TRY((radix_sort_pairs<uint64_t, uint64_t>(b.msf_key, b.msf_val, key_alt, val_alt, (int64_t)m, 0, b.keybits,
                                                 false, &alt, ws, s)));

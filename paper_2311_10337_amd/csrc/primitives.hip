@@ -109,7 +109,7 @@ size_t scan_ws_bytes(int64_t n) {
 
 ce_status scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, Ws &ws, hipStream_t s) {
   if (n <= STILE) {
-    hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(SB), 0, s, in, out, n);
+    CE_LAUNCH(k_scan_small, dim3(1), dim3(SB), 0, s, in, out, n);
     CE_HIP(hipGetLastError());
     return CE_OK;
   }
@@ -118,10 +118,10 @@ ce_status scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, Ws &w
   uint32_t *sums = ws.alloc<uint32_t>(nb + 1);
   uint32_t *sums_sc = ws.alloc<uint32_t>(nb + 1);
   CE_WS_CHECK(ws);
-  hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nb), dim3(SB), 0, s, in, n, sums);
+  CE_LAUNCH(k_scan_reduce, dim3((unsigned)nb), dim3(SB), 0, s, in, n, sums);
   CE_HIP(hipGetLastError());
   CE_TRY(scan_exclusive_u32(sums, sums_sc, nb, ws, s));
-  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(SB), 0, s, in, out, n, sums_sc);
+  CE_LAUNCH(k_scan_apply, dim3((unsigned)nb), dim3(SB), 0, s, in, out, n, sums_sc);
   CE_HIP(hipGetLastError());
   ws.release(m);
   return CE_OK;
@@ -262,10 +262,10 @@ ce_status radix_sort_pairs(K *k0, V *v0, K *k1, V *v1, int64_t n, int begin_bit,
   bool first = true;
   if (end_bit <= begin_bit) end_bit = begin_bit + 1;  // one stable pass still materialises identity values
   for (int shift = begin_bit; shift < end_bit; shift += 8) {
-    hipLaunchKernelGGL((k_rs_hist<K>), dim3((unsigned)nb), dim3(RB), 0, s, ki, n, shift, hist, nb);
+    CE_LAUNCH((k_rs_hist<K>), dim3((unsigned)nb), dim3(RB), 0, s, ki, n, shift, hist, nb);
     CE_HIP(hipGetLastError());
     CE_TRY(scan_exclusive_u32(hist, hsc, (int64_t)nb * 256, ws, s));
-    hipLaunchKernelGGL((k_rs_scatter<K, V>), dim3((unsigned)nb), dim3(RB), 0, s, ki, (const V *)vi, ko, vo, n,
+    CE_LAUNCH((k_rs_scatter<K, V>), dim3((unsigned)nb), dim3(RB), 0, s, ki, (const V *)vi, ko, vo, n,
                        shift, hsc, nb, (first && iota_values) ? 1 : 0);
     CE_HIP(hipGetLastError());
     first = false;
