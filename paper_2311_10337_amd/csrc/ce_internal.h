@@ -147,6 +147,42 @@ __host__ __device__ inline uint64_t lambda_of(int64_t w) {
 __device__ inline uint32_t wave_lane() { return threadIdx.x & 63u; }
 __device__ inline uint64_t lanes_below(uint32_t lane) { return lane == 0 ? 0ull : (~0ull >> (64 - lane)); }
 
+// One-shot wave combining for contended updates: the lanes holding the same
+// key as the first active lane (the hot key, when one key dominates) are
+// reduced into that lane by reduce(mine, leader), which every lane calls so
+// it may shuffle. Returns whether this lane must still apply an update: the
+// leader with the combined value, and every active lane with another key.
+// (A loop over all distinct keys costs up to 64 rounds when keys differ;
+// this costs one.)
+template <class Fn>
+__device__ inline bool wave_combine_first(bool active, uint32_t key, Fn reduce) {
+  const uint64_t act = __ballot(active);
+  if (act == 0) return false;
+  const int leader = __ffsll((unsigned long long)act) - 1;
+  const uint32_t k = __shfl(key, leader, 64);
+  const bool mine = active && key == k;
+  const uint64_t match = __ballot(mine);
+  if (__popcll(match) < 2) return active;
+  reduce(mine, leader);
+  return active && (!mine || (int)wave_lane() == leader);
+}
+__device__ inline uint64_t wave_sum_u64(uint64_t v) {
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+__device__ inline uint32_t wave_sum_u32(uint32_t v) {
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+  return v;
+}
+__device__ inline uint32_t wave_max_u32(uint32_t v) {
+  for (int d = 32; d >= 1; d >>= 1) { uint32_t o = __shfl_xor(v, d, 64); v = o > v ? o : v; }
+  return v;
+}
+__device__ inline uint64_t wave_min_u64(uint64_t v) {
+  for (int d = 32; d >= 1; d >>= 1) { uint64_t o = __shfl_xor(v, d, 64); v = o < v ? o : v; }
+  return v;
+}
+
 // Tile compaction: a 256-thread block keeps the elements of its tile
 // [tile_base, tile_base + 256*CT) for which keep[k] is set and appends
 // vals[k] to out[] with ONE atomic on the global counter per tile. Thread t

@@ -204,8 +204,9 @@ __device__ inline void wave_add_limbs(bool active, uint32_t row, uint64_t l0, ui
   }
 }
 
-// Per-tile aggregation in an LDS hash of rows (one global atomic per row per
-// 4096 records); a record whose row finds no free slot adds directly.
+// Per-tile aggregation: lanes with equal rows combine first, then one LDS
+// hash slot per row and tile (one global atomic per row per 4096 records); a
+// row that finds no free slot adds directly.
 constexpr int AHS = 512;
 __global__ __launch_bounds__(B) void k_cd_acc_points(const uint32_t *exc, const uint64_t *exl, const uint32_t *rowof,
                                                      int64_t m, int64_t n, uint32_t nbirth,
@@ -217,25 +218,34 @@ __global__ __launch_bounds__(B) void k_cd_acc_points(const uint32_t *exc, const 
   const int64_t tbase = (int64_t)blockIdx.x * (B * CT);
   for (int k = 0; k < CT; k++) {
     const int64_t p = tbase + (int64_t)k * B + threadIdx.x;
-    if (p >= n) continue;
-    const uint64_t L = exl[p];
-    if (L == 0) continue;  // records leaving at lambda 0 add nothing
-    const uint32_t r = row_of(exc[p], n, m, rowof, nbirth);
-    uint32_t sl = (r * 2654435761u) >> 23;  // 9 bits
-    bool placed = false;
-    for (int probe = 0; probe < 16 && !placed; probe++) {
-      uint32_t old = atomicCAS(&hk[sl], NONE32, r);
-      if (old == NONE32 || old == r) {
-        atomicAdd(&h0[sl], (unsigned long long)(L & 0xffffffffull));
-        atomicAdd(&h1[sl], (unsigned long long)(L >> 32));
-        placed = true;
-      } else {
-        sl = (sl + 1) & (AHS - 1);
-      }
+    uint64_t L = 0;
+    uint32_t r = 0;
+    if (p < n) {
+      L = exl[p];
+      if (L) r = row_of(exc[p], n, m, rowof, nbirth);
     }
-    if (!placed) {
-      atomicAdd(&acc[3 * (uint64_t)r], (unsigned long long)(L & 0xffffffffull));
-      atomicAdd(&acc[3 * (uint64_t)r + 1], (unsigned long long)(L >> 32));
+    uint64_t s0 = L & 0xffffffffull, s1 = L >> 32;
+    const bool upd = wave_combine_first(L != 0, r, [&](bool mine, int leader) {
+      const uint64_t a0 = wave_sum_u64(mine ? s0 : 0ull), a1 = wave_sum_u64(mine ? s1 : 0ull);
+      if ((int)wave_lane() == leader) { s0 = a0; s1 = a1; }
+    });
+    if (upd) {
+      uint32_t sl = (r * 2654435761u) >> 23;  // 9 bits
+      bool placed = false;
+      for (int probe = 0; probe < 16 && !placed; probe++) {
+        uint32_t old = atomicCAS(&hk[sl], NONE32, r);
+        if (old == NONE32 || old == r) {
+          atomicAdd(&h0[sl], (unsigned long long)s0);
+          atomicAdd(&h1[sl], (unsigned long long)s1);
+          placed = true;
+        } else {
+          sl = (sl + 1) & (AHS - 1);
+        }
+      }
+      if (!placed) {
+        atomicAdd(&acc[3 * (uint64_t)r], (unsigned long long)s0);
+        atomicAdd(&acc[3 * (uint64_t)r + 1], (unsigned long long)s1);
+      }
     }
   }
   __syncthreads();

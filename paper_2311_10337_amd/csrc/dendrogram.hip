@@ -135,28 +135,35 @@ __global__ __launch_bounds__(B) void k_krt_accum(int64_t m, int lo, int hi, uint
   const int64_t tbase = (int64_t)blockIdx.x * (B * KCT);
   for (int k = 0; k < KCT; k++) {
     const int64_t tix = tbase + (int64_t)k * B + threadIdx.x;
-    if (tix >= nthreads) continue;
-    const int64_t j = step_row(tix, lo, hi, q);
-    if (j >= m) continue;
-    const uint32_t h = hooked[j];
-    if (h == NONE32) continue;
-    const uint32_t f = g_find(uf, h);
-    const uint32_t add = uf[h].z, mj = (uint32_t)(j + 1);
-    uint32_t sl = (f * 2654435761u) >> 24;  // 8 bits
-    bool placed = false;
-    for (int probe = 0; probe < 16 && !placed; probe++) {
-      uint32_t old = atomicCAS(&hk[sl], NONE32, f);
-      if (old == NONE32 || old == f) {
-        atomicAdd(&hs[sl], add);
-        atomicMax(&hm[sl], mj);
-        placed = true;
-      } else {
-        sl = (sl + 1) & (KHS - 1);
-      }
+    const int64_t j = tix < nthreads ? step_row(tix, lo, hi, q) : m;
+    uint32_t h = NONE32, f = 0, add = 0, mj = 0;
+    if (j < m) h = hooked[j];
+    if (h != NONE32) {
+      f = g_find(uf, h);
+      add = uf[h].z;
+      mj = (uint32_t)(j + 1);
     }
-    if (!placed) {
-      atomicAdd(&uf[f].z, add);
-      atomicMax(&uf[f].y, mj);
+    const bool upd = wave_combine_first(h != NONE32, f, [&](bool mine, int leader) {
+      const uint32_t sa = wave_sum_u32(mine ? add : 0u), sm = wave_max_u32(mine ? mj : 0u);
+      if ((int)wave_lane() == leader) { add = sa; mj = sm; }
+    });
+    if (upd) {
+      uint32_t sl = (f * 2654435761u) >> 24;  // 8 bits
+      bool placed = false;
+      for (int probe = 0; probe < 16 && !placed; probe++) {
+        uint32_t old = atomicCAS(&hk[sl], NONE32, f);
+        if (old == NONE32 || old == f) {
+          atomicAdd(&hs[sl], add);
+          atomicMax(&hm[sl], mj);
+          placed = true;
+        } else {
+          sl = (sl + 1) & (KHS - 1);
+        }
+      }
+      if (!placed) {
+        atomicAdd(&uf[f].z, add);
+        atomicMax(&uf[f].y, mj);
+      }
     }
   }
   __syncthreads();

@@ -154,26 +154,38 @@ __global__ __launch_bounds__(B) void k_bv_min(const uint32_t *live, int64_t nliv
   const int64_t tbase = (int64_t)blockIdx.x * (B * CT);
   for (int k = 0; k < CT; k++) {
     const int64_t i = tbase + (int64_t)k * B + threadIdx.x;
-    if (i >= nlive) continue;
-    const uint32_t e = live[i];
-    const unsigned long long key = skel_key[e];
-    const uint32_t cu = comp[skel_tail[e]], cv = comp[e >> 1];
-    if (cu == cv) continue;
+    unsigned long long key = NONE64;
+    uint32_t cu = 0, cv = 0;
+    bool act = false;
+    if (i < nlive) {
+      const uint32_t e = live[i];
+      key = skel_key[e];
+      cu = comp[skel_tail[e]];
+      cv = comp[e >> 1];
+      act = cu != cv;
+    }
 #pragma unroll
     for (int side = 0; side < 2; side++) {
       const uint32_t c = side ? cv : cu;
-      uint32_t sl = (c * 2654435761u) >> 23;  // 9 bits
-      bool placed = false;
-      for (int probe = 0; probe < 16 && !placed; probe++) {
-        uint32_t old = atomicCAS(&hk[sl], NONE32, c);
-        if (old == NONE32 || old == c) {
-          if (key < hv[sl]) atomicMin(&hv[sl], key);
-          placed = true;
-        } else {
-          sl = (sl + 1) & (MHS - 1);
+      unsigned long long kmin = key;
+      const bool upd = wave_combine_first(act, c, [&](bool mine, int leader) {
+        const unsigned long long v = wave_min_u64(mine ? key : NONE64);
+        if ((int)wave_lane() == leader) kmin = v;
+      });
+      if (upd) {
+        uint32_t sl = (c * 2654435761u) >> 23;  // 9 bits
+        bool placed = false;
+        for (int probe = 0; probe < 16 && !placed; probe++) {
+          uint32_t old = atomicCAS(&hk[sl], NONE32, c);
+          if (old == NONE32 || old == c) {
+            if (kmin < hv[sl]) atomicMin(&hv[sl], kmin);
+            placed = true;
+          } else {
+            sl = (sl + 1) & (MHS - 1);
+          }
         }
+        if (!placed && kmin < best[c]) atomicMin((unsigned long long *)&best[c], kmin);
       }
-      if (!placed && key < best[c]) atomicMin((unsigned long long *)&best[c], key);
     }
   }
   __syncthreads();
