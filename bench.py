@@ -63,7 +63,11 @@ def main():
     ap.add_argument("--workload", default="mid", choices=["tiny", "mid", "scale"])
     ap.add_argument("--cpu-sample", type=int, default=10_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--time-kernel", default=None, help="kernel whose launches are timed with HIP events")
+    ap.add_argument("--roofline-kernel", default="k_krt_accum",
+                    help="dominant kernel: its launches are timed with HIP events on its stream for the roofline")
+    ap.add_argument("--copy-calibration", type=int, default=0,
+                    help="before the steps, copy a buffer of this many bytes once (a plain copy kernel of known "
+                         "size for calibrating HBM counters)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -87,6 +91,14 @@ def main():
     dst = torch.from_numpy(w.dst).to(dev)
     tt = torch.from_numpy(w.t).to(dev)
     M, V = w.min_cluster_size, w.num_vertices
+    if args.copy_calibration:
+        a = torch.ones(args.copy_calibration, dtype=torch.uint8, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+        log("copy calibration: %d bytes copied" % args.copy_calibration)
     outs = ce.Outputs(w.n, M, dev)
     ws = torch.empty(ce.workspace_bytes(w.n, V, M), dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
@@ -98,23 +110,38 @@ def main():
         r = step()
         log("warmup %d done: m=%d clusters=%d labels=%d" % (i, r.m, r.n_clusters, r.n_labels))
     torch.cuda.synchronize()
-    if args.time_kernel:
-        ce.timing_enable(args.time_kernel)
+    if args.roofline_kernel:
+        ce.timing_enable(args.roofline_kernel)
     t0 = time.perf_counter()
     for i in range(args.steps):
         r = step()
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
     log("timed %d steps in %.3f s" % (args.steps, el))
-    if args.time_kernel:
+    roof = None
+    if args.roofline_kernel:
+        from paper_2311_10337_amd import profiling
         kms, kcnt = ce.timing_read()
         ce.timing_enable(None)
-        log("kernel %s: %d launches, %.3f ms total, %.1f us avg" % (args.time_kernel, kcnt, kms, 1e3 * kms / max(kcnt, 1)))
+        log("kernel %s: %d launches, %.3f ms total, %.1f us avg" % (args.roofline_kernel, kcnt, kms,
+                                                                  1e3 * kms / max(kcnt, 1)))
+        unit, per_unit, units = profiling.algorithmic_bytes_per_step(args.roofline_kernel, w.n, r.m)
+        if kcnt and units:
+            per_launch = per_unit * units * args.steps / kcnt
+            achieved = per_launch / (kms / kcnt * 1e-3) / 1e9
+            traffic = profiling.load_traffic(args.roofline_kernel, os.path.join(
+                ROOT, "profiles", "%s_%s_pmc.md" % (args.roofline_kernel, cfg["workload"])))
+            roof = {"bound": "hbm", "achieved": achieved, "peak": profiling.HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / profiling.HBM_PEAK_GBS, "traffic": traffic, "kernel": args.roofline_kernel,
+                    "algorithmic_bytes_per_launch": per_launch, "launches": kcnt,
+                    "avg_launch_us": 1e3 * kms / kcnt, "unit_of_work": unit, "bytes_per_unit": per_unit}
     value = w.n * args.steps / el
     line = {"metric": METRIC, "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": 1000.0 * el / args.steps, "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
             "config": dict(cfg, m_msf=r.m, n_clusters=r.n_clusters, n_labels=r.n_labels)}
+    if roof is not None:
+        line["roofline"] = roof
     if not args.no_cpu_baseline:
         log("cpu baseline on a sample")
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)

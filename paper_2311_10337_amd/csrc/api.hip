@@ -46,17 +46,22 @@ namespace {
 
 constexpr int B = 256;
 
-__global__ __launch_bounds__(B) void k_rows(const uint64_t *msf_key, const uint64_t *msf_val, const uint32_t *kc_u,
-                                            const uint32_t *kc_v, const uint32_t *ksize, const uint32_t *perm,
-                                            int64_t m, int64_t n, int idbits, ce_result out) {
+// A record that is a child of row j joins at row j, so it is one of that row's
+// two endpoints: its input id comes from the row itself (no gathers).
+__global__ __launch_bounds__(B) void k_rows(const uint64_t *msf_key, const uint4 *msf_val, const uint32_t *kc_u,
+                                            const uint32_t *kc_v, const uint32_t *ksize, int64_t m, int64_t n,
+                                            int idbits, ce_result out) {
+  const uint64_t idmask = (uint64_t(1) << idbits) - 1;
   for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
-    uint64_t v = msf_val[j];
-    int64_t w = (int64_t)(msf_key[j] >> (idbits + 1));
-    if (out.msf_tail) out.msf_tail[j] = perm[v & 0xffffffffu];
-    if (out.msf_head) out.msf_head[j] = perm[v >> 32];
+    const uint4 v = msf_val[j];
+    const uint64_t key = msf_key[j];
+    const int64_t w = (int64_t)(key >> (idbits + 1));
+    const uint32_t tr = v.x, tid = v.z, hid = (uint32_t)((key >> 1) & idmask);
+    if (out.msf_tail) out.msf_tail[j] = tid;
+    if (out.msf_head) out.msf_head[j] = hid;
     if (out.msf_w) out.msf_w[j] = w;
     uint32_t a = kc_u[j], b = kc_v[j];
-    uint32_t fa = a < (uint64_t)n ? perm[a] : a, fb = b < (uint64_t)n ? perm[b] : b;
+    uint32_t fa = a < (uint64_t)n ? (a == tr ? tid : hid) : a, fb = b < (uint64_t)n ? (b == tr ? tid : hid) : b;
     if (out.sl_left) out.sl_left[j] = fa < fb ? fa : fb;
     if (out.sl_right) out.sl_right[j] = fa < fb ? fb : fa;
     if (out.sl_w) out.sl_w[j] = w;
@@ -86,8 +91,8 @@ __global__ void k_trivial(int64_t n, ce_result out) {
 
 ce_status stage_write_rows(Bufs &b, int64_t m, const ce_result *out, hipStream_t s) {
   if (m <= 0) return CE_OK;
-  CE_LAUNCH(k_rows, dim3(grid_for(m, B)), dim3(B), 0, s, b.msf_key, b.msf_val, b.kc_u, b.kc_v, b.ksize, b.perm,
-                     m, b.n, b.idbits, *out);
+  CE_LAUNCH(k_rows, dim3(grid_for(m, B)), dim3(B), 0, s, b.msf_key, b.msf_val, b.kc_u, b.kc_v, b.ksize, m, b.n,
+            b.idbits, *out);
   CE_HIP(hipGetLastError());
   return CE_OK;
 }
@@ -98,10 +103,11 @@ static void layout(Bufs &b, Ws &ws, int64_t n, int64_t M) {
   b.perm = ws.alloc<uint32_t>(n);
   b.skel_key = ws.alloc<uint64_t>(2 * n);
   b.skel_tail = ws.alloc<uint32_t>(2 * n);
+  b.skel_tid = ws.alloc<uint32_t>(2 * n);
   b.best = ws.alloc<uint64_t>(n);
   b.msf_flag = ws.alloc<uint8_t>(2 * n);
   b.msf_key = ws.alloc<uint64_t>(n);
-  b.msf_val = ws.alloc<uint64_t>(n);
+  b.msf_val = ws.alloc<uint4>(n);
   b.kc_u = ws.alloc<uint32_t>(n);
   b.kc_v = ws.alloc<uint32_t>(n);
   b.ksize = ws.alloc<uint32_t>(n);

@@ -191,8 +191,9 @@ __device__ inline uint64_t wave_min_u64(uint64_t v) {
 // exclusive scan over the (k, wave) counts, then popcount ranks within the
 // wave. Call from all threads of the block.
 constexpr int CT = 16;
-__device__ inline void tile_append(const bool (&keep)[CT], const uint32_t (&vals)[CT], uint32_t *out,
-                                   unsigned long long *counter) {
+// Output positions for the kept elements of a tile (order as described
+// above); pos[k] is valid where keep[k]. One atomic on `counter` per tile.
+__device__ inline void tile_positions(const bool (&keep)[CT], uint32_t (&pos)[CT], unsigned long long *counter) {
   __shared__ uint32_t s_cnt[CT * 4];
   __shared__ uint32_t s_base;
   const uint32_t lane = wave_lane(), w = threadIdx.x >> 6;
@@ -217,9 +218,17 @@ __device__ inline void tile_append(const bool (&keep)[CT], const uint32_t (&vals
   __syncthreads();
   const uint64_t below = lanes_below(lane);
 #pragma unroll
+  for (int k = 0; k < CT; k++) pos[k] = s_base + s_cnt[k * 4 + w] + (uint32_t)__popcll(mask[k] & below);
+  __syncthreads();  // s_cnt / s_base may be reused by a later call
+}
+
+__device__ inline void tile_append(const bool (&keep)[CT], const uint32_t (&vals)[CT], uint32_t *out,
+                                   unsigned long long *counter) {
+  uint32_t pos[CT];
+  tile_positions(keep, pos, counter);
+#pragma unroll
   for (int k = 0; k < CT; k++)
-    if (keep[k]) out[s_base + s_cnt[k * 4 + w] + (uint32_t)__popcll(mask[k] & below)] = vals[k];
-  __syncthreads();  // s_cnt / s_base may be reused by a second call
+    if (keep[k]) out[pos[k]] = vals[k];
 }
 
 // ------------------------------------------------------------ primitives
@@ -254,10 +263,11 @@ struct Bufs {
   uint32_t *perm = nullptr;     // [n] rank -> input id
   uint64_t *skel_key = nullptr; // [2n] slot 2h+s: key of the skeleton edge whose head is rank h
   uint32_t *skel_tail = nullptr;// [2n] tail rank of that edge or NONE
+  uint32_t *skel_tid = nullptr; // [2n] input id of that tail
   uint64_t *best = nullptr;     // [n] Boruvka: minimum key leaving each component
   uint8_t *msf_flag = nullptr;  // [2n]
   uint64_t *msf_key = nullptr;  // [n] sorted MSF keys
-  uint64_t *msf_val = nullptr;  // [n] (head rank << 32) | tail rank
+  uint4 *msf_val = nullptr;     // [n] (tail rank, head rank, tail input id, 0); the head's id is in the key
   uint32_t *kc_u = nullptr, *kc_v = nullptr, *ksize = nullptr; // [n] dendrogram children (internal labels) and size
   // scratch arena (aliased across stages)
   char *scratch = nullptr;

@@ -147,6 +147,39 @@ __global__ __launch_bounds__(B) void k_cd_exit(const uint32_t *kpar, const uint3
   }
 }
 
+// Top-down exits: a small child c of a big row j sheds every record under it
+// at (cluster of j, lambda(w_j)); a DFS over c's subtree (fewer than M
+// leaves, so fewer than 2M nodes and height < M) visits each node once.
+// Records outside such subtrees keep the default exit (ROOT, 0).
+constexpr int EXIT_STACK = 64;
+__global__ __launch_bounds__(B) void k_cd_exit_down(const uint32_t *kc_u, const uint32_t *kc_v, const uint32_t *ksize,
+                                                    const uint32_t *J, const uint64_t *msf_key, int idbits, int64_t m,
+                                                    int64_t n, int64_t M, uint32_t *exc, uint64_t *exl) {
+  for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
+    if (ksize[j] < (uint64_t)M) continue;
+    const uint32_t C = J[j];
+    const uint64_t L = lambda_of(row_w(j, msf_key, idbits));
+#pragma unroll
+    for (int side = 0; side < 2; side++) {
+      const uint32_t c = side ? kc_v[j] : kc_u[j];
+      if (node_size(c, n, ksize) >= (uint64_t)M) continue;
+      uint32_t stack[EXIT_STACK];
+      int sp = 0;
+      stack[sp++] = c;
+      while (sp > 0) {
+        const uint32_t x = stack[--sp];
+        if (x < (uint64_t)n) {
+          exc[x] = C;
+          exl[x] = L;
+        } else {
+          stack[sp++] = kc_u[x - n];
+          stack[sp++] = kc_v[x - n];
+        }
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(B) void k_u8_to_u32(const uint8_t *a, int64_t n, uint32_t *o) {
   for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < n; i += (int64_t)gridDim.x * B) o[i] = a[i];
 }
@@ -600,8 +633,16 @@ ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipSt
       CE_TRY(read_u64(&b.hdr[9], &nact, 1, s));
     }
   }
-  CE_LAUNCH(k_cd_exit, dim3(grid_for(n, B)), dim3(B), 0, s, kpar, b.ksize, J, b.msf_key, b.idbits, m, n, M,
-                     exc, exl);
+  if (M <= EXIT_STACK) {
+    CE_LAUNCH(k_fill32, dim3(grid_for(n, B)), dim3(B), 0, s, exc, n, (uint32_t)(n + m));
+    CE_LAUNCH(k_fill64, dim3(grid_for(n, B)), dim3(B), 0, s, exl, n, (uint64_t)0);
+    if (m > 0)
+      CE_LAUNCH(k_cd_exit_down, dim3(grid_for(m, B)), dim3(B), 0, s, b.kc_u, b.kc_v, b.ksize, J, b.msf_key, b.idbits,
+                m, n, M, exc, exl);
+  } else {
+    CE_LAUNCH(k_cd_exit, dim3(grid_for(n, B)), dim3(B), 0, s, kpar, b.ksize, J, b.msf_key, b.idbits, m, n, M, exc,
+              exl);
+  }
   CE_LAUNCH(k_u8_to_u32, dim3(gm), dim3(B), 0, s, isbirth, m, flags32);
   CE_HIP(hipGetLastError());
   CE_TRY(scan_exclusive_u32(flags32, rowof, m, ws, s));

@@ -68,20 +68,22 @@ __global__ void k_init_hdr(uint64_t *hdr) {
   if (threadIdx.x == 0) hdr[1] = NONE64;
 }
 
-__global__ __launch_bounds__(B) void k_tkeys(const int64_t *t, int64_t n, int64_t tmin, uint64_t *keys) {
-  for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < n; i += (int64_t)gridDim.x * B)
+// the time sort carries (id, src, dst) along, so grouping needs no gathers
+__global__ __launch_bounds__(B) void k_tkeys(const int64_t *t, const int32_t *src, const int32_t *dst, int64_t n,
+                                             int64_t tmin, uint64_t *keys, uint4 *vals) {
+  for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < n; i += (int64_t)gridDim.x * B) {
     keys[i] = (uint64_t)(t[i] - tmin);
+    vals[i] = make_uint4((uint32_t)i, (uint32_t)src[i], (uint32_t)dst[i], 0u);
+  }
 }
 
-// incidence entries in rank order: (src, 2r), (dst, 2r+1)
-__global__ __launch_bounds__(B) void k_incidence(const uint32_t *perm, const int32_t *src, const int32_t *dst,
-                                                 int64_t n, uint32_t *ikey, uint32_t *ival) {
+// incidence entries in rank order: key = vertex, value (implicit) = 2r+side
+__global__ __launch_bounds__(B) void k_incidence(const uint4 *vals, int64_t n, uint32_t *perm, uint32_t *ikey) {
   for (int64_t r = (int64_t)blockIdx.x * B + threadIdx.x; r < n; r += (int64_t)gridDim.x * B) {
-    uint32_t id = perm[r];
-    ikey[2 * r] = (uint32_t)src[id];
-    ikey[2 * r + 1] = (uint32_t)dst[id];
-    ival[2 * r] = (uint32_t)(2 * r);
-    ival[2 * r + 1] = (uint32_t)(2 * r + 1);
+    const uint4 v = vals[r];
+    perm[r] = v.x;
+    ikey[2 * r] = v.y;
+    ikey[2 * r + 1] = v.z;
   }
 }
 
@@ -98,7 +100,8 @@ __global__ __launch_bounds__(B) void k_skel_tails(const uint32_t *ikey, const ui
 // Also seeds the first Boruvka round: every record starts as its own
 // component, so each edge offers its key to both of its records.
 __global__ __launch_bounds__(B) void k_skel_keys(uint32_t *skel_tail, const uint64_t *ts, const uint32_t *perm,
-                                                 int64_t n, int idbits, uint64_t *skel_key, uint64_t *best) {
+                                                 int64_t n, int idbits, uint64_t *skel_key, uint32_t *skel_tid,
+                                                 uint64_t *best) {
   for (int64_t h = (int64_t)blockIdx.x * B + threadIdx.x; h < n; h += (int64_t)gridDim.x * B) {
     uint32_t t0 = skel_tail[2 * h], t1 = skel_tail[2 * h + 1];
     if (t0 != NONE32 && t0 == t1) {  // the same pair twice: one line-graph edge
@@ -119,6 +122,8 @@ __global__ __launch_bounds__(B) void k_skel_keys(uint32_t *skel_tail, const uint
     }
     skel_key[2 * h] = k0;
     skel_key[2 * h + 1] = k1;
+    skel_tid[2 * h] = i0;
+    skel_tid[2 * h + 1] = i1;
     uint64_t mine = k0 < k1 ? k0 : k1;
     if (mine != NONE64) atomicMin((unsigned long long *)&best[h], (unsigned long long)mine);
     if (t0 != NONE32) atomicMin((unsigned long long *)&best[t0], (unsigned long long)k0);
@@ -139,14 +144,187 @@ __global__ __launch_bounds__(B) void k_rankof(const uint32_t *perm, int64_t n, u
   for (int64_t r = (int64_t)blockIdx.x * B + threadIdx.x; r < n; r += (int64_t)gridDim.x * B) rankof[perm[r]] = (uint32_t)r;
 }
 
-// Boruvka: per component, the minimum key over live edges leaving it. A tile
-// of 4096 live edges first takes per-component minima in an LDS hash (big
-// components are hit by most edges of late rounds), then one atomicMin per
-// component per tile; edges whose component finds no free slot go straight
-// to global memory.
+// slot of the (unique) edge with key k: its head is rank rankof[head id]; of
+// the two slots of that head, the one holding k
+__device__ inline uint32_t slot_of_key(uint64_t k, int idbits, const uint32_t *rankof, const uint64_t *skel_key) {
+  uint32_t hid = (uint32_t)((k >> 1) & ((uint64_t(1) << idbits) - 1));
+  uint32_t h = rankof[hid];
+  return skel_key[2 * (uint64_t)h] == k ? 2 * h : 2 * h + 1;
+}
+
+// ---------------------------------------------------------------- Boruvka
+// Round 1 runs on records (best[] was seeded while emitting the skeleton).
+// Each later round runs on a CONTRACTED graph: components carry dense ids
+// 0..C-1 and the live edges are records (key, endpoint ids, slot), so the
+// per-round arrays shrink with C and stay cache resident after round 1.
+
+// hook each component onto the component across its minimum edge; of a mutual
+// pair the smaller id stays; the hooking edge joins the forest. Hooked
+// components go to the active list for pointer jumping.
+__global__ __launch_bounds__(B) void k_bv_hook_first(int64_t n, const uint64_t *best, const uint64_t *skel_key,
+                                                     const uint32_t *skel_tail, const uint32_t *rankof, int idbits,
+                                                     uint32_t *hook, uint8_t *msf_flag, uint32_t *active,
+                                                     unsigned long long *nactive) {
+  bool keep[CT];
+  uint32_t vals[CT];
+  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < CT; k++) {
+    const int64_t c = base + (int64_t)k * B;
+    keep[k] = false;
+    vals[k] = (uint32_t)c;
+    if (c >= n) continue;
+    uint32_t to = (uint32_t)c;
+    const uint64_t bk = best[c];
+    if (bk != NONE64) {
+      const uint32_t e = slot_of_key(bk, idbits, rankof, skel_key);
+      const uint32_t tl = skel_tail[e], hd = e >> 1;
+      const uint32_t o = (tl == (uint32_t)c) ? hd : tl;
+      if (!(best[o] == bk && (uint32_t)c < o)) {
+        to = o;
+        msf_flag[e] = 1;
+        keep[k] = true;
+      }
+    }
+    hook[c] = to;
+  }
+  tile_append(keep, vals, active, nactive);
+}
+
+__global__ __launch_bounds__(B) void k_bv_hook(int64_t C, const uint64_t *best, const uint32_t *bidx,
+                                               const uint32_t *eu, const uint32_t *ev, const uint32_t *eslot,
+                                               uint32_t *hook, uint8_t *msf_flag, uint32_t *active,
+                                               unsigned long long *nactive) {
+  bool keep[CT];
+  uint32_t vals[CT];
+  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < CT; k++) {
+    const int64_t c = base + (int64_t)k * B;
+    keep[k] = false;
+    vals[k] = (uint32_t)c;
+    if (c >= C) continue;
+    uint32_t to = (uint32_t)c;
+    const uint64_t bk = best[c];
+    if (bk != NONE64) {
+      const uint32_t i = bidx[c];
+      const uint32_t o = eu[i] == (uint32_t)c ? ev[i] : eu[i];
+      if (!(best[o] == bk && (uint32_t)c < o)) {
+        to = o;
+        msf_flag[eslot[i]] = 1;
+        keep[k] = true;
+      }
+    }
+    hook[c] = to;
+  }
+  tile_append(keep, vals, active, nactive);
+}
+
+// pointer jumping over the hooked components; converged ones leave the list
+__global__ __launch_bounds__(B) void k_bv_jump(const uint32_t *act, int64_t nact, uint32_t *hook, uint32_t *out,
+                                               unsigned long long *nout) {
+  bool keep[CT];
+  uint32_t vals[CT];
+  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < CT; k++) {
+    const int64_t i = base + (int64_t)k * B;
+    keep[k] = false;
+    vals[k] = 0;
+    if (i >= nact) continue;
+    uint32_t c = act[i];
+    uint32_t h = hook[c];
+    uint32_t hh = hook[h];
+    if (hh != h) {
+      hook[c] = hh;
+      keep[k] = true;
+      vals[k] = c;
+    }
+  }
+  tile_append(keep, vals, out, nout);
+}
+
+// surviving roots get dense ids; records without any edge are left out
+__global__ __launch_bounds__(B) void k_root_flags(int64_t C, const uint32_t *hook, const uint64_t *best,
+                                                  uint32_t *flags) {
+  for (int64_t c = (int64_t)blockIdx.x * B + threadIdx.x; c < C; c += (int64_t)gridDim.x * B)
+    flags[c] = (hook[c] == (uint32_t)c && best[c] != NONE64) ? 1u : 0u;
+}
+
+// contract: live edges between different final roots, endpoints renamed to dense ids
+__global__ __launch_bounds__(B) void k_contract_first(int64_t n2, const uint64_t *skel_key, const uint32_t *skel_tail,
+                                                      const uint32_t *hook, const uint32_t *newid, uint64_t *okey,
+                                                      uint32_t *ou, uint32_t *ov, uint32_t *oslot,
+                                                      unsigned long long *cnt) {
+  bool keep[CT];
+  uint32_t pos[CT], nu[CT], nv[CT];
+  uint64_t kk[CT];
+  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < CT; k++) {
+    const int64_t e = base + (int64_t)k * B;
+    keep[k] = false;
+    kk[k] = NONE64;
+    nu[k] = nv[k] = 0;
+    if (e >= n2) continue;
+    kk[k] = skel_key[e];
+    if (kk[k] == NONE64) continue;
+    const uint32_t ru = hook[skel_tail[e]], rv = hook[e >> 1];
+    if (ru == rv) continue;
+    keep[k] = true;
+    nu[k] = newid[ru];
+    nv[k] = newid[rv];
+  }
+  tile_positions(keep, pos, cnt);
+#pragma unroll
+  for (int k = 0; k < CT; k++) {
+    if (!keep[k]) continue;
+    const uint32_t p = pos[k];
+    okey[p] = kk[k];
+    ou[p] = nu[k];
+    ov[p] = nv[k];
+    oslot[p] = (uint32_t)(base + (int64_t)k * B);
+  }
+}
+
+__global__ __launch_bounds__(B) void k_contract(int64_t E, const uint64_t *key, const uint32_t *eu, const uint32_t *ev,
+                                                const uint32_t *eslot, const uint32_t *hook, const uint32_t *newid,
+                                                uint64_t *okey, uint32_t *ou, uint32_t *ov, uint32_t *oslot,
+                                                unsigned long long *cnt) {
+  bool keep[CT];
+  uint32_t pos[CT], nu[CT], nv[CT];
+  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < CT; k++) {
+    const int64_t i = base + (int64_t)k * B;
+    keep[k] = false;
+    nu[k] = nv[k] = 0;
+    if (i >= E) continue;
+    const uint32_t ru = hook[eu[i]], rv = hook[ev[i]];
+    if (ru == rv) continue;
+    keep[k] = true;
+    nu[k] = newid[ru];
+    nv[k] = newid[rv];
+  }
+  tile_positions(keep, pos, cnt);
+#pragma unroll
+  for (int k = 0; k < CT; k++) {
+    if (!keep[k]) continue;
+    const int64_t i = base + (int64_t)k * B;
+    const uint32_t p = pos[k];
+    okey[p] = key[i];
+    ou[p] = nu[k];
+    ov[p] = nv[k];
+    oslot[p] = eslot[i];
+  }
+}
+
+// per component, the minimum key over its live edges. A tile of 4096 edges
+// first takes per-component minima in an LDS hash (late rounds send most
+// edges to a few big components), then one atomicMin per component per tile.
 constexpr int MHS = 512;
-__global__ __launch_bounds__(B) void k_bv_min(const uint32_t *live, int64_t nlive, const uint64_t *skel_key,
-                                              const uint32_t *skel_tail, const uint32_t *comp, uint64_t *best) {
+__global__ __launch_bounds__(B) void k_bv_min(int64_t E, const uint64_t *key, const uint32_t *eu, const uint32_t *ev,
+                                              uint64_t *best) {
   __shared__ uint32_t hk[MHS];
   __shared__ unsigned long long hv[MHS];
   for (int i = threadIdx.x; i < MHS; i += B) { hk[i] = NONE32; hv[i] = NONE64; }
@@ -154,22 +332,15 @@ __global__ __launch_bounds__(B) void k_bv_min(const uint32_t *live, int64_t nliv
   const int64_t tbase = (int64_t)blockIdx.x * (B * CT);
   for (int k = 0; k < CT; k++) {
     const int64_t i = tbase + (int64_t)k * B + threadIdx.x;
-    unsigned long long key = NONE64;
-    uint32_t cu = 0, cv = 0;
-    bool act = false;
-    if (i < nlive) {
-      const uint32_t e = live[i];
-      key = skel_key[e];
-      cu = comp[skel_tail[e]];
-      cv = comp[e >> 1];
-      act = cu != cv;
-    }
+    const bool act = i < E;
+    const unsigned long long kv = act ? key[i] : NONE64;
+    const uint32_t cu = act ? eu[i] : 0u, cv = act ? ev[i] : 0u;
 #pragma unroll
     for (int side = 0; side < 2; side++) {
       const uint32_t c = side ? cv : cu;
-      unsigned long long kmin = key;
+      unsigned long long kmin = kv;
       const bool upd = wave_combine_first(act, c, [&](bool mine, int leader) {
-        const unsigned long long v = wave_min_u64(mine ? key : NONE64);
+        const unsigned long long v = wave_min_u64(mine ? kv : NONE64);
         if ((int)wave_lane() == leader) kmin = v;
       });
       if (upd) {
@@ -197,108 +368,15 @@ __global__ __launch_bounds__(B) void k_bv_min(const uint32_t *live, int64_t nliv
   }
 }
 
-// slot of the (unique) edge with key k: its head is rank rankof[head id]; of
-// the two slots of that head, the one holding k
-__device__ inline uint32_t slot_of_key(uint64_t k, int idbits, const uint32_t *rankof, const uint64_t *skel_key) {
-  uint32_t hid = (uint32_t)((k >> 1) & ((uint64_t(1) << idbits) - 1));
-  uint32_t h = rankof[hid];
-  return skel_key[2 * (uint64_t)h] == k ? 2 * h : 2 * h + 1;
-}
-
-// hook each component root onto the component across its minimum edge; of a
-// mutual pair the smaller root stays; the hooking edge joins the forest.
-// Roots that hook go to the active list for pointer jumping, the others to
-// the list of roots of the next round (roots == nullptr: all records).
-__global__ __launch_bounds__(B) void k_bv_hook(const uint32_t *roots, int64_t nroots, const uint32_t *comp,
-                                               const uint64_t *best, const uint64_t *skel_key,
-                                               const uint32_t *skel_tail, const uint32_t *rankof, int idbits,
-                                               uint32_t *hook, uint8_t *msf_flag, uint32_t *active,
-                                               unsigned long long *nactive, uint32_t *keep_roots,
-                                               unsigned long long *nkeep) {
-  bool hk[CT], st[CT];
-  uint32_t vals[CT];
-  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
-#pragma unroll
-  for (int k = 0; k < CT; k++) {
-    const int64_t i = base + (int64_t)k * B;
-    hk[k] = false;
-    st[k] = false;
-    vals[k] = 0;
-    if (i >= nroots) continue;
-    const uint32_t c = roots ? roots[i] : (uint32_t)i;
-    vals[k] = c;
-    uint32_t to = c;
-    uint64_t bk = best[c];
-    if (bk != NONE64) {
-      uint32_t e = slot_of_key(bk, idbits, rankof, skel_key);
-      uint32_t cu = comp[skel_tail[e]], cv = comp[e >> 1];
-      uint32_t o = (cu == c) ? cv : cu;
-      bool mutual = best[o] == bk;
-      if (!(mutual && c < o)) {
-        to = o;
-        msf_flag[e] = 1;
-        hk[k] = true;
-      }
-    }
-    st[k] = !hk[k] && bk != NONE64;  // isolated components are final
-    hook[c] = to;
+// the edge index holding each component's minimum (keys are unique)
+__global__ __launch_bounds__(B) void k_bv_pick(int64_t E, const uint64_t *key, const uint32_t *eu, const uint32_t *ev,
+                                               const uint64_t *best, uint32_t *bidx) {
+  for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < E; i += (int64_t)gridDim.x * B) {
+    const uint64_t k = key[i];
+    const uint32_t a = eu[i], b = ev[i];
+    if (best[a] == k) bidx[a] = (uint32_t)i;
+    if (best[b] == k) bidx[b] = (uint32_t)i;
   }
-  tile_append(hk, vals, active, nactive);
-  tile_append(st, vals, keep_roots, nkeep);
-}
-
-__global__ __launch_bounds__(B) void k_fill_best(const uint32_t *roots, int64_t nroots, uint64_t *best) {
-  for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < nroots; i += (int64_t)gridDim.x * B)
-    best[roots[i]] = NONE64;
-}
-
-// pointer jumping over the hooked roots; converged ones leave the list
-__global__ __launch_bounds__(B) void k_bv_jump(const uint32_t *act, int64_t nact, uint32_t *hook, uint32_t *out,
-                                               unsigned long long *nout) {
-  bool keep[CT];
-  uint32_t vals[CT];
-  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
-#pragma unroll
-  for (int k = 0; k < CT; k++) {
-    const int64_t i = base + (int64_t)k * B;
-    keep[k] = false;
-    vals[k] = 0;
-    if (i >= nact) continue;
-    uint32_t c = act[i];
-    uint32_t h = hook[c];
-    uint32_t hh = hook[h];
-    if (hh != h) {
-      hook[c] = hh;
-      keep[k] = true;
-      vals[k] = c;
-    }
-  }
-  tile_append(keep, vals, out, nout);
-}
-
-__global__ __launch_bounds__(B) void k_bv_relabel(int64_t n, uint32_t *comp, const uint32_t *hook) {
-  for (int64_t p = (int64_t)blockIdx.x * B + threadIdx.x; p < n; p += (int64_t)gridDim.x * B) comp[p] = hook[comp[p]];
-}
-
-// keep edges whose endpoints lie in different components (live == nullptr: all slots)
-__global__ __launch_bounds__(B) void k_bv_filter(const uint32_t *live, int64_t nlive, const uint64_t *skel_key,
-                                                 const uint32_t *skel_tail, const uint32_t *comp, uint32_t *out,
-                                                 unsigned long long *cnt) {
-  bool keep[CT];
-  uint32_t vals[CT];
-  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
-#pragma unroll
-  for (int k = 0; k < CT; k++) {
-    const int64_t i = base + (int64_t)k * B;
-    keep[k] = false;
-    vals[k] = 0;
-    if (i >= nlive) continue;
-    uint32_t e = live ? live[i] : (uint32_t)i;
-    if (!live && skel_key[e] == NONE64) continue;
-    vals[k] = e;
-    keep[k] = comp[skel_tail[e]] != comp[e >> 1];
-  }
-  tile_append(keep, vals, out, cnt);
 }
 
 __global__ __launch_bounds__(B) void k_msf_list(const uint8_t *flag, int64_t n2, uint32_t *out,
@@ -316,11 +394,12 @@ __global__ __launch_bounds__(B) void k_msf_list(const uint8_t *flag, int64_t n2,
 }
 
 __global__ __launch_bounds__(B) void k_msf_gather(const uint32_t *list, int64_t m, const uint64_t *skel_key,
-                                                  const uint32_t *skel_tail, uint64_t *okey, uint64_t *oval) {
+                                                  const uint32_t *skel_tail, const uint32_t *skel_tid, uint64_t *okey,
+                                                  uint4 *oval) {
   for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < m; i += (int64_t)gridDim.x * B) {
     uint32_t e = list[i];
     okey[i] = skel_key[e];
-    oval[i] = ((uint64_t)(e >> 1) << 32) | skel_tail[e];
+    oval[i] = make_uint4(skel_tail[e], e >> 1, skel_tid[e], 0u);
   }
 }
 
@@ -334,7 +413,12 @@ uint64_t *pinned_scratch() {
   return p;
 }
 
+// Reads `count` (<= 8) u64 words through the first 64 bytes of the pinned page.
 ce_status read_u64(const uint64_t *dev, uint64_t *host_out, int count, hipStream_t s) {
+  if (count > 8) {
+    set_error("internal: read_u64 count");
+    return CE_EDEVICE;
+  }
   uint64_t *h = pinned_scratch();
   if (!h) {
     set_error("hipHostMalloc of the readback buffer failed");
@@ -366,15 +450,13 @@ __global__ void k_set_u64(uint64_t *p, uint64_t v) { *p = v; }
 
 size_t stage_sort_skeleton_scratch(int64_t n) {
   Ws w;
-  w.alloc<uint64_t>(n);      // tkey alt
-  w.alloc<uint32_t>(n);      // perm alt
+  for (int k = 0; k < 4; k++) w.alloc<uint32_t>(2 * n);  // ikey, ival and their ping-pong copies
+  size_t base = w.off;
+  w.alloc<uint64_t>(n);  // tkey alt
+  w.alloc<uint4>(n);     // (id, src, dst)
+  w.alloc<uint4>(n);     // ... ping-pong
   size_t a = w.off + radix_ws_bytes(n);
-  w = Ws();
-  w.alloc<uint32_t>(2 * n);  // ikey
-  w.alloc<uint32_t>(2 * n);  // ival
-  w.alloc<uint32_t>(2 * n);  // ikey alt
-  w.alloc<uint32_t>(2 * n);  // ival alt
-  size_t b2 = w.off + radix_ws_bytes(2 * n);
+  size_t b2 = base + radix_ws_bytes(2 * n);
   return (a > b2 ? a : b2) + 4096;
 }
 
@@ -382,29 +464,29 @@ ce_status stage_sort_skeleton(const int32_t *src, const int32_t *dst, const int6
                               hipStream_t s) {
   const int64_t n = b.n, n2 = 2 * n;
   size_t m0 = ws.mark();
-  // 1. records by (t, id): stable radix sort on t - tmin; values start as ids
-  {
-    uint64_t *tkey_alt = ws.alloc<uint64_t>(n);
-    uint32_t *perm_alt = ws.alloc<uint32_t>(n);
-    CE_WS_CHECK(ws);
-    CE_LAUNCH(k_tkeys, dim3(grid_for(n, B)), dim3(B), 0, s, t, n, b.tmin, b.ts);
-    CE_HIP(hipGetLastError());
-    bool alt = false;
-    CE_TRY((radix_sort_pairs<uint64_t, uint32_t>(b.ts, b.perm, tkey_alt, perm_alt, n, 0, b.tbits, true, &alt, ws, s)));
-    if (alt) {
-      CE_HIP(hipMemcpyAsync(b.ts, tkey_alt, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
-      CE_HIP(hipMemcpyAsync(b.perm, perm_alt, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
-    }
-    ws.release(m0);
-  }
-  // 2. incidence entries (vertex, 2*rank+side), stably sorted by vertex
   uint32_t *ikey = ws.alloc<uint32_t>(n2);
   uint32_t *ival = ws.alloc<uint32_t>(n2);
   uint32_t *ikey_alt = ws.alloc<uint32_t>(n2);
   uint32_t *ival_alt = ws.alloc<uint32_t>(n2);
   CE_WS_CHECK(ws);
-  CE_LAUNCH(k_incidence, dim3(grid_for(n, B)), dim3(B), 0, s, b.perm, src, dst, n, ikey, ival);
-  CE_HIP(hipGetLastError());
+  // 1. records by (t, id): stable radix sort on t - tmin carrying (id, src, dst)
+  {
+    size_t m1 = ws.mark();
+    uint64_t *tkey_alt = ws.alloc<uint64_t>(n);
+    uint4 *tval = ws.alloc<uint4>(n);
+    uint4 *tval_alt = ws.alloc<uint4>(n);
+    CE_WS_CHECK(ws);
+    CE_LAUNCH(k_tkeys, dim3(grid_for(n, B)), dim3(B), 0, s, t, src, dst, n, b.tmin, b.ts, tval);
+    CE_HIP(hipGetLastError());
+    bool alt = false;
+    CE_TRY((radix_sort_pairs<uint64_t, uint4>(b.ts, tval, tkey_alt, tval_alt, n, 0, b.tbits, false, &alt, ws, s)));
+    if (alt) CE_HIP(hipMemcpyAsync(b.ts, tkey_alt, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
+    // 2. incidence entries (vertex, 2*rank+side) in rank order, perm by rank
+    CE_LAUNCH(k_incidence, dim3(grid_for(n, B)), dim3(B), 0, s, alt ? tval_alt : tval, n, b.perm, ikey);
+    CE_HIP(hipGetLastError());
+    ws.release(m1);
+  }
+  // stable sort by vertex keeps every list in rank order
   bool alt = false;
   CE_TRY((radix_sort_pairs<uint32_t, uint32_t>(ikey, ival, ikey_alt, ival_alt, n2, 0, b.vbits, true, &alt, ws, s)));
   const uint32_t *sk = alt ? ikey_alt : ikey;
@@ -413,8 +495,8 @@ ce_status stage_sort_skeleton(const int32_t *src, const int32_t *dst, const int6
   CE_LAUNCH(k_skel_tails, dim3(grid_for(n2, B)), dim3(B), 0, s, sk, sv, n2, b.skel_tail);
   CE_LAUNCH(k_fill_u64, dim3(grid_for(n, B)), dim3(B), 0, s, b.best, n, NONE64);
   CE_HIP(hipGetLastError());
-  CE_LAUNCH(k_skel_keys, dim3(grid_for(n, B)), dim3(B), 0, s, b.skel_tail, b.ts, b.perm, n, b.idbits,
-                     b.skel_key, b.best);
+  CE_LAUNCH(k_skel_keys, dim3(grid_for(n, B)), dim3(B), 0, s, b.skel_tail, b.ts, b.perm, n, b.idbits, b.skel_key,
+            b.skel_tid, b.best);
   CE_HIP(hipGetLastError());
   ws.release(m0);
   return CE_OK;
@@ -422,87 +504,127 @@ ce_status stage_sort_skeleton(const int32_t *src, const int32_t *dst, const int6
 
 size_t stage_boruvka_scratch(int64_t n) {
   Ws w;
-  w.alloc<uint32_t>(n);      // comp
   w.alloc<uint32_t>(n);      // rankof
   w.alloc<uint32_t>(n);      // hook
+  w.alloc<uint32_t>(n);      // bidx
+  w.alloc<uint32_t>(n + 1);  // root flags
+  w.alloc<uint32_t>(n + 1);  // dense ids
   w.alloc<uint32_t>(n);      // active
   w.alloc<uint32_t>(n);      // active alt
-  w.alloc<uint32_t>(n);      // roots
-  w.alloc<uint32_t>(n);      // roots alt
-  w.alloc<uint32_t>(2 * n);  // live
-  w.alloc<uint32_t>(2 * n);  // live alt
-  return w.off + 4096;
+  for (int k = 0; k < 2; k++) {  // edge lists (key, u, v, slot), ping-pong
+    w.alloc<uint64_t>(2 * n);
+    w.alloc<uint32_t>(2 * n);
+    w.alloc<uint32_t>(2 * n);
+    w.alloc<uint32_t>(2 * n);
+  }
+  return w.off + scan_ws_bytes(n + 1) + 4096;
 }
 
 static unsigned tiles_for(int64_t n) { return (unsigned)((n + (int64_t)B * CT - 1) / ((int64_t)B * CT)); }
 
+// pointer jumping until every hooked component points at its final root
+static ce_status jump_all(uint32_t *&act, uint32_t *&act2, uint64_t nact, uint32_t *hook, Bufs &b, hipStream_t s) {
+  for (int it = 0; nact > 0; it++) {
+    if (it > 64) {
+      set_error("Boruvka pointer jumping did not converge");
+      return CE_EDEVICE;
+    }
+    CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[5], (uint64_t)0);
+    CE_LAUNCH(k_bv_jump, dim3(tiles_for((int64_t)nact)), dim3(B), 0, s, act, (int64_t)nact, hook, act2,
+              (unsigned long long *)&b.hdr[5]);
+    CE_HIP(hipGetLastError());
+    CE_TRY(read_u64(&b.hdr[5], &nact, 1, s));
+    uint32_t *t = act; act = act2; act2 = t;
+  }
+  return CE_OK;
+}
+
 ce_status stage_boruvka(Bufs &b, Ws &ws, hipStream_t s) {
   const int64_t n = b.n, n2 = 2 * n;
   size_t m0 = ws.mark();
-  uint32_t *comp = ws.alloc<uint32_t>(n);
   uint32_t *rankof = ws.alloc<uint32_t>(n);
   uint32_t *hook = ws.alloc<uint32_t>(n);
+  uint32_t *bidx = ws.alloc<uint32_t>(n);
+  uint32_t *flags = ws.alloc<uint32_t>(n + 1);
+  uint32_t *newid = ws.alloc<uint32_t>(n + 1);
   uint32_t *act = ws.alloc<uint32_t>(n);
   uint32_t *act2 = ws.alloc<uint32_t>(n);
-  uint32_t *roots = ws.alloc<uint32_t>(n);
-  uint32_t *roots2 = ws.alloc<uint32_t>(n);
-  uint32_t *live = ws.alloc<uint32_t>(n2);
-  uint32_t *live2 = ws.alloc<uint32_t>(n2);
+  uint64_t *key[2];
+  uint32_t *eu[2], *ev[2], *es[2];
+  for (int k = 0; k < 2; k++) {
+    key[k] = ws.alloc<uint64_t>(n2);
+    eu[k] = ws.alloc<uint32_t>(n2);
+    ev[k] = ws.alloc<uint32_t>(n2);
+    es[k] = ws.alloc<uint32_t>(n2);
+  }
   CE_WS_CHECK(ws);
-  uint64_t *best = b.best;  // seeded for the first round by k_skel_keys
+  uint64_t *best = b.best;  // seeded for round 1 while emitting the skeleton
   unsigned long long *cnt = (unsigned long long *)&b.hdr[4];
-  unsigned long long *cnt2 = (unsigned long long *)&b.hdr[5];
-  unsigned long long *cnt3 = (unsigned long long *)&b.hdr[7];
   CE_LAUNCH(k_fill_u8, dim3(grid_for(n2, B)), dim3(B), 0, s, b.msf_flag, n2, (uint8_t)0);
-  CE_LAUNCH(k_iota_u32, dim3(grid_for(n, B)), dim3(B), 0, s, comp, n);
   CE_LAUNCH(k_rankof, dim3(grid_for(n, B)), dim3(B), 0, s, b.perm, n, rankof);
+  // round 1 on records
+  CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[4], (uint64_t)0);
+  CE_LAUNCH(k_bv_hook_first, dim3(tiles_for(n)), dim3(B), 0, s, n, best, b.skel_key, b.skel_tail, rankof, b.idbits,
+            hook, b.msf_flag, act, cnt);
   CE_HIP(hipGetLastError());
-  const uint32_t *cur = nullptr;  // first round: all slots
-  const uint32_t *rcur = nullptr; // first round: all records are roots
-  int64_t nlive = n2, nroots = n;
-  int rounds = 0;
-  while (nlive > 0) {
+  uint64_t nact = 0;
+  CE_TRY(read_u64(&b.hdr[4], &nact, 1, s));
+  CE_TRY(jump_all(act, act2, nact, hook, b, s));
+  CE_LAUNCH(k_root_flags, dim3(grid_for(n, B)), dim3(B), 0, s, n, hook, best, flags);
+  CE_HIP(hipGetLastError());
+  CE_TRY(scan_exclusive_u32(flags, newid, n, ws, s));
+  CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[4], (uint64_t)0);
+  CE_LAUNCH(k_contract_first, dim3(tiles_for(n2)), dim3(B), 0, s, n2, b.skel_key, b.skel_tail, hook, newid, key[0],
+            eu[0], ev[0], es[0], cnt);
+  CE_HIP(hipGetLastError());
+  uint64_t hv[2];
+  {
+    // word 16 of the pinned page is ours; read_u64 uses the first words
+    uint32_t *h = (uint32_t *)pinned_scratch();
+    CE_HIP(hipMemcpyAsync(h + 16, newid + n, 4, hipMemcpyDeviceToHost, s));
+    CE_TRY(read_u64(&b.hdr[4], hv, 1, s));  // synchronises the stream
+    hv[1] = h[16];
+  }
+  int64_t E = (int64_t)hv[0], C = (int64_t)hv[1];
+  if (E > n2 || C > n) {
+    set_error("internal: contracted graph larger than its input");
+    return CE_EDEVICE;
+  }
+  int cur = 0, rounds = 1;
+  while (E > 0) {
     if (++rounds > 64) {
       set_error("Boruvka did not converge");
       return CE_EDEVICE;
     }
-    if (rounds > 1) {
-      CE_LAUNCH(k_fill_best, dim3(grid_for(nroots, B)), dim3(B), 0, s, rcur, nroots, best);
-      CE_LAUNCH(k_bv_min, dim3(tiles_for(nlive)), dim3(B), 0, s, cur, nlive, b.skel_key, b.skel_tail, comp, best);
-    }
+    CE_LAUNCH(k_fill_u64, dim3(grid_for(C, B)), dim3(B), 0, s, best, C, NONE64);
+    CE_LAUNCH(k_bv_min, dim3(tiles_for(E)), dim3(B), 0, s, E, key[cur], eu[cur], ev[cur], best);
+    CE_LAUNCH(k_bv_pick, dim3(grid_for(E, B)), dim3(B), 0, s, E, key[cur], eu[cur], ev[cur], best, bidx);
     CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[4], (uint64_t)0);
-    CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[7], (uint64_t)0);
-    CE_LAUNCH(k_bv_hook, dim3(tiles_for(nroots)), dim3(B), 0, s, rcur, nroots, comp, best, b.skel_key,
-                       b.skel_tail, rankof, b.idbits, hook, b.msf_flag, act, cnt, roots, cnt3);
+    CE_LAUNCH(k_bv_hook, dim3(tiles_for(C)), dim3(B), 0, s, C, best, bidx, eu[cur], ev[cur], es[cur], hook,
+              b.msf_flag, act, cnt);
     CE_HIP(hipGetLastError());
-    uint64_t hv[4];
-    CE_TRY(read_u64(&b.hdr[4], hv, 4, s));
-    uint64_t nact = hv[0];
-    nroots = (int64_t)hv[3];
-    rcur = roots;
-    uint32_t *tr = roots; roots = roots2; roots2 = tr;
-    for (int it = 0; nact > 0; it++) {
-      if (it > 64) {
-        set_error("Boruvka pointer jumping did not converge");
-        return CE_EDEVICE;
-      }
-      CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[5], (uint64_t)0);
-      CE_LAUNCH(k_bv_jump, dim3(tiles_for((int64_t)nact)), dim3(B), 0, s, act, (int64_t)nact, hook, act2,
-                         cnt2);
-      CE_HIP(hipGetLastError());
-      CE_TRY(read_u64(&b.hdr[5], &nact, 1, s));
-      uint32_t *t = act; act = act2; act2 = t;
-    }
-    CE_LAUNCH(k_bv_relabel, dim3(grid_for(n, B)), dim3(B), 0, s, n, comp, hook);
+    CE_TRY(read_u64(&b.hdr[4], &nact, 1, s));
+    CE_TRY(jump_all(act, act2, nact, hook, b, s));
+    CE_LAUNCH(k_root_flags, dim3(grid_for(C, B)), dim3(B), 0, s, C, hook, best, flags);
+    CE_HIP(hipGetLastError());
+    CE_TRY(scan_exclusive_u32(flags, newid, C, ws, s));
     CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[4], (uint64_t)0);
-    CE_LAUNCH(k_bv_filter, dim3(tiles_for(nlive)), dim3(B), 0, s, cur, nlive, b.skel_key, b.skel_tail, comp,
-                       live, cnt);
+    CE_LAUNCH(k_contract, dim3(tiles_for(E)), dim3(B), 0, s, E, key[cur], eu[cur], ev[cur], es[cur], hook, newid,
+              key[1 - cur], eu[1 - cur], ev[1 - cur], es[1 - cur], cnt);
     CE_HIP(hipGetLastError());
-    uint64_t nl = 0;
-    CE_TRY(read_u64(&b.hdr[4], &nl, 1, s));
-    nlive = (int64_t)nl;
-    cur = live;
-    uint32_t *t = live; live = live2; live2 = t;
+    {
+      uint32_t *h = (uint32_t *)pinned_scratch();
+      CE_HIP(hipMemcpyAsync(h + 16, newid + C, 4, hipMemcpyDeviceToHost, s));
+      CE_TRY(read_u64(&b.hdr[4], hv, 1, s));
+      hv[1] = h[16];
+    }
+    if ((int64_t)hv[0] > E || (int64_t)hv[1] > C) {
+      set_error("internal: contracted graph larger than its input");
+      return CE_EDEVICE;
+    }
+    E = (int64_t)hv[0];
+    C = (int64_t)hv[1];
+    cur = 1 - cur;
   }
   ws.release(m0);
   return CE_OK;
@@ -511,7 +633,7 @@ ce_status stage_boruvka(Bufs &b, Ws &ws, hipStream_t s) {
 size_t stage_msf_sort_scratch(int64_t n) {
   Ws w;
   w.alloc<uint64_t>(n);
-  w.alloc<uint64_t>(n);
+  w.alloc<uint4>(n);
   w.alloc<uint32_t>(n);
   return w.off + radix_ws_bytes(n) + 4096;
 }
@@ -520,7 +642,7 @@ ce_status stage_msf_sort(Bufs &b, Ws &ws, hipStream_t s, int64_t *m_out) {
   const int64_t n = b.n, n2 = 2 * n;
   size_t m0 = ws.mark();
   uint64_t *key_alt = ws.alloc<uint64_t>(n);
-  uint64_t *val_alt = ws.alloc<uint64_t>(n);
+  uint4 *val_alt = ws.alloc<uint4>(n);
   uint32_t *list = ws.alloc<uint32_t>(n);
   CE_WS_CHECK(ws);
   CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[6], (uint64_t)0);
@@ -535,13 +657,13 @@ ce_status stage_msf_sort(Bufs &b, Ws &ws, hipStream_t s, int64_t *m_out) {
   }
   if (m > 0)
     CE_LAUNCH(k_msf_gather, dim3(grid_for((int64_t)m, B)), dim3(B), 0, s, list, (int64_t)m, b.skel_key,
-                       b.skel_tail, b.msf_key, b.msf_val);
+              b.skel_tail, b.skel_tid, b.msf_key, b.msf_val);
   bool alt = false;
-  CE_TRY((radix_sort_pairs<uint64_t, uint64_t>(b.msf_key, b.msf_val, key_alt, val_alt, (int64_t)m, 0, b.keybits,
-                                                false, &alt, ws, s)));
+  CE_TRY((radix_sort_pairs<uint64_t, uint4>(b.msf_key, b.msf_val, key_alt, val_alt, (int64_t)m, 0, b.keybits, false,
+                                             &alt, ws, s)));
   if (alt && m > 0) {
     CE_HIP(hipMemcpyAsync(b.msf_key, key_alt, sizeof(uint64_t) * m, hipMemcpyDeviceToDevice, s));
-    CE_HIP(hipMemcpyAsync(b.msf_val, val_alt, sizeof(uint64_t) * m, hipMemcpyDeviceToDevice, s));
+    CE_HIP(hipMemcpyAsync(b.msf_val, val_alt, sizeof(uint4) * m, hipMemcpyDeviceToDevice, s));
   }
   ws.release(m0);
   *m_out = (int64_t)m;

@@ -158,6 +158,11 @@ __global__ __launch_bounds__(RB) void k_rs_hist(const K *keys, int64_t n, int sh
   }
 }
 
+template <class V>
+__device__ inline V iota_value(int64_t i) { return V(i); }
+template <>
+__device__ inline uint4 iota_value<uint4>(int64_t i) { return make_uint4((uint32_t)i, 0u, 0u, 0u); }
+
 template <class K, class V>
 __global__ __launch_bounds__(RB) void k_rs_scatter(const K *kin, const V *vin, K *kout, V *vout, int64_t n,
                                                    int shift, const uint32_t *hscan, int nblocks, int iota) {
@@ -180,7 +185,7 @@ __global__ __launch_bounds__(RB) void k_rs_scatter(const K *kin, const V *vin, K
     const int64_t i = tbase + (int64_t)w * RWT + c * 64 + lane;
     const bool valid = i < n;
     K k = valid ? kin[i] : K(0);
-    V v = valid ? (iota ? V(i) : vin[i]) : V(0);
+    V v = valid ? (iota ? iota_value<V>(i) : vin[i]) : V{};
     uint32_t d = (uint32_t)(k >> shift) & 255u;
     uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -282,6 +287,8 @@ template ce_status radix_sort_pairs<uint64_t, uint32_t>(uint64_t *, uint32_t *, 
                                                         int, int, bool, bool *, Ws &, hipStream_t);
 template ce_status radix_sort_pairs<uint32_t, uint32_t>(uint32_t *, uint32_t *, uint32_t *, uint32_t *, int64_t,
                                                         int, int, bool, bool *, Ws &, hipStream_t);
+template ce_status radix_sort_pairs<uint64_t, uint4>(uint64_t *, uint4 *, uint64_t *, uint4 *, int64_t, int, int,
+                                                     bool, bool *, Ws &, hipStream_t);
 template ce_status radix_sort_pairs<uint64_t, uint64_t>(uint64_t *, uint64_t *, uint64_t *, uint64_t *, int64_t,
                                                         int, int, bool, bool *, Ws &, hipStream_t);
 

@@ -1,0 +1,107 @@
+"""Roofline bookkeeping for bench.py: algorithmic bytes per kernel and HBM
+traffic from rocprofv3 counter runs.
+
+Algorithmic bytes are the bytes a kernel must move at minimum width, with each
+input and output touched once (random gathers count their element size, not
+the cache line they pull). ``traffic`` comes from two rocprofv3 ``--pmc`` runs
+(FETCH_SIZE, then WRITE_SIZE, KiB per dispatch), each scaled by what the same
+counter reads for a plain copy kernel of known size.
+"""
+from __future__ import annotations
+
+import csv
+import glob
+import hashlib
+import json
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+
+
+def dendrogram_levels(m: int, lds_bits: int = 9, level_bits: int = 6) -> int:
+    """Global levels of the rank-interval dendrogram for m rows."""
+    if m <= 1:
+        return 0
+    L = (m - 1).bit_length()
+    hi, lv = L - 1, 0
+    while hi >= lds_bits:
+        lo = max(hi - level_bits + 1, lds_bits)
+        lv += 1
+        hi = lo - 1
+    return lv
+
+
+# kernel -> (unit, algorithmic bytes per unit, units per step as a function of the run)
+def algorithmic_bytes_per_step(kernel: str, n: int, m: int, level_bits: int = 6) -> tuple:
+    """(unit description, bytes per unit, units per step) for a kernel of the pipeline."""
+    if kernel == "k_krt_accum":
+        # per row and global level: hooked root id (4), its size (4), the parent of that root (4),
+        # the row id it offers (4); the per-root atomics are combined in LDS
+        return ("MSF row x global level", 16, dendrogram_levels(m, level_bits=level_bits) * m)
+    if kernel == "k_krt_relabel":
+        # per row and level: two labels (8) read and rewritten (8), two sizes rewritten (8), two roots
+        # written (8), two root entries read (2 x 12)
+        return ("MSF row x global level", 56, dendrogram_levels(m, level_bits=level_bits) * m)
+    if kernel == "k_rs_scatter":
+        return ("element x pass (u64 key + u64 value)", 32, None)
+    raise KeyError(kernel)
+
+
+def source_hash(files=("csrc/dendrogram.hip", "csrc/pipeline.hip", "csrc/condense.hip", "csrc/primitives.hip",
+                       "csrc/ce_internal.h")) -> str:
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(HERE, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def _counter_rows(d):
+    paths = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+    rows = []
+    for p in paths:
+        with open(p) as fh:
+            rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def summarize_pmc(fetch_dir: str, write_dir: str, kernel: str, copy_bytes: int) -> dict:
+    """Per-dispatch HBM traffic of `kernel`, calibrated against the largest copy dispatch."""
+    out = {"kernel": kernel, "copy_bytes": copy_bytes}
+    for name, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = [r for r in _counter_rows(d) if r["Counter_Name"] == name]
+        copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
+        ref_kib = max(copies) if copies else None
+        factor = (copy_bytes / 1024.0) / ref_kib if ref_kib else None
+        mine = [float(r["Counter_Value"]) for r in rows if kernel in r["Kernel_Name"]]
+        out[name] = {"dispatches": len(mine), "avg_kib": (sum(mine) / len(mine)) if mine else None,
+                     "copy_kib": ref_kib, "scale": factor}
+    f, w = out["FETCH_SIZE"], out["WRITE_SIZE"]
+    if f["avg_kib"] is not None and w["avg_kib"] is not None and f["scale"] and w["scale"]:
+        out["traffic_bytes_per_launch"] = 1024.0 * (f["avg_kib"] * f["scale"] + w["avg_kib"] * w["scale"])
+    else:
+        out["traffic_bytes_per_launch"] = None
+    out["source_hash"] = source_hash()
+    return out
+
+
+def load_traffic(kernel: str, path: str) -> float | None:
+    """Traffic per launch from a committed PMC summary, or None if the kernels changed since."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        text = fh.read()
+    start = text.find("```json")
+    if start < 0:
+        return None
+    blob = json.loads(text[start + 7:text.find("```", start + 7)])
+    if blob.get("kernel") != kernel or blob.get("source_hash") != source_hash():
+        return None
+    return blob.get("traffic_bytes_per_launch")
+
+
+if __name__ == "__main__":
+    import sys
+    fetch_dir, write_dir, kernel, copy_bytes = sys.argv[1], sys.argv[2], sys.argv[3], int(sys.argv[4])
+    print(json.dumps(summarize_pmc(fetch_dir, write_dir, kernel, copy_bytes), indent=1))
