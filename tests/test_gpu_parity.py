@@ -149,3 +149,26 @@ def test_determinism_repeated_runs():
         b = run_gpu(w.src, w.dst, w.t, w.num_vertices, 5)
         for f in FIELDS:
             assert np.array_equal(a[f], b[f]), f
+
+
+@pytest.mark.timeout(1200)
+def test_mid_workload_full_size():
+    """The benchmark's workload at full size (R-MAT scale 20, 50M records,
+    per-pair Hawkes times over 90 days, M=10), in the configuration bench.py
+    times (preallocated workspace and outputs): every output element vs the
+    oracle (about two minutes of single-threaded oracle time)."""
+    ce = _ce()
+    w = synth.plain_mid()
+    dev = torch.device("cuda:0")
+    src, dst, tt = (torch.from_numpy(a).to(dev) for a in (w.src, w.dst, w.t))
+    outs = ce.Outputs(w.n, w.min_cluster_size, dev)
+    ws = torch.empty(ce.workspace_bytes(w.n, w.num_vertices, w.min_cluster_size), dtype=torch.uint8, device=dev)
+    note("mid full size: GPU run")
+    got = ce.to_numpy(ce.cluster_edges(src, dst, tt, w.min_cluster_size, w.num_vertices, outputs=outs, workspace=ws))
+    del src, dst, tt, outs, ws
+    note("mid full size: oracle run (m=%d)" % got["m"])
+    ref = oracle.cluster(w.src, w.dst, w.t, w.min_cluster_size, w.num_vertices, tier=1)
+    note("mid full size: comparing")
+    assert got["m"] == ref.m and got["n_clusters"] == ref.n_clusters and got["n_labels"] == ref.n_labels
+    for f in FIELDS:
+        assert np.array_equal(got[f], getattr(ref, f)), f
