@@ -30,7 +30,7 @@
  *   labels: -1 = noise, else 0..L-1 numbered by ascending minimum member id
  *
  * Memory: every pointer argument except `params`, `out` (the struct itself),
- * `counts` and `workspace_bytes` is a DEVICE pointer on the current HIP
+ * `counts` and the batch offset arrays is a DEVICE pointer on the current HIP
  * device. Inputs are read-only and owned by the caller. Outputs are owned by
  * the caller and must hold the documented row counts. The library keeps
  * nothing between calls.
@@ -114,6 +114,43 @@ size_t ce_workspace_bytes(int64_t n, int64_t num_vertices, const ce_params *para
 ce_status ce_cluster_edges(const int32_t *src, const int32_t *dst, const int64_t *t, int64_t n,
                            const ce_params *params, const ce_result *out, ce_counts *counts,
                            void *workspace, size_t workspace_bytes, void *stream);
+
+/*
+ * Batches. Many independent graphs can be clustered in one call: graph g owns
+ * the records [edge_offsets[g], edge_offsets[g+1]) of src/dst/t and the
+ * vertex ids [0, vertex_offsets[g+1] - vertex_offsets[g]) (ids are local to
+ * each graph). Two graphs share no vertex, so the line graph of the batch has
+ * no edge between them (Sec. 1.2.2) and the batch is their disjoint union:
+ * every graph's outputs equal those of ce_cluster_edges on that graph alone
+ * (Alg. 4 applied per graph), in that graph's local ids:
+ *   records 0..n_g-1 (input index - edge_offsets[g]), the k-th dendrogram row
+ *   of the graph is node n_g + k, its virtual ROOT is node n_g + m_g.
+ * Layout of the outputs (DEVICE buffers of one ce_result):
+ *   msf_*, sl_*          rows of graph g at [row_offsets[g], row_offsets[g+1])
+ *   pt_*, labels         by input index over the whole batch
+ *   cl_*                 rows of graph g at [cluster_offsets[g], cluster_offsets[g+1]),
+ *                        its ROOT last; labels are numbered per graph
+ * Capacities: rows of msf_*, sl_* >= max(n, 1) where n = edge_offsets[G];
+ *   pt_*, labels >= n; cl_* >= sum over graphs of ce_max_clusters(n_g, M)
+ *   (at most 2*floor(n/M) + G).
+ * Host arrays: edge_offsets, vertex_offsets (G+1 entries each, starting at 0,
+ *   edge offsets non-decreasing, every graph with >= 1 vertex); counts (G
+ *   entries), row_offsets and cluster_offsets (G+1 entries) are written.
+ * params.num_vertices is not used (vertex_offsets gives every graph's V).
+ * 1 <= G <= CE_MAX_GRAPHS; n <= 2^31-1; vertex_offsets[G] <= 2^31.
+ * Errors as for ce_cluster_edges; a data error in any graph fails the call.
+ */
+#define CE_MAX_GRAPHS (1LL << 24)
+
+/* Bytes of device workspace ce_cluster_batch needs; 0 on invalid arguments. */
+size_t ce_batch_workspace_bytes(const int64_t *edge_offsets, const int64_t *vertex_offsets, int64_t num_graphs,
+                                const ce_params *params);
+
+ce_status ce_cluster_batch(const int32_t *src, const int32_t *dst, const int64_t *t,
+                           const int64_t *edge_offsets, const int64_t *vertex_offsets, int64_t num_graphs,
+                           const ce_params *params, const ce_result *out, ce_counts *counts,
+                           int64_t *row_offsets, int64_t *cluster_offsets, void *workspace,
+                           size_t workspace_bytes, void *stream);
 
 /* Thread-local text of the last error on this thread (never NULL). */
 const char *ce_last_error(void);

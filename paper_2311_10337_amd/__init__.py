@@ -38,8 +38,9 @@ class CeCounts(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int64), ("n_clusters", ctypes.c_int64), ("n_labels", ctypes.c_int64)]
 
 
-_EXPORTS = ["ce_cluster_edges", "ce_workspace_bytes", "ce_max_clusters", "ce_last_error", "ce_timing_enable",
-            "ce_timing_read"]
+_EXPORTS = ["ce_cluster_edges", "ce_cluster_batch", "ce_workspace_bytes", "ce_batch_workspace_bytes",
+            "ce_max_clusters", "ce_last_error", "ce_timing_enable", "ce_timing_read"]
+CE_MAX_GRAPHS = 1 << 24
 _lib = None
 
 
@@ -54,6 +55,14 @@ def load_library(path: str = LIB_PATH):
                                                                  ctypes.POINTER(CeResult), ctypes.POINTER(CeCounts),
                                                                  ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
         lib.ce_cluster_edges.restype = ctypes.c_int
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        lib.ce_cluster_batch.argtypes = [ctypes.c_void_p] * 3 + [i64p, i64p, ctypes.c_int64, ctypes.POINTER(CeParams),
+                                                                 ctypes.POINTER(CeResult), ctypes.POINTER(CeCounts),
+                                                                 i64p, i64p, ctypes.c_void_p, ctypes.c_size_t,
+                                                                 ctypes.c_void_p]
+        lib.ce_cluster_batch.restype = ctypes.c_int
+        lib.ce_batch_workspace_bytes.argtypes = [i64p, i64p, ctypes.c_int64, ctypes.POINTER(CeParams)]
+        lib.ce_batch_workspace_bytes.restype = ctypes.c_size_t
         lib.ce_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(CeParams)]
         lib.ce_workspace_bytes.restype = ctypes.c_size_t
         lib.ce_max_clusters.argtypes = [ctypes.c_int64, ctypes.c_int64]
@@ -103,8 +112,8 @@ def timing_read():
 
 
 class ClusterError(RuntimeError):
-    def __init__(self, status, msg):
-        super().__init__("ce_cluster_edges failed (%d): %s" % (status, msg))
+    def __init__(self, status, msg, call="ce_cluster_edges"):
+        super().__init__("%s failed (%d): %s" % (call, status, msg))
         self.status = status
 
 
@@ -133,15 +142,20 @@ class Result(NamedTuple):
 
 
 class Outputs:
-    """Preallocated device output buffers for n records (reusable across calls)."""
+    """Preallocated device output buffers for n records (reusable across calls).
 
-    def __init__(self, n: int, min_cluster_size: int, device):
+    ``clusters`` overrides the cluster-row capacity (a batch needs the sum of
+    its graphs' ``max_clusters``); ``rows`` overrides the MSF-row capacity.
+    """
+
+    def __init__(self, n: int, min_cluster_size: int, device, clusters: Optional[int] = None,
+                 rows: Optional[int] = None):
         import torch
-        R = max(n - 1, 1)
-        C = max_clusters(n, min_cluster_size)
+        R = rows if rows is not None else max(n - 1, 1)
+        C = clusters if clusters is not None else max_clusters(n, min_cluster_size)
         i32, i64, u8 = torch.int32, torch.int64, torch.uint8
         e = lambda k, dt: torch.empty(max(k, 1), dtype=dt, device=device)
-        self.n, self.C = n, C
+        self.n, self.C, self.R = n, C, R
         self.t = {"msf_tail": e(R, i32), "msf_head": e(R, i32), "msf_w": e(R, i64), "sl_left": e(R, i32),
                   "sl_right": e(R, i32), "sl_w": e(R, i64), "sl_size": e(R, i32), "pt_cluster": e(n, i32),
                   "pt_lambda": e(n, i64), "cl_id": e(C, i32), "cl_parent": e(C, i32), "cl_size": e(C, i32),
@@ -186,6 +200,119 @@ def cluster_edges(src, dst, t, min_cluster_size: int, num_vertices: int, outputs
     cls = {f: o[f][:nc] for f in ("cl_id", "cl_parent", "cl_size", "cl_lambda_birth", "cl_stab_hi", "cl_stab_lo",
                                   "cl_selected")}
     return Result(m=m, n_clusters=nc, n_labels=nl, **rows, **pts, **cls)
+
+
+def _offsets_array(x, name):
+    import numpy as np
+    a = np.ascontiguousarray(np.asarray(x, dtype=np.int64))
+    if a.ndim != 1 or a.size < 2:
+        raise ValueError("%s must be a 1-D array of G+1 offsets" % name)
+    return a
+
+
+def batch_workspace_bytes(edge_offsets, vertex_offsets, min_cluster_size: int) -> int:
+    eo, vo = _offsets_array(edge_offsets, "edge_offsets"), _offsets_array(vertex_offsets, "vertex_offsets")
+    if eo.size != vo.size:
+        raise ValueError("edge_offsets and vertex_offsets must have the same length")
+    p = make_params(min_cluster_size, max(int(vo[-1]), 1))
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    return int(load_library().ce_batch_workspace_bytes(eo.ctypes.data_as(i64p), vo.ctypes.data_as(i64p),
+                                                       eo.size - 1, ctypes.byref(p)))
+
+
+def batch_cluster_capacity(edge_offsets, min_cluster_size: int) -> int:
+    """Cluster rows a batch can produce: the sum of its graphs' max_clusters."""
+    import numpy as np
+    eo = _offsets_array(edge_offsets, "edge_offsets")
+    ng = np.diff(eo)
+    return int((2 * (ng // int(min_cluster_size)) + 1).sum())
+
+
+def batch_outputs(edge_offsets, min_cluster_size: int, device) -> Outputs:
+    eo = _offsets_array(edge_offsets, "edge_offsets")
+    n = int(eo[-1])
+    return Outputs(n, min_cluster_size, device, clusters=batch_cluster_capacity(eo, min_cluster_size),
+                   rows=max(n, 1))
+
+
+class BatchResult(NamedTuple):
+    """Outputs of a batch: the device tensors of one Result laid out graph by
+    graph, plus host arrays of per-graph counts and offsets."""
+    result: Result
+    m: object               # numpy int64[G]
+    n_clusters: object      # numpy int64[G]
+    n_labels: object        # numpy int64[G]
+    edge_offsets: object    # numpy int64[G+1]
+    row_offsets: object     # numpy int64[G+1]
+    cluster_offsets: object  # numpy int64[G+1]
+
+    def graph(self, g: int) -> dict:
+        """Host copy (numpy, documented dtypes) of graph g's outputs, as cluster_edges gives them."""
+        e0, e1 = int(self.edge_offsets[g]), int(self.edge_offsets[g + 1])
+        r0, r1 = int(self.row_offsets[g]), int(self.row_offsets[g + 1])
+        c0, c1 = int(self.cluster_offsets[g]), int(self.cluster_offsets[g + 1])
+        parts = {}
+        for f in Result._fields[3:]:
+            x = getattr(self.result, f)
+            if f.startswith("msf_") or f.startswith("sl_"):
+                parts[f] = x[r0:r1]
+            elif f.startswith("pt_") or f == "labels":
+                parts[f] = x[e0:e1]
+            else:
+                parts[f] = x[c0:c1]
+        return to_numpy(Result(m=int(self.m[g]), n_clusters=int(self.n_clusters[g]), n_labels=int(self.n_labels[g]),
+                               **parts))
+
+
+def cluster_batch(src, dst, t, edge_offsets, vertex_offsets, min_cluster_size: int,
+                  outputs: Optional[Outputs] = None, workspace=None, stream=None) -> BatchResult:
+    """Cluster a batch of independent graphs in one call (``ce_cluster_batch``).
+
+    src/dst/t hold the graphs' records back to back (GPU tensors), vertex ids
+    local to each graph; edge_offsets/vertex_offsets are host arrays of G+1
+    offsets. Each graph's outputs equal a separate ``cluster_edges`` call.
+    """
+    import numpy as np
+    import torch
+    lib = load_library()
+    for name, x, dt in (("src", src, torch.int32), ("dst", dst, torch.int32), ("t", t, torch.int64)):
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == dt and x.is_contiguous() and x.dim() == 1):
+            raise TypeError("%s must be a contiguous 1-D %s GPU tensor" % (name, dt))
+    eo, vo = _offsets_array(edge_offsets, "edge_offsets"), _offsets_array(vertex_offsets, "vertex_offsets")
+    if eo.size != vo.size:
+        raise ValueError("edge_offsets and vertex_offsets must have the same length")
+    G, n = eo.size - 1, int(src.numel())
+    if dst.numel() != n or t.numel() != n or int(eo[-1]) != n:
+        raise ValueError("src, dst, t must have edge_offsets[-1] records")
+    cap = batch_cluster_capacity(eo, min_cluster_size)
+    if outputs is None or outputs.n < n or outputs.C < cap or outputs.R < max(n, 1):
+        outputs = batch_outputs(eo, min_cluster_size, src.device)
+    params = make_params(min_cluster_size, max(int(vo[-1]), 1))
+    counts = (CeCounts * G)()
+    roff = np.zeros(G + 1, dtype=np.int64)
+    coff = np.zeros(G + 1, dtype=np.int64)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    s = stream if stream is not None else torch.cuda.current_stream(src.device)
+    ws_ptr, ws_len = None, 0
+    if workspace is not None:
+        ws_ptr, ws_len = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+    st = lib.ce_cluster_batch(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                              ctypes.c_void_p(t.data_ptr()), eo.ctypes.data_as(i64p), vo.ctypes.data_as(i64p), G,
+                              ctypes.byref(params), ctypes.byref(outputs.struct), counts, roff.ctypes.data_as(i64p),
+                              coff.ctypes.data_as(i64p), ctypes.c_void_p(ws_ptr), ws_len,
+                              ctypes.c_void_p(s.cuda_stream))
+    if st != CE_OK:
+        raise ClusterError(st, last_error(), "ce_cluster_batch")
+    carr = np.ctypeslib.as_array(counts).view(np.int64).reshape(G, 3) if G else np.zeros((0, 3), np.int64)
+    m_tot, c_tot = int(roff[-1]), int(coff[-1])
+    o = outputs.t
+    rows = {f: o[f][:m_tot] for f in ("msf_tail", "msf_head", "msf_w", "sl_left", "sl_right", "sl_w", "sl_size")}
+    pts = {f: o[f][:n] for f in ("pt_cluster", "pt_lambda", "labels")}
+    cls = {f: o[f][:c_tot] for f in ("cl_id", "cl_parent", "cl_size", "cl_lambda_birth", "cl_stab_hi", "cl_stab_lo",
+                                     "cl_selected")}
+    res = Result(m=m_tot, n_clusters=c_tot, n_labels=int(carr[:, 2].sum()), **rows, **pts, **cls)
+    return BatchResult(result=res, m=carr[:, 0].copy(), n_clusters=carr[:, 1].copy(), n_labels=carr[:, 2].copy(),
+                       edge_offsets=eo, row_offsets=roff, cluster_offsets=coff)
 
 
 _UNSIGNED = {"msf_tail": "u4", "msf_head": "u4", "sl_left": "u4", "sl_right": "u4", "sl_size": "u4",

@@ -1,4 +1,11 @@
 // C ABI of libce: argument checks, workspace layout, stage orchestration.
+//
+// One code path serves a single graph and a batch. A batch of G graphs is
+// clustered as the disjoint union of its graphs (vertex ids shifted by each
+// graph's vertex offset). The union's line graph has no edge between two
+// graphs, so its spanning forest, dendrogram rows and clusters split exactly
+// into the per-graph ones; each graph keeps its own virtual root, root rule and
+// label numbering, and outputs are renumbered into each graph's local ids.
 #include <string.h>
 
 #include <mutex>
@@ -46,61 +53,137 @@ namespace {
 
 constexpr int B = 256;
 
+__global__ __launch_bounds__(B) void k_iota32(uint32_t *p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < n; i += (int64_t)gridDim.x * B) p[i] = (uint32_t)i;
+}
+__global__ __launch_bounds__(B) void k_zero32(uint32_t *p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < n; i += (int64_t)gridDim.x * B) p[i] = 0u;
+}
+
+// graph of each MSF row (the graph of its tail record) and rows per graph
+__global__ __launch_bounds__(B) void k_rowg(const uint4 *msf_val, const uint32_t *grank, int64_t m, uint32_t *rowg,
+                                            uint32_t *key, uint32_t *cnt) {
+  for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
+    const uint32_t g = grank[msf_val[j].x];
+    rowg[j] = g;
+    key[j] = g;
+    atomicAdd(&cnt[g], 1u);
+  }
+}
+
+__global__ __launch_bounds__(B) void k_rowpos(const uint32_t *sorted_j, int64_t m, uint32_t *rowpos) {
+  for (int64_t p = (int64_t)blockIdx.x * B + threadIdx.x; p < m; p += (int64_t)gridDim.x * B)
+    rowpos[sorted_j[p]] = (uint32_t)p;
+}
+
 // A record that is a child of row j joins at row j, so it is one of that row's
-// two endpoints: its input id comes from the row itself (no gathers).
+// two endpoints: its input id comes from the row itself (no gathers). Row j is
+// written at its position in the batch, with its graph's local ids.
 __global__ __launch_bounds__(B) void k_rows(const uint64_t *msf_key, const uint4 *msf_val, const uint32_t *kc_u,
-                                            const uint32_t *kc_v, const uint32_t *ksize, int64_t m, int64_t n,
-                                            int idbits, ce_result out) {
+                                            const uint32_t *kc_v, const uint32_t *ksize, const uint32_t *rowg,
+                                            const uint32_t *rowpos, const uint32_t *moff, const int64_t *eoff,
+                                            int64_t m, int64_t n, int idbits, ce_result out) {
   const uint64_t idmask = (uint64_t(1) << idbits) - 1;
   for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
     const uint4 v = msf_val[j];
     const uint64_t key = msf_key[j];
     const int64_t w = (int64_t)(key >> (idbits + 1));
-    const uint32_t tr = v.x, tid = v.z, hid = (uint32_t)((key >> 1) & idmask);
-    if (out.msf_tail) out.msf_tail[j] = tid;
-    if (out.msf_head) out.msf_head[j] = hid;
-    if (out.msf_w) out.msf_w[j] = w;
-    uint32_t a = kc_u[j], b = kc_v[j];
-    uint32_t fa = a < (uint64_t)n ? (a == tr ? tid : hid) : a, fb = b < (uint64_t)n ? (b == tr ? tid : hid) : b;
-    if (out.sl_left) out.sl_left[j] = fa < fb ? fa : fb;
-    if (out.sl_right) out.sl_right[j] = fa < fb ? fb : fa;
-    if (out.sl_w) out.sl_w[j] = w;
-    if (out.sl_size) out.sl_size[j] = ksize[j];
+    const uint32_t g = rowg[j], p = rowpos[j], m0 = moff[g];
+    const uint32_t e0 = (uint32_t)eoff[g], ng = (uint32_t)(eoff[g + 1] - eoff[g]);
+    const uint32_t tr = v.x, tid = v.z - e0, hid = (uint32_t)((key >> 1) & idmask) - e0;
+    if (out.msf_tail) out.msf_tail[p] = tid;
+    if (out.msf_head) out.msf_head[p] = hid;
+    if (out.msf_w) out.msf_w[p] = w;
+    const uint32_t a = kc_u[j], b = kc_v[j];
+    const uint32_t fa = a < (uint64_t)n ? (a == tr ? tid : hid) : ng + (rowpos[a - n] - m0);
+    const uint32_t fb = b < (uint64_t)n ? (b == tr ? tid : hid) : ng + (rowpos[b - n] - m0);
+    if (out.sl_left) out.sl_left[p] = fa < fb ? fa : fb;
+    if (out.sl_right) out.sl_right[p] = fa < fb ? fb : fa;
+    if (out.sl_w) out.sl_w[p] = w;
+    if (out.sl_size) out.sl_size[p] = ksize[j];
   }
 }
 
-// n == 0 or n == 1: no line-graph edges; every record leaves ROOT at lambda 0
-__global__ void k_trivial(int64_t n, ce_result out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  const uint32_t ROOT = (uint32_t)n;  // m = 0
-  for (int64_t p = 0; p < n; p++) {
-    if (out.pt_cluster) out.pt_cluster[p] = ROOT;
-    if (out.pt_lambda) out.pt_lambda[p] = 0;
-    if (out.labels) out.labels[p] = -1;
+// At most one record in the whole batch: there is no line-graph edge, every
+// graph's only cluster is its root (local id n_g, size n_g), and a record
+// leaves its root at lambda 0 as noise.
+__global__ void k_trivial(const int64_t *eoff, int64_t G, ce_result out) {
+  for (int64_t g = threadIdx.x; g < G; g += blockDim.x) {
+    const int64_t ng = eoff[g + 1] - eoff[g];
+    if (ng == 1) {
+      const int64_t id = eoff[g];
+      if (out.pt_cluster) out.pt_cluster[id] = 1;
+      if (out.pt_lambda) out.pt_lambda[id] = 0;
+      if (out.labels) out.labels[id] = -1;
+    }
+    if (out.cl_id) out.cl_id[g] = (uint32_t)ng;
+    if (out.cl_parent) out.cl_parent[g] = NONE32;
+    if (out.cl_size) out.cl_size[g] = (uint32_t)ng;
+    if (out.cl_lambda_birth) out.cl_lambda_birth[g] = 0;
+    if (out.cl_stab_hi) out.cl_stab_hi[g] = 0;
+    if (out.cl_stab_lo) out.cl_stab_lo[g] = 0;
+    if (out.cl_selected) out.cl_selected[g] = 0;
   }
-  if (out.cl_id) out.cl_id[0] = ROOT;
-  if (out.cl_parent) out.cl_parent[0] = NONE32;
-  if (out.cl_size) out.cl_size[0] = (uint32_t)n;
-  if (out.cl_lambda_birth) out.cl_lambda_birth[0] = 0;
-  if (out.cl_stab_hi) out.cl_stab_hi[0] = 0;
-  if (out.cl_stab_lo) out.cl_stab_lo[0] = 0;
-  if (out.cl_selected) out.cl_selected[0] = 0;
 }
 
 }  // namespace
 
+size_t stage_graph_rows_scratch(int64_t n, int64_t G) {
+  Ws w;
+  for (int k = 0; k < 4; k++) w.alloc<uint32_t>(n);
+  w.alloc<uint32_t>(G + 1);
+  return w.off + scan_ws_bytes(G + 1) + radix_ws_bytes(n) + 4096;
+}
+
+// Position of every MSF row in the output: graphs in order, the rows of one
+// graph in ascending key (a stable partition of the sorted MSF by graph).
+ce_status stage_graph_rows(Bufs &b, int64_t m, Ws &ws, hipStream_t s, int64_t *row_offsets) {
+  const int64_t G = b.G;
+  size_t m0 = ws.mark();
+  uint32_t *key = ws.alloc<uint32_t>(m), *val = ws.alloc<uint32_t>(m);
+  uint32_t *key2 = ws.alloc<uint32_t>(m), *val2 = ws.alloc<uint32_t>(m);
+  uint32_t *cnt = ws.alloc<uint32_t>(G + 1);
+  CE_WS_CHECK(ws);
+  CE_LAUNCH(k_zero32, dim3(grid_for(G + 1, B)), dim3(B), 0, s, cnt, G + 1);
+  if (m > 0) CE_LAUNCH(k_rowg, dim3(grid_for(m, B)), dim3(B), 0, s, b.msf_val, b.grank, m, b.rowg, key, cnt);
+  CE_HIP(hipGetLastError());
+  CE_TRY(scan_exclusive_u32(cnt, b.moff, G, ws, s));
+  if (m > 0) {
+    if (G == 1) {
+      CE_LAUNCH(k_iota32, dim3(grid_for(m, B)), dim3(B), 0, s, b.rowpos, m);
+    } else {
+      bool alt = false;
+      CE_TRY((radix_sort_pairs<uint32_t, uint32_t>(key, val, key2, val2, m, 0, bits_for((uint64_t)(G - 1)), true,
+                                                   &alt, ws, s)));
+      CE_LAUNCH(k_rowpos, dim3(grid_for(m, B)), dim3(B), 0, s, alt ? val2 : val, m, b.rowpos);
+    }
+  }
+  CE_HIP(hipGetLastError());
+  if (row_offsets) {
+    std::vector<uint32_t> h(G + 1);
+    CE_HIP(hipMemcpyAsync(h.data(), b.moff, sizeof(uint32_t) * (G + 1), hipMemcpyDeviceToHost, s));
+    CE_HIP(hipStreamSynchronize(s));
+    for (int64_t g = 0; g <= G; g++) row_offsets[g] = h[g];
+  }
+  ws.release(m0);
+  return CE_OK;
+}
+
 ce_status stage_write_rows(Bufs &b, int64_t m, const ce_result *out, hipStream_t s) {
   if (m <= 0) return CE_OK;
-  CE_LAUNCH(k_rows, dim3(grid_for(m, B)), dim3(B), 0, s, b.msf_key, b.msf_val, b.kc_u, b.kc_v, b.ksize, m, b.n,
-            b.idbits, *out);
+  CE_LAUNCH(k_rows, dim3(grid_for(m, B)), dim3(B), 0, s, b.msf_key, b.msf_val, b.kc_u, b.kc_v, b.ksize, b.rowg,
+            b.rowpos, b.moff, b.eoff, m, b.n, b.idbits, *out);
   CE_HIP(hipGetLastError());
   return CE_OK;
 }
 
-static void layout(Bufs &b, Ws &ws, int64_t n, int64_t M) {
+static void layout(Bufs &b, Ws &ws, int64_t n, int64_t M, int64_t G) {
   b.hdr = ws.alloc<uint64_t>(16);
+  b.eoff = ws.alloc<int64_t>(G + 1);
+  b.voff = ws.alloc<int64_t>(G + 1);
   b.ts = ws.alloc<uint64_t>(n);
   b.perm = ws.alloc<uint32_t>(n);
+  b.grank = ws.alloc<uint32_t>(n);
   b.skel_key = ws.alloc<uint64_t>(2 * n);
   b.skel_tail = ws.alloc<uint32_t>(2 * n);
   b.skel_tid = ws.alloc<uint32_t>(2 * n);
@@ -111,6 +194,10 @@ static void layout(Bufs &b, Ws &ws, int64_t n, int64_t M) {
   b.kc_u = ws.alloc<uint32_t>(n);
   b.kc_v = ws.alloc<uint32_t>(n);
   b.ksize = ws.alloc<uint32_t>(n);
+  // the skeleton is dead once the MSF is sorted: the row-placement arrays reuse it
+  b.rowg = b.skel_tail;
+  b.rowpos = b.skel_tail + n;
+  b.moff = ws.alloc<uint32_t>(G + 1);
   size_t sc = stage_sort_skeleton_scratch(n);
   size_t x = stage_boruvka_scratch(n);
   if (x > sc) sc = x;
@@ -118,78 +205,56 @@ static void layout(Bufs &b, Ws &ws, int64_t n, int64_t M) {
   if (x > sc) sc = x;
   x = stage_dendrogram_scratch(n);
   if (x > sc) sc = x;
-  x = stage_condense_scratch(n, M);
+  x = stage_graph_rows_scratch(n, G);
+  if (x > sc) sc = x;
+  x = stage_condense_scratch(n, M, G);
   if (x > sc) sc = x;
   b.scratch = ws.alloc<char>(sc);
   b.scratch_bytes = sc;
 }
 
-static ce_status check_params(int64_t n, const ce_params *p) {
+static size_t workspace_for(int64_t n, int64_t M, int64_t G) {
+  Bufs b;
+  Ws ws;
+  layout(b, ws, n, M, G);
+  return ws.peak;
+}
+
+static ce_status check_params(const ce_params *p) {
   if (!p) { set_error("params is NULL"); return CE_EINVAL; }
   if (p->struct_size < sizeof(ce_params)) { set_error("params.struct_size too small"); return CE_EINVAL; }
   if (p->mode != CE_MODE_UNDIRECTED) { set_error("unknown mode"); return CE_EINVAL; }
   if (p->flags != 0 || p->reserved != 0) { set_error("flags/reserved must be 0"); return CE_EINVAL; }
   if (p->min_cluster_size < 2) { set_error("min_cluster_size must be >= 2"); return CE_EINVAL; }
-  if (p->num_vertices < 1 || p->num_vertices > 0x80000000LL) { set_error("num_vertices must be in [1, 2^31]"); return CE_EINVAL; }
-  if (n < 0 || n > 0x7fffffffLL) { set_error("n must be in [0, 2^31-1]"); return CE_EINVAL; }
   return CE_OK;
 }
 
-}  // namespace ce
-
-using namespace ce;
-
-extern "C" {
-
-int64_t ce_max_clusters(int64_t n, int64_t M) {
-  if (n < 0 || M < 2) return 0;
-  return 2 * (n / M) + 1;
+static ce_status check_offsets(const int64_t *eoff, const int64_t *voff, int64_t G) {
+  if (G < 1 || G > CE_MAX_GRAPHS) { set_error("number of graphs must be in [1, 2^24]"); return CE_EINVAL; }
+  if (!eoff || !voff) { set_error("edge_offsets/vertex_offsets is NULL"); return CE_EINVAL; }
+  if (eoff[0] != 0 || voff[0] != 0) { set_error("offsets must start at 0"); return CE_EINVAL; }
+  for (int64_t g = 0; g < G; g++) {
+    if (eoff[g + 1] < eoff[g]) { set_error("edge_offsets must be non-decreasing"); return CE_EINVAL; }
+    if (voff[g + 1] <= voff[g]) { set_error("every graph needs at least one vertex"); return CE_EINVAL; }
+    if (eoff[g + 1] > 0x7fffffffLL || voff[g + 1] > 0x80000000LL) {
+      set_error("total records must be <= 2^31-1 and total vertices <= 2^31");
+      return CE_EINVAL;
+    }
+  }
+  return CE_OK;
 }
 
-size_t ce_workspace_bytes(int64_t n, int64_t num_vertices, const ce_params *params) {
-  ce_params p;
-  if (params) p = *params;
-  else { memset(&p, 0, sizeof p); p.struct_size = sizeof p; p.min_cluster_size = 2; }
-  p.num_vertices = num_vertices;
-  if (check_params(n, &p) != CE_OK) return 0;
-  Bufs b;
-  Ws ws;
-  layout(b, ws, n, p.min_cluster_size);
-  return ws.peak;
-}
-
-const char *ce_last_error(void) { return g_err.c_str(); }
-
-int ce_timing_enable(const char *kernel_name) {
-  std::lock_guard<std::mutex> l(g_tmu);
-  g_tname = kernel_name ? kernel_name : "";
-  g_tms = 0.0;
-  g_tcount = 0;
-  return 0;
-}
-
-int ce_timing_read(double *total_ms, int64_t *launches) {
-  std::lock_guard<std::mutex> l(g_tmu);
-  if (total_ms) *total_ms = g_tms;
-  if (launches) *launches = g_tcount;
-  return 0;
-}
-
-ce_status ce_cluster_edges(const int32_t *src, const int32_t *dst, const int64_t *t, int64_t n, const ce_params *params,
-                           const ce_result *out, ce_counts *counts, void *workspace, size_t workspace_bytes,
-                           void *stream) {
-  CE_TRY(check_params(n, params));
-  if (!out || !counts) { set_error("out/counts is NULL"); return CE_EINVAL; }
+// Runs a checked batch; eoff/voff are host arrays of G+1 offsets.
+static ce_status run_batch(const int32_t *src, const int32_t *dst, const int64_t *t, const int64_t *eoff,
+                           const int64_t *voff, int64_t G, int64_t M, const ce_result *out, ce_counts *counts,
+                           int64_t *row_offsets, int64_t *cluster_offsets, void *workspace, size_t workspace_bytes,
+                           hipStream_t s) {
+  const int64_t n = eoff[G], V = voff[G];
+  for (int64_t g = 0; g < G; g++) counts[g] = ce_counts{0, 1, 0};
   if (n > 0 && (!src || !dst || !t)) { set_error("input pointer is NULL"); return CE_EINVAL; }
-  hipStream_t s = (hipStream_t)stream;
-  const int64_t M = params->min_cluster_size, V = params->num_vertices;
-  counts->m = 0;
-  counts->n_clusters = 1;
-  counts->n_labels = 0;
-  const size_t need = ce_workspace_bytes(n, V, params);
+  const size_t need = workspace_for(n, M, G);
   void *base = workspace;
-  bool own = false;
-  bool async_alloc = true;
+  bool own = false, async_alloc = true;
   if (!base) {
     if (hipMallocAsync(&base, need, s) != hipSuccess) {
       (void)hipGetLastError();
@@ -215,20 +280,29 @@ ce_status ce_cluster_edges(const int32_t *src, const int32_t *dst, const int64_t
   ws.base = (char *)base;
   ws.cap = need;
   Bufs b;
-  layout(b, ws, n, M);
+  layout(b, ws, n, M, G);
   CE_WS_CHECK(ws);
   b.n = n;
   b.V = V;
   b.M = M;
+  b.G = G;
+  CE_HIP(hipMemcpyAsync((void *)b.eoff, eoff, sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, s));
+  CE_HIP(hipMemcpyAsync((void *)b.voff, voff, sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, s));
   uint64_t flags = 0;
   int64_t tmin = 0, tmax = 0;
-  CE_TRY(stage_validate(src, dst, t, b, s, &flags, &tmin, &tmax));
-  if (flags & 1) { set_error("self loop in input (src == dst)"); return CE_ESELFLOOP; }
-  if (flags & 2) { set_error("vertex id outside [0, num_vertices)"); return CE_ERANGE; }
+  if (n > 0) {
+    CE_TRY(stage_validate(src, dst, t, b, s, &flags, &tmin, &tmax));
+    if (flags & 1) { set_error("self loop in input (src == dst)"); return CE_ESELFLOOP; }
+    if (flags & 2) { set_error("vertex id outside [0, num_vertices) of its graph"); return CE_ERANGE; }
+  }
   if (n <= 1) {
-    CE_LAUNCH(k_trivial, dim3(1), dim3(64), 0, s, n, *out);
+    CE_LAUNCH(k_trivial, dim3(1), dim3(256), 0, s, b.eoff, G, *out);
     CE_HIP(hipGetLastError());
     CE_HIP(hipStreamSynchronize(s));
+    for (int64_t g = 0; g <= G; g++) {
+      if (row_offsets) row_offsets[g] = 0;
+      if (cluster_offsets) cluster_offsets[g] = g;
+    }
     return CE_OK;
   }
   const uint64_t span = (uint64_t)tmax - (uint64_t)tmin;
@@ -245,16 +319,92 @@ ce_status ce_cluster_edges(const int32_t *src, const int32_t *dst, const int64_t
   sw.base = b.scratch;
   sw.cap = b.scratch_bytes;
   int64_t m = 0;
+  std::vector<int64_t> roff(G + 1);
   CE_TRY(stage_sort_skeleton(src, dst, t, b, sw, s));
   CE_TRY(stage_boruvka(b, sw, s));
   CE_TRY(stage_msf_sort(b, sw, s, &m));
   CE_TRY(stage_dendrogram(b, m, sw, s));
+  CE_TRY(stage_graph_rows(b, m, sw, s, roff.data()));
   CE_TRY(stage_write_rows(b, m, out, s));
-  CE_TRY(stage_condense(b, m, out, sw, s, counts));
-  counts->m = m;
+  CE_TRY(stage_condense(b, m, out, sw, s, counts, cluster_offsets));
+  for (int64_t g = 0; g < G; g++) counts[g].m = roff[g + 1] - roff[g];
+  if (row_offsets)
+    for (int64_t g = 0; g <= G; g++) row_offsets[g] = roff[g];
   CE_HIP(hipStreamSynchronize(s));
   timing_collect();
   return CE_OK;
+}
+
+}  // namespace ce
+
+using namespace ce;
+
+extern "C" {
+
+int64_t ce_max_clusters(int64_t n, int64_t M) {
+  if (n < 0 || M < 2) return 0;
+  return 2 * (n / M) + 1;
+}
+
+size_t ce_workspace_bytes(int64_t n, int64_t num_vertices, const ce_params *params) {
+  ce_params p;
+  if (params) p = *params;
+  else { memset(&p, 0, sizeof p); p.struct_size = sizeof p; p.min_cluster_size = 2; }
+  if (check_params(&p) != CE_OK) return 0;
+  if (n < 0 || n > 0x7fffffffLL || num_vertices < 1 || num_vertices > 0x80000000LL) return 0;
+  return workspace_for(n, p.min_cluster_size, 1);
+}
+
+size_t ce_batch_workspace_bytes(const int64_t *edge_offsets, const int64_t *vertex_offsets, int64_t num_graphs,
+                                const ce_params *params) {
+  if (check_params(params) != CE_OK || check_offsets(edge_offsets, vertex_offsets, num_graphs) != CE_OK) return 0;
+  return workspace_for(edge_offsets[num_graphs], params->min_cluster_size, num_graphs);
+}
+
+const char *ce_last_error(void) { return g_err.c_str(); }
+
+int ce_timing_enable(const char *kernel_name) {
+  std::lock_guard<std::mutex> l(g_tmu);
+  g_tname = kernel_name ? kernel_name : "";
+  g_tms = 0.0;
+  g_tcount = 0;
+  return 0;
+}
+
+int ce_timing_read(double *total_ms, int64_t *launches) {
+  std::lock_guard<std::mutex> l(g_tmu);
+  if (total_ms) *total_ms = g_tms;
+  if (launches) *launches = g_tcount;
+  return 0;
+}
+
+ce_status ce_cluster_edges(const int32_t *src, const int32_t *dst, const int64_t *t, int64_t n, const ce_params *params,
+                           const ce_result *out, ce_counts *counts, void *workspace, size_t workspace_bytes,
+                           void *stream) {
+  CE_TRY(check_params(params));
+  if (!out || !counts) { set_error("out/counts is NULL"); return CE_EINVAL; }
+  if (params->num_vertices < 1 || params->num_vertices > 0x80000000LL) {
+    set_error("num_vertices must be in [1, 2^31]");
+    return CE_EINVAL;
+  }
+  if (n < 0 || n > 0x7fffffffLL) { set_error("n must be in [0, 2^31-1]"); return CE_EINVAL; }
+  const int64_t eoff[2] = {0, n}, voff[2] = {0, params->num_vertices};
+  return run_batch(src, dst, t, eoff, voff, 1, params->min_cluster_size, out, counts, nullptr, nullptr, workspace,
+                   workspace_bytes, (hipStream_t)stream);
+}
+
+ce_status ce_cluster_batch(const int32_t *src, const int32_t *dst, const int64_t *t, const int64_t *edge_offsets,
+                           const int64_t *vertex_offsets, int64_t num_graphs, const ce_params *params,
+                           const ce_result *out, ce_counts *counts, int64_t *row_offsets, int64_t *cluster_offsets,
+                           void *workspace, size_t workspace_bytes, void *stream) {
+  CE_TRY(check_params(params));
+  if (!out || !counts || !row_offsets || !cluster_offsets) {
+    set_error("out/counts/row_offsets/cluster_offsets is NULL");
+    return CE_EINVAL;
+  }
+  CE_TRY(check_offsets(edge_offsets, vertex_offsets, num_graphs));
+  return run_batch(src, dst, t, edge_offsets, vertex_offsets, num_graphs, params->min_cluster_size, out, counts,
+                   row_offsets, cluster_offsets, workspace, workspace_bytes, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -138,6 +138,16 @@ __host__ __device__ inline u128 u128_mul64(uint64_t a, uint64_t b) {
   return r;
 }
 
+// graph g with eoff[g] <= i < eoff[g+1] (eoff non-decreasing, G >= 1)
+__host__ __device__ inline uint32_t graph_of(const int64_t *eoff, int64_t G, int64_t i) {
+  int64_t lo = 0, hi = G - 1;
+  while (lo < hi) {
+    int64_t mid = (lo + hi + 1) >> 1;
+    if (eoff[mid] <= i) lo = mid; else hi = mid - 1;
+  }
+  return (uint32_t)lo;
+}
+
 // lambda(w) = floor(2^63 / max(2w, 1)) for w >= 0
 __host__ __device__ inline uint64_t lambda_of(int64_t w) {
   return w <= 0 ? (uint64_t(1) << 63) : ((uint64_t(1) << 63) / (2 * (uint64_t)w));
@@ -255,6 +265,14 @@ namespace ce {
 // r-th record by time; perm[r] is its input id.
 struct Bufs {
   int64_t n = 0, V = 0, M = 0;
+  // batch of G independent graphs packed as a disjoint union: graph g owns
+  // records [eoff[g], eoff[g+1]) and vertices [voff[g], voff[g+1]) (device copies)
+  int64_t G = 1;
+  const int64_t *eoff = nullptr, *voff = nullptr;
+  uint32_t *grank = nullptr;    // [n] graph of each record, by rank
+  uint32_t *rowg = nullptr;     // [n] graph of each MSF row (aliases the dead skeleton tails)
+  uint32_t *rowpos = nullptr;   // [n] output position of each MSF row (graphs in order, rows in key order)
+  uint32_t *moff = nullptr;     // [G+1] first output row of each graph
   int tbits = 0, idbits = 0, vbits = 0, keybits = 0;
   int64_t tmin = 0;
   // persistent
@@ -285,13 +303,16 @@ ce_status stage_sort_skeleton(const int32_t *src, const int32_t *dst, const int6
 ce_status stage_boruvka(Bufs &b, Ws &ws, hipStream_t s);
 ce_status stage_msf_sort(Bufs &b, Ws &ws, hipStream_t s, int64_t *m_out);
 ce_status stage_dendrogram(Bufs &b, int64_t m, Ws &ws, hipStream_t s);
-ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipStream_t s, ce_counts *counts);
+ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipStream_t s, ce_counts *counts,
+                         int64_t *cluster_offsets);
+ce_status stage_graph_rows(Bufs &b, int64_t m, Ws &ws, hipStream_t s, int64_t *row_offsets);
+size_t stage_graph_rows_scratch(int64_t n, int64_t G);
 ce_status stage_write_rows(Bufs &b, int64_t m, const ce_result *out, hipStream_t s);
 
 size_t stage_sort_skeleton_scratch(int64_t n);
 size_t stage_boruvka_scratch(int64_t n);
 size_t stage_msf_sort_scratch(int64_t n);
 size_t stage_dendrogram_scratch(int64_t n);
-size_t stage_condense_scratch(int64_t n, int64_t M);
+size_t stage_condense_scratch(int64_t n, int64_t M, int64_t G);
 
 }  // namespace ce

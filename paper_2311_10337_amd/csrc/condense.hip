@@ -5,8 +5,11 @@
 // Node space: records are ranks [0,n), row j of the sorted MSF is node n+j,
 // the virtual root is n+m. A node is "big" if its size >= M.
 //  - birth nodes: both children of a row whose two children are big; and the
-//    big component roots when there are at least two of them. A cluster is
-//    identified by its birth node.
+//    big component roots of a graph when it has at least two of them. A
+//    cluster is identified by its birth node.
+//  - batches: every graph g of a packed batch has its own virtual root, node
+//    n+m+g; cluster rows are laid out graph by graph (births in node order,
+//    then the graph's root), and labels are numbered per graph.
 //  - the cluster of a big node is its nearest birth ancestor-or-self, found by
 //    pointer jumping over big nodes (chains can be as deep as the data).
 //  - a record leaves the cluster of its lowest big ancestor y, at lambda(w_y);
@@ -15,6 +18,8 @@
 //  - excess of mass is a tree DP; chains are contracted by composing
 //    f(x) = max(a, x + b) (pointer jumping), leaves are raked each round.
 //  - the highest selected cluster above each cluster is again pointer jumping.
+#include <vector>
+
 #include "ce_internal.h"
 
 namespace ce {
@@ -46,16 +51,17 @@ __global__ __launch_bounds__(B) void k_cd_parents(const uint32_t *kc_u, const ui
   }
 }
 
-__global__ __launch_bounds__(B) void k_cd_bigroots(const uint32_t *kpar, const uint32_t *ksize, int64_t m, int64_t n,
-                                                   int64_t M, unsigned long long *cnt) {
+// big component roots per graph
+__global__ __launch_bounds__(B) void k_cd_bigroots(const uint32_t *kpar, const uint32_t *ksize, const uint32_t *rowg,
+                                                   int64_t m, int64_t n, int64_t M, uint32_t *nbig) {
   for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B)
-    if (kpar[n + j] == NONE32 && ksize[j] >= (uint64_t)M) atomicAdd(cnt, 1ull);
+    if (kpar[n + j] == NONE32 && ksize[j] >= (uint64_t)M) atomicAdd(&nbig[rowg[j]], 1u);
 }
 
 __global__ __launch_bounds__(B) void k_cd_birth(const uint32_t *kc_u, const uint32_t *kc_v, const uint32_t *ksize,
                                                 const uint32_t *kpar, const uint64_t *msf_key, int idbits, int64_t m,
-                                                int64_t n, int64_t M, uint64_t nbig, uint8_t *isbirth,
-                                                uint64_t *birthL) {
+                                                int64_t n, int64_t M, const uint32_t *nbig, const uint32_t *rowg,
+                                                uint8_t *isbirth, uint64_t *birthL) {
   for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
     uint32_t a = kc_u[j], b = kc_v[j];
     if (node_size(a, n, ksize) >= (uint64_t)M && node_size(b, n, ksize) >= (uint64_t)M) {
@@ -65,23 +71,23 @@ __global__ __launch_bounds__(B) void k_cd_birth(const uint32_t *kc_u, const uint
       isbirth[b - n] = 1;
       birthL[b - n] = L;
     }
-    if (kpar[n + j] == NONE32 && ksize[j] >= (uint64_t)M && nbig >= 2) {
+    if (kpar[n + j] == NONE32 && ksize[j] >= (uint64_t)M && nbig[rowg[j]] >= 2) {
       isbirth[j] = 1;
       birthL[j] = 0;
     }
   }
 }
 
+// a virtual root (n+m+g) or a birth node ends the jump
 __device__ inline bool j_terminal(uint32_t x, int64_t n, int64_t m, const uint8_t *isbirth) {
-  return x == (uint32_t)(n + m) || isbirth[x - n];
+  return x >= (uint64_t)(n + m) || isbirth[x - n];
 }
 
 // J[j] for big rows: self if birth, ROOT if a root, else the parent node.
 // Rows whose J is not yet a birth node or ROOT go to the active list.
 __global__ __launch_bounds__(B) void k_cd_jinit(const uint8_t *isbirth, const uint32_t *kpar, const uint32_t *ksize,
-                                                int64_t m, int64_t n, int64_t M, uint32_t *J, uint32_t *act,
-                                                unsigned long long *nact) {
-  const uint32_t ROOT = (uint32_t)(n + m);
+                                                const uint32_t *rowg, int64_t m, int64_t n, int64_t M, uint32_t *J,
+                                                uint32_t *act, unsigned long long *nact) {
   bool keep[CT];
   uint32_t vals[CT];
   const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
@@ -94,7 +100,7 @@ __global__ __launch_bounds__(B) void k_cd_jinit(const uint8_t *isbirth, const ui
     uint32_t v = NONE32;
     if (ksize[j] >= (uint64_t)M) {
       if (isbirth[j]) v = (uint32_t)(n + j);
-      else if (kpar[n + j] == NONE32) v = ROOT;
+      else if (kpar[n + j] == NONE32) v = (uint32_t)(n + m + rowg[j]);
       else {
         v = kpar[n + j];
         keep[k] = !j_terminal(v, n, m, isbirth);
@@ -131,14 +137,13 @@ __global__ __launch_bounds__(B) void k_cd_jstep(const uint32_t *act, int64_t nac
 
 // exit of each record: lowest big ancestor y -> (cluster of y, lambda(w_y))
 __global__ __launch_bounds__(B) void k_cd_exit(const uint32_t *kpar, const uint32_t *ksize, const uint32_t *J,
-                                               const uint64_t *msf_key, int idbits, int64_t m, int64_t n, int64_t M,
-                                               uint32_t *exc, uint64_t *exl) {
-  const uint32_t ROOT = (uint32_t)(n + m);
+                                               const uint64_t *msf_key, const uint32_t *grank, int idbits, int64_t m,
+                                               int64_t n, int64_t M, uint32_t *exc, uint64_t *exl) {
   for (int64_t p = (int64_t)blockIdx.x * B + threadIdx.x; p < n; p += (int64_t)gridDim.x * B) {
     uint32_t y = kpar[p];
     while (y != NONE32 && ksize[y - n] < (uint64_t)M) y = kpar[y];
     if (y == NONE32) {
-      exc[p] = ROOT;
+      exc[p] = (uint32_t)(n + m + grank[p]);
       exl[p] = 0;
     } else {
       exc[p] = J[y - n];
@@ -180,20 +185,28 @@ __global__ __launch_bounds__(B) void k_cd_exit_down(const uint32_t *kc_u, const 
   }
 }
 
+// default exit: the record's graph root at lambda 0
+__global__ __launch_bounds__(B) void k_exit_default(const uint32_t *grank, int64_t n, int64_t m, uint32_t *exc,
+                                                    uint64_t *exl) {
+  for (int64_t p = (int64_t)blockIdx.x * B + threadIdx.x; p < n; p += (int64_t)gridDim.x * B) {
+    exc[p] = (uint32_t)(n + m + grank[p]);
+    exl[p] = 0;
+  }
+}
+
 __global__ __launch_bounds__(B) void k_u8_to_u32(const uint8_t *a, int64_t n, uint32_t *o) {
   for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < n; i += (int64_t)gridDim.x * B) o[i] = a[i];
 }
 
-__device__ inline uint32_t row_of(uint32_t c, int64_t n, int64_t m, const uint32_t *rowof, uint32_t nbirth) {
-  return c == (uint32_t)(n + m) ? nbirth : rowof[c - n];
+__device__ inline uint32_t row_of(uint32_t c, int64_t n, int64_t m, const uint32_t *rowof, const uint32_t *rootrow) {
+  return c >= (uint64_t)(n + m) ? rootrow[c - n - m] : rowof[c - n];
 }
 
 // cluster rows: node, size, birth lambda, parent row
-__global__ __launch_bounds__(B) void k_cd_rows(const uint8_t *isbirth, const uint32_t *rowof, const uint32_t *ksize,
-                                               const uint64_t *birthL, const uint32_t *kpar, const uint32_t *J,
-                                               int64_t m, int64_t n, uint32_t nbirth, uint32_t *cnode,
-                                               uint32_t *csize, uint64_t *cbirth, uint32_t *cprow) {
-  const uint32_t ROOT = (uint32_t)(n + m);
+__global__ __launch_bounds__(B) void k_cd_rows(const uint8_t *isbirth, const uint32_t *rowof, const uint32_t *rootrow,
+                                               const uint32_t *ksize, const uint64_t *birthL, const uint32_t *kpar,
+                                               const uint32_t *J, const uint32_t *rowg, int64_t m, int64_t n,
+                                               uint32_t *cnode, uint32_t *csize, uint64_t *cbirth, uint32_t *cprow) {
   for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
     if (!isbirth[j]) continue;
     uint32_t r = rowof[j];
@@ -201,15 +214,45 @@ __global__ __launch_bounds__(B) void k_cd_rows(const uint8_t *isbirth, const uin
     csize[r] = ksize[j];
     cbirth[r] = birthL[j];
     uint32_t par = kpar[n + j];
-    uint32_t pc = par == NONE32 ? ROOT : J[par - n];
-    cprow[r] = row_of(pc, n, m, rowof, nbirth);
+    uint32_t pc = par == NONE32 ? (uint32_t)(n + m + rowg[j]) : J[par - n];
+    cprow[r] = row_of(pc, n, m, rowof, rootrow);
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    cnode[nbirth] = ROOT;
-    csize[nbirth] = (uint32_t)n;
-    cbirth[nbirth] = 0;
-    cprow[nbirth] = NONE32;
+}
+
+// one root row per graph: size = the graph's records, born at lambda 0, no parent
+__global__ __launch_bounds__(B) void k_cd_rootrows(const uint32_t *rootrow, const int64_t *eoff, int64_t G, int64_t m,
+                                                   int64_t n, uint32_t *cnode, uint32_t *csize, uint64_t *cbirth,
+                                                   uint32_t *cprow) {
+  for (int64_t g = (int64_t)blockIdx.x * B + threadIdx.x; g < G; g += (int64_t)gridDim.x * B) {
+    const uint32_t r = rootrow[g];
+    cnode[r] = (uint32_t)(n + m + g);
+    csize[r] = (uint32_t)(eoff[g + 1] - eoff[g]);
+    cbirth[r] = 0;
+    cprow[r] = NONE32;
   }
+}
+
+// births in (graph, node) order: position p gives row p + g (each earlier graph adds its root row)
+__global__ __launch_bounds__(B) void k_birth_list(const uint8_t *isbirth, const uint32_t *idx, const uint32_t *rowg,
+                                                  int64_t m, uint32_t *bkey, uint32_t *bval, uint32_t *bcnt) {
+  for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
+    if (!isbirth[j]) continue;
+    const uint32_t i = idx[j], g = rowg[j];
+    bkey[i] = g;
+    bval[i] = (uint32_t)j;
+    atomicAdd(&bcnt[g], 1u);
+  }
+}
+__global__ __launch_bounds__(B) void k_birth_rows(const uint32_t *sorted_j, const uint32_t *rowg, int64_t nb,
+                                                  uint32_t *rowof) {
+  for (int64_t p = (int64_t)blockIdx.x * B + threadIdx.x; p < nb; p += (int64_t)gridDim.x * B) {
+    const uint32_t j = sorted_j[p];
+    rowof[j] = (uint32_t)p + rowg[j];
+  }
+}
+__global__ __launch_bounds__(B) void k_root_rows(const uint32_t *bstart, int64_t G, uint32_t *rootrow) {
+  for (int64_t g = (int64_t)blockIdx.x * B + threadIdx.x; g < G; g += (int64_t)gridDim.x * B)
+    rootrow[g] = bstart[g + 1] + (uint32_t)g;
 }
 
 __device__ inline uint64_t wave_sum64(uint64_t v) {
@@ -242,7 +285,7 @@ __device__ inline void wave_add_limbs(bool active, uint32_t row, uint64_t l0, ui
 // row that finds no free slot adds directly.
 constexpr int AHS = 512;
 __global__ __launch_bounds__(B) void k_cd_acc_points(const uint32_t *exc, const uint64_t *exl, const uint32_t *rowof,
-                                                     int64_t m, int64_t n, uint32_t nbirth,
+                                                     int64_t m, int64_t n, const uint32_t *rootrow,
                                                      unsigned long long *acc) {
   __shared__ uint32_t hk[AHS];
   __shared__ unsigned long long h0[AHS], h1[AHS];
@@ -255,7 +298,7 @@ __global__ __launch_bounds__(B) void k_cd_acc_points(const uint32_t *exc, const 
     uint32_t r = 0;
     if (p < n) {
       L = exl[p];
-      if (L) r = row_of(exc[p], n, m, rowof, nbirth);
+      if (L) r = row_of(exc[p], n, m, rowof, rootrow);
     }
     uint64_t s0 = L & 0xffffffffull, s1 = L >> 32;
     const bool upd = wave_combine_first(L != 0, r, [&](bool mine, int leader) {
@@ -318,11 +361,11 @@ __global__ __launch_bounds__(B) void k_cd_stab(const unsigned long long *acc, co
   }
 }
 
-__global__ __launch_bounds__(B) void k_cd_children(const uint32_t *cprow, uint32_t nrows, uint32_t rootrow,
-                                                   uint32_t *nch, uint32_t *ch) {
+// root rows are the rows without a parent
+__global__ __launch_bounds__(B) void k_cd_children(const uint32_t *cprow, uint32_t nrows, uint32_t *nch, uint32_t *ch) {
   for (int64_t r = (int64_t)blockIdx.x * B + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * B) {
     uint32_t p = cprow[r];
-    if (p == NONE32 || p == rootrow) continue;
+    if (p == NONE32 || cprow[p] == NONE32) continue;
     uint32_t k = atomicAdd(&nch[p], 1u);
     if (k < 2) ch[2 * (uint64_t)p + k] = (uint32_t)r;
   }
@@ -347,7 +390,7 @@ __device__ inline void eom_store(const Eom &o, uint32_t r, uint8_t st, u128 v, u
 }
 
 __global__ __launch_bounds__(B) void k_eom_init(const uint32_t *nch, const uint64_t *shi, const uint64_t *slo,
-                                                uint32_t nrows, uint32_t rootrow, Eom e0, Eom e1, uint32_t *act,
+                                                const uint32_t *cprow, uint32_t nrows, Eom e0, Eom e1, uint32_t *act,
                                                 unsigned long long *nact) {
   bool keep[CT];
   uint32_t vals[CT];
@@ -358,7 +401,7 @@ __global__ __launch_bounds__(B) void k_eom_init(const uint32_t *nch, const uint6
     keep[k] = false;
     vals[k] = (uint32_t)r;
     if (r >= nrows) continue;
-    bool leaf = nch[r] == 0 || r == rootrow;
+    bool leaf = nch[r] == 0 || cprow[r] == NONE32;
     u128 S{slo[r], shi[r]}, z{0, 0};
     eom_store(e0, (uint32_t)r, leaf ? 2 : 0, S, z, z, NONE32);
     eom_store(e1, (uint32_t)r, leaf ? 2 : 0, S, z, z, NONE32);
@@ -425,9 +468,9 @@ __global__ __launch_bounds__(B) void k_eom_round(const uint32_t *act, int64_t na
 
 // selection with ties kept by the parent; ROOT never selected
 __global__ __launch_bounds__(B) void k_eom_select(const uint32_t *nch, const uint32_t *ch, Eom e, const uint64_t *shi,
-                                                  const uint64_t *slo, uint32_t nrows, uint32_t rootrow,
-                                                  uint32_t *top, uint32_t *nxt, uint32_t *top2, uint32_t *nxt2,
-                                                  const uint32_t *cprow, uint32_t *act, unsigned long long *nact) {
+                                                  const uint64_t *slo, uint32_t nrows, uint32_t *top, uint32_t *nxt,
+                                                  uint32_t *top2, uint32_t *nxt2, const uint32_t *cprow, uint32_t *act,
+                                                  unsigned long long *nact) {
   bool keep[CT];
   uint32_t vals[CT];
   const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
@@ -438,7 +481,7 @@ __global__ __launch_bounds__(B) void k_eom_select(const uint32_t *nch, const uin
     vals[k] = (uint32_t)r;
     if (r >= nrows) continue;
     bool sel;
-    if (r == rootrow) sel = false;
+    if (cprow[r] == NONE32) sel = false;
     else if (nch[r] == 0) sel = true;
     else {
       uint32_t c1 = ch[2 * r], c2 = ch[2 * r + 1];
@@ -447,7 +490,7 @@ __global__ __launch_bounds__(B) void k_eom_select(const uint32_t *nch, const uin
     }
     uint32_t t = sel ? (uint32_t)r : NONE32;
     uint32_t p = cprow[r];
-    uint32_t nx = (p == NONE32 || p == rootrow) ? NONE32 : p;
+    uint32_t nx = (p == NONE32 || cprow[p] == NONE32) ? NONE32 : p;
     top[r] = t; top2[r] = t;
     nxt[r] = nx; nxt2[r] = nx;
     keep[k] = nx != NONE32;
@@ -486,12 +529,12 @@ __global__ __launch_bounds__(B) void k_top_jump(const uint32_t *act, int64_t nac
   tile_append(keep, vals, next, nnext);
 }
 
-__global__ __launch_bounds__(B) void k_lab_rows(const uint32_t *exc, const uint32_t *rowof, const uint32_t *top,
-                                                const uint32_t *perm, int64_t m, int64_t n, uint32_t nbirth,
-                                                uint32_t *labrow, uint32_t *minmem) {
+__global__ __launch_bounds__(B) void k_lab_rows(const uint32_t *exc, const uint32_t *rowof, const uint32_t *rootrow,
+                                                const uint32_t *top, const uint32_t *cprow, const uint32_t *perm,
+                                                int64_t m, int64_t n, uint32_t *labrow, uint32_t *minmem) {
   for (int64_t p = (int64_t)blockIdx.x * B + threadIdx.x; p < n; p += (int64_t)gridDim.x * B) {
-    uint32_t r = row_of(exc[p], n, m, rowof, nbirth);
-    uint32_t lr = r == nbirth ? NONE32 : top[r];
+    uint32_t r = row_of(exc[p], n, m, rowof, rootrow);
+    uint32_t lr = cprow[r] == NONE32 ? NONE32 : top[r];
     labrow[p] = lr;
     if (lr != NONE32) atomicMin(&minmem[lr], perm[p]);
   }
@@ -503,17 +546,27 @@ __global__ __launch_bounds__(B) void k_lab_flags(const uint32_t *top, const uint
     if (top[r] == (uint32_t)r && minmem[r] != NONE32) flag[minmem[r]] = 1;
 }
 
-__global__ __launch_bounds__(B) void k_out_points(const uint32_t *perm, const uint32_t *exc, const uint64_t *exl,
-                                                  const uint32_t *labrow, const uint32_t *minmem,
-                                                  const uint32_t *fscan, int64_t n, uint32_t *pt_cluster,
+// node id inside its own graph: records keep their local ids; row j of graph g
+// is node n_g + (its index among g's rows); the root of g is n_g + m_g
+__device__ inline uint32_t local_node(uint32_t x, uint32_t g, int64_t n, int64_t m, const int64_t *eoff,
+                                      const uint32_t *moff, const uint32_t *rowpos) {
+  const uint32_t ng = (uint32_t)(eoff[g + 1] - eoff[g]);
+  if (x >= (uint64_t)(n + m)) return ng + (moff[g + 1] - moff[g]);
+  return ng + (rowpos[x - n] - moff[g]);
+}
+
+__global__ __launch_bounds__(B) void k_out_points(const uint32_t *perm, const uint32_t *grank, const uint32_t *exc,
+                                                  const uint64_t *exl, const uint32_t *labrow, const uint32_t *minmem,
+                                                  const uint32_t *fscan, const int64_t *eoff, const uint32_t *moff,
+                                                  const uint32_t *rowpos, int64_t n, int64_t m, uint32_t *pt_cluster,
                                                   uint64_t *pt_lambda, int32_t *labels) {
   for (int64_t p = (int64_t)blockIdx.x * B + threadIdx.x; p < n; p += (int64_t)gridDim.x * B) {
-    uint32_t id = perm[p];
-    if (pt_cluster) pt_cluster[id] = exc[p];
+    const uint32_t id = perm[p], g = grank[p];
+    if (pt_cluster) pt_cluster[id] = local_node(exc[p], g, n, m, eoff, moff, rowpos);
     if (pt_lambda) pt_lambda[id] = exl[p];
     if (labels) {
       uint32_t lr = labrow[p];
-      labels[id] = lr == NONE32 ? -1 : (int32_t)fscan[minmem[lr]];
+      labels[id] = lr == NONE32 ? -1 : (int32_t)(fscan[minmem[lr]] - fscan[eoff[g]]);
     }
   }
 }
@@ -521,29 +574,45 @@ __global__ __launch_bounds__(B) void k_out_points(const uint32_t *perm, const ui
 __global__ __launch_bounds__(B) void k_out_clusters(const uint32_t *cnode, const uint32_t *cprow,
                                                     const uint32_t *csize, const uint64_t *cbirth,
                                                     const uint64_t *shi, const uint64_t *slo, const uint32_t *top,
-                                                    uint32_t nrows, uint32_t rootrow, ce_result out) {
+                                                    const uint32_t *rowg, const int64_t *eoff, const uint32_t *moff,
+                                                    const uint32_t *rowpos, int64_t n, int64_t m, uint32_t nrows,
+                                                    ce_result out) {
   for (int64_t r = (int64_t)blockIdx.x * B + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * B) {
-    if (out.cl_id) out.cl_id[r] = cnode[r];
-    if (out.cl_parent) out.cl_parent[r] = cprow[r] == NONE32 ? NONE32 : cnode[cprow[r]];
+    const uint32_t c = cnode[r];
+    const uint32_t g = c >= (uint64_t)(n + m) ? (uint32_t)(c - n - m) : rowg[c - n];
+    if (out.cl_id) out.cl_id[r] = local_node(c, g, n, m, eoff, moff, rowpos);
+    if (out.cl_parent)
+      out.cl_parent[r] = cprow[r] == NONE32 ? NONE32 : local_node(cnode[cprow[r]], g, n, m, eoff, moff, rowpos);
     if (out.cl_size) out.cl_size[r] = csize[r];
     if (out.cl_lambda_birth) out.cl_lambda_birth[r] = cbirth[r];
     if (out.cl_stab_hi) out.cl_stab_hi[r] = shi[r];
     if (out.cl_stab_lo) out.cl_stab_lo[r] = slo[r];
-    if (out.cl_selected) out.cl_selected[r] = (r != rootrow && top[r] == (uint32_t)r) ? 1 : 0;
+    if (out.cl_selected) out.cl_selected[r] = (cprow[r] != NONE32 && top[r] == (uint32_t)r) ? 1 : 0;
   }
+}
+
+// labels per graph: the chosen clusters whose minimum member lies in g
+__global__ __launch_bounds__(B) void k_graph_labels(const uint32_t *fscan, const int64_t *eoff, int64_t G,
+                                                    uint32_t *nl) {
+  for (int64_t g = (int64_t)blockIdx.x * B + threadIdx.x; g < G; g += (int64_t)gridDim.x * B)
+    nl[g] = fscan[eoff[g + 1]] - fscan[eoff[g]];
 }
 
 }  // namespace
 
-size_t stage_condense_scratch(int64_t n, int64_t M) {
-  // n rows bound m; rows bound 2n/M + 1
-  int64_t m = n, R = 2 * (n / (M < 2 ? 2 : M)) + 2;
+static int64_t cluster_row_bound(int64_t n, int64_t M, int64_t G) { return 2 * (n / M) + G + 1; }
+
+size_t stage_condense_scratch(int64_t n, int64_t M, int64_t G) {
+  const int64_t m = n, R = cluster_row_bound(n, M < 2 ? 2 : M, G);
   Ws w;
   w.alloc<uint32_t>(n + m + 1);  // kpar
   w.alloc<uint32_t>(m + 1); w.alloc<uint32_t>(m + 1); w.alloc<uint32_t>(m + 1);  // J, active lists
   w.alloc<uint8_t>(m + 4);       // isbirth
   w.alloc<uint64_t>(m + 1);      // birthL
-  w.alloc<uint32_t>(m + 2); w.alloc<uint32_t>(m + 2);  // flags32, rowof
+  w.alloc<uint32_t>(m + 2); w.alloc<uint32_t>(m + 2); w.alloc<uint32_t>(m + 1);  // flags32, idx, rowof
+  for (int k = 0; k < 4; k++) w.alloc<uint32_t>(G + 2);  // nbig, bcnt, bstart, rootrow
+  w.alloc<uint32_t>(G + 1);  // labels per graph
+  for (int k = 0; k < 4; k++) w.alloc<uint32_t>(R);  // birth sort keys/values
   w.alloc<uint32_t>(n); w.alloc<uint64_t>(n);  // exc exl
   w.alloc<uint32_t>(R); w.alloc<uint32_t>(R); w.alloc<uint64_t>(R); w.alloc<uint32_t>(R);  // cnode csize cbirth cprow
   w.alloc<uint64_t>(3 * R);  // acc
@@ -559,19 +628,25 @@ size_t stage_condense_scratch(int64_t n, int64_t M) {
   w.alloc<uint32_t>(R); w.alloc<uint32_t>(R);  // row active lists
   w.alloc<uint32_t>(n);  // labrow
   w.alloc<uint32_t>(n + 1);  // flag / scan
-  return w.off + scan_ws_bytes(n + 1) + scan_ws_bytes(m + 1) + 8192;
+  return w.off + scan_ws_bytes(n + 1) + scan_ws_bytes(m + 1) + scan_ws_bytes(G + 1) + radix_ws_bytes(R) + 8192;
 }
 
-ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipStream_t s, ce_counts *counts) {
-  const int64_t n = b.n, M = b.M;
+ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipStream_t s, ce_counts *counts,
+                         int64_t *cluster_offsets) {
+  const int64_t n = b.n, M = b.M, G = b.G;
   size_t m0 = ws.mark();
-  const int64_t R = 2 * (n / M) + 2;
+  const int64_t R = cluster_row_bound(n, M, G);
   uint32_t *kpar = ws.alloc<uint32_t>(n + m + 1);
   uint32_t *J = ws.alloc<uint32_t>(m + 1);
   uint32_t *jact = ws.alloc<uint32_t>(m + 1), *jact2 = ws.alloc<uint32_t>(m + 1);
   uint8_t *isbirth = ws.alloc<uint8_t>(m + 4);
   uint64_t *birthL = ws.alloc<uint64_t>(m + 1);
-  uint32_t *flags32 = ws.alloc<uint32_t>(m + 2), *rowof = ws.alloc<uint32_t>(m + 2);
+  uint32_t *flags32 = ws.alloc<uint32_t>(m + 2), *idx = ws.alloc<uint32_t>(m + 2), *rowof = ws.alloc<uint32_t>(m + 1);
+  uint32_t *nbig = ws.alloc<uint32_t>(G + 2), *bcnt = ws.alloc<uint32_t>(G + 2), *bstart = ws.alloc<uint32_t>(G + 2);
+  uint32_t *rootrow = ws.alloc<uint32_t>(G + 2);
+  uint32_t *nlab = ws.alloc<uint32_t>(G + 1);
+  uint32_t *bkey = ws.alloc<uint32_t>(R), *bval = ws.alloc<uint32_t>(R);
+  uint32_t *bkey2 = ws.alloc<uint32_t>(R), *bval2 = ws.alloc<uint32_t>(R);
   uint32_t *exc = ws.alloc<uint32_t>(n);
   uint64_t *exl = ws.alloc<uint64_t>(n);
   uint32_t *cnode = ws.alloc<uint32_t>(R), *csize = ws.alloc<uint32_t>(R);
@@ -598,25 +673,21 @@ ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipSt
   unsigned long long *ctr = (unsigned long long *)&b.hdr[8];
   auto tiles = [](int64_t k) { return (unsigned)((k + (int64_t)B * CT - 1) / ((int64_t)B * CT)); };
 
-  const unsigned gN = grid_for(n + m + 1, B), gm = grid_for(m + 1, B);
+  const unsigned gN = grid_for(n + m + 1, B), gm = grid_for(m + 1, B), gG = grid_for(G + 1, B);
   CE_LAUNCH(k_fill32, dim3(gN), dim3(B), 0, s, kpar, n + m + 1, NONE32);
-  if (m > 0)
-    CE_LAUNCH(k_cd_parents, dim3(grid_for(m, B)), dim3(B), 0, s, b.kc_u, b.kc_v, m, n, kpar);
-  CE_LAUNCH(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[8], (uint64_t)0);
-  if (m > 0)
-    CE_LAUNCH(k_cd_bigroots, dim3(grid_for(m, B)), dim3(B), 0, s, kpar, b.ksize, m, n, M, ctr);
-  CE_HIP(hipGetLastError());
-  uint64_t nbig = 0;
-  CE_TRY(read_u64(&b.hdr[8], &nbig, 1, s));
-  {
-    CE_LAUNCH(k_fill32, dim3(grid_for((m + 4) / 4, B)), dim3(B), 0, s, (uint32_t *)isbirth, (m + 4) / 4, 0u);
-  }
+  CE_LAUNCH(k_fill32, dim3(gG), dim3(B), 0, s, nbig, G + 1, 0u);
   if (m > 0) {
-    CE_LAUNCH(k_cd_birth, dim3(grid_for(m, B)), dim3(B), 0, s, b.kc_u, b.kc_v, b.ksize, kpar, b.msf_key,
-                       b.idbits, m, n, M, nbig, isbirth, birthL);
+    CE_LAUNCH(k_cd_parents, dim3(grid_for(m, B)), dim3(B), 0, s, b.kc_u, b.kc_v, m, n, kpar);
+    CE_LAUNCH(k_cd_bigroots, dim3(grid_for(m, B)), dim3(B), 0, s, kpar, b.ksize, b.rowg, m, n, M, nbig);
+  }
+  CE_LAUNCH(k_fill32, dim3(grid_for((m + 4) / 4, B)), dim3(B), 0, s, (uint32_t *)isbirth, (m + 4) / 4, 0u);
+  CE_HIP(hipGetLastError());
+  if (m > 0) {
+    CE_LAUNCH(k_cd_birth, dim3(grid_for(m, B)), dim3(B), 0, s, b.kc_u, b.kc_v, b.ksize, kpar, b.msf_key, b.idbits, m,
+              n, M, nbig, b.rowg, isbirth, birthL);
     CE_LAUNCH(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[9], (uint64_t)0);
-    CE_LAUNCH(k_cd_jinit, dim3(tiles(m)), dim3(B), 0, s, isbirth, kpar, b.ksize, m, n, M, J, jact,
-                       (unsigned long long *)&b.hdr[9]);
+    CE_LAUNCH(k_cd_jinit, dim3(tiles(m)), dim3(B), 0, s, isbirth, kpar, b.ksize, b.rowg, m, n, M, J, jact,
+              (unsigned long long *)&b.hdr[9]);
     CE_HIP(hipGetLastError());
     uint64_t nact = 0;
     CE_TRY(read_u64(&b.hdr[9], &nact, 1, s));
@@ -626,54 +697,67 @@ ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipSt
         return CE_EDEVICE;
       }
       CE_LAUNCH(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[9], (uint64_t)0);
-      CE_LAUNCH(k_cd_jstep, dim3(tiles((int64_t)nact)), dim3(B), 0, s, jact, (int64_t)nact, J, isbirth, m, n,
-                         jact2, (unsigned long long *)&b.hdr[9]);
+      CE_LAUNCH(k_cd_jstep, dim3(tiles((int64_t)nact)), dim3(B), 0, s, jact, (int64_t)nact, J, isbirth, m, n, jact2,
+                (unsigned long long *)&b.hdr[9]);
       CE_HIP(hipGetLastError());
       uint32_t *tmp = jact; jact = jact2; jact2 = tmp;
       CE_TRY(read_u64(&b.hdr[9], &nact, 1, s));
     }
   }
   if (M <= EXIT_STACK) {
-    CE_LAUNCH(k_fill32, dim3(grid_for(n, B)), dim3(B), 0, s, exc, n, (uint32_t)(n + m));
-    CE_LAUNCH(k_fill64, dim3(grid_for(n, B)), dim3(B), 0, s, exl, n, (uint64_t)0);
+    CE_LAUNCH(k_exit_default, dim3(grid_for(n, B)), dim3(B), 0, s, b.grank, n, m, exc, exl);
     if (m > 0)
       CE_LAUNCH(k_cd_exit_down, dim3(grid_for(m, B)), dim3(B), 0, s, b.kc_u, b.kc_v, b.ksize, J, b.msf_key, b.idbits,
                 m, n, M, exc, exl);
   } else {
-    CE_LAUNCH(k_cd_exit, dim3(grid_for(n, B)), dim3(B), 0, s, kpar, b.ksize, J, b.msf_key, b.idbits, m, n, M, exc,
-              exl);
+    CE_LAUNCH(k_cd_exit, dim3(grid_for(n, B)), dim3(B), 0, s, kpar, b.ksize, J, b.msf_key, b.grank, b.idbits, m, n,
+              M, exc, exl);
   }
+  // cluster rows: births in (graph, node) order, each graph followed by its root row
   CE_LAUNCH(k_u8_to_u32, dim3(gm), dim3(B), 0, s, isbirth, m, flags32);
   CE_HIP(hipGetLastError());
-  CE_TRY(scan_exclusive_u32(flags32, rowof, m, ws, s));
-  uint64_t nb64 = 0;
+  CE_TRY(scan_exclusive_u32(flags32, idx, m, ws, s));
+  uint32_t nb = 0;
   {
-    // rowof[m] holds the number of birth nodes
     uint32_t *h = (uint32_t *)pinned_scratch();
-    CE_HIP(hipMemcpyAsync(h, rowof + m, 4, hipMemcpyDeviceToHost, s));
+    CE_HIP(hipMemcpyAsync(h + 32, idx + m, 4, hipMemcpyDeviceToHost, s));
     CE_HIP(hipStreamSynchronize(s));
-    nb64 = h[0];
+    nb = h[32];
   }
-  const uint32_t nbirth = (uint32_t)nb64, nrows = nbirth + 1, rootrow = nbirth;
+  const uint32_t nrows = nb + (uint32_t)G;
   if ((int64_t)nrows > R) {
-    set_error("cluster rows exceed 2*floor(n/M)+1");
+    set_error("cluster rows exceed 2*floor(n_g/M)+1 per graph");
     return CE_EDEVICE;
   }
+  CE_LAUNCH(k_fill32, dim3(gG), dim3(B), 0, s, bcnt, G + 1, 0u);
+  if (nb > 0)
+    CE_LAUNCH(k_birth_list, dim3(gm), dim3(B), 0, s, isbirth, idx, b.rowg, m, bkey, bval, bcnt);
+  CE_HIP(hipGetLastError());
+  CE_TRY(scan_exclusive_u32(bcnt, bstart, G, ws, s));
+  CE_LAUNCH(k_root_rows, dim3(gG), dim3(B), 0, s, bstart, G, rootrow);
+  const uint32_t *rowmap = idx;  // one graph: a birth's row is its index among births
+  if (G > 1 && nb > 0) {
+    bool alt = false;
+    CE_TRY((radix_sort_pairs<uint32_t, uint32_t>(bkey, bval, bkey2, bval2, nb, 0, bits_for((uint64_t)(G - 1)), false,
+                                                 &alt, ws, s)));
+    CE_LAUNCH(k_birth_rows, dim3(grid_for(nb, B)), dim3(B), 0, s, alt ? bval2 : bval, b.rowg, (int64_t)nb, rowof);
+    rowmap = rowof;
+  }
   const unsigned gR = grid_for(nrows, B);
-  CE_LAUNCH(k_cd_rows, dim3(gm), dim3(B), 0, s, isbirth, rowof, b.ksize, birthL, kpar, J, m, n, nbirth, cnode,
-                     csize, cbirth, cprow);
-  CE_LAUNCH(k_fill64, dim3(grid_for(3 * (int64_t)nrows, B)), dim3(B), 0, s, (uint64_t *)acc,
-                     3 * (int64_t)nrows, (uint64_t)0);
-  CE_LAUNCH(k_cd_acc_points, dim3(tiles(n)), dim3(B), 0, s, exc, exl, rowof, m, n, nbirth, acc);
-  CE_LAUNCH(k_cd_acc_children, dim3((unsigned)((nrows + B - 1) / B)), dim3(B), 0, s, csize, cbirth, cprow,
-                     nrows, acc);
+  CE_LAUNCH(k_cd_rows, dim3(gm), dim3(B), 0, s, isbirth, rowmap, rootrow, b.ksize, birthL, kpar, J, b.rowg, m, n,
+            cnode, csize, cbirth, cprow);
+  CE_LAUNCH(k_cd_rootrows, dim3(gG), dim3(B), 0, s, rootrow, b.eoff, G, m, n, cnode, csize, cbirth, cprow);
+  CE_LAUNCH(k_fill64, dim3(grid_for(3 * (int64_t)nrows, B)), dim3(B), 0, s, (uint64_t *)acc, 3 * (int64_t)nrows,
+            (uint64_t)0);
+  CE_LAUNCH(k_cd_acc_points, dim3(tiles(n)), dim3(B), 0, s, exc, exl, rowmap, m, n, rootrow, acc);
+  CE_LAUNCH(k_cd_acc_children, dim3((unsigned)((nrows + B - 1) / B)), dim3(B), 0, s, csize, cbirth, cprow, nrows,
+            acc);
   CE_LAUNCH(k_cd_stab, dim3(gR), dim3(B), 0, s, acc, csize, cbirth, nrows, shi, slo);
   CE_LAUNCH(k_fill32, dim3(gR), dim3(B), 0, s, nch, (int64_t)nrows, 0u);
   CE_LAUNCH(k_fill32, dim3(grid_for(2 * (int64_t)nrows, B)), dim3(B), 0, s, ch, 2 * (int64_t)nrows, 0u);
-  CE_LAUNCH(k_cd_children, dim3(gR), dim3(B), 0, s, cprow, nrows, rootrow, nch, ch);
+  CE_LAUNCH(k_cd_children, dim3(gR), dim3(B), 0, s, cprow, nrows, nch, ch);
   CE_LAUNCH(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[8], (uint64_t)0);
-  CE_LAUNCH(k_eom_init, dim3(tiles(nrows)), dim3(B), 0, s, nch, shi, slo, nrows, rootrow, e[0], e[1], ract,
-                     ctr);
+  CE_LAUNCH(k_eom_init, dim3(tiles(nrows)), dim3(B), 0, s, nch, shi, slo, cprow, nrows, e[0], e[1], ract, ctr);
   CE_HIP(hipGetLastError());
   uint64_t nact = 0;
   CE_TRY(read_u64(&b.hdr[8], &nact, 1, s));
@@ -684,16 +768,16 @@ ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipSt
       return CE_EDEVICE;
     }
     CE_LAUNCH(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[8], (uint64_t)0);
-    CE_LAUNCH(k_eom_round, dim3(tiles((int64_t)nact)), dim3(B), 0, s, ract, (int64_t)nact, e[cur], e[1 - cur],
-                       ch, shi, slo, ract2, ctr);
+    CE_LAUNCH(k_eom_round, dim3(tiles((int64_t)nact)), dim3(B), 0, s, ract, (int64_t)nact, e[cur], e[1 - cur], ch,
+              shi, slo, ract2, ctr);
     CE_HIP(hipGetLastError());
     cur = 1 - cur;
     uint32_t *tmp = ract; ract = ract2; ract2 = tmp;
     CE_TRY(read_u64(&b.hdr[8], &nact, 1, s));
   }
   CE_LAUNCH(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[8], (uint64_t)0);
-  CE_LAUNCH(k_eom_select, dim3(tiles(nrows)), dim3(B), 0, s, nch, ch, e[cur], shi, slo, nrows, rootrow, top,
-                     nxt, top2, nxt2, cprow, ract, ctr);
+  CE_LAUNCH(k_eom_select, dim3(tiles(nrows)), dim3(B), 0, s, nch, ch, e[cur], shi, slo, nrows, top, nxt, top2, nxt2,
+            cprow, ract, ctr);
   CE_HIP(hipGetLastError());
   CE_TRY(read_u64(&b.hdr[8], &nact, 1, s));
   for (int it = 0; nact > 0; it++) {
@@ -702,8 +786,8 @@ ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipSt
       return CE_EDEVICE;
     }
     CE_LAUNCH(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[8], (uint64_t)0);
-    CE_LAUNCH(k_top_jump, dim3(tiles((int64_t)nact)), dim3(B), 0, s, ract, (int64_t)nact, top, nxt, top2,
-                       nxt2, ract2, ctr);
+    CE_LAUNCH(k_top_jump, dim3(tiles((int64_t)nact)), dim3(B), 0, s, ract, (int64_t)nact, top, nxt, top2, nxt2, ract2,
+              ctr);
     CE_HIP(hipGetLastError());
     uint32_t *t1 = top; top = top2; top2 = t1;
     uint32_t *t2 = nxt; nxt = nxt2; nxt2 = t2;
@@ -711,26 +795,28 @@ ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipSt
     CE_TRY(read_u64(&b.hdr[8], &nact, 1, s));
   }
   CE_LAUNCH(k_fill32, dim3(gR), dim3(B), 0, s, minmem, (int64_t)nrows, NONE32);
-  CE_LAUNCH(k_lab_rows, dim3(grid_for(n, B)), dim3(B), 0, s, exc, rowof, top, b.perm, m, n, nbirth, labrow,
-                     minmem);
+  CE_LAUNCH(k_lab_rows, dim3(grid_for(n, B)), dim3(B), 0, s, exc, rowmap, rootrow, top, cprow, b.perm, m, n, labrow,
+            minmem);
   CE_LAUNCH(k_fill32, dim3(grid_for(n + 1, B)), dim3(B), 0, s, fl, n + 1, 0u);
   CE_LAUNCH(k_lab_flags, dim3(gR), dim3(B), 0, s, top, minmem, nrows, fl);
   CE_HIP(hipGetLastError());
   CE_TRY(scan_exclusive_u32(fl, fl, n, ws, s));
-  CE_LAUNCH(k_out_points, dim3(grid_for(n, B)), dim3(B), 0, s, b.perm, exc, exl, labrow, minmem, fl, n,
-                     out->pt_cluster, out->pt_lambda, out->labels);
-  CE_LAUNCH(k_out_clusters, dim3(gR), dim3(B), 0, s, cnode, cprow, csize, cbirth, shi, slo, top, nrows,
-                     rootrow, *out);
+  CE_LAUNCH(k_out_points, dim3(grid_for(n, B)), dim3(B), 0, s, b.perm, b.grank, exc, exl, labrow, minmem, fl, b.eoff,
+            b.moff, b.rowpos, n, m, out->pt_cluster, out->pt_lambda, out->labels);
+  CE_LAUNCH(k_out_clusters, dim3(gR), dim3(B), 0, s, cnode, cprow, csize, cbirth, shi, slo, top, b.rowg, b.eoff,
+            b.moff, b.rowpos, n, m, nrows, *out);
+  CE_LAUNCH(k_graph_labels, dim3(gG), dim3(B), 0, s, fl, b.eoff, G, nlab);
   CE_HIP(hipGetLastError());
-  uint32_t nl = 0;
-  {
-    uint32_t *h = (uint32_t *)pinned_scratch();
-    CE_HIP(hipMemcpyAsync(h, fl + n, 4, hipMemcpyDeviceToHost, s));
-    CE_HIP(hipStreamSynchronize(s));
-    nl = h[0];
+  std::vector<uint32_t> hb(G + 1), hl(G);
+  CE_HIP(hipMemcpyAsync(hb.data(), bstart, sizeof(uint32_t) * (G + 1), hipMemcpyDeviceToHost, s));
+  CE_HIP(hipMemcpyAsync(hl.data(), nlab, sizeof(uint32_t) * G, hipMemcpyDeviceToHost, s));
+  CE_HIP(hipStreamSynchronize(s));
+  for (int64_t g = 0; g < G; g++) {
+    counts[g].n_clusters = (int64_t)(hb[g + 1] - hb[g]) + 1;
+    counts[g].n_labels = hl[g];
+    if (cluster_offsets) cluster_offsets[g] = (int64_t)hb[g] + g;
   }
-  counts->n_clusters = nrows;
-  counts->n_labels = nl;
+  if (cluster_offsets) cluster_offsets[G] = (int64_t)nb + G;
   ws.release(m0);
   return CE_OK;
 }

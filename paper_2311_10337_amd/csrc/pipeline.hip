@@ -26,9 +26,11 @@ constexpr int B = 256;
 
 __device__ inline uint64_t t_to_ord(int64_t t) { return (uint64_t)t ^ (uint64_t(1) << 63); }
 
-// hdr[0] |= 1 self loop, 2 id out of range; hdr[1] = min t (ordered), hdr[2] = max t (ordered)
+// hdr[0] |= 1 self loop, 2 id out of range; hdr[1] = min t (ordered), hdr[2] = max t (ordered).
+// A record of graph g must name vertices in [0, voff[g+1] - voff[g]).
 __global__ __launch_bounds__(B) void k_validate(const int32_t *src, const int32_t *dst, const int64_t *t, int64_t n,
-                                                int64_t V, uint64_t *hdr) {
+                                                const int64_t *eoff, const int64_t *voff, int64_t G,
+                                                uint64_t *hdr) {
   __shared__ uint64_t smin[B / 64], smax[B / 64];
   __shared__ uint32_t sflag;
   if (threadIdx.x == 0) sflag = 0;
@@ -37,6 +39,8 @@ __global__ __launch_bounds__(B) void k_validate(const int32_t *src, const int32_
   uint32_t flag = 0;
   for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < n; i += (int64_t)gridDim.x * B) {
     int32_t a = src[i], b = dst[i];
+    const uint32_t g = G > 1 ? graph_of(eoff, G, i) : 0u;
+    const int64_t V = voff[g + 1] - voff[g];
     if (a == b) flag |= 1u;
     if (a < 0 || b < 0 || (int64_t)a >= V || (int64_t)b >= V) flag |= 2u;
     uint64_t o = t_to_ord(t[i]);
@@ -68,20 +72,26 @@ __global__ void k_init_hdr(uint64_t *hdr) {
   if (threadIdx.x == 0) hdr[1] = NONE64;
 }
 
-// the time sort carries (id, src, dst) along, so grouping needs no gathers
+// the time sort carries (id, src, dst, graph) along, so grouping needs no
+// gathers; vertex ids become global (graph offset + local id)
 __global__ __launch_bounds__(B) void k_tkeys(const int64_t *t, const int32_t *src, const int32_t *dst, int64_t n,
-                                             int64_t tmin, uint64_t *keys, uint4 *vals) {
+                                             const int64_t *eoff, const int64_t *voff, int64_t G, int64_t tmin,
+                                             uint64_t *keys, uint4 *vals) {
   for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < n; i += (int64_t)gridDim.x * B) {
+    const uint32_t g = G > 1 ? graph_of(eoff, G, i) : 0u;
+    const uint32_t vb = (uint32_t)voff[g];
     keys[i] = (uint64_t)(t[i] - tmin);
-    vals[i] = make_uint4((uint32_t)i, (uint32_t)src[i], (uint32_t)dst[i], 0u);
+    vals[i] = make_uint4((uint32_t)i, vb + (uint32_t)src[i], vb + (uint32_t)dst[i], g);
   }
 }
 
 // incidence entries in rank order: key = vertex, value (implicit) = 2r+side
-__global__ __launch_bounds__(B) void k_incidence(const uint4 *vals, int64_t n, uint32_t *perm, uint32_t *ikey) {
+__global__ __launch_bounds__(B) void k_incidence(const uint4 *vals, int64_t n, uint32_t *perm, uint32_t *grank,
+                                                 uint32_t *ikey) {
   for (int64_t r = (int64_t)blockIdx.x * B + threadIdx.x; r < n; r += (int64_t)gridDim.x * B) {
     const uint4 v = vals[r];
     perm[r] = v.x;
+    grank[r] = v.w;
     ikey[2 * r] = v.y;
     ikey[2 * r + 1] = v.z;
   }
@@ -435,7 +445,8 @@ ce_status stage_validate(const int32_t *src, const int32_t *dst, const int64_t *
   CE_LAUNCH(k_init_hdr, dim3(1), dim3(64), 0, s, b.hdr);
   CE_HIP(hipGetLastError());
   if (b.n > 0) {
-    CE_LAUNCH(k_validate, dim3(grid_for(b.n, B, 4096)), dim3(B), 0, s, src, dst, t, b.n, b.V, b.hdr);
+    CE_LAUNCH(k_validate, dim3(grid_for(b.n, B, 4096)), dim3(B), 0, s, src, dst, t, b.n, b.eoff, b.voff, b.G,
+              b.hdr);
     CE_HIP(hipGetLastError());
   }
   uint64_t h[3];
@@ -476,13 +487,13 @@ ce_status stage_sort_skeleton(const int32_t *src, const int32_t *dst, const int6
     uint4 *tval = ws.alloc<uint4>(n);
     uint4 *tval_alt = ws.alloc<uint4>(n);
     CE_WS_CHECK(ws);
-    CE_LAUNCH(k_tkeys, dim3(grid_for(n, B)), dim3(B), 0, s, t, src, dst, n, b.tmin, b.ts, tval);
+    CE_LAUNCH(k_tkeys, dim3(grid_for(n, B)), dim3(B), 0, s, t, src, dst, n, b.eoff, b.voff, b.G, b.tmin, b.ts, tval);
     CE_HIP(hipGetLastError());
     bool alt = false;
     CE_TRY((radix_sort_pairs<uint64_t, uint4>(b.ts, tval, tkey_alt, tval_alt, n, 0, b.tbits, false, &alt, ws, s)));
     if (alt) CE_HIP(hipMemcpyAsync(b.ts, tkey_alt, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
     // 2. incidence entries (vertex, 2*rank+side) in rank order, perm by rank
-    CE_LAUNCH(k_incidence, dim3(grid_for(n, B)), dim3(B), 0, s, alt ? tval_alt : tval, n, b.perm, ikey);
+    CE_LAUNCH(k_incidence, dim3(grid_for(n, B)), dim3(B), 0, s, alt ? tval_alt : tval, n, b.perm, b.grank, ikey);
     CE_HIP(hipGetLastError());
     ws.release(m1);
   }

@@ -18,8 +18,8 @@ def test_library_exports_declared_symbols():
         pytest.skip("libce.so not built")
     lib = ce.load_library()
     syms = declared_symbols()
-    assert set(syms) == {"ce_cluster_edges", "ce_workspace_bytes", "ce_max_clusters", "ce_last_error",
-                         "ce_timing_enable", "ce_timing_read"}
+    assert set(syms) == {"ce_cluster_edges", "ce_cluster_batch", "ce_workspace_bytes", "ce_batch_workspace_bytes",
+                         "ce_max_clusters", "ce_last_error", "ce_timing_enable", "ce_timing_read"}
     for s in syms:
         assert hasattr(lib, s), s
 
@@ -36,7 +36,7 @@ def test_host_only_functions():
     assert ce.workspace_bytes(10, 0, 5) == 0
     assert ce.workspace_bytes(10, 10, 1) == 0
     # about 100 bytes of workspace per record at scale
-    assert ce.workspace_bytes(10 ** 7, 10 ** 6, 10) / 10 ** 7 < 200  # bytes of workspace per record
+    assert ce.workspace_bytes(10 ** 7, 10 ** 6, 10) / 10 ** 7 < 210  # bytes of workspace per record
 
 
 def test_host_argument_errors_need_no_gpu():
@@ -59,3 +59,52 @@ def test_host_argument_errors_need_no_gpu():
     p.mode = 7
     assert lib.ce_cluster_edges(None, None, None, 0, ctypes.byref(p), ctypes.byref(res), ctypes.byref(cnt), None, 0,
                                 None) == ce.CE_EINVAL
+
+
+def test_batch_host_functions():
+    import paper_2311_10337_amd as ce
+    if not os.path.exists(ce.LIB_PATH):
+        pytest.skip("libce.so not built")
+    # one graph as a batch needs the same workspace as the single call
+    assert ce.batch_workspace_bytes([0, 5000], [0, 300], 5) == ce.workspace_bytes(5000, 300, 5)
+    many = ce.batch_workspace_bytes([0, 2000, 2000, 5000], [0, 100, 101, 300], 5)
+    assert many >= ce.workspace_bytes(5000, 300, 5)
+    assert ce.batch_workspace_bytes([0, 10, 5], [0, 3, 6], 5) == 0      # decreasing edge offsets
+    assert ce.batch_workspace_bytes([0, 10, 20], [0, 3, 3], 5) == 0     # a graph without vertices
+    assert ce.batch_workspace_bytes([1, 10], [0, 3], 5) == 0            # offsets must start at 0
+    assert ce.batch_cluster_capacity([0, 10, 10, 33], 5) == 5 + 1 + 9
+
+
+def test_batch_argument_errors_need_no_gpu():
+    import ctypes
+    import numpy as np
+    import paper_2311_10337_amd as ce
+    if not os.path.exists(ce.LIB_PATH):
+        pytest.skip("libce.so not built")
+    lib = ce.load_library()
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    res = ce.CeResult()
+    p = ce.make_params(5, 10)
+
+    def call(eo, vo, G, counts=True, offsets=True):
+        eo = np.asarray(eo, dtype=np.int64)
+        vo = np.asarray(vo, dtype=np.int64)
+        cnt = (ce.CeCounts * max(G, 1))()
+        ro = np.zeros(max(G, 0) + 1, dtype=np.int64)
+        co = np.zeros(max(G, 0) + 1, dtype=np.int64)
+        return lib.ce_cluster_batch(None, None, None, eo.ctypes.data_as(i64p), vo.ctypes.data_as(i64p), G,
+                                    ctypes.byref(p), ctypes.byref(res), cnt if counts else None,
+                                    ro.ctypes.data_as(i64p) if offsets else None, co.ctypes.data_as(i64p), None, 0,
+                                    None)
+
+    assert call([0, 0], [0, 1], 0) == ce.CE_EINVAL
+    assert "number of graphs" in ce.last_error()
+    assert call([0, 4, 2], [0, 1, 2], 2) == ce.CE_EINVAL
+    assert "non-decreasing" in ce.last_error()
+    assert call([0, 4, 6], [0, 1, 1], 2) == ce.CE_EINVAL
+    assert "vertex" in ce.last_error()
+    assert call([0, 4], [0, 3], 1, counts=False) == ce.CE_EINVAL
+    assert call([0, 4], [0, 3], 1, offsets=False) == ce.CE_EINVAL
+    assert call([0, 4], [0, 3], 1) == ce.CE_EINVAL  # null record pointers with 4 records
+    assert "input pointer" in ce.last_error()
+    assert call([0, 1 << 31], [0, 3], 1) == ce.CE_EINVAL
