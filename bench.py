@@ -55,6 +55,66 @@ def cpu_baseline(w, sample):
                       % (ns, w.n, dt)}
 
 
+def bench_batched(dev, steps, warmup):
+    """The 4096-graph batch in one call vs one call per graph, same GPU and inputs."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2311_10337_amd as ce
+    G, M = 4096, 5
+    t0 = time.perf_counter()
+    src, dst, t, eoff, voff = synth.batch_workload(G, seed=3)
+    n = int(eoff[-1])
+    log("batch workload: %d graphs, %d records (%.1f s)" % (G, n, time.perf_counter() - t0))
+    s_d = torch.from_numpy(src).to(dev)
+    d_d = torch.from_numpy(dst).to(dev)
+    t_d = torch.from_numpy(t).to(dev)
+    outs = ce.batch_outputs(eoff, M, dev)
+    ws = torch.empty(ce.batch_workspace_bytes(eoff, voff, M), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+
+    def batch_step():
+        return ce.cluster_batch(s_d, d_d, t_d, eoff, voff, M, outputs=outs, workspace=ws)
+
+    for _ in range(warmup):
+        batch_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        br = batch_step()
+    torch.cuda.synchronize()
+    el_b = (time.perf_counter() - t0) / steps
+    log("batched: %.1f ms per batch" % (1e3 * el_b))
+    del ws
+    ng = np.diff(eoff)
+    vg = np.diff(voff)
+    nmax = int(ng.max())
+    souts = ce.Outputs(nmax, M, dev)
+    sws = torch.empty(ce.workspace_bytes(nmax, int(vg.max()), M), dtype=torch.uint8, device=dev)
+
+    def single(g):
+        a, b = int(eoff[g]), int(eoff[g + 1])
+        return ce.cluster_edges(s_d[a:b], d_d[a:b], t_d[a:b], M, int(vg[g]), outputs=souts, workspace=sws)
+
+    for g in range(min(G, 64)):
+        single(g)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for g in range(G):
+        single(g)
+    torch.cuda.synchronize()
+    el_s = time.perf_counter() - t0
+    log("one graph per call: %.1f ms for the %d graphs" % (1e3 * el_s, G))
+    out = {"workload": "chung-lu-bursts-batch-4096", "graphs": G, "n_edges": n, "min_cluster_size": M, "seed": 3,
+           "sizes": "lognormal median 20000 sigma 1.5 clipped [500, 2e6]; V_g = n_g/20",
+           "batched_edges_per_s": n / el_b, "batched_ms": 1e3 * el_b, "batched_steps": steps,
+           "single_edges_per_s": n / el_s, "single_ms": 1e3 * el_s,
+           "ratio": el_s / el_b, "n_clusters": int(br.n_clusters.sum()), "n_labels": int(br.n_labels.sum())}
+    del s_d, d_d, t_d, outs, souts, sws
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -63,6 +123,8 @@ def main():
     ap.add_argument("--workload", default="mid", choices=["tiny", "mid", "scale"])
     ap.add_argument("--cpu-sample", type=int, default=20_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched-vs-one-graph-per-call measurement on the 4096-graph batch")
     ap.add_argument("--roofline-kernel", default="k_krt_accum",
                     help="dominant kernel: its launches are timed with HIP events on its stream for the roofline")
     ap.add_argument("--copy-calibration", type=int, default=0,
@@ -142,6 +204,10 @@ def main():
             "config": dict(cfg, m_msf=r.m, n_clusters=r.n_clusters, n_labels=r.n_labels)}
     if roof is not None:
         line["roofline"] = roof
+    if not args.no_batch:
+        del src, dst, tt, outs, ws
+        torch.cuda.empty_cache()
+        line["batched"] = bench_batched(dev, max(1, min(args.steps, 3)), 1)
     if not args.no_cpu_baseline:
         log("cpu baseline on a sample")
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)

@@ -60,15 +60,18 @@ __global__ __launch_bounds__(B) void k_zero32(uint32_t *p, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < n; i += (int64_t)gridDim.x * B) p[i] = 0u;
 }
 
-// graph of each MSF row (the graph of its tail record) and rows per graph
+// graph of each MSF row (the graph of its tail record)
 __global__ __launch_bounds__(B) void k_rowg(const uint4 *msf_val, const uint32_t *grank, int64_t m, uint32_t *rowg,
-                                            uint32_t *key, uint32_t *cnt) {
+                                            uint32_t *key) {
   for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
     const uint32_t g = grank[msf_val[j].x];
     rowg[j] = g;
     key[j] = g;
-    atomicAdd(&cnt[g], 1u);
   }
+}
+
+__global__ void k_set2_u32(uint32_t *p, uint32_t a, uint32_t b) {
+  if (threadIdx.x == 0) { p[0] = a; p[1] = b; }
 }
 
 __global__ __launch_bounds__(B) void k_rowpos(const uint32_t *sorted_j, int64_t m, uint32_t *rowpos) {
@@ -131,8 +134,7 @@ __global__ void k_trivial(const int64_t *eoff, int64_t G, ce_result out) {
 size_t stage_graph_rows_scratch(int64_t n, int64_t G) {
   Ws w;
   for (int k = 0; k < 4; k++) w.alloc<uint32_t>(n);
-  w.alloc<uint32_t>(G + 1);
-  return w.off + scan_ws_bytes(G + 1) + radix_ws_bytes(n) + 4096;
+  return w.off + radix_ws_bytes(n) + 4096;
 }
 
 // Position of every MSF row in the output: graphs in order, the rows of one
@@ -142,21 +144,25 @@ ce_status stage_graph_rows(Bufs &b, int64_t m, Ws &ws, hipStream_t s, int64_t *r
   size_t m0 = ws.mark();
   uint32_t *key = ws.alloc<uint32_t>(m), *val = ws.alloc<uint32_t>(m);
   uint32_t *key2 = ws.alloc<uint32_t>(m), *val2 = ws.alloc<uint32_t>(m);
-  uint32_t *cnt = ws.alloc<uint32_t>(G + 1);
   CE_WS_CHECK(ws);
-  CE_LAUNCH(k_zero32, dim3(grid_for(G + 1, B)), dim3(B), 0, s, cnt, G + 1);
-  if (m > 0) CE_LAUNCH(k_rowg, dim3(grid_for(m, B)), dim3(B), 0, s, b.msf_val, b.grank, m, b.rowg, key, cnt);
-  CE_HIP(hipGetLastError());
-  CE_TRY(scan_exclusive_u32(cnt, b.moff, G, ws, s));
-  if (m > 0) {
-    if (G == 1) {
+  if (G == 1) {
+    if (m > 0) {
+      CE_LAUNCH(k_zero32, dim3(grid_for(m, B)), dim3(B), 0, s, b.rowg, m);
       CE_LAUNCH(k_iota32, dim3(grid_for(m, B)), dim3(B), 0, s, b.rowpos, m);
-    } else {
+    }
+    CE_LAUNCH(k_set2_u32, dim3(1), dim3(64), 0, s, b.moff, 0u, (uint32_t)m);
+  } else {
+    const uint32_t *sorted = key;
+    if (m > 0) {
+      CE_LAUNCH(k_rowg, dim3(grid_for(m, B)), dim3(B), 0, s, b.msf_val, b.grank, m, b.rowg, key);
+      CE_HIP(hipGetLastError());
       bool alt = false;
       CE_TRY((radix_sort_pairs<uint32_t, uint32_t>(key, val, key2, val2, m, 0, bits_for((uint64_t)(G - 1)), true,
                                                    &alt, ws, s)));
       CE_LAUNCH(k_rowpos, dim3(grid_for(m, B)), dim3(B), 0, s, alt ? val2 : val, m, b.rowpos);
+      sorted = alt ? key2 : key;
     }
+    CE_TRY(segment_bounds_u32(sorted, m, G, b.moff, s));
   }
   CE_HIP(hipGetLastError());
   if (row_offsets) {

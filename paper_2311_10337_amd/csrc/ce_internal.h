@@ -246,6 +246,10 @@ __device__ inline void tile_append(const bool (&keep)[CT], const uint32_t (&vals
 ce_status scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, Ws &ws, hipStream_t s);
 size_t scan_ws_bytes(int64_t n);
 
+// off[g] = first position whose key is >= g, for g in [0, G] (off[G] = n), from
+// keys sorted ascending with values < G; no atomics, O(n + G) work.
+ce_status segment_bounds_u32(const uint32_t *sorted_keys, int64_t n, int64_t G, uint32_t *off, hipStream_t s);
+
 // Stable LSD radix sort of (key, value) pairs on bits [begin_bit, end_bit).
 // Sorts the data in (k0, v0) using (k1, v1) as ping-pong buffers; on return
 // *result_in_alt tells which pair holds the sorted output. With iota_values the

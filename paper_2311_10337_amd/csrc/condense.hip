@@ -234,14 +234,16 @@ __global__ __launch_bounds__(B) void k_cd_rootrows(const uint32_t *rootrow, cons
 
 // births in (graph, node) order: position p gives row p + g (each earlier graph adds its root row)
 __global__ __launch_bounds__(B) void k_birth_list(const uint8_t *isbirth, const uint32_t *idx, const uint32_t *rowg,
-                                                  int64_t m, uint32_t *bkey, uint32_t *bval, uint32_t *bcnt) {
+                                                  int64_t m, uint32_t *bkey, uint32_t *bval) {
   for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
     if (!isbirth[j]) continue;
-    const uint32_t i = idx[j], g = rowg[j];
-    bkey[i] = g;
+    const uint32_t i = idx[j];
+    bkey[i] = rowg[j];
     bval[i] = (uint32_t)j;
-    atomicAdd(&bcnt[g], 1u);
   }
+}
+__global__ void k_set2_u32(uint32_t *p, uint32_t a, uint32_t b) {
+  if (threadIdx.x == 0) { p[0] = a; p[1] = b; }
 }
 __global__ __launch_bounds__(B) void k_birth_rows(const uint32_t *sorted_j, const uint32_t *rowg, int64_t nb,
                                                   uint32_t *rowof) {
@@ -610,7 +612,7 @@ size_t stage_condense_scratch(int64_t n, int64_t M, int64_t G) {
   w.alloc<uint8_t>(m + 4);       // isbirth
   w.alloc<uint64_t>(m + 1);      // birthL
   w.alloc<uint32_t>(m + 2); w.alloc<uint32_t>(m + 2); w.alloc<uint32_t>(m + 1);  // flags32, idx, rowof
-  for (int k = 0; k < 4; k++) w.alloc<uint32_t>(G + 2);  // nbig, bcnt, bstart, rootrow
+  for (int k = 0; k < 3; k++) w.alloc<uint32_t>(G + 2);  // nbig, bstart, rootrow
   w.alloc<uint32_t>(G + 1);  // labels per graph
   for (int k = 0; k < 4; k++) w.alloc<uint32_t>(R);  // birth sort keys/values
   w.alloc<uint32_t>(n); w.alloc<uint64_t>(n);  // exc exl
@@ -642,7 +644,7 @@ ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipSt
   uint8_t *isbirth = ws.alloc<uint8_t>(m + 4);
   uint64_t *birthL = ws.alloc<uint64_t>(m + 1);
   uint32_t *flags32 = ws.alloc<uint32_t>(m + 2), *idx = ws.alloc<uint32_t>(m + 2), *rowof = ws.alloc<uint32_t>(m + 1);
-  uint32_t *nbig = ws.alloc<uint32_t>(G + 2), *bcnt = ws.alloc<uint32_t>(G + 2), *bstart = ws.alloc<uint32_t>(G + 2);
+  uint32_t *nbig = ws.alloc<uint32_t>(G + 2), *bstart = ws.alloc<uint32_t>(G + 2);
   uint32_t *rootrow = ws.alloc<uint32_t>(G + 2);
   uint32_t *nlab = ws.alloc<uint32_t>(G + 1);
   uint32_t *bkey = ws.alloc<uint32_t>(R), *bval = ws.alloc<uint32_t>(R);
@@ -729,20 +731,25 @@ ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipSt
     set_error("cluster rows exceed 2*floor(n_g/M)+1 per graph");
     return CE_EDEVICE;
   }
-  CE_LAUNCH(k_fill32, dim3(gG), dim3(B), 0, s, bcnt, G + 1, 0u);
-  if (nb > 0)
-    CE_LAUNCH(k_birth_list, dim3(gm), dim3(B), 0, s, isbirth, idx, b.rowg, m, bkey, bval, bcnt);
-  CE_HIP(hipGetLastError());
-  CE_TRY(scan_exclusive_u32(bcnt, bstart, G, ws, s));
-  CE_LAUNCH(k_root_rows, dim3(gG), dim3(B), 0, s, bstart, G, rootrow);
   const uint32_t *rowmap = idx;  // one graph: a birth's row is its index among births
-  if (G > 1 && nb > 0) {
-    bool alt = false;
-    CE_TRY((radix_sort_pairs<uint32_t, uint32_t>(bkey, bval, bkey2, bval2, nb, 0, bits_for((uint64_t)(G - 1)), false,
-                                                 &alt, ws, s)));
-    CE_LAUNCH(k_birth_rows, dim3(grid_for(nb, B)), dim3(B), 0, s, alt ? bval2 : bval, b.rowg, (int64_t)nb, rowof);
-    rowmap = rowof;
+  if (G == 1) {
+    CE_LAUNCH(k_set2_u32, dim3(1), dim3(64), 0, s, bstart, 0u, nb);
+  } else {
+    const uint32_t *sorted = bkey;
+    if (nb > 0) {
+      CE_LAUNCH(k_birth_list, dim3(gm), dim3(B), 0, s, isbirth, idx, b.rowg, m, bkey, bval);
+      CE_HIP(hipGetLastError());
+      bool alt = false;
+      CE_TRY((radix_sort_pairs<uint32_t, uint32_t>(bkey, bval, bkey2, bval2, nb, 0, bits_for((uint64_t)(G - 1)),
+                                                   false, &alt, ws, s)));
+      CE_LAUNCH(k_birth_rows, dim3(grid_for(nb, B)), dim3(B), 0, s, alt ? bval2 : bval, b.rowg, (int64_t)nb, rowof);
+      sorted = alt ? bkey2 : bkey;
+      rowmap = rowof;
+    }
+    CE_TRY(segment_bounds_u32(sorted, nb, G, bstart, s));
   }
+  CE_HIP(hipGetLastError());
+  CE_LAUNCH(k_root_rows, dim3(gG), dim3(B), 0, s, bstart, G, rootrow);
   const unsigned gR = grid_for(nrows, B);
   CE_LAUNCH(k_cd_rows, dim3(gm), dim3(B), 0, s, isbirth, rowmap, rootrow, b.ksize, birthL, kpar, J, b.rowg, m, n,
             cnode, csize, cbirth, cprow);

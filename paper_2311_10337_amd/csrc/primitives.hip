@@ -127,6 +127,27 @@ ce_status scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, Ws &w
   return CE_OK;
 }
 
+// ------------------------------------------------------------ segment bounds
+namespace {
+
+// off[g] = first position p with key[p] >= g, for g in [0, G]; each of the
+// n+1 gaps between neighbouring keys writes the offsets that fall in it
+__global__ __launch_bounds__(256) void k_seg_bounds(const uint32_t *key, int64_t n, int64_t G, uint32_t *off) {
+  for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p <= n; p += (int64_t)gridDim.x * 256) {
+    const int64_t lo = p == 0 ? 0 : (int64_t)key[p - 1] + 1;
+    const int64_t hi = p == n ? G : (int64_t)key[p];
+    for (int64_t g = lo; g <= hi; g++) off[g] = (uint32_t)p;
+  }
+}
+
+}  // namespace
+
+ce_status segment_bounds_u32(const uint32_t *sorted_keys, int64_t n, int64_t G, uint32_t *off, hipStream_t s) {
+  CE_LAUNCH(k_seg_bounds, dim3(grid_for(n + 1, 256)), dim3(256), 0, s, sorted_keys, n, G, off);
+  CE_HIP(hipGetLastError());
+  return CE_OK;
+}
+
 // ------------------------------------------------------------ radix sort
 namespace {
 
