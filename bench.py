@@ -115,6 +115,96 @@ def bench_batched(dev, steps, warmup):
     return out
 
 
+def bench_serving(dev, count, workers=3, budget_gib=64):
+    """Open-loop replay of the request stream (Poisson arrivals at 200/s) through the
+    continuous-batching server, then the same requests submitted all at once,
+    against one call per request."""
+    import numpy as np
+    import torch
+    import synth
+    import paper_2311_10337_amd as ce
+    M = 10
+    sizes = synth.request_sizes(20000, seed=4)[:count]
+    arr = synth.request_arrivals(20000, seed=4)[:count]
+    arr = arr - arr[0]
+    t0 = time.perf_counter()
+    reqs = [synth.request_graph(r, int(sizes[r]), seed=4) for r in range(count)]
+    total = int(sum(len(r[0]) for r in reqs))
+    log("serving workload: %d requests, %d records (%.1f s)" % (count, total, time.perf_counter() - t0))
+    outs = [ce.Outputs(len(r[0]), M, dev) for r in reqs]
+    srv = ce.Server(budget_gib << 30, workers=workers, max_inflight=count)
+
+    def replay(arrivals):
+        lat = np.zeros(count)
+        pending = {}
+        k = 0
+        first_sub, last_done = None, 0.0
+        start = time.perf_counter()
+        while k < count or pending:
+            progressed = False
+            now = time.perf_counter() - start
+            while k < count and now >= arrivals[k]:
+                s, d, t, V = reqs[k]
+                sub = time.perf_counter() - start
+                try:
+                    tk = srv.submit(s, d, t, M, V, outputs=outs[k])
+                except ce.ServerBusy:
+                    break
+                first_sub = sub if first_sub is None else first_sub
+                pending[tk] = (k, sub)
+                k += 1
+                progressed = True
+                now = time.perf_counter() - start
+            for tk in list(pending):
+                r = srv.poll(tk)
+                if r is not None:
+                    kk, sub = pending.pop(tk)
+                    if r.status != ce.CE_OK:
+                        raise RuntimeError("request %d failed: %s" % (kk, r.error))
+                    lat[kk] = (sub - arrivals[kk]) + r.latency_s
+                    last_done = max(last_done, sub + r.latency_s)
+                    progressed = True
+            if not progressed:
+                time.sleep(0.0002)
+        return lat, last_done - arrivals[0]
+
+    replay(np.zeros(count))  # warm-up pass, everything at once
+    st0 = srv.stats()
+    lat, wall_open = replay(arr)
+    st1 = srv.stats()
+    _, wall_sat = replay(np.zeros(count))
+    st2 = srv.stats()
+    srv.close()
+    # one call per request, inputs already on the GPU
+    dins = [tuple(torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in r[:3]) + (r[3],) for r in reqs]
+    nmax = max(len(r[0]) for r in reqs)
+    souts = ce.Outputs(nmax, M, dev)
+    sws = torch.empty(ce.workspace_bytes(nmax, max(r[3] for r in reqs), M), dtype=torch.uint8, device=dev)
+    for k in range(min(count, 16)):
+        s, d, t, V = dins[k]
+        ce.cluster_edges(s, d, t, M, V, outputs=souts, workspace=sws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s, d, t, V in dins:
+        ce.cluster_edges(s, d, t, M, V, outputs=souts, workspace=sws)
+    torch.cuda.synchronize()
+    wall_single = time.perf_counter() - t0
+    del dins, souts, sws, outs
+    torch.cuda.empty_cache()
+    log("serving: p50 %.1f ms p99 %.1f ms; saturated %.2f s, one call per request %.2f s"
+        % (1e3 * np.percentile(lat, 50), 1e3 * np.percentile(lat, 99), wall_sat, wall_single))
+    return {"workload": "rmat-hawkes-requests", "requests": count, "n_edges": total, "min_cluster_size": M,
+            "seed": 4, "arrivals": "poisson 200 req/s (open loop)",
+            "sizes": "lognormal median 70711 sigma 1.42 clipped [1e3, 5e6]; V = 2^ceil(log2(n/16))",
+            "workers": workers, "hbm_budget_bytes": budget_gib << 30,
+            "latency_p50_ms": 1e3 * float(np.percentile(lat, 50)), "latency_p99_ms": 1e3 * float(np.percentile(lat, 99)),
+            "latency_mean_ms": 1e3 * float(lat.mean()), "open_loop_edges_per_s": total / wall_open,
+            "open_loop_batches": st1["batches"] - st0["batches"],
+            "saturated_edges_per_s": total / wall_sat, "saturated_batches": st2["batches"] - st1["batches"],
+            "max_batch_requests": st2["max_batch_requests"], "max_concurrent_batches": st2["max_concurrent_batches"],
+            "single_edges_per_s": total / wall_single, "ratio": wall_single / wall_sat}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -123,6 +213,8 @@ def main():
     ap.add_argument("--workload", default="mid", choices=["tiny", "mid", "scale"])
     ap.add_argument("--cpu-sample", type=int, default=20_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=1000,
+                    help="requests of the serving stream to replay (0 skips the serving measurement)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-vs-one-graph-per-call measurement on the 4096-graph batch")
     ap.add_argument("--roofline-kernel", default="k_krt_accum",
@@ -208,6 +300,11 @@ def main():
         del src, dst, tt, outs, ws
         torch.cuda.empty_cache()
         line["batched"] = bench_batched(dev, max(1, min(args.steps, 3)), 1)
+    if args.serve_requests > 0:
+        if args.no_batch:
+            del src, dst, tt, outs, ws
+            torch.cuda.empty_cache()
+        line["serving"] = bench_serving(dev, args.serve_requests)
     if not args.no_cpu_baseline:
         log("cpu baseline on a sample")
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)

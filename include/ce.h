@@ -152,6 +152,84 @@ ce_status ce_cluster_batch(const int32_t *src, const int32_t *dst, const int64_t
                            int64_t *row_offsets, int64_t *cluster_offsets, void *workspace,
                            size_t workspace_bytes, void *stream);
 
+/*
+ * Serving: continuous batching of independent clustering requests on one GPU.
+ *
+ * A server allocates its whole HBM budget once (ce_server_create) and never
+ * allocates device memory afterwards. input_fraction_pct of it holds the
+ * records of admitted requests, resident until they finish; the rest is work
+ * memory. `workers` host threads each drive their own HIP stream: a free
+ * worker takes the oldest queued requests that share min_cluster_size and fit
+ * the free work memory (at most max_batch_records records, 0 = 2^26) and
+ * clusters them as one batch (the ce_cluster_batch computation), so requests
+ * that arrive while other batches run are admitted as memory frees up and the
+ * batches of different workers overlap on the device. Each request's result
+ * equals what ce_cluster_edges gives for it alone: graphs of a batch are
+ * clustered independently (Alg. 4 per graph).
+ */
+typedef struct ce_server ce_server;
+
+typedef struct {
+  uint32_t struct_size;         /* = sizeof(ce_server_config) */
+  int32_t device;               /* HIP device ordinal */
+  uint32_t workers;             /* 1..16 worker threads / streams */
+  uint32_t input_fraction_pct;  /* 1..90: share of the budget for resident request records */
+  uint64_t hbm_budget_bytes;    /* device memory the server owns (>= 1 MiB) */
+  int64_t max_inflight;         /* submitted but not yet polled-complete requests (>= 1) */
+  int64_t max_batch_records;    /* records per batch, 0 = 2^26 */
+} ce_server_config;
+
+typedef struct {
+  uint32_t struct_size;         /* = sizeof(ce_request) */
+  uint32_t reserved;            /* 0 */
+  const int32_t *src, *dst;     /* HOST arrays of n records, copied to the GPU before submit returns */
+  const int64_t *t;
+  int64_t n;
+  ce_params params;             /* min_cluster_size, num_vertices as for ce_cluster_edges */
+  ce_result out;                /* caller-owned DEVICE buffers with ce_cluster_edges capacities; written
+                                   when the request completes and must stay valid until then */
+} ce_request;
+
+typedef struct {
+  ce_status status;             /* the request's own outcome (e.g. CE_ESELFLOOP for its data) */
+  uint32_t reserved;
+  ce_counts counts;
+  double queue_s;               /* submit -> its batch starts */
+  double latency_s;             /* submit -> its outputs are written */
+} ce_request_status;
+
+typedef struct {
+  int64_t requests_submitted, requests_done, requests_batched, batches;
+  int64_t max_batch_requests, max_concurrent_batches;
+  int64_t input_peak_bytes, work_peak_bytes, input_capacity_bytes, work_capacity_bytes;
+} ce_server_stats;
+
+/* Starts the workers. CE_ENOMEM if the budget cannot be allocated. */
+ce_status ce_server_create(const ce_server_config *config, ce_server **server);
+
+/* Finishes every queued request, stops the workers and frees the budget. */
+ce_status ce_server_destroy(ce_server *server);
+
+/* Device bytes one request of n records occupies while it runs alone (inputs
+ * plus work memory): the admission footprint. Pure host function; 0 on
+ * invalid arguments. */
+size_t ce_server_request_bytes(int64_t n, const ce_params *params);
+
+/* Admits a request and returns its ticket. CE_ENOMEM: the request can never
+ * fit the budget; CE_EBUSY: max_inflight reached or input memory full now
+ * (retry after polling); CE_EINVAL: bad arguments. Thread-safe. */
+ce_status ce_server_submit(ce_server *server, const ce_request *request, uint64_t *ticket);
+
+/* CE_OK when the request has finished (its outcome and counts are in
+ * *status and the ticket is released), CE_EBUSY while it is still queued or
+ * running (with wait = 0; wait != 0 blocks until it finishes), CE_EINVAL for
+ * an unknown ticket. Thread-safe. */
+ce_status ce_server_poll(ce_server *server, uint64_t ticket, int wait, ce_request_status *status);
+
+/* Counters since creation (batches formed, largest batch, most batches
+ * running at once, peak memory of each region). */
+ce_status ce_server_get_stats(ce_server *server, ce_server_stats *stats);
+
 /* Thread-local text of the last error on this thread (never NULL). */
 const char *ce_last_error(void);
 

@@ -38,8 +38,36 @@ class CeCounts(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int64), ("n_clusters", ctypes.c_int64), ("n_labels", ctypes.c_int64)]
 
 
+class CeServerConfig(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("device", ctypes.c_int32), ("workers", ctypes.c_uint32),
+                ("input_fraction_pct", ctypes.c_uint32), ("hbm_budget_bytes", ctypes.c_uint64),
+                ("max_inflight", ctypes.c_int64), ("max_batch_records", ctypes.c_int64)]
+
+
+class CeRequest(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("src", ctypes.c_void_p),
+                ("dst", ctypes.c_void_p), ("t", ctypes.c_void_p), ("n", ctypes.c_int64), ("params", CeParams),
+                ("out", CeResult)]
+
+
+class CeRequestStatus(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("reserved", ctypes.c_uint32), ("counts", CeCounts),
+                ("queue_s", ctypes.c_double), ("latency_s", ctypes.c_double)]
+
+
+_STAT_FIELDS = ["requests_submitted", "requests_done", "requests_batched", "batches", "max_batch_requests",
+                "max_concurrent_batches", "input_peak_bytes", "work_peak_bytes", "input_capacity_bytes",
+                "work_capacity_bytes"]
+
+
+class CeServerStats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in _STAT_FIELDS]
+
+
 _EXPORTS = ["ce_cluster_edges", "ce_cluster_batch", "ce_workspace_bytes", "ce_batch_workspace_bytes",
-            "ce_max_clusters", "ce_last_error", "ce_timing_enable", "ce_timing_read"]
+            "ce_max_clusters", "ce_last_error", "ce_timing_enable", "ce_timing_read", "ce_server_create",
+            "ce_server_destroy", "ce_server_request_bytes", "ce_server_submit", "ce_server_poll",
+            "ce_server_get_stats"]
 CE_MAX_GRAPHS = 1 << 24
 _lib = None
 
@@ -63,6 +91,19 @@ def load_library(path: str = LIB_PATH):
         lib.ce_cluster_batch.restype = ctypes.c_int
         lib.ce_batch_workspace_bytes.argtypes = [i64p, i64p, ctypes.c_int64, ctypes.POINTER(CeParams)]
         lib.ce_batch_workspace_bytes.restype = ctypes.c_size_t
+        vp = ctypes.c_void_p
+        lib.ce_server_create.argtypes = [ctypes.POINTER(CeServerConfig), ctypes.POINTER(vp)]
+        lib.ce_server_create.restype = ctypes.c_int
+        lib.ce_server_destroy.argtypes = [vp]
+        lib.ce_server_destroy.restype = ctypes.c_int
+        lib.ce_server_request_bytes.argtypes = [ctypes.c_int64, ctypes.POINTER(CeParams)]
+        lib.ce_server_request_bytes.restype = ctypes.c_size_t
+        lib.ce_server_submit.argtypes = [vp, ctypes.POINTER(CeRequest), ctypes.POINTER(ctypes.c_uint64)]
+        lib.ce_server_submit.restype = ctypes.c_int
+        lib.ce_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.c_int, ctypes.POINTER(CeRequestStatus)]
+        lib.ce_server_poll.restype = ctypes.c_int
+        lib.ce_server_get_stats.argtypes = [vp, ctypes.POINTER(CeServerStats)]
+        lib.ce_server_get_stats.restype = ctypes.c_int
         lib.ce_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(CeParams)]
         lib.ce_workspace_bytes.restype = ctypes.c_size_t
         lib.ce_max_clusters.argtypes = [ctypes.c_int64, ctypes.c_int64]
@@ -313,6 +354,110 @@ def cluster_batch(src, dst, t, edge_offsets, vertex_offsets, min_cluster_size: i
     res = Result(m=m_tot, n_clusters=c_tot, n_labels=int(carr[:, 2].sum()), **rows, **pts, **cls)
     return BatchResult(result=res, m=carr[:, 0].copy(), n_clusters=carr[:, 1].copy(), n_labels=carr[:, 2].copy(),
                        edge_offsets=eo, row_offsets=roff, cluster_offsets=coff)
+
+
+class ServerBusy(ClusterError):
+    """The server cannot admit the request now (in-flight limit or input memory); retry after polling."""
+
+
+class RequestResult(NamedTuple):
+    status: int            # the request's own outcome (CE_OK or an error code)
+    error: str
+    result: Optional[Result]
+    queue_s: float
+    latency_s: float
+
+
+def server_request_bytes(n: int, num_vertices: int, min_cluster_size: int) -> int:
+    """Device bytes one request of n records occupies while it runs alone (the admission footprint)."""
+    p = make_params(min_cluster_size, num_vertices)
+    return int(load_library().ce_server_request_bytes(int(n), ctypes.byref(p)))
+
+
+class Server:
+    """Continuous-batching clustering server on one GPU (``ce_server_*``).
+
+    ``submit`` copies a request's host records to the GPU and returns a
+    ticket; ``poll`` returns None while the request is pending, else a
+    RequestResult with trimmed device tensors of its outputs.
+    """
+
+    def __init__(self, hbm_budget_bytes: int, workers: int = 2, max_inflight: int = 256,
+                 input_fraction_pct: int = 25, max_batch_records: int = 0, device: int = 0):
+        lib = load_library()
+        cfg = CeServerConfig(ctypes.sizeof(CeServerConfig), int(device), int(workers), int(input_fraction_pct),
+                             int(hbm_budget_bytes), int(max_inflight), int(max_batch_records))
+        h = ctypes.c_void_p()
+        st = lib.ce_server_create(ctypes.byref(cfg), ctypes.byref(h))
+        if st != CE_OK:
+            raise ClusterError(st, last_error(), "ce_server_create")
+        self._h = h
+        self._pending = {}
+
+    def submit(self, src, dst, t, min_cluster_size: int, num_vertices: int, outputs: Optional[Outputs] = None,
+               device=None) -> int:
+        import numpy as np
+        import torch
+        src = np.ascontiguousarray(src, dtype=np.int32)
+        dst = np.ascontiguousarray(dst, dtype=np.int32)
+        t = np.ascontiguousarray(t, dtype=np.int64)
+        n = int(src.shape[0])
+        if dst.shape[0] != n or t.shape[0] != n:
+            raise ValueError("src, dst, t must have the same length")
+        if outputs is None or outputs.n < n or outputs.C < max_clusters(n, min_cluster_size):
+            outputs = Outputs(n, min_cluster_size, device if device is not None else torch.device("cuda:0"))
+        req = CeRequest(ctypes.sizeof(CeRequest), 0, src.ctypes.data, dst.ctypes.data, t.ctypes.data, n,
+                        make_params(min_cluster_size, num_vertices), outputs.struct)
+        ticket = ctypes.c_uint64()
+        st = load_library().ce_server_submit(self._h, ctypes.byref(req), ctypes.byref(ticket))
+        if st == CE_EBUSY:
+            raise ServerBusy(st, last_error(), "ce_server_submit")
+        if st != CE_OK:
+            raise ClusterError(st, last_error(), "ce_server_submit")
+        self._pending[int(ticket.value)] = (outputs, n)
+        return int(ticket.value)
+
+    def poll(self, ticket: int, wait: bool = False) -> Optional[RequestResult]:
+        rs = CeRequestStatus()
+        st = load_library().ce_server_poll(self._h, int(ticket), 1 if wait else 0, ctypes.byref(rs))
+        if st == CE_EBUSY:
+            return None
+        if st != CE_OK:
+            raise ClusterError(st, last_error(), "ce_server_poll")
+        outputs, n = self._pending.pop(int(ticket))
+        err = last_error() if rs.status != CE_OK else ""
+        res = None
+        if rs.status == CE_OK:
+            m, nc, nl = int(rs.counts.m), int(rs.counts.n_clusters), int(rs.counts.n_labels)
+            o = outputs.t
+            rows = {f: o[f][:m] for f in ("msf_tail", "msf_head", "msf_w", "sl_left", "sl_right", "sl_w", "sl_size")}
+            pts = {f: o[f][:n] for f in ("pt_cluster", "pt_lambda", "labels")}
+            cls = {f: o[f][:nc] for f in ("cl_id", "cl_parent", "cl_size", "cl_lambda_birth", "cl_stab_hi",
+                                          "cl_stab_lo", "cl_selected")}
+            res = Result(m=m, n_clusters=nc, n_labels=nl, **rows, **pts, **cls)
+        return RequestResult(int(rs.status), err, res, float(rs.queue_s), float(rs.latency_s))
+
+    def stats(self) -> dict:
+        s = CeServerStats()
+        load_library().ce_server_get_stats(self._h, ctypes.byref(s))
+        return {f: int(getattr(s, f)) for f in _STAT_FIELDS}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().ce_server_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 _UNSIGNED = {"msf_tail": "u4", "msf_head": "u4", "sl_left": "u4", "sl_right": "u4", "sl_size": "u4",

@@ -19,7 +19,9 @@ def test_library_exports_declared_symbols():
     lib = ce.load_library()
     syms = declared_symbols()
     assert set(syms) == {"ce_cluster_edges", "ce_cluster_batch", "ce_workspace_bytes", "ce_batch_workspace_bytes",
-                         "ce_max_clusters", "ce_last_error", "ce_timing_enable", "ce_timing_read"}
+                         "ce_max_clusters", "ce_last_error", "ce_timing_enable", "ce_timing_read",
+                         "ce_server_create", "ce_server_destroy", "ce_server_request_bytes", "ce_server_submit",
+                         "ce_server_poll", "ce_server_get_stats"}
     for s in syms:
         assert hasattr(lib, s), s
 
@@ -108,3 +110,57 @@ def test_batch_argument_errors_need_no_gpu():
     assert call([0, 4], [0, 3], 1) == ce.CE_EINVAL  # null record pointers with 4 records
     assert "input pointer" in ce.last_error()
     assert call([0, 1 << 31], [0, 3], 1) == ce.CE_EINVAL
+
+
+def test_struct_layouts_match_the_header(tmp_path):
+    """The ctypes mirrors have the sizes and field offsets a C compiler gives the header's structs."""
+    import ctypes
+    import shutil
+    import subprocess
+    import paper_2311_10337_amd as ce
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    mirrors = {"ce_params": ce.CeParams, "ce_result": ce.CeResult, "ce_counts": ce.CeCounts,
+               "ce_server_config": ce.CeServerConfig, "ce_request": ce.CeRequest,
+               "ce_request_status": ce.CeRequestStatus, "ce_server_stats": ce.CeServerStats}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ce.h"', "int main(void) {"]
+    for cname, py in mirrors.items():
+        lines.append('  printf("%s size %%zu\\n", sizeof(%s));' % (cname, cname))
+        for f, _ in py._fields_:
+            lines.append('  printf("%s %s %%zu\\n", offsetof(%s, %s));' % (cname, f, cname, f))
+    lines.append("  return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = {}
+    for line in out:
+        if line.strip():
+            a, b, c = line.split()
+            got[(a, b)] = int(c)
+    for cname, py in mirrors.items():
+        assert got[(cname, "size")] == ctypes.sizeof(py), cname
+        for f, _ in py._fields_:
+            assert got[(cname, f)] == getattr(py, f).offset, (cname, f)
+
+
+def test_server_host_checks_need_no_gpu():
+    import ctypes
+    import paper_2311_10337_amd as ce
+    if not os.path.exists(ce.LIB_PATH):
+        pytest.skip("libce.so not built")
+    lib = ce.load_library()
+    h = ctypes.c_void_p()
+    for kw in ({"workers": 0}, {"workers": 17}, {"hbm_budget_bytes": 1000}, {"max_inflight": 0},
+               {"input_fraction_pct": 0}, {"input_fraction_pct": 95}):
+        cfg = dict(struct_size=ctypes.sizeof(ce.CeServerConfig), device=0, workers=2, input_fraction_pct=25,
+                   hbm_budget_bytes=1 << 30, max_inflight=8, max_batch_records=0)
+        cfg.update(kw)
+        assert lib.ce_server_create(ctypes.byref(ce.CeServerConfig(**cfg)), ctypes.byref(h)) == ce.CE_EINVAL, kw
+    # the admission footprint grows with n and is 0 for bad arguments
+    a = ce.server_request_bytes(10_000, 1000, 10)
+    b = ce.server_request_bytes(100_000, 1000, 10)
+    assert 0 < a < b
+    assert ce.server_request_bytes(-1, 1000, 10) == 0 and ce.server_request_bytes(10, 1000, 1) == 0
