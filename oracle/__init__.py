@@ -59,7 +59,7 @@ def _load():
         lib.oracle_kruskal.restype = i64
         lib.oracle_dendrogram.argtypes = [i64, i64, p, p, p, p, p, p, p]
         lib.oracle_dendrogram.restype = ctypes.c_int
-        lib.oracle_condense.argtypes = [i64, i64, p, p, p, p, i64] + [p] * 11 + [p]
+        lib.oracle_condense.argtypes = [i64, i64, p, p, p, p, i64] + [p] * 10 + [p]
         lib.oracle_condense.restype = ctypes.c_int
         lib.oracle_cluster.argtypes = [i64, p, p, p, i64, i64, ctypes.c_int] + [p] * 18
         lib.oracle_cluster.restype = ctypes.c_int

@@ -183,40 +183,61 @@ ce_status stage_write_rows(Bufs &b, int64_t m, const ce_result *out, hipStream_t
   return CE_OK;
 }
 
+// Workspace: a few persistent arrays, then a phase area holding
+//   X  skeleton and Boruvka state (live until the MSF is sorted), at its start
+//   Y  sorted MSF, dendrogram and row placement (live from the MSF sort on), at its end
+// Scratch A (grouping, skeleton, Boruvka) follows X and may overlap Y; scratch
+// M (MSF sort) lies between X and Y; scratch B (dendrogram, condensing) starts
+// at the phase area and overlaps X.
 static void layout(Bufs &b, Ws &ws, int64_t n, int64_t M, int64_t G) {
   b.hdr = ws.alloc<uint64_t>(16);
   b.eoff = ws.alloc<int64_t>(G + 1);
   b.voff = ws.alloc<int64_t>(G + 1);
-  b.ts = ws.alloc<uint64_t>(n);
   b.perm = ws.alloc<uint32_t>(n);
   b.grank = ws.alloc<uint32_t>(n);
+  const size_t base = ws.off;
+  b.ts = ws.alloc<uint64_t>(n);
   b.skel_key = ws.alloc<uint64_t>(2 * n);
   b.skel_tail = ws.alloc<uint32_t>(2 * n);
   b.skel_tid = ws.alloc<uint32_t>(2 * n);
   b.best = ws.alloc<uint64_t>(n);
   b.msf_flag = ws.alloc<uint8_t>(2 * n);
+  const size_t xbytes = ws.off - base;
+  Ws y;
+  y.alloc<uint64_t>(n);
+  y.alloc<uint4>(n);
+  for (int k = 0; k < 5; k++) y.alloc<uint32_t>(n);
+  y.alloc<uint32_t>(G + 1);
+  const size_t ybytes = y.off;
+  size_t scr_a = stage_sort_skeleton_scratch(n);
+  size_t x = stage_boruvka_scratch(n);
+  if (x > scr_a) scr_a = x;
+  const size_t scr_m = stage_msf_sort_scratch(n);
+  size_t scr_b = stage_dendrogram_scratch(n);
+  x = stage_graph_rows_scratch(n, G);
+  if (x > scr_b) scr_b = x;
+  x = stage_condense_scratch(n, M, G);
+  if (x > scr_b) scr_b = x;
+  auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
+  size_t phase = xbytes + al(scr_a);
+  if (xbytes + al(scr_m) + ybytes > phase) phase = xbytes + al(scr_m) + ybytes;
+  if (al(scr_b) + ybytes > phase) phase = al(scr_b) + ybytes;
+  ws.off = base + phase - ybytes;
   b.msf_key = ws.alloc<uint64_t>(n);
   b.msf_val = ws.alloc<uint4>(n);
   b.kc_u = ws.alloc<uint32_t>(n);
   b.kc_v = ws.alloc<uint32_t>(n);
   b.ksize = ws.alloc<uint32_t>(n);
-  // the skeleton is dead once the MSF is sorted: the row-placement arrays reuse it
-  b.rowg = b.skel_tail;
-  b.rowpos = b.skel_tail + n;
+  b.rowg = ws.alloc<uint32_t>(n);
+  b.rowpos = ws.alloc<uint32_t>(n);
   b.moff = ws.alloc<uint32_t>(G + 1);
-  size_t sc = stage_sort_skeleton_scratch(n);
-  size_t x = stage_boruvka_scratch(n);
-  if (x > sc) sc = x;
-  x = stage_msf_sort_scratch(n);
-  if (x > sc) sc = x;
-  x = stage_dendrogram_scratch(n);
-  if (x > sc) sc = x;
-  x = stage_graph_rows_scratch(n, G);
-  if (x > sc) sc = x;
-  x = stage_condense_scratch(n, M, G);
-  if (x > sc) sc = x;
-  b.scratch = ws.alloc<char>(sc);
-  b.scratch_bytes = sc;
+  char *pb = ws.base ? ws.base + base : nullptr;
+  b.scratch_a = pb ? pb + xbytes : nullptr;
+  b.scratch_a_bytes = phase - xbytes;
+  b.scratch_m = b.scratch_a;
+  b.scratch_m_bytes = phase - xbytes - ybytes;
+  b.scratch_b = pb;
+  b.scratch_b_bytes = phase - ybytes;
 }
 
 static size_t workspace_for(int64_t n, int64_t M, int64_t G) {
@@ -321,18 +342,22 @@ static ce_status run_batch(const int32_t *src, const int32_t *dst, const int64_t
     set_error("time span too wide: bits(span) + bits(n-1) + 1 > 64");
     return CE_ERANGE;
   }
-  Ws sw;
-  sw.base = b.scratch;
-  sw.cap = b.scratch_bytes;
+  Ws wa, wm, wb;
+  wa.base = b.scratch_a;
+  wa.cap = b.scratch_a_bytes;
+  wm.base = b.scratch_m;
+  wm.cap = b.scratch_m_bytes;
+  wb.base = b.scratch_b;
+  wb.cap = b.scratch_b_bytes;
   int64_t m = 0;
   std::vector<int64_t> roff(G + 1);
-  CE_TRY(stage_sort_skeleton(src, dst, t, b, sw, s));
-  CE_TRY(stage_boruvka(b, sw, s));
-  CE_TRY(stage_msf_sort(b, sw, s, &m));
-  CE_TRY(stage_dendrogram(b, m, sw, s));
-  CE_TRY(stage_graph_rows(b, m, sw, s, roff.data()));
+  CE_TRY(stage_sort_skeleton(src, dst, t, b, wa, s));
+  CE_TRY(stage_boruvka(b, wa, s));
+  CE_TRY(stage_msf_sort(b, wm, s, &m));
+  CE_TRY(stage_dendrogram(b, m, wb, s));
+  CE_TRY(stage_graph_rows(b, m, wb, s, roff.data()));
   CE_TRY(stage_write_rows(b, m, out, s));
-  CE_TRY(stage_condense(b, m, out, sw, s, counts, cluster_offsets));
+  CE_TRY(stage_condense(b, m, out, wb, s, counts, cluster_offsets));
   for (int64_t g = 0; g < G; g++) counts[g].m = roff[g + 1] - roff[g];
   if (row_offsets)
     for (int64_t g = 0; g <= G; g++) row_offsets[g] = roff[g];

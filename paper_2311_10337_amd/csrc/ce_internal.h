@@ -274,7 +274,7 @@ struct Bufs {
   int64_t G = 1;
   const int64_t *eoff = nullptr, *voff = nullptr;
   uint32_t *grank = nullptr;    // [n] graph of each record, by rank
-  uint32_t *rowg = nullptr;     // [n] graph of each MSF row (aliases the dead skeleton tails)
+  uint32_t *rowg = nullptr;     // [n] graph of each MSF row
   uint32_t *rowpos = nullptr;   // [n] output position of each MSF row (graphs in order, rows in key order)
   uint32_t *moff = nullptr;     // [G+1] first output row of each graph
   int tbits = 0, idbits = 0, vbits = 0, keybits = 0;
@@ -291,9 +291,11 @@ struct Bufs {
   uint64_t *msf_key = nullptr;  // [n] sorted MSF keys
   uint4 *msf_val = nullptr;     // [n] (tail rank, head rank, tail input id, 0); the head's id is in the key
   uint32_t *kc_u = nullptr, *kc_v = nullptr, *ksize = nullptr; // [n] dendrogram children (internal labels) and size
-  // scratch arena (aliased across stages)
-  char *scratch = nullptr;
-  size_t scratch_bytes = 0;
+  // scratch arenas: A for grouping, skeleton and Boruvka (it may overlap the
+  // MSF/dendrogram arrays, which are not live yet), M for sorting the MSF, B
+  // for the dendrogram and condensing (it overlaps the dead skeleton arrays)
+  char *scratch_a = nullptr, *scratch_m = nullptr, *scratch_b = nullptr;
+  size_t scratch_a_bytes = 0, scratch_m_bytes = 0, scratch_b_bytes = 0;
 };
 
 // host pinned staging for small readbacks (per thread)

@@ -38,7 +38,7 @@ def test_host_only_functions():
     assert ce.workspace_bytes(10, 0, 5) == 0
     assert ce.workspace_bytes(10, 10, 1) == 0
     # about 100 bytes of workspace per record at scale
-    assert ce.workspace_bytes(10 ** 7, 10 ** 6, 10) / 10 ** 7 < 210  # bytes of workspace per record
+    assert ce.workspace_bytes(10 ** 7, 10 ** 6, 10) / 10 ** 7 < 170  # bytes of workspace per record
 
 
 def test_host_argument_errors_need_no_gpu():
