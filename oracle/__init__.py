@@ -59,6 +59,8 @@ def _load():
         lib.oracle_kruskal.restype = i64
         lib.oracle_dendrogram.argtypes = [i64, i64, p, p, p, p, p, p, p]
         lib.oracle_dendrogram.restype = ctypes.c_int
+        lib.oracle_joined_below.argtypes = [i64, i64, p, p, p, i64, p, p, p, p]
+        lib.oracle_joined_below.restype = ctypes.c_int
         lib.oracle_condense.argtypes = [i64, i64, p, p, p, p, i64] + [p] * 10 + [p]
         lib.oracle_condense.restype = ctypes.c_int
         lib.oracle_cluster.argtypes = [i64, p, p, p, i64, i64, ctypes.c_int] + [p] * 18
@@ -145,6 +147,22 @@ def dendrogram(n, msf_tail, msf_head, msf_w):
     if rc:
         raise RuntimeError("oracle_dendrogram: %d" % rc)
     return left[:m], right[:m], lw[:m], size[:m]
+
+
+def joined_below(n, msf_tail, msf_head, msf_w, q_tail, q_head, q_w) -> np.ndarray:
+    """Cycle-property check: for each query edge, whether forest rows of smaller key already join its records."""
+    mt = np.ascontiguousarray(msf_tail, np.uint32)
+    mh = np.ascontiguousarray(msf_head, np.uint32)
+    mw = np.ascontiguousarray(msf_w, np.int64)
+    qt = np.ascontiguousarray(q_tail, np.uint32)
+    qh = np.ascontiguousarray(q_head, np.uint32)
+    qw = np.ascontiguousarray(q_w, np.int64)
+    out = np.empty(max(qt.size, 1), np.uint8)
+    rc = _load().oracle_joined_below(int(n), mt.size, mt.ctypes.data, mh.ctypes.data, mw.ctypes.data, qt.size,
+                                     qt.ctypes.data, qh.ctypes.data, qw.ctypes.data, out.ctypes.data)
+    if rc:
+        raise RuntimeError("oracle_joined_below: %d" % rc)
+    return out[:qt.size].astype(bool)
 
 
 def max_clusters(n, M):

@@ -255,6 +255,57 @@ int oracle_dendrogram(int64_t n, int64_t m, const uint32_t *msf_tail, const uint
   return OR_OK;
 }
 
+/*
+ * Checker for the cycle property of the minimum spanning forest (App. A):
+ * with the forest rows in ascending K (R3), out[i] = 1 when query edge i's
+ * two records are already joined by rows of smaller key. In the unique MSF,
+ * every line-graph edge that is not a row closes a cycle on which it has the
+ * largest key, so it is joined below; a row itself is not. Used to check a
+ * forest at sizes where Kruskal over all edges is too slow.
+ */
+typedef struct {
+  lg_edge e;
+  int64_t idx;
+} lg_query;
+
+static int cmp_query(const void *pa, const void *pb) {
+  return cmp_key(&((const lg_query *)pa)->e, &((const lg_query *)pb)->e);
+}
+
+int oracle_joined_below(int64_t n, int64_t m, const uint32_t *msf_tail, const uint32_t *msf_head,
+                        const int64_t *msf_w, int64_t q, const uint32_t *q_tail, const uint32_t *q_head,
+                        const int64_t *q_w, uint8_t *out) {
+  lg_query *qs = (lg_query *)malloc(sizeof(lg_query) * (size_t)(q ? q : 1));
+  uint32_t *par = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n ? n : 1));
+  if (!qs || !par) { free(qs); free(par); return OR_ENOMEM; }
+  for (int64_t i = 0; i < q; i++) {
+    if (q_tail[i] >= (uint64_t)n || q_head[i] >= (uint64_t)n) { free(qs); free(par); return OR_EINVAL; }
+    qs[i].e.w = q_w[i];
+    qs[i].e.tail = q_tail[i];
+    qs[i].e.head = q_head[i];
+    qs[i].idx = i;
+  }
+  qsort(qs, (size_t)q, sizeof(lg_query), cmp_query);
+  for (int64_t i = 0; i < n; i++) par[i] = (uint32_t)i;
+  int64_t j = 0;
+  for (int64_t k = 0; k < q; k++) {
+    while (j < m) {
+      lg_edge r;
+      r.w = msf_w[j];
+      r.tail = msf_tail[j];
+      r.head = msf_head[j];
+      if (cmp_key(&r, &qs[k].e) >= 0) break;
+      uint32_t a = uf_find(par, r.tail), b = uf_find(par, r.head);
+      if (a != b) par[a] = b;
+      j++;
+    }
+    out[qs[k].idx] = uf_find(par, qs[k].e.tail) == uf_find(par, qs[k].e.head);
+  }
+  free(qs);
+  free(par);
+  return OR_OK;
+}
+
 /* R5 */
 static uint64_t lam(int64_t w) {
   if (w <= 0) return (uint64_t)1 << 63;

@@ -529,3 +529,63 @@ def test_condensed_invariants_on_tiny_workload():
     s, d, tt = w.src[:3000], w.dst[:3000], w.t[:3000]
     assert_same_result(oracle.cluster(s, d, tt, M, w.num_vertices, tier=0),
                        oracle.cluster(s, d, tt, M, w.num_vertices, tier=1))
+
+
+def test_joined_below_is_the_cycle_property():
+    """The forest checker: on the MSF every non-row line-graph edge is joined below and no row is; replacing a
+    row by a heavier edge across the same cut is caught."""
+    rng = np.random.default_rng(41)
+    swaps = 0
+    for trial in range(60):
+        n = int(rng.integers(2, 40))
+        s, d, t = _random_tie_heavy(rng, n, int(rng.integers(2, 8)), int(rng.choice([3, 50])))
+        edges = oracle.full_line_graph(s, d, t)
+        mt, mh, mw = oracle.kruskal(n, edges, t)
+        if len(edges) == 0:
+            continue
+        got = oracle.joined_below(n, mt, mh, mw, edges["tail"], edges["head"], edges["w"])
+        rows = set(zip(mt.tolist(), mh.tolist()))
+        is_row = np.array([(a, b) in rows for a, b in zip(edges["tail"].tolist(), edges["head"].tolist())])
+        assert np.array_equal(got, ~is_row), trial
+        # swap: drop row k, add the cheapest non-row edge that reconnects its two sides (if any); the dropped row
+        # is then not joined below while it is no row any more
+        if len(mt) == 0:
+            continue
+        k = int(rng.integers(0, len(mt)))
+        keep = [i for i in range(len(mt)) if i != k]
+        g = nx.Graph()
+        g.add_nodes_from(range(n))
+        g.add_edges_from((int(mt[i]), int(mh[i])) for i in keep)
+        comp = nx.node_connected_component(g, int(mt[k]))
+        across = [e for e in edges if (int(e["tail"]) in comp) != (int(e["head"]) in comp)
+                  and (int(e["tail"]), int(e["head"])) != (int(mt[k]), int(mh[k]))]
+        if not across:
+            continue
+        alt = min(across, key=lambda e: (int(e["w"]), int(e["head"]), -int(e["tail"])))
+        ft = np.append(mt[keep], alt["tail"]).astype(np.uint32)
+        fh = np.append(mh[keep], alt["head"]).astype(np.uint32)
+        fw = np.append(mw[keep], alt["w"]).astype(np.int64)
+        order = sorted(range(len(ft)), key=lambda i: (int(fw[i]), int(fh[i]), -int(ft[i])))
+        ft, fh, fw = ft[order], fh[order], fw[order]
+        bad = oracle.joined_below(n, ft, fh, fw, mt[k:k + 1], mh[k:k + 1], mw[k:k + 1])
+        assert not bad[0], trial
+        swaps += 1
+    assert swaps >= 10
+
+
+def test_condense_wrapper_equals_full_pipeline():
+    """oracle.condense(oracle.dendrogram(MSF)) reproduces oracle.cluster on a mid-sized sample."""
+    import synth
+    w = synth.plain_tiny()
+    r = oracle.cluster(w.src, w.dst, w.t, w.min_cluster_size, w.num_vertices, tier=1)
+    L, R, W, S = oracle.dendrogram(w.n, r.msf_tail, r.msf_head, r.msf_w)
+    assert np.array_equal(L, r.sl_left) and np.array_equal(R, r.sl_right) and np.array_equal(S, r.sl_size)
+    c = oracle.condense(w.n, L, R, W, S, w.min_cluster_size)
+    for f in ("pt_cluster", "pt_lambda", "cl_id", "cl_parent", "cl_size", "cl_lambda_birth", "cl_stab_hi",
+              "cl_stab_lo", "cl_selected", "labels"):
+        assert np.array_equal(getattr(c, f), getattr(r, f)), f
+    assert c.n_labels == r.n_labels
+    # a forest with a cycle is rejected
+    with pytest.raises(RuntimeError):
+        oracle.dendrogram(3, np.array([0, 1, 0], np.uint32), np.array([1, 2, 2], np.uint32),
+                          np.array([1, 1, 2], np.int64))
