@@ -46,6 +46,7 @@
  *   cluster rows in ascending id (ROOT last).
  */
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -192,6 +193,23 @@ int64_t oracle_skeleton(int64_t n, const int32_t *src, const int32_t *dst, const
   return cnt;
 }
 
+/* progress lines on stderr for runs of billions of rows (CE_ORACLE_PROGRESS=1) */
+static int progress_on(void) {
+  static int on = -1;
+  if (on < 0) {
+    const char *e = getenv("CE_ORACLE_PROGRESS");
+    on = e && e[0] == '1';
+  }
+  return on;
+}
+static void progress(const char *what, int64_t done, int64_t total) {
+  if (!progress_on()) return;
+  fprintf(stderr, "[oracle] %s %lld/%lld\n", what, (long long)done, (long long)total);
+  fflush(stderr);
+}
+#define PROGRESS_EVERY(k, what, total) \
+  do { if (((k) & ((1 << 26) - 1)) == 0) progress((what), (k), (total)); } while (0)
+
 /* plain union-find with path halving */
 static uint32_t uf_find(uint32_t *par, uint32_t x) {
   while (par[x] != x) {
@@ -240,6 +258,7 @@ int oracle_dendrogram(int64_t n, int64_t m, const uint32_t *msf_tail, const uint
   if (!par || !node || !sz) { free(par); free(node); free(sz); return OR_ENOMEM; }
   for (int64_t i = 0; i < n; i++) { par[i] = (uint32_t)i; node[i] = (uint32_t)i; sz[i] = 1; }
   for (int64_t k = 0; k < m; k++) {
+    PROGRESS_EVERY(k, "dendrogram rows", m);
     uint32_t a = uf_find(par, msf_tail[k]), b = uf_find(par, msf_head[k]);
     if (a == b) { free(par); free(node); free(sz); return OR_EINVAL; } /* not a forest */
     uint32_t na = node[a], nb = node[b];
@@ -289,7 +308,9 @@ int oracle_joined_below(int64_t n, int64_t m, const uint32_t *msf_tail, const ui
   for (int64_t i = 0; i < n; i++) par[i] = (uint32_t)i;
   int64_t j = 0;
   for (int64_t k = 0; k < q; k++) {
+    PROGRESS_EVERY(k, "cycle-property queries", q);
     while (j < m) {
+      PROGRESS_EVERY(j, "cycle-property rows", m);
       lg_edge r;
       r.w = msf_w[j];
       r.tail = msf_tail[j];
@@ -366,6 +387,7 @@ int oracle_condense(int64_t n, int64_t m, const uint32_t *left, const uint32_t *
     }                                                                      \
   } while (0)
 
+  progress("condense: parents", 1, 1);
   /* R6 at ROOT: count components of size >= M */
   int64_t nbig = 0;
   for (int64_t x = 0; x < N; x++)
@@ -411,6 +433,7 @@ int oracle_condense(int64_t n, int64_t m, const uint32_t *left, const uint32_t *
 #undef SHED
   free(wl_node);
 
+  progress("condense: exits", 1, 1);
   /* O8 stability: points that leave C, and child clusters born inside C */
   for (int64_t p = 0; p < n; p++) {
     uint32_t C = pt_cluster[p];
@@ -437,6 +460,7 @@ int oracle_condense(int64_t n, int64_t m, const uint32_t *left, const uint32_t *
     nc++;
   }
 
+  progress("condense: stability", 1, 1);
   /* O9 excess of mass: explicit post-order over the cluster tree */
   int64_t *child_cnt = (int64_t *)calloc((size_t)nc, sizeof(int64_t));
   u128 *best = (u128 *)calloc((size_t)nc, sizeof(u128));
@@ -477,6 +501,7 @@ int oracle_condense(int64_t n, int64_t m, const uint32_t *left, const uint32_t *
     cl_selected[r] = (uint8_t)chosen;
     lab_row[r] = chosen ? (int32_t)r : (anc_sel[r] ? lab_row[pr] : -1);
   }
+  progress("condense: selection", 1, 1);
   /* O10 labels */
   int32_t *lab_of_row = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nc ? nc : 1));
   int64_t *minmem = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nc ? nc : 1));

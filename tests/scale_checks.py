@@ -62,7 +62,9 @@ def sample_line_graph_edges(src, dst, t, V, n_vertices, per_vertex, seed):
     return tail, head, t[head] - t[tail]
 
 
-def check_result(src, dst, t, V, M, got, n_vertices=4000, per_vertex=64, seed=7, log=print):
+def check_msf_and_dendrogram(data, got, n_vertices=4000, per_vertex=64, seed=7, log=print):
+    """data: {"src", "dst", "t", "V"}; got: the result as host arrays. Consumes data's arrays."""
+    src, dst, t, V = data["src"], data["dst"], data["t"], data["V"]
     n = len(src)
     m = got["m"]
     tail = got["msf_tail"].astype(np.int64)
@@ -74,6 +76,7 @@ def check_result(src, dst, t, V, M, got, n_vertices=4000, per_vertex=64, seed=7,
         share = ((src[tail] == src[head]) | (src[tail] == dst[head]) | (dst[tail] == src[head]) |
                  (dst[tail] == dst[head]))
         assert share.all(), "an MSF row joins records that share no vertex"
+        del share
         assert np.array_equal(mw, t[head] - t[tail]), "MSF weight"
         assert np.all((t[tail] < t[head]) | ((t[tail] == t[head]) & (tail < head))), "row orientation"
         assert np.all(key_lt(mw[:-1], head[:-1], tail[:-1], mw[1:], head[1:], tail[1:])), "row order"
@@ -86,15 +89,20 @@ def check_result(src, dst, t, V, M, got, n_vertices=4000, per_vertex=64, seed=7,
     _, lab = connected_components(g, directed=False)
     del g
     c_line = len(np.unique(lab[deg > 0]))
+    del lab, deg
     assert m == n - c_line, "forest size %d, line graph needs %d rows" % (m, n - c_line)
     log("components %d" % c_line)
+
+    qt, qh, qw = sample_line_graph_edges(src, dst, t, V, n_vertices, per_vertex, seed)
+    data.clear()
+    del src, dst, t
 
     L, R, LW, S = oracle.dendrogram(n, got["msf_tail"], got["msf_head"], mw)  # raises on a cycle
     for f, ref in (("sl_left", L), ("sl_right", R), ("sl_w", LW), ("sl_size", S)):
         assert np.array_equal(got[f], ref), f
+    del L, R, LW, S
     log("dendrogram equal")
 
-    qt, qh, qw = sample_line_graph_edges(src, dst, t, V, n_vertices, per_vertex, seed)
     joined = oracle.joined_below(n, got["msf_tail"], got["msf_head"], mw, qt, qh, qw)
     # a sampled pair not joined below must itself be a row (a row joined below would have closed a cycle,
     # which the union-find above rejects)
@@ -109,8 +117,18 @@ def check_result(src, dst, t, V, M, got, n_vertices=4000, per_vertex=64, seed=7,
     assert found.all(), "cycle property fails for %d sampled edges" % int((~found).sum())
     log("cycle property on %d sampled line-graph edges (%d of them rows)" % (len(qt), len(U)))
 
-    c = oracle.condense(n, L, R, LW, S, M)
+
+def check_condensed(n, M, got, log=print):
+    """Condensed tree, stabilities, selection and labels: the oracle's condensing on the result's own
+    dendrogram rows (checked equal to the oracle's union-find by check_msf_and_dendrogram)."""
+    c = oracle.condense(n, got["sl_left"], got["sl_right"], got["sl_w"], got["sl_size"], M)
     assert (got["n_clusters"], got["n_labels"]) == (len(c.cl_id), c.n_labels)
     for f in FIELDS_AFTER_MSF:
         assert np.array_equal(got[f], getattr(c, f)), f
     log("condensed tree and labels equal")
+
+
+def check_result(src, dst, t, V, M, got, n_vertices=4000, per_vertex=64, seed=7, log=print):
+    n = len(src)
+    check_msf_and_dendrogram({"src": src, "dst": dst, "t": t, "V": V}, got, n_vertices, per_vertex, seed, log)
+    check_condensed(n, M, got, log)

@@ -2,9 +2,12 @@
 365-day Hawkes times, M = 25), in the launch configuration bench.py times.
 
 The full oracle would need hours of one host core here, so the MSF is checked
-by the properties that pin it and everything after it exactly by the oracle
-run on the GPU's MSF rows (tests/scale_checks.py). Runs only with
-CE_SCALE_TEST=1: about ten minutes and 150 GB of host memory.
+by the properties that pin it, the dendrogram exactly by the oracle's
+union-find on the GPU's MSF rows, and the condensed tree, stabilities,
+selection and labels exactly by the oracle's condensing on the GPU's
+dendrogram rows (tests/scale_checks.py). Two tests, each about ten minutes of
+host work and up to 200 GB of host memory; they run only with
+CE_SCALE_TEST=1, one per process (-k msf, -k condensed).
 """
 import os
 import sys
@@ -13,11 +16,11 @@ import time
 import pytest
 
 import synth
-from scale_checks import check_result
+from scale_checks import check_condensed, check_msf_and_dendrogram
 
 torch = pytest.importorskip("torch")
 pytestmark = [pytest.mark.gpu, pytest.mark.skipif(os.environ.get("CE_SCALE_TEST") != "1",
-                                                  reason="2^30-record check: set CE_SCALE_TEST=1 (long, 150 GB host)")]
+                                                  reason="2^30-record check: set CE_SCALE_TEST=1 (long, 200 GB host)")]
 
 
 def note(msg):
@@ -25,20 +28,36 @@ def note(msg):
     sys.stdout.flush()
 
 
-@pytest.mark.timeout(1150)
-def test_scale_workload():
+def run_scale(keep_inputs):
     import paper_2311_10337_amd as ce
+    os.environ["CE_ORACLE_PROGRESS"] = "1"
     w = synth.plain_scale()
-    n, V, M = w.n, w.num_vertices, w.min_cluster_size
-    note("generated n=%d V=%d" % (n, V))
+    note("generated n=%d V=%d" % (w.n, w.num_vertices))
     dev = torch.device("cuda:0")
     s_d = torch.from_numpy(w.src).to(dev)
     d_d = torch.from_numpy(w.dst).to(dev)
     t_d = torch.from_numpy(w.t).to(dev)
-    res = ce.cluster_edges(s_d, d_d, t_d, M, V)
+    res = ce.cluster_edges(s_d, d_d, t_d, w.min_cluster_size, w.num_vertices)
     del s_d, d_d, t_d
     got = ce.to_numpy(res)
     del res
     torch.cuda.empty_cache()
     note("gpu done: m=%d clusters=%d labels=%d" % (got["m"], got["n_clusters"], got["n_labels"]))
-    check_result(w.src, w.dst, w.t, V, M, got, log=note)
+    data = {"src": w.src, "dst": w.dst, "t": w.t, "V": w.num_vertices} if keep_inputs else None
+    return w.n, w.min_cluster_size, data, got
+
+
+@pytest.mark.timeout(1150)
+def test_scale_msf_and_dendrogram():
+    n, M, data, got = run_scale(True)
+    for f in ("pt_cluster", "pt_lambda", "labels"):
+        del got[f]
+    check_msf_and_dendrogram(data, got, log=note)
+
+
+@pytest.mark.timeout(1150)
+def test_scale_condensed():
+    n, M, _, got = run_scale(False)
+    for f in ("msf_tail", "msf_head", "msf_w"):
+        del got[f]
+    check_condensed(n, M, got, log=note)
