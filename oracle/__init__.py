@@ -6,9 +6,11 @@ it; the two share no code. The arithmetic lives in ``ce_oracle.c`` (plain C,
 host only); this module is argument marshalling.
 
 Tier A (``tier=0``) is the definition: the full undirected line graph
-(Sec. 1.2.2) and Kruskal in canonical-key order. Tier B (``tier=1``) follows
-the method's own steps: per-vertex time-sorted incidence lists, the path
-skeleton (Alg. 3 with the undirected node-local MST of Sec. 5.3), Kruskal.
+(Sec. 1.2.2), or with ``causal=True`` the increment-weighted line graph of
+Def. 1, and Kruskal in canonical-key order. Tier B (``tier=1``) follows the
+method's own steps: per-vertex time-sorted incidence lists, then the path
+skeleton (Alg. 3 with the undirected node-local MST of Sec. 5.3) or the
+Alg. 2 windows, then Kruskal.
 Both continue with the union-find dendrogram and the HDBSCAN condensing and
 excess-of-mass extraction of Alg. 1.
 """
@@ -63,7 +65,11 @@ def _load():
         lib.oracle_joined_below.restype = ctypes.c_int
         lib.oracle_condense.argtypes = [i64, i64, p, p, p, p, i64] + [p] * 10 + [p]
         lib.oracle_condense.restype = ctypes.c_int
-        lib.oracle_cluster.argtypes = [i64, p, p, p, i64, i64, ctypes.c_int] + [p] * 18
+        lib.oracle_causal_line_graph.argtypes = [i64, p, p, p, i64, p]
+        lib.oracle_causal_line_graph.restype = i64
+        lib.oracle_causal_skeleton.argtypes = [i64, p, p, p, i64, p]
+        lib.oracle_causal_skeleton.restype = i64
+        lib.oracle_cluster.argtypes = [i64, p, p, p, i64, i64, ctypes.c_int, ctypes.c_int] + [p] * 18
         lib.oracle_cluster.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -116,6 +122,29 @@ def skeleton(src, dst, t, V=None) -> np.ndarray:
     out = np.empty(max(cnt, 1), dtype=LG_EDGE)
     lib.oracle_skeleton(src.size, src.ctypes.data, dst.ctypes.data, t.ctypes.data, V, out.ctypes.data)
     return out[:cnt]
+
+
+def _edges(fn, src, dst, t, V, limit):
+    src, dst, t = _prep(src, dst, t)
+    V = _V(src, dst, V)
+    cnt = int(fn(src.size, src.ctypes.data, dst.ctypes.data, t.ctypes.data, V, None))
+    if cnt < 0:
+        raise RuntimeError("oracle edge generator: %d" % cnt)
+    if cnt > limit:
+        raise MemoryError("line graph has %d edges (limit %d)" % (cnt, limit))
+    out = np.empty(max(cnt, 1), dtype=LG_EDGE)
+    fn(src.size, src.ctypes.data, dst.ctypes.data, t.ctypes.data, V, out.ctypes.data)
+    return out[:cnt]
+
+
+def causal_line_graph(src, dst, t, V=None, limit=200_000_000) -> np.ndarray:
+    """All arcs (tail, head, w) of the increment-weighted line graph (Def. 1)."""
+    return _edges(_load().oracle_causal_line_graph, src, dst, t, V, limit)
+
+
+def causal_skeleton(src, dst, t, V=None) -> np.ndarray:
+    """Alg. 2 window rows (tail, head, w) at every vertex, in vertex then list order."""
+    return _edges(_load().oracle_causal_skeleton, src, dst, t, V, 1 << 62)
 
 
 def kruskal(n, edges, t):
@@ -233,8 +262,9 @@ class Result(NamedTuple):
     n_labels: int
 
 
-def cluster(src, dst, t, min_cluster_size, num_vertices=None, tier=1) -> Result:
-    """Whole pipeline. tier=0: full line graph (definition); tier=1: path skeleton."""
+def cluster(src, dst, t, min_cluster_size, num_vertices=None, tier=1, causal=False) -> Result:
+    """Whole pipeline. tier=0: full line graph (definition); tier=1: skeleton (Alg. 3). causal=True: the
+    increment-weighted line graph of Def. 1 (tip-to-tail arcs, Alg. 2 windows in tier 1)."""
     src, dst, t = _prep(src, dst, t)
     n = src.size
     V = _V(src, dst, num_vertices)
@@ -248,7 +278,7 @@ def cluster(src, dst, t, min_cluster_size, num_vertices=None, tier=1) -> Result:
             np.empty(C, np.uint64), np.empty(C, np.uint64), np.empty(C, np.uint8),
             np.empty(max(n, 1), np.int32)]
     hdr = np.zeros(4, np.int64)
-    _load().oracle_cluster(n, src.ctypes.data, dst.ctypes.data, t.ctypes.data, V, M, int(tier),
+    _load().oracle_cluster(n, src.ctypes.data, dst.ctypes.data, t.ctypes.data, V, M, int(tier), int(bool(causal)),
                            *[b.ctypes.data for b in bufs], hdr.ctypes.data)
     st, m, nc, nl = (int(x) for x in hdr)
     if st != 0:

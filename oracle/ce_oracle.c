@@ -39,6 +39,18 @@
  *      label = the selected cluster above a point's exit cluster, else -1;
  *      labels numbered by ascending minimum member id.
  *
+ * Readings of the causal mode (Def. 1 with Alg. 2):
+ *   C1 list order of E_i: time, then in-edges before out-edges at equal
+ *      times, then id; this is the order the perturbation in the proof of
+ *      Thm 2 induces (in-edge offsets of order gamma^2 below out-edge ones).
+ *   C2 arc r -> s: tail = r (arrives), head = s (leaves), w = t_s - t_r; the
+ *      canonical key is K = (w, head, 2^32-1-tail) as in R3, so among arcs
+ *      of one out-edge with equal w the later in-edge (larger id) is first.
+ *   C3 an out-edge with an empty window emits nothing and the window stays
+ *      empty.
+ *   Direction only decides which pairs are arcs; the spanning forest,
+ *   dendrogram and condensing treat arcs as undirected edges (Alg. 1).
+ *
  * Output conventions (identical to the GPU library's documented ones):
  *   MSF rows (tail, head, w) in ascending K; m = n - (#components).
  *   Dendrogram row k creates node n+k: (left=min child, right=max child, w, size).
@@ -188,6 +200,101 @@ int64_t oracle_skeleton(int64_t n, const int32_t *src, const int32_t *dst, const
       cnt++;
     }
   }
+  free(off);
+  free(lst);
+  return cnt;
+}
+
+/*
+ * CAUSAL mode, Tier A: the increment-weighted line graph of Def. 1. An arc
+ * joins record r to record s when r's head vertex is s's tail vertex (P1,
+ * tip-to-tail) and t_r <= t_s (P2), with weight t_s - t_r (P3). The arc is
+ * found at that shared vertex i: r is an in-edge of i, s an out-edge. Rows are
+ * (tail = r, head = s, w); the canonical key is the same K = (w, head,
+ * 2^32-1-tail) (reading C2). Antiparallel arcs between one pair of records
+ * (possible only at equal times) are two rows with different keys.
+ */
+int64_t oracle_causal_line_graph(int64_t n, const int32_t *src, const int32_t *dst, const int64_t *t,
+                                 int64_t V, lg_edge *out) {
+  int64_t *off;
+  uint32_t *lst;
+  if (build_incidence(n, src, dst, V, &off, &lst)) return OR_ENOMEM;
+  int64_t cnt = 0;
+  for (int64_t x = 0; x < V; x++) {
+    for (int64_t i = off[x]; i < off[x + 1]; i++) {
+      uint32_t r = lst[i];
+      if (dst[r] != x) continue; /* r must arrive at x */
+      for (int64_t j = off[x]; j < off[x + 1]; j++) {
+        uint32_t q = lst[j];
+        if (src[q] != x || t[r] > t[q]) continue; /* q must leave x, not earlier */
+        if (out) {
+          out[cnt].tail = r;
+          out[cnt].head = q;
+          out[cnt].w = t[q] - t[r];
+        }
+        cnt++;
+      }
+    }
+  }
+  free(off);
+  free(lst);
+  return cnt;
+}
+
+/*
+ * CAUSAL mode, Tier B: Alg. 2 (node-local MST) at every vertex, united by
+ * Alg. 3. The incidence list of vertex x is sorted by time with in-edges
+ * before out-edges at equal times and then by id (reading C1); a window
+ * collects in-edges; each out-edge is joined to every in-edge in the window,
+ * after which only the window's last in-edge stays (an empty window stays
+ * empty, reading C3).
+ */
+static int32_t g_x;          /* the vertex whose list is being sorted */
+static const int32_t *g_dst; /* record heads, to tell in-edges of g_x */
+
+static int cmp_causal(const void *pa, const void *pb) {
+  uint32_t a = *(const uint32_t *)pa, b = *(const uint32_t *)pb;
+  if (g_t[a] != g_t[b]) return g_t[a] < g_t[b] ? -1 : 1;
+  int ia = g_dst[a] == g_x, ib = g_dst[b] == g_x; /* 1 = arrives at x */
+  if (ia != ib) return ia ? -1 : 1;
+  if (a != b) return a < b ? -1 : 1;
+  return 0;
+}
+
+int64_t oracle_causal_skeleton(int64_t n, const int32_t *src, const int32_t *dst, const int64_t *t, int64_t V,
+                               lg_edge *out) {
+  int64_t *off;
+  uint32_t *lst;
+  if (build_incidence(n, src, dst, V, &off, &lst)) return OR_ENOMEM;
+  uint32_t *win = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n ? n : 1));
+  if (!win) { free(off); free(lst); return OR_ENOMEM; }
+  g_t = t;
+  g_dst = dst;
+  int64_t cnt = 0;
+  for (int64_t x = 0; x < V; x++) {
+    int64_t d = off[x + 1] - off[x];
+    if (d < 2) continue;
+    g_x = (int32_t)x;
+    qsort(lst + off[x], (size_t)d, sizeof(uint32_t), cmp_causal); /* "Sort E_i by time" */
+    int64_t wn = 0;
+    for (int64_t k = off[x]; k < off[x + 1]; k++) {
+      uint32_t e = lst[k];
+      if (dst[e] == x) { /* in-edge: joins the window */
+        win[wn++] = e;
+        continue;
+      }
+      for (int64_t j = 0; j < wn; j++) {
+        if (out) {
+          out[cnt].tail = win[j];
+          out[cnt].head = e;
+          out[cnt].w = t[e] - t[win[j]];
+        }
+        cnt++;
+      }
+      if (wn) { win[0] = win[wn - 1]; wn = 1; }
+    }
+  }
+  free(win);
   free(off);
   free(lst);
   return cnt;
@@ -530,12 +637,13 @@ int oracle_condense(int64_t n, int64_t m, const uint32_t *left, const uint32_t *
 
 /*
  * Whole pipeline (Alg. 4): tier 0 = definition (full line graph), tier 1 =
- * skeleton (Alg. 3). Output arrays are caller-allocated: msf_* and sl_* hold
- * n-1 rows (n >= 1), cl_* hold 2*floor(n/M)+1 rows. hdr = {status, m,
- * n_clusters, n_labels}.
+ * skeleton (Alg. 3); causal = 0 for the undirected line graph, 1 for the
+ * increment-weighted line graph of Def. 1 (Alg. 2 per vertex in tier 1).
+ * Output arrays are caller-allocated: msf_* and sl_* hold n-1 rows (n >= 1),
+ * cl_* hold 2*floor(n/M)+1 rows. hdr = {status, m, n_clusters, n_labels}.
  */
 int oracle_cluster(int64_t n, const int32_t *src, const int32_t *dst, const int64_t *t, int64_t V,
-                   int64_t M, int tier, uint32_t *msf_tail, uint32_t *msf_head, int64_t *msf_w,
+                   int64_t M, int tier, int causal, uint32_t *msf_tail, uint32_t *msf_head, int64_t *msf_w,
                    uint32_t *sl_left, uint32_t *sl_right, int64_t *sl_w, uint32_t *sl_size,
                    uint32_t *pt_cluster, uint64_t *pt_lambda, uint32_t *cl_id, uint32_t *cl_parent,
                    uint32_t *cl_size, uint64_t *cl_lambda_birth, uint64_t *cl_stab_hi,
@@ -544,13 +652,14 @@ int oracle_cluster(int64_t n, const int32_t *src, const int32_t *dst, const int6
   if (M < 2) { hdr[0] = OR_EINVAL; return OR_EINVAL; }
   int rc = oracle_validate(n, src, dst, t, V);
   if (rc) { hdr[0] = rc; return rc; }
-  int64_t E = tier == 0 ? oracle_full_line_graph(n, src, dst, t, V, NULL)
-                        : oracle_skeleton(n, src, dst, t, V, NULL);
+  int64_t (*gen)(int64_t, const int32_t *, const int32_t *, const int64_t *, int64_t, lg_edge *) =
+      causal ? (tier == 0 ? oracle_causal_line_graph : oracle_causal_skeleton)
+             : (tier == 0 ? oracle_full_line_graph : oracle_skeleton);
+  int64_t E = gen(n, src, dst, t, V, NULL);
   if (E < 0) { hdr[0] = (int)E; return (int)E; }
   lg_edge *edges = (lg_edge *)malloc(sizeof(lg_edge) * (size_t)(E ? E : 1));
   if (!edges) { hdr[0] = OR_ENOMEM; return OR_ENOMEM; }
-  if (tier == 0) oracle_full_line_graph(n, src, dst, t, V, edges);
-  else oracle_skeleton(n, src, dst, t, V, edges);
+  gen(n, src, dst, t, V, edges);
   int64_t m = oracle_kruskal(n, E, edges, t, msf_tail, msf_head, msf_w);
   free(edges);
   if (m < 0) { hdr[0] = (int)m; return (int)m; }

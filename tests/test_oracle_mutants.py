@@ -1,5 +1,6 @@
 """Planted mistakes in the oracle (on the CPU): each mutated copy of the oracle's
-C source must fail at least one pin in test_oracle_pins.py. This shows the pins
+C source must fail at least one pin in test_oracle_pins.py or
+test_oracle_causal.py. This shows the pins
 would catch a dropped term, a wrong sign or index, or a transposed operand."""
 import os
 import subprocess
@@ -25,6 +26,15 @@ MUTANTS = [
     ("root rule: one big component becomes a cluster", "if (nbig >= 2) {", "if (nbig >= 1) {"),
     ("labels numbered by maximum member", "if (got >= 0 && p < minmem[got]) minmem[got] = p;",
      "if (got >= 0 && (minmem[got] == INT64_MAX || p > minmem[got])) minmem[got] = p;"),
+    ("causal: out-edges first at equal times", "if (ia != ib) return ia ? -1 : 1;",
+     "if (ia != ib) return ia ? 1 : -1;"),
+    ("causal: window keeps every in-edge", "if (wn) { win[0] = win[wn - 1]; wn = 1; }", "if (0) { wn = 1; }"),
+    ("causal: window emptied after an out-edge", "if (wn) { win[0] = win[wn - 1]; wn = 1; }", "wn = 0;"),
+    ("causal: strict temporal causality", "if (src[q] != x || t[r] > t[q]) continue;",
+     "if (src[q] != x || t[r] >= t[q]) continue;"),
+    ("causal: head-to-head pairs", "if (src[q] != x || t[r] > t[q]) continue;",
+     "if (dst[q] != x || q == r || t[r] > t[q]) continue;"),
+    ("causal: window weight reversed", "out[cnt].w = t[e] - t[win[j]];", "out[cnt].w = t[win[j]] - t[e];"),
 ]
 
 
@@ -39,6 +49,7 @@ def test_pins_catch_planted_mistake(name, old, new, tmp_path):
     subprocess.check_call(["gcc", "-O1", "-shared", "-fPIC", "-o", str(lib), str(mut)])
     env = dict(os.environ, CE_ORACLE_LIB=str(lib))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py"), "-k", "not four_records_full"],
+                        os.path.join(ROOT, "tests", "test_oracle_pins.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_causal.py"), "-k", "not four_records"],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, "planted mistake '%s' passed every pin:\n%s" % (name, r.stdout[-2000:])
