@@ -55,11 +55,21 @@ typedef enum {
   CE_EBUSY = -6       /* serving queue full */
 } ce_status;
 
-typedef enum { CE_MODE_UNDIRECTED = 0 } ce_mode;
+/* UNDIRECTED: records sharing a vertex are adjacent, w = |t_a - t_b|, and the
+ * skeleton is the time-sorted path through each vertex's records (Sec. 5.3).
+ * CAUSAL: the increment-weighted line graph of Def. 1: an arc joins record r
+ * to record s when r's head vertex is s's tail vertex and t_r <= t_s, with
+ * w = t_s - t_r; the skeleton is Alg. 2 at every vertex (time order, in-edges
+ * before out-edges at equal times, then id). MSF rows are (tail = r, head = s,
+ * w) and the key is again K = (w, head, 2^32-1-tail); arcs are undirected for
+ * the forest, dendrogram and condensing (Alg. 1). The packed key needs
+ * bits(span) + bits(n-1) + bits(c-1) <= 64, where c is the largest number of
+ * records arriving at one vertex at one time (else CE_ERANGE). */
+typedef enum { CE_MODE_UNDIRECTED = 0, CE_MODE_CAUSAL = 1 } ce_mode;
 
 typedef struct {
   uint32_t struct_size;      /* = sizeof(ce_params) */
-  uint32_t mode;             /* CE_MODE_UNDIRECTED */
+  uint32_t mode;             /* ce_mode */
   int64_t min_cluster_size;  /* M >= 2 (Alg. 1 input) */
   int64_t num_vertices;      /* V > 0; vertex ids must lie in [0, V) */
   uint32_t flags;            /* must be 0 */

@@ -16,7 +16,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libce.so")
 
 CE_OK, CE_EINVAL, CE_ESELFLOOP, CE_ERANGE, CE_ENOMEM, CE_EDEVICE, CE_EBUSY = 0, -1, -2, -3, -4, -5, -6
-CE_MODE_UNDIRECTED = 0
+CE_MODE_UNDIRECTED, CE_MODE_CAUSAL = 0, 1
 NONE32 = 0xFFFFFFFF
 
 
@@ -123,8 +123,9 @@ def exported_symbols():
     return {name: hasattr(lib, name) for name in _EXPORTS}
 
 
-def make_params(min_cluster_size: int, num_vertices: int) -> CeParams:
-    return CeParams(ctypes.sizeof(CeParams), CE_MODE_UNDIRECTED, int(min_cluster_size), int(num_vertices), 0, 0)
+def make_params(min_cluster_size: int, num_vertices: int, causal: bool = False) -> CeParams:
+    mode = CE_MODE_CAUSAL if causal else CE_MODE_UNDIRECTED
+    return CeParams(ctypes.sizeof(CeParams), mode, int(min_cluster_size), int(num_vertices), 0, 0)
 
 
 def workspace_bytes(n: int, num_vertices: int, min_cluster_size: int) -> int:
@@ -206,8 +207,11 @@ class Outputs:
 
 
 def cluster_edges(src, dst, t, min_cluster_size: int, num_vertices: int, outputs: Optional[Outputs] = None,
-                  workspace=None, stream=None) -> Result:
+                  workspace=None, stream=None, causal: bool = False) -> Result:
     """Cluster temporal edges (src[i], dst[i], t[i]) held in GPU tensors (int32, int32, int64).
+
+    ``causal=True`` uses the increment-weighted (tip-to-tail) line graph
+    instead of the undirected one.
 
     Runs ``ce_cluster_edges`` on the current (or given) HIP stream and returns
     when the results are written. ``workspace`` may be a uint8 device tensor of
@@ -223,7 +227,7 @@ def cluster_edges(src, dst, t, min_cluster_size: int, num_vertices: int, outputs
         raise ValueError("src, dst, t must have the same length")
     if outputs is None or outputs.n < n or outputs.C < max_clusters(n, min_cluster_size):
         outputs = Outputs(n, min_cluster_size, src.device)
-    params = make_params(min_cluster_size, num_vertices)
+    params = make_params(min_cluster_size, num_vertices, causal)
     counts = CeCounts()
     s = stream if stream is not None else torch.cuda.current_stream(src.device)
     ws_ptr, ws_len = None, 0
@@ -306,7 +310,7 @@ class BatchResult(NamedTuple):
 
 
 def cluster_batch(src, dst, t, edge_offsets, vertex_offsets, min_cluster_size: int,
-                  outputs: Optional[Outputs] = None, workspace=None, stream=None) -> BatchResult:
+                  outputs: Optional[Outputs] = None, workspace=None, stream=None, causal: bool = False) -> BatchResult:
     """Cluster a batch of independent graphs in one call (``ce_cluster_batch``).
 
     src/dst/t hold the graphs' records back to back (GPU tensors), vertex ids
@@ -328,7 +332,7 @@ def cluster_batch(src, dst, t, edge_offsets, vertex_offsets, min_cluster_size: i
     cap = batch_cluster_capacity(eo, min_cluster_size)
     if outputs is None or outputs.n < n or outputs.C < cap or outputs.R < max(n, 1):
         outputs = batch_outputs(eo, min_cluster_size, src.device)
-    params = make_params(min_cluster_size, max(int(vo[-1]), 1))
+    params = make_params(min_cluster_size, max(int(vo[-1]), 1), causal)
     counts = (CeCounts * G)()
     roff = np.zeros(G + 1, dtype=np.int64)
     coff = np.zeros(G + 1, dtype=np.int64)
@@ -395,7 +399,7 @@ class Server:
         self._pending = {}
 
     def submit(self, src, dst, t, min_cluster_size: int, num_vertices: int, outputs: Optional[Outputs] = None,
-               device=None) -> int:
+               device=None, causal: bool = False) -> int:
         import numpy as np
         import torch
         src = np.ascontiguousarray(src, dtype=np.int32)
@@ -407,7 +411,7 @@ class Server:
         if outputs is None or outputs.n < n or outputs.C < max_clusters(n, min_cluster_size):
             outputs = Outputs(n, min_cluster_size, device if device is not None else torch.device("cuda:0"))
         req = CeRequest(ctypes.sizeof(CeRequest), 0, src.ctypes.data, dst.ctypes.data, t.ctypes.data, n,
-                        make_params(min_cluster_size, num_vertices), outputs.struct)
+                        make_params(min_cluster_size, num_vertices, causal), outputs.struct)
         ticket = ctypes.c_uint64()
         st = load_library().ce_server_submit(self._h, ctypes.byref(req), ctypes.byref(ticket))
         if st == CE_EBUSY:

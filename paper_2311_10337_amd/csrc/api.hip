@@ -85,15 +85,16 @@ __global__ __launch_bounds__(B) void k_rowpos(const uint32_t *sorted_j, int64_t 
 __global__ __launch_bounds__(B) void k_rows(const uint64_t *msf_key, const uint4 *msf_val, const uint32_t *kc_u,
                                             const uint32_t *kc_v, const uint32_t *ksize, const uint32_t *rowg,
                                             const uint32_t *rowpos, const uint32_t *moff, const int64_t *eoff,
-                                            int64_t m, int64_t n, int idbits, ce_result out) {
+                                            int64_t m, int64_t n, int idbits, int wshift, int hshift,
+                                            ce_result out) {
   const uint64_t idmask = (uint64_t(1) << idbits) - 1;
   for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
     const uint4 v = msf_val[j];
     const uint64_t key = msf_key[j];
-    const int64_t w = (int64_t)(key >> (idbits + 1));
+    const int64_t w = (int64_t)(key >> wshift);
     const uint32_t g = rowg[j], p = rowpos[j], m0 = moff[g];
     const uint32_t e0 = (uint32_t)eoff[g], ng = (uint32_t)(eoff[g + 1] - eoff[g]);
-    const uint32_t tr = v.x, tid = v.z - e0, hid = (uint32_t)((key >> 1) & idmask) - e0;
+    const uint32_t tr = v.x, tid = v.z - e0, hid = (uint32_t)((key >> hshift) & idmask) - e0;
     if (out.msf_tail) out.msf_tail[p] = tid;
     if (out.msf_head) out.msf_head[p] = hid;
     if (out.msf_w) out.msf_w[p] = w;
@@ -178,7 +179,7 @@ ce_status stage_graph_rows(Bufs &b, int64_t m, Ws &ws, hipStream_t s, int64_t *r
 ce_status stage_write_rows(Bufs &b, int64_t m, const ce_result *out, hipStream_t s) {
   if (m <= 0) return CE_OK;
   CE_LAUNCH(k_rows, dim3(grid_for(m, B)), dim3(B), 0, s, b.msf_key, b.msf_val, b.kc_u, b.kc_v, b.ksize, b.rowg,
-            b.rowpos, b.moff, b.eoff, m, b.n, b.idbits, *out);
+            b.rowpos, b.moff, b.eoff, m, b.n, b.idbits, b.wshift, b.hshift, *out);
   CE_HIP(hipGetLastError());
   return CE_OK;
 }
@@ -211,6 +212,8 @@ static void layout(Bufs &b, Ws &ws, int64_t n, int64_t M, int64_t G) {
   const size_t ybytes = y.off;
   size_t scr_a = stage_sort_skeleton_scratch(n);
   size_t x = stage_boruvka_scratch(n);
+  if (x > scr_a) scr_a = x;
+  x = stage_causal_skeleton_scratch(n);
   if (x > scr_a) scr_a = x;
   const size_t scr_m = stage_msf_sort_scratch(n);
   size_t scr_b = stage_dendrogram_scratch(n);
@@ -250,7 +253,7 @@ static size_t workspace_for(int64_t n, int64_t M, int64_t G) {
 static ce_status check_params(const ce_params *p) {
   if (!p) { set_error("params is NULL"); return CE_EINVAL; }
   if (p->struct_size < sizeof(ce_params)) { set_error("params.struct_size too small"); return CE_EINVAL; }
-  if (p->mode != CE_MODE_UNDIRECTED) { set_error("unknown mode"); return CE_EINVAL; }
+  if (p->mode != CE_MODE_UNDIRECTED && p->mode != CE_MODE_CAUSAL) { set_error("unknown mode"); return CE_EINVAL; }
   if (p->flags != 0 || p->reserved != 0) { set_error("flags/reserved must be 0"); return CE_EINVAL; }
   if (p->min_cluster_size < 2) { set_error("min_cluster_size must be >= 2"); return CE_EINVAL; }
   return CE_OK;
@@ -273,7 +276,8 @@ static ce_status check_offsets(const int64_t *eoff, const int64_t *voff, int64_t
 
 // Runs a checked batch; eoff/voff are host arrays of G+1 offsets.
 static ce_status run_batch(const int32_t *src, const int32_t *dst, const int64_t *t, const int64_t *eoff,
-                           const int64_t *voff, int64_t G, int64_t M, const ce_result *out, ce_counts *counts,
+                           const int64_t *voff, int64_t G, int64_t M, bool causal, const ce_result *out,
+                           ce_counts *counts,
                            int64_t *row_offsets, int64_t *cluster_offsets, void *workspace, size_t workspace_bytes,
                            hipStream_t s) {
   const int64_t n = eoff[G], V = voff[G];
@@ -337,8 +341,11 @@ static ce_status run_batch(const int32_t *src, const int32_t *dst, const int64_t
   b.tbits = bits_for(span);
   b.idbits = bits_for((uint64_t)(n - 1));
   b.vbits = bits_for((uint64_t)(V - 1));
-  b.keybits = b.tbits + b.idbits + 1;
-  if (b.keybits > 64) {
+  b.causal = causal;
+  b.hshift = 1;  // causal mode sets its own shifts once the tie indices are known
+  b.wshift = b.idbits + 1;
+  b.keybits = b.tbits + b.wshift;
+  if (!causal && b.keybits > 64) {
     set_error("time span too wide: bits(span) + bits(n-1) + 1 > 64");
     return CE_ERANGE;
   }
@@ -351,7 +358,8 @@ static ce_status run_batch(const int32_t *src, const int32_t *dst, const int64_t
   wb.cap = b.scratch_b_bytes;
   int64_t m = 0;
   std::vector<int64_t> roff(G + 1);
-  CE_TRY(stage_sort_skeleton(src, dst, t, b, wa, s));
+  if (causal) CE_TRY(stage_causal_skeleton(src, dst, t, b, wa, s));
+  else CE_TRY(stage_sort_skeleton(src, dst, t, b, wa, s));
   CE_TRY(stage_boruvka(b, wa, s));
   CE_TRY(stage_msf_sort(b, wm, s, &m));
   CE_TRY(stage_dendrogram(b, m, wb, s));
@@ -420,8 +428,8 @@ ce_status ce_cluster_edges(const int32_t *src, const int32_t *dst, const int64_t
   }
   if (n < 0 || n > 0x7fffffffLL) { set_error("n must be in [0, 2^31-1]"); return CE_EINVAL; }
   const int64_t eoff[2] = {0, n}, voff[2] = {0, params->num_vertices};
-  return run_batch(src, dst, t, eoff, voff, 1, params->min_cluster_size, out, counts, nullptr, nullptr, workspace,
-                   workspace_bytes, (hipStream_t)stream);
+  return run_batch(src, dst, t, eoff, voff, 1, params->min_cluster_size, params->mode == CE_MODE_CAUSAL, out, counts,
+                   nullptr, nullptr, workspace, workspace_bytes, (hipStream_t)stream);
 }
 
 ce_status ce_cluster_batch(const int32_t *src, const int32_t *dst, const int64_t *t, const int64_t *edge_offsets,
@@ -434,8 +442,9 @@ ce_status ce_cluster_batch(const int32_t *src, const int32_t *dst, const int64_t
     return CE_EINVAL;
   }
   CE_TRY(check_offsets(edge_offsets, vertex_offsets, num_graphs));
-  return run_batch(src, dst, t, edge_offsets, vertex_offsets, num_graphs, params->min_cluster_size, out, counts,
-                   row_offsets, cluster_offsets, workspace, workspace_bytes, (hipStream_t)stream);
+  return run_batch(src, dst, t, edge_offsets, vertex_offsets, num_graphs, params->min_cluster_size,
+                   params->mode == CE_MODE_CAUSAL, out, counts, row_offsets, cluster_offsets, workspace,
+                   workspace_bytes, (hipStream_t)stream);
 }
 
 }  // extern "C"

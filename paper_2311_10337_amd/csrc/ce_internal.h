@@ -278,6 +278,11 @@ struct Bufs {
   uint32_t *rowpos = nullptr;   // [n] output position of each MSF row (graphs in order, rows in key order)
   uint32_t *moff = nullptr;     // [G+1] first output row of each graph
   int tbits = 0, idbits = 0, vbits = 0, keybits = 0;
+  // packed key = w << wshift | head id << hshift | low bits (undirected: one
+  // bit ordering the two edges of a head; causal: the tail's tie index)
+  int wshift = 0, hshift = 0, jbits = 0;
+  bool causal = false;
+  int64_t S = 0;  // causal skeleton rows (slots 0..S-1)
   int64_t tmin = 0;
   // persistent
   uint64_t *hdr = nullptr;      // [16] device header / counters
@@ -316,6 +321,11 @@ size_t stage_graph_rows_scratch(int64_t n, int64_t G);
 ce_status stage_write_rows(Bufs &b, int64_t m, const ce_result *out, hipStream_t s);
 
 size_t stage_sort_skeleton_scratch(int64_t n);
+ce_status sort_records_by_time(const int32_t *src, const int32_t *dst, const int64_t *t, Bufs &b, Ws &ws,
+                               hipStream_t s, const uint4 **vals);
+ce_status stage_causal_skeleton(const int32_t *src, const int32_t *dst, const int64_t *t, Bufs &b, Ws &ws,
+                                hipStream_t s);
+size_t stage_causal_skeleton_scratch(int64_t n);
 size_t stage_boruvka_scratch(int64_t n);
 size_t stage_msf_sort_scratch(int64_t n);
 size_t stage_dendrogram_scratch(int64_t n);

@@ -31,8 +31,8 @@ constexpr int B = 256;
 __device__ inline uint32_t node_size(uint32_t x, int64_t n, const uint32_t *ksize) {
   return x < (uint64_t)n ? 1u : ksize[x - n];
 }
-__device__ inline int64_t row_w(int64_t j, const uint64_t *msf_key, int idbits) {
-  return (int64_t)(msf_key[j] >> (idbits + 1));
+__device__ inline int64_t row_w(int64_t j, const uint64_t *msf_key, int wshift) {
+  return (int64_t)(msf_key[j] >> wshift);
 }
 
 __global__ __launch_bounds__(B) void k_fill32(uint32_t *p, int64_t n, uint32_t v) {
@@ -59,13 +59,13 @@ __global__ __launch_bounds__(B) void k_cd_bigroots(const uint32_t *kpar, const u
 }
 
 __global__ __launch_bounds__(B) void k_cd_birth(const uint32_t *kc_u, const uint32_t *kc_v, const uint32_t *ksize,
-                                                const uint32_t *kpar, const uint64_t *msf_key, int idbits, int64_t m,
+                                                const uint32_t *kpar, const uint64_t *msf_key, int wshift, int64_t m,
                                                 int64_t n, int64_t M, const uint32_t *nbig, const uint32_t *rowg,
                                                 uint8_t *isbirth, uint64_t *birthL) {
   for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
     uint32_t a = kc_u[j], b = kc_v[j];
     if (node_size(a, n, ksize) >= (uint64_t)M && node_size(b, n, ksize) >= (uint64_t)M) {
-      uint64_t L = lambda_of(row_w(j, msf_key, idbits));
+      uint64_t L = lambda_of(row_w(j, msf_key, wshift));
       isbirth[a - n] = 1;
       birthL[a - n] = L;
       isbirth[b - n] = 1;
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(B) void k_cd_jstep(const uint32_t *act, int64_t nac
 
 // exit of each record: lowest big ancestor y -> (cluster of y, lambda(w_y))
 __global__ __launch_bounds__(B) void k_cd_exit(const uint32_t *kpar, const uint32_t *ksize, const uint32_t *J,
-                                               const uint64_t *msf_key, const uint32_t *grank, int idbits, int64_t m,
+                                               const uint64_t *msf_key, const uint32_t *grank, int wshift, int64_t m,
                                                int64_t n, int64_t M, uint32_t *exc, uint64_t *exl) {
   for (int64_t p = (int64_t)blockIdx.x * B + threadIdx.x; p < n; p += (int64_t)gridDim.x * B) {
     uint32_t y = kpar[p];
@@ -147,7 +147,7 @@ __global__ __launch_bounds__(B) void k_cd_exit(const uint32_t *kpar, const uint3
       exl[p] = 0;
     } else {
       exc[p] = J[y - n];
-      exl[p] = lambda_of(row_w((int64_t)y - n, msf_key, idbits));
+      exl[p] = lambda_of(row_w((int64_t)y - n, msf_key, wshift));
     }
   }
 }
@@ -158,12 +158,12 @@ __global__ __launch_bounds__(B) void k_cd_exit(const uint32_t *kpar, const uint3
 // Records outside such subtrees keep the default exit (ROOT, 0).
 constexpr int EXIT_STACK = 64;
 __global__ __launch_bounds__(B) void k_cd_exit_down(const uint32_t *kc_u, const uint32_t *kc_v, const uint32_t *ksize,
-                                                    const uint32_t *J, const uint64_t *msf_key, int idbits, int64_t m,
+                                                    const uint32_t *J, const uint64_t *msf_key, int wshift, int64_t m,
                                                     int64_t n, int64_t M, uint32_t *exc, uint64_t *exl) {
   for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
     if (ksize[j] < (uint64_t)M) continue;
     const uint32_t C = J[j];
-    const uint64_t L = lambda_of(row_w(j, msf_key, idbits));
+    const uint64_t L = lambda_of(row_w(j, msf_key, wshift));
 #pragma unroll
     for (int side = 0; side < 2; side++) {
       const uint32_t c = side ? kc_v[j] : kc_u[j];
@@ -685,7 +685,7 @@ ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipSt
   CE_LAUNCH(k_fill32, dim3(grid_for((m + 4) / 4, B)), dim3(B), 0, s, (uint32_t *)isbirth, (m + 4) / 4, 0u);
   CE_HIP(hipGetLastError());
   if (m > 0) {
-    CE_LAUNCH(k_cd_birth, dim3(grid_for(m, B)), dim3(B), 0, s, b.kc_u, b.kc_v, b.ksize, kpar, b.msf_key, b.idbits, m,
+    CE_LAUNCH(k_cd_birth, dim3(grid_for(m, B)), dim3(B), 0, s, b.kc_u, b.kc_v, b.ksize, kpar, b.msf_key, b.wshift, m,
               n, M, nbig, b.rowg, isbirth, birthL);
     CE_LAUNCH(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[9], (uint64_t)0);
     CE_LAUNCH(k_cd_jinit, dim3(tiles(m)), dim3(B), 0, s, isbirth, kpar, b.ksize, b.rowg, m, n, M, J, jact,
@@ -709,10 +709,10 @@ ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipSt
   if (M <= EXIT_STACK) {
     CE_LAUNCH(k_exit_default, dim3(grid_for(n, B)), dim3(B), 0, s, b.grank, n, m, exc, exl);
     if (m > 0)
-      CE_LAUNCH(k_cd_exit_down, dim3(grid_for(m, B)), dim3(B), 0, s, b.kc_u, b.kc_v, b.ksize, J, b.msf_key, b.idbits,
+      CE_LAUNCH(k_cd_exit_down, dim3(grid_for(m, B)), dim3(B), 0, s, b.kc_u, b.kc_v, b.ksize, J, b.msf_key, b.wshift,
                 m, n, M, exc, exl);
   } else {
-    CE_LAUNCH(k_cd_exit, dim3(grid_for(n, B)), dim3(B), 0, s, kpar, b.ksize, J, b.msf_key, b.grank, b.idbits, m, n,
+    CE_LAUNCH(k_cd_exit, dim3(grid_for(n, B)), dim3(B), 0, s, kpar, b.ksize, J, b.msf_key, b.grank, b.wshift, m, n,
               M, exc, exl);
   }
   // cluster rows: births in (graph, node) order, each graph followed by its root row

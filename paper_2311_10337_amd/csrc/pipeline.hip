@@ -403,6 +403,30 @@ __global__ __launch_bounds__(B) void k_msf_list(const uint8_t *flag, int64_t n2,
   tile_append(keep, vals, out, cnt);
 }
 
+// causal skeleton rows (key, tail rank, head rank) as live edge records
+__global__ __launch_bounds__(B) void k_edges_from_skeleton(int64_t S, const uint64_t *skel_key,
+                                                           const uint32_t *skel_tail, const uint32_t *skel_head,
+                                                           uint64_t *key, uint32_t *eu, uint32_t *ev, uint32_t *es) {
+  for (int64_t e = (int64_t)blockIdx.x * B + threadIdx.x; e < S; e += (int64_t)gridDim.x * B) {
+    key[e] = skel_key[e];
+    eu[e] = skel_tail[e];
+    ev[e] = skel_head[e];
+    es[e] = (uint32_t)e;
+  }
+}
+
+// causal rows keep the head rank in skel_tid; the tail id comes from perm
+__global__ __launch_bounds__(B) void k_msf_gather_causal(const uint32_t *list, int64_t m, const uint64_t *skel_key,
+                                                         const uint32_t *skel_tail, const uint32_t *skel_head,
+                                                         const uint32_t *perm, uint64_t *okey, uint4 *oval) {
+  for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < m; i += (int64_t)gridDim.x * B) {
+    uint32_t e = list[i];
+    const uint32_t tr = skel_tail[e];
+    okey[i] = skel_key[e];
+    oval[i] = make_uint4(tr, skel_head[e], perm[tr], 0u);
+  }
+}
+
 __global__ __launch_bounds__(B) void k_msf_gather(const uint32_t *list, int64_t m, const uint64_t *skel_key,
                                                   const uint32_t *skel_tail, const uint32_t *skel_tid, uint64_t *okey,
                                                   uint4 *oval) {
@@ -471,6 +495,25 @@ size_t stage_sort_skeleton_scratch(int64_t n) {
   return (a > b2 ? a : b2) + 4096;
 }
 
+// Records by (t, id): stable radix sort on t - tmin carrying (id, global src,
+// global dst, graph). b.ts receives the sorted times; *vals points at the
+// sorted payload inside ws (the caller releases it).
+ce_status sort_records_by_time(const int32_t *src, const int32_t *dst, const int64_t *t, Bufs &b, Ws &ws,
+                               hipStream_t s, const uint4 **vals) {
+  const int64_t n = b.n;
+  uint64_t *tkey_alt = ws.alloc<uint64_t>(n);
+  uint4 *tval = ws.alloc<uint4>(n);
+  uint4 *tval_alt = ws.alloc<uint4>(n);
+  CE_WS_CHECK(ws);
+  CE_LAUNCH(k_tkeys, dim3(grid_for(n, B)), dim3(B), 0, s, t, src, dst, n, b.eoff, b.voff, b.G, b.tmin, b.ts, tval);
+  CE_HIP(hipGetLastError());
+  bool alt = false;
+  CE_TRY((radix_sort_pairs<uint64_t, uint4>(b.ts, tval, tkey_alt, tval_alt, n, 0, b.tbits, false, &alt, ws, s)));
+  if (alt) CE_HIP(hipMemcpyAsync(b.ts, tkey_alt, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
+  *vals = alt ? tval_alt : tval;
+  return CE_OK;
+}
+
 ce_status stage_sort_skeleton(const int32_t *src, const int32_t *dst, const int64_t *t, Bufs &b, Ws &ws,
                               hipStream_t s) {
   const int64_t n = b.n, n2 = 2 * n;
@@ -480,20 +523,13 @@ ce_status stage_sort_skeleton(const int32_t *src, const int32_t *dst, const int6
   uint32_t *ikey_alt = ws.alloc<uint32_t>(n2);
   uint32_t *ival_alt = ws.alloc<uint32_t>(n2);
   CE_WS_CHECK(ws);
-  // 1. records by (t, id): stable radix sort on t - tmin carrying (id, src, dst)
+  // 1. records by (t, id)
   {
     size_t m1 = ws.mark();
-    uint64_t *tkey_alt = ws.alloc<uint64_t>(n);
-    uint4 *tval = ws.alloc<uint4>(n);
-    uint4 *tval_alt = ws.alloc<uint4>(n);
-    CE_WS_CHECK(ws);
-    CE_LAUNCH(k_tkeys, dim3(grid_for(n, B)), dim3(B), 0, s, t, src, dst, n, b.eoff, b.voff, b.G, b.tmin, b.ts, tval);
-    CE_HIP(hipGetLastError());
-    bool alt = false;
-    CE_TRY((radix_sort_pairs<uint64_t, uint4>(b.ts, tval, tkey_alt, tval_alt, n, 0, b.tbits, false, &alt, ws, s)));
-    if (alt) CE_HIP(hipMemcpyAsync(b.ts, tkey_alt, sizeof(uint64_t) * n, hipMemcpyDeviceToDevice, s));
+    const uint4 *vals = nullptr;
+    CE_TRY(sort_records_by_time(src, dst, t, b, ws, s, &vals));
     // 2. incidence entries (vertex, 2*rank+side) in rank order, perm by rank
-    CE_LAUNCH(k_incidence, dim3(grid_for(n, B)), dim3(B), 0, s, alt ? tval_alt : tval, n, b.perm, b.grank, ikey);
+    CE_LAUNCH(k_incidence, dim3(grid_for(n, B)), dim3(B), 0, s, vals, n, b.perm, b.grank, ikey);
     CE_HIP(hipGetLastError());
     ws.release(m1);
   }
@@ -572,36 +608,50 @@ ce_status stage_boruvka(Bufs &b, Ws &ws, hipStream_t s) {
   uint64_t *best = b.best;  // seeded for round 1 while emitting the skeleton
   unsigned long long *cnt = (unsigned long long *)&b.hdr[4];
   CE_LAUNCH(k_fill_u8, dim3(grid_for(n2, B)), dim3(B), 0, s, b.msf_flag, n2, (uint8_t)0);
-  CE_LAUNCH(k_rankof, dim3(grid_for(n, B)), dim3(B), 0, s, b.perm, n, rankof);
-  // round 1 on records
-  CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[4], (uint64_t)0);
-  CE_LAUNCH(k_bv_hook_first, dim3(tiles_for(n)), dim3(B), 0, s, n, best, b.skel_key, b.skel_tail, rankof, b.idbits,
-            hook, b.msf_flag, act, cnt);
-  CE_HIP(hipGetLastError());
+  int64_t E = 0, C = 0;
+  int cur = 0, rounds = 0;
   uint64_t nact = 0;
-  CE_TRY(read_u64(&b.hdr[4], &nact, 1, s));
-  CE_TRY(jump_all(act, act2, nact, hook, b, s));
-  CE_LAUNCH(k_root_flags, dim3(grid_for(n, B)), dim3(B), 0, s, n, hook, best, flags);
-  CE_HIP(hipGetLastError());
-  CE_TRY(scan_exclusive_u32(flags, newid, n, ws, s));
-  CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[4], (uint64_t)0);
-  CE_LAUNCH(k_contract_first, dim3(tiles_for(n2)), dim3(B), 0, s, n2, b.skel_key, b.skel_tail, hook, newid, key[0],
-            eu[0], ev[0], es[0], cnt);
-  CE_HIP(hipGetLastError());
   uint64_t hv[2];
-  {
-    // word 16 of the pinned page is ours; read_u64 uses the first words
-    uint32_t *h = (uint32_t *)pinned_scratch();
-    CE_HIP(hipMemcpyAsync(h + 16, newid + n, 4, hipMemcpyDeviceToHost, s));
-    CE_TRY(read_u64(&b.hdr[4], hv, 1, s));  // synchronises the stream
-    hv[1] = h[16];
+  if (b.causal) {
+    // causal skeleton rows can share a head, so every round, the first
+    // included, runs on the edge-list form with records as components
+    if (b.S > 0)
+      CE_LAUNCH(k_edges_from_skeleton, dim3(grid_for(b.S, B)), dim3(B), 0, s, b.S, b.skel_key, b.skel_tail,
+                b.skel_tid, key[0], eu[0], ev[0], es[0]);
+    CE_HIP(hipGetLastError());
+    E = b.S;
+    C = n;
+  } else {
+    CE_LAUNCH(k_rankof, dim3(grid_for(n, B)), dim3(B), 0, s, b.perm, n, rankof);
+    // round 1 on records
+    CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[4], (uint64_t)0);
+    CE_LAUNCH(k_bv_hook_first, dim3(tiles_for(n)), dim3(B), 0, s, n, best, b.skel_key, b.skel_tail, rankof,
+              b.idbits, hook, b.msf_flag, act, cnt);
+    CE_HIP(hipGetLastError());
+    CE_TRY(read_u64(&b.hdr[4], &nact, 1, s));
+    CE_TRY(jump_all(act, act2, nact, hook, b, s));
+    CE_LAUNCH(k_root_flags, dim3(grid_for(n, B)), dim3(B), 0, s, n, hook, best, flags);
+    CE_HIP(hipGetLastError());
+    CE_TRY(scan_exclusive_u32(flags, newid, n, ws, s));
+    CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[4], (uint64_t)0);
+    CE_LAUNCH(k_contract_first, dim3(tiles_for(n2)), dim3(B), 0, s, n2, b.skel_key, b.skel_tail, hook, newid,
+              key[0], eu[0], ev[0], es[0], cnt);
+    CE_HIP(hipGetLastError());
+    {
+      // word 16 of the pinned page is ours; read_u64 uses the first words
+      uint32_t *h = (uint32_t *)pinned_scratch();
+      CE_HIP(hipMemcpyAsync(h + 16, newid + n, 4, hipMemcpyDeviceToHost, s));
+      CE_TRY(read_u64(&b.hdr[4], hv, 1, s));  // synchronises the stream
+      hv[1] = h[16];
+    }
+    E = (int64_t)hv[0];
+    C = (int64_t)hv[1];
+    if (E > n2 || C > n) {
+      set_error("internal: contracted graph larger than its input");
+      return CE_EDEVICE;
+    }
+    rounds = 1;
   }
-  int64_t E = (int64_t)hv[0], C = (int64_t)hv[1];
-  if (E > n2 || C > n) {
-    set_error("internal: contracted graph larger than its input");
-    return CE_EDEVICE;
-  }
-  int cur = 0, rounds = 1;
   while (E > 0) {
     if (++rounds > 64) {
       set_error("Boruvka did not converge");
@@ -666,7 +716,10 @@ ce_status stage_msf_sort(Bufs &b, Ws &ws, hipStream_t s, int64_t *m_out) {
     set_error("spanning forest larger than n-1");
     return CE_EDEVICE;
   }
-  if (m > 0)
+  if (m > 0 && b.causal)
+    CE_LAUNCH(k_msf_gather_causal, dim3(grid_for((int64_t)m, B)), dim3(B), 0, s, list, (int64_t)m, b.skel_key,
+              b.skel_tail, b.skel_tid, b.perm, b.msf_key, b.msf_val);
+  else if (m > 0)
     CE_LAUNCH(k_msf_gather, dim3(grid_for((int64_t)m, B)), dim3(B), 0, s, list, (int64_t)m, b.skel_key,
               b.skel_tail, b.skel_tid, b.msf_key, b.msf_val);
   bool alt = false;

@@ -145,6 +145,7 @@ __global__ __launch_bounds__(B) void k_scatter(const ScatterDesc *d, ce_result s
 struct Request {
   uint64_t ticket = 0;
   int64_t n = 0, V = 0, M = 0;
+  uint32_t mode = CE_MODE_UNDIRECTED;
   size_t in_off = 0, in_bytes = 0;
   ce_result out{};
   ce_counts counts{0, 1, 0};
@@ -249,16 +250,17 @@ struct ce_server {
   ce_server_stats st{};
 
   void worker(int k);
-  void run_batch(std::vector<Request *> &rs, int64_t M, size_t work_off, hipStream_t s);
+  void run_batch(std::vector<Request *> &rs, int64_t M, uint32_t mode, size_t work_off, hipStream_t s);
 };
 
-void ce_server::run_batch(std::vector<Request *> &rs, int64_t M, size_t work_off, hipStream_t s) {
+void ce_server::run_batch(std::vector<Request *> &rs, int64_t M, uint32_t mode, size_t work_off, hipStream_t s) {
   const int64_t G = (int64_t)rs.size();
   char *in = mem, *work = mem + in_cap + work_off;
   ce_params p;
   memset(&p, 0, sizeof p);
   p.struct_size = sizeof p;
   p.min_cluster_size = M;
+  p.mode = mode;
   auto input = [&](Request *r, int k) -> char * {
     const size_t n = (size_t)r->n;
     const size_t offs[3] = {0, align_up(4 * n), 2 * align_up(4 * n)};
@@ -361,12 +363,14 @@ void ce_server::worker(int k) {
   for (;;) {
     cv_work.wait(lk, [&] { return stop || !queue.empty(); });
     if (stop && queue.empty()) return;
-    // the oldest request fixes M; take later requests with the same M while they fit
+    // the oldest request fixes M and the mode; take later requests with the
+    // same ones while they fit
     const int64_t M = queue.front()->M;
+    const uint32_t mode = queue.front()->mode;
     std::vector<Request *> pick;
     int64_t recs = 0;
     for (Request *r : queue) {
-      if (r->M != M) continue;
+      if (r->M != M || r->mode != mode) continue;
       if (!pick.empty() && (recs + r->n > max_batch_records || (int64_t)pick.size() >= MAX_BATCH_GRAPHS)) break;
       pick.push_back(r);
       recs += r->n;
@@ -409,7 +413,7 @@ void ce_server::worker(int k) {
     const auto t0 = Clock::now();
     for (Request *r : pick) r->t_start = t0;
     lk.unlock();
-    run_batch(pick, M, off, s);
+    run_batch(pick, M, mode, off, s);
     const auto t1 = Clock::now();
     lk.lock();
     work_arena.release(off, bytes);
@@ -503,7 +507,8 @@ ce_status ce_server_submit(ce_server *srv, const ce_request *req, uint64_t *tick
   if (!srv || !req || !ticket) { set_error("server/request/ticket is NULL"); return CE_EINVAL; }
   if (req->struct_size < sizeof(ce_request)) { set_error("request.struct_size too small"); return CE_EINVAL; }
   const ce_params &p = req->params;
-  if (p.struct_size < sizeof(ce_params) || p.mode != CE_MODE_UNDIRECTED || p.flags || p.reserved ||
+  if (p.struct_size < sizeof(ce_params) || (p.mode != CE_MODE_UNDIRECTED && p.mode != CE_MODE_CAUSAL) || p.flags ||
+      p.reserved ||
       p.min_cluster_size < 2 || p.num_vertices < 1 || p.num_vertices > 0x80000000LL) {
     set_error("invalid request params");
     return CE_EINVAL;
@@ -516,6 +521,7 @@ ce_status ce_server_submit(ce_server *srv, const ce_request *req, uint64_t *tick
   r->n = n;
   r->V = p.num_vertices;
   r->M = p.min_cluster_size;
+  r->mode = p.mode;
   r->out = req->out;
   r->t_submit = t_submit;
   r->in_bytes = 2 * align_up(4 * (size_t)n) + align_up(8 * (size_t)n);
