@@ -42,17 +42,17 @@ def make_workload(name):
     raise ValueError(name)
 
 
-def cpu_baseline(w, sample):
+def cpu_baseline(w, sample, causal=False):
     """Time the CPU oracle (single-threaded plain C) on the first `sample` records."""
     import oracle
     ns = min(sample, w.n)
     t0 = time.perf_counter()
-    r = oracle.cluster(w.src[:ns], w.dst[:ns], w.t[:ns], w.min_cluster_size, w.num_vertices, tier=1)
+    r = oracle.cluster(w.src[:ns], w.dst[:ns], w.t[:ns], w.min_cluster_size, w.num_vertices, tier=1, causal=causal)
     dt = time.perf_counter() - t0
     assert r.status == 0
     return {"value": ns / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d of %d records of the same workload (path-skeleton oracle, one host thread, %.1f s)"
-                      % (ns, w.n, dt)}
+            "sample": "first %d of %d records of the same workload (%s oracle, one host thread, %.1f s)"
+                      % (ns, w.n, "Alg. 2 window" if causal else "path-skeleton", dt)}
 
 
 def bench_batched(dev, steps, warmup):
@@ -211,6 +211,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="mid", choices=["tiny", "mid", "scale"])
+    ap.add_argument("--mode", default="undirected", choices=["undirected", "causal"],
+                    help="line graph: undirected (shared vertex, |dt|) or causal (tip-to-tail, increment weights)")
     ap.add_argument("--cpu-sample", type=int, default=20_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=1000,
@@ -257,8 +259,11 @@ def main():
     ws = torch.empty(ce.workspace_bytes(w.n, V, M), dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
 
+    causal = args.mode == "causal"
+    cfg["line_graph"] = args.mode
+
     def step():
-        return ce.cluster_edges(src, dst, tt, M, V, outputs=outs, workspace=ws)
+        return ce.cluster_edges(src, dst, tt, M, V, outputs=outs, workspace=ws, causal=causal)
 
     for i in range(args.warmup):
         r = step()
@@ -307,7 +312,7 @@ def main():
         line["serving"] = bench_serving(dev, args.serve_requests)
     if not args.no_cpu_baseline:
         log("cpu baseline on a sample")
-        line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample)
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample, causal)
     line["host"] = {"cpu": platform.processor() or platform.machine(), "nproc": os.cpu_count()}
     print(json.dumps(line), flush=True)
 
