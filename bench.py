@@ -261,6 +261,7 @@ def main():
 
     causal = args.mode == "causal"
     cfg["line_graph"] = args.mode
+    tag = cfg["workload"] + ("_causal" if causal else "")
 
     def step():
         return ce.cluster_edges(src, dst, tt, M, V, outputs=outs, workspace=ws, causal=causal)
@@ -289,18 +290,32 @@ def main():
             per_launch = per_unit * units * args.steps / kcnt
             achieved = per_launch / (kms / kcnt * 1e-3) / 1e9
             traffic = profiling.load_traffic(args.roofline_kernel, os.path.join(
-                ROOT, "profiles", "%s_%s_pmc.md" % (args.roofline_kernel, cfg["workload"])))
+                ROOT, "profiles", "%s_%s_pmc.md" % (args.roofline_kernel, tag)))
             roof = {"bound": "hbm", "achieved": achieved, "peak": profiling.HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / profiling.HBM_PEAK_GBS, "traffic": traffic, "kernel": args.roofline_kernel,
                     "algorithmic_bytes_per_launch": per_launch, "launches": kcnt,
                     "avg_launch_us": 1e3 * kms / kcnt, "unit_of_work": unit, "bytes_per_unit": per_unit}
     value = w.n * args.steps / el
+    # whole path: HBM traffic per step from the committed counter summary (calibrated FETCH_SIZE +
+    # WRITE_SIZE over every dispatch of one step), over the step's wall time; and the algorithmic model
+    from paper_2311_10337_amd import profiling
+    step_s = el / args.steps
+    pipe = profiling.load_pipeline_traffic(os.path.join(ROOT, "profiles", "pipeline_%s_pmc.md" % tag))
+    algo = profiling.PATH_BYTES_PER_EDGE * w.n
+    hbm = {"peak_GBs": profiling.HBM_PEAK_GBS, "traffic_bytes_per_step": pipe,
+           "achieved_GBs": pipe / step_s / 1e9 if pipe else None,
+           "frac": pipe / step_s / 1e9 / profiling.HBM_PEAK_GBS if pipe else None,
+           "algorithmic_bytes_per_step": algo, "algorithmic_GBs": algo / step_s / 1e9,
+           "algorithmic_frac": algo / step_s / 1e9 / profiling.HBM_PEAK_GBS,
+           "note": "traffic from rocprofv3 counters of the same workload (profiles/), time = this run's wall "
+                   "time per step; algorithmic = %d B per temporal edge" % profiling.PATH_BYTES_PER_EDGE}
     line = {"metric": METRIC, "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": 1000.0 * el / args.steps, "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
             "config": dict(cfg, m_msf=r.m, n_clusters=r.n_clusters, n_labels=r.n_labels)}
     if roof is not None:
         line["roofline"] = roof
+    line["hbm_pipeline"] = hbm
     if not args.no_batch:
         del src, dst, tt, outs, ws
         torch.cuda.empty_cache()

@@ -49,7 +49,7 @@ def algorithmic_bytes_per_step(kernel: str, n: int, m: int, level_bits: int = 6)
 
 
 def source_hash(files=("csrc/dendrogram.hip", "csrc/pipeline.hip", "csrc/condense.hip", "csrc/primitives.hip",
-                       "csrc/ce_internal.h")) -> str:
+                       "csrc/ce_internal.h", "csrc/causal.hip", "csrc/api.hip")) -> str:
     h = hashlib.sha256()
     for f in files:
         with open(os.path.join(HERE, f), "rb") as fh:
@@ -63,7 +63,20 @@ def _counter_rows(d):
     for p in paths:
         with open(p) as fh:
             rows.extend(csv.DictReader(fh))
+    rows.sort(key=lambda r: int(r["Dispatch_Id"]))
     return rows
+
+
+def _is_library(name: str) -> bool:
+    return name.startswith("ce::") or name.startswith("void ce::")
+
+
+def _calibration_kib(rows):
+    """Counter value of the calibration copy: the largest runtime copy issued before the first library
+    kernel (the pipeline's own device copies come later and can be larger)."""
+    first = next((i for i, r in enumerate(rows) if _is_library(r["Kernel_Name"])), len(rows))
+    copies = [float(r["Counter_Value"]) for r in rows[:first] if "copyBuffer" in r["Kernel_Name"]]
+    return max(copies) if copies else None
 
 
 def summarize_pmc(fetch_dir: str, write_dir: str, kernel: str, copy_bytes: int) -> dict:
@@ -71,8 +84,7 @@ def summarize_pmc(fetch_dir: str, write_dir: str, kernel: str, copy_bytes: int) 
     out = {"kernel": kernel, "copy_bytes": copy_bytes}
     for name, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
         rows = [r for r in _counter_rows(d) if r["Counter_Name"] == name]
-        copies = [float(r["Counter_Value"]) for r in rows if "copyBuffer" in r["Kernel_Name"]]
-        ref_kib = max(copies) if copies else None
+        ref_kib = _calibration_kib(rows)
         factor = (copy_bytes / 1024.0) / ref_kib if ref_kib else None
         mine = [float(r["Counter_Value"]) for r in rows if kernel in r["Kernel_Name"]]
         out[name] = {"dispatches": len(mine), "avg_kib": (sum(mine) / len(mine)) if mine else None,
@@ -84,6 +96,53 @@ def summarize_pmc(fetch_dir: str, write_dir: str, kernel: str, copy_bytes: int) 
         out["traffic_bytes_per_launch"] = None
     out["source_hash"] = source_hash()
     return out
+
+
+def _is_host_side(name: str) -> bool:
+    # torch's own kernels (input fills and copies made by the benchmark harness)
+    return "at::native" in name
+
+
+def summarize_pipeline_pmc(fetch_dir: str, write_dir: str, copy_bytes: int, steps: int = 1) -> dict:
+    """HBM traffic of the whole pipeline per step: every dispatch from the first to the last library
+    kernel (library kernels and the runtime copies they issue), calibrated like summarize_pmc."""
+    out = {"scope": "pipeline", "copy_bytes": copy_bytes, "steps": steps}
+    for name, d in (("FETCH_SIZE", fetch_dir), ("WRITE_SIZE", write_dir)):
+        rows = [r for r in _counter_rows(d) if r["Counter_Name"] == name]
+        ref_kib = _calibration_kib(rows)
+        factor = (copy_bytes / 1024.0) / ref_kib if ref_kib else None
+        lib = [i for i, r in enumerate(rows) if _is_library(r["Kernel_Name"])]
+        span = rows[lib[0]:lib[-1] + 1] if lib else []
+        mine = [float(r["Counter_Value"]) for r in span if not _is_host_side(r["Kernel_Name"])]
+        out[name] = {"dispatches": len(mine), "total_kib": sum(mine), "copy_kib": ref_kib, "scale": factor}
+    f, w = out["FETCH_SIZE"], out["WRITE_SIZE"]
+    if f["scale"] and w["scale"]:
+        out["traffic_bytes_per_step"] = 1024.0 * (f["total_kib"] * f["scale"] + w["total_kib"] * w["scale"]) / steps
+    else:
+        out["traffic_bytes_per_step"] = None
+    out["source_hash"] = source_hash()
+    return out
+
+
+def load_pipeline_traffic(path: str) -> float | None:
+    """Pipeline traffic per step from a committed summary, or None if the kernels changed since."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        text = fh.read()
+    start = text.find("```json")
+    if start < 0:
+        return None
+    blob = json.loads(text[start + 7:text.find("```", start + 7)])
+    if blob.get("scope") != "pipeline" or blob.get("source_hash") != source_hash():
+        return None
+    return blob.get("traffic_bytes_per_step")
+
+
+# algorithmic bytes per temporal edge of the whole path: each intermediate written once and read once at
+# minimal width (input 16, incidence 48, skeleton 64, MSF rows 32, dendrogram rows 20, per-record outputs 12,
+# labels 4)
+PATH_BYTES_PER_EDGE = 196
 
 
 def load_traffic(kernel: str, path: str) -> float | None:
@@ -104,4 +163,8 @@ def load_traffic(kernel: str, path: str) -> float | None:
 if __name__ == "__main__":
     import sys
     fetch_dir, write_dir, kernel, copy_bytes = sys.argv[1], sys.argv[2], sys.argv[3], int(sys.argv[4])
-    print(json.dumps(summarize_pmc(fetch_dir, write_dir, kernel, copy_bytes), indent=1))
+    if kernel == "pipeline":
+        steps = int(sys.argv[5]) if len(sys.argv) > 5 else 1
+        print(json.dumps(summarize_pipeline_pmc(fetch_dir, write_dir, copy_bytes, steps), indent=1))
+    else:
+        print(json.dumps(summarize_pmc(fetch_dir, write_dir, kernel, copy_bytes), indent=1))
