@@ -68,13 +68,17 @@ typedef enum {
 typedef enum { CE_MODE_UNDIRECTED = 0, CE_MODE_CAUSAL = 1 } ce_mode;
 
 typedef struct {
-  uint32_t struct_size;      /* = sizeof(ce_params) */
+  uint32_t struct_size;      /* = sizeof(ce_params); 32 = the earlier layout without max_dt (no cutoff) */
   uint32_t mode;             /* ce_mode */
   int64_t min_cluster_size;  /* M >= 2 (Alg. 1 input) */
   int64_t num_vertices;      /* V > 0; vertex ids must lie in [0, V) */
   uint32_t flags;            /* must be 0 */
   uint32_t reserved;         /* must be 0 */
+  int64_t max_dt;            /* >= 0: the time-filtered line graph (Sec. 5.1), only line-graph edges with
+                                w <= max_dt; the forest is then the rows of the unfiltered one with
+                                w <= max_dt (Thm 3 at that threshold). < 0: no cutoff */
 } ce_params;
+#define CE_PARAMS_V1_SIZE 32
 
 /* Caller-allocated DEVICE output buffers. Any pointer may be NULL to skip
  * that output. Row capacities: rows of msf_* and sl_* >= max(n-1, 1);

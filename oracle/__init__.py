@@ -69,7 +69,7 @@ def _load():
         lib.oracle_causal_line_graph.restype = i64
         lib.oracle_causal_skeleton.argtypes = [i64, p, p, p, i64, p]
         lib.oracle_causal_skeleton.restype = i64
-        lib.oracle_cluster.argtypes = [i64, p, p, p, i64, i64, ctypes.c_int, ctypes.c_int] + [p] * 18
+        lib.oracle_cluster.argtypes = [i64, p, p, p, i64, i64, ctypes.c_int, ctypes.c_int, i64] + [p] * 18
         lib.oracle_cluster.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -262,9 +262,10 @@ class Result(NamedTuple):
     n_labels: int
 
 
-def cluster(src, dst, t, min_cluster_size, num_vertices=None, tier=1, causal=False) -> Result:
+def cluster(src, dst, t, min_cluster_size, num_vertices=None, tier=1, causal=False, max_dt=-1) -> Result:
     """Whole pipeline. tier=0: full line graph (definition); tier=1: skeleton (Alg. 3). causal=True: the
-    increment-weighted line graph of Def. 1 (tip-to-tail arcs, Alg. 2 windows in tier 1)."""
+    increment-weighted line graph of Def. 1 (tip-to-tail arcs, Alg. 2 windows in tier 1). max_dt >= 0: only
+    line-graph edges with w <= max_dt (time-filtered line graph)."""
     src, dst, t = _prep(src, dst, t)
     n = src.size
     V = _V(src, dst, num_vertices)
@@ -279,7 +280,7 @@ def cluster(src, dst, t, min_cluster_size, num_vertices=None, tier=1, causal=Fal
             np.empty(max(n, 1), np.int32)]
     hdr = np.zeros(4, np.int64)
     _load().oracle_cluster(n, src.ctypes.data, dst.ctypes.data, t.ctypes.data, V, M, int(tier), int(bool(causal)),
-                           *[b.ctypes.data for b in bufs], hdr.ctypes.data)
+                           int(max_dt), *[b.ctypes.data for b in bufs], hdr.ctypes.data)
     st, m, nc, nl = (int(x) for x in hdr)
     if st != 0:
         e = [np.empty(0, b.dtype) for b in bufs]

@@ -639,11 +639,13 @@ int oracle_condense(int64_t n, int64_t m, const uint32_t *left, const uint32_t *
  * Whole pipeline (Alg. 4): tier 0 = definition (full line graph), tier 1 =
  * skeleton (Alg. 3); causal = 0 for the undirected line graph, 1 for the
  * increment-weighted line graph of Def. 1 (Alg. 2 per vertex in tier 1).
+ * max_dt >= 0 keeps only line-graph edges with w <= max_dt (the time-filtered
+ * line graph of Sec. 5.1), in either tier; max_dt < 0 keeps all.
  * Output arrays are caller-allocated: msf_* and sl_* hold n-1 rows (n >= 1),
  * cl_* hold 2*floor(n/M)+1 rows. hdr = {status, m, n_clusters, n_labels}.
  */
 int oracle_cluster(int64_t n, const int32_t *src, const int32_t *dst, const int64_t *t, int64_t V,
-                   int64_t M, int tier, int causal, uint32_t *msf_tail, uint32_t *msf_head, int64_t *msf_w,
+                   int64_t M, int tier, int causal, int64_t max_dt, uint32_t *msf_tail, uint32_t *msf_head, int64_t *msf_w,
                    uint32_t *sl_left, uint32_t *sl_right, int64_t *sl_w, uint32_t *sl_size,
                    uint32_t *pt_cluster, uint64_t *pt_lambda, uint32_t *cl_id, uint32_t *cl_parent,
                    uint32_t *cl_size, uint64_t *cl_lambda_birth, uint64_t *cl_stab_hi,
@@ -660,6 +662,12 @@ int oracle_cluster(int64_t n, const int32_t *src, const int32_t *dst, const int6
   lg_edge *edges = (lg_edge *)malloc(sizeof(lg_edge) * (size_t)(E ? E : 1));
   if (!edges) { hdr[0] = OR_ENOMEM; return OR_ENOMEM; }
   gen(n, src, dst, t, V, edges);
+  if (max_dt >= 0) { /* time-filtered line graph (Sec. 5.1): keep only w <= max_dt */
+    int64_t k = 0;
+    for (int64_t e = 0; e < E; e++)
+      if (edges[e].w <= max_dt) edges[k++] = edges[e];
+    E = k;
+  }
   int64_t m = oracle_kruskal(n, E, edges, t, msf_tail, msf_head, msf_w);
   free(edges);
   if (m < 0) { hdr[0] = (int)m; return (int)m; }

@@ -22,7 +22,8 @@ NONE32 = 0xFFFFFFFF
 
 class CeParams(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("mode", ctypes.c_uint32), ("min_cluster_size", ctypes.c_int64),
-                ("num_vertices", ctypes.c_int64), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("num_vertices", ctypes.c_int64), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("max_dt", ctypes.c_int64)]
 
 
 _RESULT_FIELDS = ["msf_tail", "msf_head", "msf_w", "sl_left", "sl_right", "sl_w", "sl_size", "pt_cluster",
@@ -123,9 +124,9 @@ def exported_symbols():
     return {name: hasattr(lib, name) for name in _EXPORTS}
 
 
-def make_params(min_cluster_size: int, num_vertices: int, causal: bool = False) -> CeParams:
+def make_params(min_cluster_size: int, num_vertices: int, causal: bool = False, max_dt: int = -1) -> CeParams:
     mode = CE_MODE_CAUSAL if causal else CE_MODE_UNDIRECTED
-    return CeParams(ctypes.sizeof(CeParams), mode, int(min_cluster_size), int(num_vertices), 0, 0)
+    return CeParams(ctypes.sizeof(CeParams), mode, int(min_cluster_size), int(num_vertices), 0, 0, int(max_dt))
 
 
 def workspace_bytes(n: int, num_vertices: int, min_cluster_size: int) -> int:
@@ -207,11 +208,12 @@ class Outputs:
 
 
 def cluster_edges(src, dst, t, min_cluster_size: int, num_vertices: int, outputs: Optional[Outputs] = None,
-                  workspace=None, stream=None, causal: bool = False) -> Result:
+                  workspace=None, stream=None, causal: bool = False, max_dt: int = -1) -> Result:
     """Cluster temporal edges (src[i], dst[i], t[i]) held in GPU tensors (int32, int32, int64).
 
     ``causal=True`` uses the increment-weighted (tip-to-tail) line graph
-    instead of the undirected one.
+    instead of the undirected one; ``max_dt >= 0`` keeps only line-graph
+    edges with w <= max_dt.
 
     Runs ``ce_cluster_edges`` on the current (or given) HIP stream and returns
     when the results are written. ``workspace`` may be a uint8 device tensor of
@@ -227,7 +229,7 @@ def cluster_edges(src, dst, t, min_cluster_size: int, num_vertices: int, outputs
         raise ValueError("src, dst, t must have the same length")
     if outputs is None or outputs.n < n or outputs.C < max_clusters(n, min_cluster_size):
         outputs = Outputs(n, min_cluster_size, src.device)
-    params = make_params(min_cluster_size, num_vertices, causal)
+    params = make_params(min_cluster_size, num_vertices, causal, max_dt)
     counts = CeCounts()
     s = stream if stream is not None else torch.cuda.current_stream(src.device)
     ws_ptr, ws_len = None, 0
@@ -310,7 +312,8 @@ class BatchResult(NamedTuple):
 
 
 def cluster_batch(src, dst, t, edge_offsets, vertex_offsets, min_cluster_size: int,
-                  outputs: Optional[Outputs] = None, workspace=None, stream=None, causal: bool = False) -> BatchResult:
+                  outputs: Optional[Outputs] = None, workspace=None, stream=None, causal: bool = False,
+                  max_dt: int = -1) -> BatchResult:
     """Cluster a batch of independent graphs in one call (``ce_cluster_batch``).
 
     src/dst/t hold the graphs' records back to back (GPU tensors), vertex ids
@@ -332,7 +335,7 @@ def cluster_batch(src, dst, t, edge_offsets, vertex_offsets, min_cluster_size: i
     cap = batch_cluster_capacity(eo, min_cluster_size)
     if outputs is None or outputs.n < n or outputs.C < cap or outputs.R < max(n, 1):
         outputs = batch_outputs(eo, min_cluster_size, src.device)
-    params = make_params(min_cluster_size, max(int(vo[-1]), 1), causal)
+    params = make_params(min_cluster_size, max(int(vo[-1]), 1), causal, max_dt)
     counts = (CeCounts * G)()
     roff = np.zeros(G + 1, dtype=np.int64)
     coff = np.zeros(G + 1, dtype=np.int64)
@@ -399,7 +402,7 @@ class Server:
         self._pending = {}
 
     def submit(self, src, dst, t, min_cluster_size: int, num_vertices: int, outputs: Optional[Outputs] = None,
-               device=None, causal: bool = False) -> int:
+               device=None, causal: bool = False, max_dt: int = -1) -> int:
         import numpy as np
         import torch
         src = np.ascontiguousarray(src, dtype=np.int32)
@@ -411,7 +414,7 @@ class Server:
         if outputs is None or outputs.n < n or outputs.C < max_clusters(n, min_cluster_size):
             outputs = Outputs(n, min_cluster_size, device if device is not None else torch.device("cuda:0"))
         req = CeRequest(ctypes.sizeof(CeRequest), 0, src.ctypes.data, dst.ctypes.data, t.ctypes.data, n,
-                        make_params(min_cluster_size, num_vertices, causal), outputs.struct)
+                        make_params(min_cluster_size, num_vertices, causal, max_dt), outputs.struct)
         ticket = ctypes.c_uint64()
         st = load_library().ce_server_submit(self._h, ctypes.byref(req), ctypes.byref(ticket))
         if st == CE_EBUSY:

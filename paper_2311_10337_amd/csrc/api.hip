@@ -243,6 +243,9 @@ static void layout(Bufs &b, Ws &ws, int64_t n, int64_t M, int64_t G) {
   b.scratch_b_bytes = phase - ybytes;
 }
 
+// the cutoff, when the caller's struct has the field
+static int64_t max_dt_of(const ce_params *p) { return p->struct_size >= sizeof(ce_params) ? p->max_dt : -1; }
+
 static size_t workspace_for(int64_t n, int64_t M, int64_t G) {
   Bufs b;
   Ws ws;
@@ -252,7 +255,7 @@ static size_t workspace_for(int64_t n, int64_t M, int64_t G) {
 
 static ce_status check_params(const ce_params *p) {
   if (!p) { set_error("params is NULL"); return CE_EINVAL; }
-  if (p->struct_size < sizeof(ce_params)) { set_error("params.struct_size too small"); return CE_EINVAL; }
+  if (p->struct_size < CE_PARAMS_V1_SIZE) { set_error("params.struct_size too small"); return CE_EINVAL; }
   if (p->mode != CE_MODE_UNDIRECTED && p->mode != CE_MODE_CAUSAL) { set_error("unknown mode"); return CE_EINVAL; }
   if (p->flags != 0 || p->reserved != 0) { set_error("flags/reserved must be 0"); return CE_EINVAL; }
   if (p->min_cluster_size < 2) { set_error("min_cluster_size must be >= 2"); return CE_EINVAL; }
@@ -276,8 +279,8 @@ static ce_status check_offsets(const int64_t *eoff, const int64_t *voff, int64_t
 
 // Runs a checked batch; eoff/voff are host arrays of G+1 offsets.
 static ce_status run_batch(const int32_t *src, const int32_t *dst, const int64_t *t, const int64_t *eoff,
-                           const int64_t *voff, int64_t G, int64_t M, bool causal, const ce_result *out,
-                           ce_counts *counts,
+                           const int64_t *voff, int64_t G, int64_t M, bool causal, int64_t max_dt,
+                           const ce_result *out, ce_counts *counts,
                            int64_t *row_offsets, int64_t *cluster_offsets, void *workspace, size_t workspace_bytes,
                            hipStream_t s) {
   const int64_t n = eoff[G], V = voff[G];
@@ -362,6 +365,7 @@ static ce_status run_batch(const int32_t *src, const int32_t *dst, const int64_t
   else CE_TRY(stage_sort_skeleton(src, dst, t, b, wa, s));
   CE_TRY(stage_boruvka(b, wa, s));
   CE_TRY(stage_msf_sort(b, wm, s, &m));
+  if (max_dt >= 0) CE_TRY(stage_time_filter(b, max_dt, s, &m));
   CE_TRY(stage_dendrogram(b, m, wb, s));
   CE_TRY(stage_graph_rows(b, m, wb, s, roff.data()));
   CE_TRY(stage_write_rows(b, m, out, s));
@@ -387,8 +391,13 @@ int64_t ce_max_clusters(int64_t n, int64_t M) {
 
 size_t ce_workspace_bytes(int64_t n, int64_t num_vertices, const ce_params *params) {
   ce_params p;
-  if (params) p = *params;
-  else { memset(&p, 0, sizeof p); p.struct_size = sizeof p; p.min_cluster_size = 2; }
+  memset(&p, 0, sizeof p);
+  p.struct_size = sizeof p;
+  p.min_cluster_size = 2;
+  if (params) {  // a caller's struct may be the shorter earlier layout
+    const size_t k = params->struct_size < sizeof p ? params->struct_size : sizeof p;
+    memcpy(&p, params, k);
+  }
   if (check_params(&p) != CE_OK) return 0;
   if (n < 0 || n > 0x7fffffffLL || num_vertices < 1 || num_vertices > 0x80000000LL) return 0;
   return workspace_for(n, p.min_cluster_size, 1);
@@ -428,8 +437,8 @@ ce_status ce_cluster_edges(const int32_t *src, const int32_t *dst, const int64_t
   }
   if (n < 0 || n > 0x7fffffffLL) { set_error("n must be in [0, 2^31-1]"); return CE_EINVAL; }
   const int64_t eoff[2] = {0, n}, voff[2] = {0, params->num_vertices};
-  return run_batch(src, dst, t, eoff, voff, 1, params->min_cluster_size, params->mode == CE_MODE_CAUSAL, out, counts,
-                   nullptr, nullptr, workspace, workspace_bytes, (hipStream_t)stream);
+  return run_batch(src, dst, t, eoff, voff, 1, params->min_cluster_size, params->mode == CE_MODE_CAUSAL,
+                   max_dt_of(params), out, counts, nullptr, nullptr, workspace, workspace_bytes, (hipStream_t)stream);
 }
 
 ce_status ce_cluster_batch(const int32_t *src, const int32_t *dst, const int64_t *t, const int64_t *edge_offsets,
@@ -443,8 +452,8 @@ ce_status ce_cluster_batch(const int32_t *src, const int32_t *dst, const int64_t
   }
   CE_TRY(check_offsets(edge_offsets, vertex_offsets, num_graphs));
   return run_batch(src, dst, t, edge_offsets, vertex_offsets, num_graphs, params->min_cluster_size,
-                   params->mode == CE_MODE_CAUSAL, out, counts, row_offsets, cluster_offsets, workspace,
-                   workspace_bytes, (hipStream_t)stream);
+                   params->mode == CE_MODE_CAUSAL, max_dt_of(params), out, counts, row_offsets, cluster_offsets,
+                   workspace, workspace_bytes, (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -326,6 +326,7 @@ ce_status sort_records_by_time(const int32_t *src, const int32_t *dst, const int
 ce_status stage_causal_skeleton(const int32_t *src, const int32_t *dst, const int64_t *t, Bufs &b, Ws &ws,
                                 hipStream_t s);
 size_t stage_causal_skeleton_scratch(int64_t n);
+ce_status stage_time_filter(Bufs &b, int64_t max_dt, hipStream_t s, int64_t *m);
 size_t stage_boruvka_scratch(int64_t n);
 size_t stage_msf_sort_scratch(int64_t n);
 size_t stage_dendrogram_scratch(int64_t n);

@@ -691,6 +691,39 @@ ce_status stage_boruvka(Bufs &b, Ws &ws, hipStream_t s) {
   return CE_OK;
 }
 
+// rows with key < limit (rows are sorted, so they are a prefix): one binary search
+__global__ void k_prefix_below(const uint64_t *key, int64_t m, uint64_t limit, uint64_t *out) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int64_t lo = 0, hi = m;
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if (key[mid] < limit) lo = mid + 1;
+    else hi = mid;
+  }
+  *out = (uint64_t)lo;
+}
+
+// Time-filtered line graph (Sec. 5.1): only edges with w <= max_dt. The
+// filtered skeleton has the filtered line graph's components at every
+// threshold up to max_dt (Thm 3), and Kruskal takes edges in key order, so
+// its forest is the prefix of the sorted MSF with w <= max_dt.
+ce_status stage_time_filter(Bufs &b, int64_t max_dt, hipStream_t s, int64_t *m) {
+  if (*m <= 0 || max_dt < 0) return CE_OK;
+  const unsigned __int128 lim = ((unsigned __int128)max_dt + 1) << b.wshift;
+  if (lim > (unsigned __int128)NONE64) return CE_OK;  // every key is below it: no row is longer
+  const uint64_t limit = (uint64_t)lim;
+  CE_LAUNCH(k_prefix_below, dim3(1), dim3(64), 0, s, b.msf_key, *m, limit, &b.hdr[6]);
+  CE_HIP(hipGetLastError());
+  uint64_t k = 0;
+  CE_TRY(read_u64(&b.hdr[6], &k, 1, s));
+  if ((int64_t)k > *m) {
+    set_error("internal: time filter");
+    return CE_EDEVICE;
+  }
+  *m = (int64_t)k;
+  return CE_OK;
+}
+
 size_t stage_msf_sort_scratch(int64_t n) {
   Ws w;
   w.alloc<uint64_t>(n);

@@ -146,6 +146,7 @@ struct Request {
   uint64_t ticket = 0;
   int64_t n = 0, V = 0, M = 0;
   uint32_t mode = CE_MODE_UNDIRECTED;
+  int64_t max_dt = -1;
   size_t in_off = 0, in_bytes = 0;
   ce_result out{};
   ce_counts counts{0, 1, 0};
@@ -250,17 +251,20 @@ struct ce_server {
   ce_server_stats st{};
 
   void worker(int k);
-  void run_batch(std::vector<Request *> &rs, int64_t M, uint32_t mode, size_t work_off, hipStream_t s);
+  void run_batch(std::vector<Request *> &rs, size_t work_off, hipStream_t s);
 };
 
-void ce_server::run_batch(std::vector<Request *> &rs, int64_t M, uint32_t mode, size_t work_off, hipStream_t s) {
+// every request of a batch shares M, the mode and the cutoff
+void ce_server::run_batch(std::vector<Request *> &rs, size_t work_off, hipStream_t s) {
+  const int64_t M = rs[0]->M;
   const int64_t G = (int64_t)rs.size();
   char *in = mem, *work = mem + in_cap + work_off;
   ce_params p;
   memset(&p, 0, sizeof p);
   p.struct_size = sizeof p;
   p.min_cluster_size = M;
-  p.mode = mode;
+  p.mode = rs[0]->mode;
+  p.max_dt = rs[0]->max_dt;
   auto input = [&](Request *r, int k) -> char * {
     const size_t n = (size_t)r->n;
     const size_t offs[3] = {0, align_up(4 * n), 2 * align_up(4 * n)};
@@ -363,14 +367,14 @@ void ce_server::worker(int k) {
   for (;;) {
     cv_work.wait(lk, [&] { return stop || !queue.empty(); });
     if (stop && queue.empty()) return;
-    // the oldest request fixes M and the mode; take later requests with the
-    // same ones while they fit
-    const int64_t M = queue.front()->M;
-    const uint32_t mode = queue.front()->mode;
+    // the oldest request fixes M, the mode and the cutoff; take later
+    // requests with the same ones while they fit
+    const Request *head = queue.front();
+    const int64_t M = head->M;
     std::vector<Request *> pick;
     int64_t recs = 0;
     for (Request *r : queue) {
-      if (r->M != M || r->mode != mode) continue;
+      if (r->M != M || r->mode != head->mode || r->max_dt != head->max_dt) continue;
       if (!pick.empty() && (recs + r->n > max_batch_records || (int64_t)pick.size() >= MAX_BATCH_GRAPHS)) break;
       pick.push_back(r);
       recs += r->n;
@@ -413,7 +417,7 @@ void ce_server::worker(int k) {
     const auto t0 = Clock::now();
     for (Request *r : pick) r->t_start = t0;
     lk.unlock();
-    run_batch(pick, M, mode, off, s);
+    run_batch(pick, off, s);
     const auto t1 = Clock::now();
     lk.lock();
     work_arena.release(off, bytes);
@@ -507,7 +511,7 @@ ce_status ce_server_submit(ce_server *srv, const ce_request *req, uint64_t *tick
   if (!srv || !req || !ticket) { set_error("server/request/ticket is NULL"); return CE_EINVAL; }
   if (req->struct_size < sizeof(ce_request)) { set_error("request.struct_size too small"); return CE_EINVAL; }
   const ce_params &p = req->params;
-  if (p.struct_size < sizeof(ce_params) || (p.mode != CE_MODE_UNDIRECTED && p.mode != CE_MODE_CAUSAL) || p.flags ||
+  if (p.struct_size < CE_PARAMS_V1_SIZE || (p.mode != CE_MODE_UNDIRECTED && p.mode != CE_MODE_CAUSAL) || p.flags ||
       p.reserved ||
       p.min_cluster_size < 2 || p.num_vertices < 1 || p.num_vertices > 0x80000000LL) {
     set_error("invalid request params");
@@ -522,6 +526,7 @@ ce_status ce_server_submit(ce_server *srv, const ce_request *req, uint64_t *tick
   r->V = p.num_vertices;
   r->M = p.min_cluster_size;
   r->mode = p.mode;
+  r->max_dt = p.struct_size >= sizeof(ce_params) ? p.max_dt : -1;
   r->out = req->out;
   r->t_submit = t_submit;
   r->in_bytes = 2 * align_up(4 * (size_t)n) + align_up(8 * (size_t)n);

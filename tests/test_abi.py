@@ -164,3 +164,22 @@ def test_server_host_checks_need_no_gpu():
     b = ce.server_request_bytes(100_000, 1000, 10)
     assert 0 < a < b
     assert ce.server_request_bytes(-1, 1000, 10) == 0 and ce.server_request_bytes(10, 1000, 1) == 0
+
+
+def test_earlier_params_layout_is_accepted():
+    """A caller built against the 32-byte parameter struct (no max_dt) is read as "no cutoff"."""
+    import ctypes
+    import paper_2311_10337_amd as ce
+    if not os.path.exists(ce.LIB_PATH):
+        pytest.skip("libce.so not built")
+    lib = ce.load_library()
+
+    class ParamsV1(ctypes.Structure):
+        _fields_ = ce.CeParams._fields_[:-1]
+
+    assert ctypes.sizeof(ParamsV1) == 32
+    v1 = ParamsV1(32, 0, 5, 100, 0, 0)
+    a = lib.ce_workspace_bytes(1000, 100, ctypes.cast(ctypes.pointer(v1), ctypes.POINTER(ce.CeParams)))
+    assert a == ce.workspace_bytes(1000, 100, 5) > 0
+    v1.struct_size = 24
+    assert lib.ce_workspace_bytes(1000, 100, ctypes.cast(ctypes.pointer(v1), ctypes.POINTER(ce.CeParams))) == 0

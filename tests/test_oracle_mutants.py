@@ -35,6 +35,8 @@ MUTANTS = [
     ("causal: head-to-head pairs", "if (src[q] != x || t[r] > t[q]) continue;",
      "if (dst[q] != x || q == r || t[r] > t[q]) continue;"),
     ("causal: window weight reversed", "out[cnt].w = t[e] - t[win[j]];", "out[cnt].w = t[win[j]] - t[e];"),
+    ("time filter strict", "if (edges[e].w <= max_dt) edges[k++] = edges[e];",
+     "if (edges[e].w < max_dt) edges[k++] = edges[e];"),
 ]
 
 

@@ -589,3 +589,33 @@ def test_condense_wrapper_equals_full_pipeline():
     with pytest.raises(RuntimeError):
         oracle.dendrogram(3, np.array([0, 1, 0], np.uint32), np.array([1, 2, 2], np.uint32),
                           np.array([1, 1, 2], np.int64))
+
+
+def test_time_filtered_line_graph():
+    """Time-filtered line graph (Sec. 5.1): only edges with w <= max_dt. Definition and skeleton tiers agree for
+    every cutoff (Thm 3 at that threshold), and the forest is exactly the unfiltered forest's rows with
+    w <= max_dt (Kruskal takes edges in key order, so the filter cuts a prefix); networkx MSF weight of the
+    filtered full line graph agrees."""
+    rng = np.random.default_rng(17)
+    for trial in range(120):
+        n = int(rng.integers(2, 50))
+        V = int(rng.integers(2, 8))
+        s, d, t = _random_tie_heavy(rng, n, V, int(rng.choice([5, 60, 3000])))
+        for causal in (False, True):
+            full = oracle.cluster(s, d, t, 2, V, tier=1, causal=causal)
+            edges = oracle.causal_line_graph(s, d, t, V) if causal else oracle.full_line_graph(s, d, t, V)
+            for cut in sorted(set([0, 1, 7] + [int(x) for x in rng.choice(full.msf_w, min(3, full.m))] if full.m
+                                  else [0, 3])):
+                a = oracle.cluster(s, d, t, 2, V, tier=0, causal=causal, max_dt=cut)
+                b = oracle.cluster(s, d, t, 2, V, tier=1, causal=causal, max_dt=cut)
+                assert_same_result(a, b)
+                keep = full.msf_w <= cut
+                assert np.array_equal(a.msf_w, full.msf_w[keep]) and np.array_equal(a.msf_tail, full.msf_tail[keep])
+                g = nx.Graph()
+                g.add_nodes_from(range(n))
+                for e in edges[edges["w"] <= cut]:
+                    u, v, w = int(e["tail"]), int(e["head"]), int(e["w"])
+                    if not g.has_edge(u, v) or g[u][v]["weight"] > w:
+                        g.add_edge(u, v, weight=w)
+                assert int(a.msf_w.sum()) == sum(x[2]["weight"] for x in nx.minimum_spanning_edges(g, data=True))
+                assert a.m == n - nx.number_connected_components(g)
