@@ -64,6 +64,8 @@ def _load():
         lib.oracle_joined_below.argtypes = [i64, i64, p, p, p, i64, p, p, p, p]
         lib.oracle_joined_below.restype = ctypes.c_int
         lib.oracle_condense.argtypes = [i64, i64, p, p, p, p, i64] + [p] * 10 + [p]
+        lib.oracle_condense_discrete.argtypes = [i64, i64, p, p, p, p, i64, i64, p] + [p] * 10 + [p, p, p]
+        lib.oracle_condense_discrete.restype = ctypes.c_int
         lib.oracle_condense.restype = ctypes.c_int
         lib.oracle_causal_line_graph.argtypes = [i64, p, p, p, i64, p]
         lib.oracle_causal_line_graph.restype = i64
@@ -236,6 +238,59 @@ def condense(n, left, right, lw, size, M) -> Condensed:
         raise RuntimeError("oracle_condense: %d" % rc)
     k = int(cnt.n_clusters)
     return Condensed(ptc[:n], ptl[:n], *[a[:k] for a in arrs], labels[:n], int(cnt.n_labels))
+
+
+class Discrete(NamedTuple):
+    condensed: Condensed
+    dd_level: np.ndarray   # level (threshold index) of every dendrogram row
+    dd_top: np.ndarray     # node n+j of the row's level top j (its D-node)
+
+
+def condense_discrete(n, left, right, lw, size, M, thresholds) -> Discrete:
+    """Alg. 5 discrete dendrogram cut from the exact one, condensed with several children per node. All rows
+    must have w <= thresholds[-1]."""
+    left = np.ascontiguousarray(left, np.uint32)
+    right = np.ascontiguousarray(right, np.uint32)
+    lw = np.ascontiguousarray(lw, np.int64)
+    size = np.ascontiguousarray(size, np.uint32)
+    thr = np.ascontiguousarray(thresholds, np.int64)
+    m = left.size
+    C = max_clusters(n, M)
+    ptc = np.empty(max(n, 1), np.uint32)
+    ptl = np.empty(max(n, 1), np.uint64)
+    arrs = [np.empty(C, np.uint32), np.empty(C, np.uint32), np.empty(C, np.uint32), np.empty(C, np.uint64),
+            np.empty(C, np.uint64), np.empty(C, np.uint64), np.empty(C, np.uint8)]
+    labels = np.empty(max(n, 1), np.int32)
+    dl = np.empty(max(m, 1), np.uint32)
+    dt = np.empty(max(m, 1), np.uint32)
+    cnt = _Counts()
+    rc = _load().oracle_condense_discrete(int(n), m, left.ctypes.data, right.ctypes.data, lw.ctypes.data,
+                                          size.ctypes.data, int(M), thr.size, thr.ctypes.data, ptc.ctypes.data,
+                                          ptl.ctypes.data, *[a.ctypes.data for a in arrs], labels.ctypes.data,
+                                          dl.ctypes.data, dt.ctypes.data, ctypes.byref(cnt))
+    if rc:
+        raise RuntimeError("oracle_condense_discrete: %d" % rc)
+    k = int(cnt.n_clusters)
+    cond = Condensed(ptc[:n], ptl[:n], *[a[:k] for a in arrs], labels[:n], int(cnt.n_labels))
+    return Discrete(cond, dl[:m], dt[:m])
+
+
+def cluster_discrete(src, dst, t, min_cluster_size, thresholds, num_vertices=None, tier=1, causal=False):
+    """Whole pipeline with the discrete dendrogram: the forest up to the last threshold, its exact dendrogram
+    (sl_* fields), then the Alg. 5 levels and the condensing on the discrete tree. Returns (Result, dd_level,
+    dd_top); the Result's condensed fields are the discrete ones."""
+    thr = np.asarray(thresholds, np.int64)
+    r = cluster(src, dst, t, min_cluster_size, num_vertices, tier=tier, causal=causal, max_dt=int(thr[-1]))
+    if r.status != 0:
+        return r, None, None
+    n = len(src)
+    d = condense_discrete(n, r.sl_left, r.sl_right, r.sl_w, r.sl_size, min_cluster_size, thr)
+    c = d.condensed
+    res = r._replace(pt_cluster=c.pt_cluster, pt_lambda=c.pt_lambda, cl_id=c.cl_id, cl_parent=c.cl_parent,
+                     cl_size=c.cl_size, cl_lambda_birth=c.cl_lambda_birth, cl_stab_hi=c.cl_stab_hi,
+                     cl_stab_lo=c.cl_stab_lo, cl_selected=c.cl_selected, labels=c.labels,
+                     n_clusters=len(c.cl_id), n_labels=c.n_labels)
+    return res, d.dd_level, d.dd_top
 
 
 class Result(NamedTuple):

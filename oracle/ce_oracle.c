@@ -451,11 +451,84 @@ typedef struct {
  * cluster it leaves and the lambda at which it leaves; cluster rows in
  * ascending id; labels. Arrays cl_* must hold 2*floor(n/M)+1 rows.
  */
+/*
+ * dtop == NULL: the binary dendrogram, node n+k merging left[k] and right[k]
+ * at lambda(lw[k]). dtop != NULL: the discrete dendrogram of Alg. 5 cut from
+ * it (see oracle_condense_discrete): row k belongs to the D-node of its level
+ * top dtop[k]; a D-node merges, at node_lam[its row], every child of its
+ * block's rows that lies outside the block.
+ */
+static int condense_impl(int64_t n, int64_t m, const uint32_t *left, const uint32_t *right, const int64_t *lw,
+                         const uint32_t *size, int64_t M, const uint32_t *dtop, const uint64_t *node_lam,
+                         uint32_t *pt_cluster, uint64_t *pt_lambda, uint32_t *cl_id, uint32_t *cl_parent,
+                         uint32_t *cl_size, uint64_t *cl_lambda_birth, uint64_t *cl_stab_hi,
+                         uint64_t *cl_stab_lo, uint8_t *cl_selected, int32_t *labels, condense_counts *counts);
+
 int oracle_condense(int64_t n, int64_t m, const uint32_t *left, const uint32_t *right,
                     const int64_t *lw, const uint32_t *size, int64_t M, uint32_t *pt_cluster,
                     uint64_t *pt_lambda, uint32_t *cl_id, uint32_t *cl_parent, uint32_t *cl_size,
                     uint64_t *cl_lambda_birth, uint64_t *cl_stab_hi, uint64_t *cl_stab_lo,
                     uint8_t *cl_selected, int32_t *labels, condense_counts *counts) {
+  return condense_impl(n, m, left, right, lw, size, M, NULL, NULL, pt_cluster, pt_lambda, cl_id, cl_parent,
+                       cl_size, cl_lambda_birth, cl_stab_hi, cl_stab_lo, cl_selected, labels, counts);
+}
+
+/*
+ * Alg. 5 (discrete dendrogram) cut from the exact one: thresholds thr[0] <
+ * ... < thr[q-1]; a row's level is the first threshold its weight does not
+ * exceed (reading: comps(H, omega) keeps edges with w <= omega, App. A).
+ * The rows must all satisfy w <= thr[q-1] (the caller drops the others: they
+ * merge nothing below the last threshold). The components at a level are
+ * the subtrees of rows of that level or lower; a component that first
+ * appears at level i is a D-node, represented by its highest row (its level
+ * top: a row whose parent has a higher level, or none). dd_level[k] is row
+ * k's level, dd_top[k] the node n+j of its level top j. Condensing then
+ * follows Campello et al. on this tree with several children per node: at a
+ * D-node, children of size >= M are big; two or more big children each start
+ * a cluster at the node's lambda = lambda(thr[level]); one continues the
+ * cluster; small children shed their records at that lambda.
+ */
+int oracle_condense_discrete(int64_t n, int64_t m, const uint32_t *left, const uint32_t *right,
+                             const int64_t *lw, const uint32_t *size, int64_t M, int64_t q, const int64_t *thr,
+                             uint32_t *pt_cluster, uint64_t *pt_lambda, uint32_t *cl_id, uint32_t *cl_parent,
+                             uint32_t *cl_size, uint64_t *cl_lambda_birth, uint64_t *cl_stab_hi,
+                             uint64_t *cl_stab_lo, uint8_t *cl_selected, int32_t *labels, uint32_t *dd_level,
+                             uint32_t *dd_top, condense_counts *counts) {
+  if (q < 1) return OR_EINVAL;
+  for (int64_t i = 1; i < q; i++)
+    if (thr[i] <= thr[i - 1]) return OR_EINVAL;
+  uint32_t *rowpar = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(m ? m : 1));
+  uint64_t *nlam = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(m ? m : 1));
+  if (!rowpar || !nlam) { free(rowpar); free(nlam); return OR_ENOMEM; }
+  for (int64_t k = 0; k < m; k++) {
+    int64_t L = 0;
+    while (L < q && lw[k] > thr[L]) L++;
+    if (L == q) { free(rowpar); free(nlam); return OR_EINVAL; } /* above the last threshold */
+    dd_level[k] = (uint32_t)L;
+    nlam[k] = lam(thr[L]);
+    rowpar[k] = NONE32;
+  }
+  for (int64_t k = 0; k < m; k++) {
+    if (left[k] >= (uint64_t)n) rowpar[left[k] - n] = (uint32_t)k;
+    if (right[k] >= (uint64_t)n) rowpar[right[k] - n] = (uint32_t)k;
+  }
+  /* parents are later rows: from the last row down, a row inherits its parent's top at equal level */
+  for (int64_t k = m - 1; k >= 0; k--) {
+    uint32_t p = rowpar[k];
+    dd_top[k] = (p != NONE32 && dd_level[p] == dd_level[k]) ? dd_top[p] : (uint32_t)(n + k);
+  }
+  free(rowpar);
+  int rc = condense_impl(n, m, left, right, lw, size, M, dd_top, nlam, pt_cluster, pt_lambda, cl_id, cl_parent,
+                         cl_size, cl_lambda_birth, cl_stab_hi, cl_stab_lo, cl_selected, labels, counts);
+  free(nlam);
+  return rc;
+}
+
+static int condense_impl(int64_t n, int64_t m, const uint32_t *left, const uint32_t *right, const int64_t *lw,
+                         const uint32_t *size, int64_t M, const uint32_t *dtop, const uint64_t *node_lam,
+                         uint32_t *pt_cluster, uint64_t *pt_lambda, uint32_t *cl_id, uint32_t *cl_parent,
+                         uint32_t *cl_size, uint64_t *cl_lambda_birth, uint64_t *cl_stab_hi,
+                         uint64_t *cl_stab_lo, uint8_t *cl_selected, int32_t *labels, condense_counts *counts) {
   if (M < 2) return OR_EINVAL;
   int64_t N = n + m;            /* dendrogram nodes */
   uint32_t ROOT = (uint32_t)N;  /* virtual root */
@@ -513,6 +586,40 @@ int oracle_condense(int64_t n, int64_t m, const uint32_t *left, const uint32_t *
     }
     wl_node[wl++] = (uint32_t)x;
   }
+  /* discrete: children of a D-node, gathered by walking its block */
+  uint32_t *dch = dtop ? (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(N + 1)) : NULL;
+  uint32_t *blk = dtop ? (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(N + 1)) : NULL;
+  if (dtop && (!dch || !blk)) {
+    free(dch); free(blk); free(wl_node);
+    free(parent); free(nsize); free(clus); free(stack); free(is_cluster); free(cpar); free(cbirth); free(stab);
+    return OR_ENOMEM;
+  }
+  while (wl && dtop) {
+    uint32_t x = wl_node[--wl];
+    uint32_t C = clus[x];
+    uint64_t L = node_lam[x - n];
+    int64_t nc = 0, nb = 0, bsp = 0;
+    blk[bsp++] = x;
+    while (bsp) {
+      uint32_t y = blk[--bsp];
+      uint32_t cs[2] = {left[y - n], right[y - n]};
+      for (int h = 0; h < 2; h++) {
+        uint32_t c = cs[h];
+        if (c >= (uint32_t)n && dtop[c - n] == x) blk[bsp++] = c; /* same block */
+        else dch[nc++] = c;
+      }
+    }
+    for (int64_t i = 0; i < nc; i++) nb += nsize[dch[i]] >= (uint64_t)M;
+    for (int64_t i = 0; i < nc; i++) {
+      uint32_t c = dch[i];
+      if (nsize[c] < (uint64_t)M) { SHED(c, C, L); continue; }
+      if (nb >= 2) { is_cluster[c] = 1; cpar[c] = C; cbirth[c] = L; clus[c] = c; }
+      else clus[c] = C;
+      wl_node[wl++] = c;
+    }
+  }
+  free(dch);
+  free(blk);
   while (wl) {
     uint32_t x = wl_node[--wl];
     uint32_t C = clus[x];

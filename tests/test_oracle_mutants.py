@@ -1,6 +1,6 @@
 """Planted mistakes in the oracle (on the CPU): each mutated copy of the oracle's
-C source must fail at least one pin in test_oracle_pins.py or
-test_oracle_causal.py. This shows the pins
+C source must fail at least one pin in test_oracle_pins.py,
+test_oracle_causal.py or test_oracle_discrete.py. This shows the pins
 would catch a dropped term, a wrong sign or index, or a transposed operand."""
 import os
 import subprocess
@@ -37,6 +37,11 @@ MUTANTS = [
     ("causal: window weight reversed", "out[cnt].w = t[e] - t[win[j]];", "out[cnt].w = t[win[j]] - t[e];"),
     ("time filter strict", "if (edges[e].w <= max_dt) edges[k++] = edges[e];",
      "if (edges[e].w < max_dt) edges[k++] = edges[e];"),
+    ("discrete levels with strict thresholds", "while (L < q && lw[k] > thr[L]) L++;",
+     "while (L < q && lw[k] >= thr[L]) L++;"),
+    ("discrete birth with one big child", "if (nb >= 2) { is_cluster[c] = 1;", "if (nb >= 1) { is_cluster[c] = 1;"),
+    ("discrete blocks ignore levels", "dd_top[k] = (p != NONE32 && dd_level[p] == dd_level[k]) ? dd_top[p]",
+     "dd_top[k] = (p != NONE32) ? dd_top[p]"),
 ]
 
 
@@ -52,6 +57,7 @@ def test_pins_catch_planted_mistake(name, old, new, tmp_path):
     env = dict(os.environ, CE_ORACLE_LIB=str(lib))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_causal.py"), "-k", "not four_records"],
+                        os.path.join(ROOT, "tests", "test_oracle_causal.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_discrete.py"), "-k", "not four_records"],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, "planted mistake '%s' passed every pin:\n%s" % (name, r.stdout[-2000:])
