@@ -77,8 +77,17 @@ typedef struct {
   int64_t max_dt;            /* >= 0: the time-filtered line graph (Sec. 5.1), only line-graph edges with
                                 w <= max_dt; the forest is then the rows of the unfiltered one with
                                 w <= max_dt (Thm 3 at that threshold). < 0: no cutoff */
+  const int64_t *thresholds; /* HOST array of num_thresholds strictly increasing weights >= 0, or NULL */
+  int64_t num_thresholds;    /* 0: the exact dendrogram. 1..CE_MAX_THRESHOLDS: the discrete dendrogram of
+                                Alg. 5: a row's level is the first threshold its w does not exceed (rows
+                                above the last one are dropped, as with max_dt); condensing runs on the
+                                discrete tree, whose node at a level merges all of that level's joins at
+                                once, at lambda(threshold): a node with two or more children of size >= M
+                                starts a cluster for each of them; see dd_level / dd_top in ce_result */
 } ce_params;
-#define CE_PARAMS_V1_SIZE 32
+#define CE_PARAMS_V1_SIZE 32 /* without max_dt */
+#define CE_PARAMS_V2_SIZE 40 /* without the thresholds */
+#define CE_MAX_THRESHOLDS 64
 
 /* Caller-allocated DEVICE output buffers. Any pointer may be NULL to skip
  * that output. Row capacities: rows of msf_* and sl_* >= max(n-1, 1);
@@ -96,6 +105,14 @@ typedef struct {
   uint64_t *cl_stab_hi, *cl_stab_lo;
   uint8_t *cl_selected;   /* 1 = the cluster is one of the output labels */
   int32_t *labels;
+  /* discrete dendrogram only (NULL otherwise), one entry per dendrogram row:
+   * dd_level = the row's level (threshold index); dd_top = the node id n+j of
+   * the row's level top j, the highest row reached through parents of the
+   * same level: the discrete node (a component first present at that level)
+   * the row belongs to. Discrete nodes are the rows with dd_top == own node;
+   * a node's parent is the dd_top of its parent row. Cluster ids are such
+   * node ids. */
+  uint32_t *dd_level, *dd_top;
 } ce_result;
 
 /* Host-side counts filled when the call returns. */

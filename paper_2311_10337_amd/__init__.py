@@ -23,12 +23,12 @@ NONE32 = 0xFFFFFFFF
 class CeParams(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("mode", ctypes.c_uint32), ("min_cluster_size", ctypes.c_int64),
                 ("num_vertices", ctypes.c_int64), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
-                ("max_dt", ctypes.c_int64)]
+                ("max_dt", ctypes.c_int64), ("thresholds", ctypes.c_void_p), ("num_thresholds", ctypes.c_int64)]
 
 
 _RESULT_FIELDS = ["msf_tail", "msf_head", "msf_w", "sl_left", "sl_right", "sl_w", "sl_size", "pt_cluster",
                   "pt_lambda", "cl_id", "cl_parent", "cl_size", "cl_lambda_birth", "cl_stab_hi", "cl_stab_lo",
-                  "cl_selected", "labels"]
+                  "cl_selected", "labels", "dd_level", "dd_top"]
 
 
 class CeResult(ctypes.Structure):
@@ -124,9 +124,19 @@ def exported_symbols():
     return {name: hasattr(lib, name) for name in _EXPORTS}
 
 
-def make_params(min_cluster_size: int, num_vertices: int, causal: bool = False, max_dt: int = -1) -> CeParams:
+def make_params(min_cluster_size: int, num_vertices: int, causal: bool = False, max_dt: int = -1,
+                thresholds=None) -> CeParams:
+    """Parameters; `thresholds` (increasing weights) selects the discrete dendrogram. The returned struct keeps
+    a reference to the thresholds' host array."""
+    import numpy as np
     mode = CE_MODE_CAUSAL if causal else CE_MODE_UNDIRECTED
-    return CeParams(ctypes.sizeof(CeParams), mode, int(min_cluster_size), int(num_vertices), 0, 0, int(max_dt))
+    p = CeParams(ctypes.sizeof(CeParams), mode, int(min_cluster_size), int(num_vertices), 0, 0, int(max_dt), None, 0)
+    if thresholds is not None and len(thresholds) > 0:
+        thr = np.ascontiguousarray(np.asarray(thresholds, dtype=np.int64))
+        p.thresholds = thr.ctypes.data
+        p.num_thresholds = thr.size
+        p._keep = thr
+    return p
 
 
 def workspace_bytes(n: int, num_vertices: int, min_cluster_size: int) -> int:
@@ -161,7 +171,8 @@ class ClusterError(RuntimeError):
 
 
 class Result(NamedTuple):
-    """Device tensors. u32/u64 fields are stored in int32/int64 tensors bit for bit."""
+    """Device tensors. u32/u64 fields are stored in int32/int64 tensors bit for bit. dd_level and dd_top are
+    None unless the discrete dendrogram was asked for."""
     m: int
     n_clusters: int
     n_labels: int
@@ -182,6 +193,8 @@ class Result(NamedTuple):
     cl_stab_lo: object
     cl_selected: object
     labels: object
+    dd_level: object = None
+    dd_top: object = None
 
 
 class Outputs:
@@ -203,17 +216,18 @@ class Outputs:
                   "sl_right": e(R, i32), "sl_w": e(R, i64), "sl_size": e(R, i32), "pt_cluster": e(n, i32),
                   "pt_lambda": e(n, i64), "cl_id": e(C, i32), "cl_parent": e(C, i32), "cl_size": e(C, i32),
                   "cl_lambda_birth": e(C, i64), "cl_stab_hi": e(C, i64), "cl_stab_lo": e(C, i64),
-                  "cl_selected": e(C, u8), "labels": e(n, i32)}
+                  "cl_selected": e(C, u8), "labels": e(n, i32), "dd_level": e(R, i32), "dd_top": e(R, i32)}
         self.struct = CeResult(**{f: ctypes.c_void_p(self.t[f].data_ptr()) for f in _RESULT_FIELDS})
 
 
 def cluster_edges(src, dst, t, min_cluster_size: int, num_vertices: int, outputs: Optional[Outputs] = None,
-                  workspace=None, stream=None, causal: bool = False, max_dt: int = -1) -> Result:
+                  workspace=None, stream=None, causal: bool = False, max_dt: int = -1, thresholds=None) -> Result:
     """Cluster temporal edges (src[i], dst[i], t[i]) held in GPU tensors (int32, int32, int64).
 
     ``causal=True`` uses the increment-weighted (tip-to-tail) line graph
     instead of the undirected one; ``max_dt >= 0`` keeps only line-graph
-    edges with w <= max_dt.
+    edges with w <= max_dt; ``thresholds`` selects the discrete dendrogram
+    (Alg. 5) and its condensing.
 
     Runs ``ce_cluster_edges`` on the current (or given) HIP stream and returns
     when the results are written. ``workspace`` may be a uint8 device tensor of
@@ -229,7 +243,7 @@ def cluster_edges(src, dst, t, min_cluster_size: int, num_vertices: int, outputs
         raise ValueError("src, dst, t must have the same length")
     if outputs is None or outputs.n < n or outputs.C < max_clusters(n, min_cluster_size):
         outputs = Outputs(n, min_cluster_size, src.device)
-    params = make_params(min_cluster_size, num_vertices, causal, max_dt)
+    params = make_params(min_cluster_size, num_vertices, causal, max_dt, thresholds)
     counts = CeCounts()
     s = stream if stream is not None else torch.cuda.current_stream(src.device)
     ws_ptr, ws_len = None, 0
@@ -246,7 +260,8 @@ def cluster_edges(src, dst, t, min_cluster_size: int, num_vertices: int, outputs
     pts = {f: o[f][:n] for f in ("pt_cluster", "pt_lambda", "labels")}
     cls = {f: o[f][:nc] for f in ("cl_id", "cl_parent", "cl_size", "cl_lambda_birth", "cl_stab_hi", "cl_stab_lo",
                                   "cl_selected")}
-    return Result(m=m, n_clusters=nc, n_labels=nl, **rows, **pts, **cls)
+    dd = {f: o[f][:m] for f in ("dd_level", "dd_top")} if params.num_thresholds else {}
+    return Result(m=m, n_clusters=nc, n_labels=nl, **rows, **pts, **cls, **dd)
 
 
 def _offsets_array(x, name):
@@ -301,7 +316,9 @@ class BatchResult(NamedTuple):
         parts = {}
         for f in Result._fields[3:]:
             x = getattr(self.result, f)
-            if f.startswith("msf_") or f.startswith("sl_"):
+            if x is None:
+                parts[f] = None
+            elif f.startswith("msf_") or f.startswith("sl_") or f.startswith("dd_"):
                 parts[f] = x[r0:r1]
             elif f.startswith("pt_") or f == "labels":
                 parts[f] = x[e0:e1]
@@ -313,7 +330,7 @@ class BatchResult(NamedTuple):
 
 def cluster_batch(src, dst, t, edge_offsets, vertex_offsets, min_cluster_size: int,
                   outputs: Optional[Outputs] = None, workspace=None, stream=None, causal: bool = False,
-                  max_dt: int = -1) -> BatchResult:
+                  max_dt: int = -1, thresholds=None) -> BatchResult:
     """Cluster a batch of independent graphs in one call (``ce_cluster_batch``).
 
     src/dst/t hold the graphs' records back to back (GPU tensors), vertex ids
@@ -335,7 +352,7 @@ def cluster_batch(src, dst, t, edge_offsets, vertex_offsets, min_cluster_size: i
     cap = batch_cluster_capacity(eo, min_cluster_size)
     if outputs is None or outputs.n < n or outputs.C < cap or outputs.R < max(n, 1):
         outputs = batch_outputs(eo, min_cluster_size, src.device)
-    params = make_params(min_cluster_size, max(int(vo[-1]), 1), causal, max_dt)
+    params = make_params(min_cluster_size, max(int(vo[-1]), 1), causal, max_dt, thresholds)
     counts = (CeCounts * G)()
     roff = np.zeros(G + 1, dtype=np.int64)
     coff = np.zeros(G + 1, dtype=np.int64)
@@ -358,7 +375,8 @@ def cluster_batch(src, dst, t, edge_offsets, vertex_offsets, min_cluster_size: i
     pts = {f: o[f][:n] for f in ("pt_cluster", "pt_lambda", "labels")}
     cls = {f: o[f][:c_tot] for f in ("cl_id", "cl_parent", "cl_size", "cl_lambda_birth", "cl_stab_hi", "cl_stab_lo",
                                      "cl_selected")}
-    res = Result(m=m_tot, n_clusters=c_tot, n_labels=int(carr[:, 2].sum()), **rows, **pts, **cls)
+    dd = {f: o[f][:m_tot] for f in ("dd_level", "dd_top")} if params.num_thresholds else {}
+    res = Result(m=m_tot, n_clusters=c_tot, n_labels=int(carr[:, 2].sum()), **rows, **pts, **cls, **dd)
     return BatchResult(result=res, m=carr[:, 0].copy(), n_clusters=carr[:, 1].copy(), n_labels=carr[:, 2].copy(),
                        edge_offsets=eo, row_offsets=roff, cluster_offsets=coff)
 
@@ -402,7 +420,7 @@ class Server:
         self._pending = {}
 
     def submit(self, src, dst, t, min_cluster_size: int, num_vertices: int, outputs: Optional[Outputs] = None,
-               device=None, causal: bool = False, max_dt: int = -1) -> int:
+               device=None, causal: bool = False, max_dt: int = -1, thresholds=None) -> int:
         import numpy as np
         import torch
         src = np.ascontiguousarray(src, dtype=np.int32)
@@ -414,14 +432,14 @@ class Server:
         if outputs is None or outputs.n < n or outputs.C < max_clusters(n, min_cluster_size):
             outputs = Outputs(n, min_cluster_size, device if device is not None else torch.device("cuda:0"))
         req = CeRequest(ctypes.sizeof(CeRequest), 0, src.ctypes.data, dst.ctypes.data, t.ctypes.data, n,
-                        make_params(min_cluster_size, num_vertices, causal, max_dt), outputs.struct)
+                        make_params(min_cluster_size, num_vertices, causal, max_dt, thresholds), outputs.struct)
         ticket = ctypes.c_uint64()
         st = load_library().ce_server_submit(self._h, ctypes.byref(req), ctypes.byref(ticket))
         if st == CE_EBUSY:
             raise ServerBusy(st, last_error(), "ce_server_submit")
         if st != CE_OK:
             raise ClusterError(st, last_error(), "ce_server_submit")
-        self._pending[int(ticket.value)] = (outputs, n)
+        self._pending[int(ticket.value)] = (outputs, n, thresholds is not None and len(thresholds) > 0)
         return int(ticket.value)
 
     def poll(self, ticket: int, wait: bool = False) -> Optional[RequestResult]:
@@ -431,7 +449,7 @@ class Server:
             return None
         if st != CE_OK:
             raise ClusterError(st, last_error(), "ce_server_poll")
-        outputs, n = self._pending.pop(int(ticket))
+        outputs, n, discrete = self._pending.pop(int(ticket))
         err = last_error() if rs.status != CE_OK else ""
         res = None
         if rs.status == CE_OK:
@@ -441,7 +459,8 @@ class Server:
             pts = {f: o[f][:n] for f in ("pt_cluster", "pt_lambda", "labels")}
             cls = {f: o[f][:nc] for f in ("cl_id", "cl_parent", "cl_size", "cl_lambda_birth", "cl_stab_hi",
                                           "cl_stab_lo", "cl_selected")}
-            res = Result(m=m, n_clusters=nc, n_labels=nl, **rows, **pts, **cls)
+            dd = {f: o[f][:m] for f in ("dd_level", "dd_top")} if discrete else {}
+            res = Result(m=m, n_clusters=nc, n_labels=nl, **rows, **pts, **cls, **dd)
         return RequestResult(int(rs.status), err, res, float(rs.queue_s), float(rs.latency_s))
 
     def stats(self) -> dict:
@@ -469,13 +488,16 @@ class Server:
 
 _UNSIGNED = {"msf_tail": "u4", "msf_head": "u4", "sl_left": "u4", "sl_right": "u4", "sl_size": "u4",
              "pt_cluster": "u4", "pt_lambda": "u8", "cl_id": "u4", "cl_parent": "u4", "cl_size": "u4",
-             "cl_lambda_birth": "u8", "cl_stab_hi": "u8", "cl_stab_lo": "u8"}
+             "cl_lambda_birth": "u8", "cl_stab_hi": "u8", "cl_stab_lo": "u8", "dd_level": "u4", "dd_top": "u4"}
 
 
 def to_numpy(res: Result) -> dict:
     """Copy a Result to host numpy arrays with the documented (unsigned) dtypes."""
     out = {"m": res.m, "n_clusters": res.n_clusters, "n_labels": res.n_labels}
     for f in Result._fields[3:]:
-        a = getattr(res, f).cpu().numpy()
+        x = getattr(res, f)
+        if x is None:
+            continue
+        a = x.cpu().numpy()
         out[f] = a.view(_UNSIGNED[f]) if f in _UNSIGNED else a
     return out

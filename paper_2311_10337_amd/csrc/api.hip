@@ -190,8 +190,9 @@ ce_status stage_write_rows(Bufs &b, int64_t m, const ce_result *out, hipStream_t
 // Scratch A (grouping, skeleton, Boruvka) follows X and may overlap Y; scratch
 // M (MSF sort) lies between X and Y; scratch B (dendrogram, condensing) starts
 // at the phase area and overlaps X.
-static void layout(Bufs &b, Ws &ws, int64_t n, int64_t M, int64_t G) {
+static void layout(Bufs &b, Ws &ws, int64_t n, int64_t M, int64_t G, bool discrete) {
   b.hdr = ws.alloc<uint64_t>(16);
+  b.thr = ws.alloc<int64_t>(CE_MAX_THRESHOLDS);
   b.eoff = ws.alloc<int64_t>(G + 1);
   b.voff = ws.alloc<int64_t>(G + 1);
   b.perm = ws.alloc<uint32_t>(n);
@@ -219,7 +220,7 @@ static void layout(Bufs &b, Ws &ws, int64_t n, int64_t M, int64_t G) {
   size_t scr_b = stage_dendrogram_scratch(n);
   x = stage_graph_rows_scratch(n, G);
   if (x > scr_b) scr_b = x;
-  x = stage_condense_scratch(n, M, G);
+  x = stage_condense_scratch(n, M, G, discrete);
   if (x > scr_b) scr_b = x;
   auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
   size_t phase = xbytes + al(scr_a);
@@ -243,13 +244,40 @@ static void layout(Bufs &b, Ws &ws, int64_t n, int64_t M, int64_t G) {
   b.scratch_b_bytes = phase - ybytes;
 }
 
-// the cutoff, when the caller's struct has the field
-static int64_t max_dt_of(const ce_params *p) { return p->struct_size >= sizeof(ce_params) ? p->max_dt : -1; }
+// fields the caller's struct has (earlier layouts end before them)
+static int64_t max_dt_of(const ce_params *p) { return p->struct_size >= CE_PARAMS_V2_SIZE ? p->max_dt : -1; }
 
-static size_t workspace_for(int64_t n, int64_t M, int64_t G) {
+struct Thresholds {
+  const int64_t *v = nullptr;
+  int64_t q = 0;
+};
+
+static ce_status thresholds_of(const ce_params *p, Thresholds *th) {
+  th->v = nullptr;
+  th->q = 0;
+  if (p->struct_size < sizeof(ce_params) || p->num_thresholds == 0) return CE_OK;
+  if (p->num_thresholds < 0 || p->num_thresholds > CE_MAX_THRESHOLDS || !p->thresholds) {
+    set_error("num_thresholds must be in [0, 64] with a thresholds array");
+    return CE_EINVAL;
+  }
+  for (int64_t i = 0; i < p->num_thresholds; i++) {
+    if (p->thresholds[i] < 0 || (i > 0 && p->thresholds[i] <= p->thresholds[i - 1])) {
+      set_error("thresholds must be >= 0 and strictly increasing");
+      return CE_EINVAL;
+    }
+  }
+  th->v = p->thresholds;
+  th->q = p->num_thresholds;
+  return CE_OK;
+}
+
+// condensing on the discrete dendrogram needs room for nodes with many children
+static bool discrete_of(const ce_params *p) { return p->struct_size >= sizeof(ce_params) && p->num_thresholds > 0; }
+
+static size_t workspace_for(int64_t n, int64_t M, int64_t G, bool discrete) {
   Bufs b;
   Ws ws;
-  layout(b, ws, n, M, G);
+  layout(b, ws, n, M, G, discrete);
   return ws.peak;
 }
 
@@ -280,13 +308,13 @@ static ce_status check_offsets(const int64_t *eoff, const int64_t *voff, int64_t
 // Runs a checked batch; eoff/voff are host arrays of G+1 offsets.
 static ce_status run_batch(const int32_t *src, const int32_t *dst, const int64_t *t, const int64_t *eoff,
                            const int64_t *voff, int64_t G, int64_t M, bool causal, int64_t max_dt,
-                           const ce_result *out, ce_counts *counts,
+                           Thresholds th, const ce_result *out, ce_counts *counts,
                            int64_t *row_offsets, int64_t *cluster_offsets, void *workspace, size_t workspace_bytes,
                            hipStream_t s) {
   const int64_t n = eoff[G], V = voff[G];
   for (int64_t g = 0; g < G; g++) counts[g] = ce_counts{0, 1, 0};
   if (n > 0 && (!src || !dst || !t)) { set_error("input pointer is NULL"); return CE_EINVAL; }
-  const size_t need = workspace_for(n, M, G);
+  const size_t need = workspace_for(n, M, G, th.q > 0);
   void *base = workspace;
   bool own = false, async_alloc = true;
   if (!base) {
@@ -314,13 +342,19 @@ static ce_status run_batch(const int32_t *src, const int32_t *dst, const int64_t
   ws.base = (char *)base;
   ws.cap = need;
   Bufs b;
-  layout(b, ws, n, M, G);
+  layout(b, ws, n, M, G, th.q > 0);
   CE_WS_CHECK(ws);
   b.n = n;
   b.V = V;
   b.M = M;
   b.G = G;
   CE_HIP(hipMemcpyAsync((void *)b.eoff, eoff, sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, s));
+  if (th.q > 0) {
+    CE_HIP(hipMemcpyAsync((void *)b.thr, th.v, sizeof(int64_t) * th.q, hipMemcpyHostToDevice, s));
+    b.q = (int)th.q;
+    // rows above the last threshold merge nothing in the discrete dendrogram
+    if (max_dt < 0 || max_dt > th.v[th.q - 1]) max_dt = th.v[th.q - 1];
+  }
   CE_HIP(hipMemcpyAsync((void *)b.voff, voff, sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, s));
   uint64_t flags = 0;
   int64_t tmin = 0, tmax = 0;
@@ -400,13 +434,13 @@ size_t ce_workspace_bytes(int64_t n, int64_t num_vertices, const ce_params *para
   }
   if (check_params(&p) != CE_OK) return 0;
   if (n < 0 || n > 0x7fffffffLL || num_vertices < 1 || num_vertices > 0x80000000LL) return 0;
-  return workspace_for(n, p.min_cluster_size, 1);
+  return workspace_for(n, p.min_cluster_size, 1, discrete_of(&p));
 }
 
 size_t ce_batch_workspace_bytes(const int64_t *edge_offsets, const int64_t *vertex_offsets, int64_t num_graphs,
                                 const ce_params *params) {
   if (check_params(params) != CE_OK || check_offsets(edge_offsets, vertex_offsets, num_graphs) != CE_OK) return 0;
-  return workspace_for(edge_offsets[num_graphs], params->min_cluster_size, num_graphs);
+  return workspace_for(edge_offsets[num_graphs], params->min_cluster_size, num_graphs, discrete_of(params));
 }
 
 const char *ce_last_error(void) { return g_err.c_str(); }
@@ -437,8 +471,11 @@ ce_status ce_cluster_edges(const int32_t *src, const int32_t *dst, const int64_t
   }
   if (n < 0 || n > 0x7fffffffLL) { set_error("n must be in [0, 2^31-1]"); return CE_EINVAL; }
   const int64_t eoff[2] = {0, n}, voff[2] = {0, params->num_vertices};
+  Thresholds th;
+  CE_TRY(thresholds_of(params, &th));
   return run_batch(src, dst, t, eoff, voff, 1, params->min_cluster_size, params->mode == CE_MODE_CAUSAL,
-                   max_dt_of(params), out, counts, nullptr, nullptr, workspace, workspace_bytes, (hipStream_t)stream);
+                   max_dt_of(params), th, out, counts, nullptr, nullptr, workspace, workspace_bytes,
+                   (hipStream_t)stream);
 }
 
 ce_status ce_cluster_batch(const int32_t *src, const int32_t *dst, const int64_t *t, const int64_t *edge_offsets,
@@ -451,8 +488,10 @@ ce_status ce_cluster_batch(const int32_t *src, const int32_t *dst, const int64_t
     return CE_EINVAL;
   }
   CE_TRY(check_offsets(edge_offsets, vertex_offsets, num_graphs));
+  Thresholds th;
+  CE_TRY(thresholds_of(params, &th));
   return run_batch(src, dst, t, edge_offsets, vertex_offsets, num_graphs, params->min_cluster_size,
-                   params->mode == CE_MODE_CAUSAL, max_dt_of(params), out, counts, row_offsets, cluster_offsets,
+                   params->mode == CE_MODE_CAUSAL, max_dt_of(params), th, out, counts, row_offsets, cluster_offsets,
                    workspace, workspace_bytes, (hipStream_t)stream);
 }
 

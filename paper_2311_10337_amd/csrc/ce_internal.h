@@ -283,6 +283,9 @@ struct Bufs {
   int wshift = 0, hshift = 0, jbits = 0;
   bool causal = false;
   int64_t S = 0;  // causal skeleton rows (slots 0..S-1)
+  // discrete dendrogram (Alg. 5): q thresholds on the device, 0 = exact
+  const int64_t *thr = nullptr;
+  int q = 0;
   int64_t tmin = 0;
   // persistent
   uint64_t *hdr = nullptr;      // [16] device header / counters
@@ -330,6 +333,6 @@ ce_status stage_time_filter(Bufs &b, int64_t max_dt, hipStream_t s, int64_t *m);
 size_t stage_boruvka_scratch(int64_t n);
 size_t stage_msf_sort_scratch(int64_t n);
 size_t stage_dendrogram_scratch(int64_t n);
-size_t stage_condense_scratch(int64_t n, int64_t M, int64_t G);
+size_t stage_condense_scratch(int64_t n, int64_t M, int64_t G, bool discrete);
 
 }  // namespace ce

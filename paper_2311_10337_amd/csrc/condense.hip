@@ -59,13 +59,13 @@ __global__ __launch_bounds__(B) void k_cd_bigroots(const uint32_t *kpar, const u
 }
 
 __global__ __launch_bounds__(B) void k_cd_birth(const uint32_t *kc_u, const uint32_t *kc_v, const uint32_t *ksize,
-                                                const uint32_t *kpar, const uint64_t *msf_key, int wshift, int64_t m,
+                                                const uint32_t *kpar, const uint64_t *rowL, bool discrete, int64_t m,
                                                 int64_t n, int64_t M, const uint32_t *nbig, const uint32_t *rowg,
                                                 uint8_t *isbirth, uint64_t *birthL) {
   for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
     uint32_t a = kc_u[j], b = kc_v[j];
-    if (node_size(a, n, ksize) >= (uint64_t)M && node_size(b, n, ksize) >= (uint64_t)M) {
-      uint64_t L = lambda_of(row_w(j, msf_key, wshift));
+    if (!discrete && node_size(a, n, ksize) >= (uint64_t)M && node_size(b, n, ksize) >= (uint64_t)M) {
+      uint64_t L = rowL[j];
       isbirth[a - n] = 1;
       birthL[a - n] = L;
       isbirth[b - n] = 1;
@@ -75,6 +75,70 @@ __global__ __launch_bounds__(B) void k_cd_birth(const uint32_t *kc_u, const uint
       isbirth[j] = 1;
       birthL[j] = 0;
     }
+  }
+}
+
+// lambda of every row: of its weight, or with thresholds (the discrete
+// dendrogram of Alg. 5) of its level's threshold, level = the first threshold
+// the weight does not exceed
+__global__ __launch_bounds__(B) void k_row_lambda(const uint64_t *msf_key, int wshift, int64_t m, const int64_t *thr,
+                                                  int q, uint64_t *rowL, uint32_t *level) {
+  for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
+    const int64_t w = (int64_t)(msf_key[j] >> wshift);
+    if (q == 0) {
+      rowL[j] = lambda_of(w);
+      continue;
+    }
+    int L = 0;
+    while (L < q - 1 && w > thr[L]) L++;  // rows above the last threshold were dropped before
+    rowL[j] = lambda_of(thr[L]);
+    level[j] = (uint32_t)L;
+  }
+}
+
+// Discrete dendrogram: a row's level top is its highest ancestor reached
+// through parents of the same level (the component that first appears at that
+// level, a D-node). First step: the parent if it has the same level.
+__global__ __launch_bounds__(B) void k_dd_top_init(const uint32_t *kpar, const uint32_t *level, int64_t m, int64_t n,
+                                                   uint32_t *top) {
+  for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
+    const uint32_t p = kpar[n + j];
+    top[j] = (p != NONE32 && level[p - n] == level[j]) ? p : (uint32_t)(n + j);
+  }
+}
+// pointer doubling over rows; counts rows that moved
+__global__ __launch_bounds__(B) void k_dd_top_jump(const uint32_t *tin, int64_t m, int64_t n, uint32_t *tout,
+                                                   unsigned long long *moved) {
+  uint32_t cnt = 0;
+  for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
+    const uint32_t t = tin[j], tt = tin[t - n];
+    tout[j] = tt;
+    cnt += tt != t;
+  }
+  cnt = wave_sum_u32(cnt);
+  if (wave_lane() == 0 && cnt) atomicAdd(moved, (unsigned long long)cnt);
+}
+// big children of every D-node: the level tops (rows that are their own top)
+// hanging below its block; records are never big (M >= 2)
+__global__ __launch_bounds__(B) void k_dd_bigcount(const uint32_t *kpar, const uint32_t *ksize, const uint32_t *top,
+                                                   int64_t m, int64_t n, int64_t M, uint32_t *bigcnt) {
+  for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
+    const uint32_t p = kpar[n + j];
+    if (p == NONE32 || top[j] != (uint32_t)(n + j) || ksize[j] < (uint64_t)M) continue;
+    atomicAdd(&bigcnt[top[p - n] - n], 1u);
+  }
+}
+// a big child of a D-node with two or more big children starts a cluster at
+// the D-node's lambda
+__global__ __launch_bounds__(B) void k_dd_birth(const uint32_t *kpar, const uint32_t *ksize, const uint32_t *top,
+                                                const uint32_t *bigcnt, const uint64_t *rowL, int64_t m, int64_t n,
+                                                int64_t M, uint8_t *isbirth, uint64_t *birthL) {
+  for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
+    const uint32_t p = kpar[n + j];
+    if (p == NONE32 || top[j] != (uint32_t)(n + j) || ksize[j] < (uint64_t)M) continue;
+    if (bigcnt[top[p - n] - n] < 2) continue;
+    isbirth[j] = 1;
+    birthL[j] = rowL[p - n];
   }
 }
 
@@ -137,7 +201,7 @@ __global__ __launch_bounds__(B) void k_cd_jstep(const uint32_t *act, int64_t nac
 
 // exit of each record: lowest big ancestor y -> (cluster of y, lambda(w_y))
 __global__ __launch_bounds__(B) void k_cd_exit(const uint32_t *kpar, const uint32_t *ksize, const uint32_t *J,
-                                               const uint64_t *msf_key, const uint32_t *grank, int wshift, int64_t m,
+                                               const uint64_t *rowL, const uint32_t *grank, int64_t m,
                                                int64_t n, int64_t M, uint32_t *exc, uint64_t *exl) {
   for (int64_t p = (int64_t)blockIdx.x * B + threadIdx.x; p < n; p += (int64_t)gridDim.x * B) {
     uint32_t y = kpar[p];
@@ -147,7 +211,7 @@ __global__ __launch_bounds__(B) void k_cd_exit(const uint32_t *kpar, const uint3
       exl[p] = 0;
     } else {
       exc[p] = J[y - n];
-      exl[p] = lambda_of(row_w((int64_t)y - n, msf_key, wshift));
+      exl[p] = rowL[y - n];
     }
   }
 }
@@ -158,12 +222,12 @@ __global__ __launch_bounds__(B) void k_cd_exit(const uint32_t *kpar, const uint3
 // Records outside such subtrees keep the default exit (ROOT, 0).
 constexpr int EXIT_STACK = 64;
 __global__ __launch_bounds__(B) void k_cd_exit_down(const uint32_t *kc_u, const uint32_t *kc_v, const uint32_t *ksize,
-                                                    const uint32_t *J, const uint64_t *msf_key, int wshift, int64_t m,
+                                                    const uint32_t *J, const uint64_t *rowL, int64_t m,
                                                     int64_t n, int64_t M, uint32_t *exc, uint64_t *exl) {
   for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
     if (ksize[j] < (uint64_t)M) continue;
     const uint32_t C = J[j];
-    const uint64_t L = lambda_of(row_w(j, msf_key, wshift));
+    const uint64_t L = rowL[j];
 #pragma unroll
     for (int side = 0; side < 2; side++) {
       const uint32_t c = side ? kc_v[j] : kc_u[j];
@@ -373,6 +437,56 @@ __global__ __launch_bounds__(B) void k_cd_children(const uint32_t *cprow, uint32
   }
 }
 
+// More than two child clusters (discrete dendrogram): children listed per
+// parent, then a parent with k children gets a chain of k-2 virtual nodes
+// (rows nrows..) of stability 0, so that every node has at most two children
+// and a virtual node's value max(0, x + y) is the plain sum of its two.
+__global__ __launch_bounds__(B) void k_cd_childcount(const uint32_t *cprow, uint32_t nrows, uint32_t *nch) {
+  for (int64_t r = (int64_t)blockIdx.x * B + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * B) {
+    const uint32_t p = cprow[r];
+    if (p == NONE32 || cprow[p] == NONE32) continue;
+    atomicAdd(&nch[p], 1u);
+  }
+}
+__global__ __launch_bounds__(B) void k_cd_childlist(const uint32_t *cprow, const uint32_t *choff, uint32_t nrows,
+                                                    uint32_t *fill, uint32_t *clist) {
+  for (int64_t r = (int64_t)blockIdx.x * B + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * B) {
+    const uint32_t p = cprow[r];
+    if (p == NONE32 || cprow[p] == NONE32) continue;
+    clist[choff[p] + atomicAdd(&fill[p], 1u)] = (uint32_t)r;
+  }
+}
+__global__ __launch_bounds__(B) void k_cd_vcount(const uint32_t *nch, uint32_t nrows, uint32_t *vcnt) {
+  for (int64_t r = (int64_t)blockIdx.x * B + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * B)
+    vcnt[r] = nch[r] > 2 ? nch[r] - 2 : 0u;
+}
+__global__ __launch_bounds__(B) void k_cd_pairs(const uint32_t *nch, const uint32_t *choff, const uint32_t *clist,
+                                                const uint32_t *vbase, uint32_t nrows, uint32_t *ch, uint32_t *vnch,
+                                                uint64_t *shi, uint64_t *slo) {
+  for (int64_t p = (int64_t)blockIdx.x * B + threadIdx.x; p < nrows; p += (int64_t)gridDim.x * B) {
+    const uint32_t k = nch[p];
+    if (k == 0) continue;
+    const uint32_t *L = clist + choff[p];
+    if (k <= 2) {
+      ch[2 * p] = L[0];
+      ch[2 * p + 1] = k == 2 ? L[1] : L[0];
+      continue;
+    }
+    // p -> (L0, v0), v_i -> (L_{i+1}, v_{i+1}), the last virtual node -> (L_{k-2}, L_{k-1})
+    const uint32_t v0 = nrows + vbase[p];
+    ch[2 * p] = L[0];
+    ch[2 * p + 1] = v0;
+    for (uint32_t i = 0; i + 2 < k; i++) {
+      const uint32_t v = v0 + i;
+      ch[2 * (uint64_t)v] = L[i + 1];
+      ch[2 * (uint64_t)v + 1] = (i + 3 < k) ? v + 1 : L[k - 1];
+      vnch[v] = 2;
+      shi[v] = 0;
+      slo[v] = 0;
+    }
+  }
+}
+
 // EOM state per row: st = 0 pending-binary, 1 pending-unary, 2 done
 struct Eom {
   uint8_t *st;
@@ -392,8 +506,8 @@ __device__ inline void eom_store(const Eom &o, uint32_t r, uint8_t st, u128 v, u
 }
 
 __global__ __launch_bounds__(B) void k_eom_init(const uint32_t *nch, const uint64_t *shi, const uint64_t *slo,
-                                                const uint32_t *cprow, uint32_t nrows, Eom e0, Eom e1, uint32_t *act,
-                                                unsigned long long *nact) {
+                                                const uint32_t *cprow, uint32_t nreal, uint32_t nrows, Eom e0,
+                                                Eom e1, uint32_t *act, unsigned long long *nact) {
   bool keep[CT];
   uint32_t vals[CT];
   const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
@@ -403,7 +517,8 @@ __global__ __launch_bounds__(B) void k_eom_init(const uint32_t *nch, const uint6
     keep[k] = false;
     vals[k] = (uint32_t)r;
     if (r >= nrows) continue;
-    bool leaf = nch[r] == 0 || cprow[r] == NONE32;
+    // rows from nreal on are virtual sum nodes, never leaves
+    bool leaf = r < nreal && (nch[r] == 0 || cprow[r] == NONE32);
     u128 S{slo[r], shi[r]}, z{0, 0};
     eom_store(e0, (uint32_t)r, leaf ? 2 : 0, S, z, z, NONE32);
     eom_store(e1, (uint32_t)r, leaf ? 2 : 0, S, z, z, NONE32);
@@ -593,6 +708,17 @@ __global__ __launch_bounds__(B) void k_out_clusters(const uint32_t *cnode, const
   }
 }
 
+// discrete dendrogram per output row: level, and the row's D-node as a node id
+__global__ __launch_bounds__(B) void k_out_discrete(const uint32_t *level, const uint32_t *top, const uint32_t *rowg,
+                                                    const int64_t *eoff, const uint32_t *moff, const uint32_t *rowpos,
+                                                    int64_t n, int64_t m, uint32_t *dd_level, uint32_t *dd_top) {
+  for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
+    const uint32_t g = rowg[j], p = rowpos[j];
+    if (dd_level) dd_level[p] = level[j];
+    if (dd_top) dd_top[p] = local_node(top[j], g, n, m, eoff, moff, rowpos);
+  }
+}
+
 // labels per graph: the chosen clusters whose minimum member lies in g
 __global__ __launch_bounds__(B) void k_graph_labels(const uint32_t *fscan, const int64_t *eoff, int64_t G,
                                                     uint32_t *nl) {
@@ -602,15 +728,44 @@ __global__ __launch_bounds__(B) void k_graph_labels(const uint32_t *fscan, const
 
 }  // namespace
 
+// level tops by pointer doubling, big children per D-node, births
+static ce_status discrete_births(Bufs &b, int64_t m, const uint32_t *kpar, const uint32_t *level,
+                                 const uint64_t *rowL, uint32_t *&top, uint32_t *&top2, uint32_t *bigcnt,
+                                 uint8_t *isbirth, uint64_t *birthL, hipStream_t s) {
+  const int64_t n = b.n, M = b.M;
+  const unsigned g = grid_for(m, B);
+  CE_LAUNCH(k_dd_top_init, dim3(g), dim3(B), 0, s, kpar, level, m, n, top);
+  CE_HIP(hipGetLastError());
+  for (int it = 0;; it++) {
+    if (it > 40) {
+      set_error("level-top pointer jumping did not converge");
+      return CE_EDEVICE;
+    }
+    CE_LAUNCH(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[9], (uint64_t)0);
+    CE_LAUNCH(k_dd_top_jump, dim3(g), dim3(B), 0, s, top, m, n, top2, (unsigned long long *)&b.hdr[9]);
+    CE_HIP(hipGetLastError());
+    uint32_t *t = top; top = top2; top2 = t;
+    uint64_t moved = 0;
+    CE_TRY(read_u64(&b.hdr[9], &moved, 1, s));
+    if (moved == 0) break;
+  }
+  CE_LAUNCH(k_fill32, dim3(g), dim3(B), 0, s, bigcnt, m, 0u);
+  CE_LAUNCH(k_dd_bigcount, dim3(g), dim3(B), 0, s, kpar, b.ksize, top, m, n, M, bigcnt);
+  CE_LAUNCH(k_dd_birth, dim3(g), dim3(B), 0, s, kpar, b.ksize, top, bigcnt, rowL, m, n, M, isbirth, birthL);
+  CE_HIP(hipGetLastError());
+  return CE_OK;
+}
+
 static int64_t cluster_row_bound(int64_t n, int64_t M, int64_t G) { return 2 * (n / M) + G + 1; }
 
-size_t stage_condense_scratch(int64_t n, int64_t M, int64_t G) {
-  const int64_t m = n, R = cluster_row_bound(n, M < 2 ? 2 : M, G);
+size_t stage_condense_scratch(int64_t n, int64_t M, int64_t G, bool discrete) {
+  const int64_t m = n, R = cluster_row_bound(n, M < 2 ? 2 : M, G), RE = discrete ? 2 * R : R;
   Ws w;
   w.alloc<uint32_t>(n + m + 1);  // kpar
   w.alloc<uint32_t>(m + 1); w.alloc<uint32_t>(m + 1); w.alloc<uint32_t>(m + 1);  // J, active lists
   w.alloc<uint8_t>(m + 4);       // isbirth
   w.alloc<uint64_t>(m + 1);      // birthL
+  w.alloc<uint64_t>(m + 1);      // rowL (the discrete arrays reuse exc, exl, labrow and fl)
   w.alloc<uint32_t>(m + 2); w.alloc<uint32_t>(m + 2); w.alloc<uint32_t>(m + 1);  // flags32, idx, rowof
   for (int k = 0; k < 3; k++) w.alloc<uint32_t>(G + 2);  // nbig, bstart, rootrow
   w.alloc<uint32_t>(G + 1);  // labels per graph
@@ -618,31 +773,35 @@ size_t stage_condense_scratch(int64_t n, int64_t M, int64_t G) {
   w.alloc<uint32_t>(n); w.alloc<uint64_t>(n);  // exc exl
   w.alloc<uint32_t>(R); w.alloc<uint32_t>(R); w.alloc<uint64_t>(R); w.alloc<uint32_t>(R);  // cnode csize cbirth cprow
   w.alloc<uint64_t>(3 * R);  // acc
-  w.alloc<uint64_t>(R); w.alloc<uint64_t>(R);  // shi slo
-  w.alloc<uint32_t>(R); w.alloc<uint32_t>(2 * R);  // nch ch
+  w.alloc<uint64_t>(RE); w.alloc<uint64_t>(RE);  // shi slo (and virtual nodes)
+  w.alloc<uint32_t>(RE); w.alloc<uint32_t>(2 * RE);  // nch ch
+  if (discrete)
+    for (int k = 0; k < 4; k++) w.alloc<uint32_t>(R + 1);  // child offsets, fill counts, lists, virtual bases
   for (int k = 0; k < 2; k++) {
-    w.alloc<uint8_t>(R);
-    for (int q = 0; q < 6; q++) w.alloc<uint64_t>(R);
-    w.alloc<uint32_t>(R);
+    w.alloc<uint8_t>(RE);
+    for (int q = 0; q < 6; q++) w.alloc<uint64_t>(RE);
+    w.alloc<uint32_t>(RE);
   }
   for (int k = 0; k < 4; k++) w.alloc<uint32_t>(R);  // top nxt x2
   w.alloc<uint32_t>(R);  // minmem
-  w.alloc<uint32_t>(R); w.alloc<uint32_t>(R);  // row active lists
+  w.alloc<uint32_t>(RE); w.alloc<uint32_t>(RE);  // row active lists
   w.alloc<uint32_t>(n);  // labrow
   w.alloc<uint32_t>(n + 1);  // flag / scan
-  return w.off + scan_ws_bytes(n + 1) + scan_ws_bytes(m + 1) + scan_ws_bytes(G + 1) + radix_ws_bytes(R) + 8192;
+  return w.off + scan_ws_bytes(n + 1) + scan_ws_bytes(m + 1) + scan_ws_bytes(G + 1) + scan_ws_bytes(R + 1) +
+         radix_ws_bytes(R) + 8192;
 }
 
 ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipStream_t s, ce_counts *counts,
                          int64_t *cluster_offsets) {
   const int64_t n = b.n, M = b.M, G = b.G;
   size_t m0 = ws.mark();
-  const int64_t R = cluster_row_bound(n, M, G);
+  const int64_t R = cluster_row_bound(n, M, G), RE = b.q > 0 ? 2 * R : R;
   uint32_t *kpar = ws.alloc<uint32_t>(n + m + 1);
   uint32_t *J = ws.alloc<uint32_t>(m + 1);
   uint32_t *jact = ws.alloc<uint32_t>(m + 1), *jact2 = ws.alloc<uint32_t>(m + 1);
   uint8_t *isbirth = ws.alloc<uint8_t>(m + 4);
   uint64_t *birthL = ws.alloc<uint64_t>(m + 1);
+  uint64_t *rowL = ws.alloc<uint64_t>(m + 1);
   uint32_t *flags32 = ws.alloc<uint32_t>(m + 2), *idx = ws.alloc<uint32_t>(m + 2), *rowof = ws.alloc<uint32_t>(m + 1);
   uint32_t *nbig = ws.alloc<uint32_t>(G + 2), *bstart = ws.alloc<uint32_t>(G + 2);
   uint32_t *rootrow = ws.alloc<uint32_t>(G + 2);
@@ -655,23 +814,33 @@ ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipSt
   uint64_t *cbirth = ws.alloc<uint64_t>(R);
   uint32_t *cprow = ws.alloc<uint32_t>(R);
   unsigned long long *acc = ws.alloc<unsigned long long>(3 * R);
-  uint64_t *shi = ws.alloc<uint64_t>(R), *slo = ws.alloc<uint64_t>(R);
-  uint32_t *nch = ws.alloc<uint32_t>(R), *ch = ws.alloc<uint32_t>(2 * R);
+  uint64_t *shi = ws.alloc<uint64_t>(RE), *slo = ws.alloc<uint64_t>(RE);
+  uint32_t *nch = ws.alloc<uint32_t>(RE), *ch = ws.alloc<uint32_t>(2 * RE);
+  uint32_t *choff = nullptr, *cfill = nullptr, *clist = nullptr, *vbase = nullptr;
+  if (b.q > 0) {
+    choff = ws.alloc<uint32_t>(R + 1);
+    cfill = ws.alloc<uint32_t>(R + 1);
+    clist = ws.alloc<uint32_t>(R + 1);
+    vbase = ws.alloc<uint32_t>(R + 1);
+  }
   Eom e[2];
   for (int k = 0; k < 2; k++) {
-    e[k].st = ws.alloc<uint8_t>(R);
-    e[k].vhi = ws.alloc<uint64_t>(R); e[k].vlo = ws.alloc<uint64_t>(R);
-    e[k].ahi = ws.alloc<uint64_t>(R); e[k].alo = ws.alloc<uint64_t>(R);
-    e[k].bhi = ws.alloc<uint64_t>(R); e[k].blo = ws.alloc<uint64_t>(R);
-    e[k].dep = ws.alloc<uint32_t>(R);
+    e[k].st = ws.alloc<uint8_t>(RE);
+    e[k].vhi = ws.alloc<uint64_t>(RE); e[k].vlo = ws.alloc<uint64_t>(RE);
+    e[k].ahi = ws.alloc<uint64_t>(RE); e[k].alo = ws.alloc<uint64_t>(RE);
+    e[k].bhi = ws.alloc<uint64_t>(RE); e[k].blo = ws.alloc<uint64_t>(RE);
+    e[k].dep = ws.alloc<uint32_t>(RE);
   }
   uint32_t *top = ws.alloc<uint32_t>(R), *nxt = ws.alloc<uint32_t>(R);
   uint32_t *top2 = ws.alloc<uint32_t>(R), *nxt2 = ws.alloc<uint32_t>(R);
   uint32_t *minmem = ws.alloc<uint32_t>(R);
-  uint32_t *ract = ws.alloc<uint32_t>(R), *ract2 = ws.alloc<uint32_t>(R);
+  uint32_t *ract = ws.alloc<uint32_t>(RE), *ract2 = ws.alloc<uint32_t>(RE);
   uint32_t *labrow = ws.alloc<uint32_t>(n);
   uint32_t *fl = ws.alloc<uint32_t>(n + 1);
   CE_WS_CHECK(ws);
+  // discrete dendrogram: level, level tops (two arrays) and big-child counts per row live only until the
+  // births are known and the per-row discrete outputs written, before exits, labels and flags use these
+  uint32_t *level = exc, *dtop = labrow, *dtop2 = fl, *bigcnt = (uint32_t *)exl;
   unsigned long long *ctr = (unsigned long long *)&b.hdr[8];
   auto tiles = [](int64_t k) { return (unsigned)((k + (int64_t)B * CT - 1) / ((int64_t)B * CT)); };
 
@@ -685,8 +854,17 @@ ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipSt
   CE_LAUNCH(k_fill32, dim3(grid_for((m + 4) / 4, B)), dim3(B), 0, s, (uint32_t *)isbirth, (m + 4) / 4, 0u);
   CE_HIP(hipGetLastError());
   if (m > 0) {
-    CE_LAUNCH(k_cd_birth, dim3(grid_for(m, B)), dim3(B), 0, s, b.kc_u, b.kc_v, b.ksize, kpar, b.msf_key, b.wshift, m,
-              n, M, nbig, b.rowg, isbirth, birthL);
+    CE_LAUNCH(k_row_lambda, dim3(grid_for(m, B)), dim3(B), 0, s, b.msf_key, b.wshift, m, b.thr, b.q, rowL, level);
+    CE_LAUNCH(k_cd_birth, dim3(grid_for(m, B)), dim3(B), 0, s, b.kc_u, b.kc_v, b.ksize, kpar, rowL, b.q > 0, m, n,
+              M, nbig, b.rowg, isbirth, birthL);
+    CE_HIP(hipGetLastError());
+    if (b.q > 0) {
+      CE_TRY(discrete_births(b, m, kpar, level, rowL, dtop, dtop2, bigcnt, isbirth, birthL, s));
+      if (out->dd_level || out->dd_top)
+        CE_LAUNCH(k_out_discrete, dim3(grid_for(m, B)), dim3(B), 0, s, level, dtop, b.rowg, b.eoff, b.moff, b.rowpos,
+                  n, m, out->dd_level, out->dd_top);
+      CE_HIP(hipGetLastError());
+    }
     CE_LAUNCH(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[9], (uint64_t)0);
     CE_LAUNCH(k_cd_jinit, dim3(tiles(m)), dim3(B), 0, s, isbirth, kpar, b.ksize, b.rowg, m, n, M, J, jact,
               (unsigned long long *)&b.hdr[9]);
@@ -709,10 +887,10 @@ ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipSt
   if (M <= EXIT_STACK) {
     CE_LAUNCH(k_exit_default, dim3(grid_for(n, B)), dim3(B), 0, s, b.grank, n, m, exc, exl);
     if (m > 0)
-      CE_LAUNCH(k_cd_exit_down, dim3(grid_for(m, B)), dim3(B), 0, s, b.kc_u, b.kc_v, b.ksize, J, b.msf_key, b.wshift,
+      CE_LAUNCH(k_cd_exit_down, dim3(grid_for(m, B)), dim3(B), 0, s, b.kc_u, b.kc_v, b.ksize, J, rowL,
                 m, n, M, exc, exl);
   } else {
-    CE_LAUNCH(k_cd_exit, dim3(grid_for(n, B)), dim3(B), 0, s, kpar, b.ksize, J, b.msf_key, b.grank, b.wshift, m, n,
+    CE_LAUNCH(k_cd_exit, dim3(grid_for(n, B)), dim3(B), 0, s, kpar, b.ksize, J, rowL, b.grank, m, n,
               M, exc, exl);
   }
   // cluster rows: births in (graph, node) order, each graph followed by its root row
@@ -762,9 +940,32 @@ ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipSt
   CE_LAUNCH(k_cd_stab, dim3(gR), dim3(B), 0, s, acc, csize, cbirth, nrows, shi, slo);
   CE_LAUNCH(k_fill32, dim3(gR), dim3(B), 0, s, nch, (int64_t)nrows, 0u);
   CE_LAUNCH(k_fill32, dim3(grid_for(2 * (int64_t)nrows, B)), dim3(B), 0, s, ch, 2 * (int64_t)nrows, 0u);
-  CE_LAUNCH(k_cd_children, dim3(gR), dim3(B), 0, s, cprow, nrows, nch, ch);
+  uint32_t nvirt = 0;
+  if (b.q > 0) {
+    // any number of child clusters: per-parent lists, then chains of virtual sum nodes
+    CE_LAUNCH(k_cd_childcount, dim3(gR), dim3(B), 0, s, cprow, nrows, nch);
+    CE_HIP(hipGetLastError());
+    CE_TRY(scan_exclusive_u32(nch, choff, nrows, ws, s));
+    CE_LAUNCH(k_fill32, dim3(gR), dim3(B), 0, s, cfill, (int64_t)nrows, 0u);
+    CE_LAUNCH(k_cd_childlist, dim3(gR), dim3(B), 0, s, cprow, choff, nrows, cfill, clist);
+    CE_LAUNCH(k_cd_vcount, dim3(gR), dim3(B), 0, s, nch, nrows, vbase);
+    CE_HIP(hipGetLastError());
+    CE_TRY(scan_exclusive_u32(vbase, vbase, nrows, ws, s));
+    uint32_t *h = (uint32_t *)pinned_scratch();
+    CE_HIP(hipMemcpyAsync(h + 33, vbase + nrows, 4, hipMemcpyDeviceToHost, s));
+    CE_HIP(hipStreamSynchronize(s));
+    nvirt = h[33];
+    if ((int64_t)nrows + nvirt > RE) {
+      set_error("virtual cluster nodes exceed the workspace bound");
+      return CE_EDEVICE;
+    }
+    CE_LAUNCH(k_cd_pairs, dim3(gR), dim3(B), 0, s, nch, choff, clist, vbase, nrows, ch, nch, shi, slo);
+  } else {
+    CE_LAUNCH(k_cd_children, dim3(gR), dim3(B), 0, s, cprow, nrows, nch, ch);
+  }
+  const uint32_t neom = nrows + nvirt;
   CE_LAUNCH(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[8], (uint64_t)0);
-  CE_LAUNCH(k_eom_init, dim3(tiles(nrows)), dim3(B), 0, s, nch, shi, slo, cprow, nrows, e[0], e[1], ract, ctr);
+  CE_LAUNCH(k_eom_init, dim3(tiles(neom)), dim3(B), 0, s, nch, shi, slo, cprow, nrows, neom, e[0], e[1], ract, ctr);
   CE_HIP(hipGetLastError());
   uint64_t nact = 0;
   CE_TRY(read_u64(&b.hdr[8], &nact, 1, s));

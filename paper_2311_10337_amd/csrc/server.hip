@@ -122,6 +122,8 @@ __global__ __launch_bounds__(B) void k_scatter(const ScatterDesc *d, ce_result s
       if (o.sl_right) o.sl_right[i] = s.sl_right[r];
       if (o.sl_w) o.sl_w[i] = s.sl_w[r];
       if (o.sl_size) o.sl_size[i] = s.sl_size[r];
+      if (o.dd_level && s.dd_level) o.dd_level[i] = s.dd_level[r];
+      if (o.dd_top && s.dd_top) o.dd_top[i] = s.dd_top[r];
     }
     if (i < q.n) {
       const int64_t p = q.p0 + i;
@@ -147,6 +149,7 @@ struct Request {
   int64_t n = 0, V = 0, M = 0;
   uint32_t mode = CE_MODE_UNDIRECTED;
   int64_t max_dt = -1;
+  std::vector<int64_t> thr;  // discrete dendrogram thresholds (copied at submit)
   size_t in_off = 0, in_bytes = 0;
   ce_result out{};
   ce_counts counts{0, 1, 0};
@@ -158,19 +161,20 @@ struct Request {
 
 // output arrays of a batch of total n records and c cluster rows, laid out in one block
 struct OutLayout {
-  size_t off[17];
+  size_t off[19];
   size_t bytes;
 };
 
 OutLayout out_layout(int64_t n, int64_t c) {
   const size_t R = n > 1 ? (size_t)n : 1, P = n > 0 ? (size_t)n : 1, C = c > 0 ? (size_t)c : 1;
-  const size_t sz[17] = {4u * R, 4u * R, 8u * R, 4u * R, 4u * R, 8u * R, 4u * R,   // msf_*, sl_*
+  const size_t sz[19] = {4u * R, 4u * R, 8u * R, 4u * R, 4u * R, 8u * R, 4u * R,   // msf_*, sl_*
                          4u * P, 8u * P,                                           // pt_*
                          4u * C, 4u * C, 4u * C, 8u * C, 8u * C, 8u * C, 1u * C,   // cl_*
-                         4u * P};                                                  // labels
+                         4u * P,                                                   // labels
+                         4u * R, 4u * R};                                          // dd_level, dd_top
   OutLayout L;
   size_t at = 0;
-  for (int k = 0; k < 17; k++) {
+  for (int k = 0; k < 19; k++) {
     L.off[k] = at;
     at += align_up(sz[k]);
   }
@@ -197,6 +201,8 @@ ce_result out_pointers(char *base, const OutLayout &L) {
   r.cl_stab_lo = (uint64_t *)(base + L.off[14]);
   r.cl_selected = (uint8_t *)(base + L.off[15]);
   r.labels = (int32_t *)(base + L.off[16]);
+  r.dd_level = (uint32_t *)(base + L.off[17]);
+  r.dd_top = (uint32_t *)(base + L.off[18]);
   return r;
 }
 
@@ -218,6 +224,8 @@ size_t batch_bytes(const std::vector<Request *> &rs, int64_t M) {
   p.struct_size = sizeof p;
   p.min_cluster_size = M;
   p.num_vertices = voff[G];
+  p.num_thresholds = (int64_t)rs[0]->thr.size();  // sizing only looks at whether there are any
+  p.thresholds = rs[0]->thr.data();
   size_t ws = ce_batch_workspace_bytes(eoff.data(), voff.data(), G, &p);
   if (G == 1) {
     const size_t w1 = ce_workspace_bytes(rs[0]->n, rs[0]->V, &p);
@@ -265,6 +273,8 @@ void ce_server::run_batch(std::vector<Request *> &rs, size_t work_off, hipStream
   p.min_cluster_size = M;
   p.mode = rs[0]->mode;
   p.max_dt = rs[0]->max_dt;
+  p.thresholds = rs[0]->thr.empty() ? nullptr : rs[0]->thr.data();
+  p.num_thresholds = (int64_t)rs[0]->thr.size();
   auto input = [&](Request *r, int k) -> char * {
     const size_t n = (size_t)r->n;
     const size_t offs[3] = {0, align_up(4 * n), 2 * align_up(4 * n)};
@@ -374,7 +384,7 @@ void ce_server::worker(int k) {
     std::vector<Request *> pick;
     int64_t recs = 0;
     for (Request *r : queue) {
-      if (r->M != M || r->mode != head->mode || r->max_dt != head->max_dt) continue;
+      if (r->M != M || r->mode != head->mode || r->max_dt != head->max_dt || r->thr != head->thr) continue;
       if (!pick.empty() && (recs + r->n > max_batch_records || (int64_t)pick.size() >= MAX_BATCH_GRAPHS)) break;
       pick.push_back(r);
       recs += r->n;
@@ -503,6 +513,8 @@ size_t ce_server_request_bytes(int64_t n, const ce_params *params) {
   r.n = n;
   r.V = params->num_vertices;
   r.M = params->min_cluster_size;
+  if (params->struct_size >= sizeof(ce_params) && params->num_thresholds > 0 && params->thresholds)
+    r.thr.assign(params->thresholds, params->thresholds + params->num_thresholds);
   std::vector<Request *> one{&r};
   return batch_bytes(one, r.M) + align_up(4 * (size_t)n) * 2 + align_up(8 * (size_t)n);
 }
@@ -526,7 +538,19 @@ ce_status ce_server_submit(ce_server *srv, const ce_request *req, uint64_t *tick
   r->V = p.num_vertices;
   r->M = p.min_cluster_size;
   r->mode = p.mode;
-  r->max_dt = p.struct_size >= sizeof(ce_params) ? p.max_dt : -1;
+  r->max_dt = p.struct_size >= CE_PARAMS_V2_SIZE ? p.max_dt : -1;
+  if (p.struct_size >= sizeof(ce_params) && p.num_thresholds != 0) {
+    if (p.num_thresholds < 0 || p.num_thresholds > CE_MAX_THRESHOLDS || !p.thresholds) {
+      set_error("num_thresholds must be in [0, 64] with a thresholds array");
+      return CE_EINVAL;
+    }
+    r->thr.assign(p.thresholds, p.thresholds + p.num_thresholds);
+    for (size_t i = 0; i < r->thr.size(); i++)
+      if (r->thr[i] < 0 || (i > 0 && r->thr[i] <= r->thr[i - 1])) {
+        set_error("thresholds must be >= 0 and strictly increasing");
+        return CE_EINVAL;
+      }
+  }
   r->out = req->out;
   r->t_submit = t_submit;
   r->in_bytes = 2 * align_up(4 * (size_t)n) + align_up(8 * (size_t)n);

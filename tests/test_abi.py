@@ -175,7 +175,7 @@ def test_earlier_params_layout_is_accepted():
     lib = ce.load_library()
 
     class ParamsV1(ctypes.Structure):
-        _fields_ = ce.CeParams._fields_[:-1]
+        _fields_ = ce.CeParams._fields_[:6]
 
     assert ctypes.sizeof(ParamsV1) == 32
     v1 = ParamsV1(32, 0, 5, 100, 0, 0)
