@@ -42,17 +42,23 @@ def make_workload(name):
     raise ValueError(name)
 
 
-def cpu_baseline(w, sample, causal=False):
+def cpu_baseline(w, sample, causal=False, thresholds=None):
     """Time the CPU oracle (single-threaded plain C) on the first `sample` records."""
     import oracle
     ns = min(sample, w.n)
     t0 = time.perf_counter()
-    r = oracle.cluster(w.src[:ns], w.dst[:ns], w.t[:ns], w.min_cluster_size, w.num_vertices, tier=1, causal=causal)
+    if thresholds:
+        r = oracle.cluster_discrete(w.src[:ns], w.dst[:ns], w.t[:ns], w.min_cluster_size, thresholds,
+                                    w.num_vertices, tier=1, causal=causal)[0]
+    else:
+        r = oracle.cluster(w.src[:ns], w.dst[:ns], w.t[:ns], w.min_cluster_size, w.num_vertices, tier=1,
+                           causal=causal)
     dt = time.perf_counter() - t0
     assert r.status == 0
     return {"value": ns / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d of %d records of the same workload (%s oracle, one host thread, %.1f s)"
-                      % (ns, w.n, "Alg. 2 window" if causal else "path-skeleton", dt)}
+            "sample": "first %d of %d records of the same workload (%s oracle%s, one host thread, %.1f s)"
+                      % (ns, w.n, "Alg. 2 window" if causal else "path-skeleton",
+                         ", discrete dendrogram with %d thresholds" % len(thresholds) if thresholds else "", dt)}
 
 
 def bench_batched(dev, steps, warmup):
@@ -213,6 +219,8 @@ def main():
     ap.add_argument("--workload", default="mid", choices=["tiny", "mid", "scale"])
     ap.add_argument("--mode", default="undirected", choices=["undirected", "causal"],
                     help="line graph: undirected (shared vertex, |dt|) or causal (tip-to-tail, increment weights)")
+    ap.add_argument("--thresholds", default="none",
+                    help="discrete dendrogram: 'none' (exact dendrogram), 'paper' (2^0 .. 2^28 s) or a comma list")
     ap.add_argument("--cpu-sample", type=int, default=20_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=1000,
@@ -255,16 +263,24 @@ def main():
         torch.cuda.synchronize()
         del a, b
         log("copy calibration: %d bytes copied" % args.copy_calibration)
+    if args.thresholds == "none":
+        thr = None
+    elif args.thresholds == "paper":
+        thr = [1 << k for k in range(29)]
+    else:
+        thr = [int(x) for x in args.thresholds.split(",")]
     outs = ce.Outputs(w.n, M, dev)
-    ws = torch.empty(ce.workspace_bytes(w.n, V, M), dtype=torch.uint8, device=dev)
+    ws = torch.empty(ce.workspace_bytes(w.n, V, M, thresholds=thr), dtype=torch.uint8, device=dev)
     torch.cuda.synchronize()
 
     causal = args.mode == "causal"
     cfg["line_graph"] = args.mode
-    tag = cfg["workload"] + ("_causal" if causal else "")
+    tag = cfg["workload"] + ("_causal" if causal else "") + ("_discrete" if thr else "")
+    if thr:
+        cfg["dendrogram"] = "discrete, %d thresholds %d..%d s" % (len(thr), thr[0], thr[-1])
 
     def step():
-        return ce.cluster_edges(src, dst, tt, M, V, outputs=outs, workspace=ws, causal=causal)
+        return ce.cluster_edges(src, dst, tt, M, V, outputs=outs, workspace=ws, causal=causal, thresholds=thr)
 
     for i in range(args.warmup):
         r = step()
@@ -327,7 +343,7 @@ def main():
         line["serving"] = bench_serving(dev, args.serve_requests)
     if not args.no_cpu_baseline:
         log("cpu baseline on a sample")
-        line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample, causal)
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample, causal, thr)
     line["host"] = {"cpu": platform.processor() or platform.machine(), "nproc": os.cpu_count()}
     print(json.dumps(line), flush=True)
 

@@ -139,8 +139,9 @@ def make_params(min_cluster_size: int, num_vertices: int, causal: bool = False, 
     return p
 
 
-def workspace_bytes(n: int, num_vertices: int, min_cluster_size: int) -> int:
-    p = make_params(min_cluster_size, num_vertices)
+def workspace_bytes(n: int, num_vertices: int, min_cluster_size: int, thresholds=None) -> int:
+    """Workspace for one graph; condensing on the discrete dendrogram (``thresholds``) needs more."""
+    p = make_params(min_cluster_size, num_vertices, thresholds=thresholds)
     return int(load_library().ce_workspace_bytes(int(n), int(num_vertices), ctypes.byref(p)))
 
 
@@ -272,11 +273,11 @@ def _offsets_array(x, name):
     return a
 
 
-def batch_workspace_bytes(edge_offsets, vertex_offsets, min_cluster_size: int) -> int:
+def batch_workspace_bytes(edge_offsets, vertex_offsets, min_cluster_size: int, thresholds=None) -> int:
     eo, vo = _offsets_array(edge_offsets, "edge_offsets"), _offsets_array(vertex_offsets, "vertex_offsets")
     if eo.size != vo.size:
         raise ValueError("edge_offsets and vertex_offsets must have the same length")
-    p = make_params(min_cluster_size, max(int(vo[-1]), 1))
+    p = make_params(min_cluster_size, max(int(vo[-1]), 1), thresholds=thresholds)
     i64p = ctypes.POINTER(ctypes.c_int64)
     return int(load_library().ce_batch_workspace_bytes(eo.ctypes.data_as(i64p), vo.ctypes.data_as(i64p),
                                                        eo.size - 1, ctypes.byref(p)))
