@@ -12,7 +12,9 @@ method's own steps: per-vertex time-sorted incidence lists, then the path
 skeleton (Alg. 3 with the undirected node-local MST of Sec. 5.3) or the
 Alg. 2 windows, then Kruskal.
 Both continue with the union-find dendrogram and the HDBSCAN condensing and
-excess-of-mass extraction of Alg. 1.
+excess-of-mass extraction of Alg. 1. Dynamic hypergraphs (Sec. 5.3) have the
+same two tiers: every pair of hyperedges whose vertex sets meet, or the
+per-vertex time-sorted paths over incident hyperedges.
 """
 from __future__ import annotations
 
@@ -73,6 +75,14 @@ def _load():
         lib.oracle_causal_skeleton.restype = i64
         lib.oracle_cluster.argtypes = [i64, p, p, p, i64, i64, ctypes.c_int, ctypes.c_int, i64] + [p] * 18
         lib.oracle_cluster.restype = ctypes.c_int
+        lib.oracle_hyper_validate.argtypes = [i64, p, p, p, i64]
+        lib.oracle_hyper_validate.restype = ctypes.c_int
+        lib.oracle_hyper_line_graph.argtypes = [i64, p, p, p, i64, p]
+        lib.oracle_hyper_line_graph.restype = i64
+        lib.oracle_hyper_skeleton.argtypes = [i64, p, p, p, i64, p]
+        lib.oracle_hyper_skeleton.restype = i64
+        lib.oracle_cluster_hyper.argtypes = [i64, p, p, p, i64, i64, ctypes.c_int, i64] + [p] * 18
+        lib.oracle_cluster_hyper.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -281,9 +291,12 @@ def cluster_discrete(src, dst, t, min_cluster_size, thresholds, num_vertices=Non
     dd_top); the Result's condensed fields are the discrete ones."""
     thr = np.asarray(thresholds, np.int64)
     r = cluster(src, dst, t, min_cluster_size, num_vertices, tier=tier, causal=causal, max_dt=int(thr[-1]))
+    return _discrete_tail(r, len(src), min_cluster_size, thr)
+
+
+def _discrete_tail(r, n, min_cluster_size, thr):
     if r.status != 0:
         return r, None, None
-    n = len(src)
     d = condense_discrete(n, r.sl_left, r.sl_right, r.sl_w, r.sl_size, min_cluster_size, thr)
     c = d.condensed
     res = r._replace(pt_cluster=c.pt_cluster, pt_lambda=c.pt_lambda, cl_id=c.cl_id, cl_parent=c.cl_parent,
@@ -322,8 +335,72 @@ def cluster(src, dst, t, min_cluster_size, num_vertices=None, tier=1, causal=Fal
     increment-weighted line graph of Def. 1 (tip-to-tail arcs, Alg. 2 windows in tier 1). max_dt >= 0: only
     line-graph edges with w <= max_dt (time-filtered line graph)."""
     src, dst, t = _prep(src, dst, t)
-    n = src.size
     V = _V(src, dst, num_vertices)
+    return _pipeline(lambda M, bufs, hdr: _load().oracle_cluster(
+        src.size, src.ctypes.data, dst.ctypes.data, t.ctypes.data, V, M, int(tier), int(bool(causal)), int(max_dt),
+        *[b.ctypes.data for b in bufs], hdr.ctypes.data), src.size, min_cluster_size)
+
+
+def _hyper_prep(members, offsets, t):
+    members = np.ascontiguousarray(members, dtype=np.int32)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    t = np.ascontiguousarray(t, dtype=np.int64)
+    assert offsets.ndim == 1 and offsets.size == t.size + 1 and members.ndim == 1
+    return members, offsets, t
+
+
+def _hyper_V(members, V):
+    return int(members.max(initial=-1) + 1) if V is None or V == 0 else int(V)
+
+
+def hyper_validate(members, offsets, t, V=None) -> int:
+    members, offsets, t = _hyper_prep(members, offsets, t)
+    return int(_load().oracle_hyper_validate(t.size, offsets.ctypes.data, members.ctypes.data, t.ctypes.data,
+                                             _hyper_V(members, V)))
+
+
+def _hyper_edges(fn, members, offsets, t, V, limit):
+    members, offsets, t = _hyper_prep(members, offsets, t)
+    V = _hyper_V(members, V)
+    args = (t.size, offsets.ctypes.data, members.ctypes.data, t.ctypes.data, V)
+    cnt = int(fn(*args, None))
+    if cnt < 0:
+        raise RuntimeError("oracle edge generator: %d" % cnt)
+    if cnt > limit:
+        raise MemoryError("line graph has %d edges (limit %d)" % (cnt, limit))
+    out = np.empty(max(cnt, 1), dtype=LG_EDGE)
+    fn(*args, out.ctypes.data)
+    return out[:cnt]
+
+
+def hyper_line_graph(members, offsets, t, V=None, limit=200_000_000) -> np.ndarray:
+    """Every line-graph edge of a dynamic hypergraph (hyperedges whose vertex sets meet), each pair once."""
+    return _hyper_edges(_load().oracle_hyper_line_graph, members, offsets, t, V, limit)
+
+
+def hyper_skeleton(members, offsets, t, V=None) -> np.ndarray:
+    """Per-vertex time-sorted paths over incident hyperedges: sum_i (d_i - 1) rows, vertex then list order."""
+    return _hyper_edges(_load().oracle_hyper_skeleton, members, offsets, t, V, 1 << 62)
+
+
+def cluster_hyper(members, offsets, t, min_cluster_size, num_vertices=None, tier=1, max_dt=-1) -> Result:
+    """Whole pipeline on a dynamic hypergraph (hyperedge r = members[offsets[r]:offsets[r+1]] at time t[r]).
+    tier=0: full line graph; tier=1: per-vertex path skeleton. Per-record outputs are per hyperedge."""
+    members, offsets, t = _hyper_prep(members, offsets, t)
+    V = _hyper_V(members, num_vertices)
+    return _pipeline(lambda M, bufs, hdr: _load().oracle_cluster_hyper(
+        t.size, offsets.ctypes.data, members.ctypes.data, t.ctypes.data, V, M, int(tier), int(max_dt),
+        *[b.ctypes.data for b in bufs], hdr.ctypes.data), t.size, min_cluster_size)
+
+
+def cluster_hyper_discrete(members, offsets, t, min_cluster_size, thresholds, num_vertices=None, tier=1):
+    """cluster_hyper with the discrete dendrogram, as cluster_discrete does for graphs."""
+    thr = np.asarray(thresholds, np.int64)
+    r = cluster_hyper(members, offsets, t, min_cluster_size, num_vertices, tier=tier, max_dt=int(thr[-1]))
+    return _discrete_tail(r, t.size if hasattr(t, "size") else len(t), min_cluster_size, thr)
+
+
+def _pipeline(call, n, min_cluster_size) -> Result:
     M = int(min_cluster_size)
     R = max(n - 1, 1)
     C = max_clusters(n, max(M, 2))
@@ -334,8 +411,7 @@ def cluster(src, dst, t, min_cluster_size, num_vertices=None, tier=1, causal=Fal
             np.empty(C, np.uint64), np.empty(C, np.uint64), np.empty(C, np.uint8),
             np.empty(max(n, 1), np.int32)]
     hdr = np.zeros(4, np.int64)
-    _load().oracle_cluster(n, src.ctypes.data, dst.ctypes.data, t.ctypes.data, V, M, int(tier), int(bool(causal)),
-                           int(max_dt), *[b.ctypes.data for b in bufs], hdr.ctypes.data)
+    call(M, bufs, hdr)
     st, m, nc, nl = (int(x) for x in hdr)
     if st != 0:
         e = [np.empty(0, b.dtype) for b in bufs]

@@ -51,6 +51,16 @@
  *   Direction only decides which pairs are arcs; the spanning forest,
  *   dendrogram and condensing treat arcs as undirected edges (Alg. 1).
  *
+ * Readings of dynamic hypergraphs (Sec. 5.3, undirected):
+ *   H1 a hyperedge is a set S_r of vertices with a time t_r, given as a CSR
+ *      (offsets, members); a vertex listed twice in one hyperedge counts once,
+ *      and an empty hyperedge is a line-graph node without neighbours.
+ *   H2 two hyperedges are adjacent when their sets meet; as for graphs
+ *      (R2) a pair is ONE line-graph edge however many vertices it shares,
+ *      with w = |t_r - t_s| and the canonical key of R3.
+ *   H3 the skeleton is, per vertex, the path through its incident
+ *      hyperedges in the record order R1 (the node-local MST for |dt|).
+ *
  * Output conventions (identical to the GPU library's documented ones):
  *   MSF rows (tail, head, w) in ascending K; m = n - (#components).
  *   Dendrogram row k creates node n+k: (left=min child, right=max child, w, size).
@@ -751,6 +761,36 @@ static int condense_impl(int64_t n, int64_t m, const uint32_t *left, const uint3
  * Output arrays are caller-allocated: msf_* and sl_* hold n-1 rows (n >= 1),
  * cl_* hold 2*floor(n/M)+1 rows. hdr = {status, m, n_clusters, n_labels}.
  */
+/* Alg. 1 on the given line-graph edges (freed here): optional time filter,
+ * Kruskal, dendrogram, condensing. */
+static int finish_pipeline(int64_t n, int64_t E, lg_edge *edges, const int64_t *t, int64_t M, int64_t max_dt,
+                           uint32_t *msf_tail, uint32_t *msf_head, int64_t *msf_w, uint32_t *sl_left,
+                           uint32_t *sl_right, int64_t *sl_w, uint32_t *sl_size, uint32_t *pt_cluster,
+                           uint64_t *pt_lambda, uint32_t *cl_id, uint32_t *cl_parent, uint32_t *cl_size,
+                           uint64_t *cl_lambda_birth, uint64_t *cl_stab_hi, uint64_t *cl_stab_lo,
+                           uint8_t *cl_selected, int32_t *labels, int64_t *hdr) {
+  if (max_dt >= 0) { /* time-filtered line graph (Sec. 5.1): keep only w <= max_dt */
+    int64_t k = 0;
+    for (int64_t e = 0; e < E; e++)
+      if (edges[e].w <= max_dt) edges[k++] = edges[e];
+    E = k;
+  }
+  int64_t m = oracle_kruskal(n, E, edges, t, msf_tail, msf_head, msf_w);
+  free(edges);
+  if (m < 0) { hdr[0] = (int)m; return (int)m; }
+  int rc = oracle_dendrogram(n, m, msf_tail, msf_head, msf_w, sl_left, sl_right, sl_w, sl_size);
+  if (rc) { hdr[0] = rc; return rc; }
+  condense_counts cc = {0, 0};
+  rc = oracle_condense(n, m, sl_left, sl_right, sl_w, sl_size, M, pt_cluster, pt_lambda, cl_id,
+                       cl_parent, cl_size, cl_lambda_birth, cl_stab_hi, cl_stab_lo, cl_selected,
+                       labels, &cc);
+  if (rc) { hdr[0] = rc; return rc; }
+  hdr[1] = m;
+  hdr[2] = cc.n_clusters;
+  hdr[3] = cc.n_labels;
+  return OR_OK;
+}
+
 int oracle_cluster(int64_t n, const int32_t *src, const int32_t *dst, const int64_t *t, int64_t V,
                    int64_t M, int tier, int causal, int64_t max_dt, uint32_t *msf_tail, uint32_t *msf_head, int64_t *msf_w,
                    uint32_t *sl_left, uint32_t *sl_right, int64_t *sl_w, uint32_t *sl_size,
@@ -769,24 +809,122 @@ int oracle_cluster(int64_t n, const int32_t *src, const int32_t *dst, const int6
   lg_edge *edges = (lg_edge *)malloc(sizeof(lg_edge) * (size_t)(E ? E : 1));
   if (!edges) { hdr[0] = OR_ENOMEM; return OR_ENOMEM; }
   gen(n, src, dst, t, V, edges);
-  if (max_dt >= 0) { /* time-filtered line graph (Sec. 5.1): keep only w <= max_dt */
-    int64_t k = 0;
-    for (int64_t e = 0; e < E; e++)
-      if (edges[e].w <= max_dt) edges[k++] = edges[e];
-    E = k;
+  return finish_pipeline(n, E, edges, t, M, max_dt, msf_tail, msf_head, msf_w, sl_left, sl_right, sl_w, sl_size,
+                         pt_cluster, pt_lambda, cl_id, cl_parent, cl_size, cl_lambda_birth, cl_stab_hi, cl_stab_lo,
+                         cl_selected, labels, hdr);
+}
+
+/* ------------------------------------------------------------------ */
+/* Dynamic hypergraphs (Sec. 5.3), readings H1-H3                      */
+/* ------------------------------------------------------------------ */
+/* hyperedge r is the set of members[off[r] .. off[r+1]) with time t[r] */
+int oracle_hyper_validate(int64_t n, const int64_t *off, const int32_t *members, const int64_t *t, int64_t V) {
+  if (n < 0 || n > 2147483647LL || V < 0) return OR_EINVAL;
+  if (off[0] != 0) return OR_EINVAL;
+  for (int64_t r = 0; r < n; r++)
+    if (off[r + 1] < off[r]) return OR_EINVAL;
+  if (off[n] > 2147483647LL) return OR_EINVAL;
+  for (int64_t k = 0; k < off[n]; k++)
+    if (members[k] < 0 || (int64_t)members[k] >= V) return OR_ERANGE;
+  if (n == 0) return OR_OK;
+  int64_t tmin = t[0], tmax = t[0];
+  for (int64_t r = 0; r < n; r++) {
+    if (t[r] < tmin) tmin = t[r];
+    if (t[r] > tmax) tmax = t[r];
   }
-  int64_t m = oracle_kruskal(n, E, edges, t, msf_tail, msf_head, msf_w);
-  free(edges);
-  if (m < 0) { hdr[0] = (int)m; return (int)m; }
-  rc = oracle_dendrogram(n, m, msf_tail, msf_head, msf_w, sl_left, sl_right, sl_w, sl_size);
-  if (rc) { hdr[0] = rc; return rc; }
-  condense_counts cc = {0, 0};
-  rc = oracle_condense(n, m, sl_left, sl_right, sl_w, sl_size, M, pt_cluster, pt_lambda, cl_id,
-                       cl_parent, cl_size, cl_lambda_birth, cl_stab_hi, cl_stab_lo, cl_selected,
-                       labels, &cc);
-  if (rc) { hdr[0] = rc; return rc; }
-  hdr[1] = m;
-  hdr[2] = cc.n_clusters;
-  hdr[3] = cc.n_labels;
+  if ((u128)((__int128)tmax - (__int128)tmin) >= ((u128)1 << 62)) return OR_ERANGE;
   return OR_OK;
+}
+
+/*
+ * Tier A, the definition (H2): every unordered pair of distinct hyperedges
+ * whose sets meet is one line-graph edge. For each hyperedge a its vertices
+ * are stamped with a; a later hyperedge b is adjacent when one of its members
+ * carries the stamp. If out == NULL only the count is returned.
+ */
+int64_t oracle_hyper_line_graph(int64_t n, const int64_t *off, const int32_t *members, const int64_t *t, int64_t V,
+                                lg_edge *out) {
+  int64_t *stamp = (int64_t *)malloc(sizeof(int64_t) * (size_t)(V ? V : 1));
+  if (!stamp) return OR_ENOMEM;
+  for (int64_t v = 0; v < V; v++) stamp[v] = -1;
+  g_t = t;
+  int64_t cnt = 0;
+  for (int64_t a = 0; a < n; a++) {
+    for (int64_t k = off[a]; k < off[a + 1]; k++) stamp[members[k]] = a;
+    for (int64_t b = a + 1; b < n; b++) {
+      int meet = 0;
+      for (int64_t k = off[b]; k < off[b + 1] && !meet; k++) meet = stamp[members[k]] == a;
+      if (!meet) continue;
+      if (out) out[cnt] = make_edge((uint32_t)a, (uint32_t)b);
+      cnt++;
+    }
+  }
+  free(stamp);
+  return cnt;
+}
+
+/*
+ * Tier B, the method's steps for hypergraphs (H3, Sec. 5.3): the incident
+ * hyperedges of every vertex (each once, H1) sorted by the record order R1,
+ * then each consecutive pair. Emits sum_i (d_i - 1) rows over vertices with
+ * d_i >= 1; a pair consecutive at several vertices appears once per vertex
+ * (Kruskal keeps one).
+ */
+int64_t oracle_hyper_skeleton(int64_t n, const int64_t *off, const int32_t *members, const int64_t *t, int64_t V,
+                              lg_edge *out) {
+  int64_t nnz = off[n];
+  int64_t *voff = (int64_t *)calloc((size_t)V + 1, sizeof(int64_t));
+  int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)(V + 1));
+  int64_t *last = (int64_t *)malloc(sizeof(int64_t) * (size_t)(V + 1));
+  uint32_t *lst = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(nnz + 1));
+  if (!voff || !fill || !last || !lst) { free(voff); free(fill); free(last); free(lst); return OR_ENOMEM; }
+  /* incidence lists E_i with each hyperedge once per vertex */
+  for (int64_t v = 0; v < V; v++) last[v] = -1;
+  for (int64_t r = 0; r < n; r++)
+    for (int64_t k = off[r]; k < off[r + 1]; k++)
+      if (last[members[k]] != r) { last[members[k]] = r; voff[members[k] + 1]++; }
+  for (int64_t v = 0; v < V; v++) voff[v + 1] += voff[v];
+  memcpy(fill, voff, sizeof(int64_t) * (size_t)V);
+  for (int64_t v = 0; v < V; v++) last[v] = -1;
+  for (int64_t r = 0; r < n; r++)
+    for (int64_t k = off[r]; k < off[r + 1]; k++)
+      if (last[members[k]] != r) { last[members[k]] = r; lst[fill[members[k]]++] = (uint32_t)r; }
+  g_t = t;
+  int64_t cnt = 0;
+  for (int64_t x = 0; x < V; x++) {
+    int64_t d = voff[x + 1] - voff[x];
+    if (d < 2) continue;
+    qsort(lst + voff[x], (size_t)d, sizeof(uint32_t), cmp_rec); /* "sort the incident hyperedges" */
+    for (int64_t k = voff[x] + 1; k < voff[x + 1]; k++) {
+      const uint32_t prev = lst[k - 1], cur = lst[k];
+      if (out) out[cnt] = make_edge(prev, cur);
+      cnt++;
+    }
+  }
+  free(voff); free(fill); free(last); free(lst);
+  return cnt;
+}
+
+/* Whole pipeline on a dynamic hypergraph; tier 0 = definition, 1 = skeleton;
+ * outputs and hdr as in oracle_cluster, per hyperedge. */
+int oracle_cluster_hyper(int64_t n, const int64_t *off, const int32_t *members, const int64_t *t, int64_t V,
+                         int64_t M, int tier, int64_t max_dt, uint32_t *msf_tail, uint32_t *msf_head,
+                         int64_t *msf_w, uint32_t *sl_left, uint32_t *sl_right, int64_t *sl_w, uint32_t *sl_size,
+                         uint32_t *pt_cluster, uint64_t *pt_lambda, uint32_t *cl_id, uint32_t *cl_parent,
+                         uint32_t *cl_size, uint64_t *cl_lambda_birth, uint64_t *cl_stab_hi,
+                         uint64_t *cl_stab_lo, uint8_t *cl_selected, int32_t *labels, int64_t *hdr) {
+  hdr[0] = hdr[1] = hdr[2] = hdr[3] = 0;
+  if (M < 2) { hdr[0] = OR_EINVAL; return OR_EINVAL; }
+  int rc = oracle_hyper_validate(n, off, members, t, V);
+  if (rc) { hdr[0] = rc; return rc; }
+  int64_t (*gen)(int64_t, const int64_t *, const int32_t *, const int64_t *, int64_t, lg_edge *) =
+      tier == 0 ? oracle_hyper_line_graph : oracle_hyper_skeleton;
+  int64_t E = gen(n, off, members, t, V, NULL);
+  if (E < 0) { hdr[0] = (int)E; return (int)E; }
+  lg_edge *edges = (lg_edge *)malloc(sizeof(lg_edge) * (size_t)(E ? E : 1));
+  if (!edges) { hdr[0] = OR_ENOMEM; return OR_ENOMEM; }
+  gen(n, off, members, t, V, edges);
+  return finish_pipeline(n, E, edges, t, M, max_dt, msf_tail, msf_head, msf_w, sl_left, sl_right, sl_w, sl_size,
+                         pt_cluster, pt_lambda, cl_id, cl_parent, cl_size, cl_lambda_birth, cl_stab_hi, cl_stab_lo,
+                         cl_selected, labels, hdr);
 }

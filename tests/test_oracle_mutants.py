@@ -42,6 +42,12 @@ MUTANTS = [
     ("discrete birth with one big child", "if (nb >= 2) { is_cluster[c] = 1;", "if (nb >= 1) { is_cluster[c] = 1;"),
     ("discrete blocks ignore levels", "dd_top[k] = (p != NONE32 && dd_level[p] == dd_level[k]) ? dd_top[p]",
      "dd_top[k] = (p != NONE32) ? dd_top[p]"),
+    ("hyper: meeting tested on the first member only", "for (int64_t k = off[b]; k < off[b + 1] && !meet; k++)",
+     "for (int64_t k = off[b]; k < off[b] + 1 && k < off[b + 1] && !meet; k++)"),
+    ("hyper: incident lists left unsorted",
+     'qsort(lst + voff[x], (size_t)d, sizeof(uint32_t), cmp_rec); /* "sort the incident hyperedges" */',
+     "/* unsorted */"),
+    ("hyper: star instead of path", "out[cnt] = make_edge(prev, cur);", "out[cnt] = make_edge(lst[voff[x]], cur);"),
 ]
 
 
@@ -58,6 +64,7 @@ def test_pins_catch_planted_mistake(name, old, new, tmp_path):
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py"),
                         os.path.join(ROOT, "tests", "test_oracle_causal.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_discrete.py"), "-k", "not four_records"],
+                        os.path.join(ROOT, "tests", "test_oracle_discrete.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_hyper.py"), "-k", "not four_records"],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, "planted mistake '%s' passed every pin:\n%s" % (name, r.stdout[-2000:])
