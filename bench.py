@@ -61,6 +61,46 @@ def cpu_baseline(w, sample, causal=False, thresholds=None):
                          ", discrete dendrogram with %d thresholds" % len(thresholds) if thresholds else "", dt)}
 
 
+def bench_hyper(dev, steps, warmup):
+    """Dynamic hypergraph (Sec. 5.3): the 2e7-hyperedge multi-recipient workload through
+    ce_cluster_hyperedges, inputs resident in HBM, workspace and outputs preallocated."""
+    import torch
+    import synth
+    import paper_2311_10337_amd as ce
+    t0 = time.perf_counter()
+    w = synth.hyper_mid()
+    log("hypergraph workload: %d hyperedges, %d memberships (%.1f s)" % (w.n, w.nnz, time.perf_counter() - t0))
+    mem = torch.from_numpy(w.members).to(dev)
+    off = torch.from_numpy(w.offsets).to(dev)
+    tt = torch.from_numpy(w.t).to(dev)
+    M, V = w.min_cluster_size, w.num_vertices
+    outs = ce.Outputs(w.n, M, dev)
+    ws = torch.empty(ce.hyper_workspace_bytes(w.n, w.nnz, V, M), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+
+    def step():
+        return ce.cluster_hyperedges(mem, off, tt, M, V, outputs=outs, workspace=ws)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = step()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    log("hypergraph: %.1f ms per step" % (1e3 * el))
+    out = {"workload": "hyper-bursts-mid", "n_hyperedges": w.n, "memberships": w.nnz, "n_vertices": V,
+           "min_cluster_size": M, "seed": 6,
+           "recipe": "Chung-Lu 2.1 sender + recipients, recipients per message lognormal median 2 sigma 1 "
+                     "clipped [1, 64], Poisson bursts over 90 days",
+           "hyperedges_per_s": w.n / el, "memberships_per_s": w.nnz / el, "ms_per_step": 1e3 * el, "steps": steps,
+           "m_msf": r.m, "n_clusters": r.n_clusters, "n_labels": r.n_labels}
+    del mem, off, tt, outs, ws
+    torch.cuda.empty_cache()
+    return out
+
+
 def bench_batched(dev, steps, warmup):
     """The 4096-graph batch in one call vs one call per graph, same GPU and inputs."""
     import numpy as np
@@ -225,6 +265,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=1000,
                     help="requests of the serving stream to replay (0 skips the serving measurement)")
+    ap.add_argument("--no-hyper", action="store_true",
+                    help="skip the dynamic-hypergraph measurement (2e7 multi-recipient messages)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-vs-one-graph-per-call measurement on the 4096-graph batch")
     ap.add_argument("--roofline-kernel", default="k_krt_accum",
@@ -332,15 +374,14 @@ def main():
     if roof is not None:
         line["roofline"] = roof
     line["hbm_pipeline"] = hbm
+    del src, dst, tt, outs, ws
+    torch.cuda.empty_cache()
     if not args.no_batch:
-        del src, dst, tt, outs, ws
-        torch.cuda.empty_cache()
         line["batched"] = bench_batched(dev, max(1, min(args.steps, 3)), 1)
     if args.serve_requests > 0:
-        if args.no_batch:
-            del src, dst, tt, outs, ws
-            torch.cuda.empty_cache()
         line["serving"] = bench_serving(dev, args.serve_requests)
+    if not args.no_hyper:
+        line["hypergraph"] = bench_hyper(dev, max(1, min(args.steps, 3)), 1)
     if not args.no_cpu_baseline:
         log("cpu baseline on a sample")
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample, causal, thr)

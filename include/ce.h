@@ -147,6 +147,34 @@ ce_status ce_cluster_edges(const int32_t *src, const int32_t *dst, const int64_t
                            void *workspace, size_t workspace_bytes, void *stream);
 
 /*
+ * Dynamic hypergraphs (Sec. 5.3, undirected). Record r is a hyperedge: the
+ * vertex set members[offsets[r] .. offsets[r+1]) observed at time t[r]. Two
+ * hyperedges are adjacent in the line graph when their sets meet, with weight
+ * |t_r - t_s| (one line-graph edge per pair, however many vertices it
+ * shares). The skeleton is, per vertex, the path through its incident
+ * hyperedges in (t, id) order: sum_i (d_i - 1) <= nnz edges, the input size.
+ * Everything after the skeleton is the graph pipeline, so the outputs have the
+ * layout and conventions of ce_cluster_edges with hyperedges as records
+ * (msf_tail/msf_head and point outputs are hyperedge ids).
+ *   members  : int32[nnz] DEVICE, vertex ids in [0, params.num_vertices); a
+ *              vertex listed twice in one hyperedge counts once
+ *   offsets  : int64[n+1] DEVICE, offsets[0] = 0, non-decreasing,
+ *              offsets[n] = nnz; an empty hyperedge is an isolated record
+ *   t        : int64[n] DEVICE, seconds
+ *   params   : mode must be CE_MODE_UNDIRECTED (directed hypergraphs are not
+ *              supported: CE_EINVAL); max_dt and thresholds as for graphs
+ * Limits: n <= 2^31-1, nnz <= 2^31-1. The packed key needs
+ *   bits(max t - min t) + bits(n-1) + bits(longest run of equal times - 1)
+ *   <= 64, else CE_ERANGE. Errors: CE_EINVAL for bad offsets, CE_ERANGE for a
+ * member outside [0, V); no output is written on an error.
+ */
+size_t ce_hyper_workspace_bytes(int64_t n, int64_t nnz, const ce_params *params);
+
+ce_status ce_cluster_hyperedges(const int32_t *members, const int64_t *offsets, const int64_t *t, int64_t n,
+                                int64_t nnz, const ce_params *params, const ce_result *out, ce_counts *counts,
+                                void *workspace, size_t workspace_bytes, void *stream);
+
+/*
  * Batches. Many independent graphs can be clustered in one call: graph g owns
  * the records [edge_offsets[g], edge_offsets[g+1]) of src/dst/t and the
  * vertex ids [0, vertex_offsets[g+1] - vertex_offsets[g]) (ids are local to

@@ -84,6 +84,13 @@ def load_library(path: str = LIB_PATH):
                                                                  ctypes.POINTER(CeResult), ctypes.POINTER(CeCounts),
                                                                  ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
         lib.ce_cluster_edges.restype = ctypes.c_int
+        lib.ce_cluster_hyperedges.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int64, ctypes.c_int64,
+                                                                      ctypes.POINTER(CeParams), ctypes.POINTER(CeResult),
+                                                                      ctypes.POINTER(CeCounts), ctypes.c_void_p,
+                                                                      ctypes.c_size_t, ctypes.c_void_p]
+        lib.ce_cluster_hyperedges.restype = ctypes.c_int
+        lib.ce_hyper_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(CeParams)]
+        lib.ce_hyper_workspace_bytes.restype = ctypes.c_size_t
         i64p = ctypes.POINTER(ctypes.c_int64)
         lib.ce_cluster_batch.argtypes = [ctypes.c_void_p] * 3 + [i64p, i64p, ctypes.c_int64, ctypes.POINTER(CeParams),
                                                                  ctypes.POINTER(CeResult), ctypes.POINTER(CeCounts),
@@ -255,6 +262,48 @@ def cluster_edges(src, dst, t, min_cluster_size: int, num_vertices: int, outputs
                               ctypes.byref(counts), ctypes.c_void_p(ws_ptr), ws_len, ctypes.c_void_p(s.cuda_stream))
     if st != CE_OK:
         raise ClusterError(st, last_error())
+    return _result(outputs, n, counts, params)
+
+
+def hyper_workspace_bytes(n: int, nnz: int, num_vertices: int, min_cluster_size: int, thresholds=None) -> int:
+    """Workspace for a dynamic hypergraph of n hyperedges with nnz memberships."""
+    p = make_params(min_cluster_size, num_vertices, thresholds=thresholds)
+    return int(load_library().ce_hyper_workspace_bytes(int(n), int(nnz), ctypes.byref(p)))
+
+
+def cluster_hyperedges(members, offsets, t, min_cluster_size: int, num_vertices: int,
+                       outputs: Optional[Outputs] = None, workspace=None, stream=None, max_dt: int = -1,
+                       thresholds=None) -> Result:
+    """Cluster the hyperedges of a dynamic hypergraph (Sec. 5.3): hyperedge r is the vertex set
+    members[offsets[r]:offsets[r+1]] at time t[r]; all three are contiguous GPU tensors (int32, int64,
+    int64). Outputs are per hyperedge, in the layout of ``cluster_edges``."""
+    import torch
+    lib = load_library()
+    for name, x, dt in (("members", members, torch.int32), ("offsets", offsets, torch.int64),
+                        ("t", t, torch.int64)):
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == dt and x.is_contiguous() and x.dim() == 1):
+            raise TypeError("%s must be a contiguous 1-D %s GPU tensor" % (name, dt))
+    n, nnz = int(t.numel()), int(members.numel())
+    if offsets.numel() != n + 1:
+        raise ValueError("offsets must have n + 1 entries")
+    if outputs is None or outputs.n < n or outputs.C < max_clusters(n, min_cluster_size):
+        outputs = Outputs(n, min_cluster_size, t.device)
+    params = make_params(min_cluster_size, num_vertices, False, max_dt, thresholds)
+    counts = CeCounts()
+    s = stream if stream is not None else torch.cuda.current_stream(t.device)
+    ws_ptr, ws_len = None, 0
+    if workspace is not None:
+        ws_ptr, ws_len = workspace.data_ptr(), workspace.numel() * workspace.element_size()
+    st = lib.ce_cluster_hyperedges(ctypes.c_void_p(members.data_ptr()), ctypes.c_void_p(offsets.data_ptr()),
+                                   ctypes.c_void_p(t.data_ptr()), n, nnz, ctypes.byref(params),
+                                   ctypes.byref(outputs.struct), ctypes.byref(counts), ctypes.c_void_p(ws_ptr),
+                                   ws_len, ctypes.c_void_p(s.cuda_stream))
+    if st != CE_OK:
+        raise ClusterError(st, last_error())
+    return _result(outputs, n, counts, params)
+
+
+def _result(outputs, n, counts, params) -> Result:
     m, nc, nl = int(counts.m), int(counts.n_clusters), int(counts.n_labels)
     o = outputs.t
     rows = {f: o[f][:m] for f in ("msf_tail", "msf_head", "msf_w", "sl_left", "sl_right", "sl_w", "sl_size")}

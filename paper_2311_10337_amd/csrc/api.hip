@@ -190,7 +190,10 @@ ce_status stage_write_rows(Bufs &b, int64_t m, const ce_result *out, hipStream_t
 // Scratch A (grouping, skeleton, Boruvka) follows X and may overlap Y; scratch
 // M (MSF sort) lies between X and Y; scratch B (dendrogram, condensing) starts
 // at the phase area and overlaps X.
-static void layout(Bufs &b, Ws &ws, int64_t n, int64_t M, int64_t G, bool discrete) {
+// nnz >= 0: a hypergraph with nnz memberships (its skeleton has at most nnz rows)
+static void layout(Bufs &b, Ws &ws, int64_t n, int64_t M, int64_t G, bool discrete, int64_t nnz) {
+  const int64_t slots = nnz >= 0 ? (nnz > 0 ? nnz : 1) : 2 * n;
+  b.slots = slots;
   b.hdr = ws.alloc<uint64_t>(16);
   b.thr = ws.alloc<int64_t>(CE_MAX_THRESHOLDS);
   b.eoff = ws.alloc<int64_t>(G + 1);
@@ -199,11 +202,11 @@ static void layout(Bufs &b, Ws &ws, int64_t n, int64_t M, int64_t G, bool discre
   b.grank = ws.alloc<uint32_t>(n);
   const size_t base = ws.off;
   b.ts = ws.alloc<uint64_t>(n);
-  b.skel_key = ws.alloc<uint64_t>(2 * n);
-  b.skel_tail = ws.alloc<uint32_t>(2 * n);
-  b.skel_tid = ws.alloc<uint32_t>(2 * n);
+  b.skel_key = ws.alloc<uint64_t>(slots);
+  b.skel_tail = ws.alloc<uint32_t>(slots);
+  b.skel_tid = ws.alloc<uint32_t>(slots);
   b.best = ws.alloc<uint64_t>(n);
-  b.msf_flag = ws.alloc<uint8_t>(2 * n);
+  b.msf_flag = ws.alloc<uint8_t>(slots);
   const size_t xbytes = ws.off - base;
   Ws y;
   y.alloc<uint64_t>(n);
@@ -211,10 +214,10 @@ static void layout(Bufs &b, Ws &ws, int64_t n, int64_t M, int64_t G, bool discre
   for (int k = 0; k < 5; k++) y.alloc<uint32_t>(n);
   y.alloc<uint32_t>(G + 1);
   const size_t ybytes = y.off;
-  size_t scr_a = stage_sort_skeleton_scratch(n);
-  size_t x = stage_boruvka_scratch(n);
+  size_t scr_a = stage_boruvka_scratch(n, slots);
+  size_t x = nnz >= 0 ? stage_hyper_skeleton_scratch(n, nnz) : stage_sort_skeleton_scratch(n);
   if (x > scr_a) scr_a = x;
-  x = stage_causal_skeleton_scratch(n);
+  x = nnz >= 0 ? 0 : stage_causal_skeleton_scratch(n);
   if (x > scr_a) scr_a = x;
   const size_t scr_m = stage_msf_sort_scratch(n);
   size_t scr_b = stage_dendrogram_scratch(n);
@@ -274,10 +277,10 @@ static ce_status thresholds_of(const ce_params *p, Thresholds *th) {
 // condensing on the discrete dendrogram needs room for nodes with many children
 static bool discrete_of(const ce_params *p) { return p->struct_size >= sizeof(ce_params) && p->num_thresholds > 0; }
 
-static size_t workspace_for(int64_t n, int64_t M, int64_t G, bool discrete) {
+static size_t workspace_for(int64_t n, int64_t M, int64_t G, bool discrete, int64_t nnz = -1) {
   Bufs b;
   Ws ws;
-  layout(b, ws, n, M, G, discrete);
+  layout(b, ws, n, M, G, discrete, nnz);
   return ws.peak;
 }
 
@@ -305,16 +308,34 @@ static ce_status check_offsets(const int64_t *eoff, const int64_t *voff, int64_t
   return CE_OK;
 }
 
-// Runs a checked batch; eoff/voff are host arrays of G+1 offsets.
+// A dynamic hypergraph's memberships (device CSR), for run_batch.
+struct HyperIn {
+  const int32_t *members;
+  const int64_t *offsets;
+  int64_t nnz;
+};
+
+// Runs a checked batch; eoff/voff are host arrays of G+1 offsets. With hy,
+// the records are the hyperedges of one hypergraph (G = 1) and src/dst are
+// not used.
 static ce_status run_batch(const int32_t *src, const int32_t *dst, const int64_t *t, const int64_t *eoff,
                            const int64_t *voff, int64_t G, int64_t M, bool causal, int64_t max_dt,
                            Thresholds th, const ce_result *out, ce_counts *counts,
                            int64_t *row_offsets, int64_t *cluster_offsets, void *workspace, size_t workspace_bytes,
-                           hipStream_t s) {
+                           hipStream_t s, const HyperIn *hy = nullptr) {
   const int64_t n = eoff[G], V = voff[G];
   for (int64_t g = 0; g < G; g++) counts[g] = ce_counts{0, 1, 0};
-  if (n > 0 && (!src || !dst || !t)) { set_error("input pointer is NULL"); return CE_EINVAL; }
-  const size_t need = workspace_for(n, M, G, th.q > 0);
+  if (hy) {
+    if (!hy->offsets || (n > 0 && !t) || (hy->nnz > 0 && !hy->members)) {
+      set_error("input pointer is NULL");
+      return CE_EINVAL;
+    }
+  } else if (n > 0 && (!src || !dst || !t)) {
+    set_error("input pointer is NULL");
+    return CE_EINVAL;
+  }
+  const int64_t nnz = hy ? hy->nnz : -1;
+  const size_t need = workspace_for(n, M, G, th.q > 0, nnz);
   void *base = workspace;
   bool own = false, async_alloc = true;
   if (!base) {
@@ -342,7 +363,7 @@ static ce_status run_batch(const int32_t *src, const int32_t *dst, const int64_t
   ws.base = (char *)base;
   ws.cap = need;
   Bufs b;
-  layout(b, ws, n, M, G, th.q > 0);
+  layout(b, ws, n, M, G, th.q > 0, nnz);
   CE_WS_CHECK(ws);
   b.n = n;
   b.V = V;
@@ -358,7 +379,14 @@ static ce_status run_batch(const int32_t *src, const int32_t *dst, const int64_t
   CE_HIP(hipMemcpyAsync((void *)b.voff, voff, sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, s));
   uint64_t flags = 0;
   int64_t tmin = 0, tmax = 0;
-  if (n > 0) {
+  if (hy) {
+    CE_TRY(stage_hyper_validate(hy->members, hy->offsets, t, nnz, b, s, &flags, &tmin, &tmax));
+    if (flags & 4) {
+      set_error("offsets must start at 0, be non-decreasing and end at nnz");
+      return CE_EINVAL;
+    }
+    if (flags & 2) { set_error("member outside [0, num_vertices)"); return CE_ERANGE; }
+  } else if (n > 0) {
     CE_TRY(stage_validate(src, dst, t, b, s, &flags, &tmin, &tmax));
     if (flags & 1) { set_error("self loop in input (src == dst)"); return CE_ESELFLOOP; }
     if (flags & 2) { set_error("vertex id outside [0, num_vertices) of its graph"); return CE_ERANGE; }
@@ -378,11 +406,11 @@ static ce_status run_batch(const int32_t *src, const int32_t *dst, const int64_t
   b.tbits = bits_for(span);
   b.idbits = bits_for((uint64_t)(n - 1));
   b.vbits = bits_for((uint64_t)(V - 1));
-  b.causal = causal;
-  b.hshift = 1;  // causal mode sets its own shifts once the tie indices are known
+  b.flat = causal || hy;
+  b.hshift = 1;  // causal and hypergraph modes set their own shifts once the tie terms are known
   b.wshift = b.idbits + 1;
   b.keybits = b.tbits + b.wshift;
-  if (!causal && b.keybits > 64) {
+  if (!b.flat && b.keybits > 64) {
     set_error("time span too wide: bits(span) + bits(n-1) + 1 > 64");
     return CE_ERANGE;
   }
@@ -395,7 +423,8 @@ static ce_status run_batch(const int32_t *src, const int32_t *dst, const int64_t
   wb.cap = b.scratch_b_bytes;
   int64_t m = 0;
   std::vector<int64_t> roff(G + 1);
-  if (causal) CE_TRY(stage_causal_skeleton(src, dst, t, b, wa, s));
+  if (hy) CE_TRY(stage_hyper_skeleton(hy->members, hy->offsets, t, nnz, b, wa, s));
+  else if (causal) CE_TRY(stage_causal_skeleton(src, dst, t, b, wa, s));
   else CE_TRY(stage_sort_skeleton(src, dst, t, b, wa, s));
   CE_TRY(stage_boruvka(b, wa, s));
   CE_TRY(stage_msf_sort(b, wm, s, &m));
@@ -476,6 +505,36 @@ ce_status ce_cluster_edges(const int32_t *src, const int32_t *dst, const int64_t
   return run_batch(src, dst, t, eoff, voff, 1, params->min_cluster_size, params->mode == CE_MODE_CAUSAL,
                    max_dt_of(params), th, out, counts, nullptr, nullptr, workspace, workspace_bytes,
                    (hipStream_t)stream);
+}
+
+size_t ce_hyper_workspace_bytes(int64_t n, int64_t nnz, const ce_params *params) {
+  if (check_params(params) != CE_OK || params->mode != CE_MODE_UNDIRECTED) return 0;
+  if (n < 0 || n > 0x7fffffffLL || nnz < 0 || nnz > 0x7fffffffLL) return 0;
+  if (params->num_vertices < 1 || params->num_vertices > 0x80000000LL) return 0;
+  return workspace_for(n, params->min_cluster_size, 1, discrete_of(params), nnz);
+}
+
+ce_status ce_cluster_hyperedges(const int32_t *members, const int64_t *offsets, const int64_t *t, int64_t n,
+                                int64_t nnz, const ce_params *params, const ce_result *out, ce_counts *counts,
+                                void *workspace, size_t workspace_bytes, void *stream) {
+  CE_TRY(check_params(params));
+  if (params->mode != CE_MODE_UNDIRECTED) {
+    set_error("hypergraphs are undirected: mode must be CE_MODE_UNDIRECTED");
+    return CE_EINVAL;
+  }
+  if (!out || !counts) { set_error("out/counts is NULL"); return CE_EINVAL; }
+  if (params->num_vertices < 1 || params->num_vertices > 0x80000000LL) {
+    set_error("num_vertices must be in [1, 2^31]");
+    return CE_EINVAL;
+  }
+  if (n < 0 || n > 0x7fffffffLL) { set_error("n must be in [0, 2^31-1]"); return CE_EINVAL; }
+  if (nnz < 0 || nnz > 0x7fffffffLL) { set_error("nnz must be in [0, 2^31-1]"); return CE_EINVAL; }
+  const int64_t eoff[2] = {0, n}, voff[2] = {0, params->num_vertices};
+  Thresholds th;
+  CE_TRY(thresholds_of(params, &th));
+  const HyperIn hy{members, offsets, nnz};
+  return run_batch(nullptr, nullptr, t, eoff, voff, 1, params->min_cluster_size, false, max_dt_of(params), th, out,
+                   counts, nullptr, nullptr, workspace, workspace_bytes, (hipStream_t)stream, &hy);
 }
 
 ce_status ce_cluster_batch(const int32_t *src, const int32_t *dst, const int64_t *t, const int64_t *edge_offsets,

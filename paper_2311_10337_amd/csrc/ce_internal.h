@@ -281,8 +281,11 @@ struct Bufs {
   // packed key = w << wshift | head id << hshift | low bits (undirected: one
   // bit ordering the two edges of a head; causal: the tail's tie index)
   int wshift = 0, hshift = 0, jbits = 0;
-  bool causal = false;
-  int64_t S = 0;  // causal skeleton rows (slots 0..S-1)
+  // flat skeleton (causal and hypergraph modes): rows in slots 0..S-1, each
+  // with its head rank in skel_tid; otherwise slot 2h+side belongs to head h
+  bool flat = false;
+  int64_t S = 0;
+  int64_t slots = 0;  // capacity of the skeleton arrays: 2n, or nnz for hypergraphs
   // discrete dendrogram (Alg. 5): q thresholds on the device, 0 = exact
   const int64_t *thr = nullptr;
   int q = 0;
@@ -291,11 +294,11 @@ struct Bufs {
   uint64_t *hdr = nullptr;      // [16] device header / counters
   uint64_t *ts = nullptr;       // [n] t - tmin by rank
   uint32_t *perm = nullptr;     // [n] rank -> input id
-  uint64_t *skel_key = nullptr; // [2n] slot 2h+s: key of the skeleton edge whose head is rank h
-  uint32_t *skel_tail = nullptr;// [2n] tail rank of that edge or NONE
-  uint32_t *skel_tid = nullptr; // [2n] input id of that tail
+  uint64_t *skel_key = nullptr; // [slots] slot 2h+s: key of the skeleton edge whose head is rank h
+  uint32_t *skel_tail = nullptr;// [slots] tail rank of that edge or NONE
+  uint32_t *skel_tid = nullptr; // [slots] input id of that tail (flat: the head rank)
   uint64_t *best = nullptr;     // [n] Boruvka: minimum key leaving each component
-  uint8_t *msf_flag = nullptr;  // [2n]
+  uint8_t *msf_flag = nullptr;  // [slots]
   uint64_t *msf_key = nullptr;  // [n] sorted MSF keys
   uint4 *msf_val = nullptr;     // [n] (tail rank, head rank, tail input id, 0); the head's id is in the key
   uint32_t *kc_u = nullptr, *kc_v = nullptr, *ksize = nullptr; // [n] dendrogram children (internal labels) and size
@@ -330,7 +333,13 @@ ce_status stage_causal_skeleton(const int32_t *src, const int32_t *dst, const in
                                 hipStream_t s);
 size_t stage_causal_skeleton_scratch(int64_t n);
 ce_status stage_time_filter(Bufs &b, int64_t max_dt, hipStream_t s, int64_t *m);
-size_t stage_boruvka_scratch(int64_t n);
+size_t stage_boruvka_scratch(int64_t n, int64_t slots);
+// dynamic hypergraphs (Sec. 5.3): members/offsets CSR per hyperedge
+ce_status stage_hyper_validate(const int32_t *members, const int64_t *offsets, const int64_t *t, int64_t nnz,
+                               Bufs &b, hipStream_t s, uint64_t *flags, int64_t *tmin, int64_t *tmax);
+ce_status stage_hyper_skeleton(const int32_t *members, const int64_t *offsets, const int64_t *t, int64_t nnz,
+                               Bufs &b, Ws &ws, hipStream_t s);
+size_t stage_hyper_skeleton_scratch(int64_t n, int64_t nnz);
 size_t stage_msf_sort_scratch(int64_t n);
 size_t stage_dendrogram_scratch(int64_t n);
 size_t stage_condense_scratch(int64_t n, int64_t M, int64_t G, bool discrete);

@@ -403,7 +403,7 @@ __global__ __launch_bounds__(B) void k_msf_list(const uint8_t *flag, int64_t n2,
   tile_append(keep, vals, out, cnt);
 }
 
-// causal skeleton rows (key, tail rank, head rank) as live edge records
+// flat skeleton rows (key, tail rank, head rank) as live edge records
 __global__ __launch_bounds__(B) void k_edges_from_skeleton(int64_t S, const uint64_t *skel_key,
                                                            const uint32_t *skel_tail, const uint32_t *skel_head,
                                                            uint64_t *key, uint32_t *eu, uint32_t *ev, uint32_t *es) {
@@ -415,7 +415,7 @@ __global__ __launch_bounds__(B) void k_edges_from_skeleton(int64_t S, const uint
   }
 }
 
-// causal rows keep the head rank in skel_tid; the tail id comes from perm
+// flat rows keep the head rank in skel_tid; the tail id comes from perm
 __global__ __launch_bounds__(B) void k_msf_gather_causal(const uint32_t *list, int64_t m, const uint64_t *skel_key,
                                                          const uint32_t *skel_tail, const uint32_t *skel_head,
                                                          const uint32_t *perm, uint64_t *okey, uint4 *oval) {
@@ -549,7 +549,7 @@ ce_status stage_sort_skeleton(const int32_t *src, const int32_t *dst, const int6
   return CE_OK;
 }
 
-size_t stage_boruvka_scratch(int64_t n) {
+size_t stage_boruvka_scratch(int64_t n, int64_t slots) {
   Ws w;
   w.alloc<uint32_t>(n);      // rankof
   w.alloc<uint32_t>(n);      // hook
@@ -559,10 +559,10 @@ size_t stage_boruvka_scratch(int64_t n) {
   w.alloc<uint32_t>(n);      // active
   w.alloc<uint32_t>(n);      // active alt
   for (int k = 0; k < 2; k++) {  // edge lists (key, u, v, slot), ping-pong
-    w.alloc<uint64_t>(2 * n);
-    w.alloc<uint32_t>(2 * n);
-    w.alloc<uint32_t>(2 * n);
-    w.alloc<uint32_t>(2 * n);
+    w.alloc<uint64_t>(slots);
+    w.alloc<uint32_t>(slots);
+    w.alloc<uint32_t>(slots);
+    w.alloc<uint32_t>(slots);
   }
   return w.off + scan_ws_bytes(n + 1) + 4096;
 }
@@ -587,7 +587,7 @@ static ce_status jump_all(uint32_t *&act, uint32_t *&act2, uint64_t nact, uint32
 }
 
 ce_status stage_boruvka(Bufs &b, Ws &ws, hipStream_t s) {
-  const int64_t n = b.n, n2 = 2 * n;
+  const int64_t n = b.n, n2 = b.slots;
   size_t m0 = ws.mark();
   uint32_t *rankof = ws.alloc<uint32_t>(n);
   uint32_t *hook = ws.alloc<uint32_t>(n);
@@ -612,9 +612,9 @@ ce_status stage_boruvka(Bufs &b, Ws &ws, hipStream_t s) {
   int cur = 0, rounds = 0;
   uint64_t nact = 0;
   uint64_t hv[2];
-  if (b.causal) {
-    // causal skeleton rows can share a head, so every round, the first
-    // included, runs on the edge-list form with records as components
+  if (b.flat) {
+    // causal and hypergraph skeleton rows can share a head, so every round,
+    // the first included, runs on the edge-list form with records as components
     if (b.S > 0)
       CE_LAUNCH(k_edges_from_skeleton, dim3(grid_for(b.S, B)), dim3(B), 0, s, b.S, b.skel_key, b.skel_tail,
                 b.skel_tid, key[0], eu[0], ev[0], es[0]);
@@ -733,7 +733,7 @@ size_t stage_msf_sort_scratch(int64_t n) {
 }
 
 ce_status stage_msf_sort(Bufs &b, Ws &ws, hipStream_t s, int64_t *m_out) {
-  const int64_t n = b.n, n2 = 2 * n;
+  const int64_t n = b.n, n2 = b.slots;
   size_t m0 = ws.mark();
   uint64_t *key_alt = ws.alloc<uint64_t>(n);
   uint4 *val_alt = ws.alloc<uint4>(n);
@@ -749,7 +749,7 @@ ce_status stage_msf_sort(Bufs &b, Ws &ws, hipStream_t s, int64_t *m_out) {
     set_error("spanning forest larger than n-1");
     return CE_EDEVICE;
   }
-  if (m > 0 && b.causal)
+  if (m > 0 && b.flat)
     CE_LAUNCH(k_msf_gather_causal, dim3(grid_for((int64_t)m, B)), dim3(B), 0, s, list, (int64_t)m, b.skel_key,
               b.skel_tail, b.skel_tid, b.perm, b.msf_key, b.msf_val);
   else if (m > 0)

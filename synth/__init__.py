@@ -171,3 +171,55 @@ def request_graph(r, n_r, seed=4):
     scale = max(1, int(math.ceil(math.log2(max(2.0, n_r / 16.0)))))
     s, d, t = rmat_hawkes(int(n_r), scale, child_seed(seed, r), T=90 * DAY)
     return s, d, t, 1 << scale
+
+
+@dataclass
+class HyperWorkload:
+    name: str
+    members: np.ndarray   # int32[nnz]
+    offsets: np.ndarray   # int64[n+1]
+    t: np.ndarray         # int64[n]
+    num_vertices: int
+    min_cluster_size: int
+
+    @property
+    def n(self):
+        return int(self.t.shape[0])
+
+    @property
+    def nnz(self):
+        return int(self.members.shape[0])
+
+
+def hyper_bursts(n, V, seed, median=2.0, sigma=1.0, dmax=64, T=30 * DAY):
+    """Dynamic hypergraph of multi-recipient messages: hyperedge r is a Chung-Lu burst record (sender, first
+    recipient, time) plus k_r - 1 further Chung-Lu recipients, k_r ~ lognormal(median, sigma) clipped to
+    [1, dmax]. A recipient may repeat within a message (the hyperedge is the set). Returns (members, offsets, t)."""
+    s, d, t = chung_lu_bursts(n, V, seed, T=T)
+    k = lognormal_sizes(n, median, sigma, 1, dmax, child_seed(seed, 1))
+    extra = int((k - 1).sum())
+    _, xd, _ = chung_lu_bursts(max(extra, 1), V, child_seed(seed, 2), T=T)
+    off = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(k + 1, out=off[1:])
+    members = np.empty(int(off[-1]), dtype=np.int32)
+    first = np.ones(members.shape[0], dtype=bool)
+    members[off[:-1]] = s
+    members[off[:-1] + 1] = d
+    first[off[:-1]] = False
+    first[off[:-1] + 1] = False
+    members[first] = xd[:extra]
+    return members, off, t
+
+
+def hyper_tiny(seed=5, n=200_000, V=10_000):
+    """Tiny hypergraph workload: 200k multi-recipient messages over 10k Chung-Lu vertices, bursts over 30 days,
+    M=5."""
+    mem, off, t = hyper_bursts(n, V, seed)
+    return HyperWorkload("hyper-bursts n=%d V=%d M=5" % (n, V), mem, off, t, V, 5)
+
+
+def hyper_mid(seed=6, n=20_000_000, V=1 << 20):
+    """Mid hypergraph workload: 2e7 multi-recipient messages over 2^20 Chung-Lu vertices, bursts over 90 days,
+    M=10."""
+    mem, off, t = hyper_bursts(n, V, seed, T=90 * DAY)
+    return HyperWorkload("hyper-bursts n=%d V=2^20 M=10" % n, mem, off, t, V, 10)

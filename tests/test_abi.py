@@ -21,7 +21,8 @@ def test_library_exports_declared_symbols():
     assert set(syms) == {"ce_cluster_edges", "ce_cluster_batch", "ce_workspace_bytes", "ce_batch_workspace_bytes",
                          "ce_max_clusters", "ce_last_error", "ce_timing_enable", "ce_timing_read",
                          "ce_server_create", "ce_server_destroy", "ce_server_request_bytes", "ce_server_submit",
-                         "ce_server_poll", "ce_server_get_stats"}
+                         "ce_server_poll", "ce_server_get_stats", "ce_cluster_hyperedges",
+                         "ce_hyper_workspace_bytes"}
     for s in syms:
         assert hasattr(lib, s), s
 
@@ -61,6 +62,30 @@ def test_host_argument_errors_need_no_gpu():
     p.mode = 7
     assert lib.ce_cluster_edges(None, None, None, 0, ctypes.byref(p), ctypes.byref(res), ctypes.byref(cnt), None, 0,
                                 None) == ce.CE_EINVAL
+
+
+def test_hypergraph_host_functions_and_errors():
+    import ctypes
+    import paper_2311_10337_amd as ce
+    if not os.path.exists(ce.LIB_PATH):
+        pytest.skip("libce.so not built")
+    lib = ce.load_library()
+    a = ce.hyper_workspace_bytes(1000, 3000, 100, 5)
+    assert 0 < a < ce.hyper_workspace_bytes(1000, 30000, 100, 5)
+    assert ce.hyper_workspace_bytes(1000, 3000, 100, 5, thresholds=[1, 2]) > a
+    assert ce.hyper_workspace_bytes(-1, 3, 100, 5) == 0 and ce.hyper_workspace_bytes(10, -1, 100, 5) == 0
+    p = ce.make_params(5, 100, causal=True)
+    assert lib.ce_hyper_workspace_bytes(10, 30, ctypes.byref(p)) == 0
+    res, cnt = ce.CeResult(), ce.CeCounts()
+    assert lib.ce_cluster_hyperedges(None, None, None, 0, 0, ctypes.byref(p), ctypes.byref(res), ctypes.byref(cnt),
+                                     None, 0, None) == ce.CE_EINVAL
+    assert "undirected" in ce.last_error()
+    p = ce.make_params(5, 100)
+    assert lib.ce_cluster_hyperedges(None, None, None, 4, 9, ctypes.byref(p), ctypes.byref(res), ctypes.byref(cnt),
+                                     None, 0, None) == ce.CE_EINVAL
+    assert "input pointer" in ce.last_error()
+    assert lib.ce_cluster_hyperedges(None, None, None, 4, -1, ctypes.byref(p), ctypes.byref(res), ctypes.byref(cnt),
+                                     None, 0, None) == ce.CE_EINVAL
 
 
 def test_batch_host_functions():

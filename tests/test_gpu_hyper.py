@@ -1,0 +1,171 @@
+"""GPU parity of dynamic hypergraphs (Sec. 5.3): every output field of
+ce_cluster_hyperedges against the oracle's hypergraph pipeline, from the hand
+example and degenerate inputs to the 2e7-hyperedge workload, with the time
+cutoff and the discrete dendrogram; argument and data errors."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+FIELDS = ("msf_tail", "msf_head", "msf_w", "sl_left", "sl_right", "sl_w", "sl_size", "pt_cluster", "pt_lambda",
+          "cl_id", "cl_parent", "cl_size", "cl_lambda_birth", "cl_stab_hi", "cl_stab_lo", "cl_selected", "labels")
+
+
+def _ce():
+    import paper_2311_10337_amd as ce
+    if not os.path.exists(ce.LIB_PATH):
+        pytest.fail("libce.so is not built")
+    return ce
+
+
+def note(msg):
+    print("[gpu-hyper] " + msg, flush=True)
+    sys.stdout.flush()
+
+
+def dev(mem, off, t):
+    d = torch.device("cuda:0")
+    return (torch.from_numpy(np.ascontiguousarray(mem, np.int32)).to(d),
+            torch.from_numpy(np.ascontiguousarray(off, np.int64)).to(d),
+            torch.from_numpy(np.ascontiguousarray(t, np.int64)).to(d))
+
+
+def csr(sets):
+    off = np.zeros(len(sets) + 1, np.int64)
+    for r, S in enumerate(sets):
+        off[r + 1] = off[r] + len(S)
+    return np.array([v for S in sets for v in S], np.int32), off
+
+
+def ref_dict(mem, off, t, V, M, max_dt=-1, thr=None):
+    if thr is not None:
+        r, dl, dt = oracle.cluster_hyper_discrete(mem, off, t, M, thr, V)
+    else:
+        r = oracle.cluster_hyper(mem, off, t, M, V, tier=1, max_dt=max_dt)
+    assert r.status == 0
+    out = {"m": r.m, "n_clusters": r.n_clusters, "n_labels": r.n_labels}
+    for f in FIELDS:
+        out[f] = getattr(r, f)
+    if thr is not None:
+        out["dd_level"], out["dd_top"] = dl, dt
+    return out
+
+
+def same(got, ref, label):
+    assert (got["m"], got["n_clusters"], got["n_labels"]) == (ref["m"], ref["n_clusters"], ref["n_labels"]), label
+    for f in FIELDS + (("dd_level", "dd_top") if "dd_level" in ref else ()):
+        a, b = got[f], ref[f]
+        if not np.array_equal(a, b):
+            bad = np.nonzero(a != b)[0][:10] if a.shape == b.shape else "shape %s vs %s" % (a.shape, b.shape)
+            raise AssertionError("%s: field %s differs at %s" % (label, f, bad))
+
+
+def check(mem, off, t, V, M, label, max_dt=-1, thr=None):
+    ce = _ce()
+    note("%s n=%d nnz=%d max_dt=%d thresholds=%s" % (label, len(t), len(mem), max_dt, None if thr is None else
+                                                        len(thr)))
+    got = ce.to_numpy(ce.cluster_hyperedges(*dev(mem, off, t), M, V, max_dt=max_dt, thresholds=thr))
+    same(got, ref_dict(mem, off, t, V, M, max_dt, thr), label)
+    return got
+
+
+def random_sets(rng, n, V, dmax):
+    sets = []
+    for _ in range(n):
+        S = [int(x) for x in rng.integers(0, V, int(rng.integers(0, dmax + 1)))]
+        if S and rng.random() < 0.2:
+            S.append(S[0])
+        sets.append(S)
+    return sets
+
+
+def test_hand_example_and_degenerate_inputs():
+    mem, off = csr([[0, 1, 2], [2, 3], [3, 4, 5], [6], []])
+    got = check(mem, off, np.array([0, 10, 15, 5, 7], np.int64), 7, 2, "hand")
+    assert list(got["msf_w"]) == [5, 10]
+    z = np.zeros(0, np.int64)
+    check(np.zeros(0, np.int32), np.zeros(1, np.int64), z, 3, 2, "n=0")
+    check(np.array([1, 2], np.int32), np.array([0, 2], np.int64), np.array([4], np.int64), 3, 2, "n=1")
+    check(np.zeros(0, np.int32), np.zeros(7, np.int64), np.arange(6, dtype=np.int64), 3, 2, "all empty")
+    # every hyperedge holds vertex 0: one path through all of them
+    n = 3000
+    rng = np.random.default_rng(5)
+    t = rng.integers(0, 50, n).astype(np.int64)
+    got = check(np.zeros(n, np.int32), np.arange(n + 1, dtype=np.int64), t, 1, 5, "one shared vertex")
+    assert got["m"] == n - 1
+    # one hyperedge spanning every vertex among small ones
+    sets = random_sets(rng, 500, 60, 3)
+    sets[250] = list(range(60))
+    mem, off = csr(sets)
+    check(mem, off, rng.integers(0, 1000, 500).astype(np.int64), 60, 3, "spanning hyperedge")
+
+
+def test_random_hypergraphs():
+    rng = np.random.default_rng(83)
+    for k in range(80):
+        n = int(rng.integers(1, 500))
+        V = int(rng.integers(1, 40))
+        mem, off = csr(random_sets(rng, n, V, int(rng.choice([2, 4, 8]))))
+        t = rng.integers(0, int(rng.choice([3, 100, 10 ** 6])), n).astype(np.int64)
+        check(mem, off, t, V, int(rng.choice([2, 3, 5])), "random%d" % k)
+
+
+def test_pairs_equal_the_graph_path():
+    ce = _ce()
+    w = synth.plain_tiny()
+    mem = np.stack([w.src, w.dst], axis=1).reshape(-1)
+    off = np.arange(0, 2 * w.n + 1, 2, dtype=np.int64)
+    note("tiny graph as pairs n=%d" % w.n)
+    a = ce.to_numpy(ce.cluster_hyperedges(*dev(mem, off, w.t), w.min_cluster_size, w.num_vertices))
+    d = torch.device("cuda:0")
+    b = ce.to_numpy(ce.cluster_edges(torch.from_numpy(w.src).to(d), torch.from_numpy(w.dst).to(d),
+                                     torch.from_numpy(w.t).to(d), w.min_cluster_size, w.num_vertices))
+    same(a, b, "pairs vs graph")
+
+
+def test_cutoff_and_discrete():
+    rng = np.random.default_rng(89)
+    for k in range(30):
+        n = int(rng.integers(2, 400))
+        mem, off = csr(random_sets(rng, n, 25, 5))
+        t = rng.integers(0, 5000, n).astype(np.int64)
+        check(mem, off, t, 25, 3, "cut%d" % k, max_dt=int(rng.choice([0, 10, 300])))
+        thr = sorted(set(int(x) for x in rng.integers(0, 3000, 4)))
+        check(mem, off, t, 25, 3, "discrete%d" % k, thr=thr)
+
+
+def test_tiny_workload():
+    w = synth.hyper_tiny()
+    check(w.members, w.offsets, w.t, w.num_vertices, w.min_cluster_size, "hyper-tiny")
+    check(w.members, w.offsets, w.t, w.num_vertices, w.min_cluster_size, "hyper-tiny paper thresholds",
+          thr=[1 << k for k in range(29)])
+
+
+def test_errors():
+    ce = _ce()
+    t = np.array([0, 1, 2], np.int64)
+    mem = np.array([0, 1, 1, 2], np.int32)
+    for off, status in (([0, 2, 1, 4], ce.CE_EINVAL), ([1, 2, 3, 4], ce.CE_EINVAL), ([0, 2, 3, 3], ce.CE_EINVAL)):
+        note("bad offsets %s" % off)
+        with pytest.raises(ce.ClusterError) as ei:
+            ce.cluster_hyperedges(*dev(mem, np.array(off, np.int64), t), 2, 3)
+        assert ei.value.status == status
+    note("member out of range")
+    with pytest.raises(ce.ClusterError) as ei:
+        ce.cluster_hyperedges(*dev(np.array([0, 1, 3, 2], np.int32), np.array([0, 2, 3, 4], np.int64), t), 2, 3)
+    assert ei.value.status == ce.CE_ERANGE
+    # a valid call afterwards is unaffected
+    check(mem, np.array([0, 2, 3, 4], np.int64), t, 3, 2, "after errors")
+
+
+@pytest.mark.timeout(1200)
+def test_mid_workload_full_size():
+    w = synth.hyper_mid()
+    check(w.members, w.offsets, w.t, w.num_vertices, w.min_cluster_size, "hyper-mid")

@@ -1,6 +1,6 @@
 """Planted mistakes in the oracle (on the CPU): each mutated copy of the oracle's
 C source must fail at least one pin in test_oracle_pins.py,
-test_oracle_causal.py or test_oracle_discrete.py. This shows the pins
+test_oracle_causal.py, test_oracle_discrete.py or test_oracle_hyper.py. This shows the pins
 would catch a dropped term, a wrong sign or index, or a transposed operand."""
 import os
 import subprocess
