@@ -18,6 +18,11 @@
 // union them. Sizes travel with labels. When intervals are small enough
 // (512 rows) one workgroup finishes all remaining levels in LDS with binary
 // splits, and the labels at the end are exactly the children.
+//
+// Within a level, the relabeling of sub-interval q and its unions run in one
+// kernel: every hook records the sub-interval it was made in, so a find that
+// must see the roots at the start of q stops at nodes hooked during q, and
+// path halving never shortcuts such a link.
 #include "ce_internal.h"
 
 namespace ce {
@@ -34,28 +39,52 @@ __device__ inline void st(uint32_t *p, uint32_t v) {
 }
 
 // One 16-byte entry per label keeps everything a level needs in a single
-// cache line: x = parent, y = largest row + 1 of the component (0 = none),
-// z = component size. (The hot-root atomics are pre-aggregated in LDS.)
-// lock-free find with path halving; parent pointers only move to ancestors
-__device__ inline uint32_t g_find(uint4 *uf, uint32_t x) {
+// cache line: x = parent, y = the sub-interval in which the node was hooked
+// (NONE while it is a root), z = largest row + 1 of the component (0 = none),
+// w = component size. x and y change together (one 64-bit CAS); z and w change
+// only between kernels of a sub-interval. (The hot-root atomics are
+// pre-aggregated in LDS.)
+__device__ inline uint2 ld2(const uint4 *e) {
+  const uint64_t v = __hip_atomic_load((const uint64_t *)e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+}
+
+// root at the start of sub-interval q: links made during q (or later) are not followed
+__device__ inline uint32_t g_find_before(uint4 *uf, uint32_t x, uint32_t q) {
   while (true) {
-    uint32_t p = ld(&uf[x].x);
-    if (p == x) return x;
-    uint32_t gp = ld(&uf[p].x);
-    if (gp == p) return p;
-    st(&uf[x].x, gp);
-    x = gp;
+    const uint2 e = ld2(&uf[x]);
+    if (e.x == x || e.y >= q) return x;
+    const uint2 pe = ld2(&uf[e.x]);
+    if (pe.x == e.x || pe.y >= q) return e.x;
+    st(&uf[x].x, pe.x);  // both links are older than q
+    x = pe.x;
   }
 }
 
-// returns the root that was hooked (the larger of the two roots)
-__device__ inline uint32_t g_union(uint4 *uf, uint32_t a, uint32_t b) {
+// current root; halves only links older than q, so the roots at the start of
+// q stay reachable for g_find_before
+__device__ inline uint32_t g_find(uint4 *uf, uint32_t x, uint32_t q) {
   while (true) {
-    a = g_find(uf, a);
-    b = g_find(uf, b);
+    const uint2 e = ld2(&uf[x]);
+    if (e.x == x) return x;
+    const uint2 pe = ld2(&uf[e.x]);
+    if (pe.x == e.x) return e.x;
+    if (e.y < q && pe.y < q) st(&uf[x].x, pe.x);
+    x = pe.x;
+  }
+}
+
+// hooks the larger of the two roots under the smaller during sub-interval q;
+// returns the hooked root
+__device__ inline uint32_t g_union(uint4 *uf, uint32_t a, uint32_t b, uint32_t q) {
+  while (true) {
+    a = g_find(uf, a, q);
+    b = g_find(uf, b, q);
     if (a == b) return NONE32;
-    uint32_t hi = a > b ? a : b, lo = a > b ? b : a;
-    if (atomicCAS(&uf[hi].x, hi, lo) == hi) return hi;
+    const uint32_t hi = a > b ? a : b, lo = a > b ? b : a;
+    const unsigned long long want = ((unsigned long long)NONE32 << 32) | hi;
+    const unsigned long long to = ((unsigned long long)q << 32) | lo;
+    if (atomicCAS((unsigned long long *)&uf[hi], want, to) == want) return hi;
   }
 }
 
@@ -74,9 +103,15 @@ __global__ __launch_bounds__(B) void k_krt_reset(const uint32_t *lu, const uint3
                                                  const uint32_t *sv, int64_t m, uint4 *uf) {
   for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
     uint32_t a = lu[j], b = lv[j];
-    uf[a] = make_uint4(a, 0u, su[j], 0u);
-    uf[b] = make_uint4(b, 0u, sv[j], 0u);
+    uf[a] = make_uint4(a, NONE32, 0u, su[j]);
+    uf[b] = make_uint4(b, NONE32, 0u, sv[j]);
   }
+}
+
+// the first level's labels are exactly the records, each of size 1: a streaming fill
+__global__ __launch_bounds__(B) void k_krt_reset_records(int64_t n, uint4 *uf) {
+  for (int64_t r = (int64_t)blockIdx.x * B + threadIdx.x; r < n; r += (int64_t)gridDim.x * B)
+    uf[r] = make_uint4((uint32_t)r, NONE32, 0u, 1u);
 }
 
 __device__ inline int64_t step_row(int64_t tix, int lo, int hi, uint32_t q) {
@@ -85,39 +120,32 @@ __device__ inline int64_t step_row(int64_t tix, int lo, int hi, uint32_t q) {
   return (interval << (hi + 1)) | ((int64_t)q << lo) | off;
 }
 
-// relabel the rows of sub-interval q (q >= 1) to the roots after sub-intervals < q
-__global__ __launch_bounds__(B) void k_krt_relabel(int64_t m, int64_t n, int lo, int hi, uint32_t q, int64_t nthreads,
-                                                   uint32_t *lu, uint32_t *lv, uint32_t *su, uint32_t *sv,
-                                                   uint32_t *ru, uint32_t *rv, uint4 *uf) {
+// Sub-interval q: relabel its rows to the roots at the start of q (for q >= 1:
+// the largest row and size of the component after sub-intervals < q), then
+// union them. Largest rows and sizes (z, w) are read while other threads hook
+// roots, which changes only x and y.
+__global__ __launch_bounds__(B) void k_krt_union(int64_t m, int64_t n, int lo, int hi, uint32_t q, int64_t nthreads,
+                                                 uint32_t *lu, uint32_t *lv, uint32_t *su, uint32_t *sv, uint4 *uf,
+                                                 uint32_t *hooked) {
   for (int64_t tix = (int64_t)blockIdx.x * B + threadIdx.x; tix < nthreads; tix += (int64_t)gridDim.x * B) {
     int64_t j = step_row(tix, lo, hi, q);
     if (j >= m) continue;
-    uint32_t a = g_find(uf, lu[j]);
-    ru[j] = a;
-    uint4 na = uf[a];
-    if (na.y) {
-      lu[j] = (uint32_t)(n + na.y - 1);
-      su[j] = na.z;
+    uint32_t a = lu[j], b = lv[j];
+    if (q) {
+      a = g_find_before(uf, a, q);
+      const uint4 na = uf[a];
+      if (na.z) {
+        lu[j] = (uint32_t)(n + na.z - 1);
+        su[j] = na.w;
+      }
+      b = g_find_before(uf, b, q);
+      const uint4 nb = uf[b];
+      if (nb.z) {
+        lv[j] = (uint32_t)(n + nb.z - 1);
+        sv[j] = nb.w;
+      }
     }
-    uint32_t b = g_find(uf, lv[j]);
-    rv[j] = b;
-    uint4 nb = uf[b];
-    if (nb.y) {
-      lv[j] = (uint32_t)(n + nb.y - 1);
-      sv[j] = nb.z;
-    }
-  }
-}
-
-__global__ __launch_bounds__(B) void k_krt_union(int64_t m, int lo, int hi, uint32_t q, int64_t nthreads,
-                                                 const uint32_t *lu, const uint32_t *lv, const uint32_t *ru,
-                                                 const uint32_t *rv, uint4 *uf, uint32_t *hooked) {
-  for (int64_t tix = (int64_t)blockIdx.x * B + threadIdx.x; tix < nthreads; tix += (int64_t)gridDim.x * B) {
-    int64_t j = step_row(tix, lo, hi, q);
-    if (j >= m) continue;
-    uint32_t a = q ? ru[j] : lu[j];
-    uint32_t b = q ? rv[j] : lv[j];
-    hooked[j] = g_union(uf, a, b);
+    hooked[j] = g_union(uf, a, b, q);
   }
 }
 
@@ -139,8 +167,8 @@ __global__ __launch_bounds__(B) void k_krt_accum(int64_t m, int lo, int hi, uint
     uint32_t h = NONE32, f = 0, add = 0, mj = 0;
     if (j < m) h = hooked[j];
     if (h != NONE32) {
-      f = g_find(uf, h);
-      add = uf[h].z;
+      f = g_find(uf, h, NONE32);  // every link is complete now: full halving
+      add = uf[h].w;
       mj = (uint32_t)(j + 1);
     }
     const bool upd = wave_combine_first(h != NONE32, f, [&](bool mine, int leader) {
@@ -161,8 +189,8 @@ __global__ __launch_bounds__(B) void k_krt_accum(int64_t m, int lo, int hi, uint
         }
       }
       if (!placed) {
-        atomicAdd(&uf[f].z, add);
-        atomicMax(&uf[f].y, mj);
+        atomicAdd(&uf[f].w, add);
+        atomicMax(&uf[f].z, mj);
       }
     }
   }
@@ -170,8 +198,8 @@ __global__ __launch_bounds__(B) void k_krt_accum(int64_t m, int lo, int hi, uint
   for (int i = threadIdx.x; i < KHS; i += B) {
     const uint32_t f = hk[i];
     if (f == NONE32) continue;
-    atomicAdd(&uf[f].z, hs[i]);
-    atomicMax(&uf[f].y, hm[i]);
+    atomicAdd(&uf[f].w, hs[i]);
+    atomicMax(&uf[f].z, hm[i]);
   }
 }
 
@@ -320,7 +348,7 @@ int krt_level_bits() {
 
 size_t stage_dendrogram_scratch(int64_t n) {
   Ws w;
-  for (int k = 0; k < 7; k++) w.alloc<uint32_t>(n);  // lu lv su sv ru rv hooked
+  for (int k = 0; k < 5; k++) w.alloc<uint32_t>(n);  // lu lv su sv hooked
   w.alloc<uint4>(2 * n);  // packed union-find over labels < n + m
   return w.off + 4096;
 }
@@ -331,7 +359,6 @@ ce_status stage_dendrogram(Bufs &b, int64_t m, Ws &ws, hipStream_t s) {
   size_t m0 = ws.mark();
   uint32_t *lu = ws.alloc<uint32_t>(m), *lv = ws.alloc<uint32_t>(m);
   uint32_t *su = ws.alloc<uint32_t>(m), *sv = ws.alloc<uint32_t>(m);
-  uint32_t *ru = ws.alloc<uint32_t>(m), *rv = ws.alloc<uint32_t>(m);
   uint32_t *hooked = ws.alloc<uint32_t>(m);
   uint4 *uf = ws.alloc<uint4>(n + m);
   CE_WS_CHECK(ws);
@@ -340,6 +367,7 @@ ce_status stage_dendrogram(Bufs &b, int64_t m, Ws &ws, hipStream_t s) {
   const int L = bits_for((uint64_t)(m - 1));  // rows are j < 2^L
   const int kb = krt_level_bits();
   int hi = L - 1;
+  bool first = true;
   while (hi >= LS_BITS) {
     int lo = hi - kb + 1;
     if (lo < LS_BITS) lo = LS_BITS;
@@ -347,13 +375,13 @@ ce_status stage_dendrogram(Bufs &b, int64_t m, Ws &ws, hipStream_t s) {
     const int64_t nint = (m + (int64_t(1) << (hi + 1)) - 1) >> (hi + 1);
     const int64_t nthreads = nint << lo;
     const unsigned g = grid_for(nthreads, B, 1 << 16);
-    CE_LAUNCH(k_krt_reset, dim3(grid_for(m, B)), dim3(B), 0, s, lu, lv, su, sv, m, uf);
+    if (first) CE_LAUNCH(k_krt_reset_records, dim3(grid_for(n, B)), dim3(B), 0, s, n, uf);
+    else CE_LAUNCH(k_krt_reset, dim3(grid_for(m, B)), dim3(B), 0, s, lu, lv, su, sv, m, uf);
+    first = false;
     for (uint32_t q = 0; q < K; q++) {
       // sub-interval q exists in at least one interval?
       if (((int64_t)q << lo) >= m) break;
-      if (q) CE_LAUNCH(k_krt_relabel, dim3(g), dim3(B), 0, s, m, n, lo, hi, q, nthreads, lu, lv, su, sv, ru,
-                                rv, uf);
-      CE_LAUNCH(k_krt_union, dim3(g), dim3(B), 0, s, m, lo, hi, q, nthreads, lu, lv, ru, rv, uf, hooked);
+      CE_LAUNCH(k_krt_union, dim3(g), dim3(B), 0, s, m, n, lo, hi, q, nthreads, lu, lv, su, sv, uf, hooked);
       CE_LAUNCH(k_krt_accum, dim3((unsigned)((nthreads + B * KCT - 1) / (B * KCT))), dim3(B), 0, s, m, lo, hi,
                          q, nthreads, hooked, uf);
     }
