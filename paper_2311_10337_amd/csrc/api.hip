@@ -61,10 +61,10 @@ __global__ __launch_bounds__(B) void k_zero32(uint32_t *p, int64_t n) {
 }
 
 // graph of each MSF row (the graph of its tail record)
-__global__ __launch_bounds__(B) void k_rowg(const uint4 *msf_val, const uint32_t *grank, int64_t m, uint32_t *rowg,
+__global__ __launch_bounds__(B) void k_rowg(const uint64_t *msf_val, const uint32_t *grank, int64_t m, uint32_t *rowg,
                                             uint32_t *key) {
   for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
-    const uint32_t g = grank[msf_val[j].x];
+    const uint32_t g = grank[(uint32_t)msf_val[j]];
     rowg[j] = g;
     key[j] = g;
   }
@@ -82,19 +82,20 @@ __global__ __launch_bounds__(B) void k_rowpos(const uint32_t *sorted_j, int64_t 
 // A record that is a child of row j joins at row j, so it is one of that row's
 // two endpoints: its input id comes from the row itself (no gathers). Row j is
 // written at its position in the batch, with its graph's local ids.
-__global__ __launch_bounds__(B) void k_rows(const uint64_t *msf_key, const uint4 *msf_val, const uint32_t *kc_u,
+__global__ __launch_bounds__(B) void k_rows(const uint64_t *msf_key, const uint64_t *msf_val, const uint32_t *perm,
+                                            const uint32_t *kc_u,
                                             const uint32_t *kc_v, const uint32_t *ksize, const uint32_t *rowg,
                                             const uint32_t *rowpos, const uint32_t *moff, const int64_t *eoff,
                                             int64_t m, int64_t n, int idbits, int wshift, int hshift,
                                             ce_result out) {
   const uint64_t idmask = (uint64_t(1) << idbits) - 1;
   for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
-    const uint4 v = msf_val[j];
+    const uint32_t tr = (uint32_t)msf_val[j];
     const uint64_t key = msf_key[j];
     const int64_t w = (int64_t)(key >> wshift);
     const uint32_t g = rowg[j], p = rowpos[j], m0 = moff[g];
     const uint32_t e0 = (uint32_t)eoff[g], ng = (uint32_t)(eoff[g + 1] - eoff[g]);
-    const uint32_t tr = v.x, tid = v.z - e0, hid = (uint32_t)((key >> hshift) & idmask) - e0;
+    const uint32_t tid = perm[tr] - e0, hid = (uint32_t)((key >> hshift) & idmask) - e0;
     if (out.msf_tail) out.msf_tail[p] = tid;
     if (out.msf_head) out.msf_head[p] = hid;
     if (out.msf_w) out.msf_w[p] = w;
@@ -178,7 +179,7 @@ ce_status stage_graph_rows(Bufs &b, int64_t m, Ws &ws, hipStream_t s, int64_t *r
 
 ce_status stage_write_rows(Bufs &b, int64_t m, const ce_result *out, hipStream_t s) {
   if (m <= 0) return CE_OK;
-  CE_LAUNCH(k_rows, dim3(grid_for(m, B)), dim3(B), 0, s, b.msf_key, b.msf_val, b.kc_u, b.kc_v, b.ksize, b.rowg,
+  CE_LAUNCH(k_rows, dim3(grid_for(m, B)), dim3(B), 0, s, b.msf_key, b.msf_val, b.perm, b.kc_u, b.kc_v, b.ksize, b.rowg,
             b.rowpos, b.moff, b.eoff, m, b.n, b.idbits, b.wshift, b.hshift, *out);
   CE_HIP(hipGetLastError());
   return CE_OK;
@@ -210,7 +211,7 @@ static void layout(Bufs &b, Ws &ws, int64_t n, int64_t M, int64_t G, bool discre
   const size_t xbytes = ws.off - base;
   Ws y;
   y.alloc<uint64_t>(n);
-  y.alloc<uint4>(n);
+  y.alloc<uint64_t>(n);
   for (int k = 0; k < 5; k++) y.alloc<uint32_t>(n);
   y.alloc<uint32_t>(G + 1);
   const size_t ybytes = y.off;
@@ -231,7 +232,7 @@ static void layout(Bufs &b, Ws &ws, int64_t n, int64_t M, int64_t G, bool discre
   if (al(scr_b) + ybytes > phase) phase = al(scr_b) + ybytes;
   ws.off = base + phase - ybytes;
   b.msf_key = ws.alloc<uint64_t>(n);
-  b.msf_val = ws.alloc<uint4>(n);
+  b.msf_val = ws.alloc<uint64_t>(n);
   b.kc_u = ws.alloc<uint32_t>(n);
   b.kc_v = ws.alloc<uint32_t>(n);
   b.ksize = ws.alloc<uint32_t>(n);

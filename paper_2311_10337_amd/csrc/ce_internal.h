@@ -300,7 +300,7 @@ struct Bufs {
   uint64_t *best = nullptr;     // [n] Boruvka: minimum key leaving each component
   uint8_t *msf_flag = nullptr;  // [slots]
   uint64_t *msf_key = nullptr;  // [n] sorted MSF keys
-  uint4 *msf_val = nullptr;     // [n] (tail rank, head rank, tail input id, 0); the head's id is in the key
+  uint64_t *msf_val = nullptr;  // [n] tail rank | head rank << 32; the head's id is in the key
   uint32_t *kc_u = nullptr, *kc_v = nullptr, *ksize = nullptr; // [n] dendrogram children (internal labels) and size
   // scratch arenas: A for grouping, skeleton and Boruvka (it may overlap the
   // MSF/dendrogram arrays, which are not live yet), M for sorting the MSF, B

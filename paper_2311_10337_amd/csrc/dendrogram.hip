@@ -88,12 +88,12 @@ __device__ inline uint32_t g_union(uint4 *uf, uint32_t a, uint32_t b, uint32_t q
   }
 }
 
-__global__ __launch_bounds__(B) void k_krt_init(const uint4 *msf_val, int64_t m, uint32_t *lu, uint32_t *lv,
+__global__ __launch_bounds__(B) void k_krt_init(const uint64_t *msf_val, int64_t m, uint32_t *lu, uint32_t *lv,
                                                 uint32_t *su, uint32_t *sv) {
   for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
-    const uint4 v = msf_val[j];
-    lu[j] = v.x;  // tail rank
-    lv[j] = v.y;  // head rank
+    const uint64_t v = msf_val[j];
+    lu[j] = (uint32_t)v;          // tail rank
+    lv[j] = (uint32_t)(v >> 32);  // head rank
     su[j] = 1;
     sv[j] = 1;
   }

@@ -418,22 +418,20 @@ __global__ __launch_bounds__(B) void k_edges_from_skeleton(int64_t S, const uint
 // flat rows keep the head rank in skel_tid; the tail id comes from perm
 __global__ __launch_bounds__(B) void k_msf_gather_causal(const uint32_t *list, int64_t m, const uint64_t *skel_key,
                                                          const uint32_t *skel_tail, const uint32_t *skel_head,
-                                                         const uint32_t *perm, uint64_t *okey, uint4 *oval) {
+                                                         uint64_t *okey, uint64_t *oval) {
   for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < m; i += (int64_t)gridDim.x * B) {
     uint32_t e = list[i];
-    const uint32_t tr = skel_tail[e];
     okey[i] = skel_key[e];
-    oval[i] = make_uint4(tr, skel_head[e], perm[tr], 0u);
+    oval[i] = (uint64_t)skel_tail[e] | ((uint64_t)skel_head[e] << 32);
   }
 }
 
 __global__ __launch_bounds__(B) void k_msf_gather(const uint32_t *list, int64_t m, const uint64_t *skel_key,
-                                                  const uint32_t *skel_tail, const uint32_t *skel_tid, uint64_t *okey,
-                                                  uint4 *oval) {
+                                                  const uint32_t *skel_tail, uint64_t *okey, uint64_t *oval) {
   for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < m; i += (int64_t)gridDim.x * B) {
     uint32_t e = list[i];
     okey[i] = skel_key[e];
-    oval[i] = make_uint4(skel_tail[e], e >> 1, skel_tid[e], 0u);
+    oval[i] = (uint64_t)skel_tail[e] | ((uint64_t)(e >> 1) << 32);
   }
 }
 
@@ -727,7 +725,7 @@ ce_status stage_time_filter(Bufs &b, int64_t max_dt, hipStream_t s, int64_t *m) 
 size_t stage_msf_sort_scratch(int64_t n) {
   Ws w;
   w.alloc<uint64_t>(n);
-  w.alloc<uint4>(n);
+  w.alloc<uint64_t>(n);
   w.alloc<uint32_t>(n);
   return w.off + radix_ws_bytes(n) + 4096;
 }
@@ -736,7 +734,7 @@ ce_status stage_msf_sort(Bufs &b, Ws &ws, hipStream_t s, int64_t *m_out) {
   const int64_t n = b.n, n2 = b.slots;
   size_t m0 = ws.mark();
   uint64_t *key_alt = ws.alloc<uint64_t>(n);
-  uint4 *val_alt = ws.alloc<uint4>(n);
+  uint64_t *val_alt = ws.alloc<uint64_t>(n);
   uint32_t *list = ws.alloc<uint32_t>(n);
   CE_WS_CHECK(ws);
   CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[6], (uint64_t)0);
@@ -749,18 +747,22 @@ ce_status stage_msf_sort(Bufs &b, Ws &ws, hipStream_t s, int64_t *m_out) {
     set_error("spanning forest larger than n-1");
     return CE_EDEVICE;
   }
+  // gather into the buffer pair from which an odd or even number of radix
+  // passes ends in msf_key / msf_val, so no copy follows the sort
+  const int passes = b.keybits > 8 ? (b.keybits + 7) / 8 : 1;
+  uint64_t *gk = (passes & 1) ? key_alt : b.msf_key, *gv = (passes & 1) ? val_alt : b.msf_val;
+  uint64_t *ok = (passes & 1) ? b.msf_key : key_alt, *ov = (passes & 1) ? b.msf_val : val_alt;
   if (m > 0 && b.flat)
     CE_LAUNCH(k_msf_gather_causal, dim3(grid_for((int64_t)m, B)), dim3(B), 0, s, list, (int64_t)m, b.skel_key,
-              b.skel_tail, b.skel_tid, b.perm, b.msf_key, b.msf_val);
+              b.skel_tail, b.skel_tid, gk, gv);
   else if (m > 0)
     CE_LAUNCH(k_msf_gather, dim3(grid_for((int64_t)m, B)), dim3(B), 0, s, list, (int64_t)m, b.skel_key,
-              b.skel_tail, b.skel_tid, b.msf_key, b.msf_val);
+              b.skel_tail, gk, gv);
   bool alt = false;
-  CE_TRY((radix_sort_pairs<uint64_t, uint4>(b.msf_key, b.msf_val, key_alt, val_alt, (int64_t)m, 0, b.keybits, false,
-                                             &alt, ws, s)));
-  if (alt && m > 0) {
-    CE_HIP(hipMemcpyAsync(b.msf_key, key_alt, sizeof(uint64_t) * m, hipMemcpyDeviceToDevice, s));
-    CE_HIP(hipMemcpyAsync(b.msf_val, val_alt, sizeof(uint4) * m, hipMemcpyDeviceToDevice, s));
+  CE_TRY((radix_sort_pairs<uint64_t, uint64_t>(gk, gv, ok, ov, (int64_t)m, 0, b.keybits, false, &alt, ws, s)));
+  if (m > 0 && (alt ? ok : gk) != b.msf_key) {  // (not reached: the pass count is as computed)
+    CE_HIP(hipMemcpyAsync(b.msf_key, alt ? ok : gk, sizeof(uint64_t) * m, hipMemcpyDeviceToDevice, s));
+    CE_HIP(hipMemcpyAsync(b.msf_val, alt ? ov : gv, sizeof(uint64_t) * m, hipMemcpyDeviceToDevice, s));
   }
   ws.release(m0);
   *m_out = (int64_t)m;
