@@ -216,38 +216,11 @@ __global__ __launch_bounds__(B) void k_cd_exit(const uint32_t *kpar, const uint3
   }
 }
 
-// Top-down exits: a small child c of a big row j sheds every record under it
-// at (cluster of j, lambda(w_j)); a DFS over c's subtree (fewer than M
-// leaves, so fewer than 2M nodes and height < M) visits each node once.
-// Records outside such subtrees keep the default exit (ROOT, 0).
+// Top-down exits (k_cd_exit_down_acc below): a small child c of a big row j
+// sheds every record under it at (cluster of j, lambda(w_j)); a DFS over c's
+// subtree (fewer than M leaves, so fewer than 2M nodes and height < M) visits
+// each node once. Records outside such subtrees keep the default exit (ROOT, 0).
 constexpr int EXIT_STACK = 64;
-__global__ __launch_bounds__(B) void k_cd_exit_down(const uint32_t *kc_u, const uint32_t *kc_v, const uint32_t *ksize,
-                                                    const uint32_t *J, const uint64_t *rowL, int64_t m,
-                                                    int64_t n, int64_t M, uint32_t *exc, uint64_t *exl) {
-  for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
-    if (ksize[j] < (uint64_t)M) continue;
-    const uint32_t C = J[j];
-    const uint64_t L = rowL[j];
-#pragma unroll
-    for (int side = 0; side < 2; side++) {
-      const uint32_t c = side ? kc_v[j] : kc_u[j];
-      if (node_size(c, n, ksize) >= (uint64_t)M) continue;
-      uint32_t stack[EXIT_STACK];
-      int sp = 0;
-      stack[sp++] = c;
-      while (sp > 0) {
-        const uint32_t x = stack[--sp];
-        if (x < (uint64_t)n) {
-          exc[x] = C;
-          exl[x] = L;
-        } else {
-          stack[sp++] = kc_u[x - n];
-          stack[sp++] = kc_v[x - n];
-        }
-      }
-    }
-  }
-}
 
 // default exit: the record's graph root at lambda 0
 __global__ __launch_bounds__(B) void k_exit_default(const uint32_t *grank, int64_t n, int64_t m, uint32_t *exc,
@@ -396,6 +369,89 @@ __global__ __launch_bounds__(B) void k_cd_acc_points(const uint32_t *exc, const 
     if (r == NONE32) continue;
     if (h0[i]) atomicAdd(&acc[3 * (uint64_t)r], h0[i]);
     if (h1[i]) atomicAdd(&acc[3 * (uint64_t)r + 1], h1[i]);
+  }
+}
+
+// Exits of the records under the small children of big rows (as
+// k_cd_exit_down) together with the point term of each cluster's stability:
+// the records of small child c all leave the cluster of row j at lambda_j, so
+// they add size(c) * lambda_j, summed per cluster row in an LDS hash and then
+// one atomic per limb, row and tile. Runs once the cluster rows are known.
+__global__ __launch_bounds__(B) void k_cd_exit_down_acc(const uint32_t *kc_u, const uint32_t *kc_v,
+                                                        const uint32_t *ksize, const uint32_t *J,
+                                                        const uint64_t *rowL, const uint32_t *rowof,
+                                                        const uint32_t *rootrow, int64_t m, int64_t n, int64_t M,
+                                                        uint32_t *exc, uint64_t *exl, unsigned long long *acc) {
+  __shared__ uint32_t hk[AHS];
+  __shared__ unsigned long long h0[AHS], h1[AHS], h2[AHS];
+  for (int i = threadIdx.x; i < AHS; i += B) { hk[i] = NONE32; h0[i] = 0; h1[i] = 0; h2[i] = 0; }
+  __syncthreads();
+  const int64_t tbase = (int64_t)blockIdx.x * (B * CT);
+  for (int k = 0; k < CT; k++) {
+    const int64_t j = tbase + (int64_t)k * B + threadIdx.x;
+    uint32_t cnt = 0, r = 0;
+    uint64_t L = 0;
+    if (j < m && ksize[j] >= (uint64_t)M) {
+      const uint32_t C = J[j];
+      L = rowL[j];
+#pragma unroll
+      for (int side = 0; side < 2; side++) {
+        const uint32_t c = side ? kc_v[j] : kc_u[j];
+        const uint32_t sz = node_size(c, n, ksize);
+        if (sz >= (uint64_t)M) continue;
+        cnt += sz;
+        uint32_t stack[EXIT_STACK];
+        int sp = 0;
+        stack[sp++] = c;
+        while (sp > 0) {
+          const uint32_t x = stack[--sp];
+          if (x < (uint64_t)n) {
+            exc[x] = C;
+            exl[x] = L;
+          } else {
+            stack[sp++] = kc_u[x - n];
+            stack[sp++] = kc_v[x - n];
+          }
+        }
+      }
+      if (cnt && L) r = row_of(C, n, m, rowof, rootrow);
+    }
+    const bool act = cnt != 0 && L != 0;
+    const u128 prod = u128_mul64(cnt, L);
+    uint64_t s0 = prod.lo & 0xffffffffull, s1 = prod.lo >> 32, s2 = prod.hi;
+    const bool upd = wave_combine_first(act, r, [&](bool mine, int leader) {
+      const uint64_t a0 = wave_sum_u64(mine ? s0 : 0ull), a1 = wave_sum_u64(mine ? s1 : 0ull),
+                     a2 = wave_sum_u64(mine ? s2 : 0ull);
+      if ((int)wave_lane() == leader) { s0 = a0; s1 = a1; s2 = a2; }
+    });
+    if (upd) {
+      uint32_t sl = (r * 2654435761u) >> 23;  // 9 bits
+      bool placed = false;
+      for (int probe = 0; probe < 16 && !placed; probe++) {
+        uint32_t old = atomicCAS(&hk[sl], NONE32, r);
+        if (old == NONE32 || old == r) {
+          atomicAdd(&h0[sl], (unsigned long long)s0);
+          atomicAdd(&h1[sl], (unsigned long long)s1);
+          atomicAdd(&h2[sl], (unsigned long long)s2);
+          placed = true;
+        } else {
+          sl = (sl + 1) & (AHS - 1);
+        }
+      }
+      if (!placed) {
+        atomicAdd(&acc[3 * (uint64_t)r], (unsigned long long)s0);
+        atomicAdd(&acc[3 * (uint64_t)r + 1], (unsigned long long)s1);
+        atomicAdd(&acc[3 * (uint64_t)r + 2], (unsigned long long)s2);
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < AHS; i += B) {
+    uint32_t r = hk[i];
+    if (r == NONE32) continue;
+    if (h0[i]) atomicAdd(&acc[3 * (uint64_t)r], h0[i]);
+    if (h1[i]) atomicAdd(&acc[3 * (uint64_t)r + 1], h1[i]);
+    if (h2[i]) atomicAdd(&acc[3 * (uint64_t)r + 2], h2[i]);
   }
 }
 
@@ -884,15 +940,6 @@ ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipSt
       CE_TRY(read_u64(&b.hdr[9], &nact, 1, s));
     }
   }
-  if (M <= EXIT_STACK) {
-    CE_LAUNCH(k_exit_default, dim3(grid_for(n, B)), dim3(B), 0, s, b.grank, n, m, exc, exl);
-    if (m > 0)
-      CE_LAUNCH(k_cd_exit_down, dim3(grid_for(m, B)), dim3(B), 0, s, b.kc_u, b.kc_v, b.ksize, J, rowL,
-                m, n, M, exc, exl);
-  } else {
-    CE_LAUNCH(k_cd_exit, dim3(grid_for(n, B)), dim3(B), 0, s, kpar, b.ksize, J, rowL, b.grank, m, n,
-              M, exc, exl);
-  }
   // cluster rows: births in (graph, node) order, each graph followed by its root row
   CE_LAUNCH(k_u8_to_u32, dim3(gm), dim3(B), 0, s, isbirth, m, flags32);
   CE_HIP(hipGetLastError());
@@ -934,7 +981,17 @@ ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipSt
   CE_LAUNCH(k_cd_rootrows, dim3(gG), dim3(B), 0, s, rootrow, b.eoff, G, m, n, cnode, csize, cbirth, cprow);
   CE_LAUNCH(k_fill64, dim3(grid_for(3 * (int64_t)nrows, B)), dim3(B), 0, s, (uint64_t *)acc, 3 * (int64_t)nrows,
             (uint64_t)0);
-  CE_LAUNCH(k_cd_acc_points, dim3(tiles(n)), dim3(B), 0, s, exc, exl, rowmap, m, n, rootrow, acc);
+  // exits (and, for M <= EXIT_STACK, the point term of the stabilities with them)
+  if (M <= EXIT_STACK) {
+    CE_LAUNCH(k_exit_default, dim3(grid_for(n, B)), dim3(B), 0, s, b.grank, n, m, exc, exl);
+    if (m > 0)
+      CE_LAUNCH(k_cd_exit_down_acc, dim3(tiles(m)), dim3(B), 0, s, b.kc_u, b.kc_v, b.ksize, J, rowL, rowmap,
+                rootrow, m, n, M, exc, exl, acc);
+  } else {
+    CE_LAUNCH(k_cd_exit, dim3(grid_for(n, B)), dim3(B), 0, s, kpar, b.ksize, J, rowL, b.grank, m, n,
+              M, exc, exl);
+    CE_LAUNCH(k_cd_acc_points, dim3(tiles(n)), dim3(B), 0, s, exc, exl, rowmap, m, n, rootrow, acc);
+  }
   CE_LAUNCH(k_cd_acc_children, dim3((unsigned)((nrows + B - 1) / B)), dim3(B), 0, s, csize, cbirth, cprow, nrows,
             acc);
   CE_LAUNCH(k_cd_stab, dim3(gR), dim3(B), 0, s, acc, csize, cbirth, nrows, shi, slo);

@@ -109,6 +109,23 @@ def test_ragged_sizes_across_tiles():
         assert_parity(w[0], w[1], w[2], max(2, n // 20), 5, "ragged%d" % n)
 
 
+def test_min_cluster_sizes_around_the_exit_paths():
+    """Exits come from a top-down pass over small subtrees for M <= 64 and from a walk up from each record
+    above that; both sides of the switch, on the tiny workload and on random graphs."""
+    w = synth.plain_tiny()
+    for M in (63, 64, 65, 200, 5000):
+        assert_parity(w.src, w.dst, w.t, w.num_vertices, M, "tiny M=%d" % M)
+    rng = np.random.default_rng(79)
+    for it in range(20):
+        n = int(rng.integers(100, 3000))
+        V = int(rng.integers(2, 30))
+        src = rng.integers(0, V, n).astype(np.int32)
+        dst = rng.integers(0, V - 1, n).astype(np.int32)
+        dst[dst >= src] += 1
+        t = rng.integers(0, 500, n).astype(np.int64)
+        assert_parity(src, dst, t, V, int(rng.choice([64, 65, 90, 300])), "bigM%d" % it)
+
+
 def test_error_paths():
     ce = _ce()
     dev = torch.device("cuda:0")
