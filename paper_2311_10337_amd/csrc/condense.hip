@@ -702,13 +702,14 @@ __global__ __launch_bounds__(B) void k_top_jump(const uint32_t *act, int64_t nac
   tile_append(keep, vals, next, nnext);
 }
 
+// every record's exit cluster row; the smallest input id under each label
 __global__ __launch_bounds__(B) void k_lab_rows(const uint32_t *exc, const uint32_t *rowof, const uint32_t *rootrow,
                                                 const uint32_t *top, const uint32_t *cprow, const uint32_t *perm,
-                                                int64_t m, int64_t n, uint32_t *labrow, uint32_t *minmem) {
+                                                int64_t m, int64_t n, uint32_t *prow, uint32_t *minmem) {
   for (int64_t p = (int64_t)blockIdx.x * B + threadIdx.x; p < n; p += (int64_t)gridDim.x * B) {
     uint32_t r = row_of(exc[p], n, m, rowof, rootrow);
     uint32_t lr = cprow[r] == NONE32 ? NONE32 : top[r];
-    labrow[p] = lr;
+    prow[p] = r;
     if (lr != NONE32) atomicMin(&minmem[lr], perm[p]);
   }
 }
@@ -728,19 +729,14 @@ __device__ inline uint32_t local_node(uint32_t x, uint32_t g, int64_t n, int64_t
   return ng + (rowpos[x - n] - moff[g]);
 }
 
-__global__ __launch_bounds__(B) void k_out_points(const uint32_t *perm, const uint32_t *grank, const uint32_t *exc,
-                                                  const uint64_t *exl, const uint32_t *labrow, const uint32_t *minmem,
-                                                  const uint32_t *fscan, const int64_t *eoff, const uint32_t *moff,
-                                                  const uint32_t *rowpos, int64_t n, int64_t m, uint32_t *pt_cluster,
-                                                  uint64_t *pt_lambda, int32_t *labels) {
+__global__ __launch_bounds__(B) void k_out_points(const uint32_t *perm, const uint32_t *prow, const uint64_t *exl,
+                                                  const uint32_t *rlocal, const int32_t *rlab, int64_t n,
+                                                  uint32_t *pt_cluster, uint64_t *pt_lambda, int32_t *labels) {
   for (int64_t p = (int64_t)blockIdx.x * B + threadIdx.x; p < n; p += (int64_t)gridDim.x * B) {
-    const uint32_t id = perm[p], g = grank[p];
-    if (pt_cluster) pt_cluster[id] = local_node(exc[p], g, n, m, eoff, moff, rowpos);
+    const uint32_t id = perm[p], r = prow[p];
+    if (pt_cluster) pt_cluster[id] = rlocal[r];
     if (pt_lambda) pt_lambda[id] = exl[p];
-    if (labels) {
-      uint32_t lr = labrow[p];
-      labels[id] = lr == NONE32 ? -1 : (int32_t)(fscan[minmem[lr]] - fscan[eoff[g]]);
-    }
+    if (labels) labels[id] = rlab[r];
   }
 }
 
@@ -776,6 +772,24 @@ __global__ __launch_bounds__(B) void k_out_discrete(const uint32_t *level, const
 }
 
 // labels per graph: the chosen clusters whose minimum member lies in g
+// what a record exiting at cluster row r reports: the row's node in its
+// graph's local ids, and the label of its selected ancestor (-1 if none)
+__global__ __launch_bounds__(B) void k_row_point_vals(const uint32_t *cnode, const uint32_t *cprow,
+                                                      const uint32_t *top, const uint32_t *minmem,
+                                                      const uint32_t *fscan, const uint32_t *rowg,
+                                                      const int64_t *eoff, const uint32_t *moff,
+                                                      const uint32_t *rowpos, int64_t n, int64_t m, uint32_t nrows,
+                                                      uint32_t *rlocal, int32_t *rlab) {
+  for (int64_t r = (int64_t)blockIdx.x * B + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * B) {
+    const uint32_t c = cnode[r];
+    const uint32_t g = c >= (uint64_t)(n + m) ? (uint32_t)(c - n - m) : rowg[c - n];
+    rlocal[r] = local_node(c, g, n, m, eoff, moff, rowpos);
+    const uint32_t lr = cprow[r] == NONE32 ? NONE32 : top[r];
+    const uint32_t mm = lr == NONE32 ? NONE32 : minmem[lr];
+    rlab[r] = mm == NONE32 ? -1 : (int32_t)(fscan[mm] - fscan[eoff[g]]);
+  }
+}
+
 __global__ __launch_bounds__(B) void k_graph_labels(const uint32_t *fscan, const int64_t *eoff, int64_t G,
                                                     uint32_t *nl) {
   for (int64_t g = (int64_t)blockIdx.x * B + threadIdx.x; g < G; g += (int64_t)gridDim.x * B)
@@ -1066,8 +1080,13 @@ ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipSt
   CE_LAUNCH(k_lab_flags, dim3(gR), dim3(B), 0, s, top, minmem, nrows, fl);
   CE_HIP(hipGetLastError());
   CE_TRY(scan_exclusive_u32(fl, fl, n, ws, s));
-  CE_LAUNCH(k_out_points, dim3(grid_for(n, B)), dim3(B), 0, s, b.perm, b.grank, exc, exl, labrow, minmem, fl, b.eoff,
-            b.moff, b.rowpos, n, m, out->pt_cluster, out->pt_lambda, out->labels);
+  // per cluster row first (small arrays), then every record reads its row's values
+  uint32_t *rlocal = nxt;
+  int32_t *rlab = (int32_t *)nxt2;
+  CE_LAUNCH(k_row_point_vals, dim3(gR), dim3(B), 0, s, cnode, cprow, top, minmem, fl, b.rowg, b.eoff, b.moff,
+            b.rowpos, n, m, nrows, rlocal, rlab);
+  CE_LAUNCH(k_out_points, dim3(grid_for(n, B)), dim3(B), 0, s, b.perm, labrow, exl, rlocal, rlab, n,
+            out->pt_cluster, out->pt_lambda, out->labels);
   CE_LAUNCH(k_out_clusters, dim3(gR), dim3(B), 0, s, cnode, cprow, csize, cbirth, shi, slo, top, b.rowg, b.eoff,
             b.moff, b.rowpos, n, m, nrows, *out);
   CE_LAUNCH(k_graph_labels, dim3(gG), dim3(B), 0, s, fl, b.eoff, G, nlab);
