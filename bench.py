@@ -269,7 +269,7 @@ def main():
                     help="skip the dynamic-hypergraph measurement (2e7 multi-recipient messages)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-vs-one-graph-per-call measurement on the 4096-graph batch")
-    ap.add_argument("--roofline-kernel", default="k_krt_accum",
+    ap.add_argument("--roofline-kernel", default="k_krt_union",
                     help="dominant kernel: its launches are timed with HIP events on its stream for the roofline")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="before the steps, copy a buffer of this many bytes once (a plain copy kernel of known "

@@ -39,6 +39,10 @@ def algorithmic_bytes_per_step(kernel: str, n: int, m: int, level_bits: int = 6)
         # per row and global level: hooked root id (4), its size (4), the parent of that root (4),
         # the row id it offers (4); the per-root atomics are combined in LDS
         return ("MSF row x global level", 16, dendrogram_levels(m, level_bits=level_bits) * m)
+    if kernel == "k_krt_union":
+        # per row and global level: two labels read (8), the two root entries read (2 x 16), the new labels
+        # and sizes written (16), one 8-byte CAS (8), the hooked root written (4)
+        return ("MSF row x global level", 68, dendrogram_levels(m, level_bits=level_bits) * m)
     if kernel == "k_krt_relabel":
         # per row and level: two labels (8) read and rewritten (8), two sizes rewritten (8), two roots
         # written (8), two root entries read (2 x 12)
@@ -48,8 +52,11 @@ def algorithmic_bytes_per_step(kernel: str, n: int, m: int, level_bits: int = 6)
     raise KeyError(kernel)
 
 
-def source_hash(files=("csrc/dendrogram.hip", "csrc/pipeline.hip", "csrc/condense.hip", "csrc/primitives.hip",
-                       "csrc/ce_internal.h", "csrc/causal.hip", "csrc/api.hip")) -> str:
+def source_hash(files=None) -> str:
+    """Hash of every kernel source under csrc/ (sorted by name)."""
+    if files is None:
+        files = sorted(os.path.relpath(f, HERE) for f in glob.glob(os.path.join(HERE, "csrc", "*"))
+                       if f.endswith((".hip", ".h")))
     h = hashlib.sha256()
     for f in files:
         with open(os.path.join(HERE, f), "rb") as fh:
