@@ -343,7 +343,11 @@ def main():
         ce.timing_enable(None)
         log("kernel %s: %d launches, %.3f ms total, %.1f us avg" % (args.roofline_kernel, kcnt, kms,
                                                                   1e3 * kms / max(kcnt, 1)))
-        unit, per_unit, units = profiling.algorithmic_bytes_per_step(args.roofline_kernel, w.n, r.m)
+        try:
+            unit, per_unit, units = profiling.algorithmic_bytes_per_step(args.roofline_kernel, w.n, r.m)
+        except KeyError:
+            log("no algorithmic model for %s: roofline left out" % args.roofline_kernel)
+            unit, per_unit, units = None, None, None
         if kcnt and units:
             per_launch = per_unit * units * args.steps / kcnt
             achieved = per_launch / (kms / kcnt * 1e-3) / 1e9

@@ -207,6 +207,7 @@ __global__ __launch_bounds__(B) void k_krt_accum(int64_t m, int lo, int hi, uint
 constexpr int LS_BITS = 9;
 constexpr int LS = 1 << LS_BITS;  // rows per workgroup
 constexpr int HS = 4 * LS;        // hash slots (load factor <= 1/2)
+constexpr int LB = 512;           // threads per interval: one per row
 constexpr uint32_t EMPTY = 0xffffffffu;
 
 __device__ inline uint32_t l_find(volatile uint32_t *uf, uint32_t x) {
@@ -232,7 +233,7 @@ __device__ inline uint32_t l_union(volatile uint32_t *uf, uint32_t a, uint32_t b
 
 __device__ inline uint32_t hslot(uint32_t g) { return (g * 2654435761u) >> (32 - (LS_BITS + 2)); }
 
-__global__ __launch_bounds__(B) void k_krt_lds(const uint32_t *lu, const uint32_t *lv, const uint32_t *su,
+__global__ __launch_bounds__(LB) void k_krt_lds(const uint32_t *lu, const uint32_t *lv, const uint32_t *su,
                                                const uint32_t *sv, int64_t m, int64_t n, uint32_t *kc_u,
                                                uint32_t *kc_v, uint32_t *ksize) {
   __shared__ uint32_t hkey[HS];
@@ -247,11 +248,11 @@ __global__ __launch_bounds__(B) void k_krt_lds(const uint32_t *lu, const uint32_
   const int tid = threadIdx.x;
   const int64_t base = (int64_t)blockIdx.x * LS;
   const int cnt = (int)((m - base) < LS ? (m - base) : LS);
-  for (int i = tid; i < HS; i += B) hkey[i] = EMPTY;
+  for (int i = tid; i < HS; i += LB) hkey[i] = EMPTY;
   if (tid == 0) nloc = 0;
   __syncthreads();
   // 1. distinct labels of this interval into an LDS hash set
-  for (int i = tid; i < 2 * cnt; i += B) {
+  for (int i = tid; i < 2 * cnt; i += LB) {
     uint32_t g = (i & 1) ? lv[base + (i >> 1)] : lu[base + (i >> 1)];
     uint32_t s = hslot(g);
     while (true) {
@@ -262,7 +263,7 @@ __global__ __launch_bounds__(B) void k_krt_lds(const uint32_t *lu, const uint32_
   }
   __syncthreads();
   // 2. local ids for the distinct labels
-  for (int s = tid; s < HS; s += B) {
+  for (int s = tid; s < HS; s += LB) {
     uint32_t g = hkey[s];
     if (g != EMPTY) {
       uint32_t id = atomicAdd(&nloc, 1u);
@@ -272,7 +273,7 @@ __global__ __launch_bounds__(B) void k_krt_lds(const uint32_t *lu, const uint32_
   }
   __syncthreads();
   // 3. rows' labels as local ids, with sizes
-  for (int i = tid; i < 2 * cnt; i += B) {
+  for (int i = tid; i < 2 * cnt; i += LB) {
     const bool isv = i & 1;
     const int r = i >> 1;
     uint32_t g = isv ? lv[base + r] : lu[base + r];
@@ -286,17 +287,17 @@ __global__ __launch_bounds__(B) void k_krt_lds(const uint32_t *lu, const uint32_
   volatile uint32_t *vuf = luf;
   // 4. binary levels inside the interval
   for (int bit = LS_BITS - 1; bit >= 0; bit--) {
-    for (int i = tid; i < cnt; i += B) {
+    for (int i = tid; i < cnt; i += LB) {
       uint32_t a = elu[i], b = elv[i];
       luf[a] = a; luf[b] = b;
       lmx[a] = 0; lmx[b] = 0;
       lcs[a] = lsz[a]; lcs[b] = lsz[b];
     }
     __syncthreads();
-    for (int i = tid; i < cnt; i += B)
+    for (int i = tid; i < cnt; i += LB)
       if (!((i >> bit) & 1)) ehk[i] = (uint16_t)l_union(vuf, elu[i], elv[i]);
     __syncthreads();
-    for (int i = tid; i < cnt; i += B) {
+    for (int i = tid; i < cnt; i += LB) {
       if ((i >> bit) & 1) continue;
       uint32_t h = ehk[i];
       if (h == 0xffffu) continue;
@@ -305,7 +306,7 @@ __global__ __launch_bounds__(B) void k_krt_lds(const uint32_t *lu, const uint32_
       atomicMax(&lmx[f], (uint32_t)(i + 1));
     }
     __syncthreads();
-    for (int i = tid; i < cnt; i += B) {
+    for (int i = tid; i < cnt; i += LB) {
       if (!((i >> bit) & 1)) continue;
       uint32_t f = l_find(vuf, elu[i]);
       if (lmx[f]) {
@@ -323,7 +324,7 @@ __global__ __launch_bounds__(B) void k_krt_lds(const uint32_t *lu, const uint32_
     __syncthreads();
   }
   // 5. children as internal labels (record rank < n, or n + row)
-  for (int i = tid; i < cnt; i += B) {
+  for (int i = tid; i < cnt; i += LB) {
     uint32_t a = elu[i], b = elv[i];
     uint32_t ga = a < 2 * LS ? glab[a] : (uint32_t)(n + base + (a - 2 * LS));
     uint32_t gb = b < 2 * LS ? glab[b] : (uint32_t)(n + base + (b - 2 * LS));
@@ -389,7 +390,7 @@ ce_status stage_dendrogram(Bufs &b, int64_t m, Ws &ws, hipStream_t s) {
     hi = lo - 1;
   }
   const int64_t nblk = (m + LS - 1) / LS;
-  CE_LAUNCH(k_krt_lds, dim3((unsigned)nblk), dim3(B), 0, s, lu, lv, su, sv, m, n, b.kc_u, b.kc_v, b.ksize);
+  CE_LAUNCH(k_krt_lds, dim3((unsigned)nblk), dim3(LB), 0, s, lu, lv, su, sv, m, n, b.kc_u, b.kc_v, b.ksize);
   CE_HIP(hipGetLastError());
   ws.release(m0);
   return CE_OK;

@@ -47,6 +47,9 @@ def algorithmic_bytes_per_step(kernel: str, n: int, m: int, level_bits: int = 6)
         # per row and level: two labels (8) read and rewritten (8), two sizes rewritten (8), two roots
         # written (8), two root entries read (2 x 12)
         return ("MSF row x global level", 56, dendrogram_levels(m, level_bits=level_bits) * m)
+    if kernel == "k_krt_lds":
+        # per row: two labels and two sizes read (16), two children and the size written (12)
+        return ("MSF row", 28, m)
     if kernel == "k_rs_scatter":
         return ("element x pass (u64 key + u64 value)", 32, None)
     raise KeyError(kernel)
