@@ -261,9 +261,17 @@ __global__ __launch_bounds__(B) void k_root_flags(int64_t C, const uint32_t *hoo
     flags[c] = (hook[c] == (uint32_t)c && best[c] != NONE64) ? 1u : 0u;
 }
 
+// the dense id of every component's final root (one gather per component, so
+// contraction reads one id per endpoint instead of a root and then its id)
+__global__ __launch_bounds__(B) void k_final_ids(int64_t C, const uint32_t *hook, const uint32_t *newid,
+                                                 uint32_t *fin) {
+  for (int64_t c = (int64_t)blockIdx.x * B + threadIdx.x; c < C; c += (int64_t)gridDim.x * B)
+    fin[c] = newid[hook[c]];
+}
+
 // contract: live edges between different final roots, endpoints renamed to dense ids
 __global__ __launch_bounds__(B) void k_contract_first(int64_t n2, const uint64_t *skel_key, const uint32_t *skel_tail,
-                                                      const uint32_t *hook, const uint32_t *newid, uint64_t *okey,
+                                                      const uint32_t *fin, uint64_t *okey,
                                                       uint32_t *ou, uint32_t *ov, uint32_t *oslot,
                                                       unsigned long long *cnt) {
   bool keep[CT];
@@ -279,11 +287,11 @@ __global__ __launch_bounds__(B) void k_contract_first(int64_t n2, const uint64_t
     if (e >= n2) continue;
     kk[k] = skel_key[e];
     if (kk[k] == NONE64) continue;
-    const uint32_t ru = hook[skel_tail[e]], rv = hook[e >> 1];
-    if (ru == rv) continue;
+    const uint32_t fu = fin[skel_tail[e]], fv = fin[e >> 1];
+    if (fu == fv) continue;
     keep[k] = true;
-    nu[k] = newid[ru];
-    nv[k] = newid[rv];
+    nu[k] = fu;
+    nv[k] = fv;
   }
   tile_positions(keep, pos, cnt);
 #pragma unroll
@@ -298,7 +306,7 @@ __global__ __launch_bounds__(B) void k_contract_first(int64_t n2, const uint64_t
 }
 
 __global__ __launch_bounds__(B) void k_contract(int64_t E, const uint64_t *key, const uint32_t *eu, const uint32_t *ev,
-                                                const uint32_t *eslot, const uint32_t *hook, const uint32_t *newid,
+                                                const uint32_t *eslot, const uint32_t *fin,
                                                 uint64_t *okey, uint32_t *ou, uint32_t *ov, uint32_t *oslot,
                                                 unsigned long long *cnt) {
   bool keep[CT];
@@ -310,11 +318,11 @@ __global__ __launch_bounds__(B) void k_contract(int64_t E, const uint64_t *key, 
     keep[k] = false;
     nu[k] = nv[k] = 0;
     if (i >= E) continue;
-    const uint32_t ru = hook[eu[i]], rv = hook[ev[i]];
-    if (ru == rv) continue;
+    const uint32_t fu = fin[eu[i]], fv = fin[ev[i]];
+    if (fu == fv) continue;
     keep[k] = true;
-    nu[k] = newid[ru];
-    nv[k] = newid[rv];
+    nu[k] = fu;
+    nv[k] = fv;
   }
   tile_positions(keep, pos, cnt);
 #pragma unroll
@@ -631,8 +639,9 @@ ce_status stage_boruvka(Bufs &b, Ws &ws, hipStream_t s) {
     CE_LAUNCH(k_root_flags, dim3(grid_for(n, B)), dim3(B), 0, s, n, hook, best, flags);
     CE_HIP(hipGetLastError());
     CE_TRY(scan_exclusive_u32(flags, newid, n, ws, s));
+    CE_LAUNCH(k_final_ids, dim3(grid_for(n, B)), dim3(B), 0, s, n, hook, newid, flags);
     CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[4], (uint64_t)0);
-    CE_LAUNCH(k_contract_first, dim3(tiles_for(n2)), dim3(B), 0, s, n2, b.skel_key, b.skel_tail, hook, newid,
+    CE_LAUNCH(k_contract_first, dim3(tiles_for(n2)), dim3(B), 0, s, n2, b.skel_key, b.skel_tail, flags,
               key[0], eu[0], ev[0], es[0], cnt);
     CE_HIP(hipGetLastError());
     {
@@ -667,8 +676,9 @@ ce_status stage_boruvka(Bufs &b, Ws &ws, hipStream_t s) {
     CE_LAUNCH(k_root_flags, dim3(grid_for(C, B)), dim3(B), 0, s, C, hook, best, flags);
     CE_HIP(hipGetLastError());
     CE_TRY(scan_exclusive_u32(flags, newid, C, ws, s));
+    CE_LAUNCH(k_final_ids, dim3(grid_for(C, B)), dim3(B), 0, s, C, hook, newid, flags);
     CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[4], (uint64_t)0);
-    CE_LAUNCH(k_contract, dim3(tiles_for(E)), dim3(B), 0, s, E, key[cur], eu[cur], ev[cur], es[cur], hook, newid,
+    CE_LAUNCH(k_contract, dim3(tiles_for(E)), dim3(B), 0, s, E, key[cur], eu[cur], ev[cur], es[cur], flags,
               key[1 - cur], eu[1 - cur], ev[1 - cur], es[1 - cur], cnt);
     CE_HIP(hipGetLastError());
     {
