@@ -201,6 +201,10 @@ __device__ inline uint64_t wave_min_u64(uint64_t v) {
 // exclusive scan over the (k, wave) counts, then popcount ranks within the
 // wave. Call from all threads of the block.
 constexpr int CT = 16;
+// Linear probes an LDS aggregation hash tries before a key goes straight to
+// its global atomic: hot keys enter the table early, and a tile with many
+// distinct keys should not pay a long probe sequence per element.
+constexpr int HASH_PROBES = 4;
 // Output positions for the kept elements of a tile (order as described
 // above); pos[k] is valid where keep[k]. One atomic on `counter` per tile.
 __device__ inline void tile_positions(const bool (&keep)[CT], uint32_t (&pos)[CT], unsigned long long *counter) {

@@ -347,7 +347,7 @@ __global__ __launch_bounds__(B) void k_cd_acc_points(const uint32_t *exc, const 
     if (upd) {
       uint32_t sl = (r * 2654435761u) >> 23;  // 9 bits
       bool placed = false;
-      for (int probe = 0; probe < 16 && !placed; probe++) {
+      for (int probe = 0; probe < HASH_PROBES && !placed; probe++) {
         uint32_t old = atomicCAS(&hk[sl], NONE32, r);
         if (old == NONE32 || old == r) {
           atomicAdd(&h0[sl], (unsigned long long)s0);
@@ -427,7 +427,7 @@ __global__ __launch_bounds__(B) void k_cd_exit_down_acc(const uint32_t *kc_u, co
     if (upd) {
       uint32_t sl = (r * 2654435761u) >> 23;  // 9 bits
       bool placed = false;
-      for (int probe = 0; probe < 16 && !placed; probe++) {
+      for (int probe = 0; probe < HASH_PROBES && !placed; probe++) {
         uint32_t old = atomicCAS(&hk[sl], NONE32, r);
         if (old == NONE32 || old == r) {
           atomicAdd(&h0[sl], (unsigned long long)s0);

@@ -178,7 +178,7 @@ __global__ __launch_bounds__(B) void k_krt_accum(int64_t m, int lo, int hi, uint
     if (upd) {
       uint32_t sl = (f * 2654435761u) >> 24;  // 8 bits
       bool placed = false;
-      for (int probe = 0; probe < 16 && !placed; probe++) {
+      for (int probe = 0; probe < HASH_PROBES && !placed; probe++) {
         uint32_t old = atomicCAS(&hk[sl], NONE32, f);
         if (old == NONE32 || old == f) {
           atomicAdd(&hs[sl], add);

@@ -364,7 +364,7 @@ __global__ __launch_bounds__(B) void k_bv_min(int64_t E, const uint64_t *key, co
       if (upd) {
         uint32_t sl = (c * 2654435761u) >> 23;  // 9 bits
         bool placed = false;
-        for (int probe = 0; probe < 16 && !placed; probe++) {
+        for (int probe = 0; probe < HASH_PROBES && !placed; probe++) {
           uint32_t old = atomicCAS(&hk[sl], NONE32, c);
           if (old == NONE32 || old == c) {
             if (kmin < hv[sl]) atomicMin(&hv[sl], kmin);
