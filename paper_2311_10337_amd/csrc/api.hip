@@ -201,6 +201,7 @@ static void layout(Bufs &b, Ws &ws, int64_t n, int64_t M, int64_t G, bool discre
   b.voff = ws.alloc<int64_t>(G + 1);
   b.perm = ws.alloc<uint32_t>(n);
   b.grank = ws.alloc<uint32_t>(n);
+  b.rankof = ws.alloc<uint32_t>(n);
   const size_t base = ws.off;
   b.ts = ws.alloc<uint64_t>(n);
   b.skel_key = ws.alloc<uint64_t>(slots);

@@ -298,6 +298,7 @@ struct Bufs {
   uint64_t *hdr = nullptr;      // [16] device header / counters
   uint64_t *ts = nullptr;       // [n] t - tmin by rank
   uint32_t *perm = nullptr;     // [n] rank -> input id
+  uint32_t *rankof = nullptr;   // [n] input id -> rank (from the MSF stage on)
   uint64_t *skel_key = nullptr; // [slots] slot 2h+s: key of the skeleton edge whose head is rank h
   uint32_t *skel_tail = nullptr;// [slots] tail rank of that edge or NONE
   uint32_t *skel_tid = nullptr; // [slots] input id of that tail (flat: the head rank)

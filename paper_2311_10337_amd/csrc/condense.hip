@@ -729,11 +729,12 @@ __device__ inline uint32_t local_node(uint32_t x, uint32_t g, int64_t n, int64_t
   return ng + (rowpos[x - n] - moff[g]);
 }
 
-__global__ __launch_bounds__(B) void k_out_points(const uint32_t *perm, const uint32_t *prow, const uint64_t *exl,
+// per record, in input order (gathers by rank, so the writes are coalesced)
+__global__ __launch_bounds__(B) void k_out_points(const uint32_t *rankof, const uint32_t *prow, const uint64_t *exl,
                                                   const uint32_t *rlocal, const int32_t *rlab, int64_t n,
                                                   uint32_t *pt_cluster, uint64_t *pt_lambda, int32_t *labels) {
-  for (int64_t p = (int64_t)blockIdx.x * B + threadIdx.x; p < n; p += (int64_t)gridDim.x * B) {
-    const uint32_t id = perm[p], r = prow[p];
+  for (int64_t id = (int64_t)blockIdx.x * B + threadIdx.x; id < n; id += (int64_t)gridDim.x * B) {
+    const uint32_t p = rankof[id], r = prow[p];
     if (pt_cluster) pt_cluster[id] = rlocal[r];
     if (pt_lambda) pt_lambda[id] = exl[p];
     if (labels) labels[id] = rlab[r];
@@ -1085,7 +1086,7 @@ ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipSt
   int32_t *rlab = (int32_t *)nxt2;
   CE_LAUNCH(k_row_point_vals, dim3(gR), dim3(B), 0, s, cnode, cprow, top, minmem, fl, b.rowg, b.eoff, b.moff,
             b.rowpos, n, m, nrows, rlocal, rlab);
-  CE_LAUNCH(k_out_points, dim3(grid_for(n, B)), dim3(B), 0, s, b.perm, labrow, exl, rlocal, rlab, n,
+  CE_LAUNCH(k_out_points, dim3(grid_for(n, B)), dim3(B), 0, s, b.rankof, labrow, exl, rlocal, rlab, n,
             out->pt_cluster, out->pt_lambda, out->labels);
   CE_LAUNCH(k_out_clusters, dim3(gR), dim3(B), 0, s, cnode, cprow, csize, cbirth, shi, slo, top, b.rowg, b.eoff,
             b.moff, b.rowpos, n, m, nrows, *out);

@@ -557,7 +557,6 @@ ce_status stage_sort_skeleton(const int32_t *src, const int32_t *dst, const int6
 
 size_t stage_boruvka_scratch(int64_t n, int64_t slots) {
   Ws w;
-  w.alloc<uint32_t>(n);      // rankof
   w.alloc<uint32_t>(n);      // hook
   w.alloc<uint32_t>(n);      // bidx
   w.alloc<uint32_t>(n + 1);  // root flags
@@ -595,7 +594,6 @@ static ce_status jump_all(uint32_t *&act, uint32_t *&act2, uint64_t nact, uint32
 ce_status stage_boruvka(Bufs &b, Ws &ws, hipStream_t s) {
   const int64_t n = b.n, n2 = b.slots;
   size_t m0 = ws.mark();
-  uint32_t *rankof = ws.alloc<uint32_t>(n);
   uint32_t *hook = ws.alloc<uint32_t>(n);
   uint32_t *bidx = ws.alloc<uint32_t>(n);
   uint32_t *flags = ws.alloc<uint32_t>(n + 1);
@@ -611,6 +609,8 @@ ce_status stage_boruvka(Bufs &b, Ws &ws, hipStream_t s) {
     es[k] = ws.alloc<uint32_t>(n2);
   }
   CE_WS_CHECK(ws);
+  uint32_t *rankof = b.rankof;  // kept for writing the per-record outputs in input order
+  CE_LAUNCH(k_rankof, dim3(grid_for(n, B)), dim3(B), 0, s, b.perm, n, rankof);
   uint64_t *best = b.best;  // seeded for round 1 while emitting the skeleton
   unsigned long long *cnt = (unsigned long long *)&b.hdr[4];
   CE_LAUNCH(k_fill_u8, dim3(grid_for(n2, B)), dim3(B), 0, s, b.msf_flag, n2, (uint8_t)0);
@@ -628,7 +628,6 @@ ce_status stage_boruvka(Bufs &b, Ws &ws, hipStream_t s) {
     E = b.S;
     C = n;
   } else {
-    CE_LAUNCH(k_rankof, dim3(grid_for(n, B)), dim3(B), 0, s, b.perm, n, rankof);
     // round 1 on records
     CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[4], (uint64_t)0);
     CE_LAUNCH(k_bv_hook_first, dim3(tiles_for(n)), dim3(B), 0, s, n, best, b.skel_key, b.skel_tail, rankof,
