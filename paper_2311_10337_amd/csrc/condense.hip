@@ -199,38 +199,6 @@ __global__ __launch_bounds__(B) void k_cd_jstep(const uint32_t *act, int64_t nac
   tile_append(keep, vals, out, nout);
 }
 
-// exit of each record: lowest big ancestor y -> (cluster of y, lambda(w_y))
-__global__ __launch_bounds__(B) void k_cd_exit(const uint32_t *kpar, const uint32_t *ksize, const uint32_t *J,
-                                               const uint64_t *rowL, const uint32_t *grank, int64_t m,
-                                               int64_t n, int64_t M, uint32_t *exc, uint64_t *exl) {
-  for (int64_t p = (int64_t)blockIdx.x * B + threadIdx.x; p < n; p += (int64_t)gridDim.x * B) {
-    uint32_t y = kpar[p];
-    while (y != NONE32 && ksize[y - n] < (uint64_t)M) y = kpar[y];
-    if (y == NONE32) {
-      exc[p] = (uint32_t)(n + m + grank[p]);
-      exl[p] = 0;
-    } else {
-      exc[p] = J[y - n];
-      exl[p] = rowL[y - n];
-    }
-  }
-}
-
-// Top-down exits (k_cd_exit_down_acc below): a small child c of a big row j
-// sheds every record under it at (cluster of j, lambda(w_j)); a DFS over c's
-// subtree (fewer than M leaves, so fewer than 2M nodes and height < M) visits
-// each node once. Records outside such subtrees keep the default exit (ROOT, 0).
-constexpr int EXIT_STACK = 64;
-
-// default exit: the record's graph root at lambda 0
-__global__ __launch_bounds__(B) void k_exit_default(const uint32_t *grank, int64_t n, int64_t m, uint32_t *exc,
-                                                    uint64_t *exl) {
-  for (int64_t p = (int64_t)blockIdx.x * B + threadIdx.x; p < n; p += (int64_t)gridDim.x * B) {
-    exc[p] = (uint32_t)(n + m + grank[p]);
-    exl[p] = 0;
-  }
-}
-
 __global__ __launch_bounds__(B) void k_u8_to_u32(const uint8_t *a, int64_t n, uint32_t *o) {
   for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < n; i += (int64_t)gridDim.x * B) o[i] = a[i];
 }
@@ -319,69 +287,16 @@ __device__ inline void wave_add_limbs(bool active, uint32_t row, uint64_t l0, ui
   }
 }
 
-// Per-tile aggregation: lanes with equal rows combine first, then one LDS
-// hash slot per row and tile (one global atomic per row per 4096 records); a
-// row that finds no free slot adds directly.
-constexpr int AHS = 512;
-__global__ __launch_bounds__(B) void k_cd_acc_points(const uint32_t *exc, const uint64_t *exl, const uint32_t *rowof,
-                                                     int64_t m, int64_t n, const uint32_t *rootrow,
-                                                     unsigned long long *acc) {
-  __shared__ uint32_t hk[AHS];
-  __shared__ unsigned long long h0[AHS], h1[AHS];
-  for (int i = threadIdx.x; i < AHS; i += B) { hk[i] = NONE32; h0[i] = 0; h1[i] = 0; }
-  __syncthreads();
-  const int64_t tbase = (int64_t)blockIdx.x * (B * CT);
-  for (int k = 0; k < CT; k++) {
-    const int64_t p = tbase + (int64_t)k * B + threadIdx.x;
-    uint64_t L = 0;
-    uint32_t r = 0;
-    if (p < n) {
-      L = exl[p];
-      if (L) r = row_of(exc[p], n, m, rowof, rootrow);
-    }
-    uint64_t s0 = L & 0xffffffffull, s1 = L >> 32;
-    const bool upd = wave_combine_first(L != 0, r, [&](bool mine, int leader) {
-      const uint64_t a0 = wave_sum_u64(mine ? s0 : 0ull), a1 = wave_sum_u64(mine ? s1 : 0ull);
-      if ((int)wave_lane() == leader) { s0 = a0; s1 = a1; }
-    });
-    if (upd) {
-      uint32_t sl = (r * 2654435761u) >> 23;  // 9 bits
-      bool placed = false;
-      for (int probe = 0; probe < HASH_PROBES && !placed; probe++) {
-        uint32_t old = atomicCAS(&hk[sl], NONE32, r);
-        if (old == NONE32 || old == r) {
-          atomicAdd(&h0[sl], (unsigned long long)s0);
-          atomicAdd(&h1[sl], (unsigned long long)s1);
-          placed = true;
-        } else {
-          sl = (sl + 1) & (AHS - 1);
-        }
-      }
-      if (!placed) {
-        atomicAdd(&acc[3 * (uint64_t)r], (unsigned long long)s0);
-        atomicAdd(&acc[3 * (uint64_t)r + 1], (unsigned long long)s1);
-      }
-    }
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < AHS; i += B) {
-    uint32_t r = hk[i];
-    if (r == NONE32) continue;
-    if (h0[i]) atomicAdd(&acc[3 * (uint64_t)r], h0[i]);
-    if (h1[i]) atomicAdd(&acc[3 * (uint64_t)r + 1], h1[i]);
-  }
-}
+constexpr int AHS = 512;  // LDS hash slots for per-cluster-row sums
 
-// Exits of the records under the small children of big rows (as
-// k_cd_exit_down) together with the point term of each cluster's stability:
-// the records of small child c all leave the cluster of row j at lambda_j, so
-// they add size(c) * lambda_j, summed per cluster row in an LDS hash and then
-// one atomic per limb, row and tile. Runs once the cluster rows are known.
-__global__ __launch_bounds__(B) void k_cd_exit_down_acc(const uint32_t *kc_u, const uint32_t *kc_v,
-                                                        const uint32_t *ksize, const uint32_t *J,
-                                                        const uint64_t *rowL, const uint32_t *rowof,
-                                                        const uint32_t *rootrow, int64_t m, int64_t n, int64_t M,
-                                                        uint32_t *exc, uint64_t *exl, unsigned long long *acc) {
+// Point term of each cluster's stability: the records of a small child c of
+// a big row j all leave the cluster of j at lambda_j, so they add size(c) *
+// lambda_j; summed per cluster row in an LDS hash, then one atomic per limb,
+// row and tile.
+__global__ __launch_bounds__(B) void k_cd_point_terms(const uint32_t *kc_u, const uint32_t *kc_v,
+                                                      const uint32_t *ksize, const uint32_t *J, const uint64_t *rowL,
+                                                      const uint32_t *rowof, const uint32_t *rootrow, int64_t m,
+                                                      int64_t n, int64_t M, unsigned long long *acc) {
   __shared__ uint32_t hk[AHS];
   __shared__ unsigned long long h0[AHS], h1[AHS], h2[AHS];
   for (int i = threadIdx.x; i < AHS; i += B) { hk[i] = NONE32; h0[i] = 0; h1[i] = 0; h2[i] = 0; }
@@ -392,29 +307,10 @@ __global__ __launch_bounds__(B) void k_cd_exit_down_acc(const uint32_t *kc_u, co
     uint32_t cnt = 0, r = 0;
     uint64_t L = 0;
     if (j < m && ksize[j] >= (uint64_t)M) {
-      const uint32_t C = J[j];
       L = rowL[j];
-#pragma unroll
-      for (int side = 0; side < 2; side++) {
-        const uint32_t c = side ? kc_v[j] : kc_u[j];
-        const uint32_t sz = node_size(c, n, ksize);
-        if (sz >= (uint64_t)M) continue;
-        cnt += sz;
-        uint32_t stack[EXIT_STACK];
-        int sp = 0;
-        stack[sp++] = c;
-        while (sp > 0) {
-          const uint32_t x = stack[--sp];
-          if (x < (uint64_t)n) {
-            exc[x] = C;
-            exl[x] = L;
-          } else {
-            stack[sp++] = kc_u[x - n];
-            stack[sp++] = kc_v[x - n];
-          }
-        }
-      }
-      if (cnt && L) r = row_of(C, n, m, rowof, rootrow);
+      const uint32_t su = node_size(kc_u[j], n, ksize), sv = node_size(kc_v[j], n, ksize);
+      cnt = (su < (uint64_t)M ? su : 0u) + (sv < (uint64_t)M ? sv : 0u);
+      if (cnt && L) r = row_of(J[j], n, m, rowof, rootrow);
     }
     const bool act = cnt != 0 && L != 0;
     const u128 prod = u128_mul64(cnt, L);
@@ -452,6 +348,44 @@ __global__ __launch_bounds__(B) void k_cd_exit_down_acc(const uint32_t *kc_u, co
     if (h0[i]) atomicAdd(&acc[3 * (uint64_t)r], h0[i]);
     if (h1[i]) atomicAdd(&acc[3 * (uint64_t)r + 1], h1[i]);
     if (h2[i]) atomicAdd(&acc[3 * (uint64_t)r + 2], h2[i]);
+  }
+}
+
+// One 8-byte word per row for the exit walk: (parent node, size) for a small
+// row, (cluster row of its cluster, size) for a big one.
+__global__ __launch_bounds__(B) void k_cd_walk_words(const uint32_t *kpar, const uint32_t *ksize, const uint32_t *J,
+                                                     const uint32_t *rowof, const uint32_t *rootrow, int64_t n,
+                                                     int64_t m, int64_t M, uint2 *wk) {
+  for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
+    const uint32_t sz = ksize[j];
+    wk[j] = make_uint2(sz < (uint64_t)M ? kpar[n + j] : row_of(J[j], n, m, rowof, rootrow), sz);
+  }
+}
+
+// Exit of every record, in input order: from its leaf, up through the small
+// subtrees (fewer than M records, so fewer than M steps) to the first big
+// row y; it leaves the cluster of y at lambda_y, or its graph's root at 0 when
+// no big row is above it. Writes the exit cluster row and the exit lambda.
+__global__ __launch_bounds__(B) void k_cd_exit_ids(const uint32_t *rankof, const uint32_t *kpar, const uint2 *wk,
+                                                   const uint64_t *rowL, const uint32_t *grank,
+                                                   const uint32_t *rootrow, int64_t n, int64_t M, uint32_t *prow,
+                                                   uint64_t *pt_lambda) {
+  for (int64_t id = (int64_t)blockIdx.x * B + threadIdx.x; id < n; id += (int64_t)gridDim.x * B) {
+    const uint32_t p = rankof[id];
+    uint32_t y = kpar[p], r = NONE32;
+    while (y != NONE32) {
+      const uint2 e = wk[y - n];
+      if (e.y >= (uint64_t)M) {
+        r = e.x;
+        break;
+      }
+      y = e.x;
+    }
+    uint64_t L = 0;
+    if (y == NONE32) r = rootrow[grank[p]];
+    else L = rowL[y - n];
+    prow[id] = r;
+    if (pt_lambda) pt_lambda[id] = L;
   }
 }
 
@@ -702,15 +636,13 @@ __global__ __launch_bounds__(B) void k_top_jump(const uint32_t *act, int64_t nac
   tile_append(keep, vals, next, nnext);
 }
 
-// every record's exit cluster row; the smallest input id under each label
-__global__ __launch_bounds__(B) void k_lab_rows(const uint32_t *exc, const uint32_t *rowof, const uint32_t *rootrow,
-                                                const uint32_t *top, const uint32_t *cprow, const uint32_t *perm,
-                                                int64_t m, int64_t n, uint32_t *prow, uint32_t *minmem) {
-  for (int64_t p = (int64_t)blockIdx.x * B + threadIdx.x; p < n; p += (int64_t)gridDim.x * B) {
-    uint32_t r = row_of(exc[p], n, m, rowof, rootrow);
-    uint32_t lr = cprow[r] == NONE32 ? NONE32 : top[r];
-    prow[p] = r;
-    if (lr != NONE32) atomicMin(&minmem[lr], perm[p]);
+// the smallest input id under each label (records in input order)
+__global__ __launch_bounds__(B) void k_lab_rows(const uint32_t *prow, const uint32_t *top, const uint32_t *cprow,
+                                                int64_t n, uint32_t *minmem) {
+  for (int64_t id = (int64_t)blockIdx.x * B + threadIdx.x; id < n; id += (int64_t)gridDim.x * B) {
+    const uint32_t r = prow[id];
+    const uint32_t lr = cprow[r] == NONE32 ? NONE32 : top[r];
+    if (lr != NONE32) atomicMin(&minmem[lr], (uint32_t)id);
   }
 }
 
@@ -729,14 +661,12 @@ __device__ inline uint32_t local_node(uint32_t x, uint32_t g, int64_t n, int64_t
   return ng + (rowpos[x - n] - moff[g]);
 }
 
-// per record, in input order (gathers by rank, so the writes are coalesced)
-__global__ __launch_bounds__(B) void k_out_points(const uint32_t *rankof, const uint32_t *prow, const uint64_t *exl,
-                                                  const uint32_t *rlocal, const int32_t *rlab, int64_t n,
-                                                  uint32_t *pt_cluster, uint64_t *pt_lambda, int32_t *labels) {
+// per record, in input order: its exit row's node and label
+__global__ __launch_bounds__(B) void k_out_points(const uint32_t *prow, const uint32_t *rlocal, const int32_t *rlab,
+                                                  int64_t n, uint32_t *pt_cluster, int32_t *labels) {
   for (int64_t id = (int64_t)blockIdx.x * B + threadIdx.x; id < n; id += (int64_t)gridDim.x * B) {
-    const uint32_t p = rankof[id], r = prow[p];
+    const uint32_t r = prow[id];
     if (pt_cluster) pt_cluster[id] = rlocal[r];
-    if (pt_lambda) pt_lambda[id] = exl[p];
     if (labels) labels[id] = rlab[r];
   }
 }
@@ -996,17 +926,16 @@ ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipSt
   CE_LAUNCH(k_cd_rootrows, dim3(gG), dim3(B), 0, s, rootrow, b.eoff, G, m, n, cnode, csize, cbirth, cprow);
   CE_LAUNCH(k_fill64, dim3(grid_for(3 * (int64_t)nrows, B)), dim3(B), 0, s, (uint64_t *)acc, 3 * (int64_t)nrows,
             (uint64_t)0);
-  // exits (and, for M <= EXIT_STACK, the point term of the stabilities with them)
-  if (M <= EXIT_STACK) {
-    CE_LAUNCH(k_exit_default, dim3(grid_for(n, B)), dim3(B), 0, s, b.grank, n, m, exc, exl);
-    if (m > 0)
-      CE_LAUNCH(k_cd_exit_down_acc, dim3(tiles(m)), dim3(B), 0, s, b.kc_u, b.kc_v, b.ksize, J, rowL, rowmap,
-                rootrow, m, n, M, exc, exl, acc);
-  } else {
-    CE_LAUNCH(k_cd_exit, dim3(grid_for(n, B)), dim3(B), 0, s, kpar, b.ksize, J, rowL, b.grank, m, n,
-              M, exc, exl);
-    CE_LAUNCH(k_cd_acc_points, dim3(tiles(n)), dim3(B), 0, s, exc, exl, rowmap, m, n, rootrow, acc);
-  }
+  // point terms of the stabilities per big row; exits per record in input order
+  if (m > 0)
+    CE_LAUNCH(k_cd_point_terms, dim3(tiles(m)), dim3(B), 0, s, b.kc_u, b.kc_v, b.ksize, J, rowL, rowmap, rootrow, m,
+              n, M, acc);
+  uint32_t *prow = labrow;
+  uint2 *wk = (uint2 *)exl;  // m <= n words of 8 bytes
+  if (m > 0)
+    CE_LAUNCH(k_cd_walk_words, dim3(grid_for(m, B)), dim3(B), 0, s, kpar, b.ksize, J, rowmap, rootrow, n, m, M, wk);
+  CE_LAUNCH(k_cd_exit_ids, dim3(grid_for(n, B)), dim3(B), 0, s, b.rankof, kpar, wk, rowL, b.grank, rootrow, n, M,
+            prow, out->pt_lambda);
   CE_LAUNCH(k_cd_acc_children, dim3((unsigned)((nrows + B - 1) / B)), dim3(B), 0, s, csize, cbirth, cprow, nrows,
             acc);
   CE_LAUNCH(k_cd_stab, dim3(gR), dim3(B), 0, s, acc, csize, cbirth, nrows, shi, slo);
@@ -1075,8 +1004,7 @@ ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipSt
     CE_TRY(read_u64(&b.hdr[8], &nact, 1, s));
   }
   CE_LAUNCH(k_fill32, dim3(gR), dim3(B), 0, s, minmem, (int64_t)nrows, NONE32);
-  CE_LAUNCH(k_lab_rows, dim3(grid_for(n, B)), dim3(B), 0, s, exc, rowmap, rootrow, top, cprow, b.perm, m, n, labrow,
-            minmem);
+  CE_LAUNCH(k_lab_rows, dim3(grid_for(n, B)), dim3(B), 0, s, prow, top, cprow, n, minmem);
   CE_LAUNCH(k_fill32, dim3(grid_for(n + 1, B)), dim3(B), 0, s, fl, n + 1, 0u);
   CE_LAUNCH(k_lab_flags, dim3(gR), dim3(B), 0, s, top, minmem, nrows, fl);
   CE_HIP(hipGetLastError());
@@ -1086,8 +1014,7 @@ ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipSt
   int32_t *rlab = (int32_t *)nxt2;
   CE_LAUNCH(k_row_point_vals, dim3(gR), dim3(B), 0, s, cnode, cprow, top, minmem, fl, b.rowg, b.eoff, b.moff,
             b.rowpos, n, m, nrows, rlocal, rlab);
-  CE_LAUNCH(k_out_points, dim3(grid_for(n, B)), dim3(B), 0, s, b.rankof, labrow, exl, rlocal, rlab, n,
-            out->pt_cluster, out->pt_lambda, out->labels);
+  CE_LAUNCH(k_out_points, dim3(grid_for(n, B)), dim3(B), 0, s, prow, rlocal, rlab, n, out->pt_cluster, out->labels);
   CE_LAUNCH(k_out_clusters, dim3(gR), dim3(B), 0, s, cnode, cprow, csize, cbirth, shi, slo, top, b.rowg, b.eoff,
             b.moff, b.rowpos, n, m, nrows, *out);
   CE_LAUNCH(k_graph_labels, dim3(gG), dim3(B), 0, s, fl, b.eoff, G, nlab);
