@@ -109,9 +109,11 @@ __global__ __launch_bounds__(B) void k_skel_tails(const uint32_t *ikey, const ui
 
 // Also seeds the first Boruvka round: every record starts as its own
 // component, so each edge offers its key to both of its records.
+// The low bit orders the two edges of a head by descending tail id; it only
+// decides their order when they have the same weight (else w does), so the
+// tails' ids are read only then.
 __global__ __launch_bounds__(B) void k_skel_keys(uint32_t *skel_tail, const uint64_t *ts, const uint32_t *perm,
-                                                 int64_t n, int idbits, uint64_t *skel_key, uint32_t *skel_tid,
-                                                 uint64_t *best) {
+                                                 int64_t n, int idbits, uint64_t *skel_key, uint64_t *best) {
   for (int64_t h = (int64_t)blockIdx.x * B + threadIdx.x; h < n; h += (int64_t)gridDim.x * B) {
     uint32_t t0 = skel_tail[2 * h], t1 = skel_tail[2 * h + 1];
     if (t0 != NONE32 && t0 == t1) {  // the same pair twice: one line-graph edge
@@ -120,20 +122,17 @@ __global__ __launch_bounds__(B) void k_skel_keys(uint32_t *skel_tail, const uint
     }
     const uint64_t hid = perm[h];
     const uint64_t th = ts[h];
-    uint32_t i0 = t0 != NONE32 ? perm[t0] : 0u, i1 = t1 != NONE32 ? perm[t1] : 0u;
-    uint64_t k0 = NONE64, k1 = NONE64;
-    if (t0 != NONE32) {
-      uint64_t bit = (t1 != NONE32 && i0 < i1) ? 1u : 0u;
-      k0 = ((th - ts[t0]) << (idbits + 1)) | (hid << 1) | bit;
+    const uint64_t w0 = t0 != NONE32 ? th - ts[t0] : 0, w1 = t1 != NONE32 ? th - ts[t1] : 0;
+    uint64_t b0 = 0, b1 = 0;
+    if (t0 != NONE32 && t1 != NONE32 && w0 == w1) {
+      const uint32_t i0 = perm[t0], i1 = perm[t1];
+      b0 = i0 < i1 ? 1u : 0u;
+      b1 = 1u - b0;
     }
-    if (t1 != NONE32) {
-      uint64_t bit = (t0 != NONE32 && i1 < i0) ? 1u : 0u;
-      k1 = ((th - ts[t1]) << (idbits + 1)) | (hid << 1) | bit;
-    }
+    const uint64_t k0 = t0 != NONE32 ? (w0 << (idbits + 1)) | (hid << 1) | b0 : NONE64;
+    const uint64_t k1 = t1 != NONE32 ? (w1 << (idbits + 1)) | (hid << 1) | b1 : NONE64;
     skel_key[2 * h] = k0;
     skel_key[2 * h + 1] = k1;
-    skel_tid[2 * h] = i0;
-    skel_tid[2 * h + 1] = i1;
     uint64_t mine = k0 < k1 ? k0 : k1;
     if (mine != NONE64) atomicMin((unsigned long long *)&best[h], (unsigned long long)mine);
     if (t0 != NONE32) atomicMin((unsigned long long *)&best[t0], (unsigned long long)k0);
@@ -549,7 +548,7 @@ ce_status stage_sort_skeleton(const int32_t *src, const int32_t *dst, const int6
   CE_LAUNCH(k_fill_u64, dim3(grid_for(n, B)), dim3(B), 0, s, b.best, n, NONE64);
   CE_HIP(hipGetLastError());
   CE_LAUNCH(k_skel_keys, dim3(grid_for(n, B)), dim3(B), 0, s, b.skel_tail, b.ts, b.perm, n, b.idbits, b.skel_key,
-            b.skel_tid, b.best);
+            b.best);
   CE_HIP(hipGetLastError());
   ws.release(m0);
   return CE_OK;
