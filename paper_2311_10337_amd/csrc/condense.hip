@@ -107,26 +107,87 @@ __global__ __launch_bounds__(B) void k_dd_top_init(const uint32_t *kpar, const u
   }
 }
 // pointer doubling over rows; counts rows that moved
-__global__ __launch_bounds__(B) void k_dd_top_jump(const uint32_t *tin, int64_t m, int64_t n, uint32_t *tout,
-                                                   unsigned long long *moved) {
-  uint32_t cnt = 0;
-  for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
-    const uint32_t t = tin[j], tt = tin[t - n];
-    tout[j] = tt;
-    cnt += tt != t;
+// rows whose level top is not known yet (their pointer is not a top)
+__global__ __launch_bounds__(B) void k_dd_top_active(const uint32_t *top, int64_t m, int64_t n, uint32_t *act,
+                                                     unsigned long long *nact) {
+  bool keep[CT];
+  uint32_t vals[CT];
+  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < CT; k++) {
+    const int64_t j = base + (int64_t)k * B;
+    keep[k] = false;
+    vals[k] = (uint32_t)j;
+    if (j >= m) continue;
+    const uint32_t t = top[j];
+    keep[k] = t != (uint32_t)(n + j) && top[t - n] != t;
   }
-  cnt = wave_sum_u32(cnt);
-  if (wave_lane() == 0 && cnt) atomicAdd(moved, (unsigned long long)cnt);
+  tile_append(keep, vals, act, nact);
+}
+// one pointer-jumping round over the active rows, in place: a row only reads
+// pointers of rows above it, which stay valid ancestors of the same level
+__global__ __launch_bounds__(B) void k_dd_top_jump(const uint32_t *act, int64_t nact, int64_t n, uint32_t *top,
+                                                   uint32_t *next, unsigned long long *nnext) {
+  bool keep[CT];
+  uint32_t vals[CT];
+  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < CT; k++) {
+    const int64_t i = base + (int64_t)k * B;
+    keep[k] = false;
+    vals[k] = 0;
+    if (i >= nact) continue;
+    const uint32_t j = act[i], t = top[j], tt = top[t - n];
+    if (tt == t) continue;  // t is a top
+    top[j] = tt;
+    keep[k] = top[tt - n] != tt;
+    vals[k] = j;
+  }
+  tile_append(keep, vals, next, nnext);
 }
 // big children of every D-node: the level tops (rows that are their own top)
 // hanging below its block; records are never big (M >= 2)
+// big D-node children per D-node; a D-node can have millions of them, so the
+// counts are combined per wave and per tile (LDS hash) before the atomics
+constexpr int DHS = 512;
 __global__ __launch_bounds__(B) void k_dd_bigcount(const uint32_t *kpar, const uint32_t *ksize, const uint32_t *top,
                                                    int64_t m, int64_t n, int64_t M, uint32_t *bigcnt) {
-  for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
-    const uint32_t p = kpar[n + j];
-    if (p == NONE32 || top[j] != (uint32_t)(n + j) || ksize[j] < (uint64_t)M) continue;
-    atomicAdd(&bigcnt[top[p - n] - n], 1u);
+  __shared__ uint32_t hk[DHS], hc[DHS];
+  for (int i = threadIdx.x; i < DHS; i += B) { hk[i] = NONE32; hc[i] = 0; }
+  __syncthreads();
+  const int64_t tbase = (int64_t)blockIdx.x * (B * CT);
+  for (int k = 0; k < CT; k++) {
+    const int64_t j = tbase + (int64_t)k * B + threadIdx.x;
+    uint32_t d = 0, add = 0;
+    if (j < m) {
+      const uint32_t p = kpar[n + j];
+      if (p != NONE32 && top[j] == (uint32_t)(n + j) && ksize[j] >= (uint64_t)M) {
+        d = top[p - n] - (uint32_t)n;
+        add = 1;
+      }
+    }
+    const bool upd = wave_combine_first(add != 0, d, [&](bool mine, int leader) {
+      const uint32_t sum = wave_sum_u32(mine ? add : 0u);
+      if ((int)wave_lane() == leader) add = sum;
+    });
+    if (upd) {
+      uint32_t sl = (d * 2654435761u) >> 23;  // 9 bits
+      bool placed = false;
+      for (int probe = 0; probe < HASH_PROBES && !placed; probe++) {
+        const uint32_t old = atomicCAS(&hk[sl], NONE32, d);
+        if (old == NONE32 || old == d) {
+          atomicAdd(&hc[sl], add);
+          placed = true;
+        } else {
+          sl = (sl + 1) & (DHS - 1);
+        }
+      }
+      if (!placed) atomicAdd(&bigcnt[d], add);
+    }
   }
+  __syncthreads();
+  for (int i = threadIdx.x; i < DHS; i += B)
+    if (hk[i] != NONE32) atomicAdd(&bigcnt[hk[i]], hc[i]);
 }
 // a big child of a D-node with two or more big children starts a cluster at
 // the D-node's lambda
@@ -431,49 +492,54 @@ __global__ __launch_bounds__(B) void k_cd_children(const uint32_t *cprow, uint32
 // parent, then a parent with k children gets a chain of k-2 virtual nodes
 // (rows nrows..) of stability 0, so that every node has at most two children
 // and a virtual node's value max(0, x + y) is the plain sum of its two.
-__global__ __launch_bounds__(B) void k_cd_childcount(const uint32_t *cprow, uint32_t nrows, uint32_t *nch) {
+// child lists by a sort of the rows by parent (a parent can have millions of
+// children, so no per-parent atomics); rows that are not children of a
+// non-root cluster get the key nrows and sort last
+__global__ __launch_bounds__(B) void k_cd_child_keys(const uint32_t *cprow, uint32_t nrows, uint32_t *key) {
   for (int64_t r = (int64_t)blockIdx.x * B + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * B) {
     const uint32_t p = cprow[r];
-    if (p == NONE32 || cprow[p] == NONE32) continue;
-    atomicAdd(&nch[p], 1u);
+    key[r] = (p == NONE32 || cprow[p] == NONE32) ? nrows : p;
   }
 }
-__global__ __launch_bounds__(B) void k_cd_childlist(const uint32_t *cprow, const uint32_t *choff, uint32_t nrows,
-                                                    uint32_t *fill, uint32_t *clist) {
-  for (int64_t r = (int64_t)blockIdx.x * B + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * B) {
-    const uint32_t p = cprow[r];
-    if (p == NONE32 || cprow[p] == NONE32) continue;
-    clist[choff[p] + atomicAdd(&fill[p], 1u)] = (uint32_t)r;
+__global__ __launch_bounds__(B) void k_cd_child_counts(const uint32_t *choff, uint32_t nrows, uint32_t *nch,
+                                                       uint32_t *vcnt) {
+  for (int64_t p = (int64_t)blockIdx.x * B + threadIdx.x; p < nrows; p += (int64_t)gridDim.x * B) {
+    const uint32_t k = choff[p + 1] - choff[p];
+    nch[p] = k;
+    vcnt[p] = k > 2 ? k - 2 : 0u;
   }
 }
-__global__ __launch_bounds__(B) void k_cd_vcount(const uint32_t *nch, uint32_t nrows, uint32_t *vcnt) {
-  for (int64_t r = (int64_t)blockIdx.x * B + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * B)
-    vcnt[r] = nch[r] > 2 ? nch[r] - 2 : 0u;
-}
+// p -> (L0, L1), or with k > 2 children p -> (L0, v0) (virtual nodes below)
 __global__ __launch_bounds__(B) void k_cd_pairs(const uint32_t *nch, const uint32_t *choff, const uint32_t *clist,
-                                                const uint32_t *vbase, uint32_t nrows, uint32_t *ch, uint32_t *vnch,
-                                                uint64_t *shi, uint64_t *slo) {
+                                                const uint32_t *vbase, uint32_t nrows, uint32_t *ch) {
   for (int64_t p = (int64_t)blockIdx.x * B + threadIdx.x; p < nrows; p += (int64_t)gridDim.x * B) {
     const uint32_t k = nch[p];
     if (k == 0) continue;
     const uint32_t *L = clist + choff[p];
-    if (k <= 2) {
-      ch[2 * p] = L[0];
-      ch[2 * p + 1] = k == 2 ? L[1] : L[0];
-      continue;
-    }
-    // p -> (L0, v0), v_i -> (L_{i+1}, v_{i+1}), the last virtual node -> (L_{k-2}, L_{k-1})
-    const uint32_t v0 = nrows + vbase[p];
     ch[2 * p] = L[0];
-    ch[2 * p + 1] = v0;
-    for (uint32_t i = 0; i + 2 < k; i++) {
-      const uint32_t v = v0 + i;
-      ch[2 * (uint64_t)v] = L[i + 1];
-      ch[2 * (uint64_t)v + 1] = (i + 3 < k) ? v + 1 : L[k - 1];
-      vnch[v] = 2;
-      shi[v] = 0;
-      slo[v] = 0;
+    ch[2 * p + 1] = k > 2 ? nrows + vbase[p] : (k == 2 ? L[1] : L[0]);
+  }
+}
+// virtual node v (the i-th of parent p): v_i -> (L_{i+1}, v_{i+1}); the last
+// one -> (L_{k-2}, L_{k-1}); its parent is the last p with vbase[p] <= v
+__global__ __launch_bounds__(B) void k_cd_virtual(const uint32_t *nch, const uint32_t *choff, const uint32_t *clist,
+                                                  const uint32_t *vbase, uint32_t nrows, uint32_t nvirt,
+                                                  uint32_t *ch, uint32_t *vnch, uint64_t *shi, uint64_t *slo) {
+  for (int64_t v = (int64_t)blockIdx.x * B + threadIdx.x; v < nvirt; v += (int64_t)gridDim.x * B) {
+    int64_t lo = 0, hi = (int64_t)nrows - 1;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi + 1) >> 1;
+      if ((int64_t)vbase[mid] <= v) lo = mid;
+      else hi = mid - 1;
     }
+    const uint32_t p = (uint32_t)lo, i = (uint32_t)(v - vbase[p]), k = nch[p];
+    const uint32_t *L = clist + choff[p];
+    const uint64_t node = nrows + (uint64_t)v;
+    ch[2 * node] = L[i + 1];
+    ch[2 * node + 1] = (i + 3 < k) ? (uint32_t)(node + 1) : L[k - 1];
+    vnch[node] = 2;
+    shi[node] = 0;
+    slo[node] = 0;
   }
 }
 
@@ -730,25 +796,30 @@ __global__ __launch_bounds__(B) void k_graph_labels(const uint32_t *fscan, const
 }  // namespace
 
 // level tops by pointer doubling, big children per D-node, births
+// act and act2 hold m + 1 entries each (active lists of the level-top jumping)
 static ce_status discrete_births(Bufs &b, int64_t m, const uint32_t *kpar, const uint32_t *level,
-                                 const uint64_t *rowL, uint32_t *&top, uint32_t *&top2, uint32_t *bigcnt,
-                                 uint8_t *isbirth, uint64_t *birthL, hipStream_t s) {
+                                 const uint64_t *rowL, uint32_t *top, uint32_t *act, uint32_t *act2,
+                                 uint32_t *bigcnt, uint8_t *isbirth, uint64_t *birthL, hipStream_t s) {
   const int64_t n = b.n, M = b.M;
   const unsigned g = grid_for(m, B);
+  auto tiles = [](int64_t k) { return (unsigned)((k + (int64_t)B * CT - 1) / ((int64_t)B * CT)); };
+  unsigned long long *ctr = (unsigned long long *)&b.hdr[9];
   CE_LAUNCH(k_dd_top_init, dim3(g), dim3(B), 0, s, kpar, level, m, n, top);
+  CE_LAUNCH(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[9], (uint64_t)0);
+  CE_LAUNCH(k_dd_top_active, dim3(tiles(m)), dim3(B), 0, s, top, m, n, act, ctr);
   CE_HIP(hipGetLastError());
-  for (int it = 0;; it++) {
+  uint64_t nact = 0;
+  CE_TRY(read_u64(&b.hdr[9], &nact, 1, s));
+  for (int it = 0; nact > 0; it++) {
     if (it > 40) {
       set_error("level-top pointer jumping did not converge");
       return CE_EDEVICE;
     }
     CE_LAUNCH(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[9], (uint64_t)0);
-    CE_LAUNCH(k_dd_top_jump, dim3(g), dim3(B), 0, s, top, m, n, top2, (unsigned long long *)&b.hdr[9]);
+    CE_LAUNCH(k_dd_top_jump, dim3(tiles((int64_t)nact)), dim3(B), 0, s, act, (int64_t)nact, n, top, act2, ctr);
     CE_HIP(hipGetLastError());
-    uint32_t *t = top; top = top2; top2 = t;
-    uint64_t moved = 0;
-    CE_TRY(read_u64(&b.hdr[9], &moved, 1, s));
-    if (moved == 0) break;
+    uint32_t *t = act; act = act2; act2 = t;
+    CE_TRY(read_u64(&b.hdr[9], &nact, 1, s));
   }
   CE_LAUNCH(k_fill32, dim3(g), dim3(B), 0, s, bigcnt, m, 0u);
   CE_LAUNCH(k_dd_bigcount, dim3(g), dim3(B), 0, s, kpar, b.ksize, top, m, n, M, bigcnt);
@@ -777,7 +848,7 @@ size_t stage_condense_scratch(int64_t n, int64_t M, int64_t G, bool discrete) {
   w.alloc<uint64_t>(RE); w.alloc<uint64_t>(RE);  // shi slo (and virtual nodes)
   w.alloc<uint32_t>(RE); w.alloc<uint32_t>(2 * RE);  // nch ch
   if (discrete)
-    for (int k = 0; k < 4; k++) w.alloc<uint32_t>(R + 1);  // child offsets, fill counts, lists, virtual bases
+    for (int k = 0; k < 6; k++) w.alloc<uint32_t>(R + 1);  // child keys and lists (x2), offsets, virtual bases
   for (int k = 0; k < 2; k++) {
     w.alloc<uint8_t>(RE);
     for (int q = 0; q < 6; q++) w.alloc<uint64_t>(RE);
@@ -817,11 +888,14 @@ ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipSt
   unsigned long long *acc = ws.alloc<unsigned long long>(3 * R);
   uint64_t *shi = ws.alloc<uint64_t>(RE), *slo = ws.alloc<uint64_t>(RE);
   uint32_t *nch = ws.alloc<uint32_t>(RE), *ch = ws.alloc<uint32_t>(2 * RE);
-  uint32_t *choff = nullptr, *cfill = nullptr, *clist = nullptr, *vbase = nullptr;
+  uint32_t *choff = nullptr, *ckey = nullptr, *ckey2 = nullptr, *clist = nullptr, *clist2 = nullptr,
+           *vbase = nullptr;
   if (b.q > 0) {
     choff = ws.alloc<uint32_t>(R + 1);
-    cfill = ws.alloc<uint32_t>(R + 1);
+    ckey = ws.alloc<uint32_t>(R + 1);
+    ckey2 = ws.alloc<uint32_t>(R + 1);
     clist = ws.alloc<uint32_t>(R + 1);
+    clist2 = ws.alloc<uint32_t>(R + 1);
     vbase = ws.alloc<uint32_t>(R + 1);
   }
   Eom e[2];
@@ -839,9 +913,9 @@ ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipSt
   uint32_t *labrow = ws.alloc<uint32_t>(n);
   uint32_t *fl = ws.alloc<uint32_t>(n + 1);
   CE_WS_CHECK(ws);
-  // discrete dendrogram: level, level tops (two arrays) and big-child counts per row live only until the
+  // discrete dendrogram: level, level tops and big-child counts per row live only until the
   // births are known and the per-row discrete outputs written, before exits, labels and flags use these
-  uint32_t *level = exc, *dtop = labrow, *dtop2 = fl, *bigcnt = (uint32_t *)exl;
+  uint32_t *level = exc, *dtop = labrow, *bigcnt = (uint32_t *)exl;
   unsigned long long *ctr = (unsigned long long *)&b.hdr[8];
   auto tiles = [](int64_t k) { return (unsigned)((k + (int64_t)B * CT - 1) / ((int64_t)B * CT)); };
 
@@ -860,7 +934,7 @@ ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipSt
               M, nbig, b.rowg, isbirth, birthL);
     CE_HIP(hipGetLastError());
     if (b.q > 0) {
-      CE_TRY(discrete_births(b, m, kpar, level, rowL, dtop, dtop2, bigcnt, isbirth, birthL, s));
+      CE_TRY(discrete_births(b, m, kpar, level, rowL, dtop, jact, jact2, bigcnt, isbirth, birthL, s));
       if (out->dd_level || out->dd_top)
         CE_LAUNCH(k_out_discrete, dim3(grid_for(m, B)), dim3(B), 0, s, level, dtop, b.rowg, b.eoff, b.moff, b.rowpos,
                   n, m, out->dd_level, out->dd_top);
@@ -944,12 +1018,15 @@ ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipSt
   uint32_t nvirt = 0;
   if (b.q > 0) {
     // any number of child clusters: per-parent lists, then chains of virtual sum nodes
-    CE_LAUNCH(k_cd_childcount, dim3(gR), dim3(B), 0, s, cprow, nrows, nch);
+    CE_LAUNCH(k_cd_child_keys, dim3(gR), dim3(B), 0, s, cprow, nrows, ckey);
     CE_HIP(hipGetLastError());
-    CE_TRY(scan_exclusive_u32(nch, choff, nrows, ws, s));
-    CE_LAUNCH(k_fill32, dim3(gR), dim3(B), 0, s, cfill, (int64_t)nrows, 0u);
-    CE_LAUNCH(k_cd_childlist, dim3(gR), dim3(B), 0, s, cprow, choff, nrows, cfill, clist);
-    CE_LAUNCH(k_cd_vcount, dim3(gR), dim3(B), 0, s, nch, nrows, vbase);
+    bool calt = false;
+    CE_TRY((radix_sort_pairs<uint32_t, uint32_t>(ckey, clist, ckey2, clist2, nrows, 0, bits_for(nrows), true, &calt,
+                                                 ws, s)));
+    const uint32_t *sk = calt ? ckey2 : ckey;
+    if (calt) clist = clist2;
+    CE_TRY(segment_bounds_u32(sk, nrows, nrows, choff, s));
+    CE_LAUNCH(k_cd_child_counts, dim3(gR), dim3(B), 0, s, choff, nrows, nch, vbase);
     CE_HIP(hipGetLastError());
     CE_TRY(scan_exclusive_u32(vbase, vbase, nrows, ws, s));
     uint32_t *h = (uint32_t *)pinned_scratch();
@@ -960,7 +1037,11 @@ ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipSt
       set_error("virtual cluster nodes exceed the workspace bound");
       return CE_EDEVICE;
     }
-    CE_LAUNCH(k_cd_pairs, dim3(gR), dim3(B), 0, s, nch, choff, clist, vbase, nrows, ch, nch, shi, slo);
+    CE_LAUNCH(k_cd_pairs, dim3(gR), dim3(B), 0, s, nch, choff, clist, vbase, nrows, ch);
+    if (nvirt > 0)
+      CE_LAUNCH(k_cd_virtual, dim3(grid_for(nvirt, B)), dim3(B), 0, s, nch, choff, clist, vbase, nrows, nvirt, ch, nch,
+                shi, slo);
+    CE_HIP(hipGetLastError());
   } else {
     CE_LAUNCH(k_cd_children, dim3(gR), dim3(B), 0, s, cprow, nrows, nch, ch);
   }
