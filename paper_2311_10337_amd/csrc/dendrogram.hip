@@ -336,15 +336,22 @@ __global__ __launch_bounds__(LB) void k_krt_lds(const uint32_t *lu, const uint32
 
 }  // namespace
 
-int krt_level_bits() {
-  static int bits = 0;
-  if (!bits) {
+// Largest number of bits one global level may take: a level of k bits has 2^k
+// sub-intervals run one after another, each over about m / 2^k rows, and a
+// sub-interval needs about 2^19 rows or more to keep enough waves in flight
+// for its random accesses; at most 8 bits (256 sub-intervals). The
+// environment variable CE_KRT_LEVEL_BITS overrides it (1..10).
+int krt_max_level_bits(int64_t m) {
+  static int forced = -1;
+  if (forced < 0) {
     const char *e = getenv("CE_KRT_LEVEL_BITS");
-    bits = e ? atoi(e) : 6;
-    if (bits < 1) bits = 1;
-    if (bits > 10) bits = 10;
+    forced = e ? atoi(e) : 0;
+    if (forced < 0) forced = 0;
+    if (forced > 10) forced = 10;
   }
-  return bits;
+  if (forced) return forced;
+  int k = bits_for((uint64_t)(m >> 19)) - 1;
+  return k < 4 ? 4 : (k > 8 ? 8 : k);
 }
 
 size_t stage_dendrogram_scratch(int64_t n) {
@@ -366,10 +373,15 @@ ce_status stage_dendrogram(Bufs &b, int64_t m, Ws &ws, hipStream_t s) {
   CE_LAUNCH(k_krt_init, dim3(grid_for(m, B)), dim3(B), 0, s, b.msf_val, m, lu, lv, su, sv);
   CE_HIP(hipGetLastError());
   const int L = bits_for((uint64_t)(m - 1));  // rows are j < 2^L
-  const int kb = krt_level_bits();
-  int hi = L - 1;
+  // the global bits L-1 .. LS_BITS in as few levels as the largest level
+  // allows, spread evenly (the upper levels take the remainder)
+  const int gbits = L - LS_BITS, kmax = krt_max_level_bits(m);
+  const int nlev = gbits > 0 ? (gbits + kmax - 1) / kmax : 0;
+  int hi = L - 1, lev = 0;
   bool first = true;
   while (hi >= LS_BITS) {
+    const int kb = gbits / nlev + (lev < gbits % nlev ? 1 : 0);
+    lev++;
     int lo = hi - kb + 1;
     if (lo < LS_BITS) lo = LS_BITS;
     const uint32_t K = 1u << (hi - lo + 1);

@@ -19,21 +19,21 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 
 
-def dendrogram_levels(m: int, lds_bits: int = 9, level_bits: int = 6) -> int:
-    """Global levels of the rank-interval dendrogram for m rows."""
+def dendrogram_levels(m: int, lds_bits: int = 9, level_bits: int = 0) -> int:
+    """Global levels of the rank-interval dendrogram for m rows: the global bits in as few levels as the
+    largest level allows (about 2^19 rows per sub-interval, 4 to 8 bits; level_bits overrides it)."""
     if m <= 1:
         return 0
     L = (m - 1).bit_length()
-    hi, lv = L - 1, 0
-    while hi >= lds_bits:
-        lo = max(hi - level_bits + 1, lds_bits)
-        lv += 1
-        hi = lo - 1
-    return lv
+    gbits = L - lds_bits
+    if gbits <= 0:
+        return 0
+    kmax = level_bits or min(8, max(4, (m >> 19).bit_length() - 1))
+    return -(-gbits // kmax)
 
 
 # kernel -> (unit, algorithmic bytes per unit, units per step as a function of the run)
-def algorithmic_bytes_per_step(kernel: str, n: int, m: int, level_bits: int = 6) -> tuple:
+def algorithmic_bytes_per_step(kernel: str, n: int, m: int, level_bits: int = 0) -> tuple:
     """(unit description, bytes per unit, units per step) for a kernel of the pipeline."""
     if kernel == "k_krt_accum":
         # per row and global level: hooked root id (4), its size (4), the parent of that root (4),
