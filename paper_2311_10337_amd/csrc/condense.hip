@@ -31,9 +31,6 @@ constexpr int B = 256;
 __device__ inline uint32_t node_size(uint32_t x, int64_t n, const uint32_t *ksize) {
   return x < (uint64_t)n ? 1u : ksize[x - n];
 }
-__device__ inline int64_t row_w(int64_t j, const uint64_t *msf_key, int wshift) {
-  return (int64_t)(msf_key[j] >> wshift);
-}
 
 __global__ __launch_bounds__(B) void k_fill32(uint32_t *p, int64_t n, uint32_t v) {
   for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < n; i += (int64_t)gridDim.x * B) p[i] = v;
