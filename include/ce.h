@@ -3,9 +3,12 @@
  *
  * Computes the hierarchical edge clustering of a dynamic multigraph
  * (arXiv 2311.10337, "Scalable Edge Clustering of Dynamic Graphs via
- * Weighted Line Graphs"), undirected variant: line-graph nodes are the
- * temporal edges (Sec. 1.2.2), two are adjacent when they share a vertex,
- * with weight |t_a - t_b|. The library
+ * Weighted Line Graphs"). In the default undirected mode the line-graph
+ * nodes are the temporal edges (Sec. 1.2.2), two are adjacent when they share
+ * a vertex, with weight |t_a - t_b|; the causal mode (Def. 1), the time
+ * cutoff (Sec. 5.1), the discrete dendrogram (Alg. 5) and dynamic hypergraphs
+ * (Sec. 5.3) are described with their parameters and entry points below. The
+ * library
  *   1. groups each vertex's incident temporal edges and sorts them by time
  *      ("Generate adjacency list", "Sort E_i by time": Alg. 3, Alg. 2),
  *   2. emits the line-graph skeleton L* = union of node-local MSTs, which for
@@ -32,8 +35,9 @@
  * Memory: every pointer argument except `params`, `out` (the struct itself),
  * `counts` and the batch offset arrays is a DEVICE pointer on the current HIP
  * device. Inputs are read-only and owned by the caller. Outputs are owned by
- * the caller and must hold the documented row counts. The library keeps
- * nothing between calls.
+ * the caller and must hold the documented row counts. Between calls the
+ * library keeps only a 4 KiB pinned host page per calling thread (for the
+ * small counts it reads back) and the servers the caller creates.
  */
 #ifndef CE_H
 #define CE_H
