@@ -130,13 +130,18 @@ __global__ __launch_bounds__(B) void k_windows(const uint32_t *sk, const uint32_
   }
 }
 
-__device__ inline void emit_row(int64_t e, uint32_t ii, uint32_t s, uint64_t hid, uint64_t th, const uint32_t *inpos,
-                                const uint32_t *sv, const uint64_t *ts, const uint32_t *tie, int wshift, int hshift,
-                                uint64_t *skel_key, uint32_t *skel_tail, uint32_t *skel_head) {
+// writes row e and offers its key to the tail's first Boruvka minimum; returns the key
+__device__ inline uint64_t emit_row(int64_t e, uint32_t ii, uint32_t s, uint64_t hid, uint64_t th,
+                                    const uint32_t *inpos, const uint32_t *sv, const uint64_t *ts,
+                                    const uint32_t *tie, int wshift, int hshift, uint64_t *skel_key,
+                                    uint32_t *skel_tail, uint32_t *skel_head, uint64_t *best) {
   const uint32_t r = sv[inpos[ii]] >> 1;
-  skel_key[e] = ((th - ts[r]) << wshift) | (hid << hshift) | (uint64_t)tie[ii];
+  const uint64_t k = ((th - ts[r]) << wshift) | (hid << hshift) | (uint64_t)tie[ii];
+  skel_key[e] = k;
   skel_tail[e] = r;
   skel_head[e] = s;
+  atomicMin((unsigned long long *)&best[r], (unsigned long long)k);
+  return k;
 }
 
 // windows up to a wave long: one thread each; longer ones are listed
@@ -144,8 +149,8 @@ __global__ __launch_bounds__(B) void k_emit_small(const uint32_t *outpos, const 
                                                   const uint32_t *eoff, const uint32_t *inpos, const uint32_t *sv,
                                                   const uint64_t *ts, const uint32_t *perm, const uint32_t *tie,
                                                   int64_t n, int wshift, int hshift, uint64_t *skel_key,
-                                                  uint32_t *skel_tail, uint32_t *skel_head, uint32_t *big,
-                                                  unsigned long long *nbig) {
+                                                  uint32_t *skel_tail, uint32_t *skel_head, uint64_t *best,
+                                                  uint32_t *big, unsigned long long *nbig) {
   for (int64_t q = (int64_t)blockIdx.x * B + threadIdx.x; q < n; q += (int64_t)gridDim.x * B) {
     const uint32_t c = wcnt[q];
     if (c == 0) continue;
@@ -156,8 +161,13 @@ __global__ __launch_bounds__(B) void k_emit_small(const uint32_t *outpos, const 
     const uint32_t s = sv[outpos[q]] >> 1, a = wa[q];
     const uint64_t hid = perm[s], th = ts[s];
     const int64_t e0 = eoff[q];
-    for (uint32_t j = 0; j < c; j++)
-      emit_row(e0 + j, a + j, s, hid, th, inpos, sv, ts, tie, wshift, hshift, skel_key, skel_tail, skel_head);
+    uint64_t mn = NONE64;
+    for (uint32_t j = 0; j < c; j++) {
+      const uint64_t k =
+          emit_row(e0 + j, a + j, s, hid, th, inpos, sv, ts, tie, wshift, hshift, skel_key, skel_tail, skel_head, best);
+      mn = k < mn ? k : mn;
+    }
+    atomicMin((unsigned long long *)&best[s], (unsigned long long)mn);
   }
 }
 
@@ -166,13 +176,23 @@ __global__ __launch_bounds__(B) void k_emit_big(const uint32_t *big, const uint3
                                                 const uint32_t *wcnt, const uint32_t *eoff, const uint32_t *inpos,
                                                 const uint32_t *sv, const uint64_t *ts, const uint32_t *perm,
                                                 const uint32_t *tie, int wshift, int hshift, uint64_t *skel_key,
-                                                uint32_t *skel_tail, uint32_t *skel_head) {
+                                                uint32_t *skel_tail, uint32_t *skel_head, uint64_t *best) {
   const uint32_t q = big[blockIdx.x];
   const uint32_t c = wcnt[q], s = sv[outpos[q]] >> 1, a = wa[q];
   const uint64_t hid = perm[s], th = ts[s];
   const int64_t e0 = eoff[q];
-  for (uint32_t j = threadIdx.x; j < c; j += B)
-    emit_row(e0 + j, a + j, s, hid, th, inpos, sv, ts, tie, wshift, hshift, skel_key, skel_tail, skel_head);
+  uint64_t mn = NONE64;
+  for (uint32_t j = threadIdx.x; j < c; j += B) {
+    const uint64_t k =
+        emit_row(e0 + j, a + j, s, hid, th, inpos, sv, ts, tie, wshift, hshift, skel_key, skel_tail, skel_head, best);
+    mn = k < mn ? k : mn;
+  }
+  mn = wave_min_u64(mn);
+  if (wave_lane() == 0 && mn != NONE64) atomicMin((unsigned long long *)&best[s], (unsigned long long)mn);
+}
+
+__global__ __launch_bounds__(B) void k_fill_best(uint64_t *best, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < n; i += (int64_t)gridDim.x * B) best[i] = NONE64;
 }
 
 __global__ void k_zero_u64(uint64_t *p) { *p = 0; }
@@ -277,10 +297,11 @@ ce_status stage_causal_skeleton(const int32_t *src, const int32_t *dst, const in
               "in-degree - 1) > 64");
     return CE_ERANGE;
   }
-  // 4. rows
+  // 4. rows, each offering its key to both records' first Boruvka minimum
+  CE_LAUNCH(k_fill_best, dim3(grid_for(n, B)), dim3(B), 0, s, b.best, n);
   CE_LAUNCH(k_zero_u64, dim3(1), dim3(1), 0, s, &b.hdr[7]);
   CE_LAUNCH(k_emit_small, dim3(grid_for(n, B)), dim3(B), 0, s, outpos, wa, wcnt, eoff, inpos, sv, b.ts, b.perm, tie, n,
-            b.wshift, b.hshift, b.skel_key, b.skel_tail, b.skel_tid, big, (unsigned long long *)&b.hdr[7]);
+            b.wshift, b.hshift, b.skel_key, b.skel_tail, b.skel_tid, b.best, big, (unsigned long long *)&b.hdr[7]);
   CE_HIP(hipGetLastError());
   uint64_t nbig = 0;
   CE_TRY(read_u64(&b.hdr[7], &nbig, 1, s));
@@ -290,7 +311,7 @@ ce_status stage_causal_skeleton(const int32_t *src, const int32_t *dst, const in
   }
   if (nbig > 0)
     CE_LAUNCH(k_emit_big, dim3((unsigned)nbig), dim3(B), 0, s, big, outpos, wa, wcnt, eoff, inpos, sv, b.ts, b.perm,
-              tie, b.wshift, b.hshift, b.skel_key, b.skel_tail, b.skel_tid);
+              tie, b.wshift, b.hshift, b.skel_key, b.skel_tail, b.skel_tid, b.best);
   CE_HIP(hipGetLastError());
   ws.release(m0);
   return CE_OK;

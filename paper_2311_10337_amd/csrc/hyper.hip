@@ -80,6 +80,9 @@ __global__ void k_hinit_hdr(uint64_t *hdr) {
 __global__ void k_hzero(uint64_t *p) {
   if (threadIdx.x == 0) *p = 0;
 }
+__global__ __launch_bounds__(B) void k_hfill_best(uint64_t *best, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < n; i += (int64_t)gridDim.x * B) best[i] = NONE64;
+}
 
 __global__ __launch_bounds__(B) void k_htkeys(const int64_t *t, int64_t n, int64_t tmin, uint64_t *keys) {
   for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < n; i += (int64_t)gridDim.x * B)
@@ -152,14 +155,19 @@ __global__ __launch_bounds__(B) void k_hrun_max(const uint32_t *start, const uin
 __global__ __launch_bounds__(B) void k_hemit(const uint32_t *sk, const uint32_t *sv, const uint32_t *pos,
                                              int64_t nnz, const uint64_t *ts, const uint32_t *perm, const uint32_t *f,
                                              const uint32_t *fx, const uint32_t *start, int wshift, int hshift,
-                                             uint64_t *skel_key, uint32_t *skel_tail, uint32_t *skel_head) {
+                                             uint64_t *skel_key, uint32_t *skel_tail, uint32_t *skel_head,
+                                             uint64_t *best) {
   for (int64_t k = (int64_t)blockIdx.x * B + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * B) {
     if (pos[k + 1] == pos[k]) continue;
     const uint32_t tl = sv[k - 1], hd = sv[k], e = pos[k];
     const uint32_t tie = start[fx[tl] + f[tl]] - 1u - tl;
-    skel_key[e] = ((ts[hd] - ts[tl]) << wshift) | ((uint64_t)perm[hd] << hshift) | (uint64_t)tie;
+    const uint64_t key = ((ts[hd] - ts[tl]) << wshift) | ((uint64_t)perm[hd] << hshift) | (uint64_t)tie;
+    skel_key[e] = key;
     skel_tail[e] = tl;
     skel_head[e] = hd;
+    // each row offers its key to both hyperedges' first Boruvka minimum
+    atomicMin((unsigned long long *)&best[tl], (unsigned long long)key);
+    atomicMin((unsigned long long *)&best[hd], (unsigned long long)key);
   }
 }
 
@@ -284,9 +292,10 @@ ce_status stage_hyper_skeleton(const int32_t *members, const int64_t *offsets, c
               "times - 1) > 64");
     return CE_ERANGE;
   }
+  CE_LAUNCH(k_hfill_best, dim3(grid_for(n, B)), dim3(B), 0, s, b.best, n);
   if (nnz > 0)
     CE_LAUNCH(k_hemit, dim3(grid_for(nnz, B)), dim3(B), 0, s, sk, sv, pos, nnz, b.ts, b.perm, f, fx, start,
-              b.wshift, b.hshift, b.skel_key, b.skel_tail, b.skel_tid);
+              b.wshift, b.hshift, b.skel_key, b.skel_tail, b.skel_tid, b.best);
   CE_HIP(hipGetLastError());
   ws.release(m0);
   return CE_OK;

@@ -217,7 +217,7 @@ __global__ __launch_bounds__(B) void k_bv_hook(int64_t C, const uint64_t *best, 
       const uint32_t o = eu[i] == (uint32_t)c ? ev[i] : eu[i];
       if (!(best[o] == bk && (uint32_t)c < o)) {
         to = o;
-        msf_flag[eslot[i]] = 1;
+        msf_flag[eslot ? eslot[i] : i] = 1;
         keep[k] = true;
       }
     }
@@ -329,7 +329,7 @@ __global__ __launch_bounds__(B) void k_contract(int64_t E, const uint64_t *key, 
     okey[p] = key[i];
     ou[p] = nu[k];
     ov[p] = nv[k];
-    oslot[p] = eslot[i];
+    oslot[p] = eslot ? eslot[i] : (uint32_t)i;
   }
 }
 
@@ -407,17 +407,6 @@ __global__ __launch_bounds__(B) void k_msf_list(const uint8_t *flag, int64_t n2,
   tile_append(keep, vals, out, cnt);
 }
 
-// flat skeleton rows (key, tail rank, head rank) as live edge records
-__global__ __launch_bounds__(B) void k_edges_from_skeleton(int64_t S, const uint64_t *skel_key,
-                                                           const uint32_t *skel_tail, const uint32_t *skel_head,
-                                                           uint64_t *key, uint32_t *eu, uint32_t *ev, uint32_t *es) {
-  for (int64_t e = (int64_t)blockIdx.x * B + threadIdx.x; e < S; e += (int64_t)gridDim.x * B) {
-    key[e] = skel_key[e];
-    eu[e] = skel_tail[e];
-    ev[e] = skel_head[e];
-    es[e] = (uint32_t)e;
-  }
-}
 
 // flat rows keep the head rank in skel_tid; the tail id comes from perm
 __global__ __launch_bounds__(B) void k_msf_gather_causal(const uint32_t *list, int64_t m, const uint64_t *skel_key,
@@ -607,20 +596,28 @@ ce_status stage_boruvka(Bufs &b, Ws &ws, hipStream_t s) {
   CE_WS_CHECK(ws);
   uint32_t *rankof = b.rankof;  // kept for writing the per-record outputs in input order
   CE_LAUNCH(k_rankof, dim3(grid_for(n, B)), dim3(B), 0, s, b.perm, n, rankof);
-  uint64_t *best = b.best;  // seeded for round 1 while emitting the skeleton
+  uint64_t *best = b.best;  // seeded for round 1 while the skeleton was emitted
   unsigned long long *cnt = (unsigned long long *)&b.hdr[4];
   CE_LAUNCH(k_fill_u8, dim3(grid_for(n2, B)), dim3(B), 0, s, b.msf_flag, n2, (uint8_t)0);
   int64_t E = 0, C = 0;
-  int cur = 0, rounds = 0;
+  int rounds = 0;
   uint64_t nact = 0;
   uint64_t hv[2];
+  // live edges of the current round (input) and the buffer the contraction writes
+  const uint64_t *ik = key[0];
+  const uint32_t *iu = eu[0], *iv = ev[0], *is = es[0];
+  int ob = 1;
+  bool seeded = false;
   if (b.flat) {
     // causal and hypergraph skeleton rows can share a head, so every round,
-    // the first included, runs on the edge-list form with records as components
-    if (b.S > 0)
-      CE_LAUNCH(k_edges_from_skeleton, dim3(grid_for(b.S, B)), dim3(B), 0, s, b.S, b.skel_key, b.skel_tail,
-                b.skel_tid, key[0], eu[0], ev[0], es[0]);
-    CE_HIP(hipGetLastError());
+    // the first included, runs on the edge-list form with records as
+    // components; the first reads the skeleton rows in place (slot = row)
+    ik = b.skel_key;
+    iu = b.skel_tail;
+    iv = b.skel_tid;
+    is = nullptr;
+    ob = 0;
+    seeded = true;
     E = b.S;
     C = n;
   } else {
@@ -659,12 +656,14 @@ ce_status stage_boruvka(Bufs &b, Ws &ws, hipStream_t s) {
       set_error("Boruvka did not converge");
       return CE_EDEVICE;
     }
-    CE_LAUNCH(k_fill_u64, dim3(grid_for(C, B)), dim3(B), 0, s, best, C, NONE64);
-    CE_LAUNCH(k_bv_min, dim3(tiles_for(E)), dim3(B), 0, s, E, key[cur], eu[cur], ev[cur], best);
-    CE_LAUNCH(k_bv_pick, dim3(grid_for(E, B)), dim3(B), 0, s, E, key[cur], eu[cur], ev[cur], best, bidx);
+    if (!seeded) {
+      CE_LAUNCH(k_fill_u64, dim3(grid_for(C, B)), dim3(B), 0, s, best, C, NONE64);
+      CE_LAUNCH(k_bv_min, dim3(tiles_for(E)), dim3(B), 0, s, E, ik, iu, iv, best);
+    }
+    seeded = false;
+    CE_LAUNCH(k_bv_pick, dim3(grid_for(E, B)), dim3(B), 0, s, E, ik, iu, iv, best, bidx);
     CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[4], (uint64_t)0);
-    CE_LAUNCH(k_bv_hook, dim3(tiles_for(C)), dim3(B), 0, s, C, best, bidx, eu[cur], ev[cur], es[cur], hook,
-              b.msf_flag, act, cnt);
+    CE_LAUNCH(k_bv_hook, dim3(tiles_for(C)), dim3(B), 0, s, C, best, bidx, iu, iv, is, hook, b.msf_flag, act, cnt);
     CE_HIP(hipGetLastError());
     CE_TRY(read_u64(&b.hdr[4], &nact, 1, s));
     CE_TRY(jump_all(act, act2, nact, hook, b, s));
@@ -673,8 +672,8 @@ ce_status stage_boruvka(Bufs &b, Ws &ws, hipStream_t s) {
     CE_TRY(scan_exclusive_u32(flags, newid, C, ws, s));
     CE_LAUNCH(k_final_ids, dim3(grid_for(C, B)), dim3(B), 0, s, C, hook, newid, flags);
     CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[4], (uint64_t)0);
-    CE_LAUNCH(k_contract, dim3(tiles_for(E)), dim3(B), 0, s, E, key[cur], eu[cur], ev[cur], es[cur], flags,
-              key[1 - cur], eu[1 - cur], ev[1 - cur], es[1 - cur], cnt);
+    CE_LAUNCH(k_contract, dim3(tiles_for(E)), dim3(B), 0, s, E, ik, iu, iv, is, flags, key[ob], eu[ob], ev[ob],
+              es[ob], cnt);
     CE_HIP(hipGetLastError());
     {
       uint32_t *h = (uint32_t *)pinned_scratch();
@@ -688,7 +687,11 @@ ce_status stage_boruvka(Bufs &b, Ws &ws, hipStream_t s) {
     }
     E = (int64_t)hv[0];
     C = (int64_t)hv[1];
-    cur = 1 - cur;
+    ik = key[ob];
+    iu = eu[ob];
+    iv = ev[ob];
+    is = es[ob];
+    ob = 1 - ob;
   }
   ws.release(m0);
   return CE_OK;
