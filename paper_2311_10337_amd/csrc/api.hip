@@ -86,22 +86,23 @@ __global__ __launch_bounds__(B) void k_rows(const uint64_t *msf_key, const uint6
                                             const uint32_t *kc_u,
                                             const uint32_t *kc_v, const uint32_t *ksize, const uint32_t *rowg,
                                             const uint32_t *rowpos, const uint32_t *moff, const int64_t *eoff,
-                                            int64_t m, int64_t n, int idbits, int wshift, int hshift,
+                                            int64_t m, int64_t n, int idbits, int wshift, int hshift, bool one,
                                             ce_result out) {
   const uint64_t idmask = (uint64_t(1) << idbits) - 1;
   for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
     const uint32_t tr = (uint32_t)msf_val[j];
     const uint64_t key = msf_key[j];
     const int64_t w = (int64_t)(key >> wshift);
-    const uint32_t g = rowg[j], p = rowpos[j], m0 = moff[g];
-    const uint32_t e0 = (uint32_t)eoff[g], ng = (uint32_t)(eoff[g + 1] - eoff[g]);
+    // one graph: rows stay in place and local ids are the internal ones
+    const uint32_t g = one ? 0u : rowg[j], p = one ? (uint32_t)j : rowpos[j], m0 = one ? 0u : moff[g];
+    const uint32_t e0 = one ? 0u : (uint32_t)eoff[g], ng = one ? (uint32_t)n : (uint32_t)(eoff[g + 1] - eoff[g]);
     const uint32_t tid = perm[tr] - e0, hid = (uint32_t)((key >> hshift) & idmask) - e0;
     if (out.msf_tail) out.msf_tail[p] = tid;
     if (out.msf_head) out.msf_head[p] = hid;
     if (out.msf_w) out.msf_w[p] = w;
     const uint32_t a = kc_u[j], b = kc_v[j];
-    const uint32_t fa = a < (uint64_t)n ? (a == tr ? tid : hid) : ng + (rowpos[a - n] - m0);
-    const uint32_t fb = b < (uint64_t)n ? (b == tr ? tid : hid) : ng + (rowpos[b - n] - m0);
+    const uint32_t fa = a < (uint64_t)n ? (a == tr ? tid : hid) : (one ? a : ng + (rowpos[a - n] - m0));
+    const uint32_t fb = b < (uint64_t)n ? (b == tr ? tid : hid) : (one ? b : ng + (rowpos[b - n] - m0));
     if (out.sl_left) out.sl_left[p] = fa < fb ? fa : fb;
     if (out.sl_right) out.sl_right[p] = fa < fb ? fb : fa;
     if (out.sl_w) out.sl_w[p] = w;
@@ -180,7 +181,7 @@ ce_status stage_graph_rows(Bufs &b, int64_t m, Ws &ws, hipStream_t s, int64_t *r
 ce_status stage_write_rows(Bufs &b, int64_t m, const ce_result *out, hipStream_t s) {
   if (m <= 0) return CE_OK;
   CE_LAUNCH(k_rows, dim3(grid_for(m, B)), dim3(B), 0, s, b.msf_key, b.msf_val, b.perm, b.kc_u, b.kc_v, b.ksize, b.rowg,
-            b.rowpos, b.moff, b.eoff, m, b.n, b.idbits, b.wshift, b.hshift, *out);
+            b.rowpos, b.moff, b.eoff, m, b.n, b.idbits, b.wshift, b.hshift, b.G == 1, *out);
   CE_HIP(hipGetLastError());
   return CE_OK;
 }
