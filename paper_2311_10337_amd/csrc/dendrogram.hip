@@ -46,15 +46,28 @@ __device__ inline uint2 ld2(const uint4 *e) {
   return make_uint2((uint32_t)v, (uint32_t)(v >> 32));
 }
 
-// root at the start of sub-interval q: links made during q (or later) are not followed
-__device__ inline uint32_t g_find_before(uint4 *uf, uint32_t x, uint32_t q) {
+// The same 8 bytes through the caches, possibly stale: what it returns was the
+// entry's content at some time since the kernel started. A parent always has
+// a smaller label than its child (hooks put the larger root under the smaller,
+// halving moves a link to a grandparent), so a walk over stale links still
+// ends, and every node it meets is an ancestor. Used where that is enough:
+// finds that only follow links made by earlier kernels.
+__device__ inline uint2 ld2_cached(const uint4 *e) {
+  const uint64_t v = __hip_atomic_load((const uint64_t *)e, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  return make_uint2((uint32_t)v, (uint32_t)(v >> 32));
+}
+
+// root at the start of sub-interval q, from x and its entry e: links made
+// during q (or later) are not followed, and every older link was made before
+// this kernel, so a stale view of them is still exact
+__device__ inline uint32_t g_find_before(uint4 *uf, uint32_t x, uint2 e, uint32_t q) {
   while (true) {
-    const uint2 e = ld2(&uf[x]);
     if (e.x == x || e.y >= q) return x;
-    const uint2 pe = ld2(&uf[e.x]);
+    const uint2 pe = ld2_cached(&uf[e.x]);
     if (pe.x == e.x || pe.y >= q) return e.x;
     st(&uf[x].x, pe.x);  // both links are older than q
     x = pe.x;
+    e = ld2_cached(&uf[x]);
   }
 }
 
@@ -71,17 +84,38 @@ __device__ inline uint32_t g_find(uint4 *uf, uint32_t x, uint32_t q) {
   }
 }
 
+// the final root once every link of the level so far is in place (no hooks
+// run concurrently, only halving): a stale view ends at the same root
+__device__ inline uint32_t g_find_done(uint4 *uf, uint32_t x) {
+  while (true) {
+    const uint2 e = ld2_cached(&uf[x]);
+    if (e.x == x) return x;
+    const uint2 pe = ld2_cached(&uf[e.x]);
+    if (pe.x == e.x) return e.x;
+    st(&uf[x].x, pe.x);
+    x = pe.x;
+  }
+}
+
 // hooks the larger of the two roots under the smaller during sub-interval q;
-// returns the hooked root
+// returns the hooked root. a and b are the roots at the start of q, so the
+// first attempt hooks without another find: it fails only when the larger one
+// was hooked during q, and the loop then finds the current roots.
 __device__ inline uint32_t g_union(uint4 *uf, uint32_t a, uint32_t b, uint32_t q) {
+  if (a == b) return NONE32;
+  const unsigned long long to = (unsigned long long)q << 32;
+  {
+    const uint32_t hi = a > b ? a : b, lo = a > b ? b : a;
+    const unsigned long long want = ((unsigned long long)NONE32 << 32) | hi;
+    if (atomicCAS((unsigned long long *)&uf[hi], want, to | lo) == want) return hi;
+  }
   while (true) {
     a = g_find(uf, a, q);
     b = g_find(uf, b, q);
     if (a == b) return NONE32;
     const uint32_t hi = a > b ? a : b, lo = a > b ? b : a;
     const unsigned long long want = ((unsigned long long)NONE32 << 32) | hi;
-    const unsigned long long to = ((unsigned long long)q << 32) | lo;
-    if (atomicCAS((unsigned long long *)&uf[hi], want, to) == want) return hi;
+    if (atomicCAS((unsigned long long *)&uf[hi], want, to | lo) == want) return hi;
   }
 }
 
@@ -129,13 +163,14 @@ __global__ __launch_bounds__(B) void k_krt_union(int64_t m, int64_t n, int lo, i
     if (j >= m) continue;
     uint32_t a = lu[j], b = lv[j];
     if (q) {
-      a = g_find_before(uf, a, q);
+      const uint2 ea = ld2_cached(&uf[a]), eb = ld2_cached(&uf[b]);  // both walks start at once
+      a = g_find_before(uf, a, ea, q);
+      b = g_find_before(uf, b, eb, q);
       const uint4 na = uf[a];
       if (na.z) {
         lu[j] = (uint32_t)(n + na.z - 1);
         su[j] = na.w;
       }
-      b = g_find_before(uf, b, q);
       const uint4 nb = uf[b];
       if (nb.z) {
         lv[j] = (uint32_t)(n + nb.z - 1);
@@ -164,7 +199,7 @@ __global__ __launch_bounds__(B) void k_krt_accum(int64_t m, int lo, int hi, uint
     uint32_t h = NONE32, f = 0, add = 0, mj = 0;
     if (j < m) h = hooked[j];
     if (h != NONE32) {
-      f = g_find(uf, h, NONE32);  // every link is complete now: full halving
+      f = g_find_done(uf, h);  // every link of sub-interval q is in place
       add = uf[h].w;
       mj = (uint32_t)(j + 1);
     }
@@ -207,24 +242,31 @@ constexpr int HS = 4 * LS;        // hash slots (load factor <= 1/2)
 constexpr int LB = 512;           // threads per interval: one per row
 constexpr uint32_t EMPTY = 0xffffffffu;
 
-__device__ inline uint32_t l_find(volatile uint32_t *uf, uint32_t x) {
+// LDS union-find; relaxed workgroup-scope atomics (not volatile, which would
+// turn the accesses into flat ones)
+__device__ inline uint32_t l_ld(uint32_t *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP); }
+
+__device__ inline uint32_t l_find(uint32_t *uf, uint32_t x) {
   while (true) {
-    uint32_t p = uf[x];
+    uint32_t p = l_ld(&uf[x]);
     if (p == x) return x;
-    uint32_t gp = uf[p];
+    uint32_t gp = l_ld(&uf[p]);
     if (gp == p) return p;
-    uf[x] = gp;
+    __hip_atomic_store(&uf[x], gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     x = gp;
   }
 }
 
-__device__ inline uint32_t l_union(volatile uint32_t *uf, uint32_t a, uint32_t b) {
+__device__ inline uint32_t l_union(uint32_t *uf, uint32_t a, uint32_t b) {
   while (true) {
     a = l_find(uf, a);
     b = l_find(uf, b);
     if (a == b) return EMPTY;
     uint32_t hi = a > b ? a : b, lo = a > b ? b : a;
-    if (atomicCAS((uint32_t *)&uf[hi], hi, lo) == hi) return hi;
+    uint32_t want = hi;
+    if (__hip_atomic_compare_exchange_strong(&uf[hi], &want, lo, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_WORKGROUP))
+      return hi;
   }
 }
 
@@ -281,7 +323,7 @@ __global__ __launch_bounds__(LB) void k_krt_lds(const uint32_t *lu, const uint32
     lsz[id] = isv ? sv[base + r] : su[base + r];
   }
   __syncthreads();
-  volatile uint32_t *vuf = luf;
+  uint32_t *vuf = luf;
   // 4. binary levels inside the interval
   for (int bit = LS_BITS - 1; bit >= 0; bit--) {
     for (int i = tid; i < cnt; i += LB) {
