@@ -16,6 +16,8 @@
 // where bit orders the (at most two) edges sharing a head by descending tail
 // id. Edges with equal keys (a pair consecutive in both endpoint lists) are
 // the same line-graph edge; one copy is dropped.
+#include <algorithm>
+
 #include "ce_internal.h"
 
 namespace ce {
@@ -333,6 +335,52 @@ __global__ __launch_bounds__(B) void k_contract(int64_t E, const uint64_t *key, 
   }
 }
 
+// Filter split (Filter-Kruskal applied to Borůvka): the live edges with key
+// below a pivot go to the front of the output lists, the others to their
+// back, counted down from `cap`. Light and heavy together are E <= cap
+// entries, so later contractions of the light part, which only shrink it,
+// never reach the heavy part.
+__global__ __launch_bounds__(B) void k_split(int64_t E, const uint64_t *key, const uint32_t *eu, const uint32_t *ev,
+                                             const uint32_t *eslot, uint64_t pivot, int64_t cap, uint64_t *okey,
+                                             uint32_t *ou, uint32_t *ov, uint32_t *oslot, unsigned long long *nlight,
+                                             unsigned long long *nheavy) {
+  bool lt[CT], ge[CT];
+  uint32_t pl[CT], ph[CT];
+  uint64_t kk[CT];
+  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
+#pragma unroll
+  for (int k = 0; k < CT; k++) {
+    const int64_t i = base + (int64_t)k * B;
+    kk[k] = i < E ? key[i] : 0;
+    lt[k] = i < E && kk[k] < pivot;
+    ge[k] = i < E && kk[k] >= pivot;
+  }
+  tile_positions(lt, pl, nlight);
+  tile_positions(ge, ph, nheavy);
+#pragma unroll
+  for (int k = 0; k < CT; k++) {
+    if (!lt[k] && !ge[k]) continue;
+    const int64_t i = base + (int64_t)k * B;
+    const int64_t p = lt[k] ? (int64_t)pl[k] : cap - 1 - (int64_t)ph[k];
+    okey[p] = kk[k];
+    ou[p] = eu[i];
+    ov[p] = ev[i];
+    oslot[p] = eslot ? eslot[i] : (uint32_t)i;
+  }
+}
+
+// root of every component of the split graph after another light round:
+// hook maps this round's roots to their new roots
+__global__ __launch_bounds__(B) void k_compose_roots(int64_t C, const uint32_t *hook, uint32_t *rootof, bool first) {
+  for (int64_t c = (int64_t)blockIdx.x * B + threadIdx.x; c < C; c += (int64_t)gridDim.x * B)
+    rootof[c] = hook[first ? (uint32_t)c : rootof[c]];
+}
+
+// evenly spaced keys of the live list, for the pivot
+__global__ void k_sample_keys(int64_t E, const uint64_t *key, int S, uint64_t *out) {
+  for (int i = threadIdx.x; i < S; i += blockDim.x) out[i] = key[(int64_t)((unsigned __int128)i * E / S)];
+}
+
 // per component, the minimum key over its live edges. A tile of 4096 edges
 // first takes per-component minima in an LDS hash (late rounds send most
 // edges to a few big components), then one atomicMin per component per tile.
@@ -559,6 +607,54 @@ size_t stage_boruvka_scratch(int64_t n, int64_t slots) {
 
 static unsigned tiles_for(int64_t n) { return (unsigned)((n + (int64_t)B * CT - 1) / ((int64_t)B * CT)); }
 
+// A contraction's edge count (a u64 counter on the device) and the number of
+// components (the total of the dense-id scan, a u32): hv[0], hv[1].
+static ce_status read_count_and_total(const uint64_t *count, const uint32_t *total, uint64_t *hv, hipStream_t s) {
+  uint32_t *h = (uint32_t *)pinned_scratch();
+  if (!h) {
+    set_error("hipHostMalloc of the readback buffer failed");
+    return CE_EDEVICE;
+  }
+  // word 16 of the pinned page is ours; read_u64 uses the first 64 bytes
+  CE_HIP(hipMemcpyAsync(h + 16, total, 4, hipMemcpyDeviceToHost, s));
+  CE_TRY(read_u64(count, hv, 1, s));  // synchronises the stream
+  hv[1] = h[16];
+  return CE_OK;
+}
+
+// The filter split runs when the live edges number at least 2^20 and more
+// than twice the components. The environment variable CE_SPLIT_MIN_EDGES
+// (read on every call) overrides the 2^20; 0 turns the split off.
+constexpr int SPLIT_SAMPLES = 256;
+static int64_t split_min_edges() {
+  const char *e = getenv("CE_SPLIT_MIN_EDGES");
+  if (!e) return int64_t(1) << 20;
+  const long long v = atoll(e);
+  return v > 0 ? (int64_t)v : INT64_MAX;
+}
+
+// Pivot of the filter split: about C edges (one per component) fall below it.
+// The key of rank ~C*S/E among S evenly spaced samples of the live list.
+// `dev` holds S keys of device scratch.
+static ce_status split_pivot(const uint64_t *key, int64_t E, int64_t C, uint64_t *dev, hipStream_t s,
+                             uint64_t *pivot) {
+  uint64_t *h = pinned_scratch();
+  if (!h) {
+    set_error("hipHostMalloc of the readback buffer failed");
+    return CE_EDEVICE;
+  }
+  uint64_t *hs = h + 128;  // bytes 1024 .. 3071 of the page
+  CE_LAUNCH(k_sample_keys, dim3(1), dim3(B), 0, s, E, key, SPLIT_SAMPLES, dev);
+  CE_HIP(hipGetLastError());
+  CE_HIP(hipMemcpyAsync(hs, dev, sizeof(uint64_t) * SPLIT_SAMPLES, hipMemcpyDeviceToHost, s));
+  CE_HIP(hipStreamSynchronize(s));
+  std::sort(hs, hs + SPLIT_SAMPLES);
+  int64_t q = (int64_t)((unsigned __int128)SPLIT_SAMPLES * (uint64_t)C / (uint64_t)E);
+  if (q > SPLIT_SAMPLES - 1) q = SPLIT_SAMPLES - 1;
+  *pivot = hs[q];
+  return CE_OK;
+}
+
 // pointer jumping until every hooked component points at its final root
 static ce_status jump_all(uint32_t *&act, uint32_t *&act2, uint64_t nact, uint32_t *hook, Bufs &b, hipStream_t s) {
   for (int it = 0; nact > 0; it++) {
@@ -636,13 +732,7 @@ ce_status stage_boruvka(Bufs &b, Ws &ws, hipStream_t s) {
     CE_LAUNCH(k_contract_first, dim3(tiles_for(n2)), dim3(B), 0, s, n2, b.skel_key, b.skel_tail, flags,
               key[0], eu[0], ev[0], es[0], cnt);
     CE_HIP(hipGetLastError());
-    {
-      // word 16 of the pinned page is ours; read_u64 uses the first words
-      uint32_t *h = (uint32_t *)pinned_scratch();
-      CE_HIP(hipMemcpyAsync(h + 16, newid + n, 4, hipMemcpyDeviceToHost, s));
-      CE_TRY(read_u64(&b.hdr[4], hv, 1, s));  // synchronises the stream
-      hv[1] = h[16];
-    }
+    CE_TRY(read_count_and_total(&b.hdr[4], newid + n, hv, s));
     E = (int64_t)hv[0];
     C = (int64_t)hv[1];
     if (E > n2 || C > n) {
@@ -651,7 +741,51 @@ ce_status stage_boruvka(Bufs &b, Ws &ws, hipStream_t s) {
     }
     rounds = 1;
   }
+  // Filter split. When live edges far outnumber components, most of them run
+  // between components that later rounds merge anyway, and every round would
+  // scan them again. So the list is split at a pivot key: Borůvka runs on the
+  // light edges (key below the pivot) alone until none is left, then the heavy
+  // ones are contracted once and rounds go on with the survivors. Keys are
+  // unique, so the forest is the same: a light edge outside the light forest
+  // is the largest on a cycle of light edges, and contracting the light forest
+  // keeps every heavy edge's cycles. During the light phase components keep
+  // the ids they had at the split (no renumbering) and rootof, in newid, maps
+  // each of them to its current root; the heavy edges wait at the back of the
+  // output lists of buffer hb.
+  const int64_t split_min = split_min_edges();
+  bool light = false, first_light = false;
+  int hb = 0;
+  int64_t Eh = 0;
+  uint32_t *rootof = newid;
   while (E > 0) {
+    // (bidx, n words, holds the pivot samples)
+    if (!light && !seeded && E >= split_min && E > 2 * C && n * 4 >= SPLIT_SAMPLES * 8) {
+      uint64_t pivot = 0;
+      CE_TRY(split_pivot(ik, E, C, (uint64_t *)bidx, s, &pivot));
+      CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[4], (uint64_t)0);
+      CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[5], (uint64_t)0);
+      CE_LAUNCH(k_split, dim3(tiles_for(E)), dim3(B), 0, s, E, ik, iu, iv, is, pivot, n2, key[ob], eu[ob], ev[ob],
+                es[ob], cnt, (unsigned long long *)&b.hdr[5]);
+      CE_HIP(hipGetLastError());
+      CE_TRY(read_u64(&b.hdr[4], hv, 2, s));
+      if ((int64_t)(hv[0] + hv[1]) != E) {
+        set_error("internal: filter split lost edges");
+        return CE_EDEVICE;
+      }
+      const int64_t El = (int64_t)hv[0];
+      Eh = (int64_t)hv[1];
+      const int64_t off = El > 0 ? 0 : n2 - Eh;  // no light edge: the heavy ones are the whole list
+      ik = key[ob] + off;
+      iu = eu[ob] + off;
+      iv = ev[ob] + off;
+      is = es[ob] + off;
+      if (El > 0) {
+        light = first_light = true;
+        hb = ob;
+        E = El;
+      }
+      ob = 1 - ob;
+    }
     if (++rounds > 64) {
       set_error("Boruvka did not converge");
       return CE_EDEVICE;
@@ -667,31 +801,64 @@ ce_status stage_boruvka(Bufs &b, Ws &ws, hipStream_t s) {
     CE_HIP(hipGetLastError());
     CE_TRY(read_u64(&b.hdr[4], &nact, 1, s));
     CE_TRY(jump_all(act, act2, nact, hook, b, s));
-    CE_LAUNCH(k_root_flags, dim3(grid_for(C, B)), dim3(B), 0, s, C, hook, best, flags);
-    CE_HIP(hipGetLastError());
-    CE_TRY(scan_exclusive_u32(flags, newid, C, ws, s));
-    CE_LAUNCH(k_final_ids, dim3(grid_for(C, B)), dim3(B), 0, s, C, hook, newid, flags);
-    CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[4], (uint64_t)0);
-    CE_LAUNCH(k_contract, dim3(tiles_for(E)), dim3(B), 0, s, E, ik, iu, iv, is, flags, key[ob], eu[ob], ev[ob],
-              es[ob], cnt);
-    CE_HIP(hipGetLastError());
-    {
-      uint32_t *h = (uint32_t *)pinned_scratch();
-      CE_HIP(hipMemcpyAsync(h + 16, newid + C, 4, hipMemcpyDeviceToHost, s));
+    if (light) {
+      // ids stay; the edges' endpoints are this round's roots, hook gives their new ones
+      CE_LAUNCH(k_compose_roots, dim3(grid_for(C, B)), dim3(B), 0, s, C, hook, rootof, first_light);
+      first_light = false;
+      CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[4], (uint64_t)0);
+      CE_LAUNCH(k_contract, dim3(tiles_for(E)), dim3(B), 0, s, E, ik, iu, iv, is, hook, key[ob], eu[ob], ev[ob],
+                es[ob], cnt);
+      CE_HIP(hipGetLastError());
       CE_TRY(read_u64(&b.hdr[4], hv, 1, s));
-      hv[1] = h[16];
+      if ((int64_t)hv[0] > E) {
+        set_error("internal: contracted graph larger than its input");
+        return CE_EDEVICE;
+      }
+      E = (int64_t)hv[0];
+    } else {
+      CE_LAUNCH(k_root_flags, dim3(grid_for(C, B)), dim3(B), 0, s, C, hook, best, flags);
+      CE_HIP(hipGetLastError());
+      CE_TRY(scan_exclusive_u32(flags, newid, C, ws, s));
+      CE_LAUNCH(k_final_ids, dim3(grid_for(C, B)), dim3(B), 0, s, C, hook, newid, flags);
+      CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[4], (uint64_t)0);
+      CE_LAUNCH(k_contract, dim3(tiles_for(E)), dim3(B), 0, s, E, ik, iu, iv, is, flags, key[ob], eu[ob], ev[ob],
+                es[ob], cnt);
+      CE_HIP(hipGetLastError());
+      CE_TRY(read_count_and_total(&b.hdr[4], newid + C, hv, s));
+      if ((int64_t)hv[0] > E || (int64_t)hv[1] > C) {
+        set_error("internal: contracted graph larger than its input");
+        return CE_EDEVICE;
+      }
+      E = (int64_t)hv[0];
+      C = (int64_t)hv[1];
     }
-    if ((int64_t)hv[0] > E || (int64_t)hv[1] > C) {
-      set_error("internal: contracted graph larger than its input");
-      return CE_EDEVICE;
-    }
-    E = (int64_t)hv[0];
-    C = (int64_t)hv[1];
     ik = key[ob];
     iu = eu[ob];
     iv = ev[ob];
     is = es[ob];
     ob = 1 - ob;
+    if (light && E == 0) {
+      // light phase done: the heavy edges between different current roots
+      // go on (ids of the split, not renumbered; the next round renumbers)
+      const int64_t off = n2 - Eh;
+      const int to = 1 - hb;
+      CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[4], (uint64_t)0);
+      CE_LAUNCH(k_contract, dim3(tiles_for(Eh)), dim3(B), 0, s, Eh, key[hb] + off, eu[hb] + off, ev[hb] + off,
+                es[hb] + off, rootof, key[to], eu[to], ev[to], es[to], cnt);
+      CE_HIP(hipGetLastError());
+      CE_TRY(read_u64(&b.hdr[4], hv, 1, s));
+      if ((int64_t)hv[0] > Eh) {
+        set_error("internal: contracted graph larger than its input");
+        return CE_EDEVICE;
+      }
+      E = (int64_t)hv[0];
+      ik = key[to];
+      iu = eu[to];
+      iv = ev[to];
+      is = es[to];
+      ob = hb;
+      light = false;
+    }
   }
   ws.release(m0);
   return CE_OK;
