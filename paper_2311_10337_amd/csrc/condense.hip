@@ -320,29 +320,20 @@ __global__ __launch_bounds__(B) void k_root_rows(const uint32_t *bstart, int64_t
     rootrow[g] = bstart[g + 1] + (uint32_t)g;
 }
 
-__device__ inline uint64_t wave_sum64(uint64_t v) {
-  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-  return v;
-}
-
-// exact sums of 32-bit limbs; lanes with equal rows are combined first
-__device__ inline void wave_add_limbs(bool active, uint32_t row, uint64_t l0, uint64_t l1, uint64_t l2,
-                                      unsigned long long *acc) {
-  const int lane = threadIdx.x & 63;
-  uint64_t pending = __ballot(active);
-  while (pending) {
-    int leader = __ffsll((unsigned long long)pending) - 1;
-    uint32_t key = __shfl(row, leader, 64);
-    bool mine = active && row == key && ((pending >> lane) & 1ull);
-    uint64_t match = __ballot(mine);
-    uint64_t s0 = wave_sum64(mine ? l0 : 0), s1 = wave_sum64(mine ? l1 : 0), s2 = wave_sum64(mine ? l2 : 0);
-    if (lane == leader) {
-      if (s0) atomicAdd(&acc[3 * (uint64_t)key], (unsigned long long)s0);
-      if (s1) atomicAdd(&acc[3 * (uint64_t)key + 1], (unsigned long long)s1);
-      if (s2) atomicAdd(&acc[3 * (uint64_t)key + 2], (unsigned long long)s2);
-    }
-    pending &= ~match;
-  }
+// exact sums of 32-bit limbs into a row's three u64 accumulators: the lanes
+// sharing the wave's first row are summed first (one round; the others add on
+// their own), zero limbs are skipped
+__device__ inline void add_limbs(bool active, uint32_t row, uint64_t l0, uint64_t l1, uint64_t l2,
+                                 unsigned long long *acc) {
+  const bool upd = wave_combine_first(active, row, [&](bool mine, int leader) {
+    const uint64_t a0 = wave_sum_u64(mine ? l0 : 0ull), a1 = wave_sum_u64(mine ? l1 : 0ull),
+                   a2 = wave_sum_u64(mine ? l2 : 0ull);
+    if ((int)wave_lane() == leader) { l0 = a0; l1 = a1; l2 = a2; }
+  });
+  if (!upd) return;
+  if (l0) atomicAdd(&acc[3 * (uint64_t)row], (unsigned long long)l0);
+  if (l1) atomicAdd(&acc[3 * (uint64_t)row + 1], (unsigned long long)l1);
+  if (l2) atomicAdd(&acc[3 * (uint64_t)row + 2], (unsigned long long)l2);
 }
 
 constexpr int AHS = 512;  // LDS hash slots for per-cluster-row sums
@@ -458,7 +449,7 @@ __global__ __launch_bounds__(B) void k_cd_acc_children(const uint32_t *csize, co
     pr = cprow[r];
     prod = u128_mul64(csize[r], cbirth[r]);
   }
-  wave_add_limbs(act, pr, prod.lo & 0xffffffffull, prod.lo >> 32, prod.hi, acc);
+  add_limbs(act, pr, prod.lo & 0xffffffffull, prod.lo >> 32, prod.hi, acc);
 }
 
 // S = sum - size * birth  (exact u128)

@@ -185,7 +185,11 @@ __global__ __launch_bounds__(B) void k_bv_hook_first(int64_t n, const uint64_t *
     uint32_t to = (uint32_t)c;
     const uint64_t bk = best[c];
     if (bk != NONE64) {
-      const uint32_t e = slot_of_key(bk, idbits, rankof, skel_key);
+      // the minimum edge is one of c's own two head slots (read in order) or
+      // one where c is the tail (found through its head's rank)
+      const uint64_t k0 = skel_key[2 * c], k1 = skel_key[2 * c + 1];
+      const uint32_t e = k0 == bk ? (uint32_t)(2 * c)
+                                  : (k1 == bk ? (uint32_t)(2 * c + 1) : slot_of_key(bk, idbits, rankof, skel_key));
       const uint32_t tl = skel_tail[e], hd = e >> 1;
       const uint32_t o = (tl == (uint32_t)c) ? hd : tl;
       if (!(best[o] == bk && (uint32_t)c < o)) {

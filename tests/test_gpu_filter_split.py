@@ -3,8 +3,9 @@
 The split (light edges first, heavy edges contracted once afterwards) runs by
 default only from 2^20 live edges on, which the full-size and scaled workloads
 reach. CE_SPLIT_MIN_EDGES lowers that bar, so here it runs on graphs the
-oracle finishes in a moment, in every mode, at several thresholds (so it
-starts after different rounds), and must leave every output bit-exact.
+oracle finishes in a moment, in every mode and in a batch, at several
+thresholds (so it starts after different rounds), and must leave every
+output bit-exact.
 """
 import os
 
@@ -12,6 +13,7 @@ import numpy as np
 import pytest
 
 import synth
+import test_gpu_batch as batch
 import test_gpu_causal as causal
 import test_gpu_hyper as hyper
 import test_gpu_parity as undirected
@@ -78,6 +80,18 @@ def test_hypergraph(split_at):
         for thr in (1, 500):
             split_at(thr)
             hyper.check(mem, off, t, V, 4, "hyper split%d thr=%d" % (k, thr))
+
+
+def test_batch(split_at):
+    rng = np.random.default_rng(109)
+    graphs = []
+    for g in range(24):
+        n = int(rng.integers(1, 6000))
+        s, d, t, V = synth.batch_graph(g, n, seed=11)
+        graphs.append((s, d, t, V))
+    for thr in (1, 3000):
+        split_at(thr)
+        batch.check_batch_vs_oracle(graphs, 5, "batch thr=%d" % thr)
 
 
 def test_switched_off(split_at):
