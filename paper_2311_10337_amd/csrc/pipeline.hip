@@ -99,6 +99,32 @@ __global__ __launch_bounds__(B) void k_incidence(const uint4 *vals, int64_t n, u
   }
 }
 
+// One graph whose time span fits 32 bits: the id rides in the key's low half,
+// key = (t - tmin) << 32 | id, and the value is (src | dst << 32), so a radix
+// pass over bits [32, 32 + bits(span)) moves 16 bytes per record instead of 24.
+// Stability keeps ids in order within equal times either way.
+__global__ __launch_bounds__(B) void k_tkeys_packed(const int64_t *t, const int32_t *src, const int32_t *dst,
+                                                    int64_t n, int64_t tmin, uint64_t *keys, uint64_t *vals) {
+  for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < n; i += (int64_t)gridDim.x * B) {
+    keys[i] = ((uint64_t)(t[i] - tmin) << 32) | (uint64_t)i;
+    vals[i] = (uint64_t)(uint32_t)src[i] | ((uint64_t)(uint32_t)dst[i] << 32);
+  }
+}
+
+// incidence entries from the packed sort; also t - tmin by rank (keys may be ts itself)
+__global__ __launch_bounds__(B) void k_incidence_packed(const uint64_t *keys, const uint64_t *vals, int64_t n,
+                                                        uint64_t *ts, uint32_t *perm, uint32_t *grank,
+                                                        uint32_t *ikey) {
+  for (int64_t r = (int64_t)blockIdx.x * B + threadIdx.x; r < n; r += (int64_t)gridDim.x * B) {
+    const uint64_t k = keys[r], v = vals[r];
+    ts[r] = k >> 32;
+    perm[r] = (uint32_t)k;
+    grank[r] = 0;
+    ikey[2 * r] = (uint32_t)v;
+    ikey[2 * r + 1] = (uint32_t)(v >> 32);
+  }
+}
+
 // every incidence entry names its slot; the entry's predecessor in the same
 // vertex list is the tail of the skeleton edge stored there
 __global__ __launch_bounds__(B) void k_skel_tails(const uint32_t *ikey, const uint32_t *ival, int64_t n2,
@@ -567,12 +593,23 @@ ce_status stage_sort_skeleton(const int32_t *src, const int32_t *dst, const int6
   uint32_t *ival_alt = ws.alloc<uint32_t>(n2);
   CE_WS_CHECK(ws);
   // 1. records by (t, id)
+  // 2. incidence entries (vertex, 2*rank+side) in rank order, perm by rank
   {
     size_t m1 = ws.mark();
-    const uint4 *vals = nullptr;
-    CE_TRY(sort_records_by_time(src, dst, t, b, ws, s, &vals));
-    // 2. incidence entries (vertex, 2*rank+side) in rank order, perm by rank
-    CE_LAUNCH(k_incidence, dim3(grid_for(n, B)), dim3(B), 0, s, vals, n, b.perm, b.grank, ikey);
+    if (b.G == 1 && b.tbits <= 32) {
+      uint64_t *kalt = ws.alloc<uint64_t>(n), *v0 = ws.alloc<uint64_t>(n), *v1 = ws.alloc<uint64_t>(n);
+      CE_WS_CHECK(ws);
+      CE_LAUNCH(k_tkeys_packed, dim3(grid_for(n, B)), dim3(B), 0, s, t, src, dst, n, b.tmin, b.ts, v0);
+      CE_HIP(hipGetLastError());
+      bool alt = false;
+      CE_TRY((radix_sort_pairs<uint64_t, uint64_t>(b.ts, v0, kalt, v1, n, 32, 32 + b.tbits, false, &alt, ws, s)));
+      CE_LAUNCH(k_incidence_packed, dim3(grid_for(n, B)), dim3(B), 0, s, alt ? kalt : b.ts, alt ? v1 : v0, n, b.ts,
+                b.perm, b.grank, ikey);
+    } else {
+      const uint4 *vals = nullptr;
+      CE_TRY(sort_records_by_time(src, dst, t, b, ws, s, &vals));
+      CE_LAUNCH(k_incidence, dim3(grid_for(n, B)), dim3(B), 0, s, vals, n, b.perm, b.grank, ikey);
+    }
     CE_HIP(hipGetLastError());
     ws.release(m1);
   }
