@@ -38,6 +38,13 @@
  * the caller and must hold the documented row counts. Between calls the
  * library keeps only a 4 KiB pinned host page per calling thread (for the
  * small counts it reads back) and the servers the caller creates.
+ *
+ * Tuning (environment, optional; outputs never depend on them):
+ *   CE_KRT_LEVEL_BITS   1..10: largest number of row-index bits one global
+ *                       dendrogram level takes (read once per process)
+ *   CE_SPLIT_MIN_EDGES  live-edge count from which Boruvka splits its edges
+ *                       at a pivot key (default 2^20; 0 = never; read on
+ *                       every call)
  */
 #ifndef CE_H
 #define CE_H
