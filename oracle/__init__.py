@@ -65,6 +65,8 @@ def _load():
         lib.oracle_dendrogram.restype = ctypes.c_int
         lib.oracle_joined_below.argtypes = [i64, i64, p, p, p, i64, p, p, p, p]
         lib.oracle_joined_below.restype = ctypes.c_int
+        lib.oracle_level_components.argtypes = [i64, i64, p, p, p, i64, p, p]
+        lib.oracle_level_components.restype = ctypes.c_int
         lib.oracle_condense.argtypes = [i64, i64, p, p, p, p, i64] + [p] * 10 + [p]
         lib.oracle_condense_discrete.argtypes = [i64, i64, p, p, p, p, i64, i64, p] + [p] * 10 + [p, p, p]
         lib.oracle_condense_discrete.restype = ctypes.c_int
@@ -204,6 +206,21 @@ def joined_below(n, msf_tail, msf_head, msf_w, q_tail, q_head, q_w) -> np.ndarra
     if rc:
         raise RuntimeError("oracle_joined_below: %d" % rc)
     return out[:qt.size].astype(bool)
+
+
+def level_components(n, tail, head, w, thresholds) -> np.ndarray:
+    """Alg. 5 by components: labels[l, r] = smallest record id in r's component of the line graph restricted to
+    edges with w <= thresholds[l] (the given edges: full line graph, skeleton or forest), each level from scratch."""
+    tl = np.ascontiguousarray(tail, np.uint32)
+    hd = np.ascontiguousarray(head, np.uint32)
+    ww = np.ascontiguousarray(w, np.int64)
+    thr = np.ascontiguousarray(thresholds, np.int64)
+    out = np.empty(max(thr.size * int(n), 1), np.int32)
+    rc = _load().oracle_level_components(int(n), tl.size, tl.ctypes.data, hd.ctypes.data, ww.ctypes.data, thr.size,
+                                         thr.ctypes.data, out.ctypes.data)
+    if rc:
+        raise ValueError("oracle_level_components: %d" % rc)
+    return out[:thr.size * int(n)].reshape(thr.size, int(n))
 
 
 def max_clusters(n, M):

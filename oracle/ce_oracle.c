@@ -444,6 +444,46 @@ int oracle_joined_below(int64_t n, int64_t m, const uint32_t *msf_tail, const ui
   return OR_OK;
 }
 
+/*
+ * Alg. 5 as the paper computes it: the discrete dendrogram's level l is the
+ * partition of the records into connected components of the line graph that
+ * keeps only its edges with w <= thr[l]. The edges given may be the full
+ * line graph, the skeleton or the forest (Thm 3: all three have the same
+ * components at every threshold). Each level is computed on its own, from
+ * scratch: union every kept edge, then label each record with the smallest
+ * record id of its component. labels is level-major: labels[l*n + r].
+ * Thresholds must be strictly increasing and >= 0.
+ */
+int oracle_level_components(int64_t n, int64_t E, const uint32_t *tail, const uint32_t *head, const int64_t *w,
+                            int64_t q, const int64_t *thr, int32_t *labels) {
+  if (n < 0 || E < 0 || q < 0 || n > 0x7fffffffLL) return OR_EINVAL;
+  for (int64_t l = 0; l < q; l++)
+    if (thr[l] < 0 || (l > 0 && thr[l] <= thr[l - 1])) return OR_EINVAL;
+  for (int64_t e = 0; e < E; e++)
+    if (tail[e] >= (uint64_t)n || head[e] >= (uint64_t)n) return OR_EINVAL;
+  uint32_t *par = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n ? n : 1));
+  uint32_t *low = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n ? n : 1));
+  if (!par || !low) { free(par); free(low); return OR_ENOMEM; }
+  for (int64_t l = 0; l < q; l++) {
+    for (int64_t r = 0; r < n; r++) par[r] = (uint32_t)r;
+    for (int64_t e = 0; e < E; e++) {
+      if (w[e] > thr[l]) continue;
+      uint32_t a = uf_find(par, tail[e]), b = uf_find(par, head[e]);
+      if (a != b) par[a] = b;
+    }
+    /* smallest member of each component, kept at its root */
+    for (int64_t r = 0; r < n; r++) low[r] = UINT32_MAX;
+    for (int64_t r = 0; r < n; r++) {
+      uint32_t root = uf_find(par, (uint32_t)r);
+      if ((uint32_t)r < low[root]) low[root] = (uint32_t)r;
+    }
+    for (int64_t r = 0; r < n; r++) labels[l * n + r] = (int32_t)low[uf_find(par, (uint32_t)r)];
+  }
+  free(par);
+  free(low);
+  return OR_OK;
+}
+
 /* R5 */
 static uint64_t lam(int64_t w) {
   if (w <= 0) return (uint64_t)1 << 63;

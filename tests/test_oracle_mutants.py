@@ -1,6 +1,7 @@
 """Planted mistakes in the oracle (on the CPU): each mutated copy of the oracle's
 C source must fail at least one pin in test_oracle_pins.py,
-test_oracle_causal.py, test_oracle_discrete.py or test_oracle_hyper.py. This shows the pins
+test_oracle_causal.py, test_oracle_discrete.py, test_oracle_hyper.py or
+test_oracle_levels.py. This shows the pins
 would catch a dropped term, a wrong sign or index, or a transposed operand."""
 import os
 import subprocess
@@ -48,6 +49,9 @@ MUTANTS = [
      'qsort(lst + voff[x], (size_t)d, sizeof(uint32_t), cmp_rec); /* "sort the incident hyperedges" */',
      "/* unsorted */"),
     ("hyper: star instead of path", "out[cnt] = make_edge(prev, cur);", "out[cnt] = make_edge(lst[voff[x]], cur);"),
+    ("level components keep edges strictly below", "if (w[e] > thr[l]) continue;", "if (w[e] >= thr[l]) continue;"),
+    ("level components labelled by largest member", "if ((uint32_t)r < low[root]) low[root] = (uint32_t)r;",
+     "if (low[root] == UINT32_MAX || (uint32_t)r > low[root]) low[root] = (uint32_t)r;"),
 ]
 
 
@@ -65,6 +69,7 @@ def test_pins_catch_planted_mistake(name, old, new, tmp_path):
                         os.path.join(ROOT, "tests", "test_oracle_pins.py"),
                         os.path.join(ROOT, "tests", "test_oracle_causal.py"),
                         os.path.join(ROOT, "tests", "test_oracle_discrete.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_hyper.py"), "-k", "not four_records"],
+                        os.path.join(ROOT, "tests", "test_oracle_hyper.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_levels.py"), "-k", "not four_records"],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, "planted mistake '%s' passed every pin:\n%s" % (name, r.stdout[-2000:])
