@@ -61,6 +61,25 @@ def cpu_baseline(w, sample, causal=False, thresholds=None):
                          ", discrete dendrogram with %d thresholds" % len(thresholds) if thresholds else "", dt)}
 
 
+def bench_level_components(ce, r, n, thr, calls=3):
+    """Alg. 5 the paper's way, one connected-components pass per threshold (ce_level_components over the
+    forest the timed steps produced), next to the discrete dendrogram cut from the exact one in those steps."""
+    import torch
+    labels = torch.empty(len(thr) * n, dtype=torch.int32, device=r.msf_tail.device)
+    ce.level_components(r.msf_tail, r.msf_head, r.msf_w, n, thr, labels=labels)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        ce.level_components(r.msf_tail, r.msf_head, r.msf_w, n, thr, labels=labels)
+    torch.cuda.synchronize()
+    ms = 1e3 * (time.perf_counter() - t0) / calls
+    log("discrete dendrogram by per-level components: %.1f ms for %d levels" % (ms, len(thr)))
+    return {"ms_per_call": ms, "levels": len(thr), "rows": r.m, "records": n,
+            "note": "ce_level_components on the forest of the timed steps: one components pass per threshold "
+                    "(Alg. 5 as the paper computes it); the timed steps cut the same discrete dendrogram from "
+                    "the exact one"}
+
+
 def bench_hyper(dev, steps, warmup):
     """Dynamic hypergraph (Sec. 5.3): the 2e7-hyperedge multi-recipient workload through
     ce_cluster_hyperedges, inputs resident in HBM, workspace and outputs preallocated."""
@@ -378,6 +397,8 @@ def main():
     if roof is not None:
         line["roofline"] = roof
     line["hbm_pipeline"] = hbm
+    if thr:
+        line["discrete_by_components"] = bench_level_components(ce, r, w.n, thr)
     del src, dst, tt, outs, ws
     torch.cuda.empty_cache()
     if not args.no_batch:

@@ -179,6 +179,34 @@ ce_status ce_cluster_edges(const int32_t *src, const int32_t *dst, const int64_t
  *   <= 64, else CE_ERANGE. Errors: CE_EINVAL for bad offsets, CE_ERANGE for a
  * member outside [0, V); no output is written on an error.
  */
+/*
+ * Alg. 5 by connected components, as the paper computes the discrete
+ * dendrogram: one partition of the records per threshold, the components of
+ * the line graph keeping only its edges with w <= threshold. By Thm 3 (at
+ * every threshold) these are the components of the forest rows with
+ * w <= threshold, so this runs on the sorted MSF rows that ce_cluster_edges,
+ * ce_cluster_hyperedges or one graph of ce_cluster_batch wrote (any mode).
+ * It is the direct counterpart of the discrete dendrogram those calls cut
+ * from the exact one (dd_level / dd_top): a discrete node is a component
+ * that first appears at a level.
+ *   msf_tail, msf_head : uint32[m] DEVICE, record ids < n
+ *   msf_w              : int64[m] DEVICE, ascending (the forest's row order)
+ *   thresholds         : int64[q] HOST, >= 0, strictly increasing,
+ *                        q <= CE_MAX_THRESHOLDS
+ *   labels             : int32[q * n] DEVICE, level-major, caller-owned:
+ *                        labels[l*n + r] = the smallest record id in r's
+ *                        component at level l
+ *   stream             : a hipStream_t (NULL = default stream)
+ * Runs on `stream` and returns when the labels are written. Allocates
+ * 8 (2q + 1) bytes of device memory for the call (stream-ordered) and no
+ * workspace: each level's labels are the next level's union-find. q = 0 or
+ * n = 0 writes nothing. Errors: CE_EINVAL for bad arguments or rows not in
+ * ascending w, CE_ERANGE for a row naming a record >= n (labels then
+ * untouched).
+ */
+ce_status ce_level_components(const uint32_t *msf_tail, const uint32_t *msf_head, const int64_t *msf_w, int64_t m,
+                              int64_t n, const int64_t *thresholds, int64_t q, int32_t *labels, void *stream);
+
 size_t ce_hyper_workspace_bytes(int64_t n, int64_t nnz, const ce_params *params);
 
 ce_status ce_cluster_hyperedges(const int32_t *members, const int64_t *offsets, const int64_t *t, int64_t n,

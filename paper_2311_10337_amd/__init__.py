@@ -116,6 +116,10 @@ def load_library(path: str = LIB_PATH):
         lib.ce_workspace_bytes.restype = ctypes.c_size_t
         lib.ce_max_clusters.argtypes = [ctypes.c_int64, ctypes.c_int64]
         lib.ce_max_clusters.restype = ctypes.c_int64
+        lib.ce_level_components.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int64, ctypes.c_int64, i64p,
+                                                                    ctypes.c_int64, ctypes.c_void_p,
+                                                                    ctypes.c_void_p]
+        lib.ce_level_components.restype = ctypes.c_int
         lib.ce_last_error.argtypes = []
         lib.ce_last_error.restype = ctypes.c_char_p
         lib.ce_timing_enable.argtypes = [ctypes.c_char_p]
@@ -301,6 +305,39 @@ def cluster_hyperedges(members, offsets, t, min_cluster_size: int, num_vertices:
     if st != CE_OK:
         raise ClusterError(st, last_error())
     return _result(outputs, n, counts, params)
+
+
+def level_components(msf_tail, msf_head, msf_w, n: int, thresholds, labels=None, stream=None):
+    """Alg. 5 by connected components (``ce_level_components``): for each threshold, the partition of the n
+    records into components of the line graph restricted to w <= threshold, computed from the sorted forest
+    rows a clustering call returned (``Result.msf_tail``, ``msf_head``, ``msf_w``, GPU tensors). Returns an
+    int32 GPU tensor of shape (len(thresholds), n): the smallest record id of each record's component per
+    level. ``labels`` may be a preallocated contiguous int32 GPU tensor of at least len(thresholds) * n."""
+    import numpy as np
+    import torch
+    lib = load_library()
+    for name, x, dt in (("msf_tail", msf_tail, torch.int32), ("msf_head", msf_head, torch.int32),
+                        ("msf_w", msf_w, torch.int64)):
+        if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == dt and x.is_contiguous() and x.dim() == 1):
+            raise TypeError("%s must be a contiguous 1-D %s GPU tensor" % (name, dt))
+    m = int(msf_tail.numel())
+    if msf_head.numel() != m or msf_w.numel() != m:
+        raise ValueError("msf_tail, msf_head, msf_w must have the same length")
+    thr = np.ascontiguousarray(np.asarray(thresholds, dtype=np.int64).reshape(-1))
+    q, n = int(thr.size), int(n)
+    if labels is None:
+        labels = torch.empty(max(q * n, 1), dtype=torch.int32, device=msf_tail.device)
+    elif not (isinstance(labels, torch.Tensor) and labels.is_cuda and labels.dtype == torch.int32
+              and labels.is_contiguous() and labels.numel() >= q * n):
+        raise TypeError("labels must be a contiguous int32 GPU tensor of at least len(thresholds) * n entries")
+    s = stream if stream is not None else torch.cuda.current_stream(msf_tail.device)
+    st = lib.ce_level_components(ctypes.c_void_p(msf_tail.data_ptr()), ctypes.c_void_p(msf_head.data_ptr()),
+                                 ctypes.c_void_p(msf_w.data_ptr()), m, n,
+                                 thr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), q,
+                                 ctypes.c_void_p(labels.data_ptr()), ctypes.c_void_p(s.cuda_stream))
+    if st != CE_OK:
+        raise ClusterError(st, last_error(), call="ce_level_components")
+    return labels[:q * n].view(q, n)
 
 
 def _result(outputs, n, counts, params) -> Result:

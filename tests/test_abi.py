@@ -22,7 +22,7 @@ def test_library_exports_declared_symbols():
                          "ce_max_clusters", "ce_last_error", "ce_timing_enable", "ce_timing_read",
                          "ce_server_create", "ce_server_destroy", "ce_server_request_bytes", "ce_server_submit",
                          "ce_server_poll", "ce_server_get_stats", "ce_cluster_hyperedges",
-                         "ce_hyper_workspace_bytes"}
+                         "ce_hyper_workspace_bytes", "ce_level_components"}
     for s in syms:
         assert hasattr(lib, s), s
 
@@ -208,3 +208,24 @@ def test_earlier_params_layout_is_accepted():
     assert a == ce.workspace_bytes(1000, 100, 5) > 0
     v1.struct_size = 24
     assert lib.ce_workspace_bytes(1000, 100, ctypes.cast(ctypes.pointer(v1), ctypes.POINTER(ce.CeParams))) == 0
+
+
+def test_level_components_argument_errors_need_no_gpu():
+    """ce_level_components checks its arguments and thresholds on the host; q = 0 or n = 0 does nothing."""
+    import ctypes
+    import paper_2311_10337_amd as ce
+    if not os.path.exists(ce.LIB_PATH):
+        pytest.skip("libce.so not built")
+    lib = ce.load_library()
+    arr = lambda *v: (ctypes.c_int64 * max(len(v), 1))(*v)
+    call = lambda m, n, thr, q: lib.ce_level_components(None, None, None, m, n, thr, q, None, None)
+    assert call(0, 5, arr(), 0) == ce.CE_OK
+    assert call(0, 0, arr(3), 1) == ce.CE_OK
+    assert call(0, -1, arr(3), 1) == ce.CE_EINVAL
+    assert call(-1, 5, arr(3), 1) == ce.CE_EINVAL
+    assert call(0, 5, None, 1) == ce.CE_EINVAL
+    assert call(0, 5, arr(*range(65)), 65) == ce.CE_EINVAL
+    for bad in ((3, 3), (4, 2), (-1, 2)):
+        assert call(0, 5, arr(*bad), 2) == ce.CE_EINVAL
+        assert "increasing" in ce.last_error()
+    assert call(0, 5, arr(3), 1) == ce.CE_EINVAL  # labels NULL
