@@ -55,6 +55,19 @@ MUTANTS = [
 ]
 
 
+PIN_FILES = ["test_oracle_pins.py", "test_oracle_causal.py", "test_oracle_discrete.py", "test_oracle_hyper.py",
+             "test_oracle_levels.py"]
+# the pin file that covers a mutant's function runs first (pytest -x stops at the first failing pin); every
+# file still runs when it passes
+FIRST = {"causal": "test_oracle_causal.py", "discrete": "test_oracle_discrete.py", "hyper": "test_oracle_hyper.py",
+         "level": "test_oracle_levels.py", "time filter": "test_oracle_pins.py"}
+
+
+def pin_order(name):
+    first = next((f for k, f in FIRST.items() if name.startswith(k)), PIN_FILES[0])
+    return [first] + [f for f in PIN_FILES if f != first]
+
+
 @pytest.mark.slow
 @pytest.mark.parametrize("name,old,new", MUTANTS, ids=[m[0] for m in MUTANTS])
 def test_pins_catch_planted_mistake(name, old, new, tmp_path):
@@ -65,11 +78,7 @@ def test_pins_catch_planted_mistake(name, old, new, tmp_path):
     lib = tmp_path / "liboracle_mut.so"
     subprocess.check_call(["gcc", "-O1", "-shared", "-fPIC", "-o", str(lib), str(mut)])
     env = dict(os.environ, CE_ORACLE_LIB=str(lib))
-    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_causal.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_discrete.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_hyper.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_levels.py"), "-k", "not four_records"],
+    r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider"]
+                       + [os.path.join(ROOT, "tests", f) for f in pin_order(name)] + ["-k", "not four_records"],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, "planted mistake '%s' passed every pin:\n%s" % (name, r.stdout[-2000:])
