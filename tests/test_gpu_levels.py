@@ -131,6 +131,27 @@ def test_hypergraph():
         assert np.array_equal(got, ref), k
 
 
+def test_one_graph_of_a_batch():
+    """The rows of graph g of a batch (local ids, contiguous) give that graph's levels."""
+    import test_gpu_batch as batch
+    ce = _ce()
+    rng = np.random.default_rng(239)
+    graphs = []
+    for g in range(12):
+        s, d, t, V = synth.batch_graph(g, int(rng.integers(1, 4000)), seed=17)
+        graphs.append((s, d, t, V))
+    src, dst, t, eoff, voff = batch.pack(graphs)
+    note("batch of %d graphs n=%d" % (len(graphs), len(src)))
+    br = batch.run_batch(src, dst, t, eoff, voff, 5)
+    thr = [0, 60, 3600, 86400]
+    for g, (s, d, tt, V) in enumerate(graphs):
+        r0, r1 = int(br.row_offsets[g]), int(br.row_offsets[g + 1])
+        res = br.result
+        got = ce.level_components(res.msf_tail[r0:r1], res.msf_head[r0:r1], res.msf_w[r0:r1], len(tt),
+                                  thr).cpu().numpy()
+        assert np.array_equal(got, oracle_levels(s, d, tt, thr)), g
+
+
 def test_same_discrete_nodes_as_the_cut_dendrogram():
     ce = _ce()
     rng = np.random.default_rng(233)
