@@ -65,6 +65,12 @@ def bench_level_components(ce, r, n, thr, calls=3):
     """Alg. 5 the paper's way, one connected-components pass per threshold (ce_level_components over the
     forest the timed steps produced), next to the discrete dendrogram cut from the exact one in those steps."""
     import torch
+    need = 4 * len(thr) * n
+    free, _ = torch.cuda.mem_get_info(r.msf_tail.device)
+    if need > free:
+        log("per-level components skipped: %d levels of %d labels need %.1f GiB, %.1f GiB free"
+            % (len(thr), n, need / 2 ** 30, free / 2 ** 30))
+        return {"skipped": "labels of %d levels need %d bytes, %d free" % (len(thr), need, free)}
     labels = torch.empty(len(thr) * n, dtype=torch.int32, device=r.msf_tail.device)
     ce.level_components(r.msf_tail, r.msf_head, r.msf_w, n, thr, labels=labels)
     torch.cuda.synchronize()
@@ -397,9 +403,11 @@ def main():
     if roof is not None:
         line["roofline"] = roof
     line["hbm_pipeline"] = hbm
+    del ws
+    torch.cuda.empty_cache()
     if thr:
         line["discrete_by_components"] = bench_level_components(ce, r, w.n, thr)
-    del src, dst, tt, outs, ws
+    del src, dst, tt, outs
     torch.cuda.empty_cache()
     if not args.no_batch:
         line["batched"] = bench_batched(dev, max(1, min(args.steps, 3)), 1)
