@@ -1,19 +1,25 @@
 #!/usr/bin/env python3
 """Benchmark: temporal edges clustered per second on one MI355X.
 
-One step = one full clustering of the workload through the C ABI
-(group+sort by vertex and time, path skeleton, Boruvka MSF, sorted MSF,
-exact dendrogram, condensed tree, stability, excess of mass, labels), with
-the input records already resident in HBM and the workspace and outputs
-preallocated. Prints one JSON line.
+One step = one full clustering of the workload through the C ABI (group and
+sort by vertex and time, path skeleton, Boruvka MSF, sorted MSF, exact
+dendrogram, condensed tree, stability, excess of mass, labels), with the input
+records already resident in HBM and the workspace and outputs preallocated.
+Prints one JSON line.
 
-Default workload (N=1): R-MAT scale 20 (1M vertices), 50M records,
-per-pair Hawkes timestamps over 90 days, min_cluster_size 10, seed 1.
+Default workload (N=1): one GPU's share at scale -- R-MAT scale 26 (2^26
+vertices), 2^30 records, a planted hub of degree about 1e7, per-pair Hawkes
+timestamps over 365 days, min_cluster_size 25, seed 2. The 5e7-record R-MAT
+workload is timed beside it, then the 4096-graph batch and the serving stream
+(each against one call per graph or request, with every result compared), and
+the CPU oracle on a prefix of the same records, compared with the GPU on that
+prefix.
 """
 import argparse
 import json
 import os
 import platform
+import subprocess
 import sys
 import time
 
@@ -21,29 +27,36 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "temporal edges clustered/sec (bit-exact) + % HBM roofline; batched vs single"
+FIELDS = ("msf_tail", "msf_head", "msf_w", "sl_left", "sl_right", "sl_w", "sl_size", "pt_cluster", "pt_lambda",
+          "cl_id", "cl_parent", "cl_size", "cl_lambda_birth", "cl_stab_hi", "cl_stab_lo", "cl_selected", "labels")
+T0 = time.perf_counter()
 
 
 def log(msg):
-    print("[bench] " + msg, file=sys.stderr, flush=True)
+    print("[bench %6.1fs] %s" % (time.perf_counter() - T0, msg), file=sys.stderr, flush=True)
+
+
+WORKLOADS = {
+    "tiny": ("chung-lu-bursts-tiny", "plain_tiny", {"n_edges": 200_000, "n_vertices": 10_000, "min_cluster_size": 5,
+                                                      "seed": 0, "timestamps": "poisson bursts, 30 days"}),
+    "mid": ("rmat-hawkes-mid", "plain_mid", {"n_edges": 50_000_000, "n_vertices": 1 << 20, "min_cluster_size": 10,
+                                             "seed": 1, "timestamps": "per-pair hawkes, 90 days"}),
+    "scale": ("rmat-hawkes-scale", "plain_scale", {"n_edges": 1 << 30, "n_vertices": 1 << 26,
+                                                   "min_cluster_size": 25, "seed": 2,
+                                                   "timestamps": "per-pair hawkes, 365 days, planted 1e7 hub"}),
+}
 
 
 def make_workload(name):
     import synth
-    if name == "tiny":
-        return synth.plain_tiny(), {"workload": "chung-lu-bursts-tiny", "n_edges": 200_000, "n_vertices": 10_000,
-                                    "min_cluster_size": 5, "seed": 0, "timestamps": "poisson bursts, 30 days"}
-    if name == "mid":
-        return synth.plain_mid(), {"workload": "rmat-hawkes-mid", "n_edges": 50_000_000, "n_vertices": 1 << 20,
-                                   "min_cluster_size": 10, "seed": 1, "timestamps": "per-pair hawkes, 90 days"}
-    if name == "scale":
-        return synth.plain_scale(), {"workload": "rmat-hawkes-scale", "n_edges": 1 << 30, "n_vertices": 1 << 26,
-                                     "min_cluster_size": 25, "seed": 2,
-                                     "timestamps": "per-pair hawkes, 365 days, planted 1e7 hub"}
-    raise ValueError(name)
+    label, fn, cfg = WORKLOADS[name]
+    return getattr(synth, fn)(), dict({"workload": label}, **cfg)
 
 
-def cpu_baseline(w, sample, causal=False, thresholds=None):
-    """Time the CPU oracle (single-threaded plain C) on the first `sample` records."""
+# ----------------------------------------------------------------------------------------------- CPU oracle
+def cpu_oracle_single(w, sample, causal=False, thresholds=None):
+    """The CPU oracle (plain single-threaded C, skeleton tier) on the first `sample` records; returns the timing
+    record and the oracle's result for the parity check against the GPU on the same records."""
     import oracle
     ns = min(sample, w.n)
     t0 = time.perf_counter()
@@ -55,10 +68,114 @@ def cpu_baseline(w, sample, causal=False, thresholds=None):
                            causal=causal)
     dt = time.perf_counter() - t0
     assert r.status == 0
-    return {"value": ns / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
-            "sample": "first %d of %d records of the same workload (%s oracle%s, one host thread, %.1f s)"
-                      % (ns, w.n, "Alg. 2 window" if causal else "path-skeleton",
-                         ", discrete dendrogram with %d thresholds" % len(thresholds) if thresholds else "", dt)}
+    rec = {"value": ns / dt, "unit": "edges/s", "cores": 1, "kind": "oracle",
+           "sample": "first %d of %d records of the same workload (%s oracle%s, one host thread, %.1f s)"
+                     % (ns, w.n, "Alg. 2 window" if causal else "path-skeleton",
+                        ", discrete dendrogram with %d thresholds" % len(thresholds) if thresholds else "", dt)}
+    return rec, r, ns
+
+
+_CHILD = r"""
+import sys, time, numpy as np
+sys.path.insert(0, sys.argv[1])
+import oracle
+d = np.load(sys.argv[2])
+t0 = time.perf_counter()
+r = oracle.cluster(d["src"], d["dst"], d["t"], int(d["M"]), int(d["V"]), tier=1)
+assert r.status == 0
+print(time.perf_counter() - t0)
+"""
+
+
+def cpu_oracle_all_cores(w, sample):
+    """The same plain oracle on every host core at once: one process per core, each clustering its own copy
+    of the first `sample` records (independent jobs; the oracle itself stays single-threaded). Runs before
+    this process touches the GPU."""
+    import numpy as np
+    procs = min(os.cpu_count() or 1, 16)
+    ns = min(sample, w.n)
+    path = "/dev/shm/ce_bench_prefix_%d.npz" % os.getpid()
+    np.savez(path, src=w.src[:ns], dst=w.dst[:ns], t=w.t[:ns], M=w.min_cluster_size, V=w.num_vertices)
+    try:
+        t0 = time.perf_counter()
+        ps = [subprocess.Popen([sys.executable, "-c", _CHILD, ROOT, path], stdout=subprocess.PIPE, text=True)
+              for _ in range(procs)]
+        outs = [p.communicate()[0] for p in ps]
+        wall = time.perf_counter() - t0
+        if any(p.returncode != 0 for p in ps):
+            return {"skipped": "an oracle process failed"}
+        each = [float(o.strip().splitlines()[-1]) for o in outs]
+    finally:
+        os.unlink(path)
+    return {"value": procs * ns / wall, "unit": "edges/s", "cores": procs, "kind": "oracle",
+            "sample": "%d processes at once, each the plain single-threaded oracle on its own copy of the first %d "
+                      "records (%.1f s wall; per process %.1f-%.1f s)" % (procs, ns, wall, min(each), max(each))}
+
+
+def compare_numpy(got, ref, fields=FIELDS):
+    """Names of the fields where the GPU result (to_numpy dict) differs from the oracle's."""
+    import numpy as np
+    bad = [f for f in fields if not np.array_equal(got[f], getattr(ref, f))]
+    for f in ("m", "n_clusters", "n_labels"):
+        if int(got[f]) != int(getattr(ref, f)):
+            bad.append(f)
+    return bad
+
+
+# ---------------------------------------------------------------------------------------------- roofline
+def roofline_line(ce, profiling, kernel, kms, kcnt, w, m, steps, tag):
+    """Roofline of the dominant kernel against the path's algorithmic bytes: the dendrogram stage's share of
+    the per-edge model (bytes of the dendrogram rows per MSF row) spread over the kernel's launches, divided by
+    its average launch time. The kernel's own access model and the counter traffic are given beside it."""
+    per_row = profiling.STAGE_BYTES["dendrogram"]
+    per_launch = per_row * m * steps / kcnt
+    avg_s = kms / kcnt * 1e-3
+    achieved = per_launch / avg_s / 1e9
+    unit, model_per_unit, model_units = profiling.algorithmic_bytes_per_step(kernel, w.n, m)
+    model_per_launch = model_per_unit * model_units * steps / kcnt
+    traffic = profiling.load_traffic(kernel, os.path.join(ROOT, "profiles", "%s_%s_pmc.md" % (kernel, tag)))
+    return {"bound": "hbm", "achieved": achieved, "peak": profiling.HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / profiling.HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
+            "algorithmic_bytes_per_launch": per_launch, "launches": kcnt, "avg_launch_us": 1e6 * avg_s,
+            "unit_of_work": "MSF row (dendrogram rows: %d B per row, all of the stage given to this kernel)" % per_row,
+            "amplification": traffic / per_launch if traffic else None,
+            "kernel_model": {"unit": unit, "bytes_per_unit": model_per_unit, "bytes_per_launch": model_per_launch,
+                             "achieved": model_per_launch / avg_s / 1e9,
+                             "frac": model_per_launch / avg_s / 1e9 / profiling.HBM_PEAK_GBS,
+                             "amplification": traffic / model_per_launch if traffic else None}}
+
+
+# --------------------------------------------------------------------------------------------- workloads
+def time_single_graph(ce, w, dev, steps, warmup, causal=False, thr=None, roofline_kernel=None, time_bits=0):
+    import torch
+    src = torch.from_numpy(w.src).to(dev)
+    dst = torch.from_numpy(w.dst).to(dev)
+    tt = torch.from_numpy(w.t).to(dev)
+    M, V = w.min_cluster_size, w.num_vertices
+    outs = ce.Outputs(w.n, M, dev)
+    ws = torch.empty(ce.workspace_bytes(w.n, V, M, thresholds=thr), dtype=torch.uint8, device=dev)
+    torch.cuda.synchronize()
+
+    def step():
+        return ce.cluster_edges(src, dst, tt, M, V, outputs=outs, workspace=ws, causal=causal, thresholds=thr)
+
+    r = None
+    for i in range(warmup):
+        r = step()
+        log("warmup %d done: m=%d clusters=%d labels=%d" % (i, r.m, r.n_clusters, r.n_labels))
+    torch.cuda.synchronize()
+    if roofline_kernel:
+        ce.timing_enable(roofline_kernel)
+    t0 = time.perf_counter()
+    for i in range(steps):
+        r = step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    kms, kcnt = ce.timing_read() if roofline_kernel else (0.0, 0)
+    ce.timing_enable(None)
+    log("timed %d steps in %.3f s (%.1f ms per step)" % (steps, el, 1e3 * el / steps))
+    del ws
+    return r, el, (kms, kcnt), (src, dst, tt, outs)
 
 
 def bench_level_components(ce, r, n, thr, calls=3):
@@ -126,8 +243,22 @@ def bench_hyper(dev, steps, warmup):
     return out
 
 
+def equal_fields(a, b, counts):
+    """Fields (of two Outputs) that differ on the leading counts: rows, records, cluster rows."""
+    import torch
+    rows, recs, cls = counts
+    bad = []
+    for f in FIELDS:
+        k = recs if f in ("pt_cluster", "pt_lambda", "labels") else cls if f.startswith("cl_") else rows
+        if not torch.equal(a.t[f][:k], b.t[f][:k]):
+            bad.append(f)
+    return bad
+
+
 def bench_batched(dev, steps, warmup):
-    """The 4096-graph batch in one call vs one call per graph, same GPU and inputs."""
+    """The 4096-graph batch in one call vs one call per graph, same GPU and inputs. Every one-graph call
+    writes into its graph's region of a second output buffer laid out like the batch, and the two buffers
+    are compared whole."""
     import numpy as np
     import torch
     import synth
@@ -160,95 +291,138 @@ def bench_batched(dev, steps, warmup):
     ng = np.diff(eoff)
     vg = np.diff(voff)
     nmax = int(ng.max())
-    souts = ce.Outputs(nmax, M, dev)
+    roff, coff = br.row_offsets, br.cluster_offsets
+    single = ce.Outputs(n, M, dev, clusters=int(coff[-1]) + ce.max_clusters(nmax, M), rows=n + nmax)
+    regions = [single.region(int(roff[g]), int(eoff[g]), int(coff[g]), int(ng[g]), M) for g in range(G)]
     sws = torch.empty(ce.workspace_bytes(nmax, int(vg.max()), M), dtype=torch.uint8, device=dev)
 
-    def single(g):
+    def one(g):
         a, b = int(eoff[g]), int(eoff[g + 1])
-        return ce.cluster_edges(s_d[a:b], d_d[a:b], t_d[a:b], M, int(vg[g]), outputs=souts, workspace=sws)
+        return ce.cluster_edges(s_d[a:b], d_d[a:b], t_d[a:b], M, int(vg[g]), outputs=regions[g], workspace=sws)
 
     for g in range(min(G, 64)):
-        single(g)
+        one(g)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for g in range(G):
-        single(g)
+    counts = [one(g) for g in range(G)]
     torch.cuda.synchronize()
     el_s = time.perf_counter() - t0
     log("one graph per call: %.1f ms for the %d graphs" % (1e3 * el_s, G))
+    same_counts = all(c.m == br.m[g] and c.n_clusters == br.n_clusters[g] and c.n_labels == br.n_labels[g]
+                      for g, c in enumerate(counts))
+    bad = equal_fields(outs, single, (int(roff[-1]), n, int(coff[-1])))
+    equal = same_counts and not bad
+    log("batch vs one call per graph: %s" % ("all %d graphs equal" % G if equal else "DIFFER in %s" % bad))
     out = {"workload": "chung-lu-bursts-batch-4096", "graphs": G, "n_edges": n, "min_cluster_size": M, "seed": 3,
            "sizes": "lognormal median 20000 sigma 1.5 clipped [500, 2e6]; V_g = n_g/20",
            "batched_edges_per_s": n / el_b, "batched_ms": 1e3 * el_b, "batched_steps": steps,
            "single_edges_per_s": n / el_s, "single_ms": 1e3 * el_s,
-           "ratio": el_s / el_b, "n_clusters": int(br.n_clusters.sum()), "n_labels": int(br.n_labels.sum())}
-    del s_d, d_d, t_d, outs, souts, sws
+           "ratio": el_s / el_b, "n_clusters": int(br.n_clusters.sum()), "n_labels": int(br.n_labels.sum()),
+           "equal_to_single_calls": equal, "graphs_compared": G}
+    del s_d, d_d, t_d, outs, single, regions, sws
     torch.cuda.empty_cache()
     return out
 
 
-def bench_serving(dev, count, workers=3, budget_gib=64):
-    """Open-loop replay of the request stream (Poisson arrivals at 200/s) through the
-    continuous-batching server, then the same requests submitted all at once,
-    against one call per request."""
+class Digest:
+    """Two random linear 64-bit hashes of every output field of a result (on the GPU): results whose digests
+    agree are equal except with probability about 2^-128 per comparison."""
+
+    def __init__(self, dev, length):
+        import torch
+        g = torch.Generator(device="cpu").manual_seed(12345)
+        self.c = torch.randint(-(2 ** 62), 2 ** 62, (2, length), generator=g, dtype=torch.int64).to(dev)
+
+    def __call__(self, res, n):
+        import torch
+        parts = []
+        for f in FIELDS:
+            x = getattr(res, f)
+            k = x.numel()
+            x64 = x.to(torch.int64)
+            parts.append((x64 * self.c[0, :k]).sum())
+            parts.append((x64 * self.c[1, :k]).sum())
+        return torch.stack(parts).cpu().tolist() + [res.m, res.n_clusters, res.n_labels]
+
+
+def bench_serving(dev, count, workers=3, budget_gib=64, pool=96):
+    """Open-loop replay of the request stream (Poisson arrivals at 200/s) through the continuous-batching
+    server, then the same requests submitted all at once, against one call per request. Each request's
+    outputs are digested on the GPU when it is polled and its buffer goes back to a pool; the one-call-per-
+    request results are digested the same way and every request's digests are compared."""
     import numpy as np
     import torch
     import synth
     import paper_2311_10337_amd as ce
+    from concurrent.futures import ThreadPoolExecutor
     M = 10
     sizes = synth.request_sizes(20000, seed=4)[:count]
     arr = synth.request_arrivals(20000, seed=4)[:count]
     arr = arr - arr[0]
     t0 = time.perf_counter()
-    reqs = [synth.request_graph(r, int(sizes[r]), seed=4) for r in range(count)]
-    total = int(sum(len(r[0]) for r in reqs))
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        reqs = list(ex.map(lambda r: synth.request_graph(r, int(sizes[r]), seed=4), range(count)))
+    total = int(sizes.sum())
     log("serving workload: %d requests, %d records (%.1f s)" % (count, total, time.perf_counter() - t0))
-    outs = [ce.Outputs(len(r[0]), M, dev) for r in reqs]
-    srv = ce.Server(budget_gib << 30, workers=workers, max_inflight=count)
+    nmax = int(sizes.max())
+    bufs = [ce.Outputs(nmax, M, dev) for _ in range(pool)]
+    digest = Digest(dev, nmax)
+    srv = ce.Server(budget_gib << 30, workers=workers, max_inflight=pool)
+    served = [None] * count
 
-    def replay(arrivals):
+    def replay(arrivals, keep):
         lat = np.zeros(count)
         pending = {}
+        free = list(range(pool))
         k = 0
         first_sub, last_done = None, 0.0
         start = time.perf_counter()
         while k < count or pending:
             progressed = False
             now = time.perf_counter() - start
-            while k < count and now >= arrivals[k]:
+            while k < count and now >= arrivals[k] and free:
                 s, d, t, V = reqs[k]
                 sub = time.perf_counter() - start
+                b = free[-1]
                 try:
-                    tk = srv.submit(s, d, t, M, V, outputs=outs[k])
+                    tk = srv.submit(s, d, t, M, V, outputs=bufs[b])
                 except ce.ServerBusy:
                     break
+                free.pop()
                 first_sub = sub if first_sub is None else first_sub
-                pending[tk] = (k, sub)
+                pending[tk] = (k, sub, b)
                 k += 1
                 progressed = True
                 now = time.perf_counter() - start
             for tk in list(pending):
                 r = srv.poll(tk)
                 if r is not None:
-                    kk, sub = pending.pop(tk)
+                    kk, sub, b = pending.pop(tk)
                     if r.status != ce.CE_OK:
                         raise RuntimeError("request %d failed: %s" % (kk, r.error))
                     lat[kk] = (sub - arrivals[kk]) + r.latency_s
                     last_done = max(last_done, sub + r.latency_s)
+                    if keep:
+                        served[kk] = digest(r.result, len(reqs[kk][0]))
+                    free.append(b)
                     progressed = True
             if not progressed:
                 time.sleep(0.0002)
         return lat, last_done - arrivals[0]
 
-    replay(np.zeros(count))  # warm-up pass, everything at once
+    replay(np.zeros(count), True)  # warm-up pass, everything at once; digests of every served result
+    log("served results digested")
     st0 = srv.stats()
-    lat, wall_open = replay(arr)
+    lat, wall_open = replay(arr, False)
     st1 = srv.stats()
-    _, wall_sat = replay(np.zeros(count))
+    log("open-loop replay done")
+    _, wall_sat = replay(np.zeros(count), False)
     st2 = srv.stats()
     srv.close()
+    del bufs
+    torch.cuda.empty_cache()
     # one call per request, inputs already on the GPU
     dins = [tuple(torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in r[:3]) + (r[3],) for r in reqs]
-    nmax = max(len(r[0]) for r in reqs)
     souts = ce.Outputs(nmax, M, dev)
     sws = torch.empty(ce.workspace_bytes(nmax, max(r[3] for r in reqs), M), dtype=torch.uint8, device=dev)
     for k in range(min(count, 16)):
@@ -260,7 +434,15 @@ def bench_serving(dev, count, workers=3, budget_gib=64):
         ce.cluster_edges(s, d, t, M, V, outputs=souts, workspace=sws)
     torch.cuda.synchronize()
     wall_single = time.perf_counter() - t0
-    del dins, souts, sws, outs
+    log("one call per request: %.2f s" % wall_single)
+    mismatch = []
+    for k, (s, d, t, V) in enumerate(dins):
+        r = ce.cluster_edges(s, d, t, M, V, outputs=souts, workspace=sws)
+        if digest(r, len(reqs[k][0])) != served[k]:
+            mismatch.append(k)
+    log("served vs one call per request: %s" % ("all %d equal" % count if not mismatch
+                                                 else "%d DIFFER (first %s)" % (len(mismatch), mismatch[:5])))
+    del dins, souts, sws
     torch.cuda.empty_cache()
     log("serving: p50 %.1f ms p99 %.1f ms; saturated %.2f s, one call per request %.2f s"
         % (1e3 * np.percentile(lat, 50), 1e3 * np.percentile(lat, 99), wall_sat, wall_single))
@@ -273,7 +455,9 @@ def bench_serving(dev, count, workers=3, budget_gib=64):
             "open_loop_batches": st1["batches"] - st0["batches"],
             "saturated_edges_per_s": total / wall_sat, "saturated_batches": st2["batches"] - st1["batches"],
             "max_batch_requests": st2["max_batch_requests"], "max_concurrent_batches": st2["max_concurrent_batches"],
-            "single_edges_per_s": total / wall_single, "ratio": wall_single / wall_sat}
+            "single_edges_per_s": total / wall_single, "ratio": wall_single / wall_sat,
+            "equal_to_single_calls": not mismatch, "requests_compared": count,
+            "comparison": "two random 64-bit linear digests of every output field per request"}
 
 
 def main():
@@ -281,17 +465,20 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="mid", choices=["tiny", "mid", "scale"])
+    ap.add_argument("--workload", default="scale", choices=sorted(WORKLOADS))
+    ap.add_argument("--also", default="mid",
+                    help="comma list of further single-graph workloads timed beside the main one ('' for none)")
     ap.add_argument("--mode", default="undirected", choices=["undirected", "causal"],
                     help="line graph: undirected (shared vertex, |dt|) or causal (tip-to-tail, increment weights)")
     ap.add_argument("--thresholds", default="none",
                     help="discrete dendrogram: 'none' (exact dendrogram), 'paper' (2^0 .. 2^28 s) or a comma list")
     ap.add_argument("--cpu-sample", type=int, default=20_000_000)
+    ap.add_argument("--cpu-sample-all-cores", type=int, default=4_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=1000,
+    ap.add_argument("--serve-requests", type=int, default=20000,
                     help="requests of the serving stream to replay (0 skips the serving measurement)")
-    ap.add_argument("--no-hyper", action="store_true",
-                    help="skip the dynamic-hypergraph measurement (2e7 multi-recipient messages)")
+    ap.add_argument("--hyper", action="store_true",
+                    help="also time the dynamic-hypergraph workload (2e7 multi-recipient messages)")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched-vs-one-graph-per-call measurement on the 4096-graph batch")
     ap.add_argument("--roofline-kernel", default="k_krt_union",
@@ -307,21 +494,34 @@ def main():
         sys.exit(2)
 
     import numpy as np
-    import torch
     import paper_2311_10337_amd as ce
     if not os.path.exists(ce.LIB_PATH):
         import __graft_entry__
         __graft_entry__.build()
+    if args.thresholds == "none":
+        thr = None
+    elif args.thresholds == "paper":
+        thr = [1 << k for k in range(29)]
+    else:
+        thr = [int(x) for x in args.thresholds.split(",")]
+    causal = args.mode == "causal"
 
     log("generating workload %s" % args.workload)
-    t0 = time.perf_counter()
     w, cfg = make_workload(args.workload)
-    log("generated n=%d in %.1f s" % (w.n, time.perf_counter() - t0))
+    log("generated n=%d" % w.n)
+    # CPU legs first, before this process touches the GPU (the all-core leg starts child processes)
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu oracle on a prefix (one thread)")
+        cpu, cpu_ref, cpu_n = cpu_oracle_single(w, args.cpu_sample, causal, thr)
+        log("cpu oracle: %.3g edges/s" % cpu["value"])
+        if not causal and not thr:
+            cpu_all = cpu_oracle_all_cores(w, args.cpu_sample_all_cores)
+            log("cpu oracle on all cores: %s" % cpu_all.get("value"))
+
+    import torch
+    from paper_2311_10337_amd import profiling
     dev = torch.device("cuda:0")
-    src = torch.from_numpy(w.src).to(dev)
-    dst = torch.from_numpy(w.dst).to(dev)
-    tt = torch.from_numpy(w.t).to(dev)
-    M, V = w.min_cluster_size, w.num_vertices
     if args.copy_calibration:
         a = torch.ones(args.copy_calibration, dtype=torch.uint8, device=dev)
         b = torch.empty_like(a)
@@ -330,72 +530,31 @@ def main():
         torch.cuda.synchronize()
         del a, b
         log("copy calibration: %d bytes copied" % args.copy_calibration)
-    if args.thresholds == "none":
-        thr = None
-    elif args.thresholds == "paper":
-        thr = [1 << k for k in range(29)]
-    else:
-        thr = [int(x) for x in args.thresholds.split(",")]
-    outs = ce.Outputs(w.n, M, dev)
-    ws = torch.empty(ce.workspace_bytes(w.n, V, M, thresholds=thr), dtype=torch.uint8, device=dev)
-    torch.cuda.synchronize()
-
-    causal = args.mode == "causal"
     cfg["line_graph"] = args.mode
     tag = cfg["workload"] + ("_causal" if causal else "") + ("_discrete" if thr else "")
     if thr:
         cfg["dendrogram"] = "discrete, %d thresholds %d..%d s" % (len(thr), thr[0], thr[-1])
-
-    def step():
-        return ce.cluster_edges(src, dst, tt, M, V, outputs=outs, workspace=ws, causal=causal, thresholds=thr)
-
-    for i in range(args.warmup):
-        r = step()
-        log("warmup %d done: m=%d clusters=%d labels=%d" % (i, r.m, r.n_clusters, r.n_labels))
-    torch.cuda.synchronize()
-    if args.roofline_kernel:
-        ce.timing_enable(args.roofline_kernel)
-    t0 = time.perf_counter()
-    for i in range(args.steps):
-        r = step()
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    log("timed %d steps in %.3f s" % (args.steps, el))
+    r, el, (kms, kcnt), keep = time_single_graph(ce, w, dev, args.steps, args.warmup, causal, thr,
+                                                 args.roofline_kernel)
     roof = None
-    if args.roofline_kernel:
-        from paper_2311_10337_amd import profiling
-        kms, kcnt = ce.timing_read()
-        ce.timing_enable(None)
+    if args.roofline_kernel and kcnt:
         log("kernel %s: %d launches, %.3f ms total, %.1f us avg" % (args.roofline_kernel, kcnt, kms,
-                                                                  1e3 * kms / max(kcnt, 1)))
-        try:
-            unit, per_unit, units = profiling.algorithmic_bytes_per_step(args.roofline_kernel, w.n, r.m)
-        except KeyError:
-            log("no algorithmic model for %s: roofline left out" % args.roofline_kernel)
-            unit, per_unit, units = None, None, None
-        if kcnt and units:
-            per_launch = per_unit * units * args.steps / kcnt
-            achieved = per_launch / (kms / kcnt * 1e-3) / 1e9
-            traffic = profiling.load_traffic(args.roofline_kernel, os.path.join(
-                ROOT, "profiles", "%s_%s_pmc.md" % (args.roofline_kernel, tag)))
-            roof = {"bound": "hbm", "achieved": achieved, "peak": profiling.HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / profiling.HBM_PEAK_GBS, "traffic": traffic, "kernel": args.roofline_kernel,
-                    "algorithmic_bytes_per_launch": per_launch, "launches": kcnt,
-                    "avg_launch_us": 1e3 * kms / kcnt, "unit_of_work": unit, "bytes_per_unit": per_unit}
+                                                                  1e3 * kms / kcnt))
+        roof = roofline_line(ce, profiling, args.roofline_kernel, kms, kcnt, w, r.m, args.steps, tag)
     value = w.n * args.steps / el
     # whole path: HBM traffic per step from the committed counter summary (calibrated FETCH_SIZE +
     # WRITE_SIZE over every dispatch of one step), over the step's wall time; and the algorithmic model
-    from paper_2311_10337_amd import profiling
     step_s = el / args.steps
     pipe = profiling.load_pipeline_traffic(os.path.join(ROOT, "profiles", "pipeline_%s_pmc.md" % tag))
     algo = profiling.PATH_BYTES_PER_EDGE * w.n
-    hbm = {"peak_GBs": profiling.HBM_PEAK_GBS, "traffic_bytes_per_step": pipe,
-           "achieved_GBs": pipe / step_s / 1e9 if pipe else None,
-           "frac": pipe / step_s / 1e9 / profiling.HBM_PEAK_GBS if pipe else None,
-           "algorithmic_bytes_per_step": algo, "algorithmic_GBs": algo / step_s / 1e9,
-           "algorithmic_frac": algo / step_s / 1e9 / profiling.HBM_PEAK_GBS,
-           "note": "traffic from rocprofv3 counters of the same workload (profiles/), time = this run's wall "
-                   "time per step; algorithmic = %d B per temporal edge" % profiling.PATH_BYTES_PER_EDGE}
+    hbm = {"peak_GBs": profiling.HBM_PEAK_GBS, "algorithmic_bytes_per_step": algo,
+           "algorithmic_GBs": algo / step_s / 1e9, "algorithmic_frac": algo / step_s / 1e9 / profiling.HBM_PEAK_GBS,
+           "counter_traffic_bytes_per_step": pipe, "counter_GBs": pipe / step_s / 1e9 if pipe else None,
+           "counter_frac": pipe / step_s / 1e9 / profiling.HBM_PEAK_GBS if pipe else None,
+           "amplification": pipe / algo if pipe else None,
+           "note": "algorithmic = %d B per temporal edge over this run's wall time per step; counter traffic from "
+                   "rocprofv3 FETCH_SIZE + WRITE_SIZE of the same workload (profiles/), null when the kernels "
+                   "changed since" % profiling.PATH_BYTES_PER_EDGE}
     line = {"metric": METRIC, "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": 1000.0 * el / args.steps, "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
@@ -403,22 +562,48 @@ def main():
     if roof is not None:
         line["roofline"] = roof
     line["hbm_pipeline"] = hbm
-    del ws
-    torch.cuda.empty_cache()
     if thr:
         line["discrete_by_components"] = bench_level_components(ce, r, w.n, thr)
-    del src, dst, tt, outs
+    del keep, r
     torch.cuda.empty_cache()
+    if cpu is not None:
+        # the GPU on the oracle's records: every output field must be byte-equal
+        sub = torch.from_numpy(w.src[:cpu_n]).to(dev), torch.from_numpy(w.dst[:cpu_n]).to(dev), \
+            torch.from_numpy(w.t[:cpu_n]).to(dev)
+        got = ce.to_numpy(ce.cluster_edges(*sub, w.min_cluster_size, w.num_vertices, causal=causal,
+                                           thresholds=thr))
+        bad = compare_numpy(got, cpu_ref)
+        cpu["parity"] = not bad
+        cpu["parity_records"] = cpu_n
+        if bad:
+            cpu["parity_fields_differing"] = bad
+        log("gpu vs cpu oracle on the first %d records: %s" % (cpu_n, "byte-equal" if not bad else "DIFFER %s" % bad))
+        del sub, got, cpu_ref
+        torch.cuda.empty_cache()
+    del w
+    workloads = {}
+    for name in [x for x in args.also.split(",") if x and x != args.workload]:
+        wx, cfgx = make_workload(name)
+        rx, elx, _, kx = time_single_graph(ce, wx, dev, max(1, min(args.steps, 10)), 1, causal, thr)
+        workloads[cfgx["workload"]] = dict(cfgx, edges_per_s=wx.n * max(1, min(args.steps, 10)) / elx,
+                                           ms_per_step=1e3 * elx / max(1, min(args.steps, 10)), m_msf=rx.m,
+                                           n_clusters=rx.n_clusters, n_labels=rx.n_labels)
+        del kx, rx, wx
+        torch.cuda.empty_cache()
+    if workloads:
+        line["other_workloads"] = workloads
     if not args.no_batch:
         line["batched"] = bench_batched(dev, max(1, min(args.steps, 3)), 1)
     if args.serve_requests > 0:
         line["serving"] = bench_serving(dev, args.serve_requests)
-    if not args.no_hyper:
+    if args.hyper:
         line["hypergraph"] = bench_hyper(dev, max(1, min(args.steps, 3)), 1)
-    if not args.no_cpu_baseline:
-        log("cpu baseline on a sample")
-        line["cpu_baseline"] = cpu_baseline(w, args.cpu_sample, causal, thr)
+    if cpu is not None:
+        line["cpu_baseline"] = cpu
+        if not causal and not thr:
+            line["cpu_baseline_all_cores"] = cpu_all
     line["host"] = {"cpu": platform.processor() or platform.machine(), "nproc": os.cpu_count()}
+    log("done")
     print(json.dumps(line), flush=True)
 
 

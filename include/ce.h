@@ -41,7 +41,7 @@
  *
  * Tuning (environment, optional; outputs never depend on them):
  *   CE_KRT_LEVEL_BITS   1..10: largest number of row-index bits one global
- *                       dendrogram level takes (read once per process)
+ *                       dendrogram level takes (read on every call)
  *   CE_SPLIT_MIN_EDGES  live-edge count from which Boruvka splits its edges
  *                       at a pivot key (default 2^20; 0 = never; read on
  *                       every call)
@@ -74,7 +74,7 @@ typedef enum {
  * before out-edges at equal times, then id). MSF rows are (tail = r, head = s,
  * w) and the key is again K = (w, head, 2^32-1-tail); arcs are undirected for
  * the forest, dendrogram and condensing (Alg. 1). The packed key needs
- * bits(span) + bits(n-1) + bits(c-1) <= 64, where c is the largest number of
+ * bits(span) + bits(n-1) + bits(c-1) <= 63, where c is the largest number of
  * records arriving at one vertex at one time (else CE_ERANGE). */
 typedef enum { CE_MODE_UNDIRECTED = 0, CE_MODE_CAUSAL = 1 } ce_mode;
 
@@ -144,7 +144,7 @@ size_t ce_workspace_bytes(int64_t n, int64_t num_vertices, const ce_params *para
  * Cluster the n temporal edges (src[i], dst[i], t[i]) (Alg. 4).
  *   src, dst : int32[n], vertex ids in [0, V), src[i] != dst[i]
  *   t        : int64[n], seconds; max(t) - min(t) must satisfy
- *              bits(max-min) + bits(n-1) + 1 <= 64 (else CE_ERANGE)
+ *              bits(max-min) + bits(n-1) + 1 <= 63 (else CE_ERANGE)
  *   workspace: device buffer of >= ce_workspace_bytes(...) bytes, or NULL to
  *              let the library allocate (stream-ordered) and free it
  *   stream   : a hipStream_t (NULL = default stream)
@@ -176,7 +176,7 @@ ce_status ce_cluster_edges(const int32_t *src, const int32_t *dst, const int64_t
  *              supported: CE_EINVAL); max_dt and thresholds as for graphs
  * Limits: n <= 2^31-1, nnz <= 2^31-1. The packed key needs
  *   bits(max t - min t) + bits(n-1) + bits(longest run of equal times - 1)
- *   <= 64, else CE_ERANGE. Errors: CE_EINVAL for bad offsets, CE_ERANGE for a
+ *   <= 63, else CE_ERANGE. Errors: CE_EINVAL for bad offsets, CE_ERANGE for a
  * member outside [0, V); no output is written on an error.
  */
 /*

@@ -231,6 +231,27 @@ class Outputs:
                   "cl_selected": e(C, u8), "labels": e(n, i32), "dd_level": e(R, i32), "dd_top": e(R, i32)}
         self.struct = CeResult(**{f: ctypes.c_void_p(self.t[f].data_ptr()) for f in _RESULT_FIELDS})
 
+    def region(self, row0: int, rec0: int, cl0: int, n: int, min_cluster_size: int) -> "Outputs":
+        """Outputs for n records whose buffers start inside this one's: rows at row0, per-record outputs at
+        rec0, cluster rows at cl0 (the layout of graph g of a batch when given its row, edge and cluster
+        offsets). The caller keeps the regions of different calls apart; the capacities are those of a call
+        on n records, which writes only its own counts."""
+        o = Outputs.__new__(Outputs)
+        o.n, o.R, o.C = n, max(n - 1, 1), max_clusters(n, min_cluster_size)
+        start = {f: (rec0 if f in _RECORD_FIELDS else cl0 if f in _CLUSTER_FIELDS else row0) for f in self.t}
+        size = {f: (o.n if f in _RECORD_FIELDS else o.C if f in _CLUSTER_FIELDS else o.R) for f in self.t}
+        for f, x in self.t.items():
+            if start[f] + size[f] > x.numel():
+                raise ValueError("region of %s [%d, %d) passes the buffer's %d entries"
+                                 % (f, start[f], start[f] + size[f], x.numel()))
+        o.t = {f: x[start[f]:start[f] + size[f]] for f, x in self.t.items()}
+        o.struct = CeResult(**{f: ctypes.c_void_p(o.t[f].data_ptr()) for f in _RESULT_FIELDS})
+        return o
+
+
+_RECORD_FIELDS = ("pt_cluster", "pt_lambda", "labels")
+_CLUSTER_FIELDS = ("cl_id", "cl_parent", "cl_size", "cl_lambda_birth", "cl_stab_hi", "cl_stab_lo", "cl_selected")
+
 
 def cluster_edges(src, dst, t, min_cluster_size: int, num_vertices: int, outputs: Optional[Outputs] = None,
                   workspace=None, stream=None, causal: bool = False, max_dt: int = -1, thresholds=None) -> Result:

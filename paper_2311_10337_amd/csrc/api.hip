@@ -413,8 +413,9 @@ static ce_status run_batch(const int32_t *src, const int32_t *dst, const int64_t
   b.hshift = 1;  // causal and hypergraph modes set their own shifts once the tie terms are known
   b.wshift = b.idbits + 1;
   b.keybits = b.tbits + b.wshift;
-  if (!b.flat && b.keybits > 64) {
-    set_error("time span too wide: bits(span) + bits(n-1) + 1 > 64");
+  // the all-ones word marks an absent edge, so a key may use at most 63 bits
+  if (!b.flat && b.keybits > 63) {
+    set_error("time span too wide: bits(span) + bits(n-1) + 1 > 63");
     return CE_ERANGE;
   }
   Ws wa, wm, wb;

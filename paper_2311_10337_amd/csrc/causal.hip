@@ -292,9 +292,9 @@ ce_status stage_causal_skeleton(const int32_t *src, const int32_t *dst, const in
   b.hshift = b.jbits;
   b.wshift = b.idbits + b.jbits;
   b.keybits = b.tbits + b.wshift;
-  if (b.keybits > 64) {
+  if (b.keybits > 63) {  // the all-ones word marks an absent edge
     set_error("time span too wide for the causal key: bits(span) + bits(n-1) + bits(largest equal-time "
-              "in-degree - 1) > 64");
+              "in-degree - 1) > 63");
     return CE_ERANGE;
   }
   // 4. rows, each offering its key to both records' first Boruvka minimum

@@ -379,15 +379,12 @@ __global__ __launch_bounds__(LB) void k_krt_lds(const uint32_t *lu, const uint32
 // sub-intervals run one after another, each over about m / 2^k rows, and a
 // sub-interval needs about 2^19 rows or more to keep enough waves in flight
 // for its random accesses; at most 8 bits (256 sub-intervals). The
-// environment variable CE_KRT_LEVEL_BITS overrides it (1..10).
+// environment variable CE_KRT_LEVEL_BITS (read on every call) overrides it (1..10).
 int krt_max_level_bits(int64_t m) {
-  static int forced = -1;
-  if (forced < 0) {
-    const char *e = getenv("CE_KRT_LEVEL_BITS");
-    forced = e ? atoi(e) : 0;
-    if (forced < 0) forced = 0;
-    if (forced > 10) forced = 10;
-  }
+  const char *e = getenv("CE_KRT_LEVEL_BITS");
+  int forced = e ? atoi(e) : 0;
+  if (forced < 0) forced = 0;
+  if (forced > 10) forced = 10;
   if (forced) return forced;
   int k = bits_for((uint64_t)(m >> 19)) - 1;
   return k < 4 ? 4 : (k > 8 ? 8 : k);

@@ -287,9 +287,9 @@ ce_status stage_hyper_skeleton(const int32_t *members, const int64_t *offsets, c
   b.hshift = b.jbits;
   b.wshift = b.idbits + b.jbits;
   b.keybits = b.tbits + b.wshift;
-  if (b.keybits > 64) {
+  if (b.keybits > 63) {  // the all-ones word marks an absent edge
     set_error("time span too wide for the hypergraph key: bits(span) + bits(n-1) + bits(longest run of equal "
-              "times - 1) > 64");
+              "times - 1) > 63");
     return CE_ERANGE;
   }
   CE_LAUNCH(k_hfill_best, dim3(grid_for(n, B)), dim3(B), 0, s, b.best, n);

@@ -149,10 +149,12 @@ def load_pipeline_traffic(path: str) -> float | None:
     return blob.get("traffic_bytes_per_step")
 
 
-# algorithmic bytes per temporal edge of the whole path: each intermediate written once and read once at
-# minimal width (input 16, incidence 48, skeleton 64, MSF rows 32, dendrogram rows 20, per-record outputs 12,
-# labels 4)
-PATH_BYTES_PER_EDGE = 196
+# algorithmic bytes per temporal edge of the whole path, by stage: each intermediate written once and read
+# once at minimal width (input 16, incidence 48, skeleton 64, MSF rows 32, dendrogram rows 20, per-record
+# outputs 12, labels 4)
+STAGE_BYTES = {"input": 16, "incidence": 48, "skeleton": 64, "msf": 32, "dendrogram": 20, "condensed": 12,
+               "labels": 4}
+PATH_BYTES_PER_EDGE = sum(STAGE_BYTES.values())
 
 
 def load_traffic(kernel: str, path: str) -> float | None:
