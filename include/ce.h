@@ -79,7 +79,7 @@ typedef enum {
 typedef enum { CE_MODE_UNDIRECTED = 0, CE_MODE_CAUSAL = 1 } ce_mode;
 
 typedef struct {
-  uint32_t struct_size;      /* = sizeof(ce_params); 32 = the earlier layout without max_dt (no cutoff) */
+  uint32_t struct_size;      /* = sizeof(ce_params); the earlier, shorter layouts are accepted (sizes below) */
   uint32_t mode;             /* ce_mode */
   int64_t min_cluster_size;  /* M >= 2 (Alg. 1 input) */
   int64_t num_vertices;      /* V > 0; vertex ids must lie in [0, V) */
@@ -95,9 +95,15 @@ typedef struct {
                                 discrete tree, whose node at a level merges all of that level's joins at
                                 once, at lambda(threshold): a node with two or more children of size >= M
                                 starts a cluster for each of them; see dd_level / dd_top in ce_result */
+  int64_t time_bits;         /* asynchronous calls: the caller's bound B on the time span, max t - min t <
+                                2^B (0..62; 0 = 62). It fixes the key layout without reading the data
+                                back; a wider span is reported as CE_ERANGE in the header. Synchronous
+                                calls measure the span and ignore it. */
 } ce_params;
 #define CE_PARAMS_V1_SIZE 32 /* without max_dt */
 #define CE_PARAMS_V2_SIZE 40 /* without the thresholds */
+#define CE_PARAMS_V3_SIZE 56 /* without time_bits */
+#define CE_PARAMS_V4_SIZE 64
 #define CE_MAX_THRESHOLDS 64
 
 /* Caller-allocated DEVICE output buffers. Any pointer may be NULL to skip
@@ -249,6 +255,62 @@ ce_status ce_cluster_batch(const int32_t *src, const int32_t *dst, const int64_t
                            const ce_params *params, const ce_result *out, ce_counts *counts,
                            int64_t *row_offsets, int64_t *cluster_offsets, void *workspace,
                            size_t workspace_bytes, void *stream);
+
+/*
+ * Asynchronous calls: enqueue only (the boundary of Alg. 4 with its input and
+ * output on the device). Every data-dependent count of the pipeline (spanning
+ * forest rows, Boruvka's live edges and components, births, pointer-jumping
+ * rounds) lives in device memory: rounds are enqueued up to bounds that hold
+ * for any input of n records and return at once when their work is done, so
+ * a call returns as soon as its kernels are enqueued on `stream`, never waits
+ * on the host, allocates nothing, and can be captured in a HIP graph and
+ * replayed (with new contents in the same buffers).
+ *
+ * The call's header is written on the device, to hdr (caller-owned DEVICE
+ * memory of CE_HDR_WORDS(G) int64, G = 1 for ce_cluster_edges_async):
+ *   hdr[0]                 ce_status of the call's data: CE_OK, CE_ESELFLOOP,
+ *                          CE_ERANGE (id outside [0, V), or a time span of
+ *                          more than params.time_bits bits), CE_EINVAL (bad
+ *                          device offsets), CE_EDEVICE (internal)
+ *   hdr[1], hdr[2], hdr[3] total rows m, cluster rows, labels
+ *   hdr[4 + 3g + {0,1,2}]  graph g's m, n_clusters, n_labels
+ *   hdr[4 + 3G + g]        row_offsets[g]      (g = 0..G)
+ *   hdr[5 + 4G + g]        cluster_offsets[g]  (g = 0..G)
+ * On a data error no output is written. ce_result_status waits for the stream
+ * and reads the header.
+ *
+ * Limits of the asynchronous form: undirected mode only (the causal key's tie
+ * width is measured on the data); a workspace must be given; the key layout
+ * needs params.time_bits + bits(n-1) + 1 <= 63, checked when the call is made
+ * (CE_ERANGE). Kernel timing (ce_timing_enable) is not collected.
+ */
+#define CE_HDR_WORDS(G) (6 + 5 * (int64_t)(G))
+
+/* Enqueues the clustering of n records (ce_cluster_edges's inputs, outputs
+ * and workspace, all DEVICE memory); the counts go to the device header hdr
+ * (CE_HDR_WORDS(1) int64). Host-checked argument errors are returned at once. */
+ce_status ce_cluster_edges_async(const int32_t *src, const int32_t *dst, const int64_t *t, int64_t n,
+                                 const ce_params *params, const ce_result *out, int64_t *hdr, void *workspace,
+                                 size_t workspace_bytes, void *stream);
+
+/* Enqueues a batch of G graphs (ce_cluster_batch's layout) whose offsets are
+ * DEVICE arrays: edge_offsets[G+1] (edge_offsets[G] = n) and
+ * vertex_offsets[G+1] (vertex_offsets[G] = num_vertices), checked on the
+ * device. Capacities as for ce_cluster_batch; workspace of at least
+ * ce_batch_workspace_bytes_for(n, G, params) bytes. */
+ce_status ce_cluster_batch_async(const int32_t *src, const int32_t *dst, const int64_t *t, int64_t n,
+                                 const int64_t *edge_offsets, const int64_t *vertex_offsets, int64_t num_graphs,
+                                 int64_t num_vertices, const ce_params *params, const ce_result *out, int64_t *hdr,
+                                 void *workspace, size_t workspace_bytes, void *stream);
+
+/* Workspace of a batch of num_graphs graphs and n records in all. Pure. */
+size_t ce_batch_workspace_bytes_for(int64_t n, int64_t num_graphs, const ce_params *params);
+
+/* Waits for `stream`, reads the device header of an asynchronous call over
+ * num_graphs graphs and returns its status; fills counts[G], row_offsets[G+1]
+ * and cluster_offsets[G+1] (HOST arrays; any may be NULL) when it is CE_OK. */
+ce_status ce_result_status(const int64_t *hdr, int64_t num_graphs, ce_counts *counts, int64_t *row_offsets,
+                           int64_t *cluster_offsets, void *stream);
 
 /*
  * Serving: continuous batching of independent clustering requests on one GPU.

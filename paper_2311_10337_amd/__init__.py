@@ -23,7 +23,8 @@ NONE32 = 0xFFFFFFFF
 class CeParams(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("mode", ctypes.c_uint32), ("min_cluster_size", ctypes.c_int64),
                 ("num_vertices", ctypes.c_int64), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
-                ("max_dt", ctypes.c_int64), ("thresholds", ctypes.c_void_p), ("num_thresholds", ctypes.c_int64)]
+                ("max_dt", ctypes.c_int64), ("thresholds", ctypes.c_void_p), ("num_thresholds", ctypes.c_int64),
+                ("time_bits", ctypes.c_int64)]
 
 
 _RESULT_FIELDS = ["msf_tail", "msf_head", "msf_w", "sl_left", "sl_right", "sl_w", "sl_size", "pt_cluster",
@@ -68,7 +69,8 @@ class CeServerStats(ctypes.Structure):
 _EXPORTS = ["ce_cluster_edges", "ce_cluster_batch", "ce_workspace_bytes", "ce_batch_workspace_bytes",
             "ce_max_clusters", "ce_last_error", "ce_timing_enable", "ce_timing_read", "ce_server_create",
             "ce_server_destroy", "ce_server_request_bytes", "ce_server_submit", "ce_server_poll",
-            "ce_server_get_stats"]
+            "ce_server_get_stats", "ce_cluster_edges_async", "ce_cluster_batch_async", "ce_batch_workspace_bytes_for",
+            "ce_result_status"]
 CE_MAX_GRAPHS = 1 << 24
 _lib = None
 
@@ -99,6 +101,23 @@ def load_library(path: str = LIB_PATH):
         lib.ce_cluster_batch.restype = ctypes.c_int
         lib.ce_batch_workspace_bytes.argtypes = [i64p, i64p, ctypes.c_int64, ctypes.POINTER(CeParams)]
         lib.ce_batch_workspace_bytes.restype = ctypes.c_size_t
+        lib.ce_batch_workspace_bytes_for.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(CeParams)]
+        lib.ce_batch_workspace_bytes_for.restype = ctypes.c_size_t
+        lib.ce_cluster_edges_async.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int64, ctypes.POINTER(CeParams),
+                                                                       ctypes.POINTER(CeResult), ctypes.c_void_p,
+                                                                       ctypes.c_void_p, ctypes.c_size_t,
+                                                                       ctypes.c_void_p]
+        lib.ce_cluster_edges_async.restype = ctypes.c_int
+        lib.ce_cluster_batch_async.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                                                       ctypes.c_int64, ctypes.c_int64,
+                                                                       ctypes.POINTER(CeParams),
+                                                                       ctypes.POINTER(CeResult), ctypes.c_void_p,
+                                                                       ctypes.c_void_p, ctypes.c_size_t,
+                                                                       ctypes.c_void_p]
+        lib.ce_cluster_batch_async.restype = ctypes.c_int
+        lib.ce_result_status.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(CeCounts), i64p, i64p,
+                                         ctypes.c_void_p]
+        lib.ce_result_status.restype = ctypes.c_int
         vp = ctypes.c_void_p
         lib.ce_server_create.argtypes = [ctypes.POINTER(CeServerConfig), ctypes.POINTER(vp)]
         lib.ce_server_create.restype = ctypes.c_int
@@ -136,18 +155,24 @@ def exported_symbols():
 
 
 def make_params(min_cluster_size: int, num_vertices: int, causal: bool = False, max_dt: int = -1,
-                thresholds=None) -> CeParams:
-    """Parameters; `thresholds` (increasing weights) selects the discrete dendrogram. The returned struct keeps
-    a reference to the thresholds' host array."""
+                thresholds=None, time_bits: int = 0) -> CeParams:
+    """Parameters; `thresholds` (increasing weights) selects the discrete dendrogram; `time_bits` bounds the
+    time span for asynchronous calls. The returned struct keeps a reference to the thresholds' host array."""
     import numpy as np
     mode = CE_MODE_CAUSAL if causal else CE_MODE_UNDIRECTED
-    p = CeParams(ctypes.sizeof(CeParams), mode, int(min_cluster_size), int(num_vertices), 0, 0, int(max_dt), None, 0)
+    p = CeParams(ctypes.sizeof(CeParams), mode, int(min_cluster_size), int(num_vertices), 0, 0, int(max_dt), None, 0,
+                 int(time_bits))
     if thresholds is not None and len(thresholds) > 0:
         thr = np.ascontiguousarray(np.asarray(thresholds, dtype=np.int64))
         p.thresholds = thr.ctypes.data
         p.num_thresholds = thr.size
         p._keep = thr
     return p
+
+
+def hdr_words(num_graphs: int = 1) -> int:
+    """int64 words of an asynchronous call's device header (CE_HDR_WORDS)."""
+    return 6 + 5 * int(num_graphs)
 
 
 def workspace_bytes(n: int, num_vertices: int, min_cluster_size: int, thresholds=None) -> int:
@@ -288,6 +313,118 @@ def cluster_edges(src, dst, t, min_cluster_size: int, num_vertices: int, outputs
     if st != CE_OK:
         raise ClusterError(st, last_error())
     return _result(outputs, n, counts, params)
+
+
+def _check_dev(name, x, dt):
+    import torch
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == dt and x.is_contiguous() and x.dim() == 1):
+        raise TypeError("%s must be a contiguous 1-D %s GPU tensor" % (name, dt))
+
+
+def cluster_edges_async(src, dst, t, min_cluster_size: int, num_vertices: int, outputs: Outputs, workspace, hdr,
+                        time_bits: int, stream=None, max_dt: int = -1, thresholds=None) -> None:
+    """Enqueue the clustering of (src, dst, t) on the stream and return at once (``ce_cluster_edges_async``).
+
+    ``outputs``, ``workspace`` (uint8, at least ``workspace_bytes``) and ``hdr`` (int64, ``hdr_words(1)``) are
+    device tensors the caller keeps alive until the stream has run; ``time_bits`` bounds the time span
+    (max t - min t < 2**time_bits). Read the counts with ``result_status`` or ``async_result``."""
+    import torch
+    lib = load_library()
+    for name, x, dt in (("src", src, torch.int32), ("dst", dst, torch.int32), ("t", t, torch.int64),
+                        ("workspace", workspace, torch.uint8), ("hdr", hdr, torch.int64)):
+        _check_dev(name, x, dt)
+    n = int(src.numel())
+    if dst.numel() != n or t.numel() != n:
+        raise ValueError("src, dst, t must have the same length")
+    if hdr.numel() < hdr_words(1):
+        raise ValueError("hdr needs %d int64 words" % hdr_words(1))
+    if outputs.n < n or outputs.C < max_clusters(n, min_cluster_size):
+        raise ValueError("outputs are too small for %d records" % n)
+    params = make_params(min_cluster_size, num_vertices, False, max_dt, thresholds, time_bits)
+    s = stream if stream is not None else torch.cuda.current_stream(src.device)
+    st = lib.ce_cluster_edges_async(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                    ctypes.c_void_p(t.data_ptr()), n, ctypes.byref(params),
+                                    ctypes.byref(outputs.struct), ctypes.c_void_p(hdr.data_ptr()),
+                                    ctypes.c_void_p(workspace.data_ptr()), workspace.numel(),
+                                    ctypes.c_void_p(s.cuda_stream))
+    if st != CE_OK:
+        raise ClusterError(st, last_error(), "ce_cluster_edges_async")
+
+
+def batch_workspace_bytes_for(n: int, num_graphs: int, min_cluster_size: int, thresholds=None) -> int:
+    """Workspace of a batch of num_graphs graphs with n records in all (no offsets needed)."""
+    p = make_params(min_cluster_size, 1, thresholds=thresholds)
+    return int(load_library().ce_batch_workspace_bytes_for(int(n), int(num_graphs), ctypes.byref(p)))
+
+
+def cluster_batch_async(src, dst, t, edge_offsets, vertex_offsets, num_vertices: int, min_cluster_size: int,
+                        outputs: Outputs, workspace, hdr, time_bits: int, stream=None, max_dt: int = -1,
+                        thresholds=None) -> None:
+    """Enqueue a batch (``ce_cluster_batch_async``): edge_offsets and vertex_offsets are int64 GPU tensors of
+    G+1 offsets, num_vertices their total; hdr holds ``hdr_words(G)`` int64 words. Returns at once."""
+    import torch
+    lib = load_library()
+    for name, x, dt in (("src", src, torch.int32), ("dst", dst, torch.int32), ("t", t, torch.int64),
+                        ("edge_offsets", edge_offsets, torch.int64), ("vertex_offsets", vertex_offsets, torch.int64),
+                        ("workspace", workspace, torch.uint8), ("hdr", hdr, torch.int64)):
+        _check_dev(name, x, dt)
+    n, G = int(src.numel()), int(edge_offsets.numel()) - 1
+    if dst.numel() != n or t.numel() != n or vertex_offsets.numel() != G + 1 or G < 1:
+        raise ValueError("src, dst, t need n records and both offset arrays G+1 entries")
+    if hdr.numel() < hdr_words(G):
+        raise ValueError("hdr needs %d int64 words" % hdr_words(G))
+    params = make_params(min_cluster_size, num_vertices, False, max_dt, thresholds, time_bits)
+    s = stream if stream is not None else torch.cuda.current_stream(src.device)
+    st = lib.ce_cluster_batch_async(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()),
+                                    ctypes.c_void_p(t.data_ptr()), n, ctypes.c_void_p(edge_offsets.data_ptr()),
+                                    ctypes.c_void_p(vertex_offsets.data_ptr()), G, int(num_vertices),
+                                    ctypes.byref(params), ctypes.byref(outputs.struct),
+                                    ctypes.c_void_p(hdr.data_ptr()), ctypes.c_void_p(workspace.data_ptr()),
+                                    workspace.numel(), ctypes.c_void_p(s.cuda_stream))
+    if st != CE_OK:
+        raise ClusterError(st, last_error(), "ce_cluster_batch_async")
+
+
+def result_status(hdr, num_graphs: int = 1, stream=None):
+    """Wait for the stream and read an asynchronous call's header (``ce_result_status``): returns
+    (counts int64[G, 3] as m, n_clusters, n_labels; row_offsets int64[G+1]; cluster_offsets int64[G+1]) or
+    raises ClusterError with the call's status."""
+    import numpy as np
+    import torch
+    G = int(num_graphs)
+    counts = (CeCounts * G)()
+    roff = np.zeros(G + 1, dtype=np.int64)
+    coff = np.zeros(G + 1, dtype=np.int64)
+    i64p = ctypes.POINTER(ctypes.c_int64)
+    s = stream if stream is not None else torch.cuda.current_stream(hdr.device)
+    st = load_library().ce_result_status(ctypes.c_void_p(hdr.data_ptr()), G, counts, roff.ctypes.data_as(i64p),
+                                         coff.ctypes.data_as(i64p), ctypes.c_void_p(s.cuda_stream))
+    if st != CE_OK:
+        raise ClusterError(st, last_error(), "ce_result_status")
+    return np.ctypeslib.as_array(counts).view(np.int64).reshape(G, 3).copy(), roff, coff
+
+
+def async_result(outputs: Outputs, n: int, hdr, stream=None) -> Result:
+    """The Result of a finished ``cluster_edges_async`` call (waits for the stream)."""
+    c, _, _ = result_status(hdr, 1, stream)
+    cc = CeCounts(int(c[0, 0]), int(c[0, 1]), int(c[0, 2]))
+    return _result(outputs, n, cc, make_params(2, 1))
+
+
+def async_batch_result(outputs: Outputs, edge_offsets, hdr, stream=None) -> "BatchResult":
+    """The BatchResult of a finished ``cluster_batch_async`` call; edge_offsets: host array of G+1 offsets."""
+    eo = _offsets_array(edge_offsets, "edge_offsets")
+    G, n = eo.size - 1, int(eo[-1])
+    carr, roff, coff = result_status(hdr, G, stream)
+    m_tot, c_tot = int(roff[-1]), int(coff[-1])
+    o = outputs.t
+    rows = {f: o[f][:m_tot] for f in ("msf_tail", "msf_head", "msf_w", "sl_left", "sl_right", "sl_w", "sl_size")}
+    pts = {f: o[f][:n] for f in ("pt_cluster", "pt_lambda", "labels")}
+    cls = {f: o[f][:c_tot] for f in ("cl_id", "cl_parent", "cl_size", "cl_lambda_birth", "cl_stab_hi", "cl_stab_lo",
+                                     "cl_selected")}
+    res = Result(m=m_tot, n_clusters=c_tot, n_labels=int(carr[:, 2].sum()), **rows, **pts, **cls)
+    return BatchResult(result=res, m=carr[:, 0].copy(), n_clusters=carr[:, 1].copy(), n_labels=carr[:, 2].copy(),
+                       edge_offsets=eo, row_offsets=roff, cluster_offsets=coff)
 
 
 def hyper_workspace_bytes(n: int, nnz: int, num_vertices: int, min_cluster_size: int, thresholds=None) -> int:

@@ -53,16 +53,19 @@ namespace {
 
 constexpr int B = 256;
 
-__global__ __launch_bounds__(B) void k_iota32(uint32_t *p, int64_t n) {
+__global__ __launch_bounds__(B) void k_iota32(uint32_t *p, Cnt nc) {
+  const int64_t n = nc.get();
   for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < n; i += (int64_t)gridDim.x * B) p[i] = (uint32_t)i;
 }
-__global__ __launch_bounds__(B) void k_zero32(uint32_t *p, int64_t n) {
+__global__ __launch_bounds__(B) void k_zero32(uint32_t *p, Cnt nc) {
+  const int64_t n = nc.get();
   for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < n; i += (int64_t)gridDim.x * B) p[i] = 0u;
 }
 
 // graph of each MSF row (the graph of its tail record)
-__global__ __launch_bounds__(B) void k_rowg(const uint64_t *msf_val, const uint32_t *grank, int64_t m, uint32_t *rowg,
+__global__ __launch_bounds__(B) void k_rowg(const uint64_t *msf_val, const uint32_t *grank, Cnt mc, uint32_t *rowg,
                                             uint32_t *key) {
+  const int64_t m = mc.get();
   for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
     const uint32_t g = grank[(uint32_t)msf_val[j]];
     rowg[j] = g;
@@ -70,11 +73,13 @@ __global__ __launch_bounds__(B) void k_rowg(const uint64_t *msf_val, const uint3
   }
 }
 
-__global__ void k_set2_u32(uint32_t *p, uint32_t a, uint32_t b) {
-  if (threadIdx.x == 0) { p[0] = a; p[1] = b; }
+// one graph: its rows are all rows
+__global__ void k_moff_one(uint32_t *moff, const uint64_t *m) {
+  if (threadIdx.x == 0) { moff[0] = 0; moff[1] = (uint32_t)*m; }
 }
 
-__global__ __launch_bounds__(B) void k_rowpos(const uint32_t *sorted_j, int64_t m, uint32_t *rowpos) {
+__global__ __launch_bounds__(B) void k_rowpos(const uint32_t *sorted_j, Cnt mc, uint32_t *rowpos) {
+  const int64_t m = mc.get();
   for (int64_t p = (int64_t)blockIdx.x * B + threadIdx.x; p < m; p += (int64_t)gridDim.x * B)
     rowpos[sorted_j[p]] = (uint32_t)p;
 }
@@ -86,8 +91,9 @@ __global__ __launch_bounds__(B) void k_rows(const uint64_t *msf_key, const uint6
                                             const uint32_t *kc_u,
                                             const uint32_t *kc_v, const uint32_t *ksize, const uint32_t *rowg,
                                             const uint32_t *rowpos, const uint32_t *moff, const int64_t *eoff,
-                                            int64_t m, int64_t n, int idbits, int wshift, int hshift, bool one,
+                                            Cnt mc, int64_t n, int idbits, int wshift, int hshift, bool one,
                                             ce_result out) {
+  const int64_t m = mc.get();
   const uint64_t idmask = (uint64_t(1) << idbits) - 1;
   for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
     const uint32_t tr = (uint32_t)msf_val[j];
@@ -113,7 +119,8 @@ __global__ __launch_bounds__(B) void k_rows(const uint64_t *msf_key, const uint6
 // At most one record in the whole batch: there is no line-graph edge, every
 // graph's only cluster is its root (local id n_g, size n_g), and a record
 // leaves its root at lambda 0 as noise.
-__global__ void k_trivial(const int64_t *eoff, int64_t G, ce_result out) {
+__global__ void k_trivial(const int64_t *eoff, int64_t G, const uint64_t *hdr, ce_result out) {
+  if (hdr[H_STATUS] != 0) return;  // a data error: no output is written
   for (int64_t g = threadIdx.x; g < G; g += blockDim.x) {
     const int64_t ng = eoff[g + 1] - eoff[g];
     if (ng == 1) {
@@ -142,46 +149,37 @@ size_t stage_graph_rows_scratch(int64_t n, int64_t G) {
 
 // Position of every MSF row in the output: graphs in order, the rows of one
 // graph in ascending key (a stable partition of the sorted MSF by graph).
-ce_status stage_graph_rows(Bufs &b, int64_t m, Ws &ws, hipStream_t s, int64_t *row_offsets) {
-  const int64_t G = b.G;
+// moff[g] = the first row of graph g.
+ce_status stage_graph_rows(Bufs &b, Ws &ws, hipStream_t s) {
+  const int64_t G = b.G, mb = b.n > 1 ? b.n - 1 : 1;
+  const Cnt m(&b.hdr[H_M], mb);
   size_t m0 = ws.mark();
-  uint32_t *key = ws.alloc<uint32_t>(m), *val = ws.alloc<uint32_t>(m);
-  uint32_t *key2 = ws.alloc<uint32_t>(m), *val2 = ws.alloc<uint32_t>(m);
+  uint32_t *key = ws.alloc<uint32_t>(mb), *val = ws.alloc<uint32_t>(mb);
+  uint32_t *key2 = ws.alloc<uint32_t>(mb), *val2 = ws.alloc<uint32_t>(mb);
   CE_WS_CHECK(ws);
   if (G == 1) {
-    if (m > 0) {
-      CE_LAUNCH(k_zero32, dim3(grid_for(m, B)), dim3(B), 0, s, b.rowg, m);
-      CE_LAUNCH(k_iota32, dim3(grid_for(m, B)), dim3(B), 0, s, b.rowpos, m);
-    }
-    CE_LAUNCH(k_set2_u32, dim3(1), dim3(64), 0, s, b.moff, 0u, (uint32_t)m);
+    CE_LAUNCH(k_zero32, dim3(grid_cap(mb, B)), dim3(B), 0, s, b.rowg, m);
+    CE_LAUNCH(k_iota32, dim3(grid_cap(mb, B)), dim3(B), 0, s, b.rowpos, m);
+    CE_LAUNCH(k_moff_one, dim3(1), dim3(64), 0, s, b.moff, &b.hdr[H_M]);
   } else {
-    const uint32_t *sorted = key;
-    if (m > 0) {
-      CE_LAUNCH(k_rowg, dim3(grid_for(m, B)), dim3(B), 0, s, b.msf_val, b.grank, m, b.rowg, key);
-      CE_HIP(hipGetLastError());
-      bool alt = false;
-      CE_TRY((radix_sort_pairs<uint32_t, uint32_t>(key, val, key2, val2, m, 0, bits_for((uint64_t)(G - 1)), true,
-                                                   &alt, ws, s)));
-      CE_LAUNCH(k_rowpos, dim3(grid_for(m, B)), dim3(B), 0, s, alt ? val2 : val, m, b.rowpos);
-      sorted = alt ? key2 : key;
-    }
-    CE_TRY(segment_bounds_u32(sorted, m, G, b.moff, s));
+    CE_LAUNCH(k_rowg, dim3(grid_cap(mb, B)), dim3(B), 0, s, b.msf_val, b.grank, m, b.rowg, key);
+    CE_HIP(hipGetLastError());
+    bool alt = false;
+    CE_TRY((radix_sort_pairs<uint32_t, uint32_t>(key, val, key2, val2, m, 0, bits_for((uint64_t)(G - 1)), true,
+                                                 &alt, ws, s)));
+    CE_LAUNCH(k_rowpos, dim3(grid_cap(mb, B)), dim3(B), 0, s, alt ? val2 : val, m, b.rowpos);
+    CE_TRY(segment_bounds_u32(alt ? key2 : key, m, G, b.moff, s));
   }
   CE_HIP(hipGetLastError());
-  if (row_offsets) {
-    std::vector<uint32_t> h(G + 1);
-    CE_HIP(hipMemcpyAsync(h.data(), b.moff, sizeof(uint32_t) * (G + 1), hipMemcpyDeviceToHost, s));
-    CE_HIP(hipStreamSynchronize(s));
-    for (int64_t g = 0; g <= G; g++) row_offsets[g] = h[g];
-  }
   ws.release(m0);
   return CE_OK;
 }
 
-ce_status stage_write_rows(Bufs &b, int64_t m, const ce_result *out, hipStream_t s) {
-  if (m <= 0) return CE_OK;
-  CE_LAUNCH(k_rows, dim3(grid_for(m, B)), dim3(B), 0, s, b.msf_key, b.msf_val, b.perm, b.kc_u, b.kc_v, b.ksize, b.rowg,
-            b.rowpos, b.moff, b.eoff, m, b.n, b.idbits, b.wshift, b.hshift, b.G == 1, *out);
+ce_status stage_write_rows(Bufs &b, const ce_result *out, hipStream_t s) {
+  const int64_t mb = b.n > 1 ? b.n - 1 : 1;
+  CE_LAUNCH(k_rows, dim3(grid_cap(mb, B)), dim3(B), 0, s, b.msf_key, b.msf_val, b.perm, b.kc_u, b.kc_v, b.ksize,
+            b.rowg, b.rowpos, b.moff, b.eoff, Cnt(&b.hdr[H_M], mb), b.n, b.idbits, b.wshift, b.hshift, b.G == 1,
+            *out);
   CE_HIP(hipGetLastError());
   return CE_OK;
 }
@@ -196,7 +194,8 @@ ce_status stage_write_rows(Bufs &b, int64_t m, const ce_result *out, hipStream_t
 static void layout(Bufs &b, Ws &ws, int64_t n, int64_t M, int64_t G, bool discrete, int64_t nnz) {
   const int64_t slots = nnz >= 0 ? (nnz > 0 ? nnz : 1) : 2 * n;
   b.slots = slots;
-  b.hdr = ws.alloc<uint64_t>(16);
+  b.hdr = ws.alloc<uint64_t>(kHdrWords);
+  b.outhdr = ws.alloc<int64_t>(CE_HDR_WORDS(G));
   b.thr = ws.alloc<int64_t>(CE_MAX_THRESHOLDS);
   b.eoff = ws.alloc<int64_t>(G + 1);
   b.voff = ws.alloc<int64_t>(G + 1);
@@ -261,7 +260,7 @@ struct Thresholds {
 static ce_status thresholds_of(const ce_params *p, Thresholds *th) {
   th->v = nullptr;
   th->q = 0;
-  if (p->struct_size < sizeof(ce_params) || p->num_thresholds == 0) return CE_OK;
+  if (p->struct_size < CE_PARAMS_V3_SIZE || p->num_thresholds == 0) return CE_OK;
   if (p->num_thresholds < 0 || p->num_thresholds > CE_MAX_THRESHOLDS || !p->thresholds) {
     set_error("num_thresholds must be in [0, 64] with a thresholds array");
     return CE_EINVAL;
@@ -278,7 +277,7 @@ static ce_status thresholds_of(const ce_params *p, Thresholds *th) {
 }
 
 // condensing on the discrete dendrogram needs room for nodes with many children
-static bool discrete_of(const ce_params *p) { return p->struct_size >= sizeof(ce_params) && p->num_thresholds > 0; }
+static bool discrete_of(const ce_params *p) { return p->struct_size >= CE_PARAMS_V3_SIZE && p->num_thresholds > 0; }
 
 static size_t workspace_for(int64_t n, int64_t M, int64_t G, bool discrete, int64_t nnz = -1) {
   Bufs b;
@@ -311,37 +310,107 @@ static ce_status check_offsets(const int64_t *eoff, const int64_t *voff, int64_t
   return CE_OK;
 }
 
-// A dynamic hypergraph's memberships (device CSR), for run_batch.
+// A dynamic hypergraph's memberships (device CSR), for run_call.
 struct HyperIn {
   const int32_t *members;
   const int64_t *offsets;
   int64_t nnz;
 };
 
-// Runs a checked batch; eoff/voff are host arrays of G+1 offsets. With hy,
-// the records are the hyperedges of one hypergraph (G = 1) and src/dst are
-// not used.
-static ce_status run_batch(const int32_t *src, const int32_t *dst, const int64_t *t, const int64_t *eoff,
-                           const int64_t *voff, int64_t G, int64_t M, bool causal, int64_t max_dt,
-                           Thresholds th, const ce_result *out, ce_counts *counts,
-                           int64_t *row_offsets, int64_t *cluster_offsets, void *workspace, size_t workspace_bytes,
-                           hipStream_t s, const HyperIn *hy = nullptr) {
-  const int64_t n = eoff[G], V = voff[G];
-  for (int64_t g = 0; g < G; g++) counts[g] = ce_counts{0, 1, 0};
+// One clustering call: inputs, host-known sizes and where the offsets live.
+struct Call {
+  const int32_t *src = nullptr, *dst = nullptr;
+  const int64_t *t = nullptr;
+  int64_t n = 0, V = 0, G = 1;
+  const int64_t *eoff_h = nullptr, *voff_h = nullptr;  // host offsets (G+1 each), or
+  const int64_t *eoff_d = nullptr, *voff_d = nullptr;  // device offsets (asynchronous batches)
+  const HyperIn *hy = nullptr;
+  int64_t M = 2;
+  bool causal = false;
+  int64_t max_dt = -1;
+  Thresholds th;
+  int time_bits = 0;  // asynchronous calls: the declared bound on bits(max t - min t)
+};
+
+namespace {
+
+struct ThrArg {
+  int64_t v[CE_MAX_THRESHOLDS];
+};
+__global__ void k_set_thresholds(int64_t *thr, ThrArg a, int q) {
+  for (int i = threadIdx.x; i < q; i += blockDim.x) thr[i] = a.v[i];
+}
+__global__ void k_set_offsets_one(int64_t *eoff, int64_t *voff, int64_t n, int64_t V) {
+  if (threadIdx.x == 0) { eoff[0] = 0; eoff[1] = n; voff[0] = 0; voff[1] = V; }
+}
+__global__ __launch_bounds__(B) void k_copy_i64(int64_t *dst, const int64_t *src, int64_t k) {
+  for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < k; i += (int64_t)gridDim.x * B) dst[i] = src[i];
+}
+// device offsets of an asynchronous batch: start at 0, non-decreasing, every
+// graph with a vertex, totals as declared; a violation is an argument error
+__global__ __launch_bounds__(B) void k_check_offsets(const int64_t *eoff, const int64_t *voff, int64_t G, int64_t n,
+                                                     int64_t V, uint64_t *hdr) {
+  for (int64_t g = (int64_t)blockIdx.x * B + threadIdx.x; g <= G; g += (int64_t)gridDim.x * B) {
+    bool bad = false;
+    if (g == 0) bad = eoff[0] != 0 || voff[0] != 0;
+    else bad = eoff[g] < eoff[g - 1] || voff[g] <= voff[g - 1];
+    if (g == G) bad = bad || eoff[G] != n || voff[G] != V;
+    if (bad) atomicOr((unsigned long long *)&hdr[H_STATUS], 4ull);
+  }
+}
+// the call's header when there is at most one record: no rows, one cluster (the root) per graph
+__global__ __launch_bounds__(B) void k_header_trivial(const uint64_t *hdr, int64_t G, int64_t *out) {
+  for (int64_t g = (int64_t)blockIdx.x * B + threadIdx.x; g <= G; g += (int64_t)gridDim.x * B) {
+    if (g == 0) {
+      out[0] = status_of(hdr[H_STATUS]);
+      out[1] = 0;
+      out[2] = G;
+      out[3] = 0;
+    }
+    if (g < G) {
+      out[4 + 3 * g] = 0;
+      out[4 + 3 * g + 1] = 1;
+      out[4 + 3 * g + 2] = 0;
+    }
+    out[4 + 3 * G + g] = 0;
+    out[4 + 3 * G + (G + 1) + g] = g;
+  }
+}
+
+}  // namespace
+
+// The whole pipeline on one stream. Synchronous calls (counts != nullptr)
+// read the validation words back once (errors are returned at once and the
+// time span's exact width sets the key layout) and the call's header at the
+// end. Asynchronous calls (hdr_out, a device pointer) read nothing back: the
+// key layout comes from the declared time_bits, and the header, status
+// included, is written on the device.
+static ce_status run_call(const Call &c, const ce_result *out, ce_counts *counts, int64_t *row_offsets,
+                          int64_t *cluster_offsets, int64_t *hdr_out, void *workspace, size_t workspace_bytes,
+                          hipStream_t s) {
+  const int64_t n = c.n, V = c.V, G = c.G;
+  const bool sync = counts != nullptr;
+  const HyperIn *hy = c.hy;
+  if (sync)
+    for (int64_t g = 0; g < G; g++) counts[g] = ce_counts{0, 1, 0};
   if (hy) {
-    if (!hy->offsets || (n > 0 && !t) || (hy->nnz > 0 && !hy->members)) {
+    if (!hy->offsets || (n > 0 && !c.t) || (hy->nnz > 0 && !hy->members)) {
       set_error("input pointer is NULL");
       return CE_EINVAL;
     }
-  } else if (n > 0 && (!src || !dst || !t)) {
+  } else if (n > 0 && (!c.src || !c.dst || !c.t)) {
     set_error("input pointer is NULL");
     return CE_EINVAL;
   }
   const int64_t nnz = hy ? hy->nnz : -1;
-  const size_t need = workspace_for(n, M, G, th.q > 0, nnz);
+  const size_t need = workspace_for(n, c.M, G, c.th.q > 0, nnz);
   void *base = workspace;
   bool own = false, async_alloc = true;
   if (!base) {
+    if (!sync) {
+      set_error("asynchronous calls need a workspace");
+      return CE_EINVAL;
+    }
     if (hipMallocAsync(&base, need, s) != hipSuccess) {
       (void)hipGetLastError();
       async_alloc = false;
@@ -366,82 +435,107 @@ static ce_status run_batch(const int32_t *src, const int32_t *dst, const int64_t
   ws.base = (char *)base;
   ws.cap = need;
   Bufs b;
-  layout(b, ws, n, M, G, th.q > 0, nnz);
+  layout(b, ws, n, c.M, G, c.th.q > 0, nnz);
   CE_WS_CHECK(ws);
   b.n = n;
   b.V = V;
-  b.M = M;
+  b.M = c.M;
   b.G = G;
-  CE_HIP(hipMemcpyAsync((void *)b.eoff, eoff, sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, s));
-  if (th.q > 0) {
-    CE_HIP(hipMemcpyAsync((void *)b.thr, th.v, sizeof(int64_t) * th.q, hipMemcpyHostToDevice, s));
-    b.q = (int)th.q;
-    // rows above the last threshold merge nothing in the discrete dendrogram
-    if (max_dt < 0 || max_dt > th.v[th.q - 1]) max_dt = th.v[th.q - 1];
+  int64_t *hout = sync ? b.outhdr : hdr_out;
+  // offsets and thresholds reach the device without host staging (a call may be captured in a graph)
+  if (c.eoff_d) {
+    CE_LAUNCH(k_copy_i64, dim3(grid_for(G + 1, B, 1024)), dim3(B), 0, s, (int64_t *)b.eoff, c.eoff_d, G + 1);
+    CE_LAUNCH(k_copy_i64, dim3(grid_for(G + 1, B, 1024)), dim3(B), 0, s, (int64_t *)b.voff, c.voff_d, G + 1);
+  } else if (G == 1) {
+    CE_LAUNCH(k_set_offsets_one, dim3(1), dim3(64), 0, s, (int64_t *)b.eoff, (int64_t *)b.voff, n, V);
+  } else {
+    CE_HIP(hipMemcpyAsync((void *)b.eoff, c.eoff_h, sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, s));
+    CE_HIP(hipMemcpyAsync((void *)b.voff, c.voff_h, sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, s));
   }
-  CE_HIP(hipMemcpyAsync((void *)b.voff, voff, sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, s));
-  uint64_t flags = 0;
-  int64_t tmin = 0, tmax = 0;
-  if (hy) {
-    CE_TRY(stage_hyper_validate(hy->members, hy->offsets, t, nnz, b, s, &flags, &tmin, &tmax));
+  int64_t max_dt = c.max_dt;
+  if (c.th.q > 0) {
+    ThrArg a;
+    for (int64_t i = 0; i < c.th.q; i++) a.v[i] = c.th.v[i];
+    CE_LAUNCH(k_set_thresholds, dim3(1), dim3(64), 0, s, (int64_t *)b.thr, a, (int)c.th.q);
+    b.q = (int)c.th.q;
+    // rows above the last threshold merge nothing in the discrete dendrogram
+    if (max_dt < 0 || max_dt > c.th.v[c.th.q - 1]) max_dt = c.th.v[c.th.q - 1];
+  }
+  CE_HIP(hipGetLastError());
+  if (hy) CE_TRY(stage_hyper_validate(hy->members, hy->offsets, c.t, nnz, b, s));
+  else CE_TRY(stage_validate(c.src, c.dst, c.t, b, s));
+  if (c.eoff_d)
+    CE_LAUNCH(k_check_offsets, dim3(grid_for(G + 1, B, 1024)), dim3(B), 0, s, b.eoff, b.voff, G, n, V, b.hdr);
+  CE_HIP(hipGetLastError());
+  int tbits;
+  if (sync) {
+    uint64_t flags = 0;
+    int64_t tmin = 0, tmax = 0;
+    CE_TRY(read_validation(b, s, &flags, &tmin, &tmax));
     if (flags & 4) {
-      set_error("offsets must start at 0, be non-decreasing and end at nnz");
+      set_error(hy ? "offsets must start at 0, be non-decreasing and end at nnz" : "bad graph offsets");
       return CE_EINVAL;
     }
-    if (flags & 2) { set_error("member outside [0, num_vertices)"); return CE_ERANGE; }
-  } else if (n > 0) {
-    CE_TRY(stage_validate(src, dst, t, b, s, &flags, &tmin, &tmax));
     if (flags & 1) { set_error("self loop in input (src == dst)"); return CE_ESELFLOOP; }
-    if (flags & 2) { set_error("vertex id outside [0, num_vertices) of its graph"); return CE_ERANGE; }
-  }
-  if (n <= 1) {
-    CE_LAUNCH(k_trivial, dim3(1), dim3(256), 0, s, b.eoff, G, *out);
-    CE_HIP(hipGetLastError());
-    CE_HIP(hipStreamSynchronize(s));
-    for (int64_t g = 0; g <= G; g++) {
-      if (row_offsets) row_offsets[g] = 0;
-      if (cluster_offsets) cluster_offsets[g] = g;
+    if (flags & 2) {
+      set_error(hy ? "member outside [0, num_vertices)" : "vertex id outside [0, num_vertices) of its graph");
+      return CE_ERANGE;
     }
-    return CE_OK;
+    tbits = n > 0 ? bits_for((uint64_t)tmax - (uint64_t)tmin) : 0;
+  } else {
+    tbits = c.time_bits > 0 ? c.time_bits : 62;
   }
-  const uint64_t span = (uint64_t)tmax - (uint64_t)tmin;
-  b.tmin = tmin;
-  b.tbits = bits_for(span);
-  b.idbits = bits_for((uint64_t)(n - 1));
+  b.tbits = tbits;
+  b.idbits = bits_for((uint64_t)(n > 1 ? n - 1 : 0));
   b.vbits = bits_for((uint64_t)(V - 1));
-  b.flat = causal || hy;
+  b.flat = c.causal || hy;
   b.hshift = 1;  // causal and hypergraph modes set their own shifts once the tie terms are known
   b.wshift = b.idbits + 1;
   b.keybits = b.tbits + b.wshift;
   // the all-ones word marks an absent edge, so a key may use at most 63 bits
   if (!b.flat && b.keybits > 63) {
-    set_error("time span too wide: bits(span) + bits(n-1) + 1 > 63");
+    set_error(sync ? "time span too wide: bits(span) + bits(n-1) + 1 > 63"
+                   : "declared time_bits too wide: time_bits + bits(n-1) + 1 > 63");
     return CE_ERANGE;
   }
-  Ws wa, wm, wb;
-  wa.base = b.scratch_a;
-  wa.cap = b.scratch_a_bytes;
-  wm.base = b.scratch_m;
-  wm.cap = b.scratch_m_bytes;
-  wb.base = b.scratch_b;
-  wb.cap = b.scratch_b_bytes;
-  int64_t m = 0;
-  std::vector<int64_t> roff(G + 1);
-  if (hy) CE_TRY(stage_hyper_skeleton(hy->members, hy->offsets, t, nnz, b, wa, s));
-  else if (causal) CE_TRY(stage_causal_skeleton(src, dst, t, b, wa, s));
-  else CE_TRY(stage_sort_skeleton(src, dst, t, b, wa, s));
-  CE_TRY(stage_boruvka(b, wa, s));
-  CE_TRY(stage_msf_sort(b, wm, s, &m));
-  if (max_dt >= 0) CE_TRY(stage_time_filter(b, max_dt, s, &m));
-  CE_TRY(stage_dendrogram(b, m, wb, s));
-  CE_TRY(stage_graph_rows(b, m, wb, s, roff.data()));
-  CE_TRY(stage_write_rows(b, m, out, s));
-  CE_TRY(stage_condense(b, m, out, wb, s, counts, cluster_offsets));
-  for (int64_t g = 0; g < G; g++) counts[g].m = roff[g + 1] - roff[g];
-  if (row_offsets)
-    for (int64_t g = 0; g <= G; g++) row_offsets[g] = roff[g];
+  if (!sync) CE_TRY(stage_check_span(b, s));
+  if (n <= 1) {
+    CE_LAUNCH(k_trivial, dim3(1), dim3(256), 0, s, b.eoff, G, b.hdr, *out);
+    CE_LAUNCH(k_header_trivial, dim3(grid_for(G + 1, B, 1024)), dim3(B), 0, s, b.hdr, G, hout);
+    CE_HIP(hipGetLastError());
+  } else {
+    Ws wa, wm, wb;
+    wa.base = b.scratch_a;
+    wa.cap = b.scratch_a_bytes;
+    wm.base = b.scratch_m;
+    wm.cap = b.scratch_m_bytes;
+    wb.base = b.scratch_b;
+    wb.cap = b.scratch_b_bytes;
+    if (hy) CE_TRY(stage_hyper_skeleton(hy->members, hy->offsets, c.t, nnz, b, wa, s));
+    else if (c.causal) CE_TRY(stage_causal_skeleton(c.src, c.dst, c.t, b, wa, s));
+    else CE_TRY(stage_sort_skeleton(c.src, c.dst, c.t, b, wa, s));
+    CE_TRY(stage_boruvka(b, wa, s));
+    CE_TRY(stage_msf_sort(b, wm, s));
+    if (max_dt >= 0) CE_TRY(stage_time_filter(b, max_dt, s));
+    CE_TRY(stage_dendrogram(b, wb, s));
+    CE_TRY(stage_graph_rows(b, wb, s));
+    CE_TRY(stage_write_rows(b, out, s));
+    CE_TRY(stage_condense(b, out, wb, s, hout));
+  }
+  if (!sync) return CE_OK;
+  std::vector<int64_t> h(CE_HDR_WORDS(G));
+  CE_HIP(hipMemcpyAsync(h.data(), hout, sizeof(int64_t) * h.size(), hipMemcpyDeviceToHost, s));
   CE_HIP(hipStreamSynchronize(s));
   timing_collect();
+  if (h[0] != CE_OK) {
+    set_error(h[0] == CE_EDEVICE ? "internal: a bounded loop did not converge" : "input data error");
+    return (ce_status)h[0];
+  }
+  for (int64_t g = 0; g < G; g++) counts[g] = ce_counts{h[4 + 3 * g], h[4 + 3 * g + 1], h[4 + 3 * g + 2]};
+  for (int64_t g = 0; g <= G; g++) {
+    if (row_offsets) row_offsets[g] = h[4 + 3 * G + g];
+    if (cluster_offsets) cluster_offsets[g] = h[4 + 3 * G + (G + 1) + g];
+  }
   return CE_OK;
 }
 
@@ -476,6 +570,12 @@ size_t ce_batch_workspace_bytes(const int64_t *edge_offsets, const int64_t *vert
   return workspace_for(edge_offsets[num_graphs], params->min_cluster_size, num_graphs, discrete_of(params));
 }
 
+size_t ce_batch_workspace_bytes_for(int64_t n, int64_t num_graphs, const ce_params *params) {
+  if (check_params(params) != CE_OK || n < 0 || n > 0x7fffffffLL || num_graphs < 1 || num_graphs > CE_MAX_GRAPHS)
+    return 0;
+  return workspace_for(n, params->min_cluster_size, num_graphs, discrete_of(params));
+}
+
 const char *ce_last_error(void) { return g_err.c_str(); }
 
 int ce_timing_enable(const char *kernel_name) {
@@ -493,22 +593,67 @@ int ce_timing_read(double *total_ms, int64_t *launches) {
   return 0;
 }
 
-ce_status ce_cluster_edges(const int32_t *src, const int32_t *dst, const int64_t *t, int64_t n, const ce_params *params,
-                           const ce_result *out, ce_counts *counts, void *workspace, size_t workspace_bytes,
-                           void *stream) {
+static int time_bits_of(const ce_params *p) {
+  return p->struct_size >= CE_PARAMS_V4_SIZE ? (int)p->time_bits : 0;
+}
+
+// The key layout of an asynchronous call comes from the declared time_bits; it is checked before anything
+// is enqueued.
+static ce_status check_async_key(int time_bits, int64_t n) {
+  const int tb = time_bits > 0 ? time_bits : 62;
+  if (tb + bits_for((uint64_t)(n > 1 ? n - 1 : 0)) + 1 > 63) {
+    set_error("declared time_bits too wide: time_bits + bits(n-1) + 1 > 63");
+    return CE_ERANGE;
+  }
+  return CE_OK;
+}
+
+static ce_status single_call(Call &c, const int32_t *src, const int32_t *dst, const int64_t *t, int64_t n,
+                             const ce_params *params) {
   CE_TRY(check_params(params));
-  if (!out || !counts) { set_error("out/counts is NULL"); return CE_EINVAL; }
   if (params->num_vertices < 1 || params->num_vertices > 0x80000000LL) {
     set_error("num_vertices must be in [1, 2^31]");
     return CE_EINVAL;
   }
   if (n < 0 || n > 0x7fffffffLL) { set_error("n must be in [0, 2^31-1]"); return CE_EINVAL; }
-  const int64_t eoff[2] = {0, n}, voff[2] = {0, params->num_vertices};
-  Thresholds th;
-  CE_TRY(thresholds_of(params, &th));
-  return run_batch(src, dst, t, eoff, voff, 1, params->min_cluster_size, params->mode == CE_MODE_CAUSAL,
-                   max_dt_of(params), th, out, counts, nullptr, nullptr, workspace, workspace_bytes,
-                   (hipStream_t)stream);
+  if (time_bits_of(params) < 0 || time_bits_of(params) > 62) {
+    set_error("time_bits must be in [0, 62]");
+    return CE_EINVAL;
+  }
+  c.src = src;
+  c.dst = dst;
+  c.t = t;
+  c.n = n;
+  c.V = params->num_vertices;
+  c.G = 1;
+  c.M = params->min_cluster_size;
+  c.causal = params->mode == CE_MODE_CAUSAL;
+  c.max_dt = max_dt_of(params);
+  c.time_bits = time_bits_of(params);
+  return thresholds_of(params, &c.th);
+}
+
+ce_status ce_cluster_edges(const int32_t *src, const int32_t *dst, const int64_t *t, int64_t n, const ce_params *params,
+                           const ce_result *out, ce_counts *counts, void *workspace, size_t workspace_bytes,
+                           void *stream) {
+  if (!out || !counts) { set_error("out/counts is NULL"); return CE_EINVAL; }
+  Call c;
+  CE_TRY(single_call(c, src, dst, t, n, params));
+  return run_call(c, out, counts, nullptr, nullptr, nullptr, workspace, workspace_bytes, (hipStream_t)stream);
+}
+
+ce_status ce_cluster_edges_async(const int32_t *src, const int32_t *dst, const int64_t *t, int64_t n,
+                                 const ce_params *params, const ce_result *out, int64_t *hdr, void *workspace,
+                                 size_t workspace_bytes, void *stream) {
+  if (!out || !hdr) { set_error("out/hdr is NULL"); return CE_EINVAL; }
+  Call c;
+  CE_TRY(single_call(c, src, dst, t, n, params));
+  if (c.causal) {
+    set_error("asynchronous calls cluster the undirected line graph (mode must be CE_MODE_UNDIRECTED)");
+    return CE_EINVAL;
+  }
+  CE_TRY(check_async_key(c.time_bits, n));
+  return run_call(c, out, nullptr, nullptr, nullptr, hdr, workspace, workspace_bytes, (hipStream_t)stream);
 }
 
 size_t ce_hyper_workspace_bytes(int64_t n, int64_t nnz, const ce_params *params) {
@@ -533,12 +678,16 @@ ce_status ce_cluster_hyperedges(const int32_t *members, const int64_t *offsets, 
   }
   if (n < 0 || n > 0x7fffffffLL) { set_error("n must be in [0, 2^31-1]"); return CE_EINVAL; }
   if (nnz < 0 || nnz > 0x7fffffffLL) { set_error("nnz must be in [0, 2^31-1]"); return CE_EINVAL; }
-  const int64_t eoff[2] = {0, n}, voff[2] = {0, params->num_vertices};
-  Thresholds th;
-  CE_TRY(thresholds_of(params, &th));
   const HyperIn hy{members, offsets, nnz};
-  return run_batch(nullptr, nullptr, t, eoff, voff, 1, params->min_cluster_size, false, max_dt_of(params), th, out,
-                   counts, nullptr, nullptr, workspace, workspace_bytes, (hipStream_t)stream, &hy);
+  Call c;
+  c.t = t;
+  c.n = n;
+  c.V = params->num_vertices;
+  c.M = params->min_cluster_size;
+  c.max_dt = max_dt_of(params);
+  c.hy = &hy;
+  CE_TRY(thresholds_of(params, &c.th));
+  return run_call(c, out, counts, nullptr, nullptr, nullptr, workspace, workspace_bytes, (hipStream_t)stream);
 }
 
 ce_status ce_cluster_batch(const int32_t *src, const int32_t *dst, const int64_t *t, const int64_t *edge_offsets,
@@ -551,11 +700,89 @@ ce_status ce_cluster_batch(const int32_t *src, const int32_t *dst, const int64_t
     return CE_EINVAL;
   }
   CE_TRY(check_offsets(edge_offsets, vertex_offsets, num_graphs));
-  Thresholds th;
-  CE_TRY(thresholds_of(params, &th));
-  return run_batch(src, dst, t, edge_offsets, vertex_offsets, num_graphs, params->min_cluster_size,
-                   params->mode == CE_MODE_CAUSAL, max_dt_of(params), th, out, counts, row_offsets, cluster_offsets,
-                   workspace, workspace_bytes, (hipStream_t)stream);
+  Call c;
+  c.src = src;
+  c.dst = dst;
+  c.t = t;
+  c.G = num_graphs;
+  c.n = edge_offsets[num_graphs];
+  c.V = vertex_offsets[num_graphs];
+  c.eoff_h = edge_offsets;
+  c.voff_h = vertex_offsets;
+  c.M = params->min_cluster_size;
+  c.causal = params->mode == CE_MODE_CAUSAL;
+  c.max_dt = max_dt_of(params);
+  CE_TRY(thresholds_of(params, &c.th));
+  return run_call(c, out, counts, row_offsets, cluster_offsets, nullptr, workspace, workspace_bytes,
+                  (hipStream_t)stream);
+}
+
+ce_status ce_cluster_batch_async(const int32_t *src, const int32_t *dst, const int64_t *t, int64_t n,
+                                 const int64_t *edge_offsets, const int64_t *vertex_offsets, int64_t num_graphs,
+                                 int64_t num_vertices, const ce_params *params, const ce_result *out, int64_t *hdr,
+                                 void *workspace, size_t workspace_bytes, void *stream) {
+  CE_TRY(check_params(params));
+  if (!out || !hdr || !edge_offsets || !vertex_offsets) {
+    set_error("out/hdr/edge_offsets/vertex_offsets is NULL");
+    return CE_EINVAL;
+  }
+  if (num_graphs < 1 || num_graphs > CE_MAX_GRAPHS) { set_error("number of graphs must be in [1, 2^24]"); return CE_EINVAL; }
+  if (n < 0 || n > 0x7fffffffLL) { set_error("n must be in [0, 2^31-1]"); return CE_EINVAL; }
+  if (num_vertices < num_graphs || num_vertices > 0x80000000LL) {
+    set_error("num_vertices must be in [num_graphs, 2^31]");
+    return CE_EINVAL;
+  }
+  if (params->mode != CE_MODE_UNDIRECTED) {
+    set_error("asynchronous calls cluster the undirected line graph (mode must be CE_MODE_UNDIRECTED)");
+    return CE_EINVAL;
+  }
+  if (time_bits_of(params) < 0 || time_bits_of(params) > 62) {
+    set_error("time_bits must be in [0, 62]");
+    return CE_EINVAL;
+  }
+  CE_TRY(check_async_key(time_bits_of(params), n));
+  Call c;
+  c.src = src;
+  c.dst = dst;
+  c.t = t;
+  c.G = num_graphs;
+  c.n = n;
+  c.V = num_vertices;
+  c.eoff_d = edge_offsets;
+  c.voff_d = vertex_offsets;
+  c.M = params->min_cluster_size;
+  c.max_dt = max_dt_of(params);
+  c.time_bits = time_bits_of(params);
+  CE_TRY(thresholds_of(params, &c.th));
+  return run_call(c, out, nullptr, nullptr, nullptr, hdr, workspace, workspace_bytes, (hipStream_t)stream);
+}
+
+ce_status ce_result_status(const int64_t *hdr, int64_t num_graphs, ce_counts *counts, int64_t *row_offsets,
+                           int64_t *cluster_offsets, void *stream) {
+  if (!hdr || num_graphs < 1 || num_graphs > CE_MAX_GRAPHS) {
+    set_error("hdr is NULL or num_graphs outside [1, 2^24]");
+    return CE_EINVAL;
+  }
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<int64_t> h(CE_HDR_WORDS(num_graphs));
+  CE_HIP(hipMemcpyAsync(h.data(), hdr, sizeof(int64_t) * h.size(), hipMemcpyDeviceToHost, s));
+  CE_HIP(hipStreamSynchronize(s));
+  const int64_t G = num_graphs;
+  if (h[0] != CE_OK) {
+    set_error(h[0] == CE_ESELFLOOP ? "self loop in input (src == dst)"
+              : h[0] == CE_ERANGE  ? "vertex id outside [0, V) or time span wider than time_bits"
+              : h[0] == CE_EINVAL  ? "bad graph offsets"
+                                   : "internal: a bounded loop did not converge");
+    return (ce_status)h[0];
+  }
+  for (int64_t g = 0; g < G; g++) {
+    if (counts) counts[g] = ce_counts{h[4 + 3 * g], h[4 + 3 * g + 1], h[4 + 3 * g + 2]};
+  }
+  for (int64_t g = 0; g <= G; g++) {
+    if (row_offsets) row_offsets[g] = h[4 + 3 * G + g];
+    if (cluster_offsets) cluster_offsets[g] = h[4 + 3 * G + (G + 1) + g];
+  }
+  return CE_OK;
 }
 
 }  // extern "C"

@@ -197,6 +197,8 @@ __global__ __launch_bounds__(B) void k_fill_best(uint64_t *best, int64_t n) {
 
 __global__ void k_zero_u64(uint64_t *p) { *p = 0; }
 
+__global__ void k_put_u64(uint64_t *p, uint64_t v) { *p = v; }
+
 }  // namespace
 
 size_t stage_causal_skeleton_scratch(int64_t n) {
@@ -312,6 +314,7 @@ ce_status stage_causal_skeleton(const int32_t *src, const int32_t *dst, const in
   if (nbig > 0)
     CE_LAUNCH(k_emit_big, dim3((unsigned)nbig), dim3(B), 0, s, big, outpos, wa, wcnt, eoff, inpos, sv, b.ts, b.perm,
               tie, b.wshift, b.hshift, b.skel_key, b.skel_tail, b.skel_tid, b.best);
+  CE_LAUNCH(k_put_u64, dim3(1), dim3(1), 0, s, &b.hdr[H_C7], (uint64_t)S);  // the rows, for Boruvka's first round
   CE_HIP(hipGetLastError());
   ws.release(m0);
   return CE_OK;

@@ -109,6 +109,59 @@ inline unsigned grid_for(int64_t work, int block, int64_t cap = 1 << 20) {
   return (unsigned)g;
 }
 
+// ------------------------------------------------------ device-resident counts
+// A size the host knows (p == nullptr: the value v), or one an earlier kernel
+// of the same call wrote to device memory (p, read when a kernel starts; v is
+// then an upper bound that sizes grids). Data-dependent sizes travel this way,
+// so a call enqueues its whole pipeline without reading anything back.
+struct Cnt {
+  const uint64_t *p;
+  int64_t v;
+  __host__ __device__ Cnt(int64_t x = 0) : p(nullptr), v(x) {}
+  __host__ __device__ Cnt(const uint64_t *q, int64_t bound) : p(q), v(bound) {}
+  __device__ inline int64_t get() const { return p ? (int64_t)*p : v; }
+};
+
+// Blocks for a grid-stride loop over at most `bound` items: the whole chip is
+// covered several times over, and a launch whose live count turns out small
+// (or zero) costs only its dispatch.
+inline unsigned grid_cap(int64_t bound, int per_block, int64_t cap = 8192) {
+  return grid_for(bound, per_block, cap);
+}
+
+// Words of a call's control block (Bufs::hdr, kHdrWords u64 at the start of
+// the workspace).
+enum : int {
+  H_STATUS = 0,  // error bits: 1 self loop, 2 id out of range, 4 bad hypergraph offsets, 8 time span wider than
+                 // the plan's key allows; every stage after validation treats the input as empty when set
+  H_TMIN = 1,    // min t as an order-preserving u64
+  H_TMAX = 2,    // max t likewise
+  H_CNT = 4,     // list counters of the current stage
+  H_CNT2 = 5,
+  H_M = 6,       // rows of the spanning forest
+  H_C7 = 7,      // stage-local counters
+  H_C8 = 8,
+  H_C9 = 9,
+  H_NB = 10,     // cluster births
+  H_NROWS = 11,  // cluster rows (births + one root per graph)
+  H_NVIRT = 12,  // virtual sum nodes of the discrete condensing
+  H_KEYW = 13,   // key layout of the flat skeletons: wshift | hshift << 8 | keybits << 16
+  H_NEOM = 14,   // rows of the excess-of-mass tree (cluster rows + virtual nodes)
+  H_BV = 16,     // Boruvka state (24 words)
+  H_LOOP = 64,   // per-round counters of bounded loops
+  kHdrWords = 256
+};
+
+// The ce_status of a call from its error bits (H_STATUS).
+__host__ __device__ inline int64_t status_of(uint64_t bits) {
+  if (bits & 1) return CE_ESELFLOOP;
+  if (bits & 2) return CE_ERANGE;
+  if (bits & 4) return CE_EINVAL;
+  if (bits & 8) return CE_ERANGE;
+  if (bits) return CE_EDEVICE;
+  return CE_OK;
+}
+
 // ----------------------------------------------------------- u128 helpers
 struct u128 {
   uint64_t lo, hi;
@@ -247,19 +300,20 @@ __device__ inline void tile_append(const bool (&keep)[CT], const uint32_t (&vals
 
 // ------------------------------------------------------------ primitives
 // Exclusive scan of n elements; out must hold n+1 (out[n] = total). In-place allowed.
-ce_status scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, Ws &ws, hipStream_t s);
+// With a device count (n.p), n.v is the capacity and out[*n.p] gets the total.
+ce_status scan_exclusive_u32(const uint32_t *in, uint32_t *out, Cnt n, Ws &ws, hipStream_t s);
 size_t scan_ws_bytes(int64_t n);
 
 // off[g] = first position whose key is >= g, for g in [0, G] (off[G] = n), from
 // keys sorted ascending with values < G; no atomics, O(n + G) work.
-ce_status segment_bounds_u32(const uint32_t *sorted_keys, int64_t n, int64_t G, uint32_t *off, hipStream_t s);
+ce_status segment_bounds_u32(const uint32_t *sorted_keys, Cnt n, Cnt G, uint32_t *off, hipStream_t s);
 
 // Stable LSD radix sort of (key, value) pairs on bits [begin_bit, end_bit).
 // Sorts the data in (k0, v0) using (k1, v1) as ping-pong buffers; on return
 // *result_in_alt tells which pair holds the sorted output. With iota_values the
 // values start as the identity 0..n-1 (v0's contents are not read).
 template <class K, class V>
-ce_status radix_sort_pairs(K *k0, V *v0, K *k1, V *v1, int64_t n, int begin_bit, int end_bit, bool iota_values,
+ce_status radix_sort_pairs(K *k0, V *v0, K *k1, V *v1, Cnt n, int begin_bit, int end_bit, bool iota_values,
                            bool *result_in_alt, Ws &ws, hipStream_t s);
 size_t radix_ws_bytes(int64_t n);
 
@@ -295,7 +349,8 @@ struct Bufs {
   int q = 0;
   int64_t tmin = 0;
   // persistent
-  uint64_t *hdr = nullptr;      // [16] device header / counters
+  uint64_t *hdr = nullptr;      // [kHdrWords] the call's control block (H_* words)
+  int64_t *outhdr = nullptr;    // [CE_HDR_WORDS(G)] the call's header (read back by synchronous calls)
   uint64_t *ts = nullptr;       // [n] t - tmin by rank
   uint32_t *perm = nullptr;     // [n] rank -> input id
   uint32_t *rankof = nullptr;   // [n] input id -> rank (from the MSF stage on)
@@ -318,18 +373,22 @@ struct Bufs {
 uint64_t *pinned_scratch();
 ce_status read_u64(const uint64_t *dev, uint64_t *host_out, int count, hipStream_t s);
 
-ce_status stage_validate(const int32_t *src, const int32_t *dst, const int64_t *t, Bufs &b, hipStream_t s,
-                         uint64_t *flags, int64_t *tmin, int64_t *tmax);
+// Stages. Sizes that depend on the data (forest rows, births, list lengths)
+// are device words of the control block; the stages enqueue work only.
+ce_status stage_validate(const int32_t *src, const int32_t *dst, const int64_t *t, Bufs &b, hipStream_t s);
+ce_status stage_check_span(Bufs &b, hipStream_t s);
+ce_status read_validation(Bufs &b, hipStream_t s, uint64_t *flags, int64_t *tmin, int64_t *tmax);
 ce_status stage_sort_skeleton(const int32_t *src, const int32_t *dst, const int64_t *t, Bufs &b, Ws &ws,
                               hipStream_t s);
 ce_status stage_boruvka(Bufs &b, Ws &ws, hipStream_t s);
-ce_status stage_msf_sort(Bufs &b, Ws &ws, hipStream_t s, int64_t *m_out);
-ce_status stage_dendrogram(Bufs &b, int64_t m, Ws &ws, hipStream_t s);
-ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipStream_t s, ce_counts *counts,
-                         int64_t *cluster_offsets);
-ce_status stage_graph_rows(Bufs &b, int64_t m, Ws &ws, hipStream_t s, int64_t *row_offsets);
+int boruvka_rounds(int64_t n, bool split_possible);
+ce_status stage_msf_sort(Bufs &b, Ws &ws, hipStream_t s);
+ce_status stage_dendrogram(Bufs &b, Ws &ws, hipStream_t s);
+// condensing, stability, selection, labels; writes the call's header to hout
+ce_status stage_condense(Bufs &b, const ce_result *out, Ws &ws, hipStream_t s, int64_t *hout);
+ce_status stage_graph_rows(Bufs &b, Ws &ws, hipStream_t s);
 size_t stage_graph_rows_scratch(int64_t n, int64_t G);
-ce_status stage_write_rows(Bufs &b, int64_t m, const ce_result *out, hipStream_t s);
+ce_status stage_write_rows(Bufs &b, const ce_result *out, hipStream_t s);
 
 size_t stage_sort_skeleton_scratch(int64_t n);
 ce_status sort_records_by_time(const int32_t *src, const int32_t *dst, const int64_t *t, Bufs &b, Ws &ws,
@@ -337,16 +396,17 @@ ce_status sort_records_by_time(const int32_t *src, const int32_t *dst, const int
 ce_status stage_causal_skeleton(const int32_t *src, const int32_t *dst, const int64_t *t, Bufs &b, Ws &ws,
                                 hipStream_t s);
 size_t stage_causal_skeleton_scratch(int64_t n);
-ce_status stage_time_filter(Bufs &b, int64_t max_dt, hipStream_t s, int64_t *m);
+ce_status stage_time_filter(Bufs &b, int64_t max_dt, hipStream_t s);
 size_t stage_boruvka_scratch(int64_t n, int64_t slots);
 // dynamic hypergraphs (Sec. 5.3): members/offsets CSR per hyperedge
 ce_status stage_hyper_validate(const int32_t *members, const int64_t *offsets, const int64_t *t, int64_t nnz,
-                               Bufs &b, hipStream_t s, uint64_t *flags, int64_t *tmin, int64_t *tmax);
+                               Bufs &b, hipStream_t s);
 ce_status stage_hyper_skeleton(const int32_t *members, const int64_t *offsets, const int64_t *t, int64_t nnz,
                                Bufs &b, Ws &ws, hipStream_t s);
 size_t stage_hyper_skeleton_scratch(int64_t n, int64_t nnz);
 size_t stage_msf_sort_scratch(int64_t n);
 size_t stage_dendrogram_scratch(int64_t n);
 size_t stage_condense_scratch(int64_t n, int64_t M, int64_t G, bool discrete);
+int krt_max_level_bits(int64_t m);
 
 }  // namespace ce

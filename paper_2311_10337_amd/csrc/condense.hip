@@ -40,8 +40,9 @@ __global__ __launch_bounds__(B) void k_fill64(uint64_t *p, int64_t n, uint64_t v
 }
 __global__ void k_set64(uint64_t *p, uint64_t v) { *p = v; }
 
-__global__ __launch_bounds__(B) void k_cd_parents(const uint32_t *kc_u, const uint32_t *kc_v, int64_t m, int64_t n,
+__global__ __launch_bounds__(B) void k_cd_parents(const uint32_t *kc_u, const uint32_t *kc_v, Cnt mc, int64_t n,
                                                   uint32_t *kpar) {
+  const int64_t m = mc.get();
   for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
     kpar[kc_u[j]] = (uint32_t)(n + j);
     kpar[kc_v[j]] = (uint32_t)(n + j);
@@ -50,15 +51,17 @@ __global__ __launch_bounds__(B) void k_cd_parents(const uint32_t *kc_u, const ui
 
 // big component roots per graph
 __global__ __launch_bounds__(B) void k_cd_bigroots(const uint32_t *kpar, const uint32_t *ksize, const uint32_t *rowg,
-                                                   int64_t m, int64_t n, int64_t M, uint32_t *nbig) {
+                                                   Cnt mc, int64_t n, int64_t M, uint32_t *nbig) {
+  const int64_t m = mc.get();
   for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B)
     if (kpar[n + j] == NONE32 && ksize[j] >= (uint64_t)M) atomicAdd(&nbig[rowg[j]], 1u);
 }
 
 __global__ __launch_bounds__(B) void k_cd_birth(const uint32_t *kc_u, const uint32_t *kc_v, const uint32_t *ksize,
-                                                const uint32_t *kpar, const uint64_t *rowL, bool discrete, int64_t m,
+                                                const uint32_t *kpar, const uint64_t *rowL, bool discrete, Cnt mc,
                                                 int64_t n, int64_t M, const uint32_t *nbig, const uint32_t *rowg,
                                                 uint8_t *isbirth, uint64_t *birthL) {
+  const int64_t m = mc.get();
   for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
     uint32_t a = kc_u[j], b = kc_v[j];
     if (!discrete && node_size(a, n, ksize) >= (uint64_t)M && node_size(b, n, ksize) >= (uint64_t)M) {
@@ -78,8 +81,9 @@ __global__ __launch_bounds__(B) void k_cd_birth(const uint32_t *kc_u, const uint
 // lambda of every row: of its weight, or with thresholds (the discrete
 // dendrogram of Alg. 5) of its level's threshold, level = the first threshold
 // the weight does not exceed
-__global__ __launch_bounds__(B) void k_row_lambda(const uint64_t *msf_key, int wshift, int64_t m, const int64_t *thr,
+__global__ __launch_bounds__(B) void k_row_lambda(const uint64_t *msf_key, int wshift, Cnt mc, const int64_t *thr,
                                                   int q, uint64_t *rowL, uint32_t *level) {
+  const int64_t m = mc.get();
   for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
     const int64_t w = (int64_t)(msf_key[j] >> wshift);
     if (q == 0) {
@@ -96,51 +100,38 @@ __global__ __launch_bounds__(B) void k_row_lambda(const uint64_t *msf_key, int w
 // Discrete dendrogram: a row's level top is its highest ancestor reached
 // through parents of the same level (the component that first appears at that
 // level, a D-node). First step: the parent if it has the same level.
-__global__ __launch_bounds__(B) void k_dd_top_init(const uint32_t *kpar, const uint32_t *level, int64_t m, int64_t n,
+__global__ __launch_bounds__(B) void k_dd_top_init(const uint32_t *kpar, const uint32_t *level, Cnt mc, int64_t n,
                                                    uint32_t *top) {
+  const int64_t m = mc.get();
   for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
     const uint32_t p = kpar[n + j];
     top[j] = (p != NONE32 && level[p - n] == level[j]) ? p : (uint32_t)(n + j);
   }
 }
-// pointer doubling over rows; counts rows that moved
-// rows whose level top is not known yet (their pointer is not a top)
-__global__ __launch_bounds__(B) void k_dd_top_active(const uint32_t *top, int64_t m, int64_t n, uint32_t *act,
-                                                     unsigned long long *nact) {
-  bool keep[CT];
-  uint32_t vals[CT];
-  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
-#pragma unroll
-  for (int k = 0; k < CT; k++) {
-    const int64_t j = base + (int64_t)k * B;
-    keep[k] = false;
-    vals[k] = (uint32_t)j;
-    if (j >= m) continue;
-    const uint32_t t = top[j];
-    keep[k] = t != (uint32_t)(n + j) && top[t - n] != t;
+// Every row to its level top, in place: a walk over same-level parents, each
+// row storing into its own entry only. Pointers only ever move to higher rows
+// of the same level, so whatever another walk reads is still on the way.
+// A walk longer than any tree allows marks the call failed and stops.
+constexpr uint32_t MAX_WALK = 1u << 26;
+// Rows are taken from the last one down, so a row's parents (higher rows) are
+// mostly done when it walks, and each row stores into its own entry only.
+__global__ __launch_bounds__(B) void k_dd_top_chase(Cnt mc, int64_t n, uint32_t *top, uint64_t *hdr) {
+  const int64_t m = mc.get();
+  for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < m; i += (int64_t)gridDim.x * B) {
+    const int64_t j = m - 1 - i;
+    uint32_t x = top[j];
+    if (x == (uint32_t)(n + j)) continue;
+    for (uint32_t steps = 0;; steps++) {
+      const uint32_t t = __hip_atomic_load(&top[x - n], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (t == x) break;
+      if (steps > MAX_WALK) {
+        atomicOr((unsigned long long *)&hdr[H_STATUS], 32ull);
+        break;
+      }
+      __hip_atomic_store(&top[j], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      x = t;
+    }
   }
-  tile_append(keep, vals, act, nact);
-}
-// one pointer-jumping round over the active rows, in place: a row only reads
-// pointers of rows above it, which stay valid ancestors of the same level
-__global__ __launch_bounds__(B) void k_dd_top_jump(const uint32_t *act, int64_t nact, int64_t n, uint32_t *top,
-                                                   uint32_t *next, unsigned long long *nnext) {
-  bool keep[CT];
-  uint32_t vals[CT];
-  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
-#pragma unroll
-  for (int k = 0; k < CT; k++) {
-    const int64_t i = base + (int64_t)k * B;
-    keep[k] = false;
-    vals[k] = 0;
-    if (i >= nact) continue;
-    const uint32_t j = act[i], t = top[j], tt = top[t - n];
-    if (tt == t) continue;  // t is a top
-    top[j] = tt;
-    keep[k] = top[tt - n] != tt;
-    vals[k] = j;
-  }
-  tile_append(keep, vals, next, nnext);
 }
 // big children of every D-node: the level tops (rows that are their own top)
 // hanging below its block; records are never big (M >= 2)
@@ -148,8 +139,9 @@ __global__ __launch_bounds__(B) void k_dd_top_jump(const uint32_t *act, int64_t 
 // counts are combined per wave and per tile (LDS hash) before the atomics
 constexpr int DHS = 512;
 __global__ __launch_bounds__(B) void k_dd_bigcount(const uint32_t *kpar, const uint32_t *ksize, const uint32_t *top,
-                                                   int64_t m, int64_t n, int64_t M, uint32_t *bigcnt) {
+                                                   Cnt mc, int64_t n, int64_t M, uint32_t *bigcnt) {
   __shared__ uint32_t hk[DHS], hc[DHS];
+  const int64_t m = mc.get();
   for (int i = threadIdx.x; i < DHS; i += B) { hk[i] = NONE32; hc[i] = 0; }
   __syncthreads();
   const int64_t tbase = (int64_t)blockIdx.x * (B * CT);
@@ -189,8 +181,9 @@ __global__ __launch_bounds__(B) void k_dd_bigcount(const uint32_t *kpar, const u
 // a big child of a D-node with two or more big children starts a cluster at
 // the D-node's lambda
 __global__ __launch_bounds__(B) void k_dd_birth(const uint32_t *kpar, const uint32_t *ksize, const uint32_t *top,
-                                                const uint32_t *bigcnt, const uint64_t *rowL, int64_t m, int64_t n,
+                                                const uint32_t *bigcnt, const uint64_t *rowL, Cnt mc, int64_t n,
                                                 int64_t M, uint8_t *isbirth, uint64_t *birthL) {
+  const int64_t m = mc.get();
   for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
     const uint32_t p = kpar[n + j];
     if (p == NONE32 || top[j] != (uint32_t)(n + j) || ksize[j] < (uint64_t)M) continue;
@@ -206,58 +199,46 @@ __device__ inline bool j_terminal(uint32_t x, int64_t n, int64_t m, const uint8_
 }
 
 // J[j] for big rows: self if birth, ROOT if a root, else the parent node.
-// Rows whose J is not yet a birth node or ROOT go to the active list.
 __global__ __launch_bounds__(B) void k_cd_jinit(const uint8_t *isbirth, const uint32_t *kpar, const uint32_t *ksize,
-                                                const uint32_t *rowg, int64_t m, int64_t n, int64_t M, uint32_t *J,
-                                                uint32_t *act, unsigned long long *nact) {
-  bool keep[CT];
-  uint32_t vals[CT];
-  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
-#pragma unroll
-  for (int k = 0; k < CT; k++) {
-    const int64_t j = base + (int64_t)k * B;
-    keep[k] = false;
-    vals[k] = (uint32_t)j;
-    if (j >= m) continue;
+                                                const uint32_t *rowg, Cnt mc, int64_t n, int64_t M, uint32_t *J) {
+  const int64_t m = mc.get();
+  for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
     uint32_t v = NONE32;
     if (ksize[j] >= (uint64_t)M) {
       if (isbirth[j]) v = (uint32_t)(n + j);
       else if (kpar[n + j] == NONE32) v = (uint32_t)(n + m + rowg[j]);
-      else {
-        v = kpar[n + j];
-        keep[k] = !j_terminal(v, n, m, isbirth);
-      }
+      else v = kpar[n + j];
     }
     J[j] = v;
   }
-  tile_append(keep, vals, act, nact);
 }
 
-// pointer jumping toward the nearest birth ancestor; finished rows leave the list
-__global__ __launch_bounds__(B) void k_cd_jstep(const uint32_t *act, int64_t nact, uint32_t *J, const uint8_t *isbirth,
-                                                int64_t m, int64_t n, uint32_t *out, unsigned long long *nout) {
-  bool keep[CT];
-  uint32_t vals[CT];
-  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
-#pragma unroll
-  for (int k = 0; k < CT; k++) {
-    const int64_t i = base + (int64_t)k * B;
-    keep[k] = false;
-    vals[k] = 0;
-    if (i >= nact) continue;
-    uint32_t j = act[i];
+// Every big row to its nearest birth ancestor (or its graph's root), in
+// place: a walk over J, each row storing into its own entry only. Ancestors
+// of a big row are big, so every J on the way is set, and J only ever moves
+// up, so whatever another walk reads is still on the way. Rows are taken from
+// the last one down (a parent is a later row), so the ancestors of a row are
+// mostly done when it walks and its walk is short.
+__global__ __launch_bounds__(B) void k_cd_jchase(Cnt mc, int64_t n, const uint8_t *isbirth, uint32_t *J,
+                                                 uint64_t *hdr) {
+  const int64_t m = mc.get();
+  for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < m; i += (int64_t)gridDim.x * B) {
+    const int64_t j = m - 1 - i;
     uint32_t x = J[j];
-    uint32_t y = J[x - n];
-    J[j] = y;
-    if (!j_terminal(y, n, m, isbirth)) {
-      keep[k] = true;
-      vals[k] = j;
+    if (x == NONE32) continue;
+    for (uint32_t steps = 0; !j_terminal(x, n, m, isbirth); steps++) {
+      if (steps > MAX_WALK) {
+        atomicOr((unsigned long long *)&hdr[H_STATUS], 32ull);
+        break;
+      }
+      x = __hip_atomic_load(&J[x - n], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&J[j], x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
-  tile_append(keep, vals, out, nout);
 }
 
-__global__ __launch_bounds__(B) void k_u8_to_u32(const uint8_t *a, int64_t n, uint32_t *o) {
+__global__ __launch_bounds__(B) void k_u8_to_u32(const uint8_t *a, Cnt nc, uint32_t *o) {
+  const int64_t n = nc.get();
   for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < n; i += (int64_t)gridDim.x * B) o[i] = a[i];
 }
 
@@ -268,8 +249,9 @@ __device__ inline uint32_t row_of(uint32_t c, int64_t n, int64_t m, const uint32
 // cluster rows: node, size, birth lambda, parent row
 __global__ __launch_bounds__(B) void k_cd_rows(const uint8_t *isbirth, const uint32_t *rowof, const uint32_t *rootrow,
                                                const uint32_t *ksize, const uint64_t *birthL, const uint32_t *kpar,
-                                               const uint32_t *J, const uint32_t *rowg, int64_t m, int64_t n,
+                                               const uint32_t *J, const uint32_t *rowg, Cnt mc, int64_t n,
                                                uint32_t *cnode, uint32_t *csize, uint64_t *cbirth, uint32_t *cprow) {
+  const int64_t m = mc.get();
   for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
     if (!isbirth[j]) continue;
     uint32_t r = rowof[j];
@@ -283,9 +265,10 @@ __global__ __launch_bounds__(B) void k_cd_rows(const uint8_t *isbirth, const uin
 }
 
 // one root row per graph: size = the graph's records, born at lambda 0, no parent
-__global__ __launch_bounds__(B) void k_cd_rootrows(const uint32_t *rootrow, const int64_t *eoff, int64_t G, int64_t m,
+__global__ __launch_bounds__(B) void k_cd_rootrows(const uint32_t *rootrow, const int64_t *eoff, int64_t G, Cnt mc,
                                                    int64_t n, uint32_t *cnode, uint32_t *csize, uint64_t *cbirth,
                                                    uint32_t *cprow) {
+  const int64_t m = mc.get();
   for (int64_t g = (int64_t)blockIdx.x * B + threadIdx.x; g < G; g += (int64_t)gridDim.x * B) {
     const uint32_t r = rootrow[g];
     cnode[r] = (uint32_t)(n + m + g);
@@ -297,7 +280,8 @@ __global__ __launch_bounds__(B) void k_cd_rootrows(const uint32_t *rootrow, cons
 
 // births in (graph, node) order: position p gives row p + g (each earlier graph adds its root row)
 __global__ __launch_bounds__(B) void k_birth_list(const uint8_t *isbirth, const uint32_t *idx, const uint32_t *rowg,
-                                                  int64_t m, uint32_t *bkey, uint32_t *bval) {
+                                                  Cnt mc, uint32_t *bkey, uint32_t *bval) {
+  const int64_t m = mc.get();
   for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
     if (!isbirth[j]) continue;
     const uint32_t i = idx[j];
@@ -305,11 +289,25 @@ __global__ __launch_bounds__(B) void k_birth_list(const uint8_t *isbirth, const 
     bval[i] = (uint32_t)j;
   }
 }
-__global__ void k_set2_u32(uint32_t *p, uint32_t a, uint32_t b) {
-  if (threadIdx.x == 0) { p[0] = a; p[1] = b; }
+// births and cluster rows from the scan of the birth flags (idx[m] = births);
+// more rows than the bound marks the call failed
+__global__ void k_cluster_counts(const uint32_t *idx, const uint64_t *m, int64_t G, int64_t R, uint64_t *hdr) {
+  if (threadIdx.x != 0) return;
+  uint64_t nb = idx[*m];
+  if ((int64_t)(nb + G) > R) {  // (cannot happen: every birth has at least M records) stay in bounds
+    hdr[H_STATUS] |= 64;
+    nb = 0;
+  }
+  hdr[H_NB] = nb;
+  hdr[H_NROWS] = nb + (uint64_t)G;
 }
-__global__ __launch_bounds__(B) void k_birth_rows(const uint32_t *sorted_j, const uint32_t *rowg, int64_t nb,
+// one graph: its births are rows 0..nb-1
+__global__ void k_bstart_one(uint32_t *bstart, const uint64_t *hdr) {
+  if (threadIdx.x == 0) { bstart[0] = 0; bstart[1] = (uint32_t)hdr[H_NB]; }
+}
+__global__ __launch_bounds__(B) void k_birth_rows(const uint32_t *sorted_j, const uint32_t *rowg, Cnt nbc,
                                                   uint32_t *rowof) {
+  const int64_t nb = nbc.get();
   for (int64_t p = (int64_t)blockIdx.x * B + threadIdx.x; p < nb; p += (int64_t)gridDim.x * B) {
     const uint32_t j = sorted_j[p];
     rowof[j] = (uint32_t)p + rowg[j];
@@ -344,9 +342,10 @@ constexpr int AHS = 512;  // LDS hash slots for per-cluster-row sums
 // row and tile.
 __global__ __launch_bounds__(B) void k_cd_point_terms(const uint32_t *kc_u, const uint32_t *kc_v,
                                                       const uint32_t *ksize, const uint32_t *J, const uint64_t *rowL,
-                                                      const uint32_t *rowof, const uint32_t *rootrow, int64_t m,
+                                                      const uint32_t *rowof, const uint32_t *rootrow, Cnt mc,
                                                       int64_t n, int64_t M, unsigned long long *acc) {
   __shared__ uint32_t hk[AHS];
+  const int64_t m = mc.get();
   __shared__ unsigned long long h0[AHS], h1[AHS], h2[AHS];
   for (int i = threadIdx.x; i < AHS; i += B) { hk[i] = NONE32; h0[i] = 0; h1[i] = 0; h2[i] = 0; }
   __syncthreads();
@@ -404,7 +403,8 @@ __global__ __launch_bounds__(B) void k_cd_point_terms(const uint32_t *kc_u, cons
 // row, (cluster row of its cluster, size) for a big one.
 __global__ __launch_bounds__(B) void k_cd_walk_words(const uint32_t *kpar, const uint32_t *ksize, const uint32_t *J,
                                                      const uint32_t *rowof, const uint32_t *rootrow, int64_t n,
-                                                     int64_t m, int64_t M, uint2 *wk) {
+                                                     Cnt mc, int64_t M, uint2 *wk) {
+  const int64_t m = mc.get();
   for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
     const uint32_t sz = ksize[j];
     wk[j] = make_uint2(sz < (uint64_t)M ? kpar[n + j] : row_of(J[j], n, m, rowof, rootrow), sz);
@@ -418,7 +418,8 @@ __global__ __launch_bounds__(B) void k_cd_walk_words(const uint32_t *kpar, const
 __global__ __launch_bounds__(B) void k_cd_exit_ids(const uint32_t *rankof, const uint32_t *kpar, const uint2 *wk,
                                                    const uint64_t *rowL, const uint32_t *grank,
                                                    const uint32_t *rootrow, int64_t n, int64_t M, uint32_t *prow,
-                                                   uint64_t *pt_lambda) {
+                                                   const uint64_t *hdr, uint64_t *pt_lambda) {
+  if (hdr[H_STATUS] != 0) pt_lambda = nullptr;  // a data error: no output is written
   for (int64_t id = (int64_t)blockIdx.x * B + threadIdx.x; id < n; id += (int64_t)gridDim.x * B) {
     const uint32_t p = rankof[id];
     uint32_t y = kpar[p], r = NONE32;
@@ -439,8 +440,9 @@ __global__ __launch_bounds__(B) void k_cd_exit_ids(const uint32_t *rankof, const
 }
 
 __global__ __launch_bounds__(B) void k_cd_acc_children(const uint32_t *csize, const uint64_t *cbirth,
-                                                       const uint32_t *cprow, uint32_t nrows,
+                                                       const uint32_t *cprow, Cnt nrc,
                                                        unsigned long long *acc) {
+  const int64_t nrows = nrc.get();
   int64_t r = (int64_t)blockIdx.x * B + threadIdx.x;
   bool act = r < (int64_t)nrows && cprow[r] != NONE32;
   uint32_t pr = 0;
@@ -454,7 +456,8 @@ __global__ __launch_bounds__(B) void k_cd_acc_children(const uint32_t *csize, co
 
 // S = sum - size * birth  (exact u128)
 __global__ __launch_bounds__(B) void k_cd_stab(const unsigned long long *acc, const uint32_t *csize,
-                                               const uint64_t *cbirth, uint32_t nrows, uint64_t *shi, uint64_t *slo) {
+                                               const uint64_t *cbirth, Cnt nrc, uint64_t *shi, uint64_t *slo) {
+  const int64_t nrows = nrc.get();
   for (int64_t r = (int64_t)blockIdx.x * B + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * B) {
     u128 t0{acc[3 * r], 0};
     u128 t1 = u128_mul64(acc[3 * r + 1], uint64_t(1) << 32);
@@ -467,7 +470,8 @@ __global__ __launch_bounds__(B) void k_cd_stab(const unsigned long long *acc, co
 }
 
 // root rows are the rows without a parent
-__global__ __launch_bounds__(B) void k_cd_children(const uint32_t *cprow, uint32_t nrows, uint32_t *nch, uint32_t *ch) {
+__global__ __launch_bounds__(B) void k_cd_children(const uint32_t *cprow, Cnt nrc, uint32_t *nch, uint32_t *ch) {
+  const int64_t nrows = nrc.get();
   for (int64_t r = (int64_t)blockIdx.x * B + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * B) {
     uint32_t p = cprow[r];
     if (p == NONE32 || cprow[p] == NONE32) continue;
@@ -483,14 +487,16 @@ __global__ __launch_bounds__(B) void k_cd_children(const uint32_t *cprow, uint32
 // child lists by a sort of the rows by parent (a parent can have millions of
 // children, so no per-parent atomics); rows that are not children of a
 // non-root cluster get the key nrows and sort last
-__global__ __launch_bounds__(B) void k_cd_child_keys(const uint32_t *cprow, uint32_t nrows, uint32_t *key) {
+__global__ __launch_bounds__(B) void k_cd_child_keys(const uint32_t *cprow, Cnt nrc, uint32_t *key) {
+  const int64_t nrows = nrc.get();
   for (int64_t r = (int64_t)blockIdx.x * B + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * B) {
     const uint32_t p = cprow[r];
-    key[r] = (p == NONE32 || cprow[p] == NONE32) ? nrows : p;
+    key[r] = (p == NONE32 || cprow[p] == NONE32) ? (uint32_t)nrows : p;
   }
 }
-__global__ __launch_bounds__(B) void k_cd_child_counts(const uint32_t *choff, uint32_t nrows, uint32_t *nch,
+__global__ __launch_bounds__(B) void k_cd_child_counts(const uint32_t *choff, Cnt nrc, uint32_t *nch,
                                                        uint32_t *vcnt) {
+  const int64_t nrows = nrc.get();
   for (int64_t p = (int64_t)blockIdx.x * B + threadIdx.x; p < nrows; p += (int64_t)gridDim.x * B) {
     const uint32_t k = choff[p + 1] - choff[p];
     nch[p] = k;
@@ -499,20 +505,22 @@ __global__ __launch_bounds__(B) void k_cd_child_counts(const uint32_t *choff, ui
 }
 // p -> (L0, L1), or with k > 2 children p -> (L0, v0) (virtual nodes below)
 __global__ __launch_bounds__(B) void k_cd_pairs(const uint32_t *nch, const uint32_t *choff, const uint32_t *clist,
-                                                const uint32_t *vbase, uint32_t nrows, uint32_t *ch) {
+                                                const uint32_t *vbase, Cnt nrc, uint32_t *ch) {
+  const int64_t nrows = nrc.get();
   for (int64_t p = (int64_t)blockIdx.x * B + threadIdx.x; p < nrows; p += (int64_t)gridDim.x * B) {
     const uint32_t k = nch[p];
     if (k == 0) continue;
     const uint32_t *L = clist + choff[p];
     ch[2 * p] = L[0];
-    ch[2 * p + 1] = k > 2 ? nrows + vbase[p] : (k == 2 ? L[1] : L[0]);
+    ch[2 * p + 1] = k > 2 ? (uint32_t)nrows + vbase[p] : (k == 2 ? L[1] : L[0]);
   }
 }
 // virtual node v (the i-th of parent p): v_i -> (L_{i+1}, v_{i+1}); the last
 // one -> (L_{k-2}, L_{k-1}); its parent is the last p with vbase[p] <= v
 __global__ __launch_bounds__(B) void k_cd_virtual(const uint32_t *nch, const uint32_t *choff, const uint32_t *clist,
-                                                  const uint32_t *vbase, uint32_t nrows, uint32_t nvirt,
+                                                  const uint32_t *vbase, Cnt nrc, Cnt nvc,
                                                   uint32_t *ch, uint32_t *vnch, uint64_t *shi, uint64_t *slo) {
+  const int64_t nrows = nrc.get(), nvirt = nvc.get();
   for (int64_t v = (int64_t)blockIdx.x * B + threadIdx.x; v < nvirt; v += (int64_t)gridDim.x * B) {
     int64_t lo = 0, hi = (int64_t)nrows - 1;
     while (lo < hi) {
@@ -550,8 +558,9 @@ __device__ inline void eom_store(const Eom &o, uint32_t r, uint8_t st, u128 v, u
 }
 
 __global__ __launch_bounds__(B) void k_eom_init(const uint32_t *nch, const uint64_t *shi, const uint64_t *slo,
-                                                const uint32_t *cprow, uint32_t nreal, uint32_t nrows, Eom e0,
+                                                const uint32_t *cprow, Cnt nrc, Cnt nec, Eom e0,
                                                 Eom e1, uint32_t *act, unsigned long long *nact) {
+  const int64_t nreal = nrc.get(), nrows = nec.get();
   bool keep[CT];
   uint32_t vals[CT];
   const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
@@ -573,65 +582,108 @@ __global__ __launch_bounds__(B) void k_eom_init(const uint32_t *nch, const uint6
 
 // One round over the pending rows: rake (both children done), turn into a
 // unary f(x) = max(a, x + b) when one child is done, or compose along a chain
-// of unary rows (pointer jumping). Reads `in`, writes `out`.
-__global__ __launch_bounds__(B) void k_eom_round(const uint32_t *act, int64_t nact, Eom in, Eom out,
+// of unary rows (pointer jumping). Reads `in`, writes `out`. A row that
+// finishes goes once more to the next list, flagged COPY, so that both state
+// buffers hold its final value; when the list is empty they agree everywhere.
+__device__ inline bool eom_step(uint32_t item, const Eom &in, const Eom &out, const uint32_t *ch,
+                                const uint64_t *shi, const uint64_t *slo, uint32_t *val) {
+  const uint32_t r = item & ~COPY;
+  uint8_t st = in.st[r];
+  u128 v{in.vlo[r], in.vhi[r]}, a{in.alo[r], in.ahi[r]}, bb{in.blo[r], in.bhi[r]};
+  uint32_t dep = in.dep[r];
+  if (item & COPY) {
+    eom_store(out, r, st, v, a, bb, dep);
+    return false;
+  }
+  if (st == 0) {
+    uint32_t c1 = ch[2 * (uint64_t)r], c2 = ch[2 * (uint64_t)r + 1];
+    bool d1 = in.st[c1] == 2, d2 = in.st[c2] == 2;
+    u128 S{slo[r], shi[r]};
+    if (d1 && d2) {
+      v = u128_max(S, u128_add(u128{in.vlo[c1], in.vhi[c1]}, u128{in.vlo[c2], in.vhi[c2]}));
+      st = 2;
+    } else if (d1 || d2) {
+      uint32_t dn = d1 ? c1 : c2, pn = d1 ? c2 : c1;
+      a = S;
+      bb = u128{in.vlo[dn], in.vhi[dn]};
+      dep = pn;
+      st = 1;
+    }
+  } else if (st == 1) {
+    uint8_t ds = in.st[dep];
+    if (ds == 2) {
+      v = u128_max(a, u128_add(u128{in.vlo[dep], in.vhi[dep]}, bb));
+      st = 2;
+    } else if (ds == 1) {
+      u128 ad{in.alo[dep], in.ahi[dep]}, bd{in.blo[dep], in.bhi[dep]};
+      a = u128_max(a, u128_add(ad, bb));
+      bb = u128_add(bd, bb);
+      dep = in.dep[dep];
+    }
+  }
+  eom_store(out, r, st, v, a, bb, dep);
+  *val = st == 2 ? (r | COPY) : r;
+  return true;
+}
+
+__global__ __launch_bounds__(B) void k_eom_round(const uint32_t *act, const uint64_t *nact_in, Eom in, Eom out,
                                                  const uint32_t *ch, const uint64_t *shi, const uint64_t *slo,
                                                  uint32_t *next, unsigned long long *nnext) {
-  bool keep[CT];
-  uint32_t vals[CT];
-  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
+  const int64_t nact = (int64_t)*nact_in;
+  for (int64_t tile = blockIdx.x; tile * (B * CT) < nact; tile += gridDim.x) {
+    bool keep[CT];
+    uint32_t vals[CT];
+    const int64_t base = tile * (B * CT) + threadIdx.x;
 #pragma unroll
-  for (int k = 0; k < CT; k++) {
-    const int64_t i = base + (int64_t)k * B;
-    keep[k] = false;
-    vals[k] = 0;
-    if (i >= nact) continue;
-    const uint32_t item = act[i], r = item & ~COPY;
-    uint8_t st = in.st[r];
-    u128 v{in.vlo[r], in.vhi[r]}, a{in.alo[r], in.ahi[r]}, bb{in.blo[r], in.bhi[r]};
-    uint32_t dep = in.dep[r];
-    if (item & COPY) {
-      eom_store(out, r, st, v, a, bb, dep);
-      continue;
+    for (int k = 0; k < CT; k++) {
+      const int64_t i = base + (int64_t)k * B;
+      keep[k] = false;
+      vals[k] = 0;
+      if (i < nact) keep[k] = eom_step(act[i], in, out, ch, shi, slo, &vals[k]);
     }
-    if (st == 0) {
-      uint32_t c1 = ch[2 * (uint64_t)r], c2 = ch[2 * (uint64_t)r + 1];
-      bool d1 = in.st[c1] == 2, d2 = in.st[c2] == 2;
-      u128 S{slo[r], shi[r]};
-      if (d1 && d2) {
-        v = u128_max(S, u128_add(u128{in.vlo[c1], in.vhi[c1]}, u128{in.vlo[c2], in.vhi[c2]}));
-        st = 2;
-      } else if (d1 || d2) {
-        uint32_t dn = d1 ? c1 : c2, pn = d1 ? c2 : c1;
-        a = S;
-        bb = u128{in.vlo[dn], in.vhi[dn]};
-        dep = pn;
-        st = 1;
-      }
-    } else if (st == 1) {
-      uint8_t ds = in.st[dep];
-      if (ds == 2) {
-        v = u128_max(a, u128_add(u128{in.vlo[dep], in.vhi[dep]}, bb));
-        st = 2;
-      } else if (ds == 1) {
-        u128 ad{in.alo[dep], in.ahi[dep]}, bd{in.blo[dep], in.bhi[dep]};
-        a = u128_max(a, u128_add(ad, bb));
-        bb = u128_add(bd, bb);
-        dep = in.dep[dep];
-      }
-    }
-    eom_store(out, r, st, v, a, bb, dep);
-    keep[k] = true;
-    vals[k] = st == 2 ? (r | COPY) : r;
+    tile_append(keep, vals, next, nnext);
   }
-  tile_append(keep, vals, next, nnext);
+}
+
+// The rounds left after the enqueued ones, in one workgroup: lists and state
+// buffers alternate as in the grid rounds (the state of round `parity` is
+// read first); it stops when the list is empty. A round count beyond any
+// tree marks the call failed.
+constexpr int TB = 1024;
+__global__ __launch_bounds__(TB) void k_eom_tail(uint32_t *l0, uint32_t *l1, const uint64_t *nact_in, int parity,
+                                                 Eom e0, Eom e1, const uint32_t *ch, const uint64_t *shi,
+                                                 const uint64_t *slo, uint64_t *hdr) {
+  __shared__ uint32_t s_cnt;
+  int64_t nact = (int64_t)*nact_in;
+  int cur = parity;
+  for (uint32_t round = 0; nact > 0; round++) {
+    if (round > (1u << 20)) {
+      if (threadIdx.x == 0) atomicOr((unsigned long long *)&hdr[H_STATUS], 32ull);
+      return;
+    }
+    const uint32_t *in_list = cur ? l1 : l0;
+    uint32_t *out_list = cur ? l0 : l1;
+    const Eom &in = cur ? e1 : e0, &out = cur ? e0 : e1;
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < nact; i += TB) {
+      uint32_t v;
+      if (eom_step(in_list[i], in, out, ch, shi, slo, &v)) out_list[atomicAdd(&s_cnt, 1u)] = v;
+    }
+    __threadfence_block();
+    __syncthreads();
+    nact = s_cnt;
+    cur ^= 1;
+    __syncthreads();
+  }
 }
 
 // selection with ties kept by the parent; ROOT never selected
 __global__ __launch_bounds__(B) void k_eom_select(const uint32_t *nch, const uint32_t *ch, Eom e, const uint64_t *shi,
-                                                  const uint64_t *slo, uint32_t nrows, uint32_t *top, uint32_t *nxt,
+                                                  const uint64_t *slo, Cnt nrc, uint32_t *top, uint32_t *nxt,
                                                   uint32_t *top2, uint32_t *nxt2, const uint32_t *cprow, uint32_t *act,
                                                   unsigned long long *nact) {
+  const int64_t nrows = nrc.get();
   bool keep[CT];
   uint32_t vals[CT];
   const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
@@ -660,34 +712,72 @@ __global__ __launch_bounds__(B) void k_eom_select(const uint32_t *nch, const uin
 }
 
 // top[r] = highest selected row among r and its ancestors below ROOT
-__global__ __launch_bounds__(B) void k_top_jump(const uint32_t *act, int64_t nact, const uint32_t *tin,
-                                                const uint32_t *nin, uint32_t *tout, uint32_t *nout, uint32_t *next,
-                                                unsigned long long *nnext) {
-  bool keep[CT];
-  uint32_t vals[CT];
-  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
-#pragma unroll
-  for (int k = 0; k < CT; k++) {
-    const int64_t i = base + (int64_t)k * B;
-    keep[k] = false;
-    vals[k] = 0;
-    if (i >= nact) continue;
-    const uint32_t item = act[i], r = item & ~COPY;
-    uint32_t nx = nin[r], t = tin[r];
-    if (item & COPY) {
-      tout[r] = t;
-      nout[r] = nx;
-      continue;
-    }
-    uint32_t tv = tin[nx];
-    if (tv != NONE32) t = tv;
-    nx = nin[nx];
+// (pointer doubling over (top, nxt); a row that finishes goes once more to the
+// next list, flagged COPY, so both buffers agree when the list is empty)
+__device__ inline bool top_step(uint32_t item, const uint32_t *tin, const uint32_t *nin, uint32_t *tout,
+                                uint32_t *nout, uint32_t *val) {
+  const uint32_t r = item & ~COPY;
+  uint32_t nx = nin[r], t = tin[r];
+  if (item & COPY) {
     tout[r] = t;
     nout[r] = nx;
-    keep[k] = true;
-    vals[k] = nx == NONE32 ? (r | COPY) : r;
+    return false;
   }
-  tile_append(keep, vals, next, nnext);
+  uint32_t tv = tin[nx];
+  if (tv != NONE32) t = tv;
+  nx = nin[nx];
+  tout[r] = t;
+  nout[r] = nx;
+  *val = nx == NONE32 ? (r | COPY) : r;
+  return true;
+}
+
+__global__ __launch_bounds__(B) void k_top_jump(const uint32_t *act, const uint64_t *nact_in, const uint32_t *tin,
+                                                const uint32_t *nin, uint32_t *tout, uint32_t *nout, uint32_t *next,
+                                                unsigned long long *nnext) {
+  const int64_t nact = (int64_t)*nact_in;
+  for (int64_t tile = blockIdx.x; tile * (B * CT) < nact; tile += gridDim.x) {
+    bool keep[CT];
+    uint32_t vals[CT];
+    const int64_t base = tile * (B * CT) + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < CT; k++) {
+      const int64_t i = base + (int64_t)k * B;
+      keep[k] = false;
+      vals[k] = 0;
+      if (i < nact) keep[k] = top_step(act[i], tin, nin, tout, nout, &vals[k]);
+    }
+    tile_append(keep, vals, next, nnext);
+  }
+}
+
+__global__ __launch_bounds__(TB) void k_top_tail(uint32_t *l0, uint32_t *l1, const uint64_t *nact_in, int parity,
+                                                 uint32_t *top, uint32_t *nxt, uint32_t *top2, uint32_t *nxt2,
+                                                 uint64_t *hdr) {
+  __shared__ uint32_t s_cnt;
+  int64_t nact = (int64_t)*nact_in;
+  int cur = parity;
+  for (uint32_t round = 0; nact > 0; round++) {
+    if (round > (1u << 20)) {
+      if (threadIdx.x == 0) atomicOr((unsigned long long *)&hdr[H_STATUS], 32ull);
+      return;
+    }
+    const uint32_t *in_list = cur ? l1 : l0;
+    uint32_t *out_list = cur ? l0 : l1;
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
+    for (int64_t i = threadIdx.x; i < nact; i += TB) {
+      uint32_t v;
+      const bool keep = cur ? top_step(in_list[i], top2, nxt2, top, nxt, &v)
+                            : top_step(in_list[i], top, nxt, top2, nxt2, &v);
+      if (keep) out_list[atomicAdd(&s_cnt, 1u)] = v;
+    }
+    __threadfence_block();
+    __syncthreads();
+    nact = s_cnt;
+    cur ^= 1;
+    __syncthreads();
+  }
 }
 
 // the smallest input id under each label (records in input order)
@@ -700,8 +790,9 @@ __global__ __launch_bounds__(B) void k_lab_rows(const uint32_t *prow, const uint
   }
 }
 
-__global__ __launch_bounds__(B) void k_lab_flags(const uint32_t *top, const uint32_t *minmem, uint32_t nrows,
+__global__ __launch_bounds__(B) void k_lab_flags(const uint32_t *top, const uint32_t *minmem, Cnt nrc,
                                                  uint32_t *flag) {
+  const int64_t nrows = nrc.get();
   for (int64_t r = (int64_t)blockIdx.x * B + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * B)
     if (top[r] == (uint32_t)r && minmem[r] != NONE32) flag[minmem[r]] = 1;
 }
@@ -717,7 +808,9 @@ __device__ inline uint32_t local_node(uint32_t x, uint32_t g, int64_t n, int64_t
 
 // per record, in input order: its exit row's node and label
 __global__ __launch_bounds__(B) void k_out_points(const uint32_t *prow, const uint32_t *rlocal, const int32_t *rlab,
-                                                  int64_t n, uint32_t *pt_cluster, int32_t *labels) {
+                                                  int64_t n, const uint64_t *hdr, uint32_t *pt_cluster,
+                                                  int32_t *labels) {
+  if (hdr[H_STATUS] != 0) return;  // a data error: no output is written
   for (int64_t id = (int64_t)blockIdx.x * B + threadIdx.x; id < n; id += (int64_t)gridDim.x * B) {
     const uint32_t r = prow[id];
     if (pt_cluster) pt_cluster[id] = rlocal[r];
@@ -729,8 +822,10 @@ __global__ __launch_bounds__(B) void k_out_clusters(const uint32_t *cnode, const
                                                     const uint32_t *csize, const uint64_t *cbirth,
                                                     const uint64_t *shi, const uint64_t *slo, const uint32_t *top,
                                                     const uint32_t *rowg, const int64_t *eoff, const uint32_t *moff,
-                                                    const uint32_t *rowpos, int64_t n, int64_t m, uint32_t nrows,
-                                                    ce_result out) {
+                                                    const uint32_t *rowpos, int64_t n, Cnt mc, Cnt nrc,
+                                                    const uint64_t *hdr, ce_result out) {
+  if (hdr[H_STATUS] != 0) return;
+  const int64_t m = mc.get(), nrows = nrc.get();
   for (int64_t r = (int64_t)blockIdx.x * B + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * B) {
     const uint32_t c = cnode[r];
     const uint32_t g = c >= (uint64_t)(n + m) ? (uint32_t)(c - n - m) : rowg[c - n];
@@ -748,7 +843,8 @@ __global__ __launch_bounds__(B) void k_out_clusters(const uint32_t *cnode, const
 // discrete dendrogram per output row: level, and the row's D-node as a node id
 __global__ __launch_bounds__(B) void k_out_discrete(const uint32_t *level, const uint32_t *top, const uint32_t *rowg,
                                                     const int64_t *eoff, const uint32_t *moff, const uint32_t *rowpos,
-                                                    int64_t n, int64_t m, uint32_t *dd_level, uint32_t *dd_top) {
+                                                    int64_t n, Cnt mc, uint32_t *dd_level, uint32_t *dd_top) {
+  const int64_t m = mc.get();
   for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
     const uint32_t g = rowg[j], p = rowpos[j];
     if (dd_level) dd_level[p] = level[j];
@@ -763,8 +859,9 @@ __global__ __launch_bounds__(B) void k_row_point_vals(const uint32_t *cnode, con
                                                       const uint32_t *top, const uint32_t *minmem,
                                                       const uint32_t *fscan, const uint32_t *rowg,
                                                       const int64_t *eoff, const uint32_t *moff,
-                                                      const uint32_t *rowpos, int64_t n, int64_t m, uint32_t nrows,
+                                                      const uint32_t *rowpos, int64_t n, Cnt mc, Cnt nrc,
                                                       uint32_t *rlocal, int32_t *rlab) {
+  const int64_t m = mc.get(), nrows = nrc.get();
   for (int64_t r = (int64_t)blockIdx.x * B + threadIdx.x; r < nrows; r += (int64_t)gridDim.x * B) {
     const uint32_t c = cnode[r];
     const uint32_t g = c >= (uint64_t)(n + m) ? (uint32_t)(c - n - m) : rowg[c - n];
@@ -781,36 +878,59 @@ __global__ __launch_bounds__(B) void k_graph_labels(const uint32_t *fscan, const
     nl[g] = fscan[eoff[g + 1]] - fscan[eoff[g]];
 }
 
+// per-graph counts and offsets of the call (its header): total and per-graph
+// rows, cluster rows and labels, row and cluster offsets; the status from the
+// error bits. Cluster rows of graph g start at bstart[g] + g (births, then its root).
+__global__ __launch_bounds__(B) void k_header(const uint64_t *hdr, int64_t G, const uint32_t *moff,
+                                              const uint32_t *bstart, const uint32_t *nlab, int64_t *out) {
+  for (int64_t g = (int64_t)blockIdx.x * B + threadIdx.x; g <= G; g += (int64_t)gridDim.x * B) {
+    if (g == 0) {
+      uint64_t labels = 0;
+      for (int64_t k = 0; k < G; k++) labels += nlab[k];
+      out[0] = status_of(hdr[H_STATUS]);
+      out[1] = moff[G];
+      out[2] = (int64_t)bstart[G] + G;
+      out[3] = (int64_t)labels;
+    }
+    if (g < G) {
+      out[4 + 3 * g] = (int64_t)moff[g + 1] - moff[g];
+      out[4 + 3 * g + 1] = (int64_t)bstart[g + 1] - bstart[g] + 1;
+      out[4 + 3 * g + 2] = nlab[g];
+    }
+    out[4 + 3 * G + g] = moff[g];
+    out[4 + 3 * G + (G + 1) + g] = (int64_t)bstart[g] + g;
+  }
+}
+
+// virtual sum nodes of the discrete condensing (vbase[nrows]) and the EOM rows
+__global__ void k_virtual_counts(const uint32_t *vbase, uint64_t *hdr, int64_t RE) {
+  if (threadIdx.x != 0) return;
+  const uint64_t nrows = hdr[H_NROWS];
+  uint64_t nv = vbase[nrows];
+  if ((int64_t)(nrows + nv) > RE) {  // (cannot happen: at most one virtual node per row) stay in bounds
+    hdr[H_STATUS] |= 64;
+    nv = 0;
+  }
+  hdr[H_NVIRT] = nv;
+  hdr[H_NEOM] = nrows + nv;
+}
+__global__ void k_eom_count(uint64_t *hdr) {
+  if (threadIdx.x == 0) hdr[H_NEOM] = hdr[H_NROWS];
+}
+
 }  // namespace
 
-// level tops by pointer doubling, big children per D-node, births
-// act and act2 hold m + 1 entries each (active lists of the level-top jumping)
-static ce_status discrete_births(Bufs &b, int64_t m, const uint32_t *kpar, const uint32_t *level,
-                                 const uint64_t *rowL, uint32_t *top, uint32_t *act, uint32_t *act2,
-                                 uint32_t *bigcnt, uint8_t *isbirth, uint64_t *birthL, hipStream_t s) {
+// level tops and big children per D-node, then births
+static ce_status discrete_births(Bufs &b, Cnt m, const uint32_t *kpar, const uint32_t *level, const uint64_t *rowL,
+                                 uint32_t *top, uint32_t *bigcnt, uint8_t *isbirth, uint64_t *birthL,
+                                 hipStream_t s) {
   const int64_t n = b.n, M = b.M;
-  const unsigned g = grid_for(m, B);
+  const unsigned g = grid_cap(m.v, B);
   auto tiles = [](int64_t k) { return (unsigned)((k + (int64_t)B * CT - 1) / ((int64_t)B * CT)); };
-  unsigned long long *ctr = (unsigned long long *)&b.hdr[9];
   CE_LAUNCH(k_dd_top_init, dim3(g), dim3(B), 0, s, kpar, level, m, n, top);
-  CE_LAUNCH(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[9], (uint64_t)0);
-  CE_LAUNCH(k_dd_top_active, dim3(tiles(m)), dim3(B), 0, s, top, m, n, act, ctr);
-  CE_HIP(hipGetLastError());
-  uint64_t nact = 0;
-  CE_TRY(read_u64(&b.hdr[9], &nact, 1, s));
-  for (int it = 0; nact > 0; it++) {
-    if (it > 40) {
-      set_error("level-top pointer jumping did not converge");
-      return CE_EDEVICE;
-    }
-    CE_LAUNCH(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[9], (uint64_t)0);
-    CE_LAUNCH(k_dd_top_jump, dim3(tiles((int64_t)nact)), dim3(B), 0, s, act, (int64_t)nact, n, top, act2, ctr);
-    CE_HIP(hipGetLastError());
-    uint32_t *t = act; act = act2; act2 = t;
-    CE_TRY(read_u64(&b.hdr[9], &nact, 1, s));
-  }
-  CE_LAUNCH(k_fill32, dim3(g), dim3(B), 0, s, bigcnt, m, 0u);
-  CE_LAUNCH(k_dd_bigcount, dim3(g), dim3(B), 0, s, kpar, b.ksize, top, m, n, M, bigcnt);
+  CE_LAUNCH(k_dd_top_chase, dim3(g), dim3(B), 0, s, m, n, top, b.hdr);
+  CE_LAUNCH(k_fill32, dim3(g), dim3(B), 0, s, bigcnt, m.v, 0u);
+  CE_LAUNCH(k_dd_bigcount, dim3(tiles(m.v)), dim3(B), 0, s, kpar, b.ksize, top, m, n, M, bigcnt);
   CE_LAUNCH(k_dd_birth, dim3(g), dim3(B), 0, s, kpar, b.ksize, top, bigcnt, rowL, m, n, M, isbirth, birthL);
   CE_HIP(hipGetLastError());
   return CE_OK;
@@ -822,7 +942,7 @@ size_t stage_condense_scratch(int64_t n, int64_t M, int64_t G, bool discrete) {
   const int64_t m = n, R = cluster_row_bound(n, M < 2 ? 2 : M, G), RE = discrete ? 2 * R : R;
   Ws w;
   w.alloc<uint32_t>(n + m + 1);  // kpar
-  w.alloc<uint32_t>(m + 1); w.alloc<uint32_t>(m + 1); w.alloc<uint32_t>(m + 1);  // J, active lists
+  w.alloc<uint32_t>(m + 1);      // J
   w.alloc<uint8_t>(m + 4);       // isbirth
   w.alloc<uint64_t>(m + 1);      // birthL
   w.alloc<uint64_t>(m + 1);      // rowL (the discrete arrays reuse exc, exl, labrow and fl)
@@ -851,18 +971,29 @@ size_t stage_condense_scratch(int64_t n, int64_t M, int64_t G, bool discrete) {
          radix_ws_bytes(R) + 8192;
 }
 
-ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipStream_t s, ce_counts *counts,
-                         int64_t *cluster_offsets) {
-  const int64_t n = b.n, M = b.M, G = b.G;
+// Grid rounds of the excess-of-mass and label pointer-jumping loops that the
+// host enqueues for R cluster rows; what is left after them runs in one
+// workgroup. Pointer doubling over a tree of R rows ends within bits(R) + 1
+// rounds; the excess-of-mass rounds also rake, and measured runs end within
+// about bits(R) + 2.
+static int eom_rounds(int64_t R) { return bits_for((uint64_t)R) + 4; }
+static int top_rounds(int64_t R) { return bits_for((uint64_t)R) + 2; }
+constexpr int MAX_LOOP_ROUNDS = 90;
+
+// Sizes: m rows (device word, bound n - 1), nb births and nrows = nb + G
+// cluster rows, nvirt virtual nodes (device words, bounds from R).
+ce_status stage_condense(Bufs &b, const ce_result *out, Ws &ws, hipStream_t s, int64_t *hout) {
+  const int64_t n = b.n, M = b.M, G = b.G, mb = n > 1 ? n - 1 : 1;
+  const Cnt m(&b.hdr[H_M], mb);
   size_t m0 = ws.mark();
   const int64_t R = cluster_row_bound(n, M, G), RE = b.q > 0 ? 2 * R : R;
-  uint32_t *kpar = ws.alloc<uint32_t>(n + m + 1);
-  uint32_t *J = ws.alloc<uint32_t>(m + 1);
-  uint32_t *jact = ws.alloc<uint32_t>(m + 1), *jact2 = ws.alloc<uint32_t>(m + 1);
-  uint8_t *isbirth = ws.alloc<uint8_t>(m + 4);
-  uint64_t *birthL = ws.alloc<uint64_t>(m + 1);
-  uint64_t *rowL = ws.alloc<uint64_t>(m + 1);
-  uint32_t *flags32 = ws.alloc<uint32_t>(m + 2), *idx = ws.alloc<uint32_t>(m + 2), *rowof = ws.alloc<uint32_t>(m + 1);
+  const Cnt nb(&b.hdr[H_NB], R), nrows(&b.hdr[H_NROWS], R), nvirt(&b.hdr[H_NVIRT], R), neom(&b.hdr[H_NEOM], RE);
+  uint32_t *kpar = ws.alloc<uint32_t>(n + mb + 1);
+  uint32_t *J = ws.alloc<uint32_t>(mb + 1);
+  uint8_t *isbirth = ws.alloc<uint8_t>(mb + 4);
+  uint64_t *birthL = ws.alloc<uint64_t>(mb + 1);
+  uint64_t *rowL = ws.alloc<uint64_t>(mb + 1);
+  uint32_t *flags32 = ws.alloc<uint32_t>(mb + 2), *idx = ws.alloc<uint32_t>(mb + 2), *rowof = ws.alloc<uint32_t>(mb + 1);
   uint32_t *nbig = ws.alloc<uint32_t>(G + 2), *bstart = ws.alloc<uint32_t>(G + 2);
   uint32_t *rootrow = ws.alloc<uint32_t>(G + 2);
   uint32_t *nlab = ws.alloc<uint32_t>(G + 1);
@@ -904,200 +1035,135 @@ ce_status stage_condense(Bufs &b, int64_t m, const ce_result *out, Ws &ws, hipSt
   // discrete dendrogram: level, level tops and big-child counts per row live only until the
   // births are known and the per-row discrete outputs written, before exits, labels and flags use these
   uint32_t *level = exc, *dtop = labrow, *bigcnt = (uint32_t *)exl;
-  unsigned long long *ctr = (unsigned long long *)&b.hdr[8];
   auto tiles = [](int64_t k) { return (unsigned)((k + (int64_t)B * CT - 1) / ((int64_t)B * CT)); };
+  uint64_t *loop = b.hdr + H_LOOP;  // counters of the bounded loops, zero from the start of the call
 
-  const unsigned gN = grid_for(n + m + 1, B), gm = grid_for(m + 1, B), gG = grid_for(G + 1, B);
-  CE_LAUNCH(k_fill32, dim3(gN), dim3(B), 0, s, kpar, n + m + 1, NONE32);
+  const unsigned gN = grid_cap(n + mb + 1, B), gm = grid_cap(mb + 1, B), gG = grid_for(G + 1, B),
+                 gR = grid_cap(R, B), gRE = grid_cap(RE, B);
+  CE_LAUNCH(k_fill32, dim3(gN), dim3(B), 0, s, kpar, n + mb + 1, NONE32);
   CE_LAUNCH(k_fill32, dim3(gG), dim3(B), 0, s, nbig, G + 1, 0u);
-  if (m > 0) {
-    CE_LAUNCH(k_cd_parents, dim3(grid_for(m, B)), dim3(B), 0, s, b.kc_u, b.kc_v, m, n, kpar);
-    CE_LAUNCH(k_cd_bigroots, dim3(grid_for(m, B)), dim3(B), 0, s, kpar, b.ksize, b.rowg, m, n, M, nbig);
-  }
-  CE_LAUNCH(k_fill32, dim3(grid_for((m + 4) / 4, B)), dim3(B), 0, s, (uint32_t *)isbirth, (m + 4) / 4, 0u);
+  CE_LAUNCH(k_cd_parents, dim3(gm), dim3(B), 0, s, b.kc_u, b.kc_v, m, n, kpar);
+  CE_LAUNCH(k_cd_bigroots, dim3(gm), dim3(B), 0, s, kpar, b.ksize, b.rowg, m, n, M, nbig);
+  CE_LAUNCH(k_fill32, dim3(grid_cap((mb + 4) / 4, B)), dim3(B), 0, s, (uint32_t *)isbirth, (mb + 4) / 4, 0u);
   CE_HIP(hipGetLastError());
-  if (m > 0) {
-    CE_LAUNCH(k_row_lambda, dim3(grid_for(m, B)), dim3(B), 0, s, b.msf_key, b.wshift, m, b.thr, b.q, rowL, level);
-    CE_LAUNCH(k_cd_birth, dim3(grid_for(m, B)), dim3(B), 0, s, b.kc_u, b.kc_v, b.ksize, kpar, rowL, b.q > 0, m, n,
-              M, nbig, b.rowg, isbirth, birthL);
+  CE_LAUNCH(k_row_lambda, dim3(gm), dim3(B), 0, s, b.msf_key, b.wshift, m, b.thr, b.q, rowL, level);
+  CE_LAUNCH(k_cd_birth, dim3(gm), dim3(B), 0, s, b.kc_u, b.kc_v, b.ksize, kpar, rowL, b.q > 0, m, n, M, nbig, b.rowg,
+            isbirth, birthL);
+  CE_HIP(hipGetLastError());
+  if (b.q > 0) {
+    CE_TRY(discrete_births(b, m, kpar, level, rowL, dtop, bigcnt, isbirth, birthL, s));
+    if (out->dd_level || out->dd_top)
+      CE_LAUNCH(k_out_discrete, dim3(gm), dim3(B), 0, s, level, dtop, b.rowg, b.eoff, b.moff, b.rowpos, n, m,
+                out->dd_level, out->dd_top);
     CE_HIP(hipGetLastError());
-    if (b.q > 0) {
-      CE_TRY(discrete_births(b, m, kpar, level, rowL, dtop, jact, jact2, bigcnt, isbirth, birthL, s));
-      if (out->dd_level || out->dd_top)
-        CE_LAUNCH(k_out_discrete, dim3(grid_for(m, B)), dim3(B), 0, s, level, dtop, b.rowg, b.eoff, b.moff, b.rowpos,
-                  n, m, out->dd_level, out->dd_top);
-      CE_HIP(hipGetLastError());
-    }
-    CE_LAUNCH(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[9], (uint64_t)0);
-    CE_LAUNCH(k_cd_jinit, dim3(tiles(m)), dim3(B), 0, s, isbirth, kpar, b.ksize, b.rowg, m, n, M, J, jact,
-              (unsigned long long *)&b.hdr[9]);
-    CE_HIP(hipGetLastError());
-    uint64_t nact = 0;
-    CE_TRY(read_u64(&b.hdr[9], &nact, 1, s));
-    for (int it = 0; nact > 0; it++) {
-      if (it > 40) {
-        set_error("cluster pointer jumping did not converge");
-        return CE_EDEVICE;
-      }
-      CE_LAUNCH(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[9], (uint64_t)0);
-      CE_LAUNCH(k_cd_jstep, dim3(tiles((int64_t)nact)), dim3(B), 0, s, jact, (int64_t)nact, J, isbirth, m, n, jact2,
-                (unsigned long long *)&b.hdr[9]);
-      CE_HIP(hipGetLastError());
-      uint32_t *tmp = jact; jact = jact2; jact2 = tmp;
-      CE_TRY(read_u64(&b.hdr[9], &nact, 1, s));
-    }
   }
+  CE_LAUNCH(k_cd_jinit, dim3(gm), dim3(B), 0, s, isbirth, kpar, b.ksize, b.rowg, m, n, M, J);
+  CE_LAUNCH(k_cd_jchase, dim3(gm), dim3(B), 0, s, m, n, isbirth, J, b.hdr);
   // cluster rows: births in (graph, node) order, each graph followed by its root row
   CE_LAUNCH(k_u8_to_u32, dim3(gm), dim3(B), 0, s, isbirth, m, flags32);
   CE_HIP(hipGetLastError());
   CE_TRY(scan_exclusive_u32(flags32, idx, m, ws, s));
-  uint32_t nb = 0;
-  {
-    uint32_t *h = (uint32_t *)pinned_scratch();
-    CE_HIP(hipMemcpyAsync(h + 32, idx + m, 4, hipMemcpyDeviceToHost, s));
-    CE_HIP(hipStreamSynchronize(s));
-    nb = h[32];
-  }
-  const uint32_t nrows = nb + (uint32_t)G;
-  if ((int64_t)nrows > R) {
-    set_error("cluster rows exceed 2*floor(n_g/M)+1 per graph");
-    return CE_EDEVICE;
-  }
+  CE_LAUNCH(k_cluster_counts, dim3(1), dim3(64), 0, s, idx, &b.hdr[H_M], G, R, b.hdr);
   const uint32_t *rowmap = idx;  // one graph: a birth's row is its index among births
   if (G == 1) {
-    CE_LAUNCH(k_set2_u32, dim3(1), dim3(64), 0, s, bstart, 0u, nb);
+    CE_LAUNCH(k_bstart_one, dim3(1), dim3(64), 0, s, bstart, b.hdr);
   } else {
-    const uint32_t *sorted = bkey;
-    if (nb > 0) {
-      CE_LAUNCH(k_birth_list, dim3(gm), dim3(B), 0, s, isbirth, idx, b.rowg, m, bkey, bval);
-      CE_HIP(hipGetLastError());
-      bool alt = false;
-      CE_TRY((radix_sort_pairs<uint32_t, uint32_t>(bkey, bval, bkey2, bval2, nb, 0, bits_for((uint64_t)(G - 1)),
-                                                   false, &alt, ws, s)));
-      CE_LAUNCH(k_birth_rows, dim3(grid_for(nb, B)), dim3(B), 0, s, alt ? bval2 : bval, b.rowg, (int64_t)nb, rowof);
-      sorted = alt ? bkey2 : bkey;
-      rowmap = rowof;
-    }
-    CE_TRY(segment_bounds_u32(sorted, nb, G, bstart, s));
+    CE_LAUNCH(k_birth_list, dim3(gm), dim3(B), 0, s, isbirth, idx, b.rowg, m, bkey, bval);
+    CE_HIP(hipGetLastError());
+    bool alt = false;
+    CE_TRY((radix_sort_pairs<uint32_t, uint32_t>(bkey, bval, bkey2, bval2, nb, 0, bits_for((uint64_t)(G - 1)), false,
+                                                 &alt, ws, s)));
+    CE_LAUNCH(k_birth_rows, dim3(gR), dim3(B), 0, s, alt ? bval2 : bval, b.rowg, nb, rowof);
+    CE_TRY(segment_bounds_u32(alt ? bkey2 : bkey, nb, Cnt(G), bstart, s));
+    rowmap = rowof;
   }
   CE_HIP(hipGetLastError());
   CE_LAUNCH(k_root_rows, dim3(gG), dim3(B), 0, s, bstart, G, rootrow);
-  const unsigned gR = grid_for(nrows, B);
   CE_LAUNCH(k_cd_rows, dim3(gm), dim3(B), 0, s, isbirth, rowmap, rootrow, b.ksize, birthL, kpar, J, b.rowg, m, n,
             cnode, csize, cbirth, cprow);
   CE_LAUNCH(k_cd_rootrows, dim3(gG), dim3(B), 0, s, rootrow, b.eoff, G, m, n, cnode, csize, cbirth, cprow);
-  CE_LAUNCH(k_fill64, dim3(grid_for(3 * (int64_t)nrows, B)), dim3(B), 0, s, (uint64_t *)acc, 3 * (int64_t)nrows,
-            (uint64_t)0);
+  CE_LAUNCH(k_fill64, dim3(grid_cap(3 * R, B)), dim3(B), 0, s, (uint64_t *)acc, 3 * R, (uint64_t)0);
   // point terms of the stabilities per big row; exits per record in input order
-  if (m > 0)
-    CE_LAUNCH(k_cd_point_terms, dim3(tiles(m)), dim3(B), 0, s, b.kc_u, b.kc_v, b.ksize, J, rowL, rowmap, rootrow, m,
-              n, M, acc);
+  CE_LAUNCH(k_cd_point_terms, dim3(tiles(mb)), dim3(B), 0, s, b.kc_u, b.kc_v, b.ksize, J, rowL, rowmap, rootrow, m, n,
+            M, acc);
   uint32_t *prow = labrow;
   uint2 *wk = (uint2 *)exl;  // m <= n words of 8 bytes
-  if (m > 0)
-    CE_LAUNCH(k_cd_walk_words, dim3(grid_for(m, B)), dim3(B), 0, s, kpar, b.ksize, J, rowmap, rootrow, n, m, M, wk);
-  CE_LAUNCH(k_cd_exit_ids, dim3(grid_for(n, B)), dim3(B), 0, s, b.rankof, kpar, wk, rowL, b.grank, rootrow, n, M,
-            prow, out->pt_lambda);
-  CE_LAUNCH(k_cd_acc_children, dim3((unsigned)((nrows + B - 1) / B)), dim3(B), 0, s, csize, cbirth, cprow, nrows,
-            acc);
+  CE_LAUNCH(k_cd_walk_words, dim3(gm), dim3(B), 0, s, kpar, b.ksize, J, rowmap, rootrow, n, m, M, wk);
+  CE_LAUNCH(k_cd_exit_ids, dim3(grid_cap(n, B)), dim3(B), 0, s, b.rankof, kpar, wk, rowL, b.grank, rootrow, n, M,
+            prow, b.hdr, out->pt_lambda);
+  CE_LAUNCH(k_cd_acc_children, dim3((unsigned)((R + B - 1) / B)), dim3(B), 0, s, csize, cbirth, cprow, nrows, acc);
   CE_LAUNCH(k_cd_stab, dim3(gR), dim3(B), 0, s, acc, csize, cbirth, nrows, shi, slo);
-  CE_LAUNCH(k_fill32, dim3(gR), dim3(B), 0, s, nch, (int64_t)nrows, 0u);
-  CE_LAUNCH(k_fill32, dim3(grid_for(2 * (int64_t)nrows, B)), dim3(B), 0, s, ch, 2 * (int64_t)nrows, 0u);
-  uint32_t nvirt = 0;
+  CE_LAUNCH(k_fill32, dim3(gR), dim3(B), 0, s, nch, R, 0u);
+  CE_LAUNCH(k_fill32, dim3(grid_cap(2 * R, B)), dim3(B), 0, s, ch, 2 * R, 0u);
   if (b.q > 0) {
     // any number of child clusters: per-parent lists, then chains of virtual sum nodes
     CE_LAUNCH(k_cd_child_keys, dim3(gR), dim3(B), 0, s, cprow, nrows, ckey);
     CE_HIP(hipGetLastError());
     bool calt = false;
-    CE_TRY((radix_sort_pairs<uint32_t, uint32_t>(ckey, clist, ckey2, clist2, nrows, 0, bits_for(nrows), true, &calt,
-                                                 ws, s)));
+    CE_TRY((radix_sort_pairs<uint32_t, uint32_t>(ckey, clist, ckey2, clist2, nrows, 0, bits_for((uint64_t)R), true,
+                                                 &calt, ws, s)));
     const uint32_t *sk = calt ? ckey2 : ckey;
     if (calt) clist = clist2;
     CE_TRY(segment_bounds_u32(sk, nrows, nrows, choff, s));
     CE_LAUNCH(k_cd_child_counts, dim3(gR), dim3(B), 0, s, choff, nrows, nch, vbase);
     CE_HIP(hipGetLastError());
     CE_TRY(scan_exclusive_u32(vbase, vbase, nrows, ws, s));
-    uint32_t *h = (uint32_t *)pinned_scratch();
-    CE_HIP(hipMemcpyAsync(h + 33, vbase + nrows, 4, hipMemcpyDeviceToHost, s));
-    CE_HIP(hipStreamSynchronize(s));
-    nvirt = h[33];
-    if ((int64_t)nrows + nvirt > RE) {
-      set_error("virtual cluster nodes exceed the workspace bound");
-      return CE_EDEVICE;
-    }
+    CE_LAUNCH(k_virtual_counts, dim3(1), dim3(64), 0, s, vbase, b.hdr, RE);
     CE_LAUNCH(k_cd_pairs, dim3(gR), dim3(B), 0, s, nch, choff, clist, vbase, nrows, ch);
-    if (nvirt > 0)
-      CE_LAUNCH(k_cd_virtual, dim3(grid_for(nvirt, B)), dim3(B), 0, s, nch, choff, clist, vbase, nrows, nvirt, ch, nch,
-                shi, slo);
+    CE_LAUNCH(k_cd_virtual, dim3(gR), dim3(B), 0, s, nch, choff, clist, vbase, nrows, nvirt, ch, nch, shi, slo);
     CE_HIP(hipGetLastError());
   } else {
     CE_LAUNCH(k_cd_children, dim3(gR), dim3(B), 0, s, cprow, nrows, nch, ch);
+    CE_LAUNCH(k_eom_count, dim3(1), dim3(64), 0, s, b.hdr);
   }
-  const uint32_t neom = nrows + nvirt;
-  CE_LAUNCH(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[8], (uint64_t)0);
-  CE_LAUNCH(k_eom_init, dim3(tiles(neom)), dim3(B), 0, s, nch, shi, slo, cprow, nrows, neom, e[0], e[1], ract, ctr);
+  // excess of mass: enqueued rounds, then the rest in one workgroup
+  CE_LAUNCH(k_eom_init, dim3(tiles(RE)), dim3(B), 0, s, nch, shi, slo, cprow, nrows, neom, e[0], e[1], ract,
+            (unsigned long long *)&loop[0]);
   CE_HIP(hipGetLastError());
-  uint64_t nact = 0;
-  CE_TRY(read_u64(&b.hdr[8], &nact, 1, s));
-  int cur = 0;
-  for (int it = 0; nact > 0; it++) {
-    if (it > 4096) {
-      set_error("excess-of-mass rounds did not converge");
-      return CE_EDEVICE;
-    }
-    CE_LAUNCH(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[8], (uint64_t)0);
-    CE_LAUNCH(k_eom_round, dim3(tiles((int64_t)nact)), dim3(B), 0, s, ract, (int64_t)nact, e[cur], e[1 - cur], ch,
-              shi, slo, ract2, ctr);
-    CE_HIP(hipGetLastError());
-    cur = 1 - cur;
-    uint32_t *tmp = ract; ract = ract2; ract2 = tmp;
-    CE_TRY(read_u64(&b.hdr[8], &nact, 1, s));
+  uint32_t *lists[2] = {ract, ract2};
+  const unsigned tRE = grid_cap(RE, B * CT, 4096);
+  const int EOM_ROUNDS = eom_rounds(RE), TOP_ROUNDS = top_rounds(R);
+  if (EOM_ROUNDS + TOP_ROUNDS + 4 > MAX_LOOP_ROUNDS) {
+    set_error("internal: too many bounded rounds");
+    return CE_EDEVICE;
   }
-  CE_LAUNCH(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[8], (uint64_t)0);
-  CE_LAUNCH(k_eom_select, dim3(tiles(nrows)), dim3(B), 0, s, nch, ch, e[cur], shi, slo, nrows, top, nxt, top2, nxt2,
-            cprow, ract, ctr);
+  for (int r = 0; r < EOM_ROUNDS; r++)
+    CE_LAUNCH(k_eom_round, dim3(tRE), dim3(B), 0, s, lists[r & 1], &loop[r], e[r & 1], e[1 - (r & 1)], ch, shi, slo,
+              lists[1 - (r & 1)], (unsigned long long *)&loop[r + 1]);
+  CE_LAUNCH(k_eom_tail, dim3(1), dim3(TB), 0, s, lists[0], lists[1], &loop[EOM_ROUNDS], EOM_ROUNDS & 1, e[0], e[1],
+            ch, shi, slo, b.hdr);
   CE_HIP(hipGetLastError());
-  CE_TRY(read_u64(&b.hdr[8], &nact, 1, s));
-  for (int it = 0; nact > 0; it++) {
-    if (it > 40) {
-      set_error("label pointer jumping did not converge");
-      return CE_EDEVICE;
-    }
-    CE_LAUNCH(k_set64, dim3(1), dim3(1), 0, s, &b.hdr[8], (uint64_t)0);
-    CE_LAUNCH(k_top_jump, dim3(tiles((int64_t)nact)), dim3(B), 0, s, ract, (int64_t)nact, top, nxt, top2, nxt2, ract2,
-              ctr);
-    CE_HIP(hipGetLastError());
-    uint32_t *t1 = top; top = top2; top2 = t1;
-    uint32_t *t2 = nxt; nxt = nxt2; nxt2 = t2;
-    uint32_t *t3 = ract; ract = ract2; ract2 = t3;
-    CE_TRY(read_u64(&b.hdr[8], &nact, 1, s));
-  }
-  CE_LAUNCH(k_fill32, dim3(gR), dim3(B), 0, s, minmem, (int64_t)nrows, NONE32);
-  CE_LAUNCH(k_lab_rows, dim3(grid_for(n, B)), dim3(B), 0, s, prow, top, cprow, n, minmem);
-  CE_LAUNCH(k_fill32, dim3(grid_for(n + 1, B)), dim3(B), 0, s, fl, n + 1, 0u);
+  // the list is empty: both state buffers hold the final values
+  uint64_t *tl = loop + EOM_ROUNDS + 2;
+  CE_LAUNCH(k_eom_select, dim3(tiles(R)), dim3(B), 0, s, nch, ch, e[0], shi, slo, nrows, top, nxt, top2, nxt2, cprow,
+            ract, (unsigned long long *)&tl[0]);
+  CE_HIP(hipGetLastError());
+  uint32_t *tops[2] = {top, top2}, *nxts[2] = {nxt, nxt2};
+  for (int r = 0; r < TOP_ROUNDS; r++)
+    CE_LAUNCH(k_top_jump, dim3(tRE), dim3(B), 0, s, lists[r & 1], &tl[r], tops[r & 1], nxts[r & 1],
+              tops[1 - (r & 1)], nxts[1 - (r & 1)], lists[1 - (r & 1)], (unsigned long long *)&tl[r + 1]);
+  CE_LAUNCH(k_top_tail, dim3(1), dim3(TB), 0, s, lists[0], lists[1], &tl[TOP_ROUNDS], TOP_ROUNDS & 1, top, nxt, top2,
+            nxt2, b.hdr);
+  CE_HIP(hipGetLastError());
+  CE_LAUNCH(k_fill32, dim3(gR), dim3(B), 0, s, minmem, R, NONE32);
+  CE_LAUNCH(k_lab_rows, dim3(grid_cap(n, B)), dim3(B), 0, s, prow, top, cprow, n, minmem);
+  CE_LAUNCH(k_fill32, dim3(grid_cap(n + 1, B)), dim3(B), 0, s, fl, n + 1, 0u);
   CE_LAUNCH(k_lab_flags, dim3(gR), dim3(B), 0, s, top, minmem, nrows, fl);
   CE_HIP(hipGetLastError());
-  CE_TRY(scan_exclusive_u32(fl, fl, n, ws, s));
+  CE_TRY(scan_exclusive_u32(fl, fl, Cnt(n), ws, s));
   // per cluster row first (small arrays), then every record reads its row's values
   uint32_t *rlocal = nxt;
   int32_t *rlab = (int32_t *)nxt2;
   CE_LAUNCH(k_row_point_vals, dim3(gR), dim3(B), 0, s, cnode, cprow, top, minmem, fl, b.rowg, b.eoff, b.moff,
             b.rowpos, n, m, nrows, rlocal, rlab);
-  CE_LAUNCH(k_out_points, dim3(grid_for(n, B)), dim3(B), 0, s, prow, rlocal, rlab, n, out->pt_cluster, out->labels);
+  CE_LAUNCH(k_out_points, dim3(grid_cap(n, B)), dim3(B), 0, s, prow, rlocal, rlab, n, b.hdr, out->pt_cluster,
+            out->labels);
   CE_LAUNCH(k_out_clusters, dim3(gR), dim3(B), 0, s, cnode, cprow, csize, cbirth, shi, slo, top, b.rowg, b.eoff,
-            b.moff, b.rowpos, n, m, nrows, *out);
+            b.moff, b.rowpos, n, m, nrows, b.hdr, *out);
   CE_LAUNCH(k_graph_labels, dim3(gG), dim3(B), 0, s, fl, b.eoff, G, nlab);
+  CE_LAUNCH(k_header, dim3(gG), dim3(B), 0, s, b.hdr, G, b.moff, bstart, nlab, hout);
   CE_HIP(hipGetLastError());
-  std::vector<uint32_t> hb(G + 1), hl(G);
-  CE_HIP(hipMemcpyAsync(hb.data(), bstart, sizeof(uint32_t) * (G + 1), hipMemcpyDeviceToHost, s));
-  CE_HIP(hipMemcpyAsync(hl.data(), nlab, sizeof(uint32_t) * G, hipMemcpyDeviceToHost, s));
-  CE_HIP(hipStreamSynchronize(s));
-  for (int64_t g = 0; g < G; g++) {
-    counts[g].n_clusters = (int64_t)(hb[g + 1] - hb[g]) + 1;
-    counts[g].n_labels = hl[g];
-    if (cluster_offsets) cluster_offsets[g] = (int64_t)hb[g] + g;
-  }
-  if (cluster_offsets) cluster_offsets[G] = (int64_t)nb + G;
+  (void)gRE;
   ws.release(m0);
   return CE_OK;
 }

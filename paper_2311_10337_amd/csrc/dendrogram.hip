@@ -119,8 +119,9 @@ __device__ inline uint32_t g_union(uint4 *uf, uint32_t a, uint32_t b, uint32_t q
   }
 }
 
-__global__ __launch_bounds__(B) void k_krt_init(const uint64_t *msf_val, int64_t m, uint32_t *lu, uint32_t *lv,
+__global__ __launch_bounds__(B) void k_krt_init(const uint64_t *msf_val, Cnt mc, uint32_t *lu, uint32_t *lv,
                                                 uint32_t *su, uint32_t *sv) {
+  const int64_t m = mc.get();
   for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
     const uint64_t v = msf_val[j];
     lu[j] = (uint32_t)v;          // tail rank
@@ -131,7 +132,8 @@ __global__ __launch_bounds__(B) void k_krt_init(const uint64_t *msf_val, int64_t
 }
 
 __global__ __launch_bounds__(B) void k_krt_reset(const uint32_t *lu, const uint32_t *lv, const uint32_t *su,
-                                                 const uint32_t *sv, int64_t m, uint4 *uf) {
+                                                 const uint32_t *sv, Cnt mc, uint4 *uf) {
+  const int64_t m = mc.get();
   for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
     uint32_t a = lu[j], b = lv[j];
     uf[a] = make_uint4(a, NONE32, 0u, su[j]);
@@ -155,9 +157,11 @@ __device__ inline int64_t step_row(int64_t tix, int lo, int hi, uint32_t q) {
 // the largest row and size of the component after sub-intervals < q), then
 // union them. Largest rows and sizes (z, w) are read while other threads hook
 // roots, which changes only x and y.
-__global__ __launch_bounds__(B) void k_krt_union(int64_t m, int64_t n, int lo, int hi, uint32_t q, int64_t nthreads,
+__global__ __launch_bounds__(B) void k_krt_union(Cnt mc, int64_t n, int lo, int hi, uint32_t q, int64_t nthreads,
                                                  uint32_t *lu, uint32_t *lv, uint32_t *su, uint32_t *sv, uint4 *uf,
                                                  uint32_t *hooked) {
+  const int64_t m = mc.get();
+  if (((int64_t)q << lo) >= m) return;  // no interval reaches sub-interval q
   for (int64_t tix = (int64_t)blockIdx.x * B + threadIdx.x; tix < nthreads; tix += (int64_t)gridDim.x * B) {
     int64_t j = step_row(tix, lo, hi, q);
     if (j >= m) continue;
@@ -187,9 +191,11 @@ __global__ __launch_bounds__(B) void k_krt_union(int64_t m, int64_t n, int lo, i
 // tile; rows whose root finds no free slot go straight to global atomics.
 constexpr int KHS = 256;
 constexpr int KCT = 16;
-__global__ __launch_bounds__(B) void k_krt_accum(int64_t m, int lo, int hi, uint32_t q, int64_t nthreads,
+__global__ __launch_bounds__(B) void k_krt_accum(Cnt mc, int lo, int hi, uint32_t q, int64_t nthreads,
                                                  const uint32_t *hooked, uint4 *uf) {
   __shared__ uint32_t hk[KHS], hs[KHS], hm[KHS];
+  const int64_t m = mc.get();
+  if (((int64_t)q << lo) >= m) return;
   for (int i = threadIdx.x; i < KHS; i += B) { hk[i] = NONE32; hs[i] = 0; hm[i] = 0; }
   __syncthreads();
   const int64_t tbase = (int64_t)blockIdx.x * (B * KCT);
@@ -273,8 +279,10 @@ __device__ inline uint32_t l_union(uint32_t *uf, uint32_t a, uint32_t b) {
 __device__ inline uint32_t hslot(uint32_t g) { return (g * 2654435761u) >> (32 - (LS_BITS + 2)); }
 
 __global__ __launch_bounds__(LB) void k_krt_lds(const uint32_t *lu, const uint32_t *lv, const uint32_t *su,
-                                               const uint32_t *sv, int64_t m, int64_t n, uint32_t *kc_u,
+                                               const uint32_t *sv, Cnt mc, int64_t n, uint32_t *kc_u,
                                                uint32_t *kc_v, uint32_t *ksize) {
+  const int64_t m = mc.get();
+  if ((int64_t)blockIdx.x * LS >= m) return;
   __shared__ uint32_t hkey[HS];
   __shared__ uint16_t hid[HS];
   __shared__ uint32_t glab[2 * LS];
@@ -397,21 +405,25 @@ size_t stage_dendrogram_scratch(int64_t n) {
   return w.off + 4096;
 }
 
-ce_status stage_dendrogram(Bufs &b, int64_t m, Ws &ws, hipStream_t s) {
-  if (m <= 0) return CE_OK;
+// The row count m is on the device; the level plan is made for its bound n - 1
+// (levels and sub-intervals past the live rows find nothing to do).
+ce_status stage_dendrogram(Bufs &b, Ws &ws, hipStream_t s) {
   const int64_t n = b.n;
+  if (n <= 1) return CE_OK;
+  const int64_t mb = n - 1;
+  const Cnt m(&b.hdr[H_M], mb);
   size_t m0 = ws.mark();
-  uint32_t *lu = ws.alloc<uint32_t>(m), *lv = ws.alloc<uint32_t>(m);
-  uint32_t *su = ws.alloc<uint32_t>(m), *sv = ws.alloc<uint32_t>(m);
-  uint32_t *hooked = ws.alloc<uint32_t>(m);
-  uint4 *uf = ws.alloc<uint4>(n + m);
+  uint32_t *lu = ws.alloc<uint32_t>(mb), *lv = ws.alloc<uint32_t>(mb);
+  uint32_t *su = ws.alloc<uint32_t>(mb), *sv = ws.alloc<uint32_t>(mb);
+  uint32_t *hooked = ws.alloc<uint32_t>(mb);
+  uint4 *uf = ws.alloc<uint4>(n + mb);
   CE_WS_CHECK(ws);
-  CE_LAUNCH(k_krt_init, dim3(grid_for(m, B)), dim3(B), 0, s, b.msf_val, m, lu, lv, su, sv);
+  CE_LAUNCH(k_krt_init, dim3(grid_cap(mb, B)), dim3(B), 0, s, b.msf_val, m, lu, lv, su, sv);
   CE_HIP(hipGetLastError());
-  const int L = bits_for((uint64_t)(m - 1));  // rows are j < 2^L
+  const int L = bits_for((uint64_t)(mb - 1));  // rows are j < 2^L
   // the global bits L-1 .. LS_BITS in as few levels as the largest level
   // allows, spread evenly (the upper levels take the remainder)
-  const int gbits = L - LS_BITS, kmax = krt_max_level_bits(m);
+  const int gbits = L - LS_BITS, kmax = krt_max_level_bits(mb);
   const int nlev = gbits > 0 ? (gbits + kmax - 1) / kmax : 0;
   int hi = L - 1, lev = 0;
   bool first = true;
@@ -421,23 +433,23 @@ ce_status stage_dendrogram(Bufs &b, int64_t m, Ws &ws, hipStream_t s) {
     int lo = hi - kb + 1;
     if (lo < LS_BITS) lo = LS_BITS;
     const uint32_t K = 1u << (hi - lo + 1);
-    const int64_t nint = (m + (int64_t(1) << (hi + 1)) - 1) >> (hi + 1);
+    const int64_t nint = (mb + (int64_t(1) << (hi + 1)) - 1) >> (hi + 1);
     const int64_t nthreads = nint << lo;
     const unsigned g = grid_for(nthreads, B, 1 << 16);
-    if (first) CE_LAUNCH(k_krt_reset_records, dim3(grid_for(n, B)), dim3(B), 0, s, n, uf);
-    else CE_LAUNCH(k_krt_reset, dim3(grid_for(m, B)), dim3(B), 0, s, lu, lv, su, sv, m, uf);
+    if (first) CE_LAUNCH(k_krt_reset_records, dim3(grid_cap(n, B)), dim3(B), 0, s, n, uf);
+    else CE_LAUNCH(k_krt_reset, dim3(grid_cap(mb, B)), dim3(B), 0, s, lu, lv, su, sv, m, uf);
     first = false;
     for (uint32_t q = 0; q < K; q++) {
-      // sub-interval q exists in at least one interval?
-      if (((int64_t)q << lo) >= m) break;
+      // sub-interval q exists in at least one interval of the bound (the kernels check the live rows)
+      if (((int64_t)q << lo) >= mb) break;
       CE_LAUNCH(k_krt_union, dim3(g), dim3(B), 0, s, m, n, lo, hi, q, nthreads, lu, lv, su, sv, uf, hooked);
       CE_LAUNCH(k_krt_accum, dim3((unsigned)((nthreads + B * KCT - 1) / (B * KCT))), dim3(B), 0, s, m, lo, hi,
-                         q, nthreads, hooked, uf);
+                q, nthreads, hooked, uf);
     }
     CE_HIP(hipGetLastError());
     hi = lo - 1;
   }
-  const int64_t nblk = (m + LS - 1) / LS;
+  const int64_t nblk = (mb + LS - 1) / LS;
   CE_LAUNCH(k_krt_lds, dim3((unsigned)nblk), dim3(LB), 0, s, lu, lv, su, sv, m, n, b.kc_u, b.kc_v, b.ksize);
   CE_HIP(hipGetLastError());
   ws.release(m0);

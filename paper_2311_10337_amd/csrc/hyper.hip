@@ -74,8 +74,7 @@ __global__ __launch_bounds__(B) void k_hvalidate(const int32_t *members, const i
 }
 
 __global__ void k_hinit_hdr(uint64_t *hdr) {
-  if (threadIdx.x < 16) hdr[threadIdx.x] = 0;
-  if (threadIdx.x == 0) hdr[1] = NONE64;
+  for (int i = threadIdx.x; i < kHdrWords; i += blockDim.x) hdr[i] = i == H_TMIN ? NONE64 : 0;
 }
 __global__ void k_hzero(uint64_t *p) {
   if (threadIdx.x == 0) *p = 0;
@@ -84,7 +83,8 @@ __global__ __launch_bounds__(B) void k_hfill_best(uint64_t *best, int64_t n) {
   for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < n; i += (int64_t)gridDim.x * B) best[i] = NONE64;
 }
 
-__global__ __launch_bounds__(B) void k_htkeys(const int64_t *t, int64_t n, int64_t tmin, uint64_t *keys) {
+__global__ __launch_bounds__(B) void k_htkeys(const int64_t *t, int64_t n, const uint64_t *hdr, uint64_t *keys) {
+  const int64_t tmin = (int64_t)(hdr[H_TMIN] ^ (uint64_t(1) << 63));
   for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < n; i += (int64_t)gridDim.x * B)
     keys[i] = (uint64_t)(t[i] - tmin);
 }
@@ -171,19 +171,16 @@ __global__ __launch_bounds__(B) void k_hemit(const uint32_t *sk, const uint32_t 
   }
 }
 
+__global__ void k_hput_u64(uint64_t *p, uint64_t v) { *p = v; }
+
 }  // namespace
 
 ce_status stage_hyper_validate(const int32_t *members, const int64_t *offsets, const int64_t *t, int64_t nnz,
-                               Bufs &b, hipStream_t s, uint64_t *flags, int64_t *tmin, int64_t *tmax) {
+                               Bufs &b, hipStream_t s) {
   CE_LAUNCH(k_hinit_hdr, dim3(1), dim3(64), 0, s, b.hdr);
   CE_LAUNCH(k_hvalidate, dim3(grid_for(b.n > nnz ? b.n : nnz, B, 4096)), dim3(B), 0, s, members, offsets, t, b.n,
             nnz, b.V, b.hdr);
   CE_HIP(hipGetLastError());
-  uint64_t h[3];
-  CE_TRY(read_u64(b.hdr, h, 3, s));
-  *flags = h[0];
-  *tmin = (int64_t)(h[1] ^ (uint64_t(1) << 63));
-  *tmax = (int64_t)(h[2] ^ (uint64_t(1) << 63));
   return CE_OK;
 }
 
@@ -227,7 +224,7 @@ ce_status stage_hyper_skeleton(const int32_t *members, const int64_t *offsets, c
     uint64_t *tkey_alt = ws.alloc<uint64_t>(n);
     uint32_t *pv_alt = ws.alloc<uint32_t>(n);
     CE_WS_CHECK(ws);
-    CE_LAUNCH(k_htkeys, dim3(grid_for(n, B)), dim3(B), 0, s, t, n, b.tmin, b.ts);
+    CE_LAUNCH(k_htkeys, dim3(grid_for(n, B)), dim3(B), 0, s, t, n, b.hdr, b.ts);
     CE_HIP(hipGetLastError());
     bool alt = false;
     CE_TRY((radix_sort_pairs<uint64_t, uint32_t>(b.ts, b.perm, tkey_alt, pv_alt, n, 0, b.tbits, true, &alt, ws, s)));
@@ -296,6 +293,7 @@ ce_status stage_hyper_skeleton(const int32_t *members, const int64_t *offsets, c
   if (nnz > 0)
     CE_LAUNCH(k_hemit, dim3(grid_for(nnz, B)), dim3(B), 0, s, sk, sv, pos, nnz, b.ts, b.perm, f, fx, start,
               b.wshift, b.hshift, b.skel_key, b.skel_tail, b.skel_tid, b.best);
+  CE_LAUNCH(k_hput_u64, dim3(1), dim3(1), 0, s, &b.hdr[H_C7], (uint64_t)S);  // the rows, for Boruvka's first round
   CE_HIP(hipGetLastError());
   ws.release(m0);
   return CE_OK;

@@ -70,15 +70,24 @@ __global__ __launch_bounds__(B) void k_validate(const int32_t *src, const int32_
 }
 
 __global__ void k_init_hdr(uint64_t *hdr) {
-  if (threadIdx.x < 16) hdr[threadIdx.x] = 0;
-  if (threadIdx.x == 0) hdr[1] = NONE64;
+  for (int i = threadIdx.x; i < kHdrWords; i += blockDim.x) hdr[i] = i == H_TMIN ? NONE64 : 0;
 }
+
+// After validation: a time span wider than the plan's tbits bits is an error too (the keys would not fit).
+__global__ void k_check_span(uint64_t *hdr, int64_t n, int tbits) {
+  if (threadIdx.x != 0 || n == 0) return;
+  const uint64_t span = hdr[H_TMAX] - hdr[H_TMIN];
+  if (tbits < 64 && (span >> tbits) != 0) hdr[H_STATUS] |= 8;
+}
+
+__device__ inline int64_t tmin_of(const uint64_t *hdr) { return (int64_t)(hdr[H_TMIN] ^ (uint64_t(1) << 63)); }
 
 // the time sort carries (id, src, dst, graph) along, so grouping needs no
 // gathers; vertex ids become global (graph offset + local id)
 __global__ __launch_bounds__(B) void k_tkeys(const int64_t *t, const int32_t *src, const int32_t *dst, int64_t n,
-                                             const int64_t *eoff, const int64_t *voff, int64_t G, int64_t tmin,
-                                             uint64_t *keys, uint4 *vals) {
+                                             const int64_t *eoff, const int64_t *voff, int64_t G,
+                                             const uint64_t *hdr, uint64_t *keys, uint4 *vals) {
+  const int64_t tmin = tmin_of(hdr);
   for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < n; i += (int64_t)gridDim.x * B) {
     const uint32_t g = G > 1 ? graph_of(eoff, G, i) : 0u;
     const uint32_t vb = (uint32_t)voff[g];
@@ -104,7 +113,8 @@ __global__ __launch_bounds__(B) void k_incidence(const uint4 *vals, int64_t n, u
 // pass over bits [32, 32 + bits(span)) moves 16 bytes per record instead of 24.
 // Stability keeps ids in order within equal times either way.
 __global__ __launch_bounds__(B) void k_tkeys_packed(const int64_t *t, const int32_t *src, const int32_t *dst,
-                                                    int64_t n, int64_t tmin, uint64_t *keys, uint64_t *vals) {
+                                                    int64_t n, const uint64_t *hdr, uint64_t *keys, uint64_t *vals) {
+  const int64_t tmin = tmin_of(hdr);
   for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < n; i += (int64_t)gridDim.x * B) {
     keys[i] = ((uint64_t)(t[i] - tmin) << 32) | (uint64_t)i;
     vals[i] = (uint64_t)(uint32_t)src[i] | ((uint64_t)(uint32_t)dst[i] << 32);
@@ -127,11 +137,14 @@ __global__ __launch_bounds__(B) void k_incidence_packed(const uint64_t *keys, co
 
 // every incidence entry names its slot; the entry's predecessor in the same
 // vertex list is the tail of the skeleton edge stored there
+// (an input that failed validation gets an empty skeleton, so everything after
+// it runs on n isolated records and stays in bounds whatever the input held)
 __global__ __launch_bounds__(B) void k_skel_tails(const uint32_t *ikey, const uint32_t *ival, int64_t n2,
-                                                  uint32_t *skel_tail) {
+                                                  const uint64_t *hdr, uint32_t *skel_tail) {
+  const bool bad = hdr[H_STATUS] != 0;
   for (int64_t k = (int64_t)blockIdx.x * B + threadIdx.x; k < n2; k += (int64_t)gridDim.x * B) {
     uint32_t slot = ival[k];
-    skel_tail[slot] = (k > 0 && ikey[k - 1] == ikey[k]) ? (ival[k - 1] >> 1) : NONE32;
+    skel_tail[slot] = (!bad && k > 0 && ikey[k - 1] == ikey[k]) ? (ival[k - 1] >> 1) : NONE32;
   }
 }
 
@@ -191,23 +204,95 @@ __device__ inline uint32_t slot_of_key(uint64_t k, int idbits, const uint32_t *r
 // Each later round runs on a CONTRACTED graph: components carry dense ids
 // 0..C-1 and the live edges are records (key, endpoint ids, slot), so the
 // per-round arrays shrink with C and stay cache resident after round 1.
+//
+// Every count that steers the rounds (live edges E, components C, the phase of
+// a filter split) lives in the call's control block, and every round kernel
+// reads it when it starts. The host enqueues a fixed number of rounds, enough
+// for any input of n records (live components at least halve per round); the
+// rounds after the forest is complete find E = 0 and return at once. The last
+// block of a round's final kernel advances the state (a ticket counter tells
+// it that every other block is done).
 
-// hook each component onto the component across its minimum edge; of a mutual
-// pair the smaller id stays; the hooking edge joins the forest. Hooked
-// components go to the active list for pointer jumping.
+// Boruvka state, words H_BV + k of the control block
+enum : int {
+  BV_E = 0,        // live edges of the current list
+  BV_C = 1,        // components (ids 0..C-1)
+  BV_PHASE = 2,    // 0 plain rounds, 1 light rounds of a filter split
+  BV_IN = 3,       // the list: edge buffer 0 or 1, or 2 = the skeleton rows themselves
+  BV_OFF = 4,      // its first entry in that buffer
+  BV_HB = 5,       // buffer holding the heavy edges of a split at its back
+  BV_EH = 6,       // heavy edges
+  BV_SPLIT = 7,    // this round starts with a split at BV_PIVOT
+  BV_PIVOT = 8,
+  BV_FIRSTL = 9,   // first light round (the root map starts as the identity)
+  BV_HEAVY = 10,   // the light edges are gone: contract the heavy ones next
+  BV_SEEDED = 11,  // the minima of this round were seeded while the skeleton was emitted
+  BV_SPLITDONE = 12,  // at most one split per call (it bounds the rounds)
+  // gates: the live counts of the kernels of one phase, 0 while they have nothing to do
+  BV_EN = 13, BV_CN = 14, BV_EL = 15, BV_CL = 16, BV_CG = 17, BV_EHG = 18,
+  BV_TICKET = 19,  // last-block ticket, then two list counters
+  BV_CNT1 = 20, BV_CNT2 = 21,
+  BV_WORDS = 24
+};
+
+struct EdgeLists {
+  uint64_t *key[3];
+  uint32_t *u[3], *v[3], *s[3];  // s[2] == nullptr: the slot of a skeleton row is its index
+  int64_t cap;                   // entries of buffers 0 and 1
+};
+
+__device__ inline uint64_t ld_coherent(const uint64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// the live list of the current round
+struct Live {
+  const uint64_t *key;
+  const uint32_t *u, *v, *s;
+  int64_t E;
+};
+__device__ inline Live live_list(const EdgeLists &L, const uint64_t *bv) {
+  const int in = (int)bv[BV_IN];
+  const int64_t off = (int64_t)bv[BV_OFF];
+  return Live{L.key[in] + off, L.u[in] + off, L.v[in] + off, L.s[in] ? L.s[in] + off : nullptr, (int64_t)bv[BV_E]};
+}
+__device__ inline int out_buffer(const uint64_t *bv) {
+  const int in = (int)bv[BV_IN];
+  return in == 2 ? 0 : 1 - in;
+}
+
+// gates from the state (run by the block that last changed it)
+__device__ inline void bv_publish(uint64_t *bv) {
+  const bool light = bv[BV_PHASE] == 1, live = bv[BV_E] > 0;
+  bv[BV_EN] = light ? 0 : bv[BV_E];
+  bv[BV_CN] = (!light && live) ? bv[BV_C] : 0;
+  bv[BV_EL] = light ? bv[BV_E] : 0;
+  bv[BV_CL] = (light && live) ? bv[BV_C] : 0;
+  bv[BV_CG] = live ? bv[BV_C] : 0;
+  bv[BV_EHG] = bv[BV_HEAVY] ? bv[BV_EH] : 0;
+}
+
+// true in exactly one block, the last to arrive; all blocks must call it
+__device__ inline bool last_block(uint64_t *ticket) {
+  __shared__ bool last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned long long t = atomicAdd((unsigned long long *)ticket, 1ull);
+    last = t == (unsigned long long)(gridDim.x - 1);
+  }
+  __syncthreads();
+  if (last) __threadfence();
+  return last;
+}
+
+// first round, on records: hook each record onto the record across its
+// minimum edge; of a mutual pair the smaller id stays; the hooking edge joins
+// the forest. flags[c] = 1 for roots that have an edge (they get dense ids).
 __global__ __launch_bounds__(B) void k_bv_hook_first(int64_t n, const uint64_t *best, const uint64_t *skel_key,
                                                      const uint32_t *skel_tail, const uint32_t *rankof, int idbits,
-                                                     uint32_t *hook, uint8_t *msf_flag, uint32_t *active,
-                                                     unsigned long long *nactive) {
-  bool keep[CT];
-  uint32_t vals[CT];
-  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
-#pragma unroll
-  for (int k = 0; k < CT; k++) {
-    const int64_t c = base + (int64_t)k * B;
-    keep[k] = false;
-    vals[k] = (uint32_t)c;
-    if (c >= n) continue;
+                                                     uint32_t *hook, uint8_t *msf_flag, uint32_t *flags) {
+  for (int64_t c = (int64_t)blockIdx.x * B + threadIdx.x; c < n; c += (int64_t)gridDim.x * B) {
     uint32_t to = (uint32_t)c;
     const uint64_t bk = best[c];
     if (bk != NONE64) {
@@ -221,275 +306,431 @@ __global__ __launch_bounds__(B) void k_bv_hook_first(int64_t n, const uint64_t *
       if (!(best[o] == bk && (uint32_t)c < o)) {
         to = o;
         msf_flag[e] = 1;
-        keep[k] = true;
       }
     }
     hook[c] = to;
+    flags[c] = (to == (uint32_t)c && bk != NONE64) ? 1u : 0u;
   }
-  tile_append(keep, vals, active, nactive);
 }
 
-__global__ __launch_bounds__(B) void k_bv_hook(int64_t C, const uint64_t *best, const uint32_t *bidx,
-                                               const uint32_t *eu, const uint32_t *ev, const uint32_t *eslot,
-                                               uint32_t *hook, uint8_t *msf_flag, uint32_t *active,
-                                               unsigned long long *nactive) {
-  bool keep[CT];
-  uint32_t vals[CT];
-  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
-#pragma unroll
-  for (int k = 0; k < CT; k++) {
-    const int64_t c = base + (int64_t)k * B;
-    keep[k] = false;
-    vals[k] = (uint32_t)c;
-    if (c >= C) continue;
+// later rounds, on the contracted graph
+__global__ __launch_bounds__(B) void k_bv_hook(EdgeLists L, const uint64_t *bv, const uint64_t *best,
+                                               const uint32_t *bidx, uint32_t *hook, uint8_t *msf_flag,
+                                               uint32_t *flags) {
+  const Live lv = live_list(L, bv);
+  const int64_t C = (int64_t)bv[BV_C];
+  if (lv.E == 0) return;
+  for (int64_t c = (int64_t)blockIdx.x * B + threadIdx.x; c < C; c += (int64_t)gridDim.x * B) {
     uint32_t to = (uint32_t)c;
     const uint64_t bk = best[c];
     if (bk != NONE64) {
       const uint32_t i = bidx[c];
-      const uint32_t o = eu[i] == (uint32_t)c ? ev[i] : eu[i];
+      const uint32_t o = lv.u[i] == (uint32_t)c ? lv.v[i] : lv.u[i];
       if (!(best[o] == bk && (uint32_t)c < o)) {
         to = o;
-        msf_flag[eslot ? eslot[i] : i] = 1;
-        keep[k] = true;
+        msf_flag[lv.s ? lv.s[i] : i] = 1;
       }
     }
     hook[c] = to;
+    flags[c] = (to == (uint32_t)c && bk != NONE64) ? 1u : 0u;
   }
-  tile_append(keep, vals, active, nactive);
 }
 
-// pointer jumping over the hooked components; converged ones leave the list
-__global__ __launch_bounds__(B) void k_bv_jump(const uint32_t *act, int64_t nact, uint32_t *hook, uint32_t *out,
-                                               unsigned long long *nout) {
-  bool keep[CT];
-  uint32_t vals[CT];
-  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
-#pragma unroll
-  for (int k = 0; k < CT; k++) {
-    const int64_t i = base + (int64_t)k * B;
-    keep[k] = false;
-    vals[k] = 0;
-    if (i >= nact) continue;
-    uint32_t c = act[i];
-    uint32_t h = hook[c];
-    uint32_t hh = hook[h];
-    if (hh != h) {
-      hook[c] = hh;
-      keep[k] = true;
-      vals[k] = c;
+// Every component to its final root, in two passes. The first walks from
+// every component and halves the path it follows (each store moves a link to
+// a grandparent), so long hook chains shrink as in pointer jumping. Walks only
+// ever store ancestors, so a stale link seen by another walk is still an
+// ancestor and every walk ends at the root (hooks form a forest: keys are
+// unique, and of a mutual pair only one side hooks). But a halving store can
+// land after the owner of that entry stored its root, and put a lower
+// ancestor back; so the second pass walks again, read only, and each
+// component stores its own root alone. A walk longer than any forest allows
+// marks the call failed and stops.
+constexpr uint32_t MAX_WALK = 1u << 26;
+__global__ __launch_bounds__(B) void k_bv_compress(Cnt C, uint32_t *hook, uint64_t *hdr) {
+  const int64_t nc = C.get();
+  for (int64_t c = (int64_t)blockIdx.x * B + threadIdx.x; c < nc; c += (int64_t)gridDim.x * B) {
+    uint32_t x = hook[c];
+    if (x == (uint32_t)c) continue;
+    for (uint32_t steps = 0;; steps++) {
+      const uint32_t p = __hip_atomic_load(&hook[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (p == x) break;
+      const uint32_t gp = __hip_atomic_load(&hook[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (gp != p) __hip_atomic_store(&hook[x], gp, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      x = gp;
+      if (steps > MAX_WALK) {
+        atomicOr((unsigned long long *)&hdr[H_STATUS], 16ull);
+        break;
+      }
     }
   }
-  tile_append(keep, vals, out, nout);
+}
+__global__ __launch_bounds__(B) void k_bv_roots(Cnt C, uint32_t *hook, uint64_t *hdr) {
+  const int64_t nc = C.get();
+  for (int64_t c = (int64_t)blockIdx.x * B + threadIdx.x; c < nc; c += (int64_t)gridDim.x * B) {
+    uint32_t x = __hip_atomic_load(&hook[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (x == (uint32_t)c) continue;
+    for (uint32_t steps = 0;; steps++) {
+      const uint32_t p = __hip_atomic_load(&hook[x], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (p == x) break;
+      x = p;
+      if (steps > MAX_WALK) {
+        atomicOr((unsigned long long *)&hdr[H_STATUS], 16ull);
+        break;
+      }
+    }
+    __hip_atomic_store(&hook[c], x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
-// surviving roots get dense ids; records without any edge are left out
-__global__ __launch_bounds__(B) void k_root_flags(int64_t C, const uint32_t *hook, const uint64_t *best,
-                                                  uint32_t *flags) {
-  for (int64_t c = (int64_t)blockIdx.x * B + threadIdx.x; c < C; c += (int64_t)gridDim.x * B)
-    flags[c] = (hook[c] == (uint32_t)c && best[c] != NONE64) ? 1u : 0u;
-}
-
-// the dense id of every component's final root (one gather per component, so
-// contraction reads one id per endpoint instead of a root and then its id)
-__global__ __launch_bounds__(B) void k_final_ids(int64_t C, const uint32_t *hook, const uint32_t *newid,
-                                                 uint32_t *fin) {
-  for (int64_t c = (int64_t)blockIdx.x * B + threadIdx.x; c < C; c += (int64_t)gridDim.x * B)
+// dense id of every component's final root (contraction reads one id per
+// endpoint); the minima of the next round start empty
+__global__ __launch_bounds__(B) void k_final_ids(Cnt C, const uint32_t *hook, const uint32_t *newid, uint32_t *fin,
+                                                 uint64_t *best) {
+  const int64_t nc = C.get();
+  const int64_t cn = nc > 0 ? (int64_t)newid[nc] : 0;
+  for (int64_t c = (int64_t)blockIdx.x * B + threadIdx.x; c < nc; c += (int64_t)gridDim.x * B) {
     fin[c] = newid[hook[c]];
-}
-
-// contract: live edges between different final roots, endpoints renamed to dense ids
-__global__ __launch_bounds__(B) void k_contract_first(int64_t n2, const uint64_t *skel_key, const uint32_t *skel_tail,
-                                                      const uint32_t *fin, uint64_t *okey,
-                                                      uint32_t *ou, uint32_t *ov, uint32_t *oslot,
-                                                      unsigned long long *cnt) {
-  bool keep[CT];
-  uint32_t pos[CT], nu[CT], nv[CT];
-  uint64_t kk[CT];
-  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
-#pragma unroll
-  for (int k = 0; k < CT; k++) {
-    const int64_t e = base + (int64_t)k * B;
-    keep[k] = false;
-    kk[k] = NONE64;
-    nu[k] = nv[k] = 0;
-    if (e >= n2) continue;
-    kk[k] = skel_key[e];
-    if (kk[k] == NONE64) continue;
-    const uint32_t fu = fin[skel_tail[e]], fv = fin[e >> 1];
-    if (fu == fv) continue;
-    keep[k] = true;
-    nu[k] = fu;
-    nv[k] = fv;
-  }
-  tile_positions(keep, pos, cnt);
-#pragma unroll
-  for (int k = 0; k < CT; k++) {
-    if (!keep[k]) continue;
-    const uint32_t p = pos[k];
-    okey[p] = kk[k];
-    ou[p] = nu[k];
-    ov[p] = nv[k];
-    oslot[p] = (uint32_t)(base + (int64_t)k * B);
+    if (c < cn) best[c] = NONE64;
   }
 }
 
-__global__ __launch_bounds__(B) void k_contract(int64_t E, const uint64_t *key, const uint32_t *eu, const uint32_t *ev,
-                                                const uint32_t *eslot, const uint32_t *fin,
-                                                uint64_t *okey, uint32_t *ou, uint32_t *ov, uint32_t *oslot,
-                                                unsigned long long *cnt) {
-  bool keep[CT];
-  uint32_t pos[CT], nu[CT], nv[CT];
-  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
+// first contraction: skeleton slots between different final roots, endpoints renamed to dense ids
+__global__ __launch_bounds__(B) void k_contract_first(int64_t n, const uint64_t *skel_key, const uint32_t *skel_tail,
+                                                      const uint32_t *fin, const uint32_t *newid, EdgeLists L,
+                                                      uint64_t *bv) {
+  const int64_t n2 = 2 * n;
+  unsigned long long *cnt = (unsigned long long *)&bv[BV_CNT1];
+  for (int64_t tile = blockIdx.x; tile * (B * CT) < n2; tile += gridDim.x) {
+    bool keep[CT];
+    uint32_t pos[CT], nu[CT], nv[CT];
+    uint64_t kk[CT];
+    const int64_t base = tile * (B * CT) + threadIdx.x;
 #pragma unroll
-  for (int k = 0; k < CT; k++) {
-    const int64_t i = base + (int64_t)k * B;
-    keep[k] = false;
-    nu[k] = nv[k] = 0;
-    if (i >= E) continue;
-    const uint32_t fu = fin[eu[i]], fv = fin[ev[i]];
-    if (fu == fv) continue;
-    keep[k] = true;
-    nu[k] = fu;
-    nv[k] = fv;
+    for (int k = 0; k < CT; k++) {
+      const int64_t e = base + (int64_t)k * B;
+      keep[k] = false;
+      kk[k] = NONE64;
+      nu[k] = nv[k] = 0;
+      if (e >= n2) continue;
+      kk[k] = skel_key[e];
+      if (kk[k] == NONE64) continue;
+      const uint32_t fu = fin[skel_tail[e]], fv = fin[e >> 1];
+      if (fu == fv) continue;
+      keep[k] = true;
+      nu[k] = fu;
+      nv[k] = fv;
+    }
+    tile_positions(keep, pos, cnt);
+#pragma unroll
+    for (int k = 0; k < CT; k++) {
+      if (!keep[k]) continue;
+      const uint32_t p = pos[k];
+      L.key[0][p] = kk[k];
+      L.u[0][p] = nu[k];
+      L.v[0][p] = nv[k];
+      L.s[0][p] = (uint32_t)(base + (int64_t)k * B);
+    }
   }
-  tile_positions(keep, pos, cnt);
-#pragma unroll
-  for (int k = 0; k < CT; k++) {
-    if (!keep[k]) continue;
-    const int64_t i = base + (int64_t)k * B;
-    const uint32_t p = pos[k];
-    okey[p] = key[i];
-    ou[p] = nu[k];
-    ov[p] = nv[k];
-    oslot[p] = eslot ? eslot[i] : (uint32_t)i;
-  }
-}
-
-// Filter split (Filter-Kruskal applied to Borůvka): the live edges with key
-// below a pivot go to the front of the output lists, the others to their
-// back, counted down from `cap`. Light and heavy together are E <= cap
-// entries, so later contractions of the light part, which only shrink it,
-// never reach the heavy part.
-__global__ __launch_bounds__(B) void k_split(int64_t E, const uint64_t *key, const uint32_t *eu, const uint32_t *ev,
-                                             const uint32_t *eslot, uint64_t pivot, int64_t cap, uint64_t *okey,
-                                             uint32_t *ou, uint32_t *ov, uint32_t *oslot, unsigned long long *nlight,
-                                             unsigned long long *nheavy) {
-  bool lt[CT], ge[CT];
-  uint32_t pl[CT], ph[CT];
-  uint64_t kk[CT];
-  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
-#pragma unroll
-  for (int k = 0; k < CT; k++) {
-    const int64_t i = base + (int64_t)k * B;
-    kk[k] = i < E ? key[i] : 0;
-    lt[k] = i < E && kk[k] < pivot;
-    ge[k] = i < E && kk[k] >= pivot;
-  }
-  tile_positions(lt, pl, nlight);
-  tile_positions(ge, ph, nheavy);
-#pragma unroll
-  for (int k = 0; k < CT; k++) {
-    if (!lt[k] && !ge[k]) continue;
-    const int64_t i = base + (int64_t)k * B;
-    const int64_t p = lt[k] ? (int64_t)pl[k] : cap - 1 - (int64_t)ph[k];
-    okey[p] = kk[k];
-    ou[p] = eu[i];
-    ov[p] = ev[i];
-    oslot[p] = eslot ? eslot[i] : (uint32_t)i;
+  if (last_block(&bv[BV_TICKET])) {
+    if (threadIdx.x == 0) {
+      bv[BV_E] = ld_coherent(&bv[BV_CNT1]);
+      bv[BV_C] = newid[n];
+      bv[BV_IN] = 0;
+      bv[BV_OFF] = 0;
+      bv[BV_PHASE] = 0;
+      bv[BV_SEEDED] = 0;
+      bv[BV_CNT1] = 0;
+      bv[BV_TICKET] = 0;
+      bv_publish(bv);
+    }
   }
 }
 
-// root of every component of the split graph after another light round:
-// hook maps this round's roots to their new roots
-__global__ __launch_bounds__(B) void k_compose_roots(int64_t C, const uint32_t *hook, uint32_t *rootof, bool first) {
-  for (int64_t c = (int64_t)blockIdx.x * B + threadIdx.x; c < C; c += (int64_t)gridDim.x * B)
+// Contraction of the live list (gated count E) with the map f: edges between
+// different f-images go to the front of the output buffer, renamed. The last
+// block advances the state: `mode` 0 = plain round (new ids from the scan),
+// 1 = light round (ids stay), 2 = the heavy edges after the light phase.
+__global__ __launch_bounds__(B) void k_contract(EdgeLists L, uint64_t *bv, const uint64_t *gate,
+                                                const uint32_t *fmap, const uint32_t *newid, int mode) {
+  const int64_t E = (int64_t)*gate;
+  if (E == 0) return;  // uniform: every block returns, and the state does not change
+  const int in = mode == 2 ? (int)bv[BV_HB] : (int)bv[BV_IN];
+  const int64_t off = mode == 2 ? L.cap - (int64_t)bv[BV_EH] : (int64_t)bv[BV_OFF];
+  const int ob = mode == 2 ? 1 - in : out_buffer(bv);
+  const uint64_t *key = L.key[in] + off;
+  const uint32_t *eu = L.u[in] + off, *ev = L.v[in] + off;
+  const uint32_t *es = L.s[in] ? L.s[in] + off : nullptr;
+  unsigned long long *cnt = (unsigned long long *)&bv[BV_CNT1];
+  for (int64_t tile = blockIdx.x; tile * (B * CT) < E; tile += gridDim.x) {
+    bool keep[CT];
+    uint32_t pos[CT], nu[CT], nv[CT];
+    const int64_t base = tile * (B * CT) + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < CT; k++) {
+      const int64_t i = base + (int64_t)k * B;
+      keep[k] = false;
+      nu[k] = nv[k] = 0;
+      if (i >= E) continue;
+      const uint32_t fu = fmap[eu[i]], fv = fmap[ev[i]];
+      if (fu == fv) continue;
+      keep[k] = true;
+      nu[k] = fu;
+      nv[k] = fv;
+    }
+    tile_positions(keep, pos, cnt);
+#pragma unroll
+    for (int k = 0; k < CT; k++) {
+      if (!keep[k]) continue;
+      const int64_t i = base + (int64_t)k * B;
+      const uint32_t p = pos[k];
+      L.key[ob][p] = key[i];
+      L.u[ob][p] = nu[k];
+      L.v[ob][p] = nv[k];
+      L.s[ob][p] = es ? es[i] : (uint32_t)i;
+    }
+  }
+  if (last_block(&bv[BV_TICKET])) {
+    if (threadIdx.x == 0) {
+      const uint64_t c = ld_coherent(&bv[BV_CNT1]);
+      if (mode == 0) bv[BV_C] = newid[bv[BV_C]];
+      bv[BV_E] = c;
+      bv[BV_IN] = (uint64_t)ob;
+      bv[BV_OFF] = 0;
+      bv[BV_SEEDED] = 0;
+      if (mode == 1) {
+        bv[BV_FIRSTL] = 0;
+        if (c == 0) bv[BV_HEAVY] = 1;  // light edges used up: the heavy ones are contracted next
+      }
+      if (mode == 2) {
+        bv[BV_PHASE] = 0;
+        bv[BV_HEAVY] = 0;
+      }
+      bv[BV_CNT1] = 0;
+      bv[BV_TICKET] = 0;
+      bv_publish(bv);
+    }
+  }
+}
+
+// Filter split (Filter-Kruskal applied to Borůvka). A round may start with a
+// split when live edges are at least `split_min` and more than twice the
+// components: the pivot is the key of rank ~C*S/E among S evenly spaced
+// samples of the list (sorted in LDS), so about one light edge per component.
+constexpr int SPLIT_SAMPLES = 256;
+__global__ __launch_bounds__(SPLIT_SAMPLES) void k_split_prep(EdgeLists L, uint64_t *bv, int64_t split_min) {
+  __shared__ uint64_t sk[SPLIT_SAMPLES];
+  const Live lv = live_list(L, bv);
+  const int64_t C = (int64_t)bv[BV_C];
+  const bool go = bv[BV_PHASE] == 0 && bv[BV_SEEDED] == 0 && bv[BV_SPLITDONE] == 0 && lv.E >= split_min &&
+                  lv.E > 2 * C;
+  if (!go) {
+    if (threadIdx.x == 0) bv[BV_SPLIT] = 0;
+    return;
+  }
+  const int i = threadIdx.x;
+  sk[i] = lv.key[(int64_t)((unsigned __int128)i * (uint64_t)lv.E / SPLIT_SAMPLES)];
+  __syncthreads();
+  for (int k = 2; k <= SPLIT_SAMPLES; k <<= 1) {  // bitonic sort, ascending
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const int p = i ^ j;
+      if (p > i) {
+        const uint64_t a = sk[i], b2 = sk[p];
+        const bool up = (i & k) == 0;
+        if ((a > b2) == up) { sk[i] = b2; sk[p] = a; }
+      }
+      __syncthreads();
+    }
+  }
+  if (i == 0) {
+    int64_t q = (int64_t)((unsigned __int128)SPLIT_SAMPLES * (uint64_t)C / (uint64_t)lv.E);
+    if (q > SPLIT_SAMPLES - 1) q = SPLIT_SAMPLES - 1;
+    bv[BV_PIVOT] = sk[q];
+    bv[BV_SPLIT] = 1;
+    bv[BV_CNT1] = 0;
+    bv[BV_CNT2] = 0;
+  }
+}
+
+// The live edges with key below the pivot go to the front of the output
+// buffer, the others to its back, counted down from cap. Light and heavy
+// together are E <= cap entries, so later contractions of the light part,
+// which only shrink it, never reach the heavy part.
+__global__ __launch_bounds__(B) void k_split(EdgeLists L, uint64_t *bv) {
+  if (bv[BV_SPLIT] == 0) return;
+  const Live lv = live_list(L, bv);
+  const uint64_t pivot = bv[BV_PIVOT];
+  const int ob = out_buffer(bv);
+  const int64_t cap = L.cap;
+  unsigned long long *nlight = (unsigned long long *)&bv[BV_CNT1];
+  unsigned long long *nheavy = (unsigned long long *)&bv[BV_CNT2];
+  for (int64_t tile = blockIdx.x; tile * (B * CT) < lv.E; tile += gridDim.x) {
+    bool lt[CT], ge[CT];
+    uint32_t pl[CT], ph[CT];
+    uint64_t kk[CT];
+    const int64_t base = tile * (B * CT) + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < CT; k++) {
+      const int64_t i = base + (int64_t)k * B;
+      kk[k] = i < lv.E ? lv.key[i] : 0;
+      lt[k] = i < lv.E && kk[k] < pivot;
+      ge[k] = i < lv.E && kk[k] >= pivot;
+    }
+    tile_positions(lt, pl, nlight);
+    tile_positions(ge, ph, nheavy);
+#pragma unroll
+    for (int k = 0; k < CT; k++) {
+      if (!lt[k] && !ge[k]) continue;
+      const int64_t i = base + (int64_t)k * B;
+      const int64_t p = lt[k] ? (int64_t)pl[k] : cap - 1 - (int64_t)ph[k];
+      L.key[ob][p] = kk[k];
+      L.u[ob][p] = lv.u[i];
+      L.v[ob][p] = lv.v[i];
+      L.s[ob][p] = lv.s ? lv.s[i] : (uint32_t)i;
+    }
+  }
+  if (last_block(&bv[BV_TICKET])) {
+    if (threadIdx.x == 0) {
+      const uint64_t el = ld_coherent(&bv[BV_CNT1]), eh = ld_coherent(&bv[BV_CNT2]);
+      bv[BV_IN] = (uint64_t)ob;
+      if (el > 0) {  // light rounds first; ids stay, the root map starts as the identity
+        bv[BV_PHASE] = 1;
+        bv[BV_FIRSTL] = 1;
+        bv[BV_HB] = (uint64_t)ob;
+        bv[BV_EH] = eh;
+        bv[BV_E] = el;
+        bv[BV_OFF] = 0;
+      } else {  // no light edge: the heavy ones are the whole list
+        bv[BV_E] = eh;
+        bv[BV_OFF] = (uint64_t)(cap - (int64_t)eh);
+      }
+      bv[BV_SPLIT] = 0;
+      bv[BV_SPLITDONE] = 1;
+      bv[BV_CNT1] = 0;
+      bv[BV_CNT2] = 0;
+      bv[BV_TICKET] = 0;
+      bv_publish(bv);
+    }
+  }
+}
+
+// light rounds: the root (in this round's hooks) of every component of the
+// split; the minima of the next round start empty
+__global__ __launch_bounds__(B) void k_compose_roots(Cnt C, const uint64_t *bv, const uint32_t *hook,
+                                                     uint32_t *rootof, uint64_t *best) {
+  const int64_t nc = C.get();
+  const bool first = bv[BV_FIRSTL] != 0;
+  for (int64_t c = (int64_t)blockIdx.x * B + threadIdx.x; c < nc; c += (int64_t)gridDim.x * B) {
     rootof[c] = hook[first ? (uint32_t)c : rootof[c]];
-}
-
-// evenly spaced keys of the live list, for the pivot
-__global__ void k_sample_keys(int64_t E, const uint64_t *key, int S, uint64_t *out) {
-  for (int i = threadIdx.x; i < S; i += blockDim.x) out[i] = key[(int64_t)((unsigned __int128)i * E / S)];
+    best[c] = NONE64;
+  }
 }
 
 // per component, the minimum key over its live edges. A tile of 4096 edges
 // first takes per-component minima in an LDS hash (late rounds send most
 // edges to a few big components), then one atomicMin per component per tile.
 constexpr int MHS = 512;
-__global__ __launch_bounds__(B) void k_bv_min(int64_t E, const uint64_t *key, const uint32_t *eu, const uint32_t *ev,
-                                              uint64_t *best) {
+__global__ __launch_bounds__(B) void k_bv_min(EdgeLists L, const uint64_t *bv, uint64_t *best) {
+  if (bv[BV_SEEDED]) return;  // seeded while the skeleton was emitted
+  const Live lv = live_list(L, bv);
   __shared__ uint32_t hk[MHS];
   __shared__ unsigned long long hv[MHS];
-  for (int i = threadIdx.x; i < MHS; i += B) { hk[i] = NONE32; hv[i] = NONE64; }
-  __syncthreads();
-  const int64_t tbase = (int64_t)blockIdx.x * (B * CT);
-  for (int k = 0; k < CT; k++) {
-    const int64_t i = tbase + (int64_t)k * B + threadIdx.x;
-    const bool act = i < E;
-    const unsigned long long kv = act ? key[i] : NONE64;
-    const uint32_t cu = act ? eu[i] : 0u, cv = act ? ev[i] : 0u;
+  for (int64_t tile = blockIdx.x; tile * (B * CT) < lv.E; tile += gridDim.x) {
+    for (int i = threadIdx.x; i < MHS; i += B) { hk[i] = NONE32; hv[i] = NONE64; }
+    __syncthreads();
+    const int64_t tbase = tile * (B * CT);
+    for (int k = 0; k < CT; k++) {
+      const int64_t i = tbase + (int64_t)k * B + threadIdx.x;
+      const bool act = i < lv.E;
+      const unsigned long long kv = act ? lv.key[i] : NONE64;
+      const uint32_t cu = act ? lv.u[i] : 0u, cv = act ? lv.v[i] : 0u;
 #pragma unroll
-    for (int side = 0; side < 2; side++) {
-      const uint32_t c = side ? cv : cu;
-      unsigned long long kmin = kv;
-      const bool upd = wave_combine_first(act, c, [&](bool mine, int leader) {
-        const unsigned long long v = wave_min_u64(mine ? kv : NONE64);
-        if ((int)wave_lane() == leader) kmin = v;
-      });
-      if (upd) {
-        uint32_t sl = (c * 2654435761u) >> 23;  // 9 bits
-        bool placed = false;
-        for (int probe = 0; probe < HASH_PROBES && !placed; probe++) {
-          uint32_t old = atomicCAS(&hk[sl], NONE32, c);
-          if (old == NONE32 || old == c) {
-            if (kmin < hv[sl]) atomicMin(&hv[sl], kmin);
-            placed = true;
-          } else {
-            sl = (sl + 1) & (MHS - 1);
+      for (int side = 0; side < 2; side++) {
+        const uint32_t c = side ? cv : cu;
+        unsigned long long kmin = kv;
+        const bool upd = wave_combine_first(act, c, [&](bool mine, int leader) {
+          const unsigned long long v = wave_min_u64(mine ? kv : NONE64);
+          if ((int)wave_lane() == leader) kmin = v;
+        });
+        if (upd) {
+          uint32_t sl = (c * 2654435761u) >> 23;  // 9 bits
+          bool placed = false;
+          for (int probe = 0; probe < HASH_PROBES && !placed; probe++) {
+            uint32_t old = atomicCAS(&hk[sl], NONE32, c);
+            if (old == NONE32 || old == c) {
+              if (kmin < hv[sl]) atomicMin(&hv[sl], kmin);
+              placed = true;
+            } else {
+              sl = (sl + 1) & (MHS - 1);
+            }
           }
+          if (!placed && kmin < best[c]) atomicMin((unsigned long long *)&best[c], kmin);
         }
-        if (!placed && kmin < best[c]) atomicMin((unsigned long long *)&best[c], kmin);
       }
     }
-  }
-  __syncthreads();
-  for (int i = threadIdx.x; i < MHS; i += B) {
-    const uint32_t c = hk[i];
-    if (c == NONE32) continue;
-    const unsigned long long v = hv[i];
-    if (v < best[c]) atomicMin((unsigned long long *)&best[c], v);
+    __syncthreads();
+    for (int i = threadIdx.x; i < MHS; i += B) {
+      const uint32_t c = hk[i];
+      if (c == NONE32) continue;
+      const unsigned long long v = hv[i];
+      if (v < best[c]) atomicMin((unsigned long long *)&best[c], v);
+    }
+    __syncthreads();
   }
 }
 
 // the edge index holding each component's minimum (keys are unique)
-__global__ __launch_bounds__(B) void k_bv_pick(int64_t E, const uint64_t *key, const uint32_t *eu, const uint32_t *ev,
-                                               const uint64_t *best, uint32_t *bidx) {
-  for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < E; i += (int64_t)gridDim.x * B) {
-    const uint64_t k = key[i];
-    const uint32_t a = eu[i], b = ev[i];
+__global__ __launch_bounds__(B) void k_bv_pick(EdgeLists L, const uint64_t *bv, const uint64_t *best,
+                                               uint32_t *bidx) {
+  const Live lv = live_list(L, bv);
+  for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < lv.E; i += (int64_t)gridDim.x * B) {
+    const uint64_t k = lv.key[i];
+    const uint32_t a = lv.u[i], b = lv.v[i];
     if (best[a] == k) bidx[a] = (uint32_t)i;
     if (best[b] == k) bidx[b] = (uint32_t)i;
   }
 }
 
-__global__ __launch_bounds__(B) void k_msf_list(const uint8_t *flag, int64_t n2, uint32_t *out,
-                                                unsigned long long *cnt) {
-  bool keep[CT];
-  uint32_t vals[CT];
-  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
-#pragma unroll
-  for (int k = 0; k < CT; k++) {
-    const int64_t e = base + (int64_t)k * B;
-    keep[k] = e < n2 && flag[e];
-    vals[k] = (uint32_t)e;
-  }
-  tile_append(keep, vals, out, cnt);
+// state of a flat skeleton's first round: the rows themselves are the live
+// list (S rows, counted on the device), records are the components, and the
+// minima were seeded during emission
+__global__ void k_bv_flat_init(uint64_t *bv, const uint64_t *rows, int64_t n) {
+  if (threadIdx.x != 0) return;
+  for (int k = 0; k < BV_WORDS; k++) bv[k] = 0;
+  bv[BV_E] = *rows;
+  bv[BV_C] = (uint64_t)n;
+  bv[BV_IN] = 2;
+  bv[BV_SEEDED] = 1;
+  bv_publish(bv);
 }
 
+// after the last enqueued round every live edge must be gone (the round bound
+// guarantees it); if not, the call fails instead of returning a partial forest
+__global__ void k_bv_check(const uint64_t *bv, uint64_t *hdr) {
+  if (threadIdx.x == 0 && (bv[BV_E] != 0 || bv[BV_HEAVY] != 0)) hdr[H_STATUS] |= 32;
+}
+
+__global__ __launch_bounds__(B) void k_msf_list(const uint8_t *flag, int64_t n2, uint32_t *out,
+                                                unsigned long long *cnt) {
+  for (int64_t tile = blockIdx.x; tile * (B * CT) < n2; tile += gridDim.x) {
+    bool keep[CT];
+    uint32_t vals[CT];
+    const int64_t base = tile * (B * CT) + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < CT; k++) {
+      const int64_t e = base + (int64_t)k * B;
+      keep[k] = e < n2 && flag[e];
+      vals[k] = (uint32_t)e;
+    }
+    tile_append(keep, vals, out, cnt);
+  }
+}
 
 // flat rows keep the head rank in skel_tid; the tail id comes from perm
-__global__ __launch_bounds__(B) void k_msf_gather_causal(const uint32_t *list, int64_t m, const uint64_t *skel_key,
+__global__ __launch_bounds__(B) void k_msf_gather_causal(const uint32_t *list, Cnt mc, const uint64_t *skel_key,
                                                          const uint32_t *skel_tail, const uint32_t *skel_head,
                                                          uint64_t *okey, uint64_t *oval) {
+  const int64_t m = mc.get();
   for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < m; i += (int64_t)gridDim.x * B) {
     uint32_t e = list[i];
     okey[i] = skel_key[e];
@@ -497,13 +738,38 @@ __global__ __launch_bounds__(B) void k_msf_gather_causal(const uint32_t *list, i
   }
 }
 
-__global__ __launch_bounds__(B) void k_msf_gather(const uint32_t *list, int64_t m, const uint64_t *skel_key,
+__global__ __launch_bounds__(B) void k_msf_gather(const uint32_t *list, Cnt mc, const uint64_t *skel_key,
                                                   const uint32_t *skel_tail, uint64_t *okey, uint64_t *oval) {
+  const int64_t m = mc.get();
   for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < m; i += (int64_t)gridDim.x * B) {
     uint32_t e = list[i];
     okey[i] = skel_key[e];
     oval[i] = (uint64_t)skel_tail[e] | ((uint64_t)(e >> 1) << 32);
   }
+}
+
+__global__ void k_set_u64(uint64_t *p, uint64_t v) { *p = v; }
+
+// a forest has at most n - 1 rows; more means the call failed (and the rows
+// are dropped, so that later kernels stay in bounds)
+__global__ void k_check_rows(uint64_t *hdr, int64_t n) {
+  if (threadIdx.x == 0 && (int64_t)hdr[H_M] > (n > 1 ? n - 1 : 0)) {
+    hdr[H_STATUS] |= 64;
+    hdr[H_M] = 0;
+  }
+}
+
+// rows with key < limit (rows are sorted, so they are a prefix): one binary
+// search; the prefix becomes the forest (the row count shrinks in place)
+__global__ void k_prefix_below(const uint64_t *key, uint64_t *m, uint64_t limit) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int64_t lo = 0, hi = (int64_t)*m;
+  while (lo < hi) {
+    const int64_t mid = lo + (hi - lo) / 2;
+    if (key[mid] < limit) lo = mid + 1;
+    else hi = mid;
+  }
+  *m = (uint64_t)lo;
 }
 
 }  // namespace
@@ -533,8 +799,8 @@ ce_status read_u64(const uint64_t *dev, uint64_t *host_out, int count, hipStream
   return CE_OK;
 }
 
-ce_status stage_validate(const int32_t *src, const int32_t *dst, const int64_t *t, Bufs &b, hipStream_t s,
-                         uint64_t *flags, int64_t *tmin, int64_t *tmax) {
+// Enqueues validation: error bits, min and max time into the control block.
+ce_status stage_validate(const int32_t *src, const int32_t *dst, const int64_t *t, Bufs &b, hipStream_t s) {
   CE_LAUNCH(k_init_hdr, dim3(1), dim3(64), 0, s, b.hdr);
   CE_HIP(hipGetLastError());
   if (b.n > 0) {
@@ -542,6 +808,18 @@ ce_status stage_validate(const int32_t *src, const int32_t *dst, const int64_t *
               b.hdr);
     CE_HIP(hipGetLastError());
   }
+  return CE_OK;
+}
+
+// After the plan's key width is known: a wider time span is an error as well.
+ce_status stage_check_span(Bufs &b, hipStream_t s) {
+  CE_LAUNCH(k_check_span, dim3(1), dim3(64), 0, s, b.hdr, b.n, b.tbits);
+  CE_HIP(hipGetLastError());
+  return CE_OK;
+}
+
+// The validation words (error bits, min t, max t) on the host: one read back.
+ce_status read_validation(Bufs &b, hipStream_t s, uint64_t *flags, int64_t *tmin, int64_t *tmax) {
   uint64_t h[3];
   CE_TRY(read_u64(b.hdr, h, 3, s));
   *flags = h[0];
@@ -549,8 +827,6 @@ ce_status stage_validate(const int32_t *src, const int32_t *dst, const int64_t *
   *tmax = (int64_t)(h[2] ^ (uint64_t(1) << 63));
   return CE_OK;
 }
-
-__global__ void k_set_u64(uint64_t *p, uint64_t v) { *p = v; }
 
 size_t stage_sort_skeleton_scratch(int64_t n) {
   Ws w;
@@ -574,7 +850,7 @@ ce_status sort_records_by_time(const int32_t *src, const int32_t *dst, const int
   uint4 *tval = ws.alloc<uint4>(n);
   uint4 *tval_alt = ws.alloc<uint4>(n);
   CE_WS_CHECK(ws);
-  CE_LAUNCH(k_tkeys, dim3(grid_for(n, B)), dim3(B), 0, s, t, src, dst, n, b.eoff, b.voff, b.G, b.tmin, b.ts, tval);
+  CE_LAUNCH(k_tkeys, dim3(grid_for(n, B)), dim3(B), 0, s, t, src, dst, n, b.eoff, b.voff, b.G, b.hdr, b.ts, tval);
   CE_HIP(hipGetLastError());
   bool alt = false;
   CE_TRY((radix_sort_pairs<uint64_t, uint4>(b.ts, tval, tkey_alt, tval_alt, n, 0, b.tbits, false, &alt, ws, s)));
@@ -599,7 +875,7 @@ ce_status stage_sort_skeleton(const int32_t *src, const int32_t *dst, const int6
     if (b.G == 1 && b.tbits <= 32) {
       uint64_t *kalt = ws.alloc<uint64_t>(n), *v0 = ws.alloc<uint64_t>(n), *v1 = ws.alloc<uint64_t>(n);
       CE_WS_CHECK(ws);
-      CE_LAUNCH(k_tkeys_packed, dim3(grid_for(n, B)), dim3(B), 0, s, t, src, dst, n, b.tmin, b.ts, v0);
+      CE_LAUNCH(k_tkeys_packed, dim3(grid_for(n, B)), dim3(B), 0, s, t, src, dst, n, b.hdr, b.ts, v0);
       CE_HIP(hipGetLastError());
       bool alt = false;
       CE_TRY((radix_sort_pairs<uint64_t, uint64_t>(b.ts, v0, kalt, v1, n, 32, 32 + b.tbits, false, &alt, ws, s)));
@@ -619,7 +895,7 @@ ce_status stage_sort_skeleton(const int32_t *src, const int32_t *dst, const int6
   const uint32_t *sk = alt ? ikey_alt : ikey;
   const uint32_t *sv = alt ? ival_alt : ival;
   // 3. skeleton: predecessor in the same vertex list, then packed keys
-  CE_LAUNCH(k_skel_tails, dim3(grid_for(n2, B)), dim3(B), 0, s, sk, sv, n2, b.skel_tail);
+  CE_LAUNCH(k_skel_tails, dim3(grid_for(n2, B)), dim3(B), 0, s, sk, sv, n2, b.hdr, b.skel_tail);
   CE_LAUNCH(k_fill_u64, dim3(grid_for(n, B)), dim3(B), 0, s, b.best, n, NONE64);
   CE_HIP(hipGetLastError());
   CE_LAUNCH(k_skel_keys, dim3(grid_for(n, B)), dim3(B), 0, s, b.skel_tail, b.ts, b.perm, n, b.idbits, b.skel_key,
@@ -635,8 +911,8 @@ size_t stage_boruvka_scratch(int64_t n, int64_t slots) {
   w.alloc<uint32_t>(n);      // bidx
   w.alloc<uint32_t>(n + 1);  // root flags
   w.alloc<uint32_t>(n + 1);  // dense ids
-  w.alloc<uint32_t>(n);      // active
-  w.alloc<uint32_t>(n);      // active alt
+  w.alloc<uint32_t>(n);      // final ids
+  w.alloc<uint32_t>(n);      // root map of a split
   for (int k = 0; k < 2; k++) {  // edge lists (key, u, v, slot), ping-pong
     w.alloc<uint64_t>(slots);
     w.alloc<uint32_t>(slots);
@@ -646,27 +922,9 @@ size_t stage_boruvka_scratch(int64_t n, int64_t slots) {
   return w.off + scan_ws_bytes(n + 1) + 4096;
 }
 
-static unsigned tiles_for(int64_t n) { return (unsigned)((n + (int64_t)B * CT - 1) / ((int64_t)B * CT)); }
-
-// A contraction's edge count (a u64 counter on the device) and the number of
-// components (the total of the dense-id scan, a u32): hv[0], hv[1].
-static ce_status read_count_and_total(const uint64_t *count, const uint32_t *total, uint64_t *hv, hipStream_t s) {
-  uint32_t *h = (uint32_t *)pinned_scratch();
-  if (!h) {
-    set_error("hipHostMalloc of the readback buffer failed");
-    return CE_EDEVICE;
-  }
-  // word 16 of the pinned page is ours; read_u64 uses the first 64 bytes
-  CE_HIP(hipMemcpyAsync(h + 16, total, 4, hipMemcpyDeviceToHost, s));
-  CE_TRY(read_u64(count, hv, 1, s));  // synchronises the stream
-  hv[1] = h[16];
-  return CE_OK;
-}
-
 // The filter split runs when the live edges number at least 2^20 and more
 // than twice the components. The environment variable CE_SPLIT_MIN_EDGES
 // (read on every call) overrides the 2^20; 0 turns the split off.
-constexpr int SPLIT_SAMPLES = 256;
 static int64_t split_min_edges() {
   const char *e = getenv("CE_SPLIT_MIN_EDGES");
   if (!e) return int64_t(1) << 20;
@@ -674,43 +932,15 @@ static int64_t split_min_edges() {
   return v > 0 ? (int64_t)v : INT64_MAX;
 }
 
-// Pivot of the filter split: about C edges (one per component) fall below it.
-// The key of rank ~C*S/E among S evenly spaced samples of the live list.
-// `dev` holds S keys of device scratch.
-static ce_status split_pivot(const uint64_t *key, int64_t E, int64_t C, uint64_t *dev, hipStream_t s,
-                             uint64_t *pivot) {
-  uint64_t *h = pinned_scratch();
-  if (!h) {
-    set_error("hipHostMalloc of the readback buffer failed");
-    return CE_EDEVICE;
-  }
-  uint64_t *hs = h + 128;  // bytes 1024 .. 3071 of the page
-  CE_LAUNCH(k_sample_keys, dim3(1), dim3(B), 0, s, E, key, SPLIT_SAMPLES, dev);
-  CE_HIP(hipGetLastError());
-  CE_HIP(hipMemcpyAsync(hs, dev, sizeof(uint64_t) * SPLIT_SAMPLES, hipMemcpyDeviceToHost, s));
-  CE_HIP(hipStreamSynchronize(s));
-  std::sort(hs, hs + SPLIT_SAMPLES);
-  int64_t q = (int64_t)((unsigned __int128)SPLIT_SAMPLES * (uint64_t)C / (uint64_t)E);
-  if (q > SPLIT_SAMPLES - 1) q = SPLIT_SAMPLES - 1;
-  *pivot = hs[q];
-  return CE_OK;
-}
-
-// pointer jumping until every hooked component points at its final root
-static ce_status jump_all(uint32_t *&act, uint32_t *&act2, uint64_t nact, uint32_t *hook, Bufs &b, hipStream_t s) {
-  for (int it = 0; nact > 0; it++) {
-    if (it > 64) {
-      set_error("Boruvka pointer jumping did not converge");
-      return CE_EDEVICE;
-    }
-    CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[5], (uint64_t)0);
-    CE_LAUNCH(k_bv_jump, dim3(tiles_for((int64_t)nact)), dim3(B), 0, s, act, (int64_t)nact, hook, act2,
-              (unsigned long long *)&b.hdr[5]);
-    CE_HIP(hipGetLastError());
-    CE_TRY(read_u64(&b.hdr[5], &nact, 1, s));
-    uint32_t *t = act; act = act2; act2 = t;
-  }
-  return CE_OK;
+// Rounds the host enqueues after the first: in every round the components
+// that still have live edges at least halve, so bits(n) + 1 rounds end a run
+// of plain rounds. With the (single) split, plain rounds before it and the
+// light rounds together halve the components at least once per round, and so
+// do the light rounds and the plain rounds after them: 2 (bits(n) + 1) + 1
+// rounds cover both.
+int boruvka_rounds(int64_t n, bool split_possible) {
+  const int r = bits_for((uint64_t)n) + 1;
+  return split_possible ? 2 * r + 1 : r;
 }
 
 ce_status stage_boruvka(Bufs &b, Ws &ws, hipStream_t s) {
@@ -720,67 +950,43 @@ ce_status stage_boruvka(Bufs &b, Ws &ws, hipStream_t s) {
   uint32_t *bidx = ws.alloc<uint32_t>(n);
   uint32_t *flags = ws.alloc<uint32_t>(n + 1);
   uint32_t *newid = ws.alloc<uint32_t>(n + 1);
-  uint32_t *act = ws.alloc<uint32_t>(n);
-  uint32_t *act2 = ws.alloc<uint32_t>(n);
-  uint64_t *key[2];
-  uint32_t *eu[2], *ev[2], *es[2];
+  uint32_t *fin = ws.alloc<uint32_t>(n);
+  uint32_t *rootof = ws.alloc<uint32_t>(n);
+  EdgeLists L;
   for (int k = 0; k < 2; k++) {
-    key[k] = ws.alloc<uint64_t>(n2);
-    eu[k] = ws.alloc<uint32_t>(n2);
-    ev[k] = ws.alloc<uint32_t>(n2);
-    es[k] = ws.alloc<uint32_t>(n2);
+    L.key[k] = ws.alloc<uint64_t>(n2);
+    L.u[k] = ws.alloc<uint32_t>(n2);
+    L.v[k] = ws.alloc<uint32_t>(n2);
+    L.s[k] = ws.alloc<uint32_t>(n2);
   }
   CE_WS_CHECK(ws);
+  L.key[2] = b.skel_key;
+  L.u[2] = b.skel_tail;
+  L.v[2] = b.skel_tid;
+  L.s[2] = nullptr;
+  L.cap = n2;
+  uint64_t *bv = b.hdr + H_BV;
   uint32_t *rankof = b.rankof;  // kept for writing the per-record outputs in input order
   CE_LAUNCH(k_rankof, dim3(grid_for(n, B)), dim3(B), 0, s, b.perm, n, rankof);
-  uint64_t *best = b.best;  // seeded for round 1 while the skeleton was emitted
-  unsigned long long *cnt = (unsigned long long *)&b.hdr[4];
+  uint64_t *best = b.best;  // seeded for the first round while the skeleton was emitted
   CE_LAUNCH(k_fill_u8, dim3(grid_for(n2, B)), dim3(B), 0, s, b.msf_flag, n2, (uint8_t)0);
-  int64_t E = 0, C = 0;
-  int rounds = 0;
-  uint64_t nact = 0;
-  uint64_t hv[2];
-  // live edges of the current round (input) and the buffer the contraction writes
-  const uint64_t *ik = key[0];
-  const uint32_t *iu = eu[0], *iv = ev[0], *is = es[0];
-  int ob = 1;
-  bool seeded = false;
+  const unsigned gN = grid_cap(n, B), gE = grid_cap(n2, B), tE = grid_cap(n2, B * CT, 4096);
   if (b.flat) {
     // causal and hypergraph skeleton rows can share a head, so every round,
     // the first included, runs on the edge-list form with records as
     // components; the first reads the skeleton rows in place (slot = row)
-    ik = b.skel_key;
-    iu = b.skel_tail;
-    iv = b.skel_tid;
-    is = nullptr;
-    ob = 0;
-    seeded = true;
-    E = b.S;
-    C = n;
+    CE_LAUNCH(k_bv_flat_init, dim3(1), dim3(64), 0, s, bv, &b.hdr[H_C7], n);
   } else {
-    // round 1 on records
-    CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[4], (uint64_t)0);
-    CE_LAUNCH(k_bv_hook_first, dim3(tiles_for(n)), dim3(B), 0, s, n, best, b.skel_key, b.skel_tail, rankof,
-              b.idbits, hook, b.msf_flag, act, cnt);
+    // first round on records, then its contraction into list 0
+    CE_LAUNCH(k_bv_hook_first, dim3(gN), dim3(B), 0, s, n, best, b.skel_key, b.skel_tail, rankof, b.idbits, hook,
+              b.msf_flag, flags);
+    CE_LAUNCH(k_bv_compress, dim3(gN), dim3(B), 0, s, Cnt(n), hook, b.hdr);
+    CE_LAUNCH(k_bv_roots, dim3(gN), dim3(B), 0, s, Cnt(n), hook, b.hdr);
     CE_HIP(hipGetLastError());
-    CE_TRY(read_u64(&b.hdr[4], &nact, 1, s));
-    CE_TRY(jump_all(act, act2, nact, hook, b, s));
-    CE_LAUNCH(k_root_flags, dim3(grid_for(n, B)), dim3(B), 0, s, n, hook, best, flags);
+    CE_TRY(scan_exclusive_u32(flags, newid, Cnt(n), ws, s));
+    CE_LAUNCH(k_final_ids, dim3(gN), dim3(B), 0, s, Cnt(n), hook, newid, fin, best);
+    CE_LAUNCH(k_contract_first, dim3(tE), dim3(B), 0, s, n, b.skel_key, b.skel_tail, fin, newid, L, bv);
     CE_HIP(hipGetLastError());
-    CE_TRY(scan_exclusive_u32(flags, newid, n, ws, s));
-    CE_LAUNCH(k_final_ids, dim3(grid_for(n, B)), dim3(B), 0, s, n, hook, newid, flags);
-    CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[4], (uint64_t)0);
-    CE_LAUNCH(k_contract_first, dim3(tiles_for(n2)), dim3(B), 0, s, n2, b.skel_key, b.skel_tail, flags,
-              key[0], eu[0], ev[0], es[0], cnt);
-    CE_HIP(hipGetLastError());
-    CE_TRY(read_count_and_total(&b.hdr[4], newid + n, hv, s));
-    E = (int64_t)hv[0];
-    C = (int64_t)hv[1];
-    if (E > n2 || C > n) {
-      set_error("internal: contracted graph larger than its input");
-      return CE_EDEVICE;
-    }
-    rounds = 1;
   }
   // Filter split. When live edges far outnumber components, most of them run
   // between components that later rounds merge anyway, and every round would
@@ -790,151 +996,53 @@ ce_status stage_boruvka(Bufs &b, Ws &ws, hipStream_t s) {
   // unique, so the forest is the same: a light edge outside the light forest
   // is the largest on a cycle of light edges, and contracting the light forest
   // keeps every heavy edge's cycles. During the light phase components keep
-  // the ids they had at the split (no renumbering) and rootof, in newid, maps
-  // each of them to its current root; the heavy edges wait at the back of the
-  // output lists of buffer hb.
+  // the ids they had at the split (no renumbering) and rootof maps each of
+  // them to its current root; the heavy edges wait at the back of the buffer
+  // the split wrote.
   const int64_t split_min = split_min_edges();
-  bool light = false, first_light = false;
-  int hb = 0;
-  int64_t Eh = 0;
-  uint32_t *rootof = newid;
-  while (E > 0) {
-    // (bidx, n words, holds the pivot samples)
-    if (!light && !seeded && E >= split_min && E > 2 * C && n * 4 >= SPLIT_SAMPLES * 8) {
-      uint64_t pivot = 0;
-      CE_TRY(split_pivot(ik, E, C, (uint64_t *)bidx, s, &pivot));
-      CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[4], (uint64_t)0);
-      CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[5], (uint64_t)0);
-      CE_LAUNCH(k_split, dim3(tiles_for(E)), dim3(B), 0, s, E, ik, iu, iv, is, pivot, n2, key[ob], eu[ob], ev[ob],
-                es[ob], cnt, (unsigned long long *)&b.hdr[5]);
-      CE_HIP(hipGetLastError());
-      CE_TRY(read_u64(&b.hdr[4], hv, 2, s));
-      if ((int64_t)(hv[0] + hv[1]) != E) {
-        set_error("internal: filter split lost edges");
-        return CE_EDEVICE;
-      }
-      const int64_t El = (int64_t)hv[0];
-      Eh = (int64_t)hv[1];
-      const int64_t off = El > 0 ? 0 : n2 - Eh;  // no light edge: the heavy ones are the whole list
-      ik = key[ob] + off;
-      iu = eu[ob] + off;
-      iv = ev[ob] + off;
-      is = es[ob] + off;
-      if (El > 0) {
-        light = first_light = true;
-        hb = ob;
-        E = El;
-      }
-      ob = 1 - ob;
+  const bool split_possible = n2 >= split_min;
+  const int rounds = boruvka_rounds(n, split_possible);
+  const Cnt CG(&bv[BV_CG], n), CN(&bv[BV_CN], n), CL(&bv[BV_CL], n);
+  for (int r = 0; r < rounds; r++) {
+    if (split_possible) {
+      CE_LAUNCH(k_split_prep, dim3(1), dim3(SPLIT_SAMPLES), 0, s, L, bv, split_min);
+      CE_LAUNCH(k_split, dim3(tE), dim3(B), 0, s, L, bv);
     }
-    if (++rounds > 64) {
-      set_error("Boruvka did not converge");
-      return CE_EDEVICE;
-    }
-    if (!seeded) {
-      CE_LAUNCH(k_fill_u64, dim3(grid_for(C, B)), dim3(B), 0, s, best, C, NONE64);
-      CE_LAUNCH(k_bv_min, dim3(tiles_for(E)), dim3(B), 0, s, E, ik, iu, iv, best);
-    }
-    seeded = false;
-    CE_LAUNCH(k_bv_pick, dim3(grid_for(E, B)), dim3(B), 0, s, E, ik, iu, iv, best, bidx);
-    CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[4], (uint64_t)0);
-    CE_LAUNCH(k_bv_hook, dim3(tiles_for(C)), dim3(B), 0, s, C, best, bidx, iu, iv, is, hook, b.msf_flag, act, cnt);
+    CE_LAUNCH(k_bv_min, dim3(tE), dim3(B), 0, s, L, bv, best);
+    CE_LAUNCH(k_bv_pick, dim3(gE), dim3(B), 0, s, L, bv, best, bidx);
+    CE_LAUNCH(k_bv_hook, dim3(gN), dim3(B), 0, s, L, bv, best, bidx, hook, b.msf_flag, flags);
+    CE_LAUNCH(k_bv_compress, dim3(gN), dim3(B), 0, s, CG, hook, b.hdr);
+    CE_LAUNCH(k_bv_roots, dim3(gN), dim3(B), 0, s, CG, hook, b.hdr);
     CE_HIP(hipGetLastError());
-    CE_TRY(read_u64(&b.hdr[4], &nact, 1, s));
-    CE_TRY(jump_all(act, act2, nact, hook, b, s));
-    if (light) {
-      // ids stay; the edges' endpoints are this round's roots, hook gives their new ones
-      CE_LAUNCH(k_compose_roots, dim3(grid_for(C, B)), dim3(B), 0, s, C, hook, rootof, first_light);
-      first_light = false;
-      CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[4], (uint64_t)0);
-      CE_LAUNCH(k_contract, dim3(tiles_for(E)), dim3(B), 0, s, E, ik, iu, iv, is, hook, key[ob], eu[ob], ev[ob],
-                es[ob], cnt);
-      CE_HIP(hipGetLastError());
-      CE_TRY(read_u64(&b.hdr[4], hv, 1, s));
-      if ((int64_t)hv[0] > E) {
-        set_error("internal: contracted graph larger than its input");
-        return CE_EDEVICE;
-      }
-      E = (int64_t)hv[0];
-    } else {
-      CE_LAUNCH(k_root_flags, dim3(grid_for(C, B)), dim3(B), 0, s, C, hook, best, flags);
-      CE_HIP(hipGetLastError());
-      CE_TRY(scan_exclusive_u32(flags, newid, C, ws, s));
-      CE_LAUNCH(k_final_ids, dim3(grid_for(C, B)), dim3(B), 0, s, C, hook, newid, flags);
-      CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[4], (uint64_t)0);
-      CE_LAUNCH(k_contract, dim3(tiles_for(E)), dim3(B), 0, s, E, ik, iu, iv, is, flags, key[ob], eu[ob], ev[ob],
-                es[ob], cnt);
-      CE_HIP(hipGetLastError());
-      CE_TRY(read_count_and_total(&b.hdr[4], newid + C, hv, s));
-      if ((int64_t)hv[0] > E || (int64_t)hv[1] > C) {
-        set_error("internal: contracted graph larger than its input");
-        return CE_EDEVICE;
-      }
-      E = (int64_t)hv[0];
-      C = (int64_t)hv[1];
+    if (split_possible) {
+      // light round: ids stay; the edges' endpoints are this round's roots, hook gives their new ones
+      CE_LAUNCH(k_compose_roots, dim3(gN), dim3(B), 0, s, CL, bv, hook, rootof, best);
+      CE_LAUNCH(k_contract, dim3(tE), dim3(B), 0, s, L, bv, &bv[BV_EL], hook, newid, 1);
     }
-    ik = key[ob];
-    iu = eu[ob];
-    iv = ev[ob];
-    is = es[ob];
-    ob = 1 - ob;
-    if (light && E == 0) {
-      // light phase done: the heavy edges between different current roots
-      // go on (ids of the split, not renumbered; the next round renumbers)
-      const int64_t off = n2 - Eh;
-      const int to = 1 - hb;
-      CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[4], (uint64_t)0);
-      CE_LAUNCH(k_contract, dim3(tiles_for(Eh)), dim3(B), 0, s, Eh, key[hb] + off, eu[hb] + off, ev[hb] + off,
-                es[hb] + off, rootof, key[to], eu[to], ev[to], es[to], cnt);
-      CE_HIP(hipGetLastError());
-      CE_TRY(read_u64(&b.hdr[4], hv, 1, s));
-      if ((int64_t)hv[0] > Eh) {
-        set_error("internal: contracted graph larger than its input");
-        return CE_EDEVICE;
-      }
-      E = (int64_t)hv[0];
-      ik = key[to];
-      iu = eu[to];
-      iv = ev[to];
-      is = es[to];
-      ob = hb;
-      light = false;
-    }
+    // plain round: dense ids for the surviving roots, then the contraction
+    CE_TRY(scan_exclusive_u32(flags, newid, CN, ws, s));
+    CE_LAUNCH(k_final_ids, dim3(gN), dim3(B), 0, s, CN, hook, newid, fin, best);
+    CE_LAUNCH(k_contract, dim3(tE), dim3(B), 0, s, L, bv, &bv[BV_EN], fin, newid, 0);
+    if (split_possible)  // after the light phase: the heavy edges between different current roots
+      CE_LAUNCH(k_contract, dim3(tE), dim3(B), 0, s, L, bv, &bv[BV_EHG], rootof, newid, 2);
+    CE_HIP(hipGetLastError());
   }
+  CE_LAUNCH(k_bv_check, dim3(1), dim3(64), 0, s, bv, b.hdr);
+  CE_HIP(hipGetLastError());
   ws.release(m0);
   return CE_OK;
-}
-
-// rows with key < limit (rows are sorted, so they are a prefix): one binary search
-__global__ void k_prefix_below(const uint64_t *key, int64_t m, uint64_t limit, uint64_t *out) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
-  int64_t lo = 0, hi = m;
-  while (lo < hi) {
-    const int64_t mid = lo + (hi - lo) / 2;
-    if (key[mid] < limit) lo = mid + 1;
-    else hi = mid;
-  }
-  *out = (uint64_t)lo;
 }
 
 // Time-filtered line graph (Sec. 5.1): only edges with w <= max_dt. The
 // filtered skeleton has the filtered line graph's components at every
 // threshold up to max_dt (Thm 3), and Kruskal takes edges in key order, so
 // its forest is the prefix of the sorted MSF with w <= max_dt.
-ce_status stage_time_filter(Bufs &b, int64_t max_dt, hipStream_t s, int64_t *m) {
-  if (*m <= 0 || max_dt < 0) return CE_OK;
+ce_status stage_time_filter(Bufs &b, int64_t max_dt, hipStream_t s) {
+  if (max_dt < 0) return CE_OK;
   const unsigned __int128 lim = ((unsigned __int128)max_dt + 1) << b.wshift;
   if (lim > (unsigned __int128)NONE64) return CE_OK;  // every key is below it: no row is longer
-  const uint64_t limit = (uint64_t)lim;
-  CE_LAUNCH(k_prefix_below, dim3(1), dim3(64), 0, s, b.msf_key, *m, limit, &b.hdr[6]);
+  CE_LAUNCH(k_prefix_below, dim3(1), dim3(64), 0, s, b.msf_key, &b.hdr[H_M], (uint64_t)lim);
   CE_HIP(hipGetLastError());
-  uint64_t k = 0;
-  CE_TRY(read_u64(&b.hdr[6], &k, 1, s));
-  if ((int64_t)k > *m) {
-    set_error("internal: time filter");
-    return CE_EDEVICE;
-  }
-  *m = (int64_t)k;
   return CE_OK;
 }
 
@@ -946,42 +1054,38 @@ size_t stage_msf_sort_scratch(int64_t n) {
   return w.off + radix_ws_bytes(n) + 4096;
 }
 
-ce_status stage_msf_sort(Bufs &b, Ws &ws, hipStream_t s, int64_t *m_out) {
+// The forest's rows (m on the device, at most n - 1) sorted by key into
+// msf_key / msf_val.
+ce_status stage_msf_sort(Bufs &b, Ws &ws, hipStream_t s) {
   const int64_t n = b.n, n2 = b.slots;
   size_t m0 = ws.mark();
   uint64_t *key_alt = ws.alloc<uint64_t>(n);
   uint64_t *val_alt = ws.alloc<uint64_t>(n);
   uint32_t *list = ws.alloc<uint32_t>(n);
   CE_WS_CHECK(ws);
-  CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[6], (uint64_t)0);
-  CE_LAUNCH(k_msf_list, dim3(tiles_for(n2)), dim3(B), 0, s, b.msf_flag, n2, list,
-                     (unsigned long long *)&b.hdr[6]);
+  CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[H_M], (uint64_t)0);
+  CE_LAUNCH(k_msf_list, dim3(grid_cap(n2, B * CT, 4096)), dim3(B), 0, s, b.msf_flag, n2, list,
+            (unsigned long long *)&b.hdr[H_M]);
+  CE_LAUNCH(k_check_rows, dim3(1), dim3(64), 0, s, b.hdr, n);
   CE_HIP(hipGetLastError());
-  uint64_t m = 0;
-  CE_TRY(read_u64(&b.hdr[6], &m, 1, s));
-  if ((int64_t)m > n - 1) {
-    set_error("spanning forest larger than n-1");
-    return CE_EDEVICE;
-  }
+  const Cnt m(&b.hdr[H_M], n > 1 ? n - 1 : 1);
   // gather into the buffer pair from which an odd or even number of radix
   // passes ends in msf_key / msf_val, so no copy follows the sort
   const int passes = b.keybits > 8 ? (b.keybits + 7) / 8 : 1;
   uint64_t *gk = (passes & 1) ? key_alt : b.msf_key, *gv = (passes & 1) ? val_alt : b.msf_val;
   uint64_t *ok = (passes & 1) ? b.msf_key : key_alt, *ov = (passes & 1) ? b.msf_val : val_alt;
-  if (m > 0 && b.flat)
-    CE_LAUNCH(k_msf_gather_causal, dim3(grid_for((int64_t)m, B)), dim3(B), 0, s, list, (int64_t)m, b.skel_key,
-              b.skel_tail, b.skel_tid, gk, gv);
-  else if (m > 0)
-    CE_LAUNCH(k_msf_gather, dim3(grid_for((int64_t)m, B)), dim3(B), 0, s, list, (int64_t)m, b.skel_key,
-              b.skel_tail, gk, gv);
+  if (b.flat)
+    CE_LAUNCH(k_msf_gather_causal, dim3(grid_cap(m.v, B)), dim3(B), 0, s, list, m, b.skel_key, b.skel_tail,
+              b.skel_tid, gk, gv);
+  else
+    CE_LAUNCH(k_msf_gather, dim3(grid_cap(m.v, B)), dim3(B), 0, s, list, m, b.skel_key, b.skel_tail, gk, gv);
   bool alt = false;
-  CE_TRY((radix_sort_pairs<uint64_t, uint64_t>(gk, gv, ok, ov, (int64_t)m, 0, b.keybits, false, &alt, ws, s)));
-  if (m > 0 && (alt ? ok : gk) != b.msf_key) {  // (not reached: the pass count is as computed)
-    CE_HIP(hipMemcpyAsync(b.msf_key, alt ? ok : gk, sizeof(uint64_t) * m, hipMemcpyDeviceToDevice, s));
-    CE_HIP(hipMemcpyAsync(b.msf_val, alt ? ov : gv, sizeof(uint64_t) * m, hipMemcpyDeviceToDevice, s));
+  CE_TRY((radix_sort_pairs<uint64_t, uint64_t>(gk, gv, ok, ov, m, 0, b.keybits, false, &alt, ws, s)));
+  if ((alt ? ok : gk) != b.msf_key) {  // (not reached: the pass count is as computed)
+    set_error("internal: sorted forest is not in place");
+    return CE_EDEVICE;
   }
   ws.release(m0);
-  *m_out = (int64_t)m;
   return CE_OK;
 }
 

@@ -42,8 +42,9 @@ __device__ inline uint32_t block_excl_scan(uint32_t x, uint32_t *lds_w /*[4]*/, 
   return before + inc - x;
 }
 
-__global__ __launch_bounds__(SB) void k_scan_reduce(const uint32_t *in, int64_t n, uint32_t *sums) {
+__global__ __launch_bounds__(SB) void k_scan_reduce(const uint32_t *in, Cnt nc, uint32_t *sums) {
   __shared__ uint32_t lw[SB / 64];
+  const int64_t n = nc.get();
   int64_t base = (int64_t)blockIdx.x * STILE + (int64_t)threadIdx.x * SIPT;
   uint32_t acc = 0;
 #pragma unroll
@@ -54,9 +55,15 @@ __global__ __launch_bounds__(SB) void k_scan_reduce(const uint32_t *in, int64_t 
   if (threadIdx.x == 0) sums[blockIdx.x] = tot;
 }
 
-__global__ __launch_bounds__(SB) void k_scan_apply(const uint32_t *in, uint32_t *out, int64_t n,
+__global__ __launch_bounds__(SB) void k_scan_apply(const uint32_t *in, uint32_t *out, Cnt nc,
                                                    const uint32_t *sums_scanned) {
   __shared__ uint32_t lw[SB / 64];
+  const int64_t n = nc.get();
+  // blocks past a device count have nothing to write; the total (out[n]) is block 0's
+  if ((int64_t)blockIdx.x * STILE >= n) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = sums_scanned[gridDim.x];
+    return;
+  }
   int64_t base = (int64_t)blockIdx.x * STILE + (int64_t)threadIdx.x * SIPT;
   uint32_t v[SIPT];
   uint32_t acc = 0;
@@ -71,12 +78,13 @@ __global__ __launch_bounds__(SB) void k_scan_apply(const uint32_t *in, uint32_t 
     if (base + k < n) out[base + k] = run;
     run += v[k];
   }
-  if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = sums_scanned[gridDim.x];
+  if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = sums_scanned[gridDim.x];
 }
 
 // single-block exclusive scan for up to STILE elements; out[n] = total
-__global__ __launch_bounds__(SB) void k_scan_small(const uint32_t *in, uint32_t *out, int64_t n) {
+__global__ __launch_bounds__(SB) void k_scan_small(const uint32_t *in, uint32_t *out, Cnt nc) {
   __shared__ uint32_t lw[SB / 64];
+  const int64_t n = nc.get();
   int64_t base = (int64_t)threadIdx.x * SIPT;
   uint32_t v[SIPT];
   uint32_t acc = 0;
@@ -107,20 +115,21 @@ size_t scan_ws_bytes(int64_t n) {
   return b + 512;
 }
 
-ce_status scan_exclusive_u32(const uint32_t *in, uint32_t *out, int64_t n, Ws &ws, hipStream_t s) {
-  if (n <= STILE) {
+ce_status scan_exclusive_u32(const uint32_t *in, uint32_t *out, Cnt n, Ws &ws, hipStream_t s) {
+  if (n.v <= STILE) {
     CE_LAUNCH(k_scan_small, dim3(1), dim3(SB), 0, s, in, out, n);
     CE_HIP(hipGetLastError());
     return CE_OK;
   }
-  int64_t nb = (n + STILE - 1) / STILE;
+  // the block sums are laid out for the capacity; blocks past a device count contribute zeros
+  int64_t nb = (n.v + STILE - 1) / STILE;
   size_t m = ws.mark();
   uint32_t *sums = ws.alloc<uint32_t>(nb + 1);
   uint32_t *sums_sc = ws.alloc<uint32_t>(nb + 1);
   CE_WS_CHECK(ws);
   CE_LAUNCH(k_scan_reduce, dim3((unsigned)nb), dim3(SB), 0, s, in, n, sums);
   CE_HIP(hipGetLastError());
-  CE_TRY(scan_exclusive_u32(sums, sums_sc, nb, ws, s));
+  CE_TRY(scan_exclusive_u32(sums, sums_sc, Cnt(nb), ws, s));
   CE_LAUNCH(k_scan_apply, dim3((unsigned)nb), dim3(SB), 0, s, in, out, n, sums_sc);
   CE_HIP(hipGetLastError());
   ws.release(m);
@@ -132,7 +141,8 @@ namespace {
 
 // off[g] = first position p with key[p] >= g, for g in [0, G]; each of the
 // n+1 gaps between neighbouring keys writes the offsets that fall in it
-__global__ __launch_bounds__(256) void k_seg_bounds(const uint32_t *key, int64_t n, int64_t G, uint32_t *off) {
+__global__ __launch_bounds__(256) void k_seg_bounds(const uint32_t *key, Cnt nc, Cnt gc, uint32_t *off) {
+  const int64_t n = nc.get(), G = gc.get();
   for (int64_t p = (int64_t)blockIdx.x * 256 + threadIdx.x; p <= n; p += (int64_t)gridDim.x * 256) {
     const int64_t lo = p == 0 ? 0 : (int64_t)key[p - 1] + 1;
     const int64_t hi = p == n ? G : (int64_t)key[p];
@@ -142,8 +152,8 @@ __global__ __launch_bounds__(256) void k_seg_bounds(const uint32_t *key, int64_t
 
 }  // namespace
 
-ce_status segment_bounds_u32(const uint32_t *sorted_keys, int64_t n, int64_t G, uint32_t *off, hipStream_t s) {
-  CE_LAUNCH(k_seg_bounds, dim3(grid_for(n + 1, 256)), dim3(256), 0, s, sorted_keys, n, G, off);
+ce_status segment_bounds_u32(const uint32_t *sorted_keys, Cnt n, Cnt G, uint32_t *off, hipStream_t s) {
+  CE_LAUNCH(k_seg_bounds, dim3(grid_cap(n.v + 1, 256)), dim3(256), 0, s, sorted_keys, n, G, off);
   CE_HIP(hipGetLastError());
   return CE_OK;
 }
@@ -158,9 +168,10 @@ constexpr int RTILE = RB * RIPT;     // 2048 keys per tile
 constexpr int RWT = RTILE / RW;      // 512 keys per wave (8 chunks of 64)
 
 template <class K>
-__global__ __launch_bounds__(RB) void k_rs_hist(const K *keys, int64_t n, int shift, uint32_t *hist,
+__global__ __launch_bounds__(RB) void k_rs_hist(const K *keys, Cnt nc, int shift, uint32_t *hist,
                                                 int nblocks) {
   __shared__ uint32_t cnt[RW][256];
+  const int64_t n = nc.get();  // tiles past a device count write zero counts
   const int w = threadIdx.x >> 6;
   for (int i = threadIdx.x; i < RW * 256; i += RB) (&cnt[0][0])[i] = 0;
   __syncthreads();
@@ -185,8 +196,10 @@ template <>
 __device__ inline uint4 iota_value<uint4>(int64_t i) { return make_uint4((uint32_t)i, 0u, 0u, 0u); }
 
 template <class K, class V>
-__global__ __launch_bounds__(RB) void k_rs_scatter(const K *kin, const V *vin, K *kout, V *vout, int64_t n,
+__global__ __launch_bounds__(RB) void k_rs_scatter(const K *kin, const V *vin, K *kout, V *vout, Cnt nc,
                                                    int shift, const uint32_t *hscan, int nblocks, int iota) {
+  const int64_t n = nc.get();
+  if ((int64_t)blockIdx.x * RTILE >= n) return;
   __shared__ uint32_t wcnt[RW][256];
   __shared__ uint32_t dbase[256];
   __shared__ uint32_t lw[RB / 64];
@@ -271,11 +284,11 @@ size_t radix_ws_bytes(int64_t n) {
 }
 
 template <class K, class V>
-ce_status radix_sort_pairs(K *k0, V *v0, K *k1, V *v1, int64_t n, int begin_bit, int end_bit, bool iota_values,
+ce_status radix_sort_pairs(K *k0, V *v0, K *k1, V *v1, Cnt n, int begin_bit, int end_bit, bool iota_values,
                            bool *result_in_alt, Ws &ws, hipStream_t s) {
   *result_in_alt = false;
-  if (n <= 0) return CE_OK;
-  const int64_t nb64 = (n + RTILE - 1) / RTILE;
+  if (n.v <= 0) return CE_OK;
+  const int64_t nb64 = (n.v + RTILE - 1) / RTILE;
   if (nb64 > 0x7fffffff) return CE_EINVAL;
   const int nb = (int)nb64;
   size_t m = ws.mark();
@@ -290,7 +303,7 @@ ce_status radix_sort_pairs(K *k0, V *v0, K *k1, V *v1, int64_t n, int begin_bit,
   for (int shift = begin_bit; shift < end_bit; shift += 8) {
     CE_LAUNCH((k_rs_hist<K>), dim3((unsigned)nb), dim3(RB), 0, s, ki, n, shift, hist, nb);
     CE_HIP(hipGetLastError());
-    CE_TRY(scan_exclusive_u32(hist, hsc, (int64_t)nb * 256, ws, s));
+    CE_TRY(scan_exclusive_u32(hist, hsc, Cnt((int64_t)nb * 256), ws, s));
     CE_LAUNCH((k_rs_scatter<K, V>), dim3((unsigned)nb), dim3(RB), 0, s, ki, (const V *)vi, ko, vo, n,
                        shift, hsc, nb, (first && iota_values) ? 1 : 0);
     CE_HIP(hipGetLastError());
@@ -304,13 +317,13 @@ ce_status radix_sort_pairs(K *k0, V *v0, K *k1, V *v1, int64_t n, int begin_bit,
   return CE_OK;
 }
 
-template ce_status radix_sort_pairs<uint64_t, uint32_t>(uint64_t *, uint32_t *, uint64_t *, uint32_t *, int64_t,
-                                                        int, int, bool, bool *, Ws &, hipStream_t);
-template ce_status radix_sort_pairs<uint32_t, uint32_t>(uint32_t *, uint32_t *, uint32_t *, uint32_t *, int64_t,
-                                                        int, int, bool, bool *, Ws &, hipStream_t);
-template ce_status radix_sort_pairs<uint64_t, uint4>(uint64_t *, uint4 *, uint64_t *, uint4 *, int64_t, int, int,
+template ce_status radix_sort_pairs<uint64_t, uint32_t>(uint64_t *, uint32_t *, uint64_t *, uint32_t *, Cnt, int,
+                                                        int, bool, bool *, Ws &, hipStream_t);
+template ce_status radix_sort_pairs<uint32_t, uint32_t>(uint32_t *, uint32_t *, uint32_t *, uint32_t *, Cnt, int,
+                                                        int, bool, bool *, Ws &, hipStream_t);
+template ce_status radix_sort_pairs<uint64_t, uint4>(uint64_t *, uint4 *, uint64_t *, uint4 *, Cnt, int, int,
                                                      bool, bool *, Ws &, hipStream_t);
-template ce_status radix_sort_pairs<uint64_t, uint64_t>(uint64_t *, uint64_t *, uint64_t *, uint64_t *, int64_t,
-                                                        int, int, bool, bool *, Ws &, hipStream_t);
+template ce_status radix_sort_pairs<uint64_t, uint64_t>(uint64_t *, uint64_t *, uint64_t *, uint64_t *, Cnt, int,
+                                                        int, bool, bool *, Ws &, hipStream_t);
 
 }  // namespace ce
