@@ -114,12 +114,16 @@ inline unsigned grid_for(int64_t work, int block, int64_t cap = 1 << 20) {
 // of the same call wrote to device memory (p, read when a kernel starts; v is
 // then an upper bound that sizes grids). Data-dependent sizes travel this way,
 // so a call enqueues its whole pipeline without reading anything back.
+// With sh > 0 the size is ceil(*p / 2^sh) (the tiles of a device count).
 struct Cnt {
   const uint64_t *p;
   int64_t v;
-  __host__ __device__ Cnt(int64_t x = 0) : p(nullptr), v(x) {}
-  __host__ __device__ Cnt(const uint64_t *q, int64_t bound) : p(q), v(bound) {}
-  __device__ inline int64_t get() const { return p ? (int64_t)*p : v; }
+  int sh;
+  __host__ __device__ Cnt(int64_t x = 0) : p(nullptr), v(x), sh(0) {}
+  __host__ __device__ Cnt(const uint64_t *q, int64_t bound, int shift = 0) : p(q), v(bound), sh(shift) {}
+  __device__ inline int64_t get() const {
+    return p ? (int64_t)((*p + ((uint64_t(1) << sh) - 1)) >> sh) : v;
+  }
 };
 
 // Blocks for a grid-stride loop over at most `bound` items: the whole chip is

@@ -108,30 +108,54 @@ __global__ __launch_bounds__(B) void k_dd_top_init(const uint32_t *kpar, const u
     top[j] = (p != NONE32 && level[p - n] == level[j]) ? p : (uint32_t)(n + j);
   }
 }
-// Every row to its level top, in place: a walk over same-level parents, each
-// row storing into its own entry only. Pointers only ever move to higher rows
-// of the same level, so whatever another walk reads is still on the way.
-// A walk longer than any tree allows marks the call failed and stops.
-constexpr uint32_t MAX_WALK = 1u << 26;
-// Rows are taken from the last one down, so a row's parents (higher rows) are
-// mostly done when it walks, and each row stores into its own entry only.
-__global__ __launch_bounds__(B) void k_dd_top_chase(Cnt mc, int64_t n, uint32_t *top, uint64_t *hdr) {
+// rows whose level top is not known yet (their pointer is not a top)
+__global__ __launch_bounds__(B) void k_dd_top_active(const uint32_t *top, Cnt mc, int64_t n, uint32_t *act,
+                                                     unsigned long long *nact) {
   const int64_t m = mc.get();
-  for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < m; i += (int64_t)gridDim.x * B) {
-    const int64_t j = m - 1 - i;
-    uint32_t x = top[j];
-    if (x == (uint32_t)(n + j)) continue;
-    for (uint32_t steps = 0;; steps++) {
-      const uint32_t t = __hip_atomic_load(&top[x - n], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      if (t == x) break;
-      if (steps > MAX_WALK) {
-        atomicOr((unsigned long long *)&hdr[H_STATUS], 32ull);
-        break;
-      }
-      __hip_atomic_store(&top[j], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      x = t;
+  for (int64_t tile = blockIdx.x; tile * (B * CT) < m; tile += gridDim.x) {
+    bool keep[CT];
+    uint32_t vals[CT];
+    const int64_t base = tile * (B * CT) + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < CT; k++) {
+      const int64_t j = base + (int64_t)k * B;
+      keep[k] = false;
+      vals[k] = (uint32_t)j;
+      if (j >= m) continue;
+      const uint32_t t = top[j];
+      keep[k] = t != (uint32_t)(n + j) && top[t - n] != t;
     }
+    tile_append(keep, vals, act, nact);
   }
+}
+// one pointer-doubling round over the active rows, in place: a row only reads
+// pointers of rows above it, which stay valid ancestors of the same level
+__global__ __launch_bounds__(B) void k_dd_top_jump(const uint32_t *act, const uint64_t *nact_in, int64_t n,
+                                                   uint32_t *top, uint32_t *next, unsigned long long *nnext) {
+  const int64_t nact = (int64_t)*nact_in;
+  for (int64_t tile = blockIdx.x; tile * (B * CT) < nact; tile += gridDim.x) {
+    bool keep[CT];
+    uint32_t vals[CT];
+    const int64_t base = tile * (B * CT) + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < CT; k++) {
+      const int64_t i = base + (int64_t)k * B;
+      keep[k] = false;
+      vals[k] = 0;
+      if (i >= nact) continue;
+      const uint32_t j = act[i], t = top[j], tt = top[t - n];
+      if (tt == t) continue;  // t is a top
+      top[j] = tt;
+      keep[k] = top[tt - n] != tt;
+      vals[k] = j;
+    }
+    tile_append(keep, vals, next, nnext);
+  }
+}
+// after the enqueued rounds every list must be empty (pointer doubling over
+// a tree of m rows ends within bits(m) + 1 rounds); if not, the call fails
+__global__ void k_loop_done(const uint64_t *cnt, uint64_t *hdr) {
+  if (threadIdx.x == 0 && *cnt != 0) hdr[H_STATUS] |= 32;
 }
 // big children of every D-node: the level tops (rows that are their own top)
 // hanging below its block; records are never big (M >= 2)
@@ -199,41 +223,63 @@ __device__ inline bool j_terminal(uint32_t x, int64_t n, int64_t m, const uint8_
 }
 
 // J[j] for big rows: self if birth, ROOT if a root, else the parent node.
+// Rows whose J is not yet a birth node or ROOT go to the active list.
 __global__ __launch_bounds__(B) void k_cd_jinit(const uint8_t *isbirth, const uint32_t *kpar, const uint32_t *ksize,
-                                                const uint32_t *rowg, Cnt mc, int64_t n, int64_t M, uint32_t *J) {
+                                                const uint32_t *rowg, Cnt mc, int64_t n, int64_t M, uint32_t *J,
+                                                uint32_t *act, unsigned long long *nact) {
   const int64_t m = mc.get();
-  for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
-    uint32_t v = NONE32;
-    if (ksize[j] >= (uint64_t)M) {
-      if (isbirth[j]) v = (uint32_t)(n + j);
-      else if (kpar[n + j] == NONE32) v = (uint32_t)(n + m + rowg[j]);
-      else v = kpar[n + j];
+  for (int64_t tile = blockIdx.x; tile * (B * CT) < m; tile += gridDim.x) {
+    bool keep[CT];
+    uint32_t vals[CT];
+    const int64_t base = tile * (B * CT) + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < CT; k++) {
+      const int64_t j = base + (int64_t)k * B;
+      keep[k] = false;
+      vals[k] = (uint32_t)j;
+      if (j >= m) continue;
+      uint32_t v = NONE32;
+      if (ksize[j] >= (uint64_t)M) {
+        if (isbirth[j]) v = (uint32_t)(n + j);
+        else if (kpar[n + j] == NONE32) v = (uint32_t)(n + m + rowg[j]);
+        else {
+          v = kpar[n + j];
+          keep[k] = !j_terminal(v, n, m, isbirth);
+        }
+      }
+      J[j] = v;
     }
-    J[j] = v;
+    tile_append(keep, vals, act, nact);
   }
 }
 
-// Every big row to its nearest birth ancestor (or its graph's root), in
-// place: a walk over J, each row storing into its own entry only. Ancestors
-// of a big row are big, so every J on the way is set, and J only ever moves
-// up, so whatever another walk reads is still on the way. Rows are taken from
-// the last one down (a parent is a later row), so the ancestors of a row are
-// mostly done when it walks and its walk is short.
-__global__ __launch_bounds__(B) void k_cd_jchase(Cnt mc, int64_t n, const uint8_t *isbirth, uint32_t *J,
-                                                 uint64_t *hdr) {
-  const int64_t m = mc.get();
-  for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < m; i += (int64_t)gridDim.x * B) {
-    const int64_t j = m - 1 - i;
-    uint32_t x = J[j];
-    if (x == NONE32) continue;
-    for (uint32_t steps = 0; !j_terminal(x, n, m, isbirth); steps++) {
-      if (steps > MAX_WALK) {
-        atomicOr((unsigned long long *)&hdr[H_STATUS], 32ull);
-        break;
+// one pointer-doubling round toward the nearest birth ancestor; finished rows
+// leave the list (in place: J only moves up, so a pointer read while another
+// row updates it is still an ancestor on the way)
+__global__ __launch_bounds__(B) void k_cd_jstep(const uint32_t *act, const uint64_t *nact_in, uint32_t *J,
+                                                const uint8_t *isbirth, Cnt mc, int64_t n, uint32_t *out,
+                                                unsigned long long *nout) {
+  const int64_t m = mc.get(), nact = (int64_t)*nact_in;
+  for (int64_t tile = blockIdx.x; tile * (B * CT) < nact; tile += gridDim.x) {
+    bool keep[CT];
+    uint32_t vals[CT];
+    const int64_t base = tile * (B * CT) + threadIdx.x;
+#pragma unroll
+    for (int k = 0; k < CT; k++) {
+      const int64_t i = base + (int64_t)k * B;
+      keep[k] = false;
+      vals[k] = 0;
+      if (i >= nact) continue;
+      const uint32_t j = act[i];
+      const uint32_t x = J[j];
+      const uint32_t y = J[x - n];
+      J[j] = y;
+      if (!j_terminal(y, n, m, isbirth)) {
+        keep[k] = true;
+        vals[k] = j;
       }
-      x = __hip_atomic_load(&J[x - n], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __hip_atomic_store(&J[j], x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
+    tile_append(keep, vals, out, nout);
   }
 }
 
@@ -920,15 +966,27 @@ __global__ void k_eom_count(uint64_t *hdr) {
 
 }  // namespace
 
-// level tops and big children per D-node, then births
+// Rounds of a pointer-doubling loop over a tree of up to k rows: bits(k) + 1
+// end it; one more is a margin.
+static int doubling_rounds(int64_t k) { return bits_for((uint64_t)k) + 2; }
+
+// level tops (pointer doubling over same-level parents) and big children per
+// D-node, then births; act and act2 hold m + 1 entries each, loop is the
+// counter words of the rounds
 static ce_status discrete_births(Bufs &b, Cnt m, const uint32_t *kpar, const uint32_t *level, const uint64_t *rowL,
-                                 uint32_t *top, uint32_t *bigcnt, uint8_t *isbirth, uint64_t *birthL,
-                                 hipStream_t s) {
+                                 uint32_t *top, uint32_t *act, uint32_t *act2, uint64_t *loop, uint32_t *bigcnt,
+                                 uint8_t *isbirth, uint64_t *birthL, hipStream_t s) {
   const int64_t n = b.n, M = b.M;
-  const unsigned g = grid_cap(m.v, B);
+  const unsigned g = grid_cap(m.v, B), tg = grid_cap(m.v, B * CT, 4096);
   auto tiles = [](int64_t k) { return (unsigned)((k + (int64_t)B * CT - 1) / ((int64_t)B * CT)); };
   CE_LAUNCH(k_dd_top_init, dim3(g), dim3(B), 0, s, kpar, level, m, n, top);
-  CE_LAUNCH(k_dd_top_chase, dim3(g), dim3(B), 0, s, m, n, top, b.hdr);
+  CE_LAUNCH(k_dd_top_active, dim3(tg), dim3(B), 0, s, top, m, n, act, (unsigned long long *)&loop[0]);
+  const int R = doubling_rounds(m.v);
+  uint32_t *lists[2] = {act, act2};
+  for (int r = 0; r < R; r++)
+    CE_LAUNCH(k_dd_top_jump, dim3(tg), dim3(B), 0, s, lists[r & 1], &loop[r], n, top, lists[1 - (r & 1)],
+              (unsigned long long *)&loop[r + 1]);
+  CE_LAUNCH(k_loop_done, dim3(1), dim3(64), 0, s, &loop[R], b.hdr);
   CE_LAUNCH(k_fill32, dim3(g), dim3(B), 0, s, bigcnt, m.v, 0u);
   CE_LAUNCH(k_dd_bigcount, dim3(tiles(m.v)), dim3(B), 0, s, kpar, b.ksize, top, m, n, M, bigcnt);
   CE_LAUNCH(k_dd_birth, dim3(g), dim3(B), 0, s, kpar, b.ksize, top, bigcnt, rowL, m, n, M, isbirth, birthL);
@@ -942,7 +1000,7 @@ size_t stage_condense_scratch(int64_t n, int64_t M, int64_t G, bool discrete) {
   const int64_t m = n, R = cluster_row_bound(n, M < 2 ? 2 : M, G), RE = discrete ? 2 * R : R;
   Ws w;
   w.alloc<uint32_t>(n + m + 1);  // kpar
-  w.alloc<uint32_t>(m + 1);      // J
+  w.alloc<uint32_t>(m + 1); w.alloc<uint32_t>(m + 1); w.alloc<uint32_t>(m + 1);  // J, active lists
   w.alloc<uint8_t>(m + 4);       // isbirth
   w.alloc<uint64_t>(m + 1);      // birthL
   w.alloc<uint64_t>(m + 1);      // rowL (the discrete arrays reuse exc, exl, labrow and fl)
@@ -978,7 +1036,8 @@ size_t stage_condense_scratch(int64_t n, int64_t M, int64_t G, bool discrete) {
 // about bits(R) + 2.
 static int eom_rounds(int64_t R) { return bits_for((uint64_t)R) + 4; }
 static int top_rounds(int64_t R) { return bits_for((uint64_t)R) + 2; }
-constexpr int MAX_LOOP_ROUNDS = 90;
+// counter words of the bounded loops (from H_LOOP): level tops, J, excess of mass, label tops
+constexpr int LOOP_DD = 0, LOOP_J = 40, LOOP_EOM = 80, LOOP_TOP = 130, LOOP_END = kHdrWords - H_LOOP;
 
 // Sizes: m rows (device word, bound n - 1), nb births and nrows = nb + G
 // cluster rows, nvirt virtual nodes (device words, bounds from R).
@@ -990,6 +1049,7 @@ ce_status stage_condense(Bufs &b, const ce_result *out, Ws &ws, hipStream_t s, i
   const Cnt nb(&b.hdr[H_NB], R), nrows(&b.hdr[H_NROWS], R), nvirt(&b.hdr[H_NVIRT], R), neom(&b.hdr[H_NEOM], RE);
   uint32_t *kpar = ws.alloc<uint32_t>(n + mb + 1);
   uint32_t *J = ws.alloc<uint32_t>(mb + 1);
+  uint32_t *jact = ws.alloc<uint32_t>(mb + 1), *jact2 = ws.alloc<uint32_t>(mb + 1);
   uint8_t *isbirth = ws.alloc<uint8_t>(mb + 4);
   uint64_t *birthL = ws.alloc<uint64_t>(mb + 1);
   uint64_t *rowL = ws.alloc<uint64_t>(mb + 1);
@@ -1051,14 +1111,24 @@ ce_status stage_condense(Bufs &b, const ce_result *out, Ws &ws, hipStream_t s, i
             isbirth, birthL);
   CE_HIP(hipGetLastError());
   if (b.q > 0) {
-    CE_TRY(discrete_births(b, m, kpar, level, rowL, dtop, bigcnt, isbirth, birthL, s));
+    CE_TRY(discrete_births(b, m, kpar, level, rowL, dtop, jact, jact2, loop + LOOP_DD, bigcnt, isbirth, birthL, s));
     if (out->dd_level || out->dd_top)
       CE_LAUNCH(k_out_discrete, dim3(gm), dim3(B), 0, s, level, dtop, b.rowg, b.eoff, b.moff, b.rowpos, n, m,
                 out->dd_level, out->dd_top);
     CE_HIP(hipGetLastError());
   }
-  CE_LAUNCH(k_cd_jinit, dim3(gm), dim3(B), 0, s, isbirth, kpar, b.ksize, b.rowg, m, n, M, J);
-  CE_LAUNCH(k_cd_jchase, dim3(gm), dim3(B), 0, s, m, n, isbirth, J, b.hdr);
+  {
+    uint64_t *jl = loop + LOOP_J;
+    const unsigned tg = grid_cap(mb, B * CT, 4096);
+    CE_LAUNCH(k_cd_jinit, dim3(tg), dim3(B), 0, s, isbirth, kpar, b.ksize, b.rowg, m, n, M, J, jact,
+              (unsigned long long *)&jl[0]);
+    const int R = doubling_rounds(mb);
+    uint32_t *lists[2] = {jact, jact2};
+    for (int r = 0; r < R; r++)
+      CE_LAUNCH(k_cd_jstep, dim3(tg), dim3(B), 0, s, lists[r & 1], &jl[r], J, isbirth, m, n, lists[1 - (r & 1)],
+                (unsigned long long *)&jl[r + 1]);
+    CE_LAUNCH(k_loop_done, dim3(1), dim3(64), 0, s, &jl[R], b.hdr);
+  }
   // cluster rows: births in (graph, node) order, each graph followed by its root row
   CE_LAUNCH(k_u8_to_u32, dim3(gm), dim3(B), 0, s, isbirth, m, flags32);
   CE_HIP(hipGetLastError());
@@ -1117,24 +1187,25 @@ ce_status stage_condense(Bufs &b, const ce_result *out, Ws &ws, hipStream_t s, i
     CE_LAUNCH(k_eom_count, dim3(1), dim3(64), 0, s, b.hdr);
   }
   // excess of mass: enqueued rounds, then the rest in one workgroup
+  uint64_t *el = loop + LOOP_EOM;
   CE_LAUNCH(k_eom_init, dim3(tiles(RE)), dim3(B), 0, s, nch, shi, slo, cprow, nrows, neom, e[0], e[1], ract,
-            (unsigned long long *)&loop[0]);
+            (unsigned long long *)&el[0]);
   CE_HIP(hipGetLastError());
   uint32_t *lists[2] = {ract, ract2};
   const unsigned tRE = grid_cap(RE, B * CT, 4096);
   const int EOM_ROUNDS = eom_rounds(RE), TOP_ROUNDS = top_rounds(R);
-  if (EOM_ROUNDS + TOP_ROUNDS + 4 > MAX_LOOP_ROUNDS) {
+  if (LOOP_EOM + EOM_ROUNDS + 1 >= LOOP_TOP || LOOP_TOP + TOP_ROUNDS + 1 >= LOOP_END) {
     set_error("internal: too many bounded rounds");
     return CE_EDEVICE;
   }
   for (int r = 0; r < EOM_ROUNDS; r++)
-    CE_LAUNCH(k_eom_round, dim3(tRE), dim3(B), 0, s, lists[r & 1], &loop[r], e[r & 1], e[1 - (r & 1)], ch, shi, slo,
-              lists[1 - (r & 1)], (unsigned long long *)&loop[r + 1]);
-  CE_LAUNCH(k_eom_tail, dim3(1), dim3(TB), 0, s, lists[0], lists[1], &loop[EOM_ROUNDS], EOM_ROUNDS & 1, e[0], e[1],
+    CE_LAUNCH(k_eom_round, dim3(tRE), dim3(B), 0, s, lists[r & 1], &el[r], e[r & 1], e[1 - (r & 1)], ch, shi, slo,
+              lists[1 - (r & 1)], (unsigned long long *)&el[r + 1]);
+  CE_LAUNCH(k_eom_tail, dim3(1), dim3(TB), 0, s, lists[0], lists[1], &el[EOM_ROUNDS], EOM_ROUNDS & 1, e[0], e[1],
             ch, shi, slo, b.hdr);
   CE_HIP(hipGetLastError());
   // the list is empty: both state buffers hold the final values
-  uint64_t *tl = loop + EOM_ROUNDS + 2;
+  uint64_t *tl = loop + LOOP_TOP;
   CE_LAUNCH(k_eom_select, dim3(tiles(R)), dim3(B), 0, s, nch, ch, e[0], shi, slo, nrows, top, nxt, top2, nxt2, cprow,
             ract, (unsigned long long *)&tl[0]);
   CE_HIP(hipGetLastError());

@@ -42,43 +42,47 @@ __device__ inline uint32_t block_excl_scan(uint32_t x, uint32_t *lds_w /*[4]*/, 
   return before + inc - x;
 }
 
+// Tiles of STILE elements; a block takes tiles blockIdx.x, + gridDim.x, ...
+// up to the live count's tiles (the grid is capped, so a small or empty live
+// count costs little).
 __global__ __launch_bounds__(SB) void k_scan_reduce(const uint32_t *in, Cnt nc, uint32_t *sums) {
   __shared__ uint32_t lw[SB / 64];
   const int64_t n = nc.get();
-  int64_t base = (int64_t)blockIdx.x * STILE + (int64_t)threadIdx.x * SIPT;
-  uint32_t acc = 0;
+  const int64_t tiles = (n + STILE - 1) / STILE;
+  for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int64_t base = tile * STILE + (int64_t)threadIdx.x * SIPT;
+    uint32_t acc = 0;
 #pragma unroll
-  for (int k = 0; k < SIPT; k++)
-    if (base + k < n) acc += in[base + k];
-  uint32_t tot;
-  block_excl_scan(acc, lw, &tot);
-  if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+    for (int k = 0; k < SIPT; k++)
+      if (base + k < n) acc += in[base + k];
+    uint32_t tot;
+    block_excl_scan(acc, lw, &tot);
+    if (threadIdx.x == 0) sums[tile] = tot;
+  }
 }
 
 __global__ __launch_bounds__(SB) void k_scan_apply(const uint32_t *in, uint32_t *out, Cnt nc,
                                                    const uint32_t *sums_scanned) {
   __shared__ uint32_t lw[SB / 64];
   const int64_t n = nc.get();
-  // blocks past a device count have nothing to write; the total (out[n]) is block 0's
-  if ((int64_t)blockIdx.x * STILE >= n) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = sums_scanned[gridDim.x];
-    return;
-  }
-  int64_t base = (int64_t)blockIdx.x * STILE + (int64_t)threadIdx.x * SIPT;
-  uint32_t v[SIPT];
-  uint32_t acc = 0;
+  const int64_t tiles = (n + STILE - 1) / STILE;
+  for (int64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    const int64_t base = tile * STILE + (int64_t)threadIdx.x * SIPT;
+    uint32_t v[SIPT];
+    uint32_t acc = 0;
 #pragma unroll
-  for (int k = 0; k < SIPT; k++) {
-    v[k] = (base + k < n) ? in[base + k] : 0u;
-    acc += v[k];
-  }
-  uint32_t run = block_excl_scan(acc, lw, nullptr) + sums_scanned[blockIdx.x];
+    for (int k = 0; k < SIPT; k++) {
+      v[k] = (base + k < n) ? in[base + k] : 0u;
+      acc += v[k];
+    }
+    uint32_t run = block_excl_scan(acc, lw, nullptr) + sums_scanned[tile];
 #pragma unroll
-  for (int k = 0; k < SIPT; k++) {
-    if (base + k < n) out[base + k] = run;
-    run += v[k];
+    for (int k = 0; k < SIPT; k++) {
+      if (base + k < n) out[base + k] = run;
+      run += v[k];
+    }
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = sums_scanned[gridDim.x];
+  if (blockIdx.x == 0 && threadIdx.x == 0) out[n] = sums_scanned[tiles];
 }
 
 // single-block exclusive scan for up to STILE elements; out[n] = total
@@ -121,16 +125,17 @@ ce_status scan_exclusive_u32(const uint32_t *in, uint32_t *out, Cnt n, Ws &ws, h
     CE_HIP(hipGetLastError());
     return CE_OK;
   }
-  // the block sums are laid out for the capacity; blocks past a device count contribute zeros
+  // one sum per tile of the live count; the sums are scanned with the tile count as their count
   int64_t nb = (n.v + STILE - 1) / STILE;
   size_t m = ws.mark();
   uint32_t *sums = ws.alloc<uint32_t>(nb + 1);
   uint32_t *sums_sc = ws.alloc<uint32_t>(nb + 1);
   CE_WS_CHECK(ws);
-  CE_LAUNCH(k_scan_reduce, dim3((unsigned)nb), dim3(SB), 0, s, in, n, sums);
+  const unsigned g = grid_for(nb, 1, 2048);
+  CE_LAUNCH(k_scan_reduce, dim3(g), dim3(SB), 0, s, in, n, sums);
   CE_HIP(hipGetLastError());
-  CE_TRY(scan_exclusive_u32(sums, sums_sc, Cnt(nb), ws, s));
-  CE_LAUNCH(k_scan_apply, dim3((unsigned)nb), dim3(SB), 0, s, in, out, n, sums_sc);
+  CE_TRY(scan_exclusive_u32(sums, sums_sc, n.p ? Cnt(n.p, nb, n.sh + 11) : Cnt(nb), ws, s));
+  CE_LAUNCH(k_scan_apply, dim3(g), dim3(SB), 0, s, in, out, n, sums_sc);
   CE_HIP(hipGetLastError());
   ws.release(m);
   return CE_OK;
