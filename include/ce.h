@@ -303,6 +303,24 @@ ce_status ce_cluster_batch_async(const int32_t *src, const int32_t *dst, const i
                                  int64_t num_vertices, const ce_params *params, const ce_result *out, int64_t *hdr,
                                  void *workspace, size_t workspace_bytes, void *stream);
 
+/*
+ * For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): ce_cluster_edges_async
+ * with the workspace taken from a static device array of
+ * CE_NOALLOC_SCRATCH_BYTES (128 MiB) inside the library, so the call itself
+ * allocates nothing. Every GPU the library runs on holds its own copy of the
+ * array until the process ends. Calls whose workspace (ce_workspace_bytes)
+ * exceeds it return CE_ENOMEM (with the default M = 5 and V = n/20, about
+ * 650 000 records fit). All calls on one GPU share its array: calls that
+ * overlap on one GPU (other streams, other threads) race and must be
+ * serialised by the caller; the array keeps the last call's contents, and the
+ * pipeline initialises everything it reads. Inputs, outputs and hdr as for
+ * ce_cluster_edges_async.
+ */
+#define CE_NOALLOC_SCRATCH_BYTES (128LL << 20)
+ce_status ce_cluster_edges_noalloc(const int32_t *src, const int32_t *dst, const int64_t *t, int64_t n,
+                                   const ce_params *params, const ce_result *out, int64_t *hdr, void *stream);
+
 /* Workspace of a batch of num_graphs graphs and n records in all. Pure. */
 size_t ce_batch_workspace_bytes_for(int64_t n, int64_t num_graphs, const ce_params *params);
 

@@ -70,7 +70,7 @@ _EXPORTS = ["ce_cluster_edges", "ce_cluster_batch", "ce_workspace_bytes", "ce_ba
             "ce_max_clusters", "ce_last_error", "ce_timing_enable", "ce_timing_read", "ce_server_create",
             "ce_server_destroy", "ce_server_request_bytes", "ce_server_submit", "ce_server_poll",
             "ce_server_get_stats", "ce_cluster_edges_async", "ce_cluster_batch_async", "ce_batch_workspace_bytes_for",
-            "ce_result_status"]
+            "ce_result_status", "ce_cluster_edges_noalloc"]
 CE_MAX_GRAPHS = 1 << 24
 _lib = None
 
@@ -118,6 +118,10 @@ def load_library(path: str = LIB_PATH):
         lib.ce_result_status.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(CeCounts), i64p, i64p,
                                          ctypes.c_void_p]
         lib.ce_result_status.restype = ctypes.c_int
+        lib.ce_cluster_edges_noalloc.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_int64, ctypes.POINTER(CeParams),
+                                                                         ctypes.POINTER(CeResult), ctypes.c_void_p,
+                                                                         ctypes.c_void_p]
+        lib.ce_cluster_edges_noalloc.restype = ctypes.c_int
         vp = ctypes.c_void_p
         lib.ce_server_create.argtypes = [ctypes.POINTER(CeServerConfig), ctypes.POINTER(vp)]
         lib.ce_server_create.restype = ctypes.c_int

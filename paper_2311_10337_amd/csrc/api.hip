@@ -642,6 +642,37 @@ ce_status ce_cluster_edges(const int32_t *src, const int32_t *dst, const int64_t
   return run_call(c, out, counts, nullptr, nullptr, nullptr, workspace, workspace_bytes, (hipStream_t)stream);
 }
 
+// The workspace of ce_cluster_edges_noalloc: a static device array, one copy
+// on every GPU the library runs on, held until the process ends. Its
+// address on a device comes from hipGetSymbolAddress with that device
+// current (the array's name in host code is only a stand-in), taken on the
+// first call on the device and kept.
+static __device__ __align__(256) unsigned char scratch[CE_NOALLOC_SCRATCH_BYTES];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+static ce_status scratch_of_current_device(void **ptr) {
+  int dev = -1;
+  CE_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) {
+    set_error("device ordinal outside [0, 64)");
+    return CE_EINVAL;
+  }
+  std::lock_guard<std::mutex> l(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      set_error(std::string("hipGetSymbolAddress of the static scratch failed: ") + hipGetErrorString(e));
+      return CE_EDEVICE;
+    }
+    g_scratch_ptr[dev] = p;
+  }
+  *ptr = g_scratch_ptr[dev];
+  return CE_OK;
+}
+
 ce_status ce_cluster_edges_async(const int32_t *src, const int32_t *dst, const int64_t *t, int64_t n,
                                  const ce_params *params, const ce_result *out, int64_t *hdr, void *workspace,
                                  size_t workspace_bytes, void *stream) {
@@ -654,6 +685,27 @@ ce_status ce_cluster_edges_async(const int32_t *src, const int32_t *dst, const i
   }
   CE_TRY(check_async_key(c.time_bits, n));
   return run_call(c, out, nullptr, nullptr, nullptr, hdr, workspace, workspace_bytes, (hipStream_t)stream);
+}
+
+ce_status ce_cluster_edges_noalloc(const int32_t *src, const int32_t *dst, const int64_t *t, int64_t n,
+                                   const ce_params *params, const ce_result *out, int64_t *hdr, void *stream) {
+  if (!out || !hdr) { set_error("out/hdr is NULL"); return CE_EINVAL; }
+  Call c;
+  CE_TRY(single_call(c, src, dst, t, n, params));
+  if (c.causal) {
+    set_error("asynchronous calls cluster the undirected line graph (mode must be CE_MODE_UNDIRECTED)");
+    return CE_EINVAL;
+  }
+  CE_TRY(check_async_key(c.time_bits, n));
+  const size_t need = workspace_for(n, c.M, 1, c.th.q > 0);
+  if (need > (size_t)CE_NOALLOC_SCRATCH_BYTES) {
+    set_error("the call needs " + std::to_string(need) + " bytes of workspace; the static scratch holds " +
+              std::to_string((size_t)CE_NOALLOC_SCRATCH_BYTES));
+    return CE_ENOMEM;
+  }
+  void *ws = nullptr;
+  CE_TRY(scratch_of_current_device(&ws));
+  return run_call(c, out, nullptr, nullptr, nullptr, hdr, ws, (size_t)CE_NOALLOC_SCRATCH_BYTES, (hipStream_t)stream);
 }
 
 size_t ce_hyper_workspace_bytes(int64_t n, int64_t nnz, const ce_params *params) {

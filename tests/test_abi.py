@@ -23,7 +23,8 @@ def test_library_exports_declared_symbols():
                          "ce_server_create", "ce_server_destroy", "ce_server_request_bytes", "ce_server_submit",
                          "ce_server_poll", "ce_server_get_stats", "ce_cluster_hyperedges",
                          "ce_hyper_workspace_bytes", "ce_level_components", "ce_cluster_edges_async",
-                         "ce_cluster_batch_async", "ce_batch_workspace_bytes_for", "ce_result_status"}
+                         "ce_cluster_batch_async", "ce_batch_workspace_bytes_for", "ce_result_status",
+                         "ce_cluster_edges_noalloc"}
     for s in syms:
         assert hasattr(lib, s), s
 
