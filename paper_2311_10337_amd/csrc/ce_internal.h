@@ -262,6 +262,27 @@ constexpr int CT = 16;
 // its global atomic: hot keys enter the table early, and a tile with many
 // distinct keys should not pay a long probe sequence per element.
 constexpr int HASH_PROBES = 4;
+// Items per thread of a tile loop over n items, at most CT: all CT once the
+// launched grid is full, fewer when a short list (a small call, a late round)
+// would otherwise sit in a few workgroups whose threads take their items one
+// after another; then it spreads over the whole grid. Uniform over the grid.
+__device__ inline int tile_items(int64_t n) {
+  const int64_t span = (int64_t)blockDim.x * gridDim.x;
+  const int64_t per = (n + span - 1) / span;
+  return per < 1 ? 1 : (per > CT ? CT : (int)per);
+}
+// end of tile `tile` of `span` items in a list of n
+__device__ inline int64_t tile_end(int64_t n, int64_t tile, int64_t span) {
+  const int64_t e = (tile + 1) * span;
+  return n < e ? n : e;
+}
+// Host side, for kernels that take a fixed number of items per thread over a
+// list whose length the host knows (or bounds): enough items for the LDS
+// aggregation to pay, but at least about 1024 workgroups while the list allows.
+inline int items_per_thread(int64_t n, int block) {
+  const int64_t per = n / ((int64_t)block * 1024);
+  return per < 1 ? 1 : (per > CT ? CT : (int)per);
+}
 // Output positions for the kept elements of a tile (order as described
 // above); pos[k] is valid where keep[k]. One atomic on `counter` per tile.
 __device__ inline void tile_positions(const bool (&keep)[CT], uint32_t (&pos)[CT], unsigned long long *counter) {

@@ -112,16 +112,17 @@ __global__ __launch_bounds__(B) void k_dd_top_init(const uint32_t *kpar, const u
 __global__ __launch_bounds__(B) void k_dd_top_active(const uint32_t *top, Cnt mc, int64_t n, uint32_t *act,
                                                      unsigned long long *nact) {
   const int64_t m = mc.get();
-  for (int64_t tile = blockIdx.x; tile * (B * CT) < m; tile += gridDim.x) {
+  const int ct = tile_items(m);
+  for (int64_t tile = blockIdx.x; tile * (B * ct) < m; tile += gridDim.x) {
     bool keep[CT];
     uint32_t vals[CT];
-    const int64_t base = tile * (B * CT) + threadIdx.x;
+    const int64_t base = tile * (B * ct) + threadIdx.x, end = tile_end(m, tile, B * ct);
 #pragma unroll
     for (int k = 0; k < CT; k++) {
       const int64_t j = base + (int64_t)k * B;
       keep[k] = false;
       vals[k] = (uint32_t)j;
-      if (j >= m) continue;
+      if (j >= end) continue;
       const uint32_t t = top[j];
       keep[k] = t != (uint32_t)(n + j) && top[t - n] != t;
     }
@@ -133,16 +134,17 @@ __global__ __launch_bounds__(B) void k_dd_top_active(const uint32_t *top, Cnt mc
 __global__ __launch_bounds__(B) void k_dd_top_jump(const uint32_t *act, const uint64_t *nact_in, int64_t n,
                                                    uint32_t *top, uint32_t *next, unsigned long long *nnext) {
   const int64_t nact = (int64_t)*nact_in;
-  for (int64_t tile = blockIdx.x; tile * (B * CT) < nact; tile += gridDim.x) {
+  const int ct = tile_items(nact);
+  for (int64_t tile = blockIdx.x; tile * (B * ct) < nact; tile += gridDim.x) {
     bool keep[CT];
     uint32_t vals[CT];
-    const int64_t base = tile * (B * CT) + threadIdx.x;
+    const int64_t base = tile * (B * ct) + threadIdx.x, end = tile_end(nact, tile, B * ct);
 #pragma unroll
     for (int k = 0; k < CT; k++) {
       const int64_t i = base + (int64_t)k * B;
       keep[k] = false;
       vals[k] = 0;
-      if (i >= nact) continue;
+      if (i >= end) continue;
       const uint32_t j = act[i], t = top[j], tt = top[t - n];
       if (tt == t) continue;  // t is a top
       top[j] = tt;
@@ -163,13 +165,13 @@ __global__ void k_loop_done(const uint64_t *cnt, uint64_t *hdr) {
 // counts are combined per wave and per tile (LDS hash) before the atomics
 constexpr int DHS = 512;
 __global__ __launch_bounds__(B) void k_dd_bigcount(const uint32_t *kpar, const uint32_t *ksize, const uint32_t *top,
-                                                   Cnt mc, int64_t n, int64_t M, uint32_t *bigcnt) {
+                                                   Cnt mc, int64_t n, int64_t M, int kct, uint32_t *bigcnt) {
   __shared__ uint32_t hk[DHS], hc[DHS];
   const int64_t m = mc.get();
   for (int i = threadIdx.x; i < DHS; i += B) { hk[i] = NONE32; hc[i] = 0; }
   __syncthreads();
-  const int64_t tbase = (int64_t)blockIdx.x * (B * CT);
-  for (int k = 0; k < CT; k++) {
+  const int64_t tbase = (int64_t)blockIdx.x * (B * kct);
+  for (int k = 0; k < kct; k++) {
     const int64_t j = tbase + (int64_t)k * B + threadIdx.x;
     uint32_t d = 0, add = 0;
     if (j < m) {
@@ -228,16 +230,17 @@ __global__ __launch_bounds__(B) void k_cd_jinit(const uint8_t *isbirth, const ui
                                                 const uint32_t *rowg, Cnt mc, int64_t n, int64_t M, uint32_t *J,
                                                 uint32_t *act, unsigned long long *nact) {
   const int64_t m = mc.get();
-  for (int64_t tile = blockIdx.x; tile * (B * CT) < m; tile += gridDim.x) {
+  const int ct = tile_items(m);
+  for (int64_t tile = blockIdx.x; tile * (B * ct) < m; tile += gridDim.x) {
     bool keep[CT];
     uint32_t vals[CT];
-    const int64_t base = tile * (B * CT) + threadIdx.x;
+    const int64_t base = tile * (B * ct) + threadIdx.x, end = tile_end(m, tile, B * ct);
 #pragma unroll
     for (int k = 0; k < CT; k++) {
       const int64_t j = base + (int64_t)k * B;
       keep[k] = false;
       vals[k] = (uint32_t)j;
-      if (j >= m) continue;
+      if (j >= end) continue;
       uint32_t v = NONE32;
       if (ksize[j] >= (uint64_t)M) {
         if (isbirth[j]) v = (uint32_t)(n + j);
@@ -260,16 +263,17 @@ __global__ __launch_bounds__(B) void k_cd_jstep(const uint32_t *act, const uint6
                                                 const uint8_t *isbirth, Cnt mc, int64_t n, uint32_t *out,
                                                 unsigned long long *nout) {
   const int64_t m = mc.get(), nact = (int64_t)*nact_in;
-  for (int64_t tile = blockIdx.x; tile * (B * CT) < nact; tile += gridDim.x) {
+  const int ct = tile_items(nact);
+  for (int64_t tile = blockIdx.x; tile * (B * ct) < nact; tile += gridDim.x) {
     bool keep[CT];
     uint32_t vals[CT];
-    const int64_t base = tile * (B * CT) + threadIdx.x;
+    const int64_t base = tile * (B * ct) + threadIdx.x, end = tile_end(nact, tile, B * ct);
 #pragma unroll
     for (int k = 0; k < CT; k++) {
       const int64_t i = base + (int64_t)k * B;
       keep[k] = false;
       vals[k] = 0;
-      if (i >= nact) continue;
+      if (i >= end) continue;
       const uint32_t j = act[i];
       const uint32_t x = J[j];
       const uint32_t y = J[x - n];
@@ -389,14 +393,15 @@ constexpr int AHS = 512;  // LDS hash slots for per-cluster-row sums
 __global__ __launch_bounds__(B) void k_cd_point_terms(const uint32_t *kc_u, const uint32_t *kc_v,
                                                       const uint32_t *ksize, const uint32_t *J, const uint64_t *rowL,
                                                       const uint32_t *rowof, const uint32_t *rootrow, Cnt mc,
-                                                      int64_t n, int64_t M, unsigned long long *acc) {
+                                                      int64_t n, int64_t M, int kct,
+                                                      unsigned long long *acc) {
   __shared__ uint32_t hk[AHS];
   const int64_t m = mc.get();
   __shared__ unsigned long long h0[AHS], h1[AHS], h2[AHS];
   for (int i = threadIdx.x; i < AHS; i += B) { hk[i] = NONE32; h0[i] = 0; h1[i] = 0; h2[i] = 0; }
   __syncthreads();
-  const int64_t tbase = (int64_t)blockIdx.x * (B * CT);
-  for (int k = 0; k < CT; k++) {
+  const int64_t tbase = (int64_t)blockIdx.x * (B * kct);
+  for (int k = 0; k < kct; k++) {
     const int64_t j = tbase + (int64_t)k * B + threadIdx.x;
     uint32_t cnt = 0, r = 0;
     uint64_t L = 0;
@@ -607,23 +612,26 @@ __global__ __launch_bounds__(B) void k_eom_init(const uint32_t *nch, const uint6
                                                 const uint32_t *cprow, Cnt nrc, Cnt nec, Eom e0,
                                                 Eom e1, uint32_t *act, unsigned long long *nact) {
   const int64_t nreal = nrc.get(), nrows = nec.get();
-  bool keep[CT];
-  uint32_t vals[CT];
-  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
+  const int ct = tile_items(nrows);
+  for (int64_t tile = blockIdx.x; tile * (B * ct) < nrows; tile += gridDim.x) {
+    bool keep[CT];
+    uint32_t vals[CT];
+    const int64_t base = tile * (B * ct) + threadIdx.x, end = tile_end(nrows, tile, B * ct);
 #pragma unroll
-  for (int k = 0; k < CT; k++) {
-    const int64_t r = base + (int64_t)k * B;
-    keep[k] = false;
-    vals[k] = (uint32_t)r;
-    if (r >= nrows) continue;
-    // rows from nreal on are virtual sum nodes, never leaves
-    bool leaf = r < nreal && (nch[r] == 0 || cprow[r] == NONE32);
-    u128 S{slo[r], shi[r]}, z{0, 0};
-    eom_store(e0, (uint32_t)r, leaf ? 2 : 0, S, z, z, NONE32);
-    eom_store(e1, (uint32_t)r, leaf ? 2 : 0, S, z, z, NONE32);
-    keep[k] = !leaf;
+    for (int k = 0; k < CT; k++) {
+      const int64_t r = base + (int64_t)k * B;
+      keep[k] = false;
+      vals[k] = (uint32_t)r;
+      if (r >= end) continue;
+      // rows from nreal on are virtual sum nodes, never leaves
+      bool leaf = r < nreal && (nch[r] == 0 || cprow[r] == NONE32);
+      u128 S{slo[r], shi[r]}, z{0, 0};
+      eom_store(e0, (uint32_t)r, leaf ? 2 : 0, S, z, z, NONE32);
+      eom_store(e1, (uint32_t)r, leaf ? 2 : 0, S, z, z, NONE32);
+      keep[k] = !leaf;
+    }
+    tile_append(keep, vals, act, nact);
   }
-  tile_append(keep, vals, act, nact);
 }
 
 // One round over the pending rows: rake (both children done), turn into a
@@ -676,16 +684,17 @@ __global__ __launch_bounds__(B) void k_eom_round(const uint32_t *act, const uint
                                                  const uint32_t *ch, const uint64_t *shi, const uint64_t *slo,
                                                  uint32_t *next, unsigned long long *nnext) {
   const int64_t nact = (int64_t)*nact_in;
-  for (int64_t tile = blockIdx.x; tile * (B * CT) < nact; tile += gridDim.x) {
+  const int ct = tile_items(nact);
+  for (int64_t tile = blockIdx.x; tile * (B * ct) < nact; tile += gridDim.x) {
     bool keep[CT];
     uint32_t vals[CT];
-    const int64_t base = tile * (B * CT) + threadIdx.x;
+    const int64_t base = tile * (B * ct) + threadIdx.x, end = tile_end(nact, tile, B * ct);
 #pragma unroll
     for (int k = 0; k < CT; k++) {
       const int64_t i = base + (int64_t)k * B;
       keep[k] = false;
       vals[k] = 0;
-      if (i < nact) keep[k] = eom_step(act[i], in, out, ch, shi, slo, &vals[k]);
+      if (i < end) keep[k] = eom_step(act[i], in, out, ch, shi, slo, &vals[k]);
     }
     tile_append(keep, vals, next, nnext);
   }
@@ -730,31 +739,34 @@ __global__ __launch_bounds__(B) void k_eom_select(const uint32_t *nch, const uin
                                                   uint32_t *top2, uint32_t *nxt2, const uint32_t *cprow, uint32_t *act,
                                                   unsigned long long *nact) {
   const int64_t nrows = nrc.get();
-  bool keep[CT];
-  uint32_t vals[CT];
-  const int64_t base = (int64_t)blockIdx.x * (B * CT) + threadIdx.x;
+  const int ct = tile_items(nrows);
+  for (int64_t tile = blockIdx.x; tile * (B * ct) < nrows; tile += gridDim.x) {
+    bool keep[CT];
+    uint32_t vals[CT];
+    const int64_t base = tile * (B * ct) + threadIdx.x, end = tile_end(nrows, tile, B * ct);
 #pragma unroll
-  for (int k = 0; k < CT; k++) {
-    const int64_t r = base + (int64_t)k * B;
-    keep[k] = false;
-    vals[k] = (uint32_t)r;
-    if (r >= nrows) continue;
-    bool sel;
-    if (cprow[r] == NONE32) sel = false;
-    else if (nch[r] == 0) sel = true;
-    else {
-      uint32_t c1 = ch[2 * r], c2 = ch[2 * r + 1];
-      u128 sum = u128_add(u128{e.vlo[c1], e.vhi[c1]}, u128{e.vlo[c2], e.vhi[c2]});
-      sel = !u128_gt(sum, u128{slo[r], shi[r]});
+    for (int k = 0; k < CT; k++) {
+      const int64_t r = base + (int64_t)k * B;
+      keep[k] = false;
+      vals[k] = (uint32_t)r;
+      if (r >= end) continue;
+      bool sel;
+      if (cprow[r] == NONE32) sel = false;
+      else if (nch[r] == 0) sel = true;
+      else {
+        uint32_t c1 = ch[2 * r], c2 = ch[2 * r + 1];
+        u128 sum = u128_add(u128{e.vlo[c1], e.vhi[c1]}, u128{e.vlo[c2], e.vhi[c2]});
+        sel = !u128_gt(sum, u128{slo[r], shi[r]});
+      }
+      uint32_t t = sel ? (uint32_t)r : NONE32;
+      uint32_t p = cprow[r];
+      uint32_t nx = (p == NONE32 || cprow[p] == NONE32) ? NONE32 : p;
+      top[r] = t; top2[r] = t;
+      nxt[r] = nx; nxt2[r] = nx;
+      keep[k] = nx != NONE32;
     }
-    uint32_t t = sel ? (uint32_t)r : NONE32;
-    uint32_t p = cprow[r];
-    uint32_t nx = (p == NONE32 || cprow[p] == NONE32) ? NONE32 : p;
-    top[r] = t; top2[r] = t;
-    nxt[r] = nx; nxt2[r] = nx;
-    keep[k] = nx != NONE32;
+    tile_append(keep, vals, act, nact);
   }
-  tile_append(keep, vals, act, nact);
 }
 
 // top[r] = highest selected row among r and its ancestors below ROOT
@@ -782,16 +794,17 @@ __global__ __launch_bounds__(B) void k_top_jump(const uint32_t *act, const uint6
                                                 const uint32_t *nin, uint32_t *tout, uint32_t *nout, uint32_t *next,
                                                 unsigned long long *nnext) {
   const int64_t nact = (int64_t)*nact_in;
-  for (int64_t tile = blockIdx.x; tile * (B * CT) < nact; tile += gridDim.x) {
+  const int ct = tile_items(nact);
+  for (int64_t tile = blockIdx.x; tile * (B * ct) < nact; tile += gridDim.x) {
     bool keep[CT];
     uint32_t vals[CT];
-    const int64_t base = tile * (B * CT) + threadIdx.x;
+    const int64_t base = tile * (B * ct) + threadIdx.x, end = tile_end(nact, tile, B * ct);
 #pragma unroll
     for (int k = 0; k < CT; k++) {
       const int64_t i = base + (int64_t)k * B;
       keep[k] = false;
       vals[k] = 0;
-      if (i < nact) keep[k] = top_step(act[i], tin, nin, tout, nout, &vals[k]);
+      if (i < end) keep[k] = top_step(act[i], tin, nin, tout, nout, &vals[k]);
     }
     tile_append(keep, vals, next, nnext);
   }
@@ -977,8 +990,8 @@ static ce_status discrete_births(Bufs &b, Cnt m, const uint32_t *kpar, const uin
                                  uint32_t *top, uint32_t *act, uint32_t *act2, uint64_t *loop, uint32_t *bigcnt,
                                  uint8_t *isbirth, uint64_t *birthL, hipStream_t s) {
   const int64_t n = b.n, M = b.M;
-  const unsigned g = grid_cap(m.v, B), tg = grid_cap(m.v, B * CT, 4096);
-  auto tiles = [](int64_t k) { return (unsigned)((k + (int64_t)B * CT - 1) / ((int64_t)B * CT)); };
+  const unsigned g = grid_cap(m.v, B), tg = grid_cap(m.v, B, 4096);
+  auto tiles = [](int64_t k, int per = CT) { return (unsigned)((k + (int64_t)B * per - 1) / ((int64_t)B * per)); };
   CE_LAUNCH(k_dd_top_init, dim3(g), dim3(B), 0, s, kpar, level, m, n, top);
   CE_LAUNCH(k_dd_top_active, dim3(tg), dim3(B), 0, s, top, m, n, act, (unsigned long long *)&loop[0]);
   const int R = doubling_rounds(m.v);
@@ -988,7 +1001,8 @@ static ce_status discrete_births(Bufs &b, Cnt m, const uint32_t *kpar, const uin
               (unsigned long long *)&loop[r + 1]);
   CE_LAUNCH(k_loop_done, dim3(1), dim3(64), 0, s, &loop[R], b.hdr);
   CE_LAUNCH(k_fill32, dim3(g), dim3(B), 0, s, bigcnt, m.v, 0u);
-  CE_LAUNCH(k_dd_bigcount, dim3(tiles(m.v)), dim3(B), 0, s, kpar, b.ksize, top, m, n, M, bigcnt);
+  const int kb = items_per_thread(m.v, B);
+  CE_LAUNCH(k_dd_bigcount, dim3(tiles(m.v, kb)), dim3(B), 0, s, kpar, b.ksize, top, m, n, M, kb, bigcnt);
   CE_LAUNCH(k_dd_birth, dim3(g), dim3(B), 0, s, kpar, b.ksize, top, bigcnt, rowL, m, n, M, isbirth, birthL);
   CE_HIP(hipGetLastError());
   return CE_OK;
@@ -1095,7 +1109,7 @@ ce_status stage_condense(Bufs &b, const ce_result *out, Ws &ws, hipStream_t s, i
   // discrete dendrogram: level, level tops and big-child counts per row live only until the
   // births are known and the per-row discrete outputs written, before exits, labels and flags use these
   uint32_t *level = exc, *dtop = labrow, *bigcnt = (uint32_t *)exl;
-  auto tiles = [](int64_t k) { return (unsigned)((k + (int64_t)B * CT - 1) / ((int64_t)B * CT)); };
+  auto tiles = [](int64_t k, int per = CT) { return (unsigned)((k + (int64_t)B * per - 1) / ((int64_t)B * per)); };
   uint64_t *loop = b.hdr + H_LOOP;  // counters of the bounded loops, zero from the start of the call
 
   const unsigned gN = grid_cap(n + mb + 1, B), gm = grid_cap(mb + 1, B), gG = grid_for(G + 1, B),
@@ -1119,7 +1133,7 @@ ce_status stage_condense(Bufs &b, const ce_result *out, Ws &ws, hipStream_t s, i
   }
   {
     uint64_t *jl = loop + LOOP_J;
-    const unsigned tg = grid_cap(mb, B * CT, 4096);
+    const unsigned tg = grid_cap(mb, B, 4096);
     CE_LAUNCH(k_cd_jinit, dim3(tg), dim3(B), 0, s, isbirth, kpar, b.ksize, b.rowg, m, n, M, J, jact,
               (unsigned long long *)&jl[0]);
     const int R = doubling_rounds(mb);
@@ -1154,8 +1168,9 @@ ce_status stage_condense(Bufs &b, const ce_result *out, Ws &ws, hipStream_t s, i
   CE_LAUNCH(k_cd_rootrows, dim3(gG), dim3(B), 0, s, rootrow, b.eoff, G, m, n, cnode, csize, cbirth, cprow);
   CE_LAUNCH(k_fill64, dim3(grid_cap(3 * R, B)), dim3(B), 0, s, (uint64_t *)acc, 3 * R, (uint64_t)0);
   // point terms of the stabilities per big row; exits per record in input order
-  CE_LAUNCH(k_cd_point_terms, dim3(tiles(mb)), dim3(B), 0, s, b.kc_u, b.kc_v, b.ksize, J, rowL, rowmap, rootrow, m, n,
-            M, acc);
+  const int kp = items_per_thread(mb, B);
+  CE_LAUNCH(k_cd_point_terms, dim3(tiles(mb, kp)), dim3(B), 0, s, b.kc_u, b.kc_v, b.ksize, J, rowL, rowmap, rootrow, m,
+            n, M, kp, acc);
   uint32_t *prow = labrow;
   uint2 *wk = (uint2 *)exl;  // m <= n words of 8 bytes
   CE_LAUNCH(k_cd_walk_words, dim3(gm), dim3(B), 0, s, kpar, b.ksize, J, rowmap, rootrow, n, m, M, wk);
@@ -1188,11 +1203,11 @@ ce_status stage_condense(Bufs &b, const ce_result *out, Ws &ws, hipStream_t s, i
   }
   // excess of mass: enqueued rounds, then the rest in one workgroup
   uint64_t *el = loop + LOOP_EOM;
-  CE_LAUNCH(k_eom_init, dim3(tiles(RE)), dim3(B), 0, s, nch, shi, slo, cprow, nrows, neom, e[0], e[1], ract,
+  const unsigned tRE = grid_cap(RE, B, 4096);
+  CE_LAUNCH(k_eom_init, dim3(tRE), dim3(B), 0, s, nch, shi, slo, cprow, nrows, neom, e[0], e[1], ract,
             (unsigned long long *)&el[0]);
   CE_HIP(hipGetLastError());
   uint32_t *lists[2] = {ract, ract2};
-  const unsigned tRE = grid_cap(RE, B * CT, 4096);
   const int EOM_ROUNDS = eom_rounds(RE), TOP_ROUNDS = top_rounds(R);
   if (LOOP_EOM + EOM_ROUNDS + 1 >= LOOP_TOP || LOOP_TOP + TOP_ROUNDS + 1 >= LOOP_END) {
     set_error("internal: too many bounded rounds");
@@ -1206,8 +1221,8 @@ ce_status stage_condense(Bufs &b, const ce_result *out, Ws &ws, hipStream_t s, i
   CE_HIP(hipGetLastError());
   // the list is empty: both state buffers hold the final values
   uint64_t *tl = loop + LOOP_TOP;
-  CE_LAUNCH(k_eom_select, dim3(tiles(R)), dim3(B), 0, s, nch, ch, e[0], shi, slo, nrows, top, nxt, top2, nxt2, cprow,
-            ract, (unsigned long long *)&tl[0]);
+  CE_LAUNCH(k_eom_select, dim3(grid_cap(R, B, 4096)), dim3(B), 0, s, nch, ch, e[0], shi, slo, nrows, top, nxt, top2,
+            nxt2, cprow, ract, (unsigned long long *)&tl[0]);
   CE_HIP(hipGetLastError());
   uint32_t *tops[2] = {top, top2}, *nxts[2] = {nxt, nxt2};
   for (int r = 0; r < TOP_ROUNDS; r++)

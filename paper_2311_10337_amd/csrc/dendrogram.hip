@@ -185,21 +185,21 @@ __global__ __launch_bounds__(B) void k_krt_union(Cnt mc, int64_t n, int lo, int 
   }
 }
 
-// Rows of a sub-interval are consecutive, so a 4096-row tile mostly feeds few
-// components (late steps: the giant one). Sizes and largest rows are summed
-// per component root in an LDS hash first, then one atomic per root per
-// tile; rows whose root finds no free slot go straight to global atomics.
+// Rows of a sub-interval are consecutive, so a tile of up to 4096 rows
+// (kct per thread) mostly feeds few components (late steps: the giant one).
+// Sizes and largest rows are summed per component root in an LDS hash first,
+// then one atomic per root per tile; rows whose root finds no free slot go
+// straight to global atomics.
 constexpr int KHS = 256;
-constexpr int KCT = 16;
-__global__ __launch_bounds__(B) void k_krt_accum(Cnt mc, int lo, int hi, uint32_t q, int64_t nthreads,
+__global__ __launch_bounds__(B) void k_krt_accum(Cnt mc, int lo, int hi, uint32_t q, int64_t nthreads, int kct,
                                                  const uint32_t *hooked, uint4 *uf) {
   __shared__ uint32_t hk[KHS], hs[KHS], hm[KHS];
   const int64_t m = mc.get();
   if (((int64_t)q << lo) >= m) return;
   for (int i = threadIdx.x; i < KHS; i += B) { hk[i] = NONE32; hs[i] = 0; hm[i] = 0; }
   __syncthreads();
-  const int64_t tbase = (int64_t)blockIdx.x * (B * KCT);
-  for (int k = 0; k < KCT; k++) {
+  const int64_t tbase = (int64_t)blockIdx.x * (B * kct);
+  for (int k = 0; k < kct; k++) {
     const int64_t tix = tbase + (int64_t)k * B + threadIdx.x;
     const int64_t j = tix < nthreads ? step_row(tix, lo, hi, q) : m;
     uint32_t h = NONE32, f = 0, add = 0, mj = 0;
@@ -436,6 +436,7 @@ ce_status stage_dendrogram(Bufs &b, Ws &ws, hipStream_t s) {
     const int64_t nint = (mb + (int64_t(1) << (hi + 1)) - 1) >> (hi + 1);
     const int64_t nthreads = nint << lo;
     const unsigned g = grid_for(nthreads, B, 1 << 16);
+    const int kct = items_per_thread(nthreads, B);
     if (first) CE_LAUNCH(k_krt_reset_records, dim3(grid_cap(n, B)), dim3(B), 0, s, n, uf);
     else CE_LAUNCH(k_krt_reset, dim3(grid_cap(mb, B)), dim3(B), 0, s, lu, lv, su, sv, m, uf);
     first = false;
@@ -443,8 +444,8 @@ ce_status stage_dendrogram(Bufs &b, Ws &ws, hipStream_t s) {
       // sub-interval q exists in at least one interval of the bound (the kernels check the live rows)
       if (((int64_t)q << lo) >= mb) break;
       CE_LAUNCH(k_krt_union, dim3(g), dim3(B), 0, s, m, n, lo, hi, q, nthreads, lu, lv, su, sv, uf, hooked);
-      CE_LAUNCH(k_krt_accum, dim3((unsigned)((nthreads + B * KCT - 1) / (B * KCT))), dim3(B), 0, s, m, lo, hi,
-                q, nthreads, hooked, uf);
+      CE_LAUNCH(k_krt_accum, dim3((unsigned)((nthreads + B * kct - 1) / (B * kct))), dim3(B), 0, s, m, lo, hi,
+                q, nthreads, kct, hooked, uf);
     }
     CE_HIP(hipGetLastError());
     hi = lo - 1;

@@ -401,18 +401,19 @@ __global__ __launch_bounds__(B) void k_contract_first(int64_t n, const uint64_t 
                                                       uint64_t *bv) {
   const int64_t n2 = 2 * n;
   unsigned long long *cnt = (unsigned long long *)&bv[BV_CNT1];
-  for (int64_t tile = blockIdx.x; tile * (B * CT) < n2; tile += gridDim.x) {
+  const int ct = tile_items(n2);
+  for (int64_t tile = blockIdx.x; tile * (B * ct) < n2; tile += gridDim.x) {
     bool keep[CT];
     uint32_t pos[CT], nu[CT], nv[CT];
     uint64_t kk[CT];
-    const int64_t base = tile * (B * CT) + threadIdx.x;
+    const int64_t base = tile * (B * ct) + threadIdx.x, end = tile_end(n2, tile, B * ct);
 #pragma unroll
     for (int k = 0; k < CT; k++) {
       const int64_t e = base + (int64_t)k * B;
       keep[k] = false;
       kk[k] = NONE64;
       nu[k] = nv[k] = 0;
-      if (e >= n2) continue;
+      if (e >= end) continue;
       kk[k] = skel_key[e];
       if (kk[k] == NONE64) continue;
       const uint32_t fu = fin[skel_tail[e]], fv = fin[e >> 1];
@@ -462,16 +463,17 @@ __global__ __launch_bounds__(B) void k_contract(EdgeLists L, uint64_t *bv, const
   const uint32_t *eu = L.u[in] + off, *ev = L.v[in] + off;
   const uint32_t *es = L.s[in] ? L.s[in] + off : nullptr;
   unsigned long long *cnt = (unsigned long long *)&bv[BV_CNT1];
-  for (int64_t tile = blockIdx.x; tile * (B * CT) < E; tile += gridDim.x) {
+  const int ct = tile_items(E);
+  for (int64_t tile = blockIdx.x; tile * (B * ct) < E; tile += gridDim.x) {
     bool keep[CT];
     uint32_t pos[CT], nu[CT], nv[CT];
-    const int64_t base = tile * (B * CT) + threadIdx.x;
+    const int64_t base = tile * (B * ct) + threadIdx.x, end = tile_end(E, tile, B * ct);
 #pragma unroll
     for (int k = 0; k < CT; k++) {
       const int64_t i = base + (int64_t)k * B;
       keep[k] = false;
       nu[k] = nv[k] = 0;
-      if (i >= E) continue;
+      if (i >= end) continue;
       const uint32_t fu = fmap[eu[i]], fv = fmap[ev[i]];
       if (fu == fv) continue;
       keep[k] = true;
@@ -564,17 +566,18 @@ __global__ __launch_bounds__(B) void k_split(EdgeLists L, uint64_t *bv) {
   const int64_t cap = L.cap;
   unsigned long long *nlight = (unsigned long long *)&bv[BV_CNT1];
   unsigned long long *nheavy = (unsigned long long *)&bv[BV_CNT2];
-  for (int64_t tile = blockIdx.x; tile * (B * CT) < lv.E; tile += gridDim.x) {
+  const int ct = tile_items(lv.E);
+  for (int64_t tile = blockIdx.x; tile * (B * ct) < lv.E; tile += gridDim.x) {
     bool lt[CT], ge[CT];
     uint32_t pl[CT], ph[CT];
     uint64_t kk[CT];
-    const int64_t base = tile * (B * CT) + threadIdx.x;
+    const int64_t base = tile * (B * ct) + threadIdx.x, end = tile_end(lv.E, tile, B * ct);
 #pragma unroll
     for (int k = 0; k < CT; k++) {
       const int64_t i = base + (int64_t)k * B;
-      kk[k] = i < lv.E ? lv.key[i] : 0;
-      lt[k] = i < lv.E && kk[k] < pivot;
-      ge[k] = i < lv.E && kk[k] >= pivot;
+      kk[k] = i < end ? lv.key[i] : 0;
+      lt[k] = i < end && kk[k] < pivot;
+      ge[k] = i < end && kk[k] >= pivot;
     }
     tile_positions(lt, pl, nlight);
     tile_positions(ge, ph, nheavy);
@@ -626,7 +629,7 @@ __global__ __launch_bounds__(B) void k_compose_roots(Cnt C, const uint64_t *bv, 
   }
 }
 
-// per component, the minimum key over its live edges. A tile of 4096 edges
+// per component, the minimum key over its live edges. A tile of up to 4096 edges
 // first takes per-component minima in an LDS hash (late rounds send most
 // edges to a few big components), then one atomicMin per component per tile.
 constexpr int MHS = 512;
@@ -635,11 +638,12 @@ __global__ __launch_bounds__(B) void k_bv_min(EdgeLists L, const uint64_t *bv, u
   const Live lv = live_list(L, bv);
   __shared__ uint32_t hk[MHS];
   __shared__ unsigned long long hv[MHS];
-  for (int64_t tile = blockIdx.x; tile * (B * CT) < lv.E; tile += gridDim.x) {
+  const int ct = tile_items(lv.E);
+  for (int64_t tile = blockIdx.x; tile * (B * ct) < lv.E; tile += gridDim.x) {
     for (int i = threadIdx.x; i < MHS; i += B) { hk[i] = NONE32; hv[i] = NONE64; }
     __syncthreads();
-    const int64_t tbase = tile * (B * CT);
-    for (int k = 0; k < CT; k++) {
+    const int64_t tbase = tile * (B * ct);
+    for (int k = 0; k < ct; k++) {
       const int64_t i = tbase + (int64_t)k * B + threadIdx.x;
       const bool act = i < lv.E;
       const unsigned long long kv = act ? lv.key[i] : NONE64;
@@ -712,14 +716,15 @@ __global__ void k_bv_check(const uint64_t *bv, uint64_t *hdr) {
 
 __global__ __launch_bounds__(B) void k_msf_list(const uint8_t *flag, int64_t n2, uint32_t *out,
                                                 unsigned long long *cnt) {
-  for (int64_t tile = blockIdx.x; tile * (B * CT) < n2; tile += gridDim.x) {
+  const int ct = tile_items(n2);
+  for (int64_t tile = blockIdx.x; tile * (B * ct) < n2; tile += gridDim.x) {
     bool keep[CT];
     uint32_t vals[CT];
-    const int64_t base = tile * (B * CT) + threadIdx.x;
+    const int64_t base = tile * (B * ct) + threadIdx.x, end = tile_end(n2, tile, B * ct);
 #pragma unroll
     for (int k = 0; k < CT; k++) {
       const int64_t e = base + (int64_t)k * B;
-      keep[k] = e < n2 && flag[e];
+      keep[k] = e < end && flag[e];
       vals[k] = (uint32_t)e;
     }
     tile_append(keep, vals, out, cnt);
@@ -970,7 +975,7 @@ ce_status stage_boruvka(Bufs &b, Ws &ws, hipStream_t s) {
   CE_LAUNCH(k_rankof, dim3(grid_for(n, B)), dim3(B), 0, s, b.perm, n, rankof);
   uint64_t *best = b.best;  // seeded for the first round while the skeleton was emitted
   CE_LAUNCH(k_fill_u8, dim3(grid_for(n2, B)), dim3(B), 0, s, b.msf_flag, n2, (uint8_t)0);
-  const unsigned gN = grid_cap(n, B), gE = grid_cap(n2, B), tE = grid_cap(n2, B * CT, 4096);
+  const unsigned gN = grid_cap(n, B), gE = grid_cap(n2, B), tE = grid_cap(n2, B, 4096);
   if (b.flat) {
     // causal and hypergraph skeleton rows can share a head, so every round,
     // the first included, runs on the edge-list form with records as
@@ -1064,7 +1069,7 @@ ce_status stage_msf_sort(Bufs &b, Ws &ws, hipStream_t s) {
   uint32_t *list = ws.alloc<uint32_t>(n);
   CE_WS_CHECK(ws);
   CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[H_M], (uint64_t)0);
-  CE_LAUNCH(k_msf_list, dim3(grid_cap(n2, B * CT, 4096)), dim3(B), 0, s, b.msf_flag, n2, list,
+  CE_LAUNCH(k_msf_list, dim3(grid_cap(n2, B, 4096)), dim3(B), 0, s, b.msf_flag, n2, list,
             (unsigned long long *)&b.hdr[H_M]);
   CE_LAUNCH(k_check_rows, dim3(1), dim3(64), 0, s, b.hdr, n);
   CE_HIP(hipGetLastError());
