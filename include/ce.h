@@ -60,7 +60,7 @@ typedef enum {
   CE_OK = 0,
   CE_EINVAL = -1,     /* bad argument: null pointer, n < 0, M < 2, unknown mode/flags */
   CE_ESELFLOOP = -2,  /* an input record has src == dst (the model excludes self loops, Sec. 1.2.1) */
-  CE_ERANGE = -3,     /* vertex id outside [0, V), or time span too wide for the packed key */
+  CE_ERANGE = -3,     /* vertex id outside [0, V), or a time span max t - min t >= 2^62 */
   CE_ENOMEM = -4,     /* workspace too small or device allocation failed */
   CE_EDEVICE = -5,    /* a HIP runtime call failed */
   CE_EBUSY = -6       /* serving queue full */
@@ -73,9 +73,19 @@ typedef enum {
  * w = t_s - t_r; the skeleton is Alg. 2 at every vertex (time order, in-edges
  * before out-edges at equal times, then id). MSF rows are (tail = r, head = s,
  * w) and the key is again K = (w, head, 2^32-1-tail); arcs are undirected for
- * the forest, dendrogram and condensing (Alg. 1). The packed key needs
- * bits(span) + bits(n-1) + bits(c-1) <= 63, where c is the largest number of
- * records arriving at one vertex at one time (else CE_ERANGE). */
+ * the forest, dendrogram and condensing (Alg. 1).
+ *
+ * Time domain (all modes): any int64 times whose span max t - min t is below
+ * 2^62 (Sec. 1.2.1 bounds nothing; the limit keeps every weight and lambda
+ * exact). The key is one 63-bit word: w << s | tie bits when that fits, else
+ * (wide spans) the rank of w among the skeleton's distinct weights in place
+ * of w, which orders the same; the ranking costs one more sort of the
+ * skeleton weights. The ranked key needs bits(rows - 1) + s <= 63, which
+ * holds for every input of up to 2^30 records (undirected; causal and
+ * hypergraph keys also add the tie width bits(c-1), c the largest number of
+ * records arriving at one vertex at one time, or the longest run of equal
+ * times). The environment variable CE_WEIGHT_RANKS=1 (read on every call)
+ * ranks the weights even when w fits. */
 typedef enum { CE_MODE_UNDIRECTED = 0, CE_MODE_CAUSAL = 1 } ce_mode;
 
 typedef struct {
@@ -97,8 +107,9 @@ typedef struct {
                                 starts a cluster for each of them; see dd_level / dd_top in ce_result */
   int64_t time_bits;         /* asynchronous calls: the caller's bound B on the time span, max t - min t <
                                 2^B (0..62; 0 = 62). It fixes the key layout without reading the data
-                                back; a wider span is reported as CE_ERANGE in the header. Synchronous
-                                calls measure the span and ignore it. */
+                                back (w itself when B + bits(n-1) + 1 <= 63, else ranked weights); a
+                                wider span is reported as CE_ERANGE in the header. Synchronous calls
+                                measure the span and ignore it. */
 } ce_params;
 #define CE_PARAMS_V1_SIZE 32 /* without max_dt */
 #define CE_PARAMS_V2_SIZE 40 /* without the thresholds */
@@ -149,8 +160,8 @@ size_t ce_workspace_bytes(int64_t n, int64_t num_vertices, const ce_params *para
 /*
  * Cluster the n temporal edges (src[i], dst[i], t[i]) (Alg. 4).
  *   src, dst : int32[n], vertex ids in [0, V), src[i] != dst[i]
- *   t        : int64[n], seconds; max(t) - min(t) must satisfy
- *              bits(max-min) + bits(n-1) + 1 <= 63 (else CE_ERANGE)
+ *   t        : int64[n], seconds (any unit); max(t) - min(t) < 2^62 (else
+ *              CE_ERANGE); for n > 2^30 also bits(max-min) + bits(n-1) + 1 <= 63
  *   workspace: device buffer of >= ce_workspace_bytes(...) bytes, or NULL to
  *              let the library allocate (stream-ordered) and free it
  *   stream   : a hipStream_t (NULL = default stream)
@@ -180,10 +191,10 @@ ce_status ce_cluster_edges(const int32_t *src, const int32_t *dst, const int64_t
  *   t        : int64[n] DEVICE, seconds
  *   params   : mode must be CE_MODE_UNDIRECTED (directed hypergraphs are not
  *              supported: CE_EINVAL); max_dt and thresholds as for graphs
- * Limits: n <= 2^31-1, nnz <= 2^31-1. The packed key needs
- *   bits(max t - min t) + bits(n-1) + bits(longest run of equal times - 1)
- *   <= 63, else CE_ERANGE. Errors: CE_EINVAL for bad offsets, CE_ERANGE for a
- * member outside [0, V); no output is written on an error.
+ * Limits: n <= 2^31-1, nnz <= 2^31-1, max t - min t < 2^62 (the key as for
+ * graphs, with the longest run of equal times as its tie term). Errors:
+ * CE_EINVAL for bad offsets, CE_ERANGE for a member outside [0, V) or a span
+ * of 2^62 or more; no output is written on an error.
  */
 /*
  * Alg. 5 by connected components, as the paper computes the discrete
@@ -280,9 +291,12 @@ ce_status ce_cluster_batch(const int32_t *src, const int32_t *dst, const int64_t
  * and reads the header.
  *
  * Limits of the asynchronous form: undirected mode only (the causal key's tie
- * width is measured on the data); a workspace must be given; the key layout
- * needs params.time_bits + bits(n-1) + 1 <= 63, checked when the call is made
- * (CE_ERANGE). Kernel timing (ce_timing_enable) is not collected.
+ * width is measured on the data); a workspace must be given; for n > 2^30
+ * the key layout needs params.time_bits + bits(n-1) + 1 <= 63, checked when
+ * the call is made (CE_ERANGE). A declared time_bits with
+ * time_bits + bits(n-1) + 1 <= 63 keeps w itself in the key; a wider (or
+ * undeclared, 0) one ranks the weights, which costs one more sort. Kernel
+ * timing (ce_timing_enable) is not collected.
  */
 #define CE_HDR_WORDS(G) (6 + 5 * (int64_t)(G))
 

@@ -87,22 +87,20 @@ __global__ __launch_bounds__(B) void k_rowpos(const uint32_t *sorted_j, Cnt mc, 
 // A record that is a child of row j joins at row j, so it is one of that row's
 // two endpoints: its input id comes from the row itself (no gathers). Row j is
 // written at its position in the batch, with its graph's local ids.
-__global__ __launch_bounds__(B) void k_rows(const uint64_t *msf_key, const uint64_t *msf_val, const uint32_t *perm,
+__global__ __launch_bounds__(B) void k_rows(const uint64_t *msf_w, const uint64_t *msf_val, const uint32_t *perm,
                                             const uint32_t *kc_u,
                                             const uint32_t *kc_v, const uint32_t *ksize, const uint32_t *rowg,
                                             const uint32_t *rowpos, const uint32_t *moff, const int64_t *eoff,
-                                            Cnt mc, int64_t n, int idbits, int wshift, int hshift, bool one,
-                                            ce_result out) {
+                                            Cnt mc, int64_t n, bool one, ce_result out) {
   const int64_t m = mc.get();
-  const uint64_t idmask = (uint64_t(1) << idbits) - 1;
   for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
-    const uint32_t tr = (uint32_t)msf_val[j];
-    const uint64_t key = msf_key[j];
-    const int64_t w = (int64_t)(key >> wshift);
+    const uint64_t v = msf_val[j];
+    const uint32_t tr = (uint32_t)v;
+    const int64_t w = (int64_t)msf_w[j];
     // one graph: rows stay in place and local ids are the internal ones
     const uint32_t g = one ? 0u : rowg[j], p = one ? (uint32_t)j : rowpos[j], m0 = one ? 0u : moff[g];
     const uint32_t e0 = one ? 0u : (uint32_t)eoff[g], ng = one ? (uint32_t)n : (uint32_t)(eoff[g + 1] - eoff[g]);
-    const uint32_t tid = perm[tr] - e0, hid = (uint32_t)((key >> hshift) & idmask) - e0;
+    const uint32_t tid = perm[tr] - e0, hid = perm[v >> 32] - e0;
     if (out.msf_tail) out.msf_tail[p] = tid;
     if (out.msf_head) out.msf_head[p] = hid;
     if (out.msf_w) out.msf_w[p] = w;
@@ -178,8 +176,7 @@ ce_status stage_graph_rows(Bufs &b, Ws &ws, hipStream_t s) {
 ce_status stage_write_rows(Bufs &b, const ce_result *out, hipStream_t s) {
   const int64_t mb = b.n > 1 ? b.n - 1 : 1;
   CE_LAUNCH(k_rows, dim3(grid_cap(mb, B)), dim3(B), 0, s, b.msf_key, b.msf_val, b.perm, b.kc_u, b.kc_v, b.ksize,
-            b.rowg, b.rowpos, b.moff, b.eoff, Cnt(&b.hdr[H_M], mb), b.n, b.idbits, b.wshift, b.hshift, b.G == 1,
-            *out);
+            b.rowg, b.rowpos, b.moff, b.eoff, Cnt(&b.hdr[H_M], mb), b.n, b.G == 1, *out);
   CE_HIP(hipGetLastError());
   return CE_OK;
 }
@@ -482,6 +479,10 @@ static ce_status run_call(const Call &c, const ce_result *out, ce_counts *counts
       return CE_ERANGE;
     }
     tbits = n > 0 ? bits_for((uint64_t)tmax - (uint64_t)tmin) : 0;
+    if (tbits > 62) {
+      set_error("time span (max t - min t) must be below 2^62");
+      return CE_ERANGE;
+    }
   } else {
     tbits = c.time_bits > 0 ? c.time_bits : 62;
   }
@@ -491,11 +492,10 @@ static ce_status run_call(const Call &c, const ce_result *out, ce_counts *counts
   b.flat = c.causal || hy;
   b.hshift = 1;  // causal and hypergraph modes set their own shifts once the tie terms are known
   b.wshift = b.idbits + 1;
-  b.keybits = b.tbits + b.wshift;
-  // the all-ones word marks an absent edge, so a key may use at most 63 bits
-  if (!b.flat && b.keybits > 63) {
-    set_error(sync ? "time span too wide: bits(span) + bits(n-1) + 1 > 63"
-                   : "declared time_bits too wide: time_bits + bits(n-1) + 1 > 63");
+  // the all-ones word marks an absent edge, so a key may use at most 63 bits:
+  // w itself when it fits, else its rank among the 2n slots' weights
+  if (!b.flat && !choose_key_layout(b, b.slots)) {
+    set_error("time span too wide for this many records: needs bits(span) + bits(n-1) + 1 <= 63, or n <= 2^30");
     return CE_ERANGE;
   }
   if (!sync) CE_TRY(stage_check_span(b, s));
@@ -600,9 +600,10 @@ static int time_bits_of(const ce_params *p) {
 // The key layout of an asynchronous call comes from the declared time_bits; it is checked before anything
 // is enqueued.
 static ce_status check_async_key(int time_bits, int64_t n) {
-  const int tb = time_bits > 0 ? time_bits : 62;
-  if (tb + bits_for((uint64_t)(n > 1 ? n - 1 : 0)) + 1 > 63) {
-    set_error("declared time_bits too wide: time_bits + bits(n-1) + 1 > 63");
+  const int tb = time_bits > 0 ? time_bits : 62, idb = bits_for((uint64_t)(n > 1 ? n - 1 : 0));
+  // w itself, or its rank among the 2n slots' weights
+  if (tb + idb + 1 > 63 && bits_for((uint64_t)(2 * n - 1)) + idb + 1 > 63) {
+    set_error("time span too wide for this many records: needs time_bits + bits(n-1) + 1 <= 63, or n <= 2^30");
     return CE_ERANGE;
   }
   return CE_OK;

@@ -131,15 +131,22 @@ __global__ __launch_bounds__(B) void k_windows(const uint32_t *sk, const uint32_
 }
 
 // writes row e and offers its key to the tail's first Boruvka minimum; returns the key
+// (weight ranks, wraw set: the key without its weight field, the weight to
+// wraw, and no offer until the ranks are known)
 __device__ inline uint64_t emit_row(int64_t e, uint32_t ii, uint32_t s, uint64_t hid, uint64_t th,
                                     const uint32_t *inpos, const uint32_t *sv, const uint64_t *ts,
                                     const uint32_t *tie, int wshift, int hshift, uint64_t *skel_key,
-                                    uint32_t *skel_tail, uint32_t *skel_head, uint64_t *best) {
+                                    uint32_t *skel_tail, uint32_t *skel_head, uint64_t *best, uint64_t *wraw) {
   const uint32_t r = sv[inpos[ii]] >> 1;
-  const uint64_t k = ((th - ts[r]) << wshift) | (hid << hshift) | (uint64_t)tie[ii];
-  skel_key[e] = k;
   skel_tail[e] = r;
   skel_head[e] = s;
+  if (wraw) {
+    skel_key[e] = (hid << hshift) | (uint64_t)tie[ii];
+    wraw[e] = th - ts[r];
+    return NONE64;
+  }
+  const uint64_t k = ((th - ts[r]) << wshift) | (hid << hshift) | (uint64_t)tie[ii];
+  skel_key[e] = k;
   atomicMin((unsigned long long *)&best[r], (unsigned long long)k);
   return k;
 }
@@ -150,7 +157,7 @@ __global__ __launch_bounds__(B) void k_emit_small(const uint32_t *outpos, const 
                                                   const uint64_t *ts, const uint32_t *perm, const uint32_t *tie,
                                                   int64_t n, int wshift, int hshift, uint64_t *skel_key,
                                                   uint32_t *skel_tail, uint32_t *skel_head, uint64_t *best,
-                                                  uint32_t *big, unsigned long long *nbig) {
+                                                  uint64_t *wraw, uint32_t *big, unsigned long long *nbig) {
   for (int64_t q = (int64_t)blockIdx.x * B + threadIdx.x; q < n; q += (int64_t)gridDim.x * B) {
     const uint32_t c = wcnt[q];
     if (c == 0) continue;
@@ -164,10 +171,11 @@ __global__ __launch_bounds__(B) void k_emit_small(const uint32_t *outpos, const 
     uint64_t mn = NONE64;
     for (uint32_t j = 0; j < c; j++) {
       const uint64_t k =
-          emit_row(e0 + j, a + j, s, hid, th, inpos, sv, ts, tie, wshift, hshift, skel_key, skel_tail, skel_head, best);
+          emit_row(e0 + j, a + j, s, hid, th, inpos, sv, ts, tie, wshift, hshift, skel_key, skel_tail, skel_head, best,
+                   wraw);
       mn = k < mn ? k : mn;
     }
-    atomicMin((unsigned long long *)&best[s], (unsigned long long)mn);
+    if (mn != NONE64) atomicMin((unsigned long long *)&best[s], (unsigned long long)mn);
   }
 }
 
@@ -176,7 +184,8 @@ __global__ __launch_bounds__(B) void k_emit_big(const uint32_t *big, const uint3
                                                 const uint32_t *wcnt, const uint32_t *eoff, const uint32_t *inpos,
                                                 const uint32_t *sv, const uint64_t *ts, const uint32_t *perm,
                                                 const uint32_t *tie, int wshift, int hshift, uint64_t *skel_key,
-                                                uint32_t *skel_tail, uint32_t *skel_head, uint64_t *best) {
+                                                uint32_t *skel_tail, uint32_t *skel_head, uint64_t *best,
+                                                uint64_t *wraw) {
   const uint32_t q = big[blockIdx.x];
   const uint32_t c = wcnt[q], s = sv[outpos[q]] >> 1, a = wa[q];
   const uint64_t hid = perm[s], th = ts[s];
@@ -184,7 +193,8 @@ __global__ __launch_bounds__(B) void k_emit_big(const uint32_t *big, const uint3
   uint64_t mn = NONE64;
   for (uint32_t j = threadIdx.x; j < c; j += B) {
     const uint64_t k =
-        emit_row(e0 + j, a + j, s, hid, th, inpos, sv, ts, tie, wshift, hshift, skel_key, skel_tail, skel_head, best);
+        emit_row(e0 + j, a + j, s, hid, th, inpos, sv, ts, tie, wshift, hshift, skel_key, skel_tail, skel_head, best,
+                 wraw);
     mn = k < mn ? k : mn;
   }
   mn = wave_min_u64(mn);
@@ -204,6 +214,8 @@ __global__ void k_put_u64(uint64_t *p, uint64_t v) { *p = v; }
 size_t stage_causal_skeleton_scratch(int64_t n) {
   const int64_t n2 = 2 * n;
   Ws w;
+  w.alloc<uint64_t>(n2);  // raw weights, when the weights are ranked
+  const size_t r0 = w.off;
   for (int k = 0; k < 4; k++) w.alloc<uint32_t>(n2);  // ikey, ival and their ping-pong copies
   // phase 1: the time sort's arrays, then the runs of equal times beside them
   Ws a;
@@ -223,13 +235,17 @@ size_t stage_causal_skeleton_scratch(int64_t n) {
   const size_t p3 = c.off + scan_ws_bytes(n2 + 1);
   size_t x = p1 > p2 ? p1 : p2;
   if (p3 > x) x = p3;
-  return w.off + x + 4096;
+  x += w.off;
+  const size_t rk = r0 + stage_rank_weights_scratch(n2);
+  return (x > rk ? x : rk) + 4096;
 }
 
 ce_status stage_causal_skeleton(const int32_t *src, const int32_t *dst, const int64_t *t, Bufs &b, Ws &ws,
                                 hipStream_t s) {
   const int64_t n = b.n, n2 = 2 * n;
   size_t m0 = ws.mark();
+  uint64_t *wraw = ws.alloc<uint64_t>(n2);  // raw weights, when the weights are ranked
+  const size_t mr = ws.mark();
   uint32_t *ikey = ws.alloc<uint32_t>(n2);
   uint32_t *ival = ws.alloc<uint32_t>(n2);
   uint32_t *ikey_alt = ws.alloc<uint32_t>(n2);
@@ -293,17 +309,18 @@ ce_status stage_causal_skeleton(const int32_t *src, const int32_t *dst, const in
   b.jbits = bits_for(maxtie);
   b.hshift = b.jbits;
   b.wshift = b.idbits + b.jbits;
-  b.keybits = b.tbits + b.wshift;
-  if (b.keybits > 63) {  // the all-ones word marks an absent edge
-    set_error("time span too wide for the causal key: bits(span) + bits(n-1) + bits(largest equal-time "
+  if (!choose_key_layout(b, S)) {  // the all-ones word marks an absent edge
+    set_error("too many records for the causal key: bits(rows - 1) + bits(n-1) + bits(largest equal-time "
               "in-degree - 1) > 63");
     return CE_ERANGE;
   }
+  uint64_t *wr = b.rank ? wraw : nullptr;
   // 4. rows, each offering its key to both records' first Boruvka minimum
   CE_LAUNCH(k_fill_best, dim3(grid_for(n, B)), dim3(B), 0, s, b.best, n);
   CE_LAUNCH(k_zero_u64, dim3(1), dim3(1), 0, s, &b.hdr[7]);
   CE_LAUNCH(k_emit_small, dim3(grid_for(n, B)), dim3(B), 0, s, outpos, wa, wcnt, eoff, inpos, sv, b.ts, b.perm, tie, n,
-            b.wshift, b.hshift, b.skel_key, b.skel_tail, b.skel_tid, b.best, big, (unsigned long long *)&b.hdr[7]);
+            b.wshift, b.hshift, b.skel_key, b.skel_tail, b.skel_tid, b.best, wr, big,
+            (unsigned long long *)&b.hdr[7]);
   CE_HIP(hipGetLastError());
   uint64_t nbig = 0;
   CE_TRY(read_u64(&b.hdr[7], &nbig, 1, s));
@@ -313,9 +330,11 @@ ce_status stage_causal_skeleton(const int32_t *src, const int32_t *dst, const in
   }
   if (nbig > 0)
     CE_LAUNCH(k_emit_big, dim3((unsigned)nbig), dim3(B), 0, s, big, outpos, wa, wcnt, eoff, inpos, sv, b.ts, b.perm,
-              tie, b.wshift, b.hshift, b.skel_key, b.skel_tail, b.skel_tid, b.best);
+              tie, b.wshift, b.hshift, b.skel_key, b.skel_tail, b.skel_tid, b.best, wr);
   CE_LAUNCH(k_put_u64, dim3(1), dim3(1), 0, s, &b.hdr[H_C7], (uint64_t)S);  // the rows, for Boruvka's first round
   CE_HIP(hipGetLastError());
+  ws.release(mr);
+  if (b.rank) CE_TRY(stage_rank_weights(b, wraw, S, ws, s));
   ws.release(m0);
   return CE_OK;
 }

@@ -364,6 +364,9 @@ struct Bufs {
   // packed key = w << wshift | head id << hshift | low bits (undirected: one
   // bit ordering the two edges of a head; causal: the tail's tie index)
   int wshift = 0, hshift = 0, jbits = 0;
+  // weight ranks: the key's weight field holds the rank of w among the
+  // skeleton's distinct weights (when w itself would not fit the key word)
+  bool rank = false;
   // flat skeleton (causal and hypergraph modes): rows in slots 0..S-1, each
   // with its head rank in skel_tid; otherwise slot 2h+side belongs to head h
   bool flat = false;
@@ -416,6 +419,12 @@ size_t stage_graph_rows_scratch(int64_t n, int64_t G);
 ce_status stage_write_rows(Bufs &b, const ce_result *out, hipStream_t s);
 
 size_t stage_sort_skeleton_scratch(int64_t n);
+// weight ranks of the first cnt skeleton slots from their raw weights (any mode)
+ce_status stage_rank_weights(Bufs &b, uint64_t *wraw, int64_t cnt, Ws &ws, hipStream_t s);
+size_t stage_rank_weights_scratch(int64_t cnt);
+// the key layout for a time span of tbits bits: w itself, or its rank among at
+// most `rows` distinct weights; false when neither fits the 63-bit key
+bool choose_key_layout(Bufs &b, int64_t rows);
 ce_status sort_records_by_time(const int32_t *src, const int32_t *dst, const int64_t *t, Bufs &b, Ws &ws,
                                hipStream_t s, const uint4 **vals);
 ce_status stage_causal_skeleton(const int32_t *src, const int32_t *dst, const int64_t *t, Bufs &b, Ws &ws,

@@ -81,11 +81,11 @@ __global__ __launch_bounds__(B) void k_cd_birth(const uint32_t *kc_u, const uint
 // lambda of every row: of its weight, or with thresholds (the discrete
 // dendrogram of Alg. 5) of its level's threshold, level = the first threshold
 // the weight does not exceed
-__global__ __launch_bounds__(B) void k_row_lambda(const uint64_t *msf_key, int wshift, Cnt mc, const int64_t *thr,
-                                                  int q, uint64_t *rowL, uint32_t *level) {
+__global__ __launch_bounds__(B) void k_row_lambda(const uint64_t *msf_w, Cnt mc, const int64_t *thr, int q,
+                                                  uint64_t *rowL, uint32_t *level) {
   const int64_t m = mc.get();
   for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
-    const int64_t w = (int64_t)(msf_key[j] >> wshift);
+    const int64_t w = (int64_t)msf_w[j];
     if (q == 0) {
       rowL[j] = lambda_of(w);
       continue;
@@ -1120,7 +1120,7 @@ ce_status stage_condense(Bufs &b, const ce_result *out, Ws &ws, hipStream_t s, i
   CE_LAUNCH(k_cd_bigroots, dim3(gm), dim3(B), 0, s, kpar, b.ksize, b.rowg, m, n, M, nbig);
   CE_LAUNCH(k_fill32, dim3(grid_cap((mb + 4) / 4, B)), dim3(B), 0, s, (uint32_t *)isbirth, (mb + 4) / 4, 0u);
   CE_HIP(hipGetLastError());
-  CE_LAUNCH(k_row_lambda, dim3(gm), dim3(B), 0, s, b.msf_key, b.wshift, m, b.thr, b.q, rowL, level);
+  CE_LAUNCH(k_row_lambda, dim3(gm), dim3(B), 0, s, b.msf_key, m, b.thr, b.q, rowL, level);
   CE_LAUNCH(k_cd_birth, dim3(gm), dim3(B), 0, s, b.kc_u, b.kc_v, b.ksize, kpar, rowL, b.q > 0, m, n, M, nbig, b.rowg,
             isbirth, birthL);
   CE_HIP(hipGetLastError());

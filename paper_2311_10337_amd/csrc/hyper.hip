@@ -156,15 +156,20 @@ __global__ __launch_bounds__(B) void k_hemit(const uint32_t *sk, const uint32_t 
                                              int64_t nnz, const uint64_t *ts, const uint32_t *perm, const uint32_t *f,
                                              const uint32_t *fx, const uint32_t *start, int wshift, int hshift,
                                              uint64_t *skel_key, uint32_t *skel_tail, uint32_t *skel_head,
-                                             uint64_t *best) {
+                                             uint64_t *best, uint64_t *wraw) {
   for (int64_t k = (int64_t)blockIdx.x * B + threadIdx.x; k < nnz; k += (int64_t)gridDim.x * B) {
     if (pos[k + 1] == pos[k]) continue;
     const uint32_t tl = sv[k - 1], hd = sv[k], e = pos[k];
     const uint32_t tie = start[fx[tl] + f[tl]] - 1u - tl;
-    const uint64_t key = ((ts[hd] - ts[tl]) << wshift) | ((uint64_t)perm[hd] << hshift) | (uint64_t)tie;
-    skel_key[e] = key;
     skel_tail[e] = tl;
     skel_head[e] = hd;
+    if (wraw) {  // weight ranks: the weight waits in wraw, the offers wait for the ranks
+      skel_key[e] = ((uint64_t)perm[hd] << hshift) | (uint64_t)tie;
+      wraw[e] = ts[hd] - ts[tl];
+      continue;
+    }
+    const uint64_t key = ((ts[hd] - ts[tl]) << wshift) | ((uint64_t)perm[hd] << hshift) | (uint64_t)tie;
+    skel_key[e] = key;
     // each row offers its key to both hyperedges' first Boruvka minimum
     atomicMin((unsigned long long *)&best[tl], (unsigned long long)key);
     atomicMin((unsigned long long *)&best[hd], (unsigned long long)key);
@@ -186,6 +191,8 @@ ce_status stage_hyper_validate(const int32_t *members, const int64_t *offsets, c
 
 size_t stage_hyper_skeleton_scratch(int64_t n, int64_t nnz) {
   Ws w;
+  w.alloc<uint64_t>(nnz);  // raw weights, when the weights are ranked
+  const size_t r0 = w.off;
   for (int k = 0; k < 4; k++) w.alloc<uint32_t>(nnz);  // ikey, ival and their ping-pong copies
   // phase 1: the time sort, then degrees and their prefix sum
   Ws a;
@@ -206,13 +213,17 @@ size_t stage_hyper_skeleton_scratch(int64_t n, int64_t nnz) {
   size_t x = p1a > p1b ? p1a : p1b;
   if (p2 > x) x = p2;
   if (p3 > x) x = p3;
-  return w.off + x + 4096;
+  x += w.off;
+  const size_t rk = r0 + stage_rank_weights_scratch(nnz);
+  return (x > rk ? x : rk) + 4096;
 }
 
 ce_status stage_hyper_skeleton(const int32_t *members, const int64_t *offsets, const int64_t *t, int64_t nnz,
                                Bufs &b, Ws &ws, hipStream_t s) {
   const int64_t n = b.n;
   size_t m0 = ws.mark();
+  uint64_t *wraw = ws.alloc<uint64_t>(nnz);  // raw weights, when the weights are ranked
+  const size_t mr = ws.mark();
   uint32_t *ikey = ws.alloc<uint32_t>(nnz);
   uint32_t *ival = ws.alloc<uint32_t>(nnz);
   uint32_t *ikey_alt = ws.alloc<uint32_t>(nnz);
@@ -283,18 +294,19 @@ ce_status stage_hyper_skeleton(const int32_t *members, const int64_t *offsets, c
   b.jbits = bits_for(maxtie);
   b.hshift = b.jbits;
   b.wshift = b.idbits + b.jbits;
-  b.keybits = b.tbits + b.wshift;
-  if (b.keybits > 63) {  // the all-ones word marks an absent edge
-    set_error("time span too wide for the hypergraph key: bits(span) + bits(n-1) + bits(longest run of equal "
-              "times - 1) > 63");
+  if (!choose_key_layout(b, S)) {  // the all-ones word marks an absent edge
+    set_error("too many hyperedges for the hypergraph key: bits(rows - 1) + bits(n-1) + bits(longest run of "
+              "equal times - 1) > 63");
     return CE_ERANGE;
   }
   CE_LAUNCH(k_hfill_best, dim3(grid_for(n, B)), dim3(B), 0, s, b.best, n);
   if (nnz > 0)
     CE_LAUNCH(k_hemit, dim3(grid_for(nnz, B)), dim3(B), 0, s, sk, sv, pos, nnz, b.ts, b.perm, f, fx, start,
-              b.wshift, b.hshift, b.skel_key, b.skel_tail, b.skel_tid, b.best);
+              b.wshift, b.hshift, b.skel_key, b.skel_tail, b.skel_tid, b.best, b.rank ? wraw : nullptr);
   CE_LAUNCH(k_hput_u64, dim3(1), dim3(1), 0, s, &b.hdr[H_C7], (uint64_t)S);  // the rows, for Boruvka's first round
   CE_HIP(hipGetLastError());
+  ws.release(mr);
+  if (b.rank) CE_TRY(stage_rank_weights(b, wraw, S, ws, s));
   ws.release(m0);
   return CE_OK;
 }

@@ -153,8 +153,11 @@ __global__ __launch_bounds__(B) void k_skel_tails(const uint32_t *ikey, const ui
 // The low bit orders the two edges of a head by descending tail id; it only
 // decides their order when they have the same weight (else w does), so the
 // tails' ids are read only then.
+// Weight ranks (wraw set): the keys get their tie bits only, the weights go
+// to wraw, and the seeding waits for the ranks.
 __global__ __launch_bounds__(B) void k_skel_keys(uint32_t *skel_tail, const uint64_t *ts, const uint32_t *perm,
-                                                 int64_t n, int idbits, uint64_t *skel_key, uint64_t *best) {
+                                                 int64_t n, int idbits, uint64_t *skel_key, uint64_t *best,
+                                                 uint64_t *wraw) {
   for (int64_t h = (int64_t)blockIdx.x * B + threadIdx.x; h < n; h += (int64_t)gridDim.x * B) {
     uint32_t t0 = skel_tail[2 * h], t1 = skel_tail[2 * h + 1];
     if (t0 != NONE32 && t0 == t1) {  // the same pair twice: one line-graph edge
@@ -169,6 +172,13 @@ __global__ __launch_bounds__(B) void k_skel_keys(uint32_t *skel_tail, const uint
       const uint32_t i0 = perm[t0], i1 = perm[t1];
       b0 = i0 < i1 ? 1u : 0u;
       b1 = 1u - b0;
+    }
+    if (wraw) {
+      skel_key[2 * h] = t0 != NONE32 ? (hid << 1) | b0 : NONE64;
+      skel_key[2 * h + 1] = t1 != NONE32 ? (hid << 1) | b1 : NONE64;
+      wraw[2 * h] = w0;
+      wraw[2 * h + 1] = w1;
+      continue;
     }
     const uint64_t k0 = t0 != NONE32 ? (w0 << (idbits + 1)) | (hid << 1) | b0 : NONE64;
     const uint64_t k1 = t1 != NONE32 ? (w1 << (idbits + 1)) | (hid << 1) | b1 : NONE64;
@@ -764,7 +774,7 @@ __global__ void k_check_rows(uint64_t *hdr, int64_t n) {
   }
 }
 
-// rows with key < limit (rows are sorted, so they are a prefix): one binary
+// rows with weight < limit (rows are sorted, so they are a prefix): one binary
 // search; the prefix becomes the forest (the row count shrinks in place)
 __global__ void k_prefix_below(const uint64_t *key, uint64_t *m, uint64_t limit) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -775,6 +785,50 @@ __global__ void k_prefix_below(const uint64_t *key, uint64_t *m, uint64_t limit)
     else hi = mid;
   }
   *m = (uint64_t)lo;
+}
+
+// ---------------------------------------------------------------- weight ranks
+// When w << wshift does not fit the key word, the key's weight field holds the
+// weight's rank among the distinct weights of the skeleton instead: ranks
+// order exactly as the weights do, so every step that only compares keys is
+// unchanged, and the weights themselves are read back from the times once the
+// forest is known. Absent slots get the value 2^tbits, above every weight.
+__global__ __launch_bounds__(B) void k_rank_absent(const uint64_t *skel_key, int64_t cnt, int tbits, uint64_t *wraw) {
+  for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * B)
+    if (skel_key[i] == NONE64) wraw[i] = uint64_t(1) << tbits;
+}
+// first position of every distinct present weight in sorted order
+__global__ __launch_bounds__(B) void k_rank_flags(const uint64_t *w, int64_t cnt, int tbits, uint32_t *first) {
+  const uint64_t absent = uint64_t(1) << tbits;
+  for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * B)
+    first[i] = w[i] != absent && (i == 0 || w[i] != w[i - 1]) ? 1u : 0u;
+}
+// rank = distinct weights before this one; the finished key is offered to both
+// records' first Boruvka minimum (records start as their own components)
+__global__ __launch_bounds__(B) void k_rank_apply(const uint64_t *w, const uint32_t *slot, const uint32_t *first,
+                                                  const uint32_t *before, int64_t cnt, int tbits, int wshift, bool flat,
+                                                  uint64_t *skel_key, const uint32_t *skel_tail,
+                                                  const uint32_t *skel_tid, uint64_t *best) {
+  const uint64_t absent = uint64_t(1) << tbits;
+  for (int64_t i = (int64_t)blockIdx.x * B + threadIdx.x; i < cnt; i += (int64_t)gridDim.x * B) {
+    if (w[i] == absent) continue;
+    const uint32_t e = slot[i];
+    const uint64_t rank = (uint64_t)(before[i] + first[i] - 1u);
+    const uint64_t k = skel_key[e] | (rank << wshift);
+    skel_key[e] = k;
+    const uint32_t head = flat ? skel_tid[e] : e >> 1;
+    atomicMin((unsigned long long *)&best[skel_tail[e]], (unsigned long long)k);
+    atomicMin((unsigned long long *)&best[head], (unsigned long long)k);
+  }
+}
+// sorted forest rows: the weight itself in place of the key (head minus tail time)
+__global__ __launch_bounds__(B) void k_msf_weights(uint64_t *msf_key, const uint64_t *msf_val, const uint64_t *ts,
+                                                   Cnt mc, int wshift, bool rank) {
+  const int64_t m = mc.get();
+  for (int64_t j = (int64_t)blockIdx.x * B + threadIdx.x; j < m; j += (int64_t)gridDim.x * B) {
+    const uint64_t v = msf_val[j];
+    msf_key[j] = rank ? ts[v >> 32] - ts[(uint32_t)v] : msf_key[j] >> wshift;
+  }
 }
 
 }  // namespace
@@ -833,8 +887,65 @@ ce_status read_validation(Bufs &b, hipStream_t s, uint64_t *flags, int64_t *tmin
   return CE_OK;
 }
 
+bool choose_key_layout(Bufs &b, int64_t rows) {
+  // CE_WEIGHT_RANKS=1 (read on every call) ranks the weights even when they fit
+  const char *e = getenv("CE_WEIGHT_RANKS");
+  const bool force = e && atoi(e) == 1;
+  if (!force && b.tbits + b.wshift <= 63) {
+    b.rank = false;
+    b.keybits = b.tbits + b.wshift;
+    return true;
+  }
+  const int rb = bits_for((uint64_t)(rows > 1 ? rows - 1 : 1));
+  if (rb + b.wshift > 63) return false;
+  b.rank = true;
+  b.keybits = rb + b.wshift;
+  return true;
+}
+
+// Ranks the raw weights of the first cnt skeleton slots (wraw, overwritten)
+// and completes their keys and the first Boruvka minima; the keys' other bits
+// are in place. Scratch from ws.
+ce_status stage_rank_weights(Bufs &b, uint64_t *wraw, int64_t cnt, Ws &ws, hipStream_t s) {
+  if (cnt <= 0) return CE_OK;
+  size_t m0 = ws.mark();
+  uint32_t *slot = ws.alloc<uint32_t>(cnt), *slot_alt = ws.alloc<uint32_t>(cnt);
+  uint64_t *w_alt = ws.alloc<uint64_t>(cnt);
+  uint32_t *first = ws.alloc<uint32_t>(cnt + 1), *before = ws.alloc<uint32_t>(cnt + 1);
+  CE_WS_CHECK(ws);
+  const unsigned g = grid_cap(cnt, B);
+  CE_LAUNCH(k_rank_absent, dim3(g), dim3(B), 0, s, b.skel_key, cnt, b.tbits, wraw);
+  CE_HIP(hipGetLastError());
+  bool alt = false;
+  CE_TRY((radix_sort_pairs<uint64_t, uint32_t>(wraw, slot, w_alt, slot_alt, Cnt(cnt), 0, b.tbits + 1, true, &alt, ws,
+                                               s)));
+  const uint64_t *w = alt ? w_alt : wraw;
+  const uint32_t *sl = alt ? slot_alt : slot;
+  CE_LAUNCH(k_rank_flags, dim3(g), dim3(B), 0, s, w, cnt, b.tbits, first);
+  CE_HIP(hipGetLastError());
+  CE_TRY(scan_exclusive_u32(first, before, Cnt(cnt), ws, s));
+  CE_LAUNCH(k_rank_apply, dim3(g), dim3(B), 0, s, w, sl, first, before, cnt, b.tbits, b.wshift, b.flat, b.skel_key,
+            b.skel_tail, b.skel_tid, b.best);
+  CE_HIP(hipGetLastError());
+  ws.release(m0);
+  return CE_OK;
+}
+
+size_t stage_rank_weights_scratch(int64_t cnt) {
+  Ws w;
+  w.alloc<uint32_t>(cnt);
+  w.alloc<uint32_t>(cnt);
+  w.alloc<uint64_t>(cnt);
+  w.alloc<uint32_t>(cnt + 1);
+  w.alloc<uint32_t>(cnt + 1);
+  const size_t a = radix_ws_bytes(cnt), c = scan_ws_bytes(cnt + 1);
+  return w.off + (a > c ? a : c) + 4096;
+}
+
 size_t stage_sort_skeleton_scratch(int64_t n) {
   Ws w;
+  w.alloc<uint64_t>(2 * n);  // raw weights, when the weights are ranked
+  const size_t r0 = w.off;
   for (int k = 0; k < 4; k++) w.alloc<uint32_t>(2 * n);  // ikey, ival and their ping-pong copies
   size_t base = w.off;
   w.alloc<uint64_t>(n);  // tkey alt
@@ -842,7 +953,9 @@ size_t stage_sort_skeleton_scratch(int64_t n) {
   w.alloc<uint4>(n);     // ... ping-pong
   size_t a = w.off + radix_ws_bytes(n);
   size_t b2 = base + radix_ws_bytes(2 * n);
-  return (a > b2 ? a : b2) + 4096;
+  size_t c = r0 + stage_rank_weights_scratch(2 * n);
+  if (b2 > a) a = b2;
+  return (a > c ? a : c) + 4096;
 }
 
 // Records by (t, id): stable radix sort on t - tmin carrying (id, global src,
@@ -868,6 +981,8 @@ ce_status stage_sort_skeleton(const int32_t *src, const int32_t *dst, const int6
                               hipStream_t s) {
   const int64_t n = b.n, n2 = 2 * n;
   size_t m0 = ws.mark();
+  uint64_t *wraw = b.rank ? ws.alloc<uint64_t>(n2) : nullptr;  // raw weights until they are ranked
+  size_t m1 = ws.mark();
   uint32_t *ikey = ws.alloc<uint32_t>(n2);
   uint32_t *ival = ws.alloc<uint32_t>(n2);
   uint32_t *ikey_alt = ws.alloc<uint32_t>(n2);
@@ -876,7 +991,7 @@ ce_status stage_sort_skeleton(const int32_t *src, const int32_t *dst, const int6
   // 1. records by (t, id)
   // 2. incidence entries (vertex, 2*rank+side) in rank order, perm by rank
   {
-    size_t m1 = ws.mark();
+    size_t m2 = ws.mark();
     if (b.G == 1 && b.tbits <= 32) {
       uint64_t *kalt = ws.alloc<uint64_t>(n), *v0 = ws.alloc<uint64_t>(n), *v1 = ws.alloc<uint64_t>(n);
       CE_WS_CHECK(ws);
@@ -892,7 +1007,7 @@ ce_status stage_sort_skeleton(const int32_t *src, const int32_t *dst, const int6
       CE_LAUNCH(k_incidence, dim3(grid_for(n, B)), dim3(B), 0, s, vals, n, b.perm, b.grank, ikey);
     }
     CE_HIP(hipGetLastError());
-    ws.release(m1);
+    ws.release(m2);
   }
   // stable sort by vertex keeps every list in rank order
   bool alt = false;
@@ -904,8 +1019,10 @@ ce_status stage_sort_skeleton(const int32_t *src, const int32_t *dst, const int6
   CE_LAUNCH(k_fill_u64, dim3(grid_for(n, B)), dim3(B), 0, s, b.best, n, NONE64);
   CE_HIP(hipGetLastError());
   CE_LAUNCH(k_skel_keys, dim3(grid_for(n, B)), dim3(B), 0, s, b.skel_tail, b.ts, b.perm, n, b.idbits, b.skel_key,
-            b.best);
+            b.best, wraw);
   CE_HIP(hipGetLastError());
+  ws.release(m1);
+  if (b.rank) CE_TRY(stage_rank_weights(b, wraw, n2, ws, s));
   ws.release(m0);
   return CE_OK;
 }
@@ -1044,9 +1161,8 @@ ce_status stage_boruvka(Bufs &b, Ws &ws, hipStream_t s) {
 // its forest is the prefix of the sorted MSF with w <= max_dt.
 ce_status stage_time_filter(Bufs &b, int64_t max_dt, hipStream_t s) {
   if (max_dt < 0) return CE_OK;
-  const unsigned __int128 lim = ((unsigned __int128)max_dt + 1) << b.wshift;
-  if (lim > (unsigned __int128)NONE64) return CE_OK;  // every key is below it: no row is longer
-  CE_LAUNCH(k_prefix_below, dim3(1), dim3(64), 0, s, b.msf_key, &b.hdr[H_M], (uint64_t)lim);
+  // the sorted rows' weights ascend
+  CE_LAUNCH(k_prefix_below, dim3(1), dim3(64), 0, s, b.msf_key, &b.hdr[H_M], (uint64_t)max_dt + 1);
   CE_HIP(hipGetLastError());
   return CE_OK;
 }
@@ -1090,6 +1206,9 @@ ce_status stage_msf_sort(Bufs &b, Ws &ws, hipStream_t s) {
     set_error("internal: sorted forest is not in place");
     return CE_EDEVICE;
   }
+  // the keys have done their work (the order); from here on msf_key holds each row's weight
+  CE_LAUNCH(k_msf_weights, dim3(grid_cap(m.v, B)), dim3(B), 0, s, b.msf_key, b.msf_val, b.ts, m, b.wshift, b.rank);
+  CE_HIP(hipGetLastError());
   ws.release(m0);
   return CE_OK;
 }

@@ -87,13 +87,14 @@ def test_data_errors_in_the_header():
     # the same records within the declared span
     ce.cluster_edges_async(*_dev(s, d, t), 2, 4, outs, ws, hdr, time_bits=8)
     _same_as_oracle(ce.to_numpy(ce.async_result(outs, 4, hdr)), _oracle(s, d, t, 4, 2), "cycle")
-    # host-checked arguments: no workspace, a declared width the key cannot hold, causal mode
+    # host-checked arguments: a declared width beyond the time domain, no workspace, causal mode
     import ctypes
     lib = ce.load_library()
-    p = ce.make_params(2, 4, time_bits=62)
+    p = ce.make_params(2, 4, time_bits=63)
     args = [ctypes.c_void_p(x.data_ptr()) for x in _dev(s, d, t)]
     assert lib.ce_cluster_edges_async(*args, 4, ctypes.byref(p), ctypes.byref(outs.struct),
-                                      ctypes.c_void_p(hdr.data_ptr()), None, 0, None) == ce.CE_ERANGE
+                                      ctypes.c_void_p(hdr.data_ptr()), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                      None) == ce.CE_EINVAL
     p = ce.make_params(2, 4, time_bits=8)
     assert lib.ce_cluster_edges_async(*args, 4, ctypes.byref(p), ctypes.byref(outs.struct),
                                       ctypes.c_void_p(hdr.data_ptr()), None, 0, None) == ce.CE_EINVAL

@@ -165,14 +165,16 @@ def test_errors():
     check(mem, np.array([0, 2, 3, 4], np.int64), t, 3, 2, "after errors")
 
 
-def test_key_range_error():
-    """The packed key needs bits(span) + bits(n-1) + bits(longest equal-time run - 1) <= 64."""
+def test_wide_key_ranks_the_weights():
+    """bits(span) + bits(n-1) + bits(longest equal-time run - 1) > 63: the key holds the weight's rank among
+    the skeleton's distinct weights, and every output still equals the oracle; a span of 2^62 is refused."""
     ce = _ce()
     mem, off = csr([[0, 1], [1, 2], [2, 0], [0, 3], [3, 1]])
     t = np.array([0, 1, 2, (1 << 62) - 1, 5], np.int64)  # 62 + 3 bits
-    note("key range n=5 span 2^62-1")
+    note("wide key n=5 span 2^62-1")
+    check(mem, off, t, 4, 2, "span 2^62-1")
     with pytest.raises(ce.ClusterError) as ei:
-        ce.cluster_hyperedges(*dev(mem, off, t), 2, 4)
+        ce.cluster_hyperedges(*dev(mem, off, np.array([0, 1, 2, 1 << 62, 5], np.int64)), 2, 4)
     assert ei.value.status == ce.CE_ERANGE
     check(mem, off, np.array([0, 1, 2, 3, 5], np.int64), 4, 2, "after range error")
 

@@ -139,7 +139,7 @@ def test_error_paths():
     with pytest.raises(ce.ClusterError) as e:
         ce.cluster_edges(mk([0, 1], torch.int32), mk([1, 2], torch.int32), mk([0, 1], torch.int64), 1, 3)
     assert e.value.status == ce.CE_EINVAL
-    with pytest.raises(ce.ClusterError) as e:  # span needs 63 bits: 63 + bits(n-1)=2 + 1 > 64
+    with pytest.raises(ce.ClusterError) as e:  # a span of 2^63 - 1: at least 2^62 is refused
         ce.cluster_edges(mk([0, 1, 2], torch.int32), mk([1, 2, 3], torch.int32),
                          mk([-(1 << 62), 0, (1 << 62) - 1], torch.int64), 2, 4)
     assert e.value.status == ce.CE_ERANGE
