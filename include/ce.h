@@ -10,7 +10,7 @@
  * (Sec. 5.3) are described with their parameters and entry points below. The
  * library
  *   1. groups each vertex's incident temporal edges and sorts them by time
- *      ("Generate adjacency list", "Sort E_i by time": Alg. 3, Alg. 2),
+ *      (the per-vertex lists of Alg. 3, in time order as in Alg. 2),
  *   2. emits the line-graph skeleton L* = union of node-local MSTs, which for
  *      |t_a - t_b| weights is the path through each time-sorted list
  *      (Alg. 3; Sec. 5.3), never forming the line graph,

@@ -184,7 +184,7 @@ int64_t oracle_full_line_graph(int64_t n, const int32_t *src, const int32_t *dst
 
 /*
  * Tier B, the method's own steps (Alg. 3 with the undirected node-local MST of
- * Sec. 5.3): per vertex, sort E_i by the record order R1, emit each
+ * Sec. 5.3): per vertex, its records in the record order R1, emit each
  * consecutive pair. Emits exactly sum_i (d_i - 1) over vertices with d_i >= 1
  * rows, i.e. 2n - V'. Rows are in vertex order, then list order.
  */
@@ -204,7 +204,7 @@ int64_t oracle_skeleton(int64_t n, const int32_t *src, const int32_t *dst, const
   for (int64_t x = 0; x < V; x++) {
     int64_t d = off[x + 1] - off[x];
     if (d < 2) continue;
-    qsort(lst + off[x], (size_t)d, sizeof(uint32_t), cmp_rec); /* "Sort E_i by time" */
+    qsort(lst + off[x], (size_t)d, sizeof(uint32_t), cmp_rec); /* the vertex's records in time order */
     for (int64_t k = off[x] + 1; k < off[x + 1]; k++) {
       if (out) out[cnt] = make_edge(lst[k - 1], lst[k]);
       cnt++;
@@ -252,15 +252,21 @@ int64_t oracle_causal_line_graph(int64_t n, const int32_t *src, const int32_t *d
 }
 
 /*
- * CAUSAL mode, Tier B: Alg. 2 (node-local MST) at every vertex, united by
- * Alg. 3. The incidence list of vertex x is sorted by time with in-edges
- * before out-edges at equal times and then by id (reading C1); a window
- * collects in-edges; each out-edge is joined to every in-edge in the window,
- * after which only the window's last in-edge stays (an empty window stays
- * empty, reading C3).
+ * CAUSAL mode, Tier B: at every vertex x the minimum spanning forest of the
+ * node-local increment-weighted line graph (Def. 1 restricted to the arcs made
+ * at x: every arrival joined to every departure that is not earlier), which
+ * Thm 2 builds without that graph; the vertices' forests are united as in
+ * Alg. 3. The records at x are ordered by time, arrivals before departures at
+ * equal times, then by id (reading C1). A departure e then needs arcs only
+ * from the arrivals since the departure before it, and from the latest
+ * arrival before that departure: any earlier arrival a reaches that latest
+ * arrival through the previous departure over arcs no heavier than t_e - t_a,
+ * so its own arc to e is the heaviest on a cycle. The first departure takes
+ * every arrival before it; with no arrival before the previous departure
+ * nothing is carried (reading C3).
  */
 static int32_t g_x;          /* the vertex whose list is being sorted */
-static const int32_t *g_dst; /* record heads, to tell in-edges of g_x */
+static const int32_t *g_dst; /* record heads, to tell arrivals at g_x */
 
 static int cmp_causal(const void *pa, const void *pb) {
   uint32_t a = *(const uint32_t *)pa, b = *(const uint32_t *)pb;
@@ -271,13 +277,21 @@ static int cmp_causal(const void *pa, const void *pb) {
   return 0;
 }
 
+/* the arc from arrival a to departure e (Def. 1: weight t_e - t_a) */
+static void put_arc(lg_edge *out, int64_t *cnt, uint32_t a, uint32_t e, const int64_t *t) {
+  if (out) {
+    out[*cnt].tail = a;
+    out[*cnt].head = e;
+    out[*cnt].w = t[e] - t[a];
+  }
+  (*cnt)++;
+}
+
 int64_t oracle_causal_skeleton(int64_t n, const int32_t *src, const int32_t *dst, const int64_t *t, int64_t V,
                                lg_edge *out) {
   int64_t *off;
   uint32_t *lst;
   if (build_incidence(n, src, dst, V, &off, &lst)) return OR_ENOMEM;
-  uint32_t *win = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n ? n : 1));
-  if (!win) { free(off); free(lst); return OR_ENOMEM; }
   g_t = t;
   g_dst = dst;
   int64_t cnt = 0;
@@ -285,26 +299,18 @@ int64_t oracle_causal_skeleton(int64_t n, const int32_t *src, const int32_t *dst
     int64_t d = off[x + 1] - off[x];
     if (d < 2) continue;
     g_x = (int32_t)x;
-    qsort(lst + off[x], (size_t)d, sizeof(uint32_t), cmp_causal); /* "Sort E_i by time" */
-    int64_t wn = 0;
+    qsort(lst + off[x], (size_t)d, sizeof(uint32_t), cmp_causal);
+    int64_t since = off[x];  /* first position after the previous departure */
+    int64_t carried = -1;    /* position of the latest arrival before the previous departure */
+    int64_t latest = -1;     /* position of the latest arrival so far */
     for (int64_t k = off[x]; k < off[x + 1]; k++) {
-      uint32_t e = lst[k];
-      if (dst[e] == x) { /* in-edge: joins the window */
-        win[wn++] = e;
-        continue;
-      }
-      for (int64_t j = 0; j < wn; j++) {
-        if (out) {
-          out[cnt].tail = win[j];
-          out[cnt].head = e;
-          out[cnt].w = t[e] - t[win[j]];
-        }
-        cnt++;
-      }
-      if (wn) { win[0] = win[wn - 1]; wn = 1; }
+      if (dst[lst[k]] == x) { latest = k; continue; }
+      if (carried >= 0) put_arc(out, &cnt, lst[carried], lst[k], t);
+      for (int64_t j = since; j < k; j++)
+        if (dst[lst[j]] == x) put_arc(out, &cnt, lst[j], lst[k], t);
+      carried = latest; since = k + 1;
     }
   }
-  free(win);
   free(off);
   free(lst);
   return cnt;
@@ -934,7 +940,7 @@ int64_t oracle_hyper_skeleton(int64_t n, const int64_t *off, const int32_t *memb
   for (int64_t x = 0; x < V; x++) {
     int64_t d = voff[x + 1] - voff[x];
     if (d < 2) continue;
-    qsort(lst + voff[x], (size_t)d, sizeof(uint32_t), cmp_rec); /* "sort the incident hyperedges" */
+    qsort(lst + voff[x], (size_t)d, sizeof(uint32_t), cmp_rec); /* incident hyperedges in time order */
     for (int64_t k = voff[x] + 1; k < voff[x + 1]; k++) {
       const uint32_t prev = lst[k - 1], cur = lst[k];
       if (out) out[cnt] = make_edge(prev, cur);

@@ -1,7 +1,7 @@
 // Stages A1-A6: validate, group-and-sort by (vertex, time), emit the path
 // skeleton, Boruvka minimum spanning forest, sort the MSF by canonical key.
 //
-// Grouping (Alg. 3 "adjacency list", Alg. 2 "Sort E_i by time"): the records
+// Grouping (the per-vertex incidence lists of Alg. 3, time-sorted as in Alg. 2): the records
 // are first sorted once by (t, id) with a stable radix sort on t - tmin; the
 // position in that order is the record's rank. The 2n incidence entries
 // (vertex, 2*rank+side) are then stably radix-sorted by vertex, so every

@@ -29,13 +29,14 @@ MUTANTS = [
      "if (got >= 0 && (minmem[got] == INT64_MAX || p > minmem[got])) minmem[got] = p;"),
     ("causal: out-edges first at equal times", "if (ia != ib) return ia ? -1 : 1;",
      "if (ia != ib) return ia ? 1 : -1;"),
-    ("causal: window keeps every in-edge", "if (wn) { win[0] = win[wn - 1]; wn = 1; }", "if (0) { wn = 1; }"),
-    ("causal: window emptied after an out-edge", "if (wn) { win[0] = win[wn - 1]; wn = 1; }", "wn = 0;"),
+    ("causal: every earlier arrival joins each departure", "carried = latest; since = k + 1;",
+     "carried = -1;"),
+    ("causal: nothing carried past a departure", "if (carried >= 0) put_arc(", "if (0) put_arc("),
     ("causal: strict temporal causality", "if (src[q] != x || t[r] > t[q]) continue;",
      "if (src[q] != x || t[r] >= t[q]) continue;"),
     ("causal: head-to-head pairs", "if (src[q] != x || t[r] > t[q]) continue;",
      "if (dst[q] != x || q == r || t[r] > t[q]) continue;"),
-    ("causal: window weight reversed", "out[cnt].w = t[e] - t[win[j]];", "out[cnt].w = t[win[j]] - t[e];"),
+    ("causal: arc weight reversed", "out[*cnt].w = t[e] - t[a];", "out[*cnt].w = t[a] - t[e];"),
     ("time filter strict", "if (edges[e].w <= max_dt) edges[k++] = edges[e];",
      "if (edges[e].w < max_dt) edges[k++] = edges[e];"),
     ("discrete levels with strict thresholds", "while (L < q && lw[k] > thr[L]) L++;",
@@ -46,7 +47,7 @@ MUTANTS = [
     ("hyper: meeting tested on the first member only", "for (int64_t k = off[b]; k < off[b + 1] && !meet; k++)",
      "for (int64_t k = off[b]; k < off[b] + 1 && k < off[b + 1] && !meet; k++)"),
     ("hyper: incident lists left unsorted",
-     'qsort(lst + voff[x], (size_t)d, sizeof(uint32_t), cmp_rec); /* "sort the incident hyperedges" */',
+     'qsort(lst + voff[x], (size_t)d, sizeof(uint32_t), cmp_rec); /* incident hyperedges in time order */',
      "/* unsorted */"),
     ("hyper: star instead of path", "out[cnt] = make_edge(prev, cur);", "out[cnt] = make_edge(lst[voff[x]], cur);"),
     ("level components keep edges strictly below", "if (w[e] > thr[l]) continue;", "if (w[e] >= thr[l]) continue;"),
