@@ -88,6 +88,27 @@ typedef enum {
  * ranks the weights even when w fits. */
 typedef enum { CE_MODE_UNDIRECTED = 0, CE_MODE_CAUSAL = 1 } ce_mode;
 
+/* Launch choices of one call: what the autotuner (paper_2311_10337_amd.autotune)
+ * sweeps. None of them changes any output. A zero field takes the next
+ * source: the environment variables CE_RADIX_IPT, CE_LIST_GRID,
+ * CE_KRT_LEVEL_BITS and CE_SPLIT_MIN_EDGES (read on every call), then the
+ * tuning file named by CE_TUNE_FILE (its entry for the call's bucket,
+ * bits(n) and bits(num_vertices); lines "n_bits V_bits maxdeg_bits radix
+ * list_grid krt_bits split" as the autotuner writes them), then the built-in
+ * rules. */
+typedef struct {
+  uint32_t struct_size;           /* = sizeof(ce_tuning) */
+  int32_t radix_keys_per_thread;  /* keys per thread of the radix sorts: 4 (sorts of up to 2^24 keys), 8
+                                     (default) or 16 (pairs of up to 12 bytes) */
+  int32_t list_grid;              /* workgroups of the passes over live lists (compaction, Boruvka minima,
+                                     pointer jumping), 256..65536 (default 4096): with the list length it sets
+                                     the items per thread, up to 16 */
+  int32_t krt_level_bits;         /* dendrogram: the most bits one global level takes, 1..10 (default: a rule
+                                     of the row count) */
+  int64_t split_min_edges;        /* Boruvka's filter split runs from this many live edges (default 2^20);
+                                     < 0: never */
+} ce_tuning;
+
 typedef struct {
   uint32_t struct_size;      /* = sizeof(ce_params); the earlier, shorter layouts are accepted (sizes below) */
   uint32_t mode;             /* ce_mode */
@@ -110,11 +131,19 @@ typedef struct {
                                 back (w itself when B + bits(n-1) + 1 <= 63, else ranked weights); a
                                 wider span is reported as CE_ERANGE in the header. Synchronous calls
                                 measure the span and ignore it. */
+  const ce_tuning *tuning;   /* HOST, or NULL: launch choices (see ce_tuning) */
 } ce_params;
 #define CE_PARAMS_V1_SIZE 32 /* without max_dt */
 #define CE_PARAMS_V2_SIZE 40 /* without the thresholds */
 #define CE_PARAMS_V3_SIZE 56 /* without time_bits */
-#define CE_PARAMS_V4_SIZE 64
+#define CE_PARAMS_V4_SIZE 64 /* without tuning */
+
+/* The launch choices a call of n records over num_vertices vertices with
+ * these params (NULL: none given) would take, after every source of
+ * ce_tuning's fields; 0 in out->krt_level_bits is the built-in rule, -1 in
+ * out->split_min_edges is no split. Pure host function; out->struct_size
+ * must be set. Errors: CE_EINVAL. */
+ce_status ce_resolve_tuning(int64_t n, int64_t num_vertices, const ce_params *params, ce_tuning *out);
 #define CE_MAX_THRESHOLDS 64
 
 /* Caller-allocated DEVICE output buffers. Any pointer may be NULL to skip

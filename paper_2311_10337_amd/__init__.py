@@ -8,8 +8,10 @@ missing library raises.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import os
+import threading
 from typing import NamedTuple, Optional
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -20,11 +22,47 @@ CE_MODE_UNDIRECTED, CE_MODE_CAUSAL = 0, 1
 NONE32 = 0xFFFFFFFF
 
 
+class CeTuning(ctypes.Structure):
+    _fields_ = [("struct_size", ctypes.c_uint32), ("radix_keys_per_thread", ctypes.c_int32),
+                ("list_grid", ctypes.c_int32), ("krt_level_bits", ctypes.c_int32), ("split_min_edges", ctypes.c_int64)]
+
+
+TUNING_KNOBS = ("radix_keys_per_thread", "list_grid", "krt_level_bits", "split_min_edges")
+
+
 class CeParams(ctypes.Structure):
     _fields_ = [("struct_size", ctypes.c_uint32), ("mode", ctypes.c_uint32), ("min_cluster_size", ctypes.c_int64),
                 ("num_vertices", ctypes.c_int64), ("flags", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
                 ("max_dt", ctypes.c_int64), ("thresholds", ctypes.c_void_p), ("num_thresholds", ctypes.c_int64),
-                ("time_bits", ctypes.c_int64)]
+                ("time_bits", ctypes.c_int64), ("tuning", ctypes.c_void_p)]
+
+
+_tuning_state = threading.local()
+
+
+def set_tuning(knobs=None):
+    """Launch choices (a dict over TUNING_KNOBS; missing or 0 = the library's next source) for the calls this
+    thread makes from now on; None clears them. Outputs never depend on them."""
+    if knobs:
+        bad = set(knobs) - set(TUNING_KNOBS)
+        if bad:
+            raise ValueError("unknown tuning knobs: %s" % sorted(bad))
+    _tuning_state.knobs = dict(knobs) if knobs else None
+
+
+def current_tuning():
+    return getattr(_tuning_state, "knobs", None)
+
+
+@contextlib.contextmanager
+def tuned(knobs):
+    """``with tuned({...}):`` -- set_tuning for the block, then the previous choices again."""
+    prev = current_tuning()
+    set_tuning(knobs)
+    try:
+        yield
+    finally:
+        set_tuning(prev)
 
 
 _RESULT_FIELDS = ["msf_tail", "msf_head", "msf_w", "sl_left", "sl_right", "sl_w", "sl_size", "pt_cluster",
@@ -70,7 +108,7 @@ _EXPORTS = ["ce_cluster_edges", "ce_cluster_batch", "ce_workspace_bytes", "ce_ba
             "ce_max_clusters", "ce_last_error", "ce_timing_enable", "ce_timing_read", "ce_server_create",
             "ce_server_destroy", "ce_server_request_bytes", "ce_server_submit", "ce_server_poll",
             "ce_server_get_stats", "ce_cluster_edges_async", "ce_cluster_batch_async", "ce_batch_workspace_bytes_for",
-            "ce_result_status", "ce_cluster_edges_noalloc"]
+            "ce_result_status", "ce_cluster_edges_noalloc", "ce_resolve_tuning"]
 CE_MAX_GRAPHS = 1 << 24
 _lib = None
 
@@ -149,6 +187,9 @@ def load_library(path: str = LIB_PATH):
         lib.ce_timing_enable.restype = ctypes.c_int
         lib.ce_timing_read.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]
         lib.ce_timing_read.restype = ctypes.c_int
+        lib.ce_resolve_tuning.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.POINTER(CeParams),
+                                          ctypes.POINTER(CeTuning)]
+        lib.ce_resolve_tuning.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -165,13 +206,31 @@ def make_params(min_cluster_size: int, num_vertices: int, causal: bool = False, 
     import numpy as np
     mode = CE_MODE_CAUSAL if causal else CE_MODE_UNDIRECTED
     p = CeParams(ctypes.sizeof(CeParams), mode, int(min_cluster_size), int(num_vertices), 0, 0, int(max_dt), None, 0,
-                 int(time_bits))
+                 int(time_bits), None)
+    knobs = current_tuning()
+    if knobs:
+        tu = CeTuning(ctypes.sizeof(CeTuning), *[int(knobs.get(k, 0)) for k in TUNING_KNOBS])
+        p.tuning = ctypes.addressof(tu)
+        p._keep_tuning = tu
     if thresholds is not None and len(thresholds) > 0:
         thr = np.ascontiguousarray(np.asarray(thresholds, dtype=np.int64))
         p.thresholds = thr.ctypes.data
         p.num_thresholds = thr.size
         p._keep = thr
     return p
+
+
+def resolve_tuning(n: int, num_vertices: int, knobs=None) -> dict:
+    """The launch choices the library takes for a call of n records over num_vertices vertices
+    (``ce_resolve_tuning``): the given knobs, else the environment, the CE_TUNE_FILE entry, the rules."""
+    lib = load_library()
+    with tuned(knobs) if knobs is not None else contextlib.nullcontext():
+        p = make_params(2, max(int(num_vertices), 1))
+    out = CeTuning(ctypes.sizeof(CeTuning), 0, 0, 0, 0)
+    st = lib.ce_resolve_tuning(int(n), int(num_vertices), ctypes.byref(p), ctypes.byref(out))
+    if st != CE_OK:
+        raise ClusterError(st, lib.ce_last_error().decode())
+    return {k: int(getattr(out, k)) for k in TUNING_KNOBS}
 
 
 def hdr_words(num_graphs: int = 1) -> int:

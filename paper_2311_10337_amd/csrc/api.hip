@@ -7,6 +7,7 @@
 // into the per-graph ones; each graph keeps its own virtual root, root rule and
 // label numbering, and outputs are renumbered into each graph's local ids.
 #include <string.h>
+#include <sys/stat.h>
 
 #include <mutex>
 #include <string>
@@ -322,12 +323,97 @@ struct Call {
   const int64_t *eoff_h = nullptr, *voff_h = nullptr;  // host offsets (G+1 each), or
   const int64_t *eoff_d = nullptr, *voff_d = nullptr;  // device offsets (asynchronous batches)
   const HyperIn *hy = nullptr;
+  const ce_tuning *tuning = nullptr;
   int64_t M = 2;
   bool causal = false;
   int64_t max_dt = -1;
   Thresholds th;
   int time_bits = 0;  // asynchronous calls: the declared bound on bits(max t - min t)
 };
+
+// ---------------------------------------------------------------- tuning
+namespace {
+
+thread_local Tuning t_tuning;
+
+struct TuneEntry {
+  int nbits = 0, vbits = 0;
+  Tuning t;
+};
+std::mutex g_tune_mu;
+std::string g_tune_path;
+long long g_tune_stamp = -1;
+std::vector<TuneEntry> g_tune;
+
+// The entries of the file named by CE_TUNE_FILE, read again when its name or
+// time stamp changes. Lines: n_bits V_bits maxdeg_bits radix list_grid
+// krt_bits split ('#' starts a comment line); the first entry of a bucket wins.
+std::vector<TuneEntry> tune_entries() {
+  const char *path = getenv("CE_TUNE_FILE");
+  if (!path || !*path) return {};
+  struct stat st;
+  if (stat(path, &st) != 0) return {};
+  const long long stamp = (long long)st.st_mtim.tv_sec * 1000000000LL + st.st_mtim.tv_nsec;
+  std::lock_guard<std::mutex> l(g_tune_mu);
+  if (g_tune_path != path || g_tune_stamp != stamp) {
+    g_tune.clear();
+    if (FILE *f = fopen(path, "r")) {
+      char line[512];
+      while (fgets(line, sizeof line, f)) {
+        if (line[0] == '#') continue;
+        TuneEntry e;
+        int dbits = 0, ipt = 0, grid = 0, kb = 0;
+        long long split = 0;
+        if (sscanf(line, "%d %d %d %d %d %d %lld", &e.nbits, &e.vbits, &dbits, &ipt, &grid, &kb, &split) != 7)
+          continue;
+        if (ipt) e.t.radix_ipt = ipt;  // 0: the built-in choice
+        if (grid) e.t.list_grid = grid;
+        e.t.krt_level_bits = kb;
+        e.t.split_min_edges = split < 0 ? INT64_MAX : (split > 0 ? split : e.t.split_min_edges);
+        g_tune.push_back(e);
+      }
+      fclose(f);
+    }
+    g_tune_path = path;
+    g_tune_stamp = stamp;
+  }
+  return g_tune;
+}
+
+}  // namespace
+
+const Tuning &tuning() { return t_tuning; }
+TuningScope::TuningScope(const Tuning &t) : prev(t_tuning) { t_tuning = t; }
+TuningScope::~TuningScope() { t_tuning = prev; }
+
+Tuning resolve_tuning(int64_t n, int64_t V, const ce_tuning *given) {
+  Tuning t;
+  const int nb = bits_for((uint64_t)(n > 0 ? n : 0)), vb = bits_for((uint64_t)(V > 0 ? V : 0));
+  for (const TuneEntry &e : tune_entries())
+    if (e.nbits == nb && e.vbits == vb) {
+      t = e.t;
+      break;
+    }
+  if (const char *e = getenv("CE_RADIX_IPT")) if (atoi(e)) t.radix_ipt = atoi(e);
+  if (const char *e = getenv("CE_LIST_GRID")) if (atoi(e)) t.list_grid = atoi(e);
+  if (const char *e = getenv("CE_KRT_LEVEL_BITS")) t.krt_level_bits = atoi(e);
+  if (const char *e = getenv("CE_SPLIT_MIN_EDGES")) {
+    const long long v = atoll(e);
+    t.split_min_edges = v > 0 ? (int64_t)v : INT64_MAX;  // 0 turns the split off
+  }
+  if (given && given->struct_size >= sizeof(ce_tuning)) {
+    if (given->radix_keys_per_thread) t.radix_ipt = given->radix_keys_per_thread;
+    if (given->list_grid) t.list_grid = given->list_grid;
+    if (given->krt_level_bits) t.krt_level_bits = given->krt_level_bits;
+    if (given->split_min_edges) t.split_min_edges = given->split_min_edges > 0 ? given->split_min_edges : INT64_MAX;
+  }
+  if (t.radix_ipt != 4 && t.radix_ipt != 8 && t.radix_ipt != 16) t.radix_ipt = 8;
+  if (t.list_grid < 256) t.list_grid = 256;
+  if (t.list_grid > 65536) t.list_grid = 65536;
+  if (t.krt_level_bits < 0) t.krt_level_bits = 0;
+  if (t.krt_level_bits > 10) t.krt_level_bits = 10;
+  return t;
+}
 
 namespace {
 
@@ -385,6 +471,7 @@ __global__ __launch_bounds__(B) void k_header_trivial(const uint64_t *hdr, int64
 static ce_status run_call(const Call &c, const ce_result *out, ce_counts *counts, int64_t *row_offsets,
                           int64_t *cluster_offsets, int64_t *hdr_out, void *workspace, size_t workspace_bytes,
                           hipStream_t s) {
+  const TuningScope scope(resolve_tuning(c.n, c.V, c.tuning));
   const int64_t n = c.n, V = c.V, G = c.G;
   const bool sync = counts != nullptr;
   const HyperIn *hy = c.hy;
@@ -593,8 +680,26 @@ int ce_timing_read(double *total_ms, int64_t *launches) {
   return 0;
 }
 
+static const ce_tuning *tuning_of(const ce_params *p) {
+  return p->struct_size >= sizeof(ce_params) ? p->tuning : nullptr;
+}
+
 static int time_bits_of(const ce_params *p) {
   return p->struct_size >= CE_PARAMS_V4_SIZE ? (int)p->time_bits : 0;
+}
+
+ce_status ce_resolve_tuning(int64_t n, int64_t num_vertices, const ce_params *params, ce_tuning *out) {
+  if (!out || out->struct_size < sizeof(ce_tuning)) {
+    set_error("out must be a ce_tuning with struct_size set");
+    return CE_EINVAL;
+  }
+  if (params) CE_TRY(check_params(params));
+  const Tuning t = resolve_tuning(n, num_vertices, params ? tuning_of(params) : nullptr);
+  out->radix_keys_per_thread = t.radix_ipt;
+  out->list_grid = t.list_grid;
+  out->krt_level_bits = t.krt_level_bits;
+  out->split_min_edges = t.split_min_edges == INT64_MAX ? -1 : t.split_min_edges;
+  return CE_OK;
 }
 
 // The key layout of an asynchronous call comes from the declared time_bits; it is checked before anything
@@ -628,6 +733,7 @@ static ce_status single_call(Call &c, const int32_t *src, const int32_t *dst, co
   c.V = params->num_vertices;
   c.G = 1;
   c.M = params->min_cluster_size;
+  c.tuning = tuning_of(params);
   c.causal = params->mode == CE_MODE_CAUSAL;
   c.max_dt = max_dt_of(params);
   c.time_bits = time_bits_of(params);
@@ -737,6 +843,7 @@ ce_status ce_cluster_hyperedges(const int32_t *members, const int64_t *offsets, 
   c.n = n;
   c.V = params->num_vertices;
   c.M = params->min_cluster_size;
+  c.tuning = tuning_of(params);
   c.max_dt = max_dt_of(params);
   c.hy = &hy;
   CE_TRY(thresholds_of(params, &c.th));
@@ -763,6 +870,7 @@ ce_status ce_cluster_batch(const int32_t *src, const int32_t *dst, const int64_t
   c.eoff_h = edge_offsets;
   c.voff_h = vertex_offsets;
   c.M = params->min_cluster_size;
+  c.tuning = tuning_of(params);
   c.causal = params->mode == CE_MODE_CAUSAL;
   c.max_dt = max_dt_of(params);
   CE_TRY(thresholds_of(params, &c.th));
@@ -804,6 +912,7 @@ ce_status ce_cluster_batch_async(const int32_t *src, const int32_t *dst, const i
   c.eoff_d = edge_offsets;
   c.voff_d = vertex_offsets;
   c.M = params->min_cluster_size;
+  c.tuning = tuning_of(params);
   c.max_dt = max_dt_of(params);
   c.time_bits = time_bits_of(params);
   CE_TRY(thresholds_of(params, &c.th));

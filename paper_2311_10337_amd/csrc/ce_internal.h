@@ -262,6 +262,23 @@ constexpr int CT = 16;
 // its global atomic: hot keys enter the table early, and a tile with many
 // distinct keys should not pay a long probe sequence per element.
 constexpr int HASH_PROBES = 4;
+// Launch choices of the current call (ce_tuning resolved: the call's own
+// fields, the environment, the tuning file, the built-in rules). Set by the
+// entry points for the calling host thread.
+struct Tuning {
+  int radix_ipt = 8;
+  int list_grid = 4096;
+  int krt_level_bits = 0;  // 0: the rule of the row count
+  int64_t split_min_edges = int64_t(1) << 20;  // INT64_MAX: no split
+};
+const Tuning &tuning();
+struct TuningScope {
+  Tuning prev;
+  explicit TuningScope(const Tuning &t);
+  ~TuningScope();
+};
+Tuning resolve_tuning(int64_t n, int64_t V, const ce_tuning *given);
+
 // Items per thread of a tile loop over n items, at most CT: all CT once the
 // launched grid is full, fewer when a short list (a small call, a late round)
 // would otherwise sit in a few workgroups whose threads take their items one

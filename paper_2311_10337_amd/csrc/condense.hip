@@ -990,7 +990,7 @@ static ce_status discrete_births(Bufs &b, Cnt m, const uint32_t *kpar, const uin
                                  uint32_t *top, uint32_t *act, uint32_t *act2, uint64_t *loop, uint32_t *bigcnt,
                                  uint8_t *isbirth, uint64_t *birthL, hipStream_t s) {
   const int64_t n = b.n, M = b.M;
-  const unsigned g = grid_cap(m.v, B), tg = grid_cap(m.v, B, 4096);
+  const unsigned g = grid_cap(m.v, B), tg = grid_cap(m.v, B, tuning().list_grid);
   auto tiles = [](int64_t k, int per = CT) { return (unsigned)((k + (int64_t)B * per - 1) / ((int64_t)B * per)); };
   CE_LAUNCH(k_dd_top_init, dim3(g), dim3(B), 0, s, kpar, level, m, n, top);
   CE_LAUNCH(k_dd_top_active, dim3(tg), dim3(B), 0, s, top, m, n, act, (unsigned long long *)&loop[0]);
@@ -1133,7 +1133,7 @@ ce_status stage_condense(Bufs &b, const ce_result *out, Ws &ws, hipStream_t s, i
   }
   {
     uint64_t *jl = loop + LOOP_J;
-    const unsigned tg = grid_cap(mb, B, 4096);
+    const unsigned tg = grid_cap(mb, B, tuning().list_grid);
     CE_LAUNCH(k_cd_jinit, dim3(tg), dim3(B), 0, s, isbirth, kpar, b.ksize, b.rowg, m, n, M, J, jact,
               (unsigned long long *)&jl[0]);
     const int R = doubling_rounds(mb);
@@ -1203,7 +1203,7 @@ ce_status stage_condense(Bufs &b, const ce_result *out, Ws &ws, hipStream_t s, i
   }
   // excess of mass: enqueued rounds, then the rest in one workgroup
   uint64_t *el = loop + LOOP_EOM;
-  const unsigned tRE = grid_cap(RE, B, 4096);
+  const unsigned tRE = grid_cap(RE, B, tuning().list_grid);
   CE_LAUNCH(k_eom_init, dim3(tRE), dim3(B), 0, s, nch, shi, slo, cprow, nrows, neom, e[0], e[1], ract,
             (unsigned long long *)&el[0]);
   CE_HIP(hipGetLastError());
@@ -1221,8 +1221,8 @@ ce_status stage_condense(Bufs &b, const ce_result *out, Ws &ws, hipStream_t s, i
   CE_HIP(hipGetLastError());
   // the list is empty: both state buffers hold the final values
   uint64_t *tl = loop + LOOP_TOP;
-  CE_LAUNCH(k_eom_select, dim3(grid_cap(R, B, 4096)), dim3(B), 0, s, nch, ch, e[0], shi, slo, nrows, top, nxt, top2,
-            nxt2, cprow, ract, (unsigned long long *)&tl[0]);
+  CE_LAUNCH(k_eom_select, dim3(grid_cap(R, B, tuning().list_grid)), dim3(B), 0, s, nch, ch, e[0], shi, slo, nrows,
+            top, nxt, top2, nxt2, cprow, ract, (unsigned long long *)&tl[0]);
   CE_HIP(hipGetLastError());
   uint32_t *tops[2] = {top, top2}, *nxts[2] = {nxt, nxt2};
   for (int r = 0; r < TOP_ROUNDS; r++)

@@ -386,14 +386,11 @@ __global__ __launch_bounds__(LB) void k_krt_lds(const uint32_t *lu, const uint32
 // Largest number of bits one global level may take: a level of k bits has 2^k
 // sub-intervals run one after another, each over about m / 2^k rows, and a
 // sub-interval needs about 2^19 rows or more to keep enough waves in flight
-// for its random accesses; at most 8 bits (256 sub-intervals). The
-// environment variable CE_KRT_LEVEL_BITS (read on every call) overrides it (1..10).
+// for its random accesses; at most 8 bits (256 sub-intervals). A call's
+// tuning (ce_tuning.krt_level_bits, CE_KRT_LEVEL_BITS) overrides it (1..10).
 int krt_max_level_bits(int64_t m) {
-  const char *e = getenv("CE_KRT_LEVEL_BITS");
-  int forced = e ? atoi(e) : 0;
-  if (forced < 0) forced = 0;
-  if (forced > 10) forced = 10;
-  if (forced) return forced;
+  const int forced = tuning().krt_level_bits;
+  if (forced > 0) return forced;
   int k = bits_for((uint64_t)(m >> 19)) - 1;
   return k < 4 ? 4 : (k > 8 ? 8 : k);
 }

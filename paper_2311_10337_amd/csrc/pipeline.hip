@@ -1045,14 +1045,9 @@ size_t stage_boruvka_scratch(int64_t n, int64_t slots) {
 }
 
 // The filter split runs when the live edges number at least 2^20 and more
-// than twice the components. The environment variable CE_SPLIT_MIN_EDGES
-// (read on every call) overrides the 2^20; 0 turns the split off.
-static int64_t split_min_edges() {
-  const char *e = getenv("CE_SPLIT_MIN_EDGES");
-  if (!e) return int64_t(1) << 20;
-  const long long v = atoll(e);
-  return v > 0 ? (int64_t)v : INT64_MAX;
-}
+// than twice the components. A call's tuning (ce_tuning.split_min_edges,
+// CE_SPLIT_MIN_EDGES) overrides the 2^20 or turns the split off.
+static int64_t split_min_edges() { return tuning().split_min_edges; }
 
 // Rounds the host enqueues after the first: in every round the components
 // that still have live edges at least halve, so bits(n) + 1 rounds end a run
@@ -1092,7 +1087,7 @@ ce_status stage_boruvka(Bufs &b, Ws &ws, hipStream_t s) {
   CE_LAUNCH(k_rankof, dim3(grid_for(n, B)), dim3(B), 0, s, b.perm, n, rankof);
   uint64_t *best = b.best;  // seeded for the first round while the skeleton was emitted
   CE_LAUNCH(k_fill_u8, dim3(grid_for(n2, B)), dim3(B), 0, s, b.msf_flag, n2, (uint8_t)0);
-  const unsigned gN = grid_cap(n, B), gE = grid_cap(n2, B), tE = grid_cap(n2, B, 4096);
+  const unsigned gN = grid_cap(n, B), gE = grid_cap(n2, B), tE = grid_cap(n2, B, tuning().list_grid);
   if (b.flat) {
     // causal and hypergraph skeleton rows can share a head, so every round,
     // the first included, runs on the edge-list form with records as
@@ -1185,7 +1180,7 @@ ce_status stage_msf_sort(Bufs &b, Ws &ws, hipStream_t s) {
   uint32_t *list = ws.alloc<uint32_t>(n);
   CE_WS_CHECK(ws);
   CE_LAUNCH(k_set_u64, dim3(1), dim3(1), 0, s, &b.hdr[H_M], (uint64_t)0);
-  CE_LAUNCH(k_msf_list, dim3(grid_cap(n2, B, 4096)), dim3(B), 0, s, b.msf_flag, n2, list,
+  CE_LAUNCH(k_msf_list, dim3(grid_cap(n2, B, tuning().list_grid)), dim3(B), 0, s, b.msf_flag, n2, list,
             (unsigned long long *)&b.hdr[H_M]);
   CE_LAUNCH(k_check_rows, dim3(1), dim3(64), 0, s, b.hdr, n);
   CE_HIP(hipGetLastError());

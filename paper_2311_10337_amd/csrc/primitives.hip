@@ -168,21 +168,20 @@ namespace {
 
 constexpr int RB = 256;              // block
 constexpr int RW = RB / 64;          // waves per block
-constexpr int RIPT = 8;              // keys per thread
-constexpr int RTILE = RB * RIPT;     // 2048 keys per tile
-constexpr int RWT = RTILE / RW;      // 512 keys per wave (8 chunks of 64)
+// keys per thread (IPT): 4, 8 or 16 (a tuning choice); a tile is RB * IPT keys
 
-template <class K>
+template <class K, int IPT>
 __global__ __launch_bounds__(RB) void k_rs_hist(const K *keys, Cnt nc, int shift, uint32_t *hist,
                                                 int nblocks) {
+  constexpr int TILE = RB * IPT;
   __shared__ uint32_t cnt[RW][256];
   const int64_t n = nc.get();  // tiles past a device count write zero counts
   const int w = threadIdx.x >> 6;
   for (int i = threadIdx.x; i < RW * 256; i += RB) (&cnt[0][0])[i] = 0;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * RTILE;
+  const int64_t base = (int64_t)blockIdx.x * TILE;
 #pragma unroll
-  for (int k = 0; k < RIPT; k++) {
+  for (int k = 0; k < IPT; k++) {
     int64_t i = base + k * RB + threadIdx.x;
     if (i < n) atomicAdd(&cnt[w][(uint32_t)(keys[i] >> shift) & 255u], 1u);
   }
@@ -200,28 +199,29 @@ __device__ inline V iota_value(int64_t i) { return V(i); }
 template <>
 __device__ inline uint4 iota_value<uint4>(int64_t i) { return make_uint4((uint32_t)i, 0u, 0u, 0u); }
 
-template <class K, class V>
+template <class K, class V, int IPT>
 __global__ __launch_bounds__(RB) void k_rs_scatter(const K *kin, const V *vin, K *kout, V *vout, Cnt nc,
                                                    int shift, const uint32_t *hscan, int nblocks, int iota) {
+  constexpr int TILE = RB * IPT, WT = TILE / RW;  // keys per tile, per wave (IPT chunks of 64)
   const int64_t n = nc.get();
-  if ((int64_t)blockIdx.x * RTILE >= n) return;
+  if ((int64_t)blockIdx.x * TILE >= n) return;
   __shared__ uint32_t wcnt[RW][256];
   __shared__ uint32_t dbase[256];
   __shared__ uint32_t lw[RB / 64];
-  __shared__ K skey[RTILE];
-  __shared__ V sval[RTILE];
+  __shared__ K skey[TILE];
+  __shared__ V sval[TILE];
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   for (int i = tid; i < RW * 256; i += RB) (&wcnt[0][0])[i] = 0;
   __syncthreads();
-  const int64_t tbase = (int64_t)blockIdx.x * RTILE;
+  const int64_t tbase = (int64_t)blockIdx.x * TILE;
   const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  K key[RIPT];
-  V val[RIPT];
-  uint32_t off[RIPT];
-  uint32_t dig[RIPT];
+  K key[IPT];
+  V val[IPT];
+  uint32_t off[IPT];
+  uint32_t dig[IPT];
 #pragma unroll
-  for (int c = 0; c < RIPT; c++) {
-    const int64_t i = tbase + (int64_t)w * RWT + c * 64 + lane;
+  for (int c = 0; c < IPT; c++) {
+    const int64_t i = tbase + (int64_t)w * WT + c * 64 + lane;
     const bool valid = i < n;
     K k = valid ? kin[i] : K(0);
     V v = valid ? (iota ? iota_value<V>(i) : vin[i]) : V{};
@@ -261,7 +261,7 @@ __global__ __launch_bounds__(RB) void k_rs_scatter(const K *kin, const V *vin, K
   dbase[tid] = ex;
   __syncthreads();
 #pragma unroll
-  for (int c = 0; c < RIPT; c++) {
+  for (int c = 0; c < IPT; c++) {
     if (dig[c] < 256u) {
       uint32_t p = dbase[dig[c]] + wcnt[w][dig[c]] + off[c];
       skey[p] = key[c];
@@ -270,7 +270,7 @@ __global__ __launch_bounds__(RB) void k_rs_scatter(const K *kin, const V *vin, K
   }
   __syncthreads();
   const int64_t rem = n - tbase;
-  const int valid_n = rem < RTILE ? (int)rem : RTILE;
+  const int valid_n = rem < TILE ? (int)rem : TILE;
   for (int i = tid; i < valid_n; i += RB) {
     K k = skey[i];
     uint32_t d = (uint32_t)(k >> shift) & 255u;
@@ -280,20 +280,23 @@ __global__ __launch_bounds__(RB) void k_rs_scatter(const K *kin, const V *vin, K
   }
 }
 
-}  // namespace
-
-size_t radix_ws_bytes(int64_t n) {
-  int64_t nb = (n + RTILE - 1) / RTILE;
-  size_t h = (size_t)nb * 256;
-  return 2 * (((h + 1) * 4 + 255) & ~size_t(255)) + scan_ws_bytes((int64_t)h) + 512;
+// Up to 2^24 keys a sort may take 4 keys per thread (its histogram is sized
+// for that); larger sorts take at least 8. Pairs wider than 12 bytes take at
+// most 8 (the LDS staging of a 16-key tile would not fit).
+template <class K, class V>
+int radix_ipt(int64_t n) {
+  int ipt = tuning().radix_ipt;
+  if (ipt != 4 && ipt != 8 && ipt != 16) ipt = 8;
+  if (ipt == 4 && n > (int64_t(1) << 24)) ipt = 8;
+  if (ipt == 16 && sizeof(K) + sizeof(V) > 12) ipt = 8;
+  return ipt;
 }
 
-template <class K, class V>
-ce_status radix_sort_pairs(K *k0, V *v0, K *k1, V *v1, Cnt n, int begin_bit, int end_bit, bool iota_values,
-                           bool *result_in_alt, Ws &ws, hipStream_t s) {
-  *result_in_alt = false;
-  if (n.v <= 0) return CE_OK;
-  const int64_t nb64 = (n.v + RTILE - 1) / RTILE;
+template <class K, class V, int IPT>
+ce_status radix_passes(K *k0, V *v0, K *k1, V *v1, Cnt n, int begin_bit, int end_bit, bool iota_values,
+                       bool *result_in_alt, Ws &ws, hipStream_t s) {
+  constexpr int TILE = RB * IPT;
+  const int64_t nb64 = (n.v + TILE - 1) / TILE;
   if (nb64 > 0x7fffffff) return CE_EINVAL;
   const int nb = (int)nb64;
   size_t m = ws.mark();
@@ -306,10 +309,10 @@ ce_status radix_sort_pairs(K *k0, V *v0, K *k1, V *v1, Cnt n, int begin_bit, int
   bool first = true;
   if (end_bit <= begin_bit) end_bit = begin_bit + 1;  // one stable pass still materialises identity values
   for (int shift = begin_bit; shift < end_bit; shift += 8) {
-    CE_LAUNCH((k_rs_hist<K>), dim3((unsigned)nb), dim3(RB), 0, s, ki, n, shift, hist, nb);
+    CE_LAUNCH((k_rs_hist<K, IPT>), dim3((unsigned)nb), dim3(RB), 0, s, ki, n, shift, hist, nb);
     CE_HIP(hipGetLastError());
     CE_TRY(scan_exclusive_u32(hist, hsc, Cnt((int64_t)nb * 256), ws, s));
-    CE_LAUNCH((k_rs_scatter<K, V>), dim3((unsigned)nb), dim3(RB), 0, s, ki, (const V *)vi, ko, vo, n,
+    CE_LAUNCH((k_rs_scatter<K, V, IPT>), dim3((unsigned)nb), dim3(RB), 0, s, ki, (const V *)vi, ko, vo, n,
                        shift, hsc, nb, (first && iota_values) ? 1 : 0);
     CE_HIP(hipGetLastError());
     first = false;
@@ -320,6 +323,32 @@ ce_status radix_sort_pairs(K *k0, V *v0, K *k1, V *v1, Cnt n, int begin_bit, int
   *result_in_alt = alt;
   ws.release(m);
   return CE_OK;
+}
+
+}  // namespace
+
+size_t radix_ws_bytes(int64_t n) {
+  const int64_t tile = RB * (n > (int64_t(1) << 24) ? 8 : 4);  // the smallest tile a sort of n keys takes
+  int64_t nb = (n + tile - 1) / tile;
+  size_t h = (size_t)nb * 256;
+  return 2 * (((h + 1) * 4 + 255) & ~size_t(255)) + scan_ws_bytes((int64_t)h) + 512;
+}
+
+template <class K, class V>
+ce_status radix_sort_pairs(K *k0, V *v0, K *k1, V *v1, Cnt n, int begin_bit, int end_bit, bool iota_values,
+                           bool *result_in_alt, Ws &ws, hipStream_t s) {
+  *result_in_alt = false;
+  if (n.v <= 0) return CE_OK;
+  switch (radix_ipt<K, V>(n.v)) {
+    case 4:
+      return radix_passes<K, V, 4>(k0, v0, k1, v1, n, begin_bit, end_bit, iota_values, result_in_alt, ws, s);
+    case 16:
+      if constexpr (sizeof(K) + sizeof(V) <= 12)
+        return radix_passes<K, V, 16>(k0, v0, k1, v1, n, begin_bit, end_bit, iota_values, result_in_alt, ws, s);
+      [[fallthrough]];
+    default:
+      return radix_passes<K, V, 8>(k0, v0, k1, v1, n, begin_bit, end_bit, iota_values, result_in_alt, ws, s);
+  }
 }
 
 template ce_status radix_sort_pairs<uint64_t, uint32_t>(uint64_t *, uint32_t *, uint64_t *, uint32_t *, Cnt, int,

@@ -24,7 +24,7 @@ def test_library_exports_declared_symbols():
                          "ce_server_poll", "ce_server_get_stats", "ce_cluster_hyperedges",
                          "ce_hyper_workspace_bytes", "ce_level_components", "ce_cluster_edges_async",
                          "ce_cluster_batch_async", "ce_batch_workspace_bytes_for", "ce_result_status",
-                         "ce_cluster_edges_noalloc"}
+                         "ce_cluster_edges_noalloc", "ce_resolve_tuning"}
     for s in syms:
         assert hasattr(lib, s), s
 
@@ -148,7 +148,7 @@ def test_struct_layouts_match_the_header(tmp_path):
     cc = shutil.which("gcc") or shutil.which("cc")
     if cc is None:
         pytest.skip("no C compiler")
-    mirrors = {"ce_params": ce.CeParams, "ce_result": ce.CeResult, "ce_counts": ce.CeCounts,
+    mirrors = {"ce_params": ce.CeParams, "ce_tuning": ce.CeTuning, "ce_result": ce.CeResult, "ce_counts": ce.CeCounts,
                "ce_server_config": ce.CeServerConfig, "ce_request": ce.CeRequest,
                "ce_request_status": ce.CeRequestStatus, "ce_server_stats": ce.CeServerStats}
     lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "ce.h"', "int main(void) {"]
