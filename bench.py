@@ -146,8 +146,39 @@ def roofline_line(ce, profiling, kernel, kms, kcnt, w, m, steps, tag):
 
 
 # --------------------------------------------------------------------------------------------- workloads
-def time_single_graph(ce, w, dev, steps, warmup, causal=False, thr=None, roofline_kernel=None, time_bits=0):
+class tuning_file:
+    """CE_TUNE_FILE set to path (None: unset) for the block, for calls the library resolves itself."""
+
+    def __init__(self, path):
+        self.path = path
+
+    def __enter__(self):
+        self.prev = os.environ.get("CE_TUNE_FILE")
+        if self.path:
+            os.environ["CE_TUNE_FILE"] = self.path
+        else:
+            os.environ.pop("CE_TUNE_FILE", None)
+
+    def __exit__(self, *exc):
+        if self.prev is None:
+            os.environ.pop("CE_TUNE_FILE", None)
+        else:
+            os.environ["CE_TUNE_FILE"] = self.prev
+
+
+def tuned_knobs(ce, n, V):
+    """The autotuner's choice for this bucket from the package's tuning file (None: built-in choices)."""
+    from paper_2311_10337_amd import autotune
+    return autotune.knobs_for(n, V)
+
+
+def time_single_graph(ce, w, dev, steps, warmup, causal=False, thr=None, roofline_kernel=None, knobs=None,
+                      default_steps=0):
+    """Times `steps` calls under the launch choices `knobs` (None: built-in); with default_steps, then that
+    many calls with the built-in choices, whose outputs must be the same. Returns (result, seconds,
+    (kernel ms, kernel launches), device buffers, tuning record or None)."""
     import torch
+    from paper_2311_10337_amd import autotune
     src = torch.from_numpy(w.src).to(dev)
     dst = torch.from_numpy(w.dst).to(dev)
     tt = torch.from_numpy(w.t).to(dev)
@@ -160,22 +191,94 @@ def time_single_graph(ce, w, dev, steps, warmup, causal=False, thr=None, rooflin
         return ce.cluster_edges(src, dst, tt, M, V, outputs=outs, workspace=ws, causal=causal, thresholds=thr)
 
     r = None
-    for i in range(warmup):
-        r = step()
-        log("warmup %d done: m=%d clusters=%d labels=%d" % (i, r.m, r.n_clusters, r.n_labels))
-    torch.cuda.synchronize()
-    if roofline_kernel:
-        ce.timing_enable(roofline_kernel)
-    t0 = time.perf_counter()
-    for i in range(steps):
-        r = step()
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    kms, kcnt = ce.timing_read() if roofline_kernel else (0.0, 0)
-    ce.timing_enable(None)
-    log("timed %d steps in %.3f s (%.1f ms per step)" % (steps, el, 1e3 * el / steps))
+    with ce.tuned(knobs):
+        for i in range(warmup):
+            r = step()
+            log("warmup %d done: m=%d clusters=%d labels=%d" % (i, r.m, r.n_clusters, r.n_labels))
+        torch.cuda.synchronize()
+        if roofline_kernel:
+            ce.timing_enable(roofline_kernel)
+        t0 = time.perf_counter()
+        for i in range(steps):
+            r = step()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        kms, kcnt = ce.timing_read() if roofline_kernel else (0.0, 0)
+        ce.timing_enable(None)
+    log("timed %d steps in %.3f s (%.1f ms per step)%s" % (steps, el, 1e3 * el / steps,
+                                                          ", launch choices %s" % knobs if knobs else ""))
+    tune = None
+    if knobs and default_steps:
+        d_tuned = autotune.result_digest(r)
+        r0 = step()  # built-in choices: warm-up, and the outputs to compare
+        same = autotune.result_digest(r0) == d_tuned
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(default_steps):
+            r = step()
+        torch.cuda.synchronize()
+        el0 = time.perf_counter() - t0
+        tune = {"knobs": knobs, "tuned_ms_per_step": 1e3 * el / steps, "default_ms_per_step": 1e3 * el0 / default_steps,
+                "default_steps": default_steps, "speedup": (el0 / default_steps) / (el / steps),
+                "outputs_identical": same, "resolved": ce.resolve_tuning(w.n, V, knobs)}
+        log("built-in choices: %.1f ms per step, outputs %s" % (1e3 * el0 / default_steps,
+                                                               "identical" if same else "DIFFER"))
+    elif not knobs:
+        tune = {"knobs": {}, "note": "no tuning-file entry for this bucket: built-in choices",
+                "resolved": ce.resolve_tuning(w.n, V)}
     del ws
-    return r, el, (kms, kcnt), (src, dst, tt, outs)
+    return r, el, (kms, kcnt), (src, dst, tt, outs), tune
+
+
+def bench_small_calls(ce, dev, n=57_000, calls=50):
+    """One call on a median batch graph (57k records of the batch recipe's generator): synchronous,
+    asynchronous (enqueue, then one wait) and a captured HIP graph replayed; with the launch count."""
+    import torch
+    import synth
+    V = max(2, n // 20)
+    s, d, t = synth.chung_lu_bursts(n, V, 7)
+    ins = [torch.from_numpy(x).to(dev) for x in (s, d, t)]
+    M = 5
+    outs = ce.Outputs(n, M, dev)
+    ws = torch.empty(ce.workspace_bytes(n, V, M), dtype=torch.uint8, device=dev)
+    hdr = torch.zeros(ce.hdr_words(1), dtype=torch.int64, device=dev)
+    for _ in range(5):
+        ce.cluster_edges(*ins, M, V, outputs=outs, workspace=ws)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        ce.cluster_edges(*ins, M, V, outputs=outs, workspace=ws)
+    sync_ms = (time.perf_counter() - t0) / calls * 1e3
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        ce.cluster_edges_async(*ins, M, V, outs, ws, hdr, time_bits=24)
+    enq_ms = (time.perf_counter() - t0) / calls * 1e3
+    torch.cuda.synchronize()
+    async_ms = (time.perf_counter() - t0) / calls * 1e3
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream(device=dev)
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        with torch.cuda.graph(g, stream=side):
+            ce.cluster_edges_async(*ins, M, V, outs, ws, hdr, time_bits=24, stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    for _ in range(3):
+        g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        g.replay()
+    torch.cuda.synchronize()
+    graph_ms = (time.perf_counter() - t0) / calls * 1e3
+    ce.timing_enable("k_")
+    ce.cluster_edges(*ins, M, V, outputs=outs, workspace=ws)
+    _, launches = ce.timing_read()
+    ce.timing_enable(None)
+    log("one %d-record call: sync %.3f ms, async %.3f ms (enqueue %.3f), graph replay %.3f ms, %d launches"
+        % (n, sync_ms, async_ms, enq_ms, graph_ms, launches))
+    return {"n_edges": n, "n_vertices": V, "min_cluster_size": M, "calls": calls, "sync_ms": sync_ms,
+            "async_ms": async_ms, "enqueue_ms": enq_ms, "graph_replay_ms": graph_ms, "launches": launches}
 
 
 def bench_level_components(ce, r, n, thr, calls=3):
@@ -255,7 +358,7 @@ def equal_fields(a, b, counts):
     return bad
 
 
-def bench_batched(dev, steps, warmup):
+def bench_batched(dev, steps, warmup, tuning=True):
     """The 4096-graph batch in one call vs one call per graph, same GPU and inputs. Every one-graph call
     writes into its graph's region of a second output buffer laid out like the batch, and the two buffers
     are compared whole."""
@@ -278,15 +381,31 @@ def bench_batched(dev, steps, warmup):
     def batch_step():
         return ce.cluster_batch(s_d, d_d, t_d, eoff, voff, M, outputs=outs, workspace=ws)
 
-    for _ in range(warmup):
-        batch_step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        br = batch_step()
-    torch.cuda.synchronize()
-    el_b = (time.perf_counter() - t0) / steps
-    log("batched: %.1f ms per batch" % (1e3 * el_b))
+    from paper_2311_10337_amd import autotune
+    knobs = autotune.knobs_for(n, int(voff[-1])) if tuning else None
+    with ce.tuned(knobs):
+        for _ in range(warmup):
+            batch_step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            br = batch_step()
+        torch.cuda.synchronize()
+        el_b = (time.perf_counter() - t0) / steps
+    log("batched: %.1f ms per batch%s" % (1e3 * el_b, ", launch choices %s" % knobs if knobs else ""))
+    tune = None
+    if knobs:
+        d_tuned = autotune.result_digest(br.result)
+        same = autotune.result_digest(batch_step().result) == d_tuned
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            batch_step()
+        torch.cuda.synchronize()
+        el0 = (time.perf_counter() - t0) / steps
+        tune = {"knobs": knobs, "tuned_ms": 1e3 * el_b, "default_ms": 1e3 * el0, "speedup": el0 / el_b,
+                "outputs_identical": same}
+        log("batched, built-in choices: %.1f ms per batch, outputs %s" % (1e3 * el0, "identical" if same else "DIFFER"))
     del ws
     ng = np.diff(eoff)
     vg = np.diff(voff)
@@ -300,13 +419,15 @@ def bench_batched(dev, steps, warmup):
         a, b = int(eoff[g]), int(eoff[g + 1])
         return ce.cluster_edges(s_d[a:b], d_d[a:b], t_d[a:b], M, int(vg[g]), outputs=regions[g], workspace=sws)
 
-    for g in range(min(G, 64)):
-        one(g)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    counts = [one(g) for g in range(G)]
-    torch.cuda.synchronize()
-    el_s = time.perf_counter() - t0
+    # one-graph calls take their own buckets' choices from the tuning file (the library reads it)
+    with tuning_file(autotune.PACKAGE_FILE if tuning else None):
+        for g in range(min(G, 64)):
+            one(g)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        counts = [one(g) for g in range(G)]
+        torch.cuda.synchronize()
+        el_s = time.perf_counter() - t0
     log("one graph per call: %.1f ms for the %d graphs" % (1e3 * el_s, G))
     same_counts = all(c.m == br.m[g] and c.n_clusters == br.n_clusters[g] and c.n_labels == br.n_labels[g]
                       for g, c in enumerate(counts))
@@ -319,6 +440,8 @@ def bench_batched(dev, steps, warmup):
            "single_edges_per_s": n / el_s, "single_ms": 1e3 * el_s,
            "ratio": el_s / el_b, "n_clusters": int(br.n_clusters.sum()), "n_labels": int(br.n_labels.sum()),
            "equal_to_single_calls": equal, "graphs_compared": G}
+    if tune is not None:
+        out["tuning"] = tune
     del s_d, d_d, t_d, outs, single, regions, sws
     torch.cuda.empty_cache()
     return out
@@ -483,6 +606,10 @@ def main():
                     help="skip the batched-vs-one-graph-per-call measurement on the 4096-graph batch")
     ap.add_argument("--roofline-kernel", default="k_krt_union",
                     help="dominant kernel: its launches are timed with HIP events on its stream for the roofline")
+    ap.add_argument("--no-tuning", action="store_true",
+                    help="built-in launch choices only (no tuning-file lookup, no tuned-vs-default comparison)")
+    ap.add_argument("--default-steps", type=int, default=2,
+                    help="calls timed with the built-in launch choices beside tuned ones (0: none)")
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="before the steps, copy a buffer of this many bytes once (a plain copy kernel of known "
                          "size for calibrating HBM counters)")
@@ -534,8 +661,9 @@ def main():
     tag = cfg["workload"] + ("_causal" if causal else "") + ("_discrete" if thr else "")
     if thr:
         cfg["dendrogram"] = "discrete, %d thresholds %d..%d s" % (len(thr), thr[0], thr[-1])
-    r, el, (kms, kcnt), keep = time_single_graph(ce, w, dev, args.steps, args.warmup, causal, thr,
-                                                 args.roofline_kernel)
+    knobs = None if args.no_tuning else tuned_knobs(ce, w.n, w.num_vertices)
+    r, el, (kms, kcnt), keep, tune = time_single_graph(ce, w, dev, args.steps, args.warmup, causal, thr,
+                                                       args.roofline_kernel, knobs, args.default_steps)
     roof = None
     if args.roofline_kernel and kcnt:
         log("kernel %s: %d launches, %.3f ms total, %.1f us avg" % (args.roofline_kernel, kcnt, kms,
@@ -562,6 +690,8 @@ def main():
     if roof is not None:
         line["roofline"] = roof
     line["hbm_pipeline"] = hbm
+    if tune is not None:
+        line["tuning"] = {cfg["workload"]: tune}
     if thr:
         line["discrete_by_components"] = bench_level_components(ce, r, w.n, thr)
     del keep, r
@@ -584,18 +714,24 @@ def main():
     workloads = {}
     for name in [x for x in args.also.split(",") if x and x != args.workload]:
         wx, cfgx = make_workload(name)
-        rx, elx, _, kx = time_single_graph(ce, wx, dev, max(1, min(args.steps, 10)), 1, causal, thr)
-        workloads[cfgx["workload"]] = dict(cfgx, edges_per_s=wx.n * max(1, min(args.steps, 10)) / elx,
-                                           ms_per_step=1e3 * elx / max(1, min(args.steps, 10)), m_msf=rx.m,
-                                           n_clusters=rx.n_clusters, n_labels=rx.n_labels)
+        kn = None if args.no_tuning else tuned_knobs(ce, wx.n, wx.num_vertices)
+        sx = max(1, min(args.steps, 10))
+        rx, elx, _, kx, tx = time_single_graph(ce, wx, dev, sx, 1, causal, thr, knobs=kn, default_steps=sx)
+        workloads[cfgx["workload"]] = dict(cfgx, edges_per_s=wx.n * sx / elx, ms_per_step=1e3 * elx / sx,
+                                           m_msf=rx.m, n_clusters=rx.n_clusters, n_labels=rx.n_labels)
+        if tx is not None:
+            line.setdefault("tuning", {})[cfgx["workload"]] = tx
         del kx, rx, wx
         torch.cuda.empty_cache()
     if workloads:
         line["other_workloads"] = workloads
+    line["small_call"] = bench_small_calls(ce, dev)
     if not args.no_batch:
-        line["batched"] = bench_batched(dev, max(1, min(args.steps, 3)), 1)
+        line["batched"] = bench_batched(dev, max(1, min(args.steps, 3)), 1, tuning=not args.no_tuning)
     if args.serve_requests > 0:
-        line["serving"] = bench_serving(dev, args.serve_requests)
+        from paper_2311_10337_amd import autotune
+        with tuning_file(None if args.no_tuning else autotune.PACKAGE_FILE):
+            line["serving"] = bench_serving(dev, args.serve_requests)
     if args.hyper:
         line["hypergraph"] = bench_hyper(dev, max(1, min(args.steps, 3)), 1)
     if cpu is not None:

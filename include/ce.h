@@ -103,7 +103,7 @@ typedef struct {
   int32_t list_grid;              /* workgroups of the passes over live lists (compaction, Boruvka minima,
                                      pointer jumping), 256..65536 (default 4096): with the list length it sets
                                      the items per thread, up to 16 */
-  int32_t krt_level_bits;         /* dendrogram: the most bits one global level takes, 1..10 (default: a rule
+  int32_t krt_level_bits;         /* dendrogram: the most bits one global level takes, 1..12 (default: a rule
                                      of the row count) */
   int64_t split_min_edges;        /* Boruvka's filter split runs from this many live edges (default 2^20);
                                      < 0: never */

@@ -36,7 +36,7 @@ from typing import Callable, Dict, Optional, Tuple
 from . import tuned
 
 CANDIDATES: Dict[str, Tuple[int, ...]] = {
-    "krt_level_bits": (3, 4, 5, 6, 7, 8),
+    "krt_level_bits": (3, 4, 5, 6, 7, 8, 9, 10, 11, 12),
     "split_min_edges": (1 << 18, 1 << 22, -1),
     "list_grid": (1024, 2048, 8192, 16384),
     "radix_keys_per_thread": (4, 16),
@@ -256,18 +256,12 @@ def main(argv=None):
     else:
         if a.workload == "small":
             s, d, t = synth.chung_lu_bursts(57_000, 2850, 7)
-            V = 2850
-        elif a.workload == "tiny":
-            w = synth.plain_tiny()
-            s, d, t, V = w.src, w.dst, w.t, w.num_vertices
-        elif a.workload == "mid":
-            w = synth.plain_mid()
-            s, d, t, V = w.src, w.dst, w.t, w.num_vertices
+            V, M = 2850, 5
         else:
-            w = synth.plain_scale()
-            s, d, t, V = w.src, w.dst, w.t, w.num_vertices
-        log("%s: n=%d V=%d" % (a.workload, len(t), V))
-        res = tune_edges(*to(s, d, t), 5, V, reps=a.reps, path=a.out, log=log)
+            w = {"tiny": synth.plain_tiny, "mid": synth.plain_mid, "scale": synth.plain_scale}[a.workload]()
+            s, d, t, V, M = w.src, w.dst, w.t, w.num_vertices, w.min_cluster_size
+        log("%s: n=%d V=%d M=%d" % (a.workload, len(t), V, M))
+        res = tune_edges(*to(s, d, t), M, V, reps=a.reps, path=a.out, log=log)
     log("bucket %s: %s, %.3f ms -> %.3f ms (%s)" % (res["bucket"], res["knobs"] or "built-in", res["default_ms"],
                                                     res["tuned_ms"], res.get("file")))
     return res

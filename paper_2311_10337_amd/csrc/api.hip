@@ -411,7 +411,7 @@ Tuning resolve_tuning(int64_t n, int64_t V, const ce_tuning *given) {
   if (t.list_grid < 256) t.list_grid = 256;
   if (t.list_grid > 65536) t.list_grid = 65536;
   if (t.krt_level_bits < 0) t.krt_level_bits = 0;
-  if (t.krt_level_bits > 10) t.krt_level_bits = 10;
+  if (t.krt_level_bits > 12) t.krt_level_bits = 12;
   return t;
 }
 

@@ -383,16 +383,34 @@ __global__ __launch_bounds__(LB) void k_krt_lds(const uint32_t *lu, const uint32
 
 }  // namespace
 
-// Largest number of bits one global level may take: a level of k bits has 2^k
-// sub-intervals run one after another, each over about m / 2^k rows, and a
-// sub-interval needs about 2^19 rows or more to keep enough waves in flight
-// for its random accesses; at most 8 bits (256 sub-intervals). A call's
-// tuning (ce_tuning.krt_level_bits, CE_KRT_LEVEL_BITS) overrides it (1..10).
+// Largest number of bits one global level may take. The global bits
+// (L - 9 for rows j < 2^L) are split into levels; a level of k bits runs 2^k
+// sub-intervals one after another. Every level costs a pass of random
+// accesses over all rows (its reset, relabels, unions and sums: about 0.4 ns
+// per row, fitted to runs at 5e7 and 2^30 rows), and every sub-interval two
+// dependent launches (about 20 us), every level one more (15 us). The plan
+// takes the level count with the least modelled time: few wide levels for
+// large m (two at 5e7 and 2^30 rows), narrow ones when launches dominate. A
+// call's tuning (ce_tuning.krt_level_bits, CE_KRT_LEVEL_BITS) overrides it
+// (1..12).
 int krt_max_level_bits(int64_t m) {
   const int forced = tuning().krt_level_bits;
   if (forced > 0) return forced;
-  int k = bits_for((uint64_t)(m >> 19)) - 1;
-  return k < 4 ? 4 : (k > 8 ? 8 : k);
+  const int gbits = bits_for((uint64_t)(m > 1 ? m - 1 : 1)) - 9;
+  if (gbits <= 1) return 1;
+  double best = 1e30;
+  int kbest = gbits;
+  for (int nlev = 1; nlev <= gbits; nlev++) {
+    const int hi = (gbits + nlev - 1) / nlev, lo = gbits / nlev, nhi = gbits % nlev;
+    if (hi > 12) continue;
+    const double steps = (double)nhi * (double)(1 << hi) + (double)(nlev - nhi) * (double)(1 << lo);
+    const double t = nlev * (0.4e-9 * (double)m + 15e-6) + steps * 20e-6;
+    if (t < best) {
+      best = t;
+      kbest = hi;
+    }
+  }
+  return kbest;
 }
 
 size_t stage_dendrogram_scratch(int64_t n) {

@@ -56,7 +56,7 @@ def test_sources_in_order(clean_env, tmp_path):
 
 def test_limits(clean_env):
     got = ce.resolve_tuning(100, 10, {"radix_keys_per_thread": 5, "list_grid": 7, "krt_level_bits": 99})
-    assert got == {"radix_keys_per_thread": 8, "list_grid": 256, "krt_level_bits": 10, "split_min_edges": 1 << 20}
+    assert got == {"radix_keys_per_thread": 8, "list_grid": 256, "krt_level_bits": 12, "split_min_edges": 1 << 20}
     clean_env.setenv("CE_SPLIT_MIN_EDGES", "0")  # 0 turns the split off
     assert ce.resolve_tuning(100, 10)["split_min_edges"] == -1
     assert ce.resolve_tuning(100, 10, {"list_grid": 1 << 20})["list_grid"] == 65536
