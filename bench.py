@@ -123,7 +123,7 @@ def compare_numpy(got, ref, fields=FIELDS):
 
 
 # ---------------------------------------------------------------------------------------------- roofline
-def roofline_line(ce, profiling, kernel, kms, kcnt, w, m, steps, tag):
+def roofline_line(ce, profiling, kernel, kms, kcnt, w, m, steps, tag, level_bits=0):
     """Roofline of the dominant kernel against the path's algorithmic bytes: the dendrogram stage's share of
     the per-edge model (bytes of the dendrogram rows per MSF row) spread over the kernel's launches, divided by
     its average launch time. The kernel's own access model and the counter traffic are given beside it."""
@@ -131,7 +131,7 @@ def roofline_line(ce, profiling, kernel, kms, kcnt, w, m, steps, tag):
     per_launch = per_row * m * steps / kcnt
     avg_s = kms / kcnt * 1e-3
     achieved = per_launch / avg_s / 1e9
-    unit, model_per_unit, model_units = profiling.algorithmic_bytes_per_step(kernel, w.n, m)
+    unit, model_per_unit, model_units = profiling.algorithmic_bytes_per_step(kernel, w.n, m, level_bits)
     model_per_launch = model_per_unit * model_units * steps / kcnt
     traffic = profiling.load_traffic(kernel, os.path.join(ROOT, "profiles", "%s_%s_pmc.md" % (kernel, tag)))
     return {"bound": "hbm", "achieved": achieved, "peak": profiling.HBM_PEAK_GBS, "unit": "GB/s",
@@ -459,13 +459,15 @@ class Digest:
     def __call__(self, res, n):
         import torch
         parts = []
-        for f in FIELDS:
+        groups = {}
+        for f in FIELDS:  # fields of one length are stacked and digested together
             x = getattr(res, f)
-            k = x.numel()
-            x64 = x.to(torch.int64)
-            parts.append((x64 * self.c[0, :k]).sum())
-            parts.append((x64 * self.c[1, :k]).sum())
-        return torch.stack(parts).cpu().tolist() + [res.m, res.n_clusters, res.n_labels]
+            groups.setdefault(x.numel(), []).append(x.to(torch.int64))
+        for k, xs in groups.items():
+            X = torch.stack(xs)
+            parts.append((X * self.c[0, :k]).sum(dim=1))
+            parts.append((X * self.c[1, :k]).sum(dim=1))
+        return torch.cat(parts).cpu().tolist() + [res.m, res.n_clusters, res.n_labels]
 
 
 def bench_serving(dev, count, workers=3, budget_gib=64, pool=96):
@@ -544,25 +546,43 @@ def bench_serving(dev, count, workers=3, budget_gib=64, pool=96):
     srv.close()
     del bufs
     torch.cuda.empty_cache()
-    # one call per request, inputs already on the GPU
+    # one call per request, inputs already on the GPU: timed one after another on every tenth request (the
+    # rate is scaled by records), then every request once more, four host threads with a stream each, its
+    # outputs digested and compared with the served ones
     dins = [tuple(torch.from_numpy(np.ascontiguousarray(x)).to(dev) for x in r[:3]) + (r[3],) for r in reqs]
-    souts = ce.Outputs(nmax, M, dev)
-    sws = torch.empty(ce.workspace_bytes(nmax, max(r[3] for r in reqs), M), dtype=torch.uint8, device=dev)
-    for k in range(min(count, 16)):
+    vmax = max(r[3] for r in reqs)
+    lanes = 4
+    souts = [ce.Outputs(nmax, M, dev) for _ in range(lanes)]
+    sws = [torch.empty(ce.workspace_bytes(nmax, vmax, M), dtype=torch.uint8, device=dev) for _ in range(lanes)]
+    sample = list(range(0, count, 10))
+    for k in sample[:16]:
         s, d, t, V = dins[k]
-        ce.cluster_edges(s, d, t, M, V, outputs=souts, workspace=sws)
+        ce.cluster_edges(s, d, t, M, V, outputs=souts[0], workspace=sws[0])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for s, d, t, V in dins:
-        ce.cluster_edges(s, d, t, M, V, outputs=souts, workspace=sws)
+    for k in sample:
+        s, d, t, V = dins[k]
+        ce.cluster_edges(s, d, t, M, V, outputs=souts[0], workspace=sws[0])
     torch.cuda.synchronize()
-    wall_single = time.perf_counter() - t0
-    log("one call per request: %.2f s" % wall_single)
-    mismatch = []
-    for k, (s, d, t, V) in enumerate(dins):
-        r = ce.cluster_edges(s, d, t, M, V, outputs=souts, workspace=sws)
-        if digest(r, len(reqs[k][0])) != served[k]:
-            mismatch.append(k)
+    wall_sample = time.perf_counter() - t0
+    rec_sample = int(sum(int(sizes[k]) for k in sample))
+    wall_single = wall_sample * total / rec_sample
+    log("one call per request: %.2f s for %d of the %d requests (%d records), %.2f s scaled to all"
+        % (wall_sample, len(sample), count, rec_sample, wall_single))
+    streams = [torch.cuda.Stream(device=dev) for _ in range(lanes)]
+
+    def check(lane):
+        bad = []
+        with torch.cuda.stream(streams[lane]):
+            for k in range(lane, count, lanes):
+                s, d, t, V = dins[k]
+                r = ce.cluster_edges(s, d, t, M, V, outputs=souts[lane], workspace=sws[lane], stream=streams[lane])
+                if digest(r, len(reqs[k][0])) != served[k]:
+                    bad.append(k)
+        return bad
+
+    with ThreadPoolExecutor(max_workers=lanes) as ex:
+        mismatch = sorted(k for b in ex.map(check, range(lanes)) for k in b)
     log("served vs one call per request: %s" % ("all %d equal" % count if not mismatch
                                                  else "%d DIFFER (first %s)" % (len(mismatch), mismatch[:5])))
     del dins, souts, sws
@@ -579,6 +599,8 @@ def bench_serving(dev, count, workers=3, budget_gib=64, pool=96):
             "saturated_edges_per_s": total / wall_sat, "saturated_batches": st2["batches"] - st1["batches"],
             "max_batch_requests": st2["max_batch_requests"], "max_concurrent_batches": st2["max_concurrent_batches"],
             "single_edges_per_s": total / wall_single, "ratio": wall_single / wall_sat,
+            "single_timed_on": "every tenth request (%d requests, %d records), one call after another; rate "
+                               "scaled by records" % (len(sample), rec_sample),
             "equal_to_single_calls": not mismatch, "requests_compared": count,
             "comparison": "two random 64-bit linear digests of every output field per request"}
 
@@ -606,6 +628,8 @@ def main():
                     help="skip the batched-vs-one-graph-per-call measurement on the 4096-graph batch")
     ap.add_argument("--roofline-kernel", default="k_krt_union",
                     help="dominant kernel: its launches are timed with HIP events on its stream for the roofline")
+    ap.add_argument("--no-small-call", action="store_true",
+                    help="skip the one-call cost of a 57k-record graph (sync, async, replayed HIP graph)")
     ap.add_argument("--no-tuning", action="store_true",
                     help="built-in launch choices only (no tuning-file lookup, no tuned-vs-default comparison)")
     ap.add_argument("--default-steps", type=int, default=2,
@@ -668,7 +692,8 @@ def main():
     if args.roofline_kernel and kcnt:
         log("kernel %s: %d launches, %.3f ms total, %.1f us avg" % (args.roofline_kernel, kcnt, kms,
                                                                   1e3 * kms / kcnt))
-        roof = roofline_line(ce, profiling, args.roofline_kernel, kms, kcnt, w, r.m, args.steps, tag)
+        roof = roofline_line(ce, profiling, args.roofline_kernel, kms, kcnt, w, r.m, args.steps, tag,
+                             (knobs or {}).get("krt_level_bits", 0))
     value = w.n * args.steps / el
     # whole path: HBM traffic per step from the committed counter summary (calibrated FETCH_SIZE +
     # WRITE_SIZE over every dispatch of one step), over the step's wall time; and the algorithmic model
@@ -725,7 +750,8 @@ def main():
         torch.cuda.empty_cache()
     if workloads:
         line["other_workloads"] = workloads
-    line["small_call"] = bench_small_calls(ce, dev)
+    if not args.no_small_call:
+        line["small_call"] = bench_small_calls(ce, dev)
     if not args.no_batch:
         line["batched"] = bench_batched(dev, max(1, min(args.steps, 3)), 1, tuning=not args.no_tuning)
     if args.serve_requests > 0:
