@@ -1,6 +1,7 @@
 // Internal declarations shared by the HIP translation units of libce.
 // gfx950 (CDNA4) only: 64-wide wavefronts, 160 KB LDS per CU.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <stddef.h>
 #include <stdint.h>
@@ -41,35 +42,35 @@ void set_error(const std::string &msg);
   } while (0)
 
 // ------------------------------------------------------- kernel timing
-// When enabled for a kernel name (ce_timing_enable), every launch whose
-// name contains it is bracketed by HIP events on the launch stream; the
-// elapsed times are collected when ce_cluster_edges returns.
+// When enabled for a kernel name (ce_timing_enable), every launch whose name
+// contains it carries a pair of HIP events in its own dispatch
+// (hipExtLaunchKernel), stamped when the kernel starts and ends on the
+// launch stream; the elapsed times are collected when a synchronous call
+// returns.
 bool timing_wants(const char *kernel);
 void timing_push(hipEvent_t a, hipEvent_t b);
 void timing_collect();
 struct KTime {
   hipEvent_t a = nullptr, b = nullptr;
-  hipStream_t s;
   bool on;
-  KTime(const char *name, hipStream_t st) : s(st), on(timing_wants(name)) {
+  explicit KTime(const char *name) : on(timing_wants(name)) {
     if (on) {
       (void)hipEventCreate(&a);
       (void)hipEventCreate(&b);
-      (void)hipEventRecord(a, s);
     }
   }
   void stop() {
-    if (on) {
-      (void)hipEventRecord(b, s);
-      timing_push(a, b);
-    }
+    if (on) timing_push(a, b);
   }
 };
-#define CE_LAUNCH(kernel, grid, block, shmem, stream, ...)              \
-  do {                                                                \
-    ::ce::KTime kt_(#kernel, stream);                                 \
-    hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__); \
-    kt_.stop();                                                       \
+#define CE_LAUNCH(kernel, grid, block, shmem, stream, ...)                                     \
+  do {                                                                                         \
+    ::ce::KTime kt_(#kernel);                                                                  \
+    if (kt_.on)                                                                                \
+      hipExtLaunchKernelGGL(kernel, grid, block, shmem, stream, kt_.a, kt_.b, 0, __VA_ARGS__); \
+    else                                                                                       \
+      hipLaunchKernelGGL(kernel, grid, block, shmem, stream, __VA_ARGS__);                     \
+    kt_.stop();                                                                                \
   } while (0)
 
 // ---------------------------------------------------------- workspace plan
