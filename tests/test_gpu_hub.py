@@ -1,8 +1,8 @@
 """Full-oracle parity on the paths that set the 2^30-record workload apart, at a size the oracle finishes
 in about a minute: an R-MAT graph of 5e7 records whose largest vertex has a planted degree of about 1e7,
 Hawkes times over 365 days (25-bit time span), and the exact dendrogram built with three level plans: the
-default one (three global levels of 6, 6 and 5 bits here; 7, 7 and 7 at 2^30 records), two levels of 9 and
-8 bits, and five levels of 4, 4, 3, 3 and 3 bits (CE_KRT_LEVEL_BITS, read on every call). Every output field
+default one (two global levels of 9 and 8 bits here; 11 and 10 at 2^30 records), three levels of 6, 6 and 5
+bits, and five levels of 4, 4, 3, 3 and 3 bits (CE_KRT_LEVEL_BITS, read on every call). Every output field
 is compared with the oracle's (skeleton tier).
 """
 import os
@@ -46,7 +46,7 @@ def test_planted_hub_year_span_level_plans(live):
     got = {}
     old = os.environ.get("CE_KRT_LEVEL_BITS")
     try:
-        for bits in ("9", "4", None):
+        for bits in ("6", "4", None):
             if bits:
                 os.environ["CE_KRT_LEVEL_BITS"] = bits
             else:
