@@ -470,7 +470,34 @@ class Digest:
         return torch.cat(parts).cpu().tolist() + [res.m, res.n_clusters, res.n_labels]
 
 
-def bench_serving(dev, count, workers=3, budget_gib=64, pool=96):
+class OutputPool:
+    """Output buffers for served requests by size class (capacity 2^c records), made on demand up to a byte
+    cap and recycled after each request is polled and digested."""
+
+    def __init__(self, ce, M, dev, cap_bytes, per_record=72):
+        self.ce, self.M, self.dev, self.cap, self.per = ce, M, dev, cap_bytes, per_record
+        self.free, self.bytes = {}, 0
+
+    def take(self, n, idle):
+        c = max(10, (max(n, 1) - 1).bit_length())
+        for k in sorted(self.free):
+            if k >= c and self.free[k]:
+                return self.free[k].pop()
+        need = (1 << c) * self.per
+        if self.bytes + need > self.cap:
+            if not idle:
+                return None
+            self.free, self.bytes = {}, 0  # nothing in flight: drop the cached buffers and start again
+        self.bytes += need
+        o = self.ce.Outputs(1 << c, self.M, self.dev)
+        o.size_class = c
+        return o
+
+    def give(self, o):
+        self.free.setdefault(o.size_class, []).append(o)
+
+
+def bench_serving(dev, count, workers=3, budget_gib=64, inflight=512, out_gib=24):
     """Open-loop replay of the request stream (Poisson arrivals at 200/s) through the continuous-batching
     server, then the same requests submitted all at once, against one call per request. Each request's
     outputs are digested on the GPU when it is polled and its buffer goes back to a pool; the one-call-per-
@@ -490,46 +517,47 @@ def bench_serving(dev, count, workers=3, budget_gib=64, pool=96):
     total = int(sizes.sum())
     log("serving workload: %d requests, %d records (%.1f s)" % (count, total, time.perf_counter() - t0))
     nmax = int(sizes.max())
-    bufs = [ce.Outputs(nmax, M, dev) for _ in range(pool)]
+    pool = OutputPool(ce, M, dev, out_gib << 30)
     digest = Digest(dev, nmax)
-    srv = ce.Server(budget_gib << 30, workers=workers, max_inflight=pool)
+    srv = ce.Server(budget_gib << 30, workers=workers, max_inflight=inflight)
     served = [None] * count
 
     def replay(arrivals, keep):
         lat = np.zeros(count)
         pending = {}
-        free = list(range(pool))
         k = 0
         first_sub, last_done = None, 0.0
         start = time.perf_counter()
         while k < count or pending:
             progressed = False
             now = time.perf_counter() - start
-            while k < count and now >= arrivals[k] and free:
+            while k < count and now >= arrivals[k] and len(pending) < inflight:
                 s, d, t, V = reqs[k]
-                sub = time.perf_counter() - start
-                b = free[-1]
-                try:
-                    tk = srv.submit(s, d, t, M, V, outputs=bufs[b])
-                except ce.ServerBusy:
+                buf = pool.take(len(s), not pending)
+                if buf is None:
                     break
-                free.pop()
+                sub = time.perf_counter() - start
+                try:
+                    tk = srv.submit(s, d, t, M, V, outputs=buf)
+                except ce.ServerBusy:
+                    pool.give(buf)
+                    break
                 first_sub = sub if first_sub is None else first_sub
-                pending[tk] = (k, sub, b)
+                pending[tk] = (k, sub, buf)
                 k += 1
                 progressed = True
                 now = time.perf_counter() - start
             for tk in list(pending):
                 r = srv.poll(tk)
                 if r is not None:
-                    kk, sub, b = pending.pop(tk)
+                    kk, sub, buf = pending.pop(tk)
                     if r.status != ce.CE_OK:
                         raise RuntimeError("request %d failed: %s" % (kk, r.error))
                     lat[kk] = (sub - arrivals[kk]) + r.latency_s
                     last_done = max(last_done, sub + r.latency_s)
                     if keep:
                         served[kk] = digest(r.result, len(reqs[kk][0]))
-                    free.append(b)
+                    pool.give(buf)
                     progressed = True
             if not progressed:
                 time.sleep(0.0002)
@@ -544,7 +572,7 @@ def bench_serving(dev, count, workers=3, budget_gib=64, pool=96):
     _, wall_sat = replay(np.zeros(count), False)
     st2 = srv.stats()
     srv.close()
-    del bufs
+    del pool
     torch.cuda.empty_cache()
     # one call per request, inputs already on the GPU: timed one after another on every tenth request (the
     # rate is scaled by records), then every request once more, four host threads with a stream each, its
@@ -592,7 +620,8 @@ def bench_serving(dev, count, workers=3, budget_gib=64, pool=96):
     return {"workload": "rmat-hawkes-requests", "requests": count, "n_edges": total, "min_cluster_size": M,
             "seed": 4, "arrivals": "poisson 200 req/s (open loop)",
             "sizes": "lognormal median 70711 sigma 1.42 clipped [1e3, 5e6]; V = 2^ceil(log2(n/16))",
-            "workers": workers, "hbm_budget_bytes": budget_gib << 30,
+            "workers": workers, "hbm_budget_bytes": budget_gib << 30, "max_inflight": inflight,
+            "output_pool_bytes": out_gib << 30,
             "latency_p50_ms": 1e3 * float(np.percentile(lat, 50)), "latency_p99_ms": 1e3 * float(np.percentile(lat, 99)),
             "latency_mean_ms": 1e3 * float(lat.mean()), "open_loop_edges_per_s": total / wall_open,
             "open_loop_batches": st1["batches"] - st0["batches"],
