@@ -37,14 +37,19 @@
  * device. Inputs are read-only and owned by the caller. Outputs are owned by
  * the caller and must hold the documented row counts. Between calls the
  * library keeps only a 4 KiB pinned host page per calling thread (for the
- * small counts it reads back) and the servers the caller creates.
+ * small counts synchronous calls read back), the servers the caller creates,
+ * and on each GPU where ce_cluster_edges_noalloc ran, its static workspace.
  *
- * Tuning (environment, optional; outputs never depend on them):
- *   CE_KRT_LEVEL_BITS   1..10: largest number of row-index bits one global
- *                       dendrogram level takes (read on every call)
+ * Tuning (environment, optional, read on every call; outputs never depend
+ * on them; a call's own ce_tuning takes precedence, see ce_tuning below):
+ *   CE_KRT_LEVEL_BITS   1..12: largest number of row-index bits one global
+ *                       dendrogram level takes
  *   CE_SPLIT_MIN_EDGES  live-edge count from which Boruvka splits its edges
- *                       at a pivot key (default 2^20; 0 = never; read on
- *                       every call)
+ *                       at a pivot key (default 2^20; 0 = never)
+ *   CE_RADIX_IPT        keys per thread of the radix sorts (4, 8, 16)
+ *   CE_LIST_GRID        workgroups of the passes over live lists
+ *   CE_TUNE_FILE        the autotuner's tuning file (per-bucket choices)
+ *   CE_WEIGHT_RANKS     1: rank the weights even when they fit the key
  */
 #ifndef CE_H
 #define CE_H
