@@ -28,7 +28,12 @@ static std::vector<std::pair<hipEvent_t, hipEvent_t>> g_tev;
 static double g_tms = 0.0;
 static int64_t g_tcount = 0;
 
+static thread_local bool t_timing_off = false;
+TimingOff::TimingOff(bool off) : prev(t_timing_off) { t_timing_off = t_timing_off || off; }
+TimingOff::~TimingOff() { t_timing_off = prev; }
+
 bool timing_wants(const char *kernel) {
+  if (t_timing_off) return false;
   std::lock_guard<std::mutex> l(g_tmu);
   return !g_tname.empty() && strstr(kernel, g_tname.c_str()) != nullptr;
 }
@@ -474,6 +479,7 @@ static ce_status run_call(const Call &c, const ce_result *out, ce_counts *counts
   const TuningScope scope(resolve_tuning(c.n, c.V, c.tuning));
   const int64_t n = c.n, V = c.V, G = c.G;
   const bool sync = counts != nullptr;
+  const TimingOff no_timing(!sync);
   const HyperIn *hy = c.hy;
   if (sync)
     for (int64_t g = 0; g < G; g++) counts[g] = ce_counts{0, 1, 0};

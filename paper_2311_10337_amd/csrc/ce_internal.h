@@ -46,8 +46,14 @@ void set_error(const std::string &msg);
 // contains it carries a pair of HIP events in its own dispatch
 // (hipExtLaunchKernel), stamped when the kernel starts and ends on the
 // launch stream; the elapsed times are collected when a synchronous call
-// returns.
+// returns. Asynchronous calls (which may be captured in a graph) are never
+// timed: TimingOff holds timing off on the calling thread for their span.
 bool timing_wants(const char *kernel);
+struct TimingOff {
+  bool prev;
+  explicit TimingOff(bool off);
+  ~TimingOff();
+};
 void timing_push(hipEvent_t a, hipEvent_t b);
 void timing_collect();
 struct KTime {

@@ -208,3 +208,39 @@ def test_captured_call_on_new_inputs():
         graph.replay()
         got = ce.to_numpy(ce.async_result(outs, n, hdr))
         _same_as_oracle(got, _oracle(g.src, g.dst, g.t, V, M), "replay on seed %d" % seed)
+
+
+def test_async_calls_are_not_timed():
+    """Kernel timing (ce_timing_enable) covers synchronous calls only: an asynchronous call, also one captured
+    in a HIP graph, records no events and gives the same outputs."""
+    import paper_2311_10337_amd as ce
+    dev = torch.device("cuda:0")
+    n, V, M = 60_000, 3000, 5
+    g = synth.plain_tiny(seed=61, n=n, V=V)
+    ins = _dev(g.src, g.dst, g.t)
+    outs = ce.Outputs(n, M, dev)
+    ws = torch.empty(ce.workspace_bytes(n, V, M), dtype=torch.uint8, device=dev)
+    hdr = torch.zeros(ce.hdr_words(1), dtype=torch.int64, device=dev)
+    ref = _oracle(g.src, g.dst, g.t, V, M)
+    ce.timing_enable("k_")
+    try:
+        ce.cluster_edges_async(*ins, M, V, outs, ws, hdr, time_bits=24)
+        _same_as_oracle(ce.to_numpy(ce.async_result(outs, n, hdr)), ref, "timed async call")
+        graph = torch.cuda.CUDAGraph()
+        side = torch.cuda.Stream(device=dev)
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            with torch.cuda.graph(graph, stream=side):
+                ce.cluster_edges_async(*ins, M, V, outs, ws, hdr, time_bits=24, stream=torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        outs.t["labels"].fill_(-7)
+        torch.cuda.synchronize()
+        graph.replay()
+        _same_as_oracle(ce.to_numpy(ce.async_result(outs, n, hdr)), ref, "captured call with timing on")
+        ms, launches = ce.timing_read()
+        assert launches == 0
+        ce.cluster_edges(*ins, M, V, outputs=outs, workspace=ws)  # a synchronous call is timed
+        ms, launches = ce.timing_read()
+        assert launches > 100 and ms > 0
+    finally:
+        ce.timing_enable(None)
