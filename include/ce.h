@@ -104,7 +104,7 @@ typedef enum { CE_MODE_UNDIRECTED = 0, CE_MODE_CAUSAL = 1 } ce_mode;
 typedef struct {
   uint32_t struct_size;           /* = sizeof(ce_tuning) */
   int32_t radix_keys_per_thread;  /* keys per thread of the radix sorts: 4 (sorts of up to 2^24 keys), 8
-                                     (default) or 16 (pairs of up to 12 bytes) */
+                                     (default) or 16 */
   int32_t list_grid;              /* workgroups of the passes over live lists (compaction, Boruvka minima,
                                      pointer jumping), 256..65536 (default 4096): with the list length it sets
                                      the items per thread, up to 16 */

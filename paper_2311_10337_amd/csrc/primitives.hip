@@ -281,14 +281,12 @@ __global__ __launch_bounds__(RB) void k_rs_scatter(const K *kin, const V *vin, K
 }
 
 // Up to 2^24 keys a sort may take 4 keys per thread (its histogram is sized
-// for that); larger sorts take at least 8. Pairs wider than 12 bytes take at
-// most 8 (the LDS staging of a 16-key tile would not fit).
-template <class K, class V>
+// for that); larger sorts take at least 8. A 16-key tile stages up to 24 B
+// pairs in LDS: 96 KiB of the 160 KiB a gfx950 workgroup may use.
 int radix_ipt(int64_t n) {
   int ipt = tuning().radix_ipt;
   if (ipt != 4 && ipt != 8 && ipt != 16) ipt = 8;
   if (ipt == 4 && n > (int64_t(1) << 24)) ipt = 8;
-  if (ipt == 16 && sizeof(K) + sizeof(V) > 12) ipt = 8;
   return ipt;
 }
 
@@ -339,13 +337,11 @@ ce_status radix_sort_pairs(K *k0, V *v0, K *k1, V *v1, Cnt n, int begin_bit, int
                            bool *result_in_alt, Ws &ws, hipStream_t s) {
   *result_in_alt = false;
   if (n.v <= 0) return CE_OK;
-  switch (radix_ipt<K, V>(n.v)) {
+  switch (radix_ipt(n.v)) {
     case 4:
       return radix_passes<K, V, 4>(k0, v0, k1, v1, n, begin_bit, end_bit, iota_values, result_in_alt, ws, s);
     case 16:
-      if constexpr (sizeof(K) + sizeof(V) <= 12)
-        return radix_passes<K, V, 16>(k0, v0, k1, v1, n, begin_bit, end_bit, iota_values, result_in_alt, ws, s);
-      [[fallthrough]];
+      return radix_passes<K, V, 16>(k0, v0, k1, v1, n, begin_bit, end_bit, iota_values, result_in_alt, ws, s);
     default:
       return radix_passes<K, V, 8>(k0, v0, k1, v1, n, begin_bit, end_bit, iota_values, result_in_alt, ws, s);
   }
