@@ -68,10 +68,22 @@ def chung_lu_bursts(n, V, seed, gamma=2.1, T=30 * DAY, bmin=5, bmax=50, gap_mean
     return src, dst, t
 
 
-def rmat_hawkes(n, scale, seed, a=0.57, b=0.19, c=0.19, T=90 * DAY, mu=0.01, eta=0.7, beta=300.0, hub_extra=0):
-    """R-MAT endpoints (2**scale vertices), per-pair Hawkes int64 times."""
+def _outputs(n, out):
+    """The caller's (src int32, dst int32, t int64) arrays of n contiguous elements, or new ones."""
+    if out is None:
+        return _alloc(n)
+    src, dst, t = out
+    for x, dt in ((src, np.int32), (dst, np.int32), (t, np.int64)):
+        if x.dtype != dt or x.shape != (n,) or not x.flags["C_CONTIGUOUS"] or not x.flags["WRITEABLE"]:
+            raise ValueError("out arrays must be writable contiguous int32, int32, int64 of length %d" % n)
+    return src, dst, t
+
+
+def rmat_hawkes(n, scale, seed, a=0.57, b=0.19, c=0.19, T=90 * DAY, mu=0.01, eta=0.7, beta=300.0, hub_extra=0,
+                out=None):
+    """R-MAT endpoints (2**scale vertices), per-pair Hawkes int64 times (written into `out` when given)."""
     lib = _load()
-    src, dst, t = _alloc(n)
+    src, dst, t = _outputs(n, out)
     rc = lib.synth_rmat_hawkes(int(n), int(scale), float(a), float(b), float(c), int(T), float(mu), float(eta),
                                float(beta), int(hub_extra), int(seed) & (2**64 - 1),
                                src.ctypes.data, dst.ctypes.data, t.ctypes.data)
@@ -166,10 +178,11 @@ def request_arrivals(count=20000, rate=200.0, seed=4):
     return np.cumsum(exp_gaps(count, 1.0 / rate, seed))
 
 
-def request_graph(r, n_r, seed=4):
-    """Request r: R-MAT over 2^ceil(log2(n_r/16)) vertices, Hawkes times over 90 days, M=10."""
+def request_graph(r, n_r, seed=4, out=None):
+    """Request r: R-MAT over 2^ceil(log2(n_r/16)) vertices, Hawkes times over 90 days, M=10 (written into
+    `out` when given)."""
     scale = max(1, int(math.ceil(math.log2(max(2.0, n_r / 16.0)))))
-    s, d, t = rmat_hawkes(int(n_r), scale, child_seed(seed, r), T=90 * DAY)
+    s, d, t = rmat_hawkes(int(n_r), scale, child_seed(seed, r), T=90 * DAY, out=out)
     return s, d, t, 1 << scale
 
 
