@@ -2,9 +2,10 @@
 the oracle gives for that graph alone (local ids, its own root and labels).
 
 Small and mid-sized batches are checked graph by graph against the oracle; the
-full 4096-graph batch (about 2.4e8 records) is checked on sampled graphs
-against the oracle and against one-graph-per-call runs, and on properties that
-hold for every graph.
+full 4096-graph batch (about 2.4e8 records) is checked on every graph against
+the oracle (digests of every field, the oracle run in 16 host processes), on
+sampled graphs field by field and against one-graph-per-call runs, and on
+properties that hold for every graph.
 """
 import os
 import sys
@@ -196,3 +197,40 @@ def test_batch_full_size_sampled():
         a, b = int(eoff[g]), int(eoff[g + 1])
         V = int(voff[g + 1] - voff[g])
         same(br.graph(int(g)), run_single(src[a:b], dst[a:b], t[a:b], V, M), "full batch graph %d vs single" % g)
+
+
+@pytest.mark.timeout(900)
+def test_batch_every_graph_against_the_oracle():
+    """Every graph of the 4096-graph batch (one call on the GPU) against the oracle run on that graph alone:
+    digests of every output field, the oracle in worker processes that regenerate each graph from its seed."""
+    import multiprocessing
+    from concurrent.futures import ProcessPoolExecutor
+    import oracle_digests
+    ce = _ce()
+    G, M, seed = 4096, 5, 3
+    sizes = synth.batch_sizes(G, seed)
+    src, dst, t, eoff, voff = synth.batch_workload(G, seed=seed, sizes=sizes)
+    note("batch n=%d: GPU" % len(src))
+    br = run_batch(src, dst, t, eoff, voff, M)
+    whole = ce.to_numpy(br.result)  # the documented (unsigned) dtypes, as the oracle's
+    res = {f: whole[f] for f in FIELDS}
+    ro, co = br.row_offsets, br.cluster_offsets
+    gpu = []
+    for g in range(G):
+        e0, e1, r0, r1, c0, c1 = eoff[g], eoff[g + 1], ro[g], ro[g + 1], co[g], co[g + 1]
+
+        def get(f):
+            x = res[f]
+            if f.startswith(("msf_", "sl_")):
+                return x[r0:r1]
+            return x[e0:e1] if f in ("pt_cluster", "pt_lambda", "labels") else x[c0:c1]
+        gpu.append(oracle_digests.digest_fields(get, br.m[g], br.n_clusters[g], br.n_labels[g]))
+    note("oracle on every graph in 16 processes")
+    order = np.argsort(-sizes)  # largest first, so the pool drains evenly
+    jobs = [(int(g), int(sizes[g]), seed, M) for g in order]
+    with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1),
+                             mp_context=multiprocessing.get_context("spawn")) as ex:
+        ref = dict(ex.map(oracle_digests.batch_graph_digest, jobs, chunksize=4))
+    bad = [g for g in range(G) if ref[g] != gpu[g]]
+    assert not bad, "graphs differing from the oracle: %s" % bad[:10]
+    note("all %d graphs equal the oracle" % G)

@@ -209,3 +209,59 @@ def test_open_loop_arrivals_small():
         if k % 6 == 0:
             same(ce.to_numpy(results[k].result), alone(reqs[k]), "open-loop request %d" % k)
     note("latency p50 %.2f ms p99 %.2f ms" % (1e3 * np.percentile(lat, 50), 1e3 * np.percentile(lat, 99)))
+
+
+@pytest.mark.timeout(900)
+def test_stream_prefix_against_the_oracle():
+    """The first 2 000 requests of the serving stream (about 3.7e8 records, sizes up to the stream's 5e6)
+    served with continuous batching, up to 256 in flight: every request's outputs equal the oracle's on that
+    request alone (digests of every field; afterwards the oracle runs in 16 host processes that regenerate
+    each request from its seed)."""
+    import multiprocessing
+    from concurrent.futures import ProcessPoolExecutor, ThreadPoolExecutor
+    import oracle_digests
+    ce = _ce()
+    count, M, seed = 2000, 10, 4
+    sizes = synth.request_sizes(20000, seed=seed)[:count]
+    note("stream prefix: %d requests, %d records, largest %d" % (count, int(sizes.sum()), int(sizes.max())))
+    with ThreadPoolExecutor(max_workers=16) as ex:
+        reqs = list(ex.map(lambda r: synth.request_graph(r, int(sizes[r]), seed), range(count)))
+    note("generated")
+    got = {}
+    with ce.Server(32 << 30, workers=3, max_inflight=256) as srv:
+        pending = {}
+        k = 0
+        while k < count or pending:
+            while k < count and len(pending) < 256:
+                s, d, t, V = reqs[k]
+                try:
+                    pending[srv.submit(s, d, t, M, V)] = k
+                except ce.ServerBusy:
+                    break
+                k += 1
+            done = False
+            for tk in list(pending):
+                r = srv.poll(tk)
+                if r is not None:
+                    kk = pending.pop(tk)
+                    assert r.status == ce.CE_OK, (kk, r.error)
+                    h = ce.to_numpy(r.result)
+                    got[kk] = oracle_digests.digest_fields(lambda f: h[f], h["m"], h["n_clusters"], h["n_labels"])
+                    done = True
+                    if len(got) % 250 == 0:
+                        note("served and digested %d" % len(got))
+            if not done:
+                time.sleep(0.0005)
+    del reqs
+    note("oracle on every request in 16 processes")
+    ref = {}
+    with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1),
+                             mp_context=multiprocessing.get_context("spawn")) as ex:
+        jobs = [(int(r), int(sizes[r]), seed, M) for r in np.argsort(-sizes)]
+        for r, dg in ex.map(oracle_digests.request_digest, jobs, chunksize=4):
+            ref[r] = dg
+            if len(ref) % 500 == 0:
+                note("oracle %d" % len(ref))
+    bad = [r for r in range(count) if ref[r] != got[r]]
+    assert not bad, "requests differing from the oracle: %s" % bad[:10]
+    note("all %d requests equal the oracle" % count)
