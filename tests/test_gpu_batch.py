@@ -199,18 +199,29 @@ def test_batch_full_size_sampled():
         same(br.graph(int(g)), run_single(src[a:b], dst[a:b], t[a:b], V, M), "full batch graph %d vs single" % g)
 
 
+@pytest.fixture
+def live(capsys):
+    """Progress lines that reach the terminal while the test runs (long tests print as they go)."""
+    import time
+
+    def say(msg):
+        with capsys.disabled():
+            print("[gpu-batch] %s %s" % (time.strftime("%H:%M:%S"), msg), flush=True)
+    return say
+
+
 @pytest.mark.timeout(900)
-def test_batch_every_graph_against_the_oracle():
+def test_batch_every_graph_against_the_oracle(live):
     """Every graph of the 4096-graph batch (one call on the GPU) against the oracle run on that graph alone:
     digests of every output field, the oracle in worker processes that regenerate each graph from its seed."""
     import multiprocessing
-    from concurrent.futures import ProcessPoolExecutor
+    from concurrent.futures import ProcessPoolExecutor, as_completed
     import oracle_digests
     ce = _ce()
     G, M, seed = 4096, 5, 3
     sizes = synth.batch_sizes(G, seed)
     src, dst, t, eoff, voff = synth.batch_workload(G, seed=seed, sizes=sizes)
-    note("batch n=%d: GPU" % len(src))
+    live("batch n=%d: GPU" % len(src))
     br = run_batch(src, dst, t, eoff, voff, M)
     whole = ce.to_numpy(br.result)  # the documented (unsigned) dtypes, as the oracle's
     res = {f: whole[f] for f in FIELDS}
@@ -225,12 +236,19 @@ def test_batch_every_graph_against_the_oracle():
                 return x[r0:r1]
             return x[e0:e1] if f in ("pt_cluster", "pt_lambda", "labels") else x[c0:c1]
         gpu.append(oracle_digests.digest_fields(get, br.m[g], br.n_clusters[g], br.n_labels[g]))
-    note("oracle on every graph in 16 processes")
+        if (g + 1) % 1024 == 0:
+            live("digested %d GPU graphs" % (g + 1))
+    live("oracle on every graph in 16 processes")
     order = np.argsort(-sizes)  # largest first, so the pool drains evenly
     jobs = [(int(g), int(sizes[g]), seed, M) for g in order]
     with ProcessPoolExecutor(max_workers=min(16, os.cpu_count() or 1),
                              mp_context=multiprocessing.get_context("spawn")) as ex:
-        ref = dict(ex.map(oracle_digests.batch_graph_digest, jobs, chunksize=4))
+        ref = {}
+        for fut in as_completed([ex.submit(oracle_digests.batch_graph_digest, j) for j in jobs]):
+            g, dg = fut.result()
+            ref[g] = dg
+            if len(ref) % 512 == 0:
+                live("oracle %d graphs" % len(ref))
     bad = [g for g in range(G) if ref[g] != gpu[g]]
     assert not bad, "graphs differing from the oracle: %s" % bad[:10]
-    note("all %d graphs equal the oracle" % G)
+    live("all %d graphs equal the oracle" % G)
