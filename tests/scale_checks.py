@@ -77,6 +77,7 @@ def check_msf_and_dendrogram(data, got, n_vertices=4000, per_vertex=64, seed=7, 
                  (dst[tail] == dst[head]))
         assert share.all(), "an MSF row joins records that share no vertex"
         del share
+        log("rows join records that share a vertex")
         assert np.array_equal(mw, t[head] - t[tail]), "MSF weight"
         assert np.all((t[tail] < t[head]) | ((t[tail] == t[head]) & (tail < head))), "row orientation"
         assert np.all(key_lt(mw[:-1], head[:-1], tail[:-1], mw[1:], head[1:], tail[1:])), "row order"
@@ -86,6 +87,7 @@ def check_msf_and_dendrogram(data, got, n_vertices=4000, per_vertex=64, seed=7, 
     from scipy.sparse.csgraph import connected_components
     deg = np.bincount(src, minlength=V) + np.bincount(dst, minlength=V)
     g = coo_matrix((np.ones(n, np.int8), (src, dst)), shape=(V, V)).tocsr()
+    log("vertex graph built")
     _, lab = connected_components(g, directed=False)
     del g
     c_line = len(np.unique(lab[deg > 0]))
@@ -94,6 +96,7 @@ def check_msf_and_dendrogram(data, got, n_vertices=4000, per_vertex=64, seed=7, 
     log("components %d" % c_line)
 
     qt, qh, qw = sample_line_graph_edges(src, dst, t, V, n_vertices, per_vertex, seed)
+    log("sampled %d line-graph edges" % len(qt))
     data.clear()
     del src, dst, t
 
@@ -104,6 +107,7 @@ def check_msf_and_dendrogram(data, got, n_vertices=4000, per_vertex=64, seed=7, 
     log("dendrogram equal")
 
     joined = oracle.joined_below(n, got["msf_tail"], got["msf_head"], mw, qt, qh, qw)
+    log("joined-below query done")
     # a sampled pair not joined below must itself be a row (a row joined below would have closed a cycle,
     # which the union-find above rejects)
     U = np.unique(qh[~joined].astype(np.int64) * np.int64(n) + qt[~joined].astype(np.int64))
