@@ -10,7 +10,8 @@ dendrogram rows (tests/scale_checks.py).
 The condensed half (about three minutes, 70 GB of host memory) runs with
 every GPU test run. The MSF and dendrogram half needs about thirteen minutes
 and 200 GB of host memory; it runs only with CE_SCALE_TEST=1, in a process
-of its own (-k msf).
+of its own (-k msf), so that the oracle's progress lines (CE_ORACLE_PROGRESS,
+read once per process) are on.
 """
 import os
 import sys
@@ -30,14 +31,17 @@ long_check = pytest.mark.skipif(os.environ.get("CE_SCALE_TEST") != "1",
 _capsys = None
 
 
+def _say(msg):
+    print("[gpu-scale] %s %s" % (time.strftime("%H:%M:%S"), msg), flush=True)
+
+
 def note(msg):
     """Progress lines go straight to the terminal (output capture suspended), so a long check is seen working."""
-    line = "[gpu-scale] %s %s" % (time.strftime("%H:%M:%S"), msg)
     if _capsys is not None:
         with _capsys.disabled():
-            print(line, flush=True)
+            _say(msg)
     else:
-        print(line, flush=True)
+        _say(msg)
 
 
 @pytest.fixture(autouse=True)
@@ -72,11 +76,15 @@ def run_scale(keep_inputs):
 
 @long_check
 @pytest.mark.timeout(1150)
-def test_scale_msf_and_dendrogram():
+def test_scale_msf_and_dendrogram(monkeypatch):
+    # the oracle's union-find passes over 2^30 rows take minutes each: they report every 2^26 rows on stderr,
+    # which reaches the terminal while output capture is suspended
+    monkeypatch.setenv("CE_ORACLE_PROGRESS", "1")
     n, M, data, got = run_scale(True)
     for f in ("pt_cluster", "pt_lambda", "labels"):
         del got[f]
-    check_msf_and_dendrogram(data, got, log=note)
+    with _capsys.disabled():
+        check_msf_and_dendrogram(data, got, log=_say)
 
 
 @pytest.mark.timeout(600)
