@@ -407,6 +407,9 @@ def bench_batched(dev, steps, warmup, tuning=True):
                 "outputs_identical": same}
         log("batched, built-in choices: %.1f ms per batch, outputs %s" % (1e3 * el0, "identical" if same else "DIFFER"))
     del ws
+    torch.cuda.empty_cache()
+    captured = time_captured_batch(ce, (s_d, d_d, t_d), eoff, voff, M, steps, dev, knobs,
+                                   autotune.result_digest(br.result), int(t.max() - t.min()).bit_length())
     ng = np.diff(eoff)
     vg = np.diff(voff)
     nmax = int(ng.max())
@@ -439,12 +442,53 @@ def bench_batched(dev, steps, warmup, tuning=True):
            "batched_edges_per_s": n / el_b, "batched_ms": 1e3 * el_b, "batched_steps": steps,
            "single_edges_per_s": n / el_s, "single_ms": 1e3 * el_s,
            "ratio": el_s / el_b, "n_clusters": int(br.n_clusters.sum()), "n_labels": int(br.n_labels.sum()),
-           "equal_to_single_calls": equal, "graphs_compared": G}
+           "equal_to_single_calls": equal, "graphs_compared": G,
+           "captured": dict(captured, edges_per_s=n / (1e-3 * captured["ms"]),
+                            ratio=el_s / (1e-3 * captured["ms"]))}
     if tune is not None:
         out["tuning"] = tune
     del s_d, d_d, t_d, outs, single, regions, sws
     torch.cuda.empty_cache()
     return out
+
+
+def time_captured_batch(ce, ins, eoff, voff, M, steps, dev, knobs, want, time_bits):
+    """The batch as one HIP graph: the enqueue-only call (device offsets, counts in a device header) captured
+    once under the same launch choices, then replayed; its outputs are compared with the synchronous call's
+    (digest `want`)."""
+    import numpy as np
+    import torch
+    from paper_2311_10337_amd import autotune
+    G, n = len(eoff) - 1, int(eoff[-1])
+    eo = torch.from_numpy(np.ascontiguousarray(eoff, dtype=np.int64)).to(dev)
+    vo = torch.from_numpy(np.ascontiguousarray(voff, dtype=np.int64)).to(dev)
+    outs = ce.batch_outputs(eoff, M, dev)
+    ws = torch.empty(ce.batch_workspace_bytes_for(n, G, M), dtype=torch.uint8, device=dev)
+    hdr = torch.zeros(ce.hdr_words(G), dtype=torch.int64, device=dev)
+    graph = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream(device=dev)
+    side.wait_stream(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    with ce.tuned(knobs), torch.cuda.stream(side), torch.cuda.graph(graph, stream=side):
+        ce.cluster_batch_async(*ins, eo, vo, int(voff[-1]), M, outs, ws, hdr, time_bits=max(1, time_bits),
+                               stream=torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    cap_s = time.perf_counter() - t0
+    graph.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        graph.replay()
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    same = autotune.result_digest(ce.async_batch_result(outs, eoff, hdr).result) == want
+    log("batched, captured HIP graph: %.1f ms per replay (capture %.1f ms), outputs %s"
+        % (1e3 * el, 1e3 * cap_s, "identical" if same else "DIFFER"))
+    del graph, outs, ws, hdr, eo, vo
+    torch.cuda.empty_cache()
+    return {"ms": 1e3 * el, "replays": steps, "capture_ms": 1e3 * cap_s, "outputs_identical": same,
+            "call": "ce_cluster_batch_async captured once in a HIP graph and replayed"}
 
 
 class Digest:
