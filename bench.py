@@ -173,10 +173,12 @@ def tuned_knobs(ce, n, V):
 
 
 def time_single_graph(ce, w, dev, steps, warmup, causal=False, thr=None, roofline_kernel=None, knobs=None,
-                      default_steps=0):
-    """Times `steps` calls under the launch choices `knobs` (None: built-in); with default_steps, then that
-    many calls with the built-in choices, whose outputs must be the same. Returns (result, seconds,
-    (kernel ms, kernel launches), device buffers, tuning record or None)."""
+                      default_steps=0, timing_steps=0):
+    """Times `steps` calls under the launch choices `knobs` (None: built-in), with no instrumentation; then,
+    with roofline_kernel, `timing_steps` more calls in which that kernel's launches are timed by events in
+    their own dispatches; with default_steps, then that many calls with the built-in choices, whose outputs
+    must be the same. Returns (result, seconds, (kernel ms, kernel launches, steps they cover), device
+    buffers, tuning record or None, per-step milliseconds of the timed calls)."""
     import torch
     from paper_2311_10337_amd import autotune
     src = torch.from_numpy(w.src).to(dev)
@@ -196,17 +198,26 @@ def time_single_graph(ce, w, dev, steps, warmup, causal=False, thr=None, rooflin
             r = step()
             log("warmup %d done: m=%d clusters=%d labels=%d" % (i, r.m, r.n_clusters, r.n_labels))
         torch.cuda.synchronize()
-        if roofline_kernel:
-            ce.timing_enable(roofline_kernel)
+        stamps = []
         t0 = time.perf_counter()
         for i in range(steps):
-            r = step()
+            r = step()  # returns when the call's results are written
+            stamps.append(time.perf_counter())
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
-        kms, kcnt = ce.timing_read() if roofline_kernel else (0.0, 0)
-        ce.timing_enable(None)
-    log("timed %d steps in %.3f s (%.1f ms per step)%s" % (steps, el, 1e3 * el / steps,
-                                                          ", launch choices %s" % knobs if knobs else ""))
+        step_ms = [1e3 * (b - a) for a, b in zip([t0] + stamps[:-1], stamps)]
+        kms, kcnt, ksteps = 0.0, 0, 0
+        if roofline_kernel and timing_steps:
+            ce.timing_enable(roofline_kernel)
+            for i in range(timing_steps):
+                step()
+            torch.cuda.synchronize()
+            kms, kcnt = ce.timing_read()
+            ce.timing_enable(None)
+            ksteps = timing_steps
+    log("timed %d steps in %.3f s (%.1f ms per step, median %.1f)%s"
+        % (steps, el, 1e3 * el / steps, sorted(step_ms)[len(step_ms) // 2],
+           ", launch choices %s" % knobs if knobs else ""))
     tune = None
     if knobs and default_steps:
         d_tuned = autotune.result_digest(r)
@@ -227,7 +238,7 @@ def time_single_graph(ce, w, dev, steps, warmup, causal=False, thr=None, rooflin
         tune = {"knobs": {}, "note": "no tuning-file entry for this bucket: built-in choices",
                 "resolved": ce.resolve_tuning(w.n, V)}
     del ws
-    return r, el, (kms, kcnt), (src, dst, tt, outs), tune
+    return r, el, (kms, kcnt, ksteps), (src, dst, tt, outs), tune, step_ms
 
 
 def bench_small_calls(ce, dev, n=57_000, calls=50):
@@ -723,6 +734,8 @@ def main():
                     help="skip the batched-vs-one-graph-per-call measurement on the 4096-graph batch")
     ap.add_argument("--roofline-kernel", default="k_krt_union",
                     help="dominant kernel: its launches are timed with HIP events on its stream for the roofline")
+    ap.add_argument("--timing-steps", type=int, default=3,
+                    help="steps after the timed ones in which the roofline kernel's launches are timed (0: none)")
     ap.add_argument("--no-small-call", action="store_true",
                     help="skip the one-call cost of a 57k-record graph (sync, async, replayed HIP graph)")
     ap.add_argument("--no-tuning", action="store_true",
@@ -781,14 +794,16 @@ def main():
     if thr:
         cfg["dendrogram"] = "discrete, %d thresholds %d..%d s" % (len(thr), thr[0], thr[-1])
     knobs = None if args.no_tuning else tuned_knobs(ce, w.n, w.num_vertices)
-    r, el, (kms, kcnt), keep, tune = time_single_graph(ce, w, dev, args.steps, args.warmup, causal, thr,
-                                                       args.roofline_kernel, knobs, args.default_steps)
+    r, el, (kms, kcnt, ksteps), keep, tune, step_ms = time_single_graph(
+        ce, w, dev, args.steps, args.warmup, causal, thr, args.roofline_kernel, knobs, args.default_steps,
+        args.timing_steps)
     roof = None
     if args.roofline_kernel and kcnt:
-        log("kernel %s: %d launches, %.3f ms total, %.1f us avg" % (args.roofline_kernel, kcnt, kms,
-                                                                  1e3 * kms / kcnt))
-        roof = roofline_line(ce, profiling, args.roofline_kernel, kms, kcnt, w, r.m, args.steps, tag,
+        log("kernel %s: %d launches in %d steps of their own, %.3f ms total, %.1f us avg"
+            % (args.roofline_kernel, kcnt, ksteps, kms, 1e3 * kms / kcnt))
+        roof = roofline_line(ce, profiling, args.roofline_kernel, kms, kcnt, w, r.m, ksteps, tag,
                              (knobs or {}).get("krt_level_bits", 0))
+        roof["timed_in"] = "%d steps after the timed ones (events in the kernel's own dispatches)" % ksteps
     value = w.n * args.steps / el
     # whole path: HBM traffic per step from the committed counter summary (calibrated FETCH_SIZE +
     # WRITE_SIZE over every dispatch of one step), over the step's wall time; and the algorithmic model
@@ -806,7 +821,9 @@ def main():
     line = {"metric": METRIC, "value": value, "unit": "edges/s", "n_gpus": 1, "steps": args.steps,
             "warmup": args.warmup, "ms_per_step": 1000.0 * el / args.steps, "higher_is_better": True,
             "scaling": "weak", "vs_baseline": None, "dtype": "int64", "data": "synthetic",
-            "config": dict(cfg, m_msf=r.m, n_clusters=r.n_clusters, n_labels=r.n_labels)}
+            "config": dict(cfg, m_msf=r.m, n_clusters=r.n_clusters, n_labels=r.n_labels),
+            "step_ms": {"median": sorted(step_ms)[len(step_ms) // 2], "min": min(step_ms), "max": max(step_ms),
+                        "note": "host clock around each timed call (each returns when its results are written)"}}
     if roof is not None:
         line["roofline"] = roof
     line["hbm_pipeline"] = hbm
@@ -836,7 +853,7 @@ def main():
         wx, cfgx = make_workload(name)
         kn = None if args.no_tuning else tuned_knobs(ce, wx.n, wx.num_vertices)
         sx = max(1, min(args.steps, 10))
-        rx, elx, _, kx, tx = time_single_graph(ce, wx, dev, sx, 1, causal, thr, knobs=kn, default_steps=sx)
+        rx, elx, _, kx, tx, _ = time_single_graph(ce, wx, dev, sx, 1, causal, thr, knobs=kn, default_steps=sx)
         workloads[cfgx["workload"]] = dict(cfgx, edges_per_s=wx.n * sx / elx, ms_per_step=1e3 * elx / sx,
                                            m_msf=rx.m, n_clusters=rx.n_clusters, n_labels=rx.n_labels)
         if tx is not None:
