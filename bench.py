@@ -711,8 +711,8 @@ def bench_serving(dev, count, workers=3, budget_gib=64, inflight=512, out_gib=24
             "comparison": "two random 64-bit linear digests of every output field per request"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
+def make_parser():
+    ap = argparse.ArgumentParser(description="Temporal edges clustered per second on one MI355X (one JSON line).")
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
@@ -745,7 +745,11 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0,
                     help="before the steps, copy a buffer of this many bytes once (a plain copy kernel of known "
                          "size for calibrating HBM counters)")
-    args = ap.parse_args()
+    return ap
+
+
+def main():
+    args = make_parser().parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py: this build measures one GPU; --gpus %d is not supported (run with --gpus 1)" % args.gpus,
